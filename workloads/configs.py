@@ -1,0 +1,113 @@
+"""Workload parameter sets (plain data, JSON-compatible).
+
+Every workload is a dict with these keys:
+
+  name          label
+  mode          "tdse" (real time, Crank-Nicolson) or "tise" (imaginary time)
+  n_elec, dim   N electrons in d space dimensions; configuration space has
+                D = N*d dimensions, electron m owns dims m*d .. m*d+d-1
+  L             subdomains per configuration dimension (length D)
+  box_lo/box_hi global box per configuration dimension (length D)
+  overlap       overlap width eps per configuration dimension (length D)
+  nbasis        Gaussians per dimension in every subdomain (length D), or a
+                list of per-subdomain lists (uneven bases)
+  basis_extend  optional: centres run this many spacings past each end of
+                the subdomain (default 0: centres span the subdomain)
+  width         absolute Gaussian width sigma (delta = 1/(2 sigma^2)), or None
+  width_ratio   sigma = width_ratio * centre spacing, used when width is None
+  nuclei        list of nuclear positions (each of length d)
+  charges       nuclear charges
+  eps_en/eps_ee soft-Coulomb regularisation of e-n and e-e terms
+  dt, n_steps   time step and steps per window
+  mu            Robin coefficient as [re, im]
+  field         E(t) = E0 sin(omega t + phase) along spatial axis `axis`
+  init          initial state exp(-alpha |x - center|^2), L2-normalised on R^D
+  iters         Schwarz iterations (fixed count) and tol the residual target
+  face_nodes    Gauss-Legendre nodes per tangential panel: [band, middle]
+  quad_nodes    Gauss-Legendre nodes per panel for the potential quadrature
+"""
+import copy
+
+_C1 = dict(
+    name="c1-1e-1d", mode="tdse", n_elec=1, dim=1,
+    L=[4], box_lo=[-20.0], box_hi=[20.0], overlap=[2.0],
+    nbasis=[16], width=0.8, width_ratio=None,
+    nuclei=[[0.0]], charges=[1.0], eps_en=1.0, eps_ee=1.0,
+    dt=0.01, n_steps=200, mu=[0.0, -10.0],
+    field=dict(E0=0.05, omega=0.057, phase=0.0, axis=0),
+    init=dict(alpha=1.0, center=[0.0]),
+    iters=30, tol=1e-8, face_nodes=[16, 32], quad_nodes=16,
+)
+
+_C2 = dict(
+    name="c2-2e-1d", mode="tdse", n_elec=2, dim=1,
+    L=[8, 8], box_lo=[-15.0, -15.0], box_hi=[15.0, 15.0],
+    overlap=[0.375, 0.375],
+    nbasis=[8, 8], width=None, width_ratio=0.7,
+    nuclei=[[-1.4], [1.4]], charges=[1.0, 1.0], eps_en=1.0, eps_ee=1.0,
+    dt=0.005, n_steps=1000, mu=[0.0, -10.0],
+    field=dict(E0=0.05, omega=0.057, phase=0.0, axis=0),
+    init=dict(alpha=1.0, center=[0.0, 0.0]),
+    iters=20, tol=1e-8, face_nodes=[16, 32], quad_nodes=16,
+)
+
+_C2_TISE = dict(_C2, name="c2-2e-1d-tise", mode="tise", mu=[10.0, 0.0],
+                dt=0.05, n_steps=400,
+                field=dict(E0=0.0, omega=0.0, phase=0.0, axis=0))
+
+# Learned warm start runs on the two-electron system with several windows.
+_C4 = dict(_C2, name="c4-2e-1d-learned", iters=60, tol=1e-8)
+
+_C5 = dict(
+    name="c5-2e-2d", mode="tdse", n_elec=2, dim=2,
+    L=[4, 4, 4, 4], box_lo=[-10.0] * 4, box_hi=[10.0] * 4, overlap=[0.5] * 4,
+    nbasis=[6, 6, 6, 6], width=None, width_ratio=0.7,
+    nuclei=[[-1.0, 0.0], [1.0, 0.0]], charges=[1.0, 1.0],
+    eps_en=0.5, eps_ee=0.5,
+    dt=0.01, n_steps=500, mu=[0.0, -10.0],
+    field=dict(E0=0.05, omega=0.057, phase=0.0, axis=0),
+    init=dict(alpha=1.0, center=[0.0, 0.0, 0.0, 0.0]),
+    iters=30, tol=1e-8, face_nodes=[2, 4], quad_nodes=16,
+)
+
+CONFIGS = {c["name"]: c for c in (_C1, _C2, _C2_TISE, _C4, _C5)}
+
+
+def get_config(name, **overrides):
+    """Deep copy of a named workload with optional top-level overrides."""
+    cfg = copy.deepcopy(CONFIGS[name])
+    cfg.update(copy.deepcopy(overrides))
+    return cfg
+
+
+def tiny_configs():
+    """Small workloads the oracle runs in well under a second each.
+
+    They cover one and two configuration dimensions, unequal L and basis
+    sizes per dimension (to catch transposed indices), a basis size that is
+    not a multiple of any tile, complex and real Robin coefficients.
+    """
+    t1 = dict(
+        name="tiny-1d", mode="tdse", n_elec=1, dim=1,
+        L=[3], box_lo=[-8.0], box_hi=[8.0], overlap=[1.5],
+        nbasis=[7], width=None, width_ratio=0.8,
+        nuclei=[[0.3]], charges=[1.0], eps_en=1.0, eps_ee=1.0,
+        dt=0.02, n_steps=12, mu=[0.0, -4.0],
+        field=dict(E0=0.3, omega=1.1, phase=0.2, axis=0),
+        init=dict(alpha=0.7, center=[0.4]),
+        iters=6, tol=1e-8, face_nodes=[4, 6], quad_nodes=16,
+    )
+    t2 = dict(
+        name="tiny-2d", mode="tdse", n_elec=2, dim=1,
+        L=[3, 2], box_lo=[-6.0, -5.0], box_hi=[6.0, 5.5], overlap=[0.8, 0.7],
+        nbasis=[5, 4], width=None, width_ratio=0.7,
+        nuclei=[[-0.7], [0.9]], charges=[1.0, 0.8], eps_en=1.0, eps_ee=0.9,
+        dt=0.01, n_steps=8, mu=[0.5, -6.0],
+        field=dict(E0=0.2, omega=0.9, phase=0.1, axis=0),
+        init=dict(alpha=0.6, center=[0.2, -0.3]),
+        iters=4, tol=1e-8, face_nodes=[4, 6], quad_nodes=16,
+    )
+    t3 = dict(t2, name="tiny-2d-tise", mode="tise", mu=[6.0, 0.0],
+              dt=0.05, n_steps=10,
+              field=dict(E0=0.0, omega=0.0, phase=0.0, axis=0))
+    return [copy.deepcopy(t) for t in (t1, t2, t3)]
