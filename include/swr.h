@@ -1,0 +1,232 @@
+/*
+ * swr.h -- C ABI of the MI355X Schwarz Waveform Relaxation (SWR) Galerkin
+ * library for the N-body Schrodinger equation (Lorin, arXiv 1710.02401).
+ *
+ * Conventions (every entry point):
+ *   - Returns int32_t: SWR_OK (0) or a negative SWR_E_* code.  Nothing throws
+ *     across the ABI.  Out-parameters are written only on SWR_OK.  After an
+ *     error, swr_last_error(handle) returns a static-lifetime description.
+ *   - "dev" pointers are device (HBM) addresses on the handle's GPU; "host"
+ *     pointers are ordinary process memory.  The caller owns every buffer it
+ *     passes; the library owns the opaque handle and its host-side tables.
+ *   - Device memory: the library never allocates it.  The caller queries
+ *     swr_workspace_bytes, allocates one buffer (any allocator) and binds it
+ *     with swr_bind_workspace; every device array of the handle lives there.
+ *   - Streams: every device operation is enqueued on the hipStream_t passed
+ *     as `stream` (typed void* so this header needs no HIP include; NULL is
+ *     the default stream).  Calls that return host values (residuals,
+ *     energies, run statistics) synchronise that stream before returning.
+ *   - Complex numbers are interleaved (re, im) FP64 pairs.  Every floating
+ *     point quantity is FP64.  Integers are int32 unless stated.
+ *   - Items: with n_geom geometries of n_sub = prod(L) subdomains each, item
+ *     s = g * n_sub + i (i = linear subdomain index, first dimension
+ *     fastest, Section 3.4 / Section 5 indexing Omega_{i+Lj}).
+ *   - One handle per host thread; calls on one handle are not thread safe.
+ */
+#ifndef SWR_H
+#define SWR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SWR_OK = 0,
+  SWR_E_ARG = -1,      /* invalid argument (null pointer, out-of-range value) */
+  SWR_E_SIZE = -2,     /* buffer too small / size beyond a kernel's limit      */
+  SWR_E_DEVICE = -3,   /* HIP runtime error (launch, copy, no device)          */
+  SWR_E_STATE = -4,    /* call out of order (e.g. sweep before assemble)       */
+  SWR_E_SINGULAR = -5, /* zero pivot met in a device factorisation             */
+  SWR_E_NAN = -6,      /* non-finite value produced on the device              */
+  SWR_E_NOCONV = -7    /* iteration cap reached above the residual target      */
+};
+
+enum { SWR_TDSE = 0, SWR_TISE = 1 };
+
+/* Schwarz initial guess psi^(0) of a window (Section 4.1: "psi^(k=0) is a
+ * given function").  PLAIN: the window's initial state held constant in
+ * time; ZERO: no transmission data; GIVEN: Robin data supplied by the caller
+ * at the receiving face nodes (used by the learned warm start). */
+enum { SWR_WARM_PLAIN = 0, SWR_WARM_ZERO = 1, SWR_WARM_GIVEN = 2 };
+
+/* Problem description, copied by swr_create.  Lengths in atomic units.
+ * Geometry (Section 5, opening paragraph): per configuration dimension k the
+ * stated box [box_lo, box_hi] is the outer box [a - eps/2, b + eps/2], split
+ * into L[k] cores of width (b - a)/L[k]; subdomain i spans
+ * [a + i h - eps/2, a + (i+1) h + eps/2].
+ * Basis (Section 2, eq. gauss1d; Test 1.a): per dimension n equispaced
+ * centres over the subdomain (basis_extend spacings past each end), Gaussian
+ * exp(-delta (x - alpha)^2) with delta = 1/(2 sigma^2), sigma = width if
+ * width > 0 else width_ratio * spacing. */
+typedef struct swr_desc {
+  int32_t mode;              /* SWR_TDSE or SWR_TISE                          */
+  int32_t n_elec, dim;       /* N electrons in d dimensions; D = N*d <= 4     */
+  int32_t n_geom;            /* independent geometries batched together (>=1) */
+  int32_t L[4];              /* subdomains per configuration dimension        */
+  double box_lo[4], box_hi[4], overlap[4];
+  const int32_t* nbasis;     /* host: [D], or [n_sub][D] if per_subdomain     */
+  int32_t per_subdomain_basis;
+  int32_t basis_extend;
+  double width, width_ratio;
+  int32_t n_nuc;
+  const double* nuc_pos;     /* host: [n_geom][n_nuc][dim]                    */
+  const double* nuc_charge;  /* host: [n_nuc]                                 */
+  double eps_en, eps_ee;     /* soft-Coulomb regularisation (eq. pseudo)      */
+  double dt;
+  int32_t n_steps;           /* time steps per window                         */
+  double mu_re, mu_im;       /* Robin coefficient mu (eq. RTC)                */
+  double E0, omega, phase;   /* E(t) = E0 sin(omega t + phase)                */
+  int32_t axis;              /* spatial axis of the field, 0 <= axis < dim    */
+  double init_alpha;         /* phi_0 = (2a/pi)^(D/4) exp(-a |x - x0|^2)      */
+  double init_center[4];
+  int32_t face_nodes_band, face_nodes_mid; /* GL nodes per tangential panel   */
+  int32_t quad_nodes;        /* GL nodes per potential quadrature panel       */
+} swr_desc;
+
+typedef struct swr_handle_s* swr_handle;
+
+/* Sizes of a created handle (host struct, filled by swr_query). */
+typedef struct swr_info {
+  int32_t D, n_sub, n_items, K_max;
+  int64_t sum_K, sum_K2;     /* total coefficients / matrix entries           */
+  int64_t n_face_nodes;      /* receiving face nodes over all items           */
+  int64_t n_pairs;           /* (item, neighbour) transfer pairs              */
+  int64_t sum_KK_pairs;      /* entries of all transfer operators             */
+  int32_t n_steps;
+  int32_t reserved;
+  uint64_t workspace_bytes;
+} swr_info;
+
+/* ---- lifetime ------------------------------------------------------------*/
+
+/* Build the decomposition, bases, face quadrature nodes, covering sets O(y)
+ * and neighbour lists on the host (Section 4.1 SWR setting; Section 5
+ * decomposition).  Validates the description: SWR_E_ARG for inconsistent
+ * fields, SWR_E_SIZE if a basis exceeds the kernels' limits
+ * (K <= 64 per subdomain in this build).  *out receives a new handle. */
+int32_t swr_create(const swr_desc* desc, swr_handle* out);
+void swr_destroy(swr_handle h);
+const char* swr_last_error(swr_handle h);
+int32_t swr_query(swr_handle h, swr_info* info);
+
+/* Bytes of device workspace the handle needs (256-byte aligned start). */
+int32_t swr_workspace_bytes(swr_handle h, uint64_t* bytes);
+/* Bind caller-owned device memory of at least swr_workspace_bytes bytes.
+ * SWR_E_SIZE if too small, SWR_E_ARG if null or misaligned. */
+int32_t swr_bind_workspace(swr_handle h, void* dev, uint64_t bytes);
+
+/* ---- assembly (Section 4.1 local ODE systems, eq. Q; once per geometry) --*/
+
+/* Upload the host tables and assemble, for every item, the Gram matrix A,
+ * kinetic matrix Kin = 1/2 <grad v, grad v>, soft-Coulomb matrix V
+ * (Gauss-Legendre quadrature), dipole matrix Q = sum_m <x_m v, v>, boundary
+ * mass B, partition-of-unity mass W, the Robin transfer operators and the
+ * face Gram matrices used by the residual.  Requires a bound workspace. */
+int32_t swr_assemble(swr_handle h, void* stream);
+
+/* Local Cauchy data (Section 4.4 step 1; Test 1.a): c0_dev == NULL projects
+ * the Gaussian phi_0 of the description (solves A c = <phi_0, v>), else
+ * copies sum_K complex coefficients from c0_dev.  In TISE mode the result is
+ * divided by its global partition-of-unity norm. */
+int32_t swr_set_initial(swr_handle h, const void* c0_dev, void* stream);
+
+/* Schwarz initial guess of the current window (see SWR_WARM_*).  For GIVEN,
+ * g_dev holds complex Robin data g(y, t_n) on every receiving face node:
+ * layout [n_steps+1][n_face_nodes] (time-major).  Resets the iteration count
+ * and the residual reference to the window's initial state. */
+int32_t swr_warm_start(swr_handle h, int32_t mode, const void* g_dev, void* stream);
+
+/* ---- the SWR iteration (Section 4.1 eq. S1; Section 4.4) ------------------*/
+
+/* Factor every Crank-Nicolson matrix of the window,
+ * M^n = A + i dt/2 (Kin + V + mu/2 B + E(t_n) Q), n = 1..n_steps
+ * (independent of the Schwarz iterate), starting at time t0.  TISE: the
+ * implicit Euler matrix A + dt (Kin + V + mu/2 B) once per item. */
+int32_t swr_factor(swr_handle h, double t0, void* stream);
+
+/* One Schwarz iteration of local solves for every item (Section 4.4 step 2):
+ * TDSE Crank-Nicolson
+ *   M^{n+1} c^{n+1} = (A - i dt/2 (H~ + E_n Q)) c^n + (i dt/4)(f^n + f^{n+1}),
+ * TISE implicit Euler with global normalisation (eq. SIT),
+ * using the current Robin data f.  Requires swr_factor for the window. */
+int32_t swr_sweep(swr_handle h, void* stream);
+
+/* Transmission (Section 4.1, averaged Robin TC in multi-overlap zones, eq.
+ * RTC) from the iterate just computed, and the residual Res(k) of eq.
+ * (residueRT) between it and the previous iterate.  Writes Res(k) to
+ * *residual_host (synchronises the stream). */
+int32_t swr_transmit(swr_handle h, double* residual_host, void* stream);
+
+/* Whole window: factor, then sweep + transmit until Res(k) <= tol with
+ * k >= 2, or k == k_max.  iters/res receive up to 64 entries. */
+typedef struct swr_run_opts {
+  int32_t k_max;
+  double tol;
+  double t0;
+  int32_t warm;              /* SWR_WARM_*                                    */
+  const void* g_dev;         /* Robin data for SWR_WARM_GIVEN                 */
+} swr_run_opts;
+typedef struct swr_run_stats {
+  int32_t iters;
+  int32_t converged;
+  double res[64];
+  double energy;             /* TISE: (1/nu - 1)/dt at the last step          */
+} swr_run_stats;
+int32_t swr_run(swr_handle h, const swr_run_opts* opts, swr_run_stats* stats, void* stream);
+
+/* ---- outputs and inspection ------------------------------------------------*/
+
+/* Coefficient history of the current iterate: complex [item blocks], item s
+ * occupying (n_steps+1) * K_s entries time-major, items in order. */
+int32_t swr_get_history(swr_handle h, void* dst_dev, uint64_t bytes, void* stream);
+/* Current Robin data vectors f: same layout as the history. */
+int32_t swr_get_forcing(swr_handle h, void* dst_dev, uint64_t bytes, void* stream);
+/* Initial coefficients (complex, sum_K). */
+int32_t swr_get_initial(swr_handle h, void* dst_dev, uint64_t bytes, void* stream);
+/* Assembled real matrices, which = 0 A, 1 Kin, 2 V, 3 Q, 4 B, 5 W, 6 face
+ * Gram G; item s occupies K_s*K_s row-major entries, items in order. */
+int32_t swr_get_matrix(swr_handle h, int32_t which, void* dst_dev, uint64_t bytes, void* stream);
+/* Per-item sizes: host int32 [n_items][2 + 2*4]: K, n_face_nodes, then the
+ * multi-index and the per-dimension basis sizes (padded with 0). */
+int32_t swr_get_items(swr_handle h, int32_t* dst_host, uint64_t n);
+/* Subdomain boxes, host double [n_items][4][2] (lo, hi per dimension,
+ * computed with the formula order of the geometry, no contraction). */
+int32_t swr_get_boxes(swr_handle h, double* dst_host, uint64_t n);
+/* Covering-set index map: host int32 [n_face_nodes][16]; per receiving node
+ * (item, face k=0..D-1 side 0/1, node) record [count, j_0..j_14] with the
+ * subdomain linear indices (within the geometry) of O(y) in increasing
+ * order, -1 padded; count = -1 on faces lying on the global boundary. */
+int32_t swr_get_index_maps(swr_handle h, int32_t* dst_host, uint64_t n);
+/* Receiving face nodes: host double [n_face_nodes][4] coordinates and
+ * [n_face_nodes] tangential quadrature weights. */
+int32_t swr_get_face_nodes(swr_handle h, double* coords_host, double* weights_host, uint64_t n);
+
+/* Reconstruction (Section 4.3): psi(x) = mean over the subdomains whose
+ * closure holds x of psi_i(x), at time step `step` of the current history,
+ * for n_pts points (device double [n_pts][D]) of geometry `geom`; writes
+ * complex [n_pts] to out_dev (0 where no subdomain covers x). */
+int32_t swr_reconstruct(swr_handle h, int32_t geom, int32_t step, const void* pts_dev,
+                        int64_t n_pts, void* out_dev, void* stream);
+
+/* TISE local generalized eigenproblems H~_i x = lambda A_i x (Section 4.2):
+ * eigenvalues ascending, device double [sum_K], and A-orthonormal
+ * eigenvectors (columns, largest-magnitude component positive), device
+ * double [sum_K2] row-major per item.  Requires a real Robin coefficient. */
+int32_t swr_local_eigen(swr_handle h, void* lambda_dev, void* vectors_dev, void* stream);
+
+/* Last TISE normaliser nu of every step of the current iterate, device
+ * double [n_steps+1] (nu_0 = 1). */
+int32_t swr_get_norms(swr_handle h, void* dst_dev, uint64_t bytes, void* stream);
+
+/* Pending device error flags (NaN / zero pivot) since the last call:
+ * synchronises the stream, returns SWR_E_NAN / SWR_E_SINGULAR or SWR_OK,
+ * and clears them. */
+int32_t swr_status_sync(swr_handle h, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SWR_H */

@@ -1,0 +1,676 @@
+// C ABI of the SWR library: handle lifetime, caller-owned workspace, and the
+// stream-ordered sequence assemble -> set_initial -> warm_start -> factor ->
+// (sweep -> transmit)*.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/swr.h"
+#include "geometry.h"
+#include "kernels.h"
+
+using swr::Geometry;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct Buf {
+  size_t off = 0, bytes = 0;
+};
+
+struct Layout {
+  size_t total = 0;
+  Buf add(size_t bytes) {
+    Buf b;
+    total = (total + 255) & ~size_t(255);
+    b.off = total;
+    b.bytes = bytes;
+    total += bytes;
+    return b;
+  }
+};
+
+}  // namespace
+
+struct swr_handle_s {
+  Geometry g;
+  std::string err;
+  int n_mats = 0;
+  int64_t sum_K = 0, sum_K2 = 0, n_T = 0, s1_total = 0, scratch_total = 0;
+  int n_res_tiles = 0;
+  std::vector<int64_t> s1off, scratch_off;
+  std::vector<double> E_host;   // field table, kept alive for the async upload
+
+  // workspace
+  char* ws = nullptr;
+  uint64_t ws_bytes = 0;
+  Layout lay;
+  Buf bK, bOff1, bOff2, bIdx, bNb, bL, bLo, bHi, bEps, bDelta, bAoff, bAlpha, bQoff, bQn, bQx, bQw;
+  Buf bNItem, bNFace, bNCount, bNX, bNW, bNOff;
+  Buf bPI, bPJ, bPOff, bTOff, bPNode, bPNOff;
+  Buf bPos, bCharge, bS1Off, bS1, bScrOff, bScr, bCenter;
+  Buf bA, bKin, bV, bQ, bB, bW, bG, bAr, bAp, bHr;
+  Buf bT, bC0, bH[2], bF, bMinv, bE, bResPart, bResOut, bIePart, bNus, bFlags;
+
+  // state
+  bool bound = false, assembled = false, initial = false, warm = false, factored = false;
+  int cur = 0;      // history holding the latest iterate
+  int k = 0;        // Schwarz iterations done in this window
+  double t0 = 0.0;
+
+  template <class T>
+  T* ptr(const Buf& b) const { return reinterpret_cast<T*>(ws + b.off); }
+
+  swr::Items items() const {
+    swr::Items it{};
+    it.n_items = g.n_items;
+    it.n_sub = g.n_sub;
+    it.D = g.D;
+    it.n_elec = g.desc.n_elec;
+    it.dim = g.desc.dim;
+    it.axis = g.desc.axis;
+    it.K = ptr<int32_t>(bK);
+    it.off1 = ptr<int64_t>(bOff1);
+    it.off2 = ptr<int64_t>(bOff2);
+    it.idx = ptr<int32_t>(bIdx);
+    it.nb = ptr<int32_t>(bNb);
+    it.L = ptr<int32_t>(bL);
+    it.lo = ptr<double>(bLo);
+    it.hi = ptr<double>(bHi);
+    it.eps = ptr<double>(bEps);
+    it.delta = ptr<double>(bDelta);
+    it.aoff = ptr<int64_t>(bAoff);
+    it.alpha = ptr<double>(bAlpha);
+    it.qoff = ptr<int64_t>(bQoff);
+    it.qn = ptr<int32_t>(bQn);
+    it.qx = ptr<double>(bQx);
+    it.qw = ptr<double>(bQw);
+    return it;
+  }
+  swr::Nodes nodes() const {
+    swr::Nodes nd{};
+    nd.n = (int64_t)g.nodes.size();
+    nd.item = ptr<int32_t>(bNItem);
+    nd.face = ptr<int32_t>(bNFace);
+    nd.count = ptr<int32_t>(bNCount);
+    nd.x = ptr<double>(bNX);
+    nd.w = ptr<double>(bNW);
+    nd.off = ptr<int64_t>(bNOff);
+    return nd;
+  }
+  swr::Pairs pairs() const {
+    swr::Pairs pr{};
+    pr.n = (int64_t)g.pair_i.size();
+    pr.pi = ptr<int32_t>(bPI);
+    pr.pj = ptr<int32_t>(bPJ);
+    pr.poff = ptr<int64_t>(bPOff);
+    pr.toff = ptr<int64_t>(bTOff);
+    pr.node = ptr<int32_t>(bPNode);
+    pr.noff = ptr<int64_t>(bPNOff);
+    return pr;
+  }
+  double2* hist(int which) const { return ptr<double2>(bH[which]); }
+};
+
+namespace {
+
+int fail(swr_handle h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  return code;
+}
+
+#define HIPCHECK(h, expr)                                                        \
+  do {                                                                           \
+    hipError_t e_ = (expr);                                                      \
+    if (e_ != hipSuccess)                                                        \
+      return fail(h, SWR_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <class T>
+hipError_t upload(swr_handle h, const Buf& b, const std::vector<T>& v, hipStream_t st) {
+  if (v.empty()) return hipSuccess;
+  return hipMemcpyAsync(h->ws + b.off, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
+}
+
+void plan_layout(swr_handle h) {
+  const Geometry& g = h->g;
+  const size_t NI = g.n_items;
+  const size_t nn = g.nodes.size();
+  const size_t np = g.pair_i.size();
+  Layout& L = h->lay;
+  L = Layout();
+  h->bK = L.add(NI * 4);
+  h->bOff1 = L.add((NI + 1) * 8);
+  h->bOff2 = L.add((NI + 1) * 8);
+  h->bIdx = L.add(NI * 16);
+  h->bNb = L.add(NI * 16);
+  h->bL = L.add(16);
+  h->bLo = L.add(NI * 32);
+  h->bHi = L.add(NI * 32);
+  h->bEps = L.add(32);
+  h->bDelta = L.add(NI * 32);
+  h->bAoff = L.add(NI * 32);
+  h->bAlpha = L.add(g.alpha.size() * 8);
+  h->bQoff = L.add(NI * 32);
+  h->bQn = L.add(NI * 16);
+  h->bQx = L.add(g.qx.size() * 8);
+  h->bQw = L.add(g.qw.size() * 8);
+  h->bNItem = L.add(nn * 4);
+  h->bNFace = L.add(nn * 4);
+  h->bNCount = L.add(nn * 4);
+  h->bNX = L.add(nn * 32);
+  h->bNW = L.add(nn * 8);
+  h->bNOff = L.add((NI + 1) * 8);
+  h->bPI = L.add(np * 4);
+  h->bPJ = L.add(np * 4);
+  h->bPOff = L.add((NI + 1) * 8);
+  h->bTOff = L.add((np + 1) * 8);
+  h->bPNode = L.add(g.pnode.size() * 4);
+  h->bPNOff = L.add((np + 1) * 8);
+  h->bPos = L.add(std::max<size_t>(1, g.nuc_pos.size()) * 8);
+  h->bCharge = L.add(std::max<size_t>(1, g.nuc_charge.size()) * 8);
+  h->bS1Off = L.add(NI * 32);
+  h->bS1 = L.add(h->s1_total * 8);
+  h->bScrOff = L.add(NI * 8);
+  h->bScr = L.add(std::max<int64_t>(1, h->scratch_total) * 8);
+  h->bCenter = L.add(32);
+  const size_t m2 = h->sum_K2 * 8;
+  h->bA = L.add(m2);
+  h->bKin = L.add(m2);
+  h->bV = L.add(m2);
+  h->bQ = L.add(m2);
+  h->bB = L.add(m2);
+  h->bW = L.add(m2);
+  h->bG = L.add(m2);
+  h->bAr = L.add(m2);
+  h->bAp = L.add(m2);
+  h->bHr = L.add(m2);
+  h->bT = L.add(g.pair_toff.back() * 16);
+  h->bC0 = L.add(h->sum_K * 16);
+  const size_t hist = (size_t)(h->n_T + 1) * h->sum_K * 16;
+  h->bH[0] = L.add(hist);
+  h->bH[1] = L.add(hist);
+  h->bF = L.add(hist);
+  h->bMinv = L.add((size_t)h->n_mats * h->sum_K2 * 16);
+  h->bE = L.add((h->n_T + 1) * 8);
+  h->bResPart = L.add((size_t)h->n_res_tiles * NI * 8);
+  h->bResOut = L.add(8);
+  h->bIePart = L.add((size_t)(h->n_T + 1) * NI * 8);
+  h->bNus = L.add((h->n_T + 1) * 8);
+  h->bFlags = L.add(8);
+}
+
+int check_flags(swr_handle h, hipStream_t st) {
+  int flags = 0;
+  HIPCHECK(h, hipMemcpyAsync(&flags, h->ptr<int>(h->bFlags), sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHECK(h, hipStreamSynchronize(st));
+  if (flags) {
+    HIPCHECK(h, hipMemsetAsync(h->ptr<int>(h->bFlags), 0, sizeof(int), st));
+    HIPCHECK(h, hipStreamSynchronize(st));
+    if (flags & 2) return fail(h, SWR_E_SINGULAR, "zero pivot in a device factorisation");
+    return fail(h, SWR_E_NAN, "non-finite value produced on the device");
+  }
+  return SWR_OK;
+}
+
+double field(const swr_desc& d, double t) { return d.E0 * std::sin(d.omega * t + d.phase); }
+
+}  // namespace
+
+extern "C" {
+
+int32_t swr_create(const swr_desc* desc, swr_handle* out) {
+  if (!desc || !out) {
+    g_create_error = "null argument";
+    return SWR_E_ARG;
+  }
+  swr_handle h = new (std::nothrow) swr_handle_s();
+  if (!h) {
+    g_create_error = "out of host memory";
+    return SWR_E_ARG;
+  }
+  int code = SWR_OK;
+  std::string msg = swr::build_geometry(*desc, &h->g, &code);
+  if (code != SWR_OK) {
+    g_create_error = msg;
+    delete h;
+    return code;
+  }
+  Geometry& g = h->g;
+  if (g.K_max > swr::kSmallK) {
+    g_create_error = "basis size per subdomain exceeds 64 in this build";
+    delete h;
+    return SWR_E_SIZE;
+  }
+  if (g.desc.dim != 1 || g.desc.n_elec > 2) {
+    g_create_error = "this build assembles one space dimension per electron and at most 2 electrons";
+    delete h;
+    return SWR_E_SIZE;
+  }
+  h->sum_K = g.off1[g.n_items];
+  h->sum_K2 = g.off2[g.n_items];
+  h->n_T = g.desc.n_steps;
+  h->n_mats = g.desc.mode == SWR_TDSE ? g.desc.n_steps : 1;
+  h->n_res_tiles = (int)((h->n_T + 1 + 15) / 16);
+  h->s1off.assign((size_t)g.n_items * 4, 0);
+  h->scratch_off.assign(g.n_items, 0);
+  int64_t s1 = 0, scr = 0;
+  for (int s = 0; s < g.n_items; ++s) {
+    for (int k = 0; k < g.D; ++k) {
+      h->s1off[(size_t)s * 4 + k] = s1;
+      const int n = g.nb[(size_t)s * 4 + k];
+      s1 += (int64_t)n * n;
+    }
+    h->scratch_off[s] = scr;
+    if (g.desc.n_elec == 2) {
+      const int n1 = g.nb[(size_t)s * 4 + 1];
+      scr += (int64_t)g.qn[(size_t)s * 4 + 0] * n1 * n1;
+    }
+  }
+  h->s1_total = s1;
+  h->scratch_total = scr;
+  plan_layout(h);
+  *out = h;
+  return SWR_OK;
+}
+
+void swr_destroy(swr_handle h) { delete h; }
+
+const char* swr_last_error(swr_handle h) {
+  if (!h) return g_create_error.c_str();
+  return h->err.c_str();
+}
+
+int32_t swr_query(swr_handle h, swr_info* info) {
+  if (!h || !info) return fail(h, SWR_E_ARG, "null argument");
+  swr_info r{};
+  r.D = h->g.D;
+  r.n_sub = h->g.n_sub;
+  r.n_items = h->g.n_items;
+  r.K_max = h->g.K_max;
+  r.sum_K = h->sum_K;
+  r.sum_K2 = h->sum_K2;
+  r.n_face_nodes = (int64_t)h->g.nodes.size();
+  r.n_pairs = (int64_t)h->g.pair_i.size();
+  r.sum_KK_pairs = h->g.pair_toff.back();
+  r.n_steps = (int32_t)h->n_T;
+  r.workspace_bytes = h->lay.total;
+  *info = r;
+  return SWR_OK;
+}
+
+int32_t swr_workspace_bytes(swr_handle h, uint64_t* bytes) {
+  if (!h || !bytes) return fail(h, SWR_E_ARG, "null argument");
+  *bytes = h->lay.total;
+  return SWR_OK;
+}
+
+int32_t swr_bind_workspace(swr_handle h, void* dev, uint64_t bytes) {
+  if (!h || !dev) return fail(h, SWR_E_ARG, "null argument");
+  if (((uintptr_t)dev & 255) != 0) return fail(h, SWR_E_ARG, "workspace must be 256-byte aligned");
+  if (bytes < h->lay.total) return fail(h, SWR_E_SIZE, "workspace smaller than swr_workspace_bytes");
+  h->ws = (char*)dev;
+  h->ws_bytes = bytes;
+  h->bound = true;
+  h->assembled = h->initial = h->warm = h->factored = false;
+  return SWR_OK;
+}
+
+int32_t swr_assemble(swr_handle h, void* stream) {
+  if (!h) return SWR_E_ARG;
+  if (!h->bound) return fail(h, SWR_E_STATE, "no workspace bound");
+  hipStream_t st = (hipStream_t)stream;
+  const Geometry& g = h->g;
+  const size_t NI = g.n_items;
+  std::vector<int32_t> L4(4, 1);
+  std::vector<double> eps4(4, 0.0), cen4(4, 0.0);
+  for (int k = 0; k < g.D; ++k) {
+    L4[k] = g.L[k];
+    eps4[k] = g.eps[k];
+    cen4[k] = g.desc.init_center[k];
+  }
+  std::vector<int32_t> nitem, nface, ncount;
+  std::vector<double> nx, nw;
+  for (const auto& n : g.nodes) {
+    nitem.push_back(n.item);
+    nface.push_back(n.face);
+    ncount.push_back(n.count);
+    for (int k = 0; k < 4; ++k) nx.push_back(n.x[k]);
+    nw.push_back(n.w);
+  }
+  HIPCHECK(h, upload(h, h->bK, g.K, st));
+  HIPCHECK(h, upload(h, h->bOff1, g.off1, st));
+  HIPCHECK(h, upload(h, h->bOff2, g.off2, st));
+  HIPCHECK(h, upload(h, h->bIdx, g.idx, st));
+  HIPCHECK(h, upload(h, h->bNb, g.nb, st));
+  HIPCHECK(h, upload(h, h->bL, L4, st));
+  HIPCHECK(h, upload(h, h->bLo, g.lo, st));
+  HIPCHECK(h, upload(h, h->bHi, g.hi, st));
+  HIPCHECK(h, upload(h, h->bEps, eps4, st));
+  HIPCHECK(h, upload(h, h->bDelta, g.delta, st));
+  HIPCHECK(h, upload(h, h->bAoff, g.aoff, st));
+  HIPCHECK(h, upload(h, h->bAlpha, g.alpha, st));
+  HIPCHECK(h, upload(h, h->bQoff, g.qoff, st));
+  HIPCHECK(h, upload(h, h->bQn, g.qn, st));
+  HIPCHECK(h, upload(h, h->bQx, g.qx, st));
+  HIPCHECK(h, upload(h, h->bQw, g.qw, st));
+  HIPCHECK(h, upload(h, h->bNItem, nitem, st));
+  HIPCHECK(h, upload(h, h->bNFace, nface, st));
+  HIPCHECK(h, upload(h, h->bNCount, ncount, st));
+  HIPCHECK(h, upload(h, h->bNX, nx, st));
+  HIPCHECK(h, upload(h, h->bNW, nw, st));
+  HIPCHECK(h, upload(h, h->bNOff, g.node_off, st));
+  HIPCHECK(h, upload(h, h->bPI, g.pair_i, st));
+  HIPCHECK(h, upload(h, h->bPJ, g.pair_j, st));
+  HIPCHECK(h, upload(h, h->bPOff, g.pair_off, st));
+  HIPCHECK(h, upload(h, h->bTOff, g.pair_toff, st));
+  HIPCHECK(h, upload(h, h->bPNode, g.pnode, st));
+  HIPCHECK(h, upload(h, h->bPNOff, g.pnode_off, st));
+  HIPCHECK(h, upload(h, h->bPos, g.nuc_pos, st));
+  HIPCHECK(h, upload(h, h->bCharge, g.nuc_charge, st));
+  HIPCHECK(h, upload(h, h->bS1Off, h->s1off, st));
+  HIPCHECK(h, upload(h, h->bScrOff, h->scratch_off, st));
+  HIPCHECK(h, upload(h, h->bCenter, cen4, st));
+  HIPCHECK(h, hipMemsetAsync(h->ptr<int>(h->bFlags), 0, 8, st));
+
+  const swr::Items it = h->items();
+  const swr::Nodes nd = h->nodes();
+  const swr::Pairs pr = h->pairs();
+  HIPCHECK(h, swr::launch_assemble(it, h->ptr<double>(h->bA), h->ptr<double>(h->bKin),
+                                   h->ptr<double>(h->bQ), h->ptr<double>(h->bB),
+                                   h->ptr<double>(h->bW), h->ptr<double>(h->bS1),
+                                   h->ptr<int64_t>(h->bS1Off), g.K_max, st));
+  swr::Potential pot{g.desc.n_nuc, h->ptr<double>(h->bPos), h->ptr<double>(h->bCharge),
+                     g.desc.eps_en, g.desc.eps_ee};
+  HIPCHECK(h, swr::launch_potential(it, pot, h->ptr<double>(h->bS1), h->ptr<int64_t>(h->bS1Off),
+                                    h->ptr<double>(h->bV), h->ptr<double>(h->bScr),
+                                    h->ptr<int64_t>(h->bScrOff), st));
+  const double dt = g.desc.dt;
+  const int tise = g.desc.mode == SWR_TISE;
+  HIPCHECK(h, swr::launch_cn_matrices(h->sum_K2, h->ptr<double>(h->bA), h->ptr<double>(h->bKin),
+                                      h->ptr<double>(h->bV), h->ptr<double>(h->bB), 0.5 * dt,
+                                      g.desc.mu_re, g.desc.mu_im, h->ptr<double>(h->bAr),
+                                      h->ptr<double>(h->bAp), h->ptr<double>(h->bHr), tise, dt, st));
+  HIPCHECK(h, swr::launch_transfer(it, nd, pr, g.desc.mu_re, g.desc.mu_im, h->ptr<double2>(h->bT),
+                                   g.K_max, st));
+  HIPCHECK(h, swr::launch_face_gram(it, nd, h->ptr<double>(h->bG), g.K_max, st));
+  // the uploads above read host vectors local to this call
+  HIPCHECK(h, hipStreamSynchronize(st));
+  h->assembled = true;
+  h->initial = h->warm = h->factored = false;
+  return SWR_OK;
+}
+
+int32_t swr_set_initial(swr_handle h, const void* c0_dev, void* stream) {
+  if (!h) return SWR_E_ARG;
+  if (!h->assembled) return fail(h, SWR_E_STATE, "swr_assemble first");
+  hipStream_t st = (hipStream_t)stream;
+  const swr::Items it = h->items();
+  if (c0_dev) {
+    HIPCHECK(h, hipMemcpyAsync(h->ptr<double2>(h->bC0), c0_dev, h->sum_K * 16,
+                               hipMemcpyDeviceToDevice, st));
+  } else {
+    HIPCHECK(h, swr::launch_project(it, h->ptr<double>(h->bA), h->g.desc.init_alpha,
+                                    h->ptr<double>(h->bCenter), h->ptr<double2>(h->bC0),
+                                    h->ptr<int>(h->bFlags), st));
+  }
+  if (h->g.desc.mode == SWR_TISE)
+    HIPCHECK(h, swr::launch_global_normalise(it, h->ptr<double>(h->bW), h->ptr<double2>(h->bC0),
+                                             h->ptr<double>(h->bIePart), st));
+  h->initial = true;
+  int rc = swr_warm_start(h, SWR_WARM_PLAIN, nullptr, stream);
+  return rc;
+}
+
+int32_t swr_warm_start(swr_handle h, int32_t mode, const void* g_dev, void* stream) {
+  if (!h) return SWR_E_ARG;
+  if (!h->initial) return fail(h, SWR_E_STATE, "swr_set_initial first");
+  if (mode == SWR_WARM_GIVEN && !g_dev) return fail(h, SWR_E_ARG, "GIVEN warm start needs g_dev");
+  if (mode != SWR_WARM_PLAIN && mode != SWR_WARM_ZERO && mode != SWR_WARM_GIVEN)
+    return fail(h, SWR_E_ARG, "unknown warm start mode");
+  hipStream_t st = (hipStream_t)stream;
+  const swr::Items it = h->items();
+  double2* F = h->ptr<double2>(h->bF);
+  if (mode == SWR_WARM_PLAIN) {
+    HIPCHECK(h, swr::launch_transmit_const(it, h->pairs(), (int)h->n_T, h->ptr<double2>(h->bT),
+                                           h->ptr<double2>(h->bC0), F, st));
+  } else if (mode == SWR_WARM_ZERO) {
+    HIPCHECK(h, hipMemsetAsync(F, 0, h->bF.bytes, st));
+  } else {
+    HIPCHECK(h, swr::launch_forcing_from_nodes(it, h->nodes(), (int)h->n_T,
+                                               (const double2*)g_dev, F, st));
+  }
+  // iterate 0 (residual reference) = the window's initial state held constant
+  h->cur = 0;
+  HIPCHECK(h, swr::launch_fill_history(it, (int)h->n_T, h->ptr<double2>(h->bC0), h->hist(0), st));
+  h->k = 0;
+  h->warm = true;
+  return SWR_OK;
+}
+
+int32_t swr_factor(swr_handle h, double t0, void* stream) {
+  if (!h) return SWR_E_ARG;
+  if (!h->assembled) return fail(h, SWR_E_STATE, "swr_assemble first");
+  hipStream_t st = (hipStream_t)stream;
+  // the previous upload of the field table must have been consumed
+  HIPCHECK(h, hipStreamSynchronize(st));
+  h->E_host.assign(h->n_T + 1, 0.0);
+  for (int64_t n = 0; n <= h->n_T; ++n) h->E_host[n] = field(h->g.desc, t0 + n * h->g.desc.dt);
+  HIPCHECK(h, upload(h, h->bE, h->E_host, st));
+  const int tise = h->g.desc.mode == SWR_TISE;
+  HIPCHECK(h, swr::launch_invert(h->items(), h->n_mats, h->ptr<double>(h->bAr),
+                                 h->ptr<double>(h->bHr), h->ptr<double>(h->bQ),
+                                 h->ptr<double>(h->bE), 0.5 * h->g.desc.dt, tise,
+                                 h->ptr<double2>(h->bMinv), h->ptr<int>(h->bFlags), st));
+  h->factored = true;
+  h->t0 = t0;
+  return SWR_OK;
+}
+
+int32_t swr_sweep(swr_handle h, void* stream) {
+  if (!h) return SWR_E_ARG;
+  if (!h->factored) return fail(h, SWR_E_STATE, "swr_factor first");
+  if (!h->warm) return fail(h, SWR_E_STATE, "swr_warm_start (or swr_set_initial) first");
+  hipStream_t st = (hipStream_t)stream;
+  const swr::Items it = h->items();
+  const int nxt = 1 - h->cur;
+  const int nT = (int)h->n_T;
+  if (h->g.desc.mode == SWR_TDSE) {
+    HIPCHECK(h, swr::launch_cn_recur(it, nT, h->ptr<double>(h->bAp), h->ptr<double>(h->bHr),
+                                     h->ptr<double>(h->bQ), h->ptr<double>(h->bE),
+                                     0.5 * h->g.desc.dt, h->ptr<double2>(h->bMinv),
+                                     h->ptr<double2>(h->bC0), h->ptr<double2>(h->bF), h->hist(nxt),
+                                     h->ptr<int>(h->bFlags), st));
+  } else {
+    // step 0 of every item is the (normalised) initial state
+    HIPCHECK(h, swr::launch_fill_history(it, nT, h->ptr<double2>(h->bC0), h->hist(nxt), st));
+    for (int n = 0; n < nT; ++n)
+      HIPCHECK(h, swr::launch_ie_step(it, n, nT, h->g.desc.dt, h->ptr<double>(h->bA),
+                                      h->ptr<double>(h->bW), h->ptr<double2>(h->bMinv),
+                                      h->ptr<double2>(h->bF), h->hist(nxt), h->ptr<double>(h->bIePart),
+                                      h->ptr<double>(h->bNus), h->ptr<int>(h->bFlags), st));
+    HIPCHECK(h, swr::launch_ie_finish(it, nT, h->hist(nxt), h->ptr<double>(h->bIePart),
+                                      h->ptr<double>(h->bNus), st));
+  }
+  h->cur = nxt;
+  h->k += 1;
+  return SWR_OK;
+}
+
+int32_t swr_transmit(swr_handle h, double* residual_host, void* stream) {
+  if (!h) return SWR_E_ARG;
+  if (h->k < 1) return fail(h, SWR_E_STATE, "swr_sweep first");
+  hipStream_t st = (hipStream_t)stream;
+  const swr::Items it = h->items();
+  const int nT = (int)h->n_T;
+  HIPCHECK(h, swr::launch_residual(it, nT, h->g.desc.dt, h->ptr<double>(h->bG), h->hist(h->cur),
+                                   h->hist(1 - h->cur), h->ptr<double>(h->bResPart),
+                                   h->ptr<double>(h->bResOut), st));
+  const double* scale = h->g.desc.mode == SWR_TISE ? h->ptr<double>(h->bNus) : nullptr;
+  HIPCHECK(h, swr::launch_transmit(it, h->pairs(), nT, h->ptr<double2>(h->bT), h->hist(h->cur),
+                                   scale, h->ptr<double2>(h->bF), st));
+  double res = 0.0;
+  HIPCHECK(h, hipMemcpyAsync(&res, h->ptr<double>(h->bResOut), 8, hipMemcpyDeviceToHost, st));
+  HIPCHECK(h, hipStreamSynchronize(st));
+  int rc = check_flags(h, st);
+  if (rc != SWR_OK) return rc;
+  if (residual_host) *residual_host = res;
+  return SWR_OK;
+}
+
+int32_t swr_run(swr_handle h, const swr_run_opts* o, swr_run_stats* stats, void* stream) {
+  if (!h || !o) return fail(h, SWR_E_ARG, "null argument");
+  if (o->k_max < 1) return fail(h, SWR_E_ARG, "k_max must be >= 1");
+  int rc = swr_factor(h, o->t0, stream);
+  if (rc) return rc;
+  rc = swr_warm_start(h, o->warm, o->g_dev, stream);
+  if (rc) return rc;
+  swr_run_stats s{};
+  for (int k = 1; k <= o->k_max; ++k) {
+    rc = swr_sweep(h, stream);
+    if (rc) return rc;
+    double r = 0.0;
+    rc = swr_transmit(h, &r, stream);
+    if (rc) return rc;
+    if (k <= 64) s.res[k - 1] = r;
+    s.iters = k;
+    if (k >= 2 && r <= o->tol) {
+      s.converged = 1;
+      break;
+    }
+  }
+  if (h->g.desc.mode == SWR_TISE) {
+    double nu = 1.0;
+    HIPCHECK(h, hipMemcpyAsync(&nu, h->ptr<double>(h->bNus) + h->n_T, 8, hipMemcpyDeviceToHost,
+                               (hipStream_t)stream));
+    HIPCHECK(h, hipStreamSynchronize((hipStream_t)stream));
+    s.energy = (1.0 / nu - 1.0) / h->g.desc.dt;
+  }
+  if (stats) *stats = s;
+  return SWR_OK;
+}
+
+static int32_t copy_out(swr_handle h, const Buf& b, size_t bytes, void* dst, uint64_t cap,
+                        void* stream) {
+  if (!h || !dst) return fail(h, SWR_E_ARG, "null argument");
+  if (!h->bound) return fail(h, SWR_E_STATE, "no workspace bound");
+  if (cap < bytes) return fail(h, SWR_E_SIZE, "destination too small");
+  HIPCHECK(h, hipMemcpyAsync(dst, h->ws + b.off, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return SWR_OK;
+}
+
+int32_t swr_get_history(swr_handle h, void* dst_dev, uint64_t bytes, void* stream) {
+  if (!h) return SWR_E_ARG;
+  return copy_out(h, h->bH[h->cur], h->bH[h->cur].bytes, dst_dev, bytes, stream);
+}
+
+int32_t swr_get_forcing(swr_handle h, void* dst_dev, uint64_t bytes, void* stream) {
+  if (!h) return SWR_E_ARG;
+  return copy_out(h, h->bF, h->bF.bytes, dst_dev, bytes, stream);
+}
+
+int32_t swr_get_initial(swr_handle h, void* dst_dev, uint64_t bytes, void* stream) {
+  if (!h) return SWR_E_ARG;
+  return copy_out(h, h->bC0, h->bC0.bytes, dst_dev, bytes, stream);
+}
+
+int32_t swr_get_matrix(swr_handle h, int32_t which, void* dst_dev, uint64_t bytes, void* stream) {
+  if (!h) return SWR_E_ARG;
+  const Buf* bs[] = {&h->bA, &h->bKin, &h->bV, &h->bQ, &h->bB, &h->bW, &h->bG};
+  if (which < 0 || which > 6) return fail(h, SWR_E_ARG, "matrix index out of range");
+  return copy_out(h, *bs[which], bs[which]->bytes, dst_dev, bytes, stream);
+}
+
+int32_t swr_get_items(swr_handle h, int32_t* dst, uint64_t n) {
+  if (!h || !dst) return fail(h, SWR_E_ARG, "null argument");
+  const Geometry& g = h->g;
+  if (n < (uint64_t)g.n_items * 10) return fail(h, SWR_E_SIZE, "destination too small");
+  for (int s = 0; s < g.n_items; ++s) {
+    int32_t* r = dst + (size_t)s * 10;
+    r[0] = g.K[s];
+    r[1] = (int32_t)(g.node_off[s + 1] - g.node_off[s]);
+    for (int k = 0; k < 4; ++k) {
+      r[2 + k] = k < g.D ? g.idx[(size_t)s * 4 + k] : 0;
+      r[6 + k] = k < g.D ? g.nb[(size_t)s * 4 + k] : 0;
+    }
+  }
+  return SWR_OK;
+}
+
+int32_t swr_get_boxes(swr_handle h, double* dst, uint64_t n) {
+  if (!h || !dst) return fail(h, SWR_E_ARG, "null argument");
+  const Geometry& g = h->g;
+  if (n < (uint64_t)g.n_items * 8) return fail(h, SWR_E_SIZE, "destination too small");
+  for (int s = 0; s < g.n_items; ++s)
+    for (int k = 0; k < 4; ++k) {
+      dst[(size_t)s * 8 + 2 * k] = k < g.D ? g.lo[(size_t)s * 4 + k] : 0.0;
+      dst[(size_t)s * 8 + 2 * k + 1] = k < g.D ? g.hi[(size_t)s * 4 + k] : 0.0;
+    }
+  return SWR_OK;
+}
+
+int32_t swr_get_index_maps(swr_handle h, int32_t* dst, uint64_t n) {
+  if (!h || !dst) return fail(h, SWR_E_ARG, "null argument");
+  const Geometry& g = h->g;
+  if (n < (uint64_t)g.nodes.size() * 16) return fail(h, SWR_E_SIZE, "destination too small");
+  for (size_t q = 0; q < g.nodes.size(); ++q) {
+    const auto& fn = g.nodes[q];
+    int32_t* r = dst + q * 16;
+    r[0] = fn.is_global ? -1 : fn.count;
+    for (int c = 0; c < swr::kMaxCover; ++c)
+      r[1 + c] = (c < fn.count) ? fn.cover[c] % g.n_sub : -1;
+  }
+  return SWR_OK;
+}
+
+int32_t swr_get_face_nodes(swr_handle h, double* coords, double* weights, uint64_t n) {
+  if (!h || !coords || !weights) return fail(h, SWR_E_ARG, "null argument");
+  const Geometry& g = h->g;
+  if (n < (uint64_t)g.nodes.size()) return fail(h, SWR_E_SIZE, "destination too small");
+  for (size_t q = 0; q < g.nodes.size(); ++q) {
+    for (int k = 0; k < 4; ++k) coords[q * 4 + k] = g.nodes[q].x[k];
+    weights[q] = g.nodes[q].w;
+  }
+  return SWR_OK;
+}
+
+int32_t swr_reconstruct(swr_handle h, int32_t geom, int32_t step, const void* pts_dev,
+                        int64_t n_pts, void* out_dev, void* stream) {
+  if (!h || (n_pts > 0 && (!pts_dev || !out_dev))) return fail(h, SWR_E_ARG, "null argument");
+  if (geom < 0 || geom >= h->g.desc.n_geom) return fail(h, SWR_E_ARG, "geometry out of range");
+  if (step < 0 || step > h->n_T) return fail(h, SWR_E_ARG, "step out of range");
+  if (!h->initial) return fail(h, SWR_E_STATE, "no coefficients yet");
+  HIPCHECK(h, swr::launch_reconstruct(h->items(), geom, step, (int)h->n_T, h->hist(h->cur),
+                                      (const double*)pts_dev, n_pts, (double2*)out_dev,
+                                      (hipStream_t)stream));
+  return SWR_OK;
+}
+
+int32_t swr_local_eigen(swr_handle h, void* lambda_dev, void* vectors_dev, void* stream) {
+  if (!h || !lambda_dev || !vectors_dev) return fail(h, SWR_E_ARG, "null argument");
+  if (!h->assembled) return fail(h, SWR_E_STATE, "swr_assemble first");
+  if (h->g.desc.mu_im != 0.0) return fail(h, SWR_E_ARG, "local eigenproblems need a real mu");
+  hipStream_t st = (hipStream_t)stream;
+  HIPCHECK(h, swr::launch_geneig(h->items(), h->ptr<double>(h->bA), h->ptr<double>(h->bHr),
+                                 (double*)lambda_dev, (double*)vectors_dev, h->ptr<int>(h->bFlags),
+                                 st));
+  return check_flags(h, st);
+}
+
+int32_t swr_get_norms(swr_handle h, void* dst_dev, uint64_t bytes, void* stream) {
+  if (!h) return SWR_E_ARG;
+  return copy_out(h, h->bNus, (h->n_T + 1) * 8, dst_dev, bytes, stream);
+}
+
+int32_t swr_status_sync(swr_handle h, void* stream) {
+  if (!h) return SWR_E_ARG;
+  if (!h->bound) return fail(h, SWR_E_STATE, "no workspace bound");
+  return check_flags(h, (hipStream_t)stream);
+}
+
+}  // extern "C"

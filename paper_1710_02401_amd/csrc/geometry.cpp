@@ -1,0 +1,293 @@
+// Host geometry of the SWR decomposition (see geometry.h).
+// Compiled with -ffp-contract=off: every box end, centre and width follows
+// the defining formulas one IEEE operation at a time.
+#include "geometry.h"
+
+#include <algorithm>
+#include <cmath>
+#include <set>
+
+namespace swr {
+
+void gauss_legendre(int n, std::vector<double>* t, std::vector<double>* w) {
+  t->assign(n, 0.0);
+  w->assign(n, 0.0);
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < n; ++i) {
+    // i-th largest root, initial guess from the asymptotic formula
+    double x = std::cos(pi * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p0 = 1.0; p1 = x; }
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+      double dx = p1 / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = x;
+    for (int k = 2; k <= n; ++k) {
+      double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (x * p1 - p0) / (x * x - 1.0);
+    (*t)[n - 1 - i] = x;
+    (*w)[n - 1 - i] = 2.0 / ((1.0 - x * x) * dp * dp);
+  }
+  // symmetrise about 0
+  std::vector<double> ts = *t, ws = *w;
+  for (int i = 0; i < n; ++i) {
+    (*t)[i] = 0.5 * (ts[i] - ts[n - 1 - i]);
+    (*w)[i] = 0.5 * (ws[i] + ws[n - 1 - i]);
+  }
+}
+
+namespace {
+
+void composite(const std::vector<double>& edges, const std::vector<int>& counts,
+               std::vector<double>* x, std::vector<double>* w) {
+  x->clear();
+  w->clear();
+  for (size_t p = 0; p + 1 < edges.size(); ++p) {
+    std::vector<double> t, tw;
+    gauss_legendre(counts[p], &t, &tw);
+    const double a = edges[p], b = edges[p + 1];
+    const double half = 0.5 * (b - a);
+    const double mid = 0.5 * (a + b);
+    for (int j = 0; j < counts[p]; ++j) {
+      x->push_back(mid + half * t[j]);
+      w->push_back(half * tw[j]);
+    }
+  }
+}
+
+}  // namespace
+
+std::string build_geometry(const swr_desc& d, Geometry* g, int* code) {
+  *code = SWR_E_ARG;
+  if (d.n_elec < 1 || d.dim < 1) return "n_elec and dim must be >= 1";
+  const int D = d.n_elec * d.dim;
+  if (D > kMaxD) return "configuration dimension D = n_elec*dim must be <= 4";
+  if (d.n_geom < 1) return "n_geom must be >= 1";
+  if (d.mode != SWR_TDSE && d.mode != SWR_TISE) return "mode must be SWR_TDSE or SWR_TISE";
+  if (d.mode == SWR_TISE && d.mu_im != 0.0) return "imaginary time needs a real Robin coefficient";
+  if (!(d.dt != 0.0) || d.n_steps < 1) return "dt must be non-zero and n_steps >= 1";
+  if (d.axis < 0 || d.axis >= d.dim) return "field axis out of range";
+  if (d.n_nuc < 0 || (d.n_nuc > 0 && (!d.nuc_pos || !d.nuc_charge))) return "nuclei arrays missing";
+  if (!d.nbasis) return "nbasis missing";
+  if (d.face_nodes_band < 1 || d.face_nodes_mid < 1 || d.quad_nodes < 1) return "node counts must be >= 1";
+  if (!(d.eps_en > 0.0) || !(d.eps_ee > 0.0)) return "soft-Coulomb eps must be > 0";
+  if (!(d.width > 0.0) && !(d.width_ratio > 0.0)) return "width or width_ratio must be > 0";
+  if (d.basis_extend < 0) return "basis_extend must be >= 0";
+  g->desc = d;
+  g->D = D;
+  int n_sub = 1;
+  for (int k = 0; k < D; ++k) {
+    if (d.L[k] < 1) return "L must be >= 1";
+    if (!(d.box_hi[k] > d.box_lo[k])) return "box_hi must exceed box_lo";
+    if (d.overlap[k] < 0.0) return "overlap must be >= 0";
+    g->L[k] = d.L[k];
+    g->stride[k] = n_sub;
+    n_sub *= d.L[k];
+    g->eps[k] = d.overlap[k];
+  }
+  g->n_sub = n_sub;
+  g->n_items = n_sub * d.n_geom;
+  const int nb_len = d.per_subdomain_basis ? n_sub * D : D;
+  g->nbasis_in.assign(d.nbasis, d.nbasis + nb_len);
+  g->nuc_pos.assign(d.nuc_pos, d.nuc_pos + (size_t)d.n_geom * d.n_nuc * d.dim);
+  g->nuc_charge.assign(d.nuc_charge, d.nuc_charge + d.n_nuc);
+  g->desc.nbasis = g->nbasis_in.data();
+  g->desc.nuc_pos = g->nuc_pos.data();
+  g->desc.nuc_charge = g->nuc_charge.data();
+
+  // per-dimension interval ends (Section 5): a = lo + eps/2, b = hi - eps/2
+  for (int k = 0; k < D; ++k) {
+    const double a = d.box_lo[k] + 0.5 * d.overlap[k];
+    const double b = d.box_hi[k] - 0.5 * d.overlap[k];
+    const double h = (b - a) / g->L[k];
+    if (g->L[k] > 1 && !(d.overlap[k] < h)) return "overlap must be smaller than the core width";
+    g->lo1[k].resize(g->L[k]);
+    g->hi1[k].resize(g->L[k]);
+    for (int i = 0; i < g->L[k]; ++i) {
+      g->lo1[k][i] = (a + i * h) - 0.5 * d.overlap[k];
+      g->hi1[k][i] = (a + (i + 1) * h) + 0.5 * d.overlap[k];
+    }
+  }
+
+  const int NI = g->n_items;
+  g->idx.assign((size_t)NI * kMaxD, 0);
+  g->nb.assign((size_t)NI * kMaxD, 0);
+  g->K.assign(NI, 0);
+  g->off1.assign(NI + 1, 0);
+  g->off2.assign(NI + 1, 0);
+  g->lo.assign((size_t)NI * kMaxD, 0.0);
+  g->hi.assign((size_t)NI * kMaxD, 0.0);
+  g->delta.assign((size_t)NI * kMaxD, 0.0);
+  g->aoff.assign((size_t)NI * kMaxD, 0);
+  g->alpha.clear();
+  g->qoff.assign((size_t)NI * kMaxD, 0);
+  g->qn.assign((size_t)NI * kMaxD, 0);
+  g->qx.clear();
+  g->qw.clear();
+  g->K_max = 0;
+  for (int s = 0; s < NI; ++s) {
+    const int i = s % n_sub;
+    int rem = i;
+    int K = 1;
+    for (int k = 0; k < D; ++k) {
+      const int ik = rem % g->L[k];
+      rem /= g->L[k];
+      g->idx[(size_t)s * kMaxD + k] = ik;
+      const int n = d.per_subdomain_basis ? g->nbasis_in[(size_t)i * D + k] : g->nbasis_in[k];
+      if (n < 1) return "nbasis must be >= 1";
+      if (n > 1 && n - 1 - 2 * d.basis_extend < 1) return "basis_extend too large for nbasis";
+      g->nb[(size_t)s * kMaxD + k] = n;
+      K *= n;
+      const double lo = g->lo1[k][ik], hi = g->hi1[k][ik];
+      g->lo[(size_t)s * kMaxD + k] = lo;
+      g->hi[(size_t)s * kMaxD + k] = hi;
+      double sp;
+      g->aoff[(size_t)s * kMaxD + k] = (int64_t)g->alpha.size();
+      if (n == 1) {
+        sp = hi - lo;
+        g->alpha.push_back(0.5 * (lo + hi));
+      } else {
+        sp = (hi - lo) / (n - 1 - 2 * d.basis_extend);
+        const double first = lo - d.basis_extend * sp;
+        for (int j = 0; j < n; ++j) g->alpha.push_back(first + j * sp);
+      }
+      const double sigma = d.width > 0.0 ? d.width : d.width_ratio * sp;
+      const double delta = 0.5 / (sigma * sigma);
+      g->delta[(size_t)s * kMaxD + k] = delta;
+      // potential quadrature panels of width <= min(eps_en, eps_ee, sigma)
+      const double sig = std::sqrt(0.5 / delta);
+      const double hmax = std::min(std::min(d.eps_en, d.eps_ee), sig);
+      const int npan = std::max(1, (int)std::ceil((hi - lo) / hmax));
+      const double wdt = (hi - lo) / npan;
+      std::vector<double> edges;
+      for (int p = 0; p < npan; ++p) edges.push_back(lo + p * wdt);
+      edges.push_back(hi);
+      std::vector<double> x, w;
+      composite(edges, std::vector<int>(npan, d.quad_nodes), &x, &w);
+      g->qoff[(size_t)s * kMaxD + k] = (int64_t)g->qx.size();
+      g->qn[(size_t)s * kMaxD + k] = (int32_t)x.size();
+      g->qx.insert(g->qx.end(), x.begin(), x.end());
+      g->qw.insert(g->qw.end(), w.begin(), w.end());
+    }
+    g->K[s] = K;
+    g->K_max = std::max(g->K_max, K);
+    g->off1[s + 1] = g->off1[s] + K;
+    g->off2[s + 1] = g->off2[s] + (int64_t)K * K;
+  }
+
+  // receiving face nodes and covering sets O(y) (closed membership)
+  g->nodes.clear();
+  g->node_off.assign(NI + 1, 0);
+  for (int s = 0; s < NI; ++s) {
+    const int geom = s / n_sub;
+    const int32_t* ix = &g->idx[(size_t)s * kMaxD];
+    const double* slo = &g->lo[(size_t)s * kMaxD];
+    const double* shi = &g->hi[(size_t)s * kMaxD];
+    for (int k = 0; k < D; ++k) {
+      for (int side = 0; side < 2; ++side) {
+        const int is_global = (side == 0 && ix[k] == 0) || (side == 1 && ix[k] == g->L[k] - 1);
+        // tangential rules, increasing dimension, last fastest
+        std::vector<int> tang;
+        for (int t = 0; t < D; ++t)
+          if (t != k) tang.push_back(t);
+        std::vector<std::vector<double>> tx(tang.size()), tw(tang.size());
+        for (size_t c = 0; c < tang.size(); ++c) {
+          const int t = tang[c];
+          std::vector<double> edges = {slo[t], slo[t] + g->eps[t], shi[t] - g->eps[t], shi[t]};
+          composite(edges, {d.face_nodes_band, d.face_nodes_mid, d.face_nodes_band}, &tx[c], &tw[c]);
+        }
+        size_t n_y = 1;
+        for (auto& v : tx) n_y *= v.size();
+        for (size_t q = 0; q < n_y; ++q) {
+          FaceNode fn{};
+          fn.item = s;
+          fn.face = 2 * k + side;
+          fn.is_global = is_global;
+          fn.x[k] = side ? shi[k] : slo[k];
+          double w = 1.0;
+          size_t rem2 = q;
+          for (int c = (int)tang.size() - 1; c >= 0; --c) {
+            const size_t nn = tx[c].size();
+            const size_t j = rem2 % nn;
+            rem2 /= nn;
+            fn.x[tang[c]] = tx[c][j];
+          }
+          rem2 = q;
+          std::vector<double> wj(tang.size());
+          for (int c = (int)tang.size() - 1; c >= 0; --c) {
+            const size_t nn = tx[c].size();
+            wj[c] = tw[c][rem2 % nn];
+            rem2 /= nn;
+          }
+          for (size_t c = 0; c < tang.size(); ++c) w = w * wj[c];
+          fn.w = w;
+          fn.count = 0;
+          for (int c = 0; c < kMaxCover; ++c) fn.cover[c] = -1;
+          if (!is_global) {
+            // candidates: 3^D neighbourhood (sufficient since eps < h)
+            int total = 1;
+            for (int t = 0; t < D; ++t) total *= 3;
+            std::vector<int> found;
+            for (int cnd = 0; cnd < total; ++cnd) {
+              int r = cnd, lin = 0;
+              bool ok = true;
+              for (int t = 0; t < D && ok; ++t) {
+                const int jt = ix[t] + (r % 3) - 1;
+                r /= 3;
+                if (jt < 0 || jt >= g->L[t]) { ok = false; break; }
+                if (!(g->lo1[t][jt] <= fn.x[t] && fn.x[t] <= g->hi1[t][jt])) ok = false;
+                lin += jt * g->stride[t];
+              }
+              if (ok && lin != (s % n_sub)) found.push_back(lin);
+            }
+            std::sort(found.begin(), found.end());
+            if ((int)found.size() > kMaxCover) { *code = SWR_E_SIZE; return "covering set too large"; }
+            fn.count = (int32_t)found.size();
+            for (size_t c = 0; c < found.size(); ++c) fn.cover[c] = geom * n_sub + found[c];
+          }
+          g->nodes.push_back(fn);
+        }
+      }
+    }
+    g->node_off[s + 1] = (int64_t)g->nodes.size();
+  }
+
+  // neighbour pairs and their node lists
+  g->pair_i.clear();
+  g->pair_j.clear();
+  g->pair_off.assign(NI + 1, 0);
+  g->pair_toff.assign(1, 0);
+  g->pnode.clear();
+  g->pnode_off.assign(1, 0);
+  for (int s = 0; s < NI; ++s) {
+    std::set<int> nb;
+    for (int64_t q = g->node_off[s]; q < g->node_off[s + 1]; ++q)
+      for (int c = 0; c < g->nodes[q].count; ++c) nb.insert(g->nodes[q].cover[c]);
+    for (int j : nb) {
+      g->pair_i.push_back(s);
+      g->pair_j.push_back(j);
+      g->pair_toff.push_back(g->pair_toff.back() + (int64_t)g->K[s] * g->K[j]);
+      for (int64_t q = g->node_off[s]; q < g->node_off[s + 1]; ++q)
+        for (int c = 0; c < g->nodes[q].count; ++c)
+          if (g->nodes[q].cover[c] == j) g->pnode.push_back((int32_t)q);
+      g->pnode_off.push_back((int64_t)g->pnode.size());
+    }
+    g->pair_off[s + 1] = (int64_t)g->pair_i.size();
+  }
+  *code = SWR_OK;
+  return "";
+}
+
+}  // namespace swr

@@ -1,0 +1,80 @@
+// Host-side decomposition, local bases, face quadrature and covering sets.
+//
+// Section 5 (opening paragraph) gives the uniform decomposition of the
+// global box into L^{dN} overlapping hypercubes; Section 4.1 defines the
+// interfaces Gamma_{i;j} = boundary(Omega_i) cap Omega_j and the averaging
+// over the set O of subdomains sharing a multi-overlap zone.  Everything here
+// is exact integer/FP64 bookkeeping done once per handle; geometry.cpp is
+// compiled without floating-point contraction so that box ends and centres
+// follow the formulas operation by operation.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/swr.h"
+
+namespace swr {
+
+constexpr int kMaxD = 4;
+constexpr int kMaxCover = 15;  // 2^4 - 1
+
+struct FaceNode {
+  int32_t item;        // receiving item
+  int32_t face;        // 2*k + side
+  int32_t is_global;   // face lies on the global boundary
+  int32_t count;       // |O(y)| (0 on global faces)
+  int32_t cover[kMaxCover];  // global item indices of O(y), increasing
+  double x[kMaxD];
+  double w;            // tangential quadrature weight
+};
+
+struct Geometry {
+  swr_desc desc{};
+  std::vector<int32_t> nbasis_in;     // copy of desc.nbasis
+  std::vector<double> nuc_pos, nuc_charge;
+
+  int D = 0, n_sub = 0, n_items = 0, K_max = 0;
+  int L[kMaxD]{}, stride[kMaxD]{};
+  double eps[kMaxD]{};
+  std::vector<double> lo1[kMaxD], hi1[kMaxD];
+
+  // per item
+  std::vector<int32_t> idx;      // [n_items][kMaxD]
+  std::vector<int32_t> nb;       // [n_items][kMaxD]
+  std::vector<int32_t> K;        // [n_items]
+  std::vector<int64_t> off1;     // prefix sums of K   (n_items + 1)
+  std::vector<int64_t> off2;     // prefix sums of K^2 (n_items + 1)
+  std::vector<double> lo, hi;    // [n_items][kMaxD]
+  std::vector<double> delta;     // [n_items][kMaxD]
+  std::vector<int64_t> aoff;     // [n_items][kMaxD] offsets into alpha
+  std::vector<double> alpha;     // centres, concatenated
+
+  // receiving face nodes, item-major then face then node (oracle order)
+  std::vector<FaceNode> nodes;
+  std::vector<int64_t> node_off; // (n_items + 1)
+
+  // neighbour pairs (i, j) with j in some O(y) of i's nodes
+  std::vector<int32_t> pair_i, pair_j;
+  std::vector<int64_t> pair_off;  // (n_items + 1): pairs of item i
+  std::vector<int64_t> pair_toff; // offset of T_ij entries (n_pairs + 1)
+  // nodes of i whose covering set holds j: list per pair
+  std::vector<int32_t> pnode;     // node indices
+  std::vector<int64_t> pnode_off; // (n_pairs + 1)
+
+  // potential quadrature: per item per dim composite Gauss-Legendre rule
+  std::vector<double> qx, qw;     // concatenated
+  std::vector<int64_t> qoff;      // [n_items][kMaxD] offsets, plus count
+  std::vector<int32_t> qn;        // [n_items][kMaxD] node counts
+};
+
+// Returns an empty string on success, else the error message; *code gets
+// the SWR_E_* status.
+std::string build_geometry(const swr_desc& d, Geometry* g, int* code);
+
+// n-point Gauss-Legendre rule on [-1, 1], ascending nodes (Newton on the
+// three-term recurrence of the Legendre polynomials).
+void gauss_legendre(int n, std::vector<double>* t, std::vector<double>* w);
+
+}  // namespace swr

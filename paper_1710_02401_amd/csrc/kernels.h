@@ -1,0 +1,113 @@
+// Device-side data views and kernel launchers of the SWR library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace swr {
+
+constexpr int kSmallK = 64;      // in-LDS kernels handle K <= kSmallK
+constexpr int kBlock = 256;      // threads per block of the batched kernels
+
+// Per-item tables (device pointers), passed by value to kernels.
+struct Items {
+  int n_items, n_sub, D, n_elec, dim, axis;
+  const int32_t* K;      // [n_items]
+  const int64_t* off1;   // [n_items+1] prefix sums of K
+  const int64_t* off2;   // [n_items+1] prefix sums of K^2
+  const int32_t* idx;    // [n_items][4] multi-index
+  const int32_t* nb;     // [n_items][4] basis size per dimension
+  const int32_t* L;      // [4]
+  const double* lo;      // [n_items][4]
+  const double* hi;      // [n_items][4]
+  const double* eps;     // [4]
+  const double* delta;   // [n_items][4]
+  const int64_t* aoff;   // [n_items][4] offsets into alpha
+  const double* alpha;   // centres
+  const int64_t* qoff;   // [n_items][4] offsets into qx/qw
+  const int32_t* qn;     // [n_items][4]
+  const double* qx;
+  const double* qw;
+};
+
+// Receiving face nodes (struct-of-arrays).
+struct Nodes {
+  int64_t n;
+  const int32_t* item;   // [n]
+  const int32_t* face;   // [n] 2*k + side
+  const int32_t* count;  // [n] |O(y)|, 0 on global faces
+  const double* x;       // [n][4]
+  const double* w;       // [n]
+  const int64_t* off;    // [n_items+1]
+};
+
+struct Pairs {
+  int64_t n;
+  const int32_t* pi;     // [n] receiving item
+  const int32_t* pj;     // [n] sending item
+  const int64_t* poff;   // [n_items+1] pairs of item i
+  const int64_t* toff;   // [n+1] offsets of T_ij entries (complex)
+  const int32_t* node;   // node lists
+  const int64_t* noff;   // [n+1]
+};
+
+struct Potential {
+  int n_nuc;
+  const double* pos;     // [n_geom][n_nuc][dim]
+  const double* charge;  // [n_nuc]
+  double eps_en, eps_ee;
+};
+
+// ---- launchers (return hipError_t of the launch) ----
+hipError_t launch_assemble(const Items& it, double* A, double* Kin, double* Q, double* B,
+                           double* W, double* S1, const int64_t* s1off, int K_max,
+                           hipStream_t st);
+hipError_t launch_potential(const Items& it, const Potential& pot, const double* S1,
+                            const int64_t* s1off, double* V, double* scratch,
+                            const int64_t* scratch_off, hipStream_t st);
+hipError_t launch_transfer(const Items& it, const Nodes& nd, const Pairs& pr, double mu_re,
+                           double mu_im, double2* T, int K_max, hipStream_t st);
+hipError_t launch_face_gram(const Items& it, const Nodes& nd, double* G, int K_max,
+                            hipStream_t st);
+hipError_t launch_project(const Items& it, const double* A, double init_alpha,
+                          const double* init_center, double2* c0, int* flags,
+                          hipStream_t st);
+hipError_t launch_cn_matrices(int64_t n, const double* A, const double* Kin, const double* V,
+                              const double* B, double tau, double mu_re, double mu_im, double* Ar,
+                              double* Ap, double* Hr, int tise, double dt, hipStream_t st);
+hipError_t launch_invert(const Items& it, int n_mats, const double* Ar, const double* Hr,
+                         const double* Q, const double* Efield, double tau, int tise,
+                         double2* Minv, int* flags, hipStream_t st);
+hipError_t launch_cn_recur(const Items& it, int n_steps, const double* Ap, const double* Hr,
+                           const double* Q, const double* Efield, double tau,
+                           const double2* Minv, const double2* c0, const double2* F,
+                           double2* hist, int* flags, hipStream_t st);
+hipError_t launch_transmit(const Items& it, const Pairs& pr, int n_steps, const double2* T,
+                           const double2* hist, const double* scale, double2* F,
+                           hipStream_t st);
+hipError_t launch_transmit_const(const Items& it, const Pairs& pr, int n_steps,
+                                 const double2* T, const double2* c0, double2* F,
+                                 hipStream_t st);
+hipError_t launch_fill_history(const Items& it, int n_steps, const double2* c0, double2* hist,
+                               hipStream_t st);
+hipError_t launch_forcing_from_nodes(const Items& it, const Nodes& nd, int n_steps,
+                                     const double2* g, double2* F, hipStream_t st);
+hipError_t launch_residual(const Items& it, int n_steps, double dt, const double* G,
+                           const double2* cur, const double2* prev, double* partial,
+                           double* out, hipStream_t st);
+hipError_t launch_ie_step(const Items& it, int n, int n_steps, double dt, const double* A,
+                          const double* W, const double2* Minv, const double2* F,
+                          double2* hist, double* partial, double* nus, int* flags,
+                          hipStream_t st);
+hipError_t launch_ie_finish(const Items& it, int n_steps, double2* hist, const double* partial,
+                            double* nus, hipStream_t st);
+hipError_t launch_global_normalise(const Items& it, const double* W, double2* c0,
+                                   double* partial, hipStream_t st);
+hipError_t launch_geneig(const Items& it, const double* A, const double* Hr, double* lam,
+                         double* X, int* flags, hipStream_t st);
+hipError_t launch_reconstruct(const Items& it, int geom, int step, int n_steps,
+                              const double2* hist, const double* pts, int64_t n_pts,
+                              double2* out, hipStream_t st);
+
+}  // namespace swr

@@ -1,0 +1,1142 @@
+// HIP kernels (gfx950) of the SWR-Galerkin hot path.
+//
+// Layout conventions (all FP64, complex = double2 interleaved):
+//   real matrices of item s: K_s x K_s row-major at off2[s];
+//   histories / Robin data vectors: item s block of (n_steps+1) x K_s
+//   entries, time-major, at (n_steps+1) * off1[s];
+//   inverse Crank-Nicolson matrices: item s, matrix n, stored transposed
+//   (column m of the inverse contiguous) at n_mats * off2[s] + n * K_s^2.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels.h"
+
+namespace swr {
+namespace {
+
+constexpr int kFlagNaN = 1;
+constexpr int kFlagPivot = 2;
+
+__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a*b + c
+__device__ inline double2 cfma(double2 a, double2 b, double2 c) {
+  return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+}
+__device__ inline double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ inline double2 crecip(double2 a) {
+  // 1/a with scaling against overflow
+  if (fabs(a.x) >= fabs(a.y)) {
+    double r = a.y / a.x, d = a.x + a.y * r;
+    return make_double2(1.0 / d, -r / d);
+  }
+  double r = a.x / a.y, d = a.y + a.x * r;
+  return make_double2(r / d, -1.0 / d);
+}
+__device__ inline bool cfinite(double2 a) { return isfinite(a.x) && isfinite(a.y); }
+
+// erf(uh) - erf(ul), ul <= uh, with the complementary function in the tails
+__device__ inline double erf_diff(double ul, double uh) {
+  if (ul > 0.0) return erfc(ul) - erfc(uh);
+  if (uh < 0.0) return erfc(-uh) - erfc(-ul);
+  return erf(uh) - erf(ul);
+}
+
+// One-dimensional integrals of phi_a phi_b over [lo, hi] (Gaussian product
+// rule): overlap S, position X, kinetic T = 1/2 int phi_a' phi_b'.
+__device__ inline void pair_integrals(double aa, double da, double ab, double db, double lo,
+                                      double hi, double* S, double* X, double* T) {
+  const double p = da + db;
+  const double P = (da * aa + db * ab) / p;
+  const double E = exp(-da * db * (aa - ab) * (aa - ab) / p);
+  const double sp = sqrt(p);
+  const double ul = sp * (lo - P), uh = sp * (hi - P);
+  const double I0 = 0.5 * sqrt(M_PI / p) * erf_diff(ul, uh);
+  const double el = exp(-ul * ul), eh = exp(-uh * uh);
+  const double I1 = (el - eh) / (2.0 * p);
+  const double I2 = I0 / (2.0 * p) - ((hi - P) * eh - (lo - P) * el) / (2.0 * p);
+  *S = E * I0;
+  if (X) *X = E * (P * I0 + I1);
+  if (T) *T = 2.0 * da * db * E * (I2 + (2.0 * P - aa - ab) * I1 + (P - aa) * (P - ab) * I0);
+}
+
+__device__ inline double pair_overlap(double aa, double da, double ab, double db, double lo,
+                                      double hi) {
+  double S;
+  pair_integrals(aa, da, ab, db, lo, hi, &S, nullptr, nullptr);
+  return S;
+}
+
+// split flat basis index (last dimension fastest) into per-dim indices
+__device__ inline void split_index(int l, const int32_t* nb, int D, int* li) {
+  for (int k = D - 1; k >= 0; --k) {
+    li[k] = l % nb[k];
+    l /= nb[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Assembly of the separable matrices (Section 1.2 Galerkin form, Section 4.1
+// eq. Q, Robin boundary mass, partition-of-unity mass).
+__global__ void k_assemble(Items it, double* A, double* Kin, double* Q, double* B, double* W,
+                           double* S1, const int64_t* s1off) {
+  const int s = blockIdx.y;
+  const int K = it.K[s];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= K * K) return;
+  const int l = e / K, m = e % K;
+  const int D = it.D;
+  const int32_t* nb = it.nb + 4 * s;
+  int li[4], mi[4];
+  split_index(l, nb, D, li);
+  split_index(m, nb, D, mi);
+  double Sk[4], Xk[4], Tk[4], Bk[4], Wk[4];
+  for (int k = 0; k < D; ++k) {
+    const double lo = it.lo[4 * s + k], hi = it.hi[4 * s + k], d = it.delta[4 * s + k];
+    const double* al = it.alpha + it.aoff[4 * s + k];
+    const double aa = al[li[k]], ab = al[mi[k]];
+    pair_integrals(aa, d, ab, d, lo, hi, &Sk[k], &Xk[k], &Tk[k]);
+    const double fla = exp(-d * (lo - aa) * (lo - aa)), flb = exp(-d * (lo - ab) * (lo - ab));
+    const double fha = exp(-d * (hi - aa) * (hi - aa)), fhb = exp(-d * (hi - ab) * (hi - ab));
+    Bk[k] = fla * flb + fha * fhb;
+    double w = Sk[k];
+    const double eps = it.eps[k];
+    if (it.idx[4 * s + k] > 0) w -= 0.5 * pair_overlap(aa, d, ab, d, lo, lo + eps);
+    if (it.idx[4 * s + k] < it.L[k] - 1) w -= 0.5 * pair_overlap(aa, d, ab, d, hi - eps, hi);
+    Wk[k] = w;
+  }
+  double a = 1.0, wprod = 1.0, kin = 0.0, bsum = 0.0, q = 0.0;
+  for (int k = 0; k < D; ++k) {
+    a *= Sk[k];
+    wprod *= Wk[k];
+    double tk = Tk[k], bk = Bk[k];
+    for (int k2 = 0; k2 < D; ++k2)
+      if (k2 != k) { tk *= Sk[k2]; bk *= Sk[k2]; }
+    kin += tk;
+    bsum += bk;
+  }
+  for (int el = 0; el < it.n_elec; ++el) {
+    const int km = el * it.dim + it.axis;
+    double x = Xk[km];
+    for (int k2 = 0; k2 < D; ++k2)
+      if (k2 != km) x *= Sk[k2];
+    q += x;
+  }
+  const int64_t o = it.off2[s] + (int64_t)l * K + m;
+  A[o] = a;
+  Kin[o] = kin;
+  Q[o] = q;
+  B[o] = bsum;
+  W[o] = wprod;
+  // per-dimension overlap factors, written by the entry whose other indices are 0
+  for (int k = 0; k < D; ++k) {
+    bool base = true;
+    for (int k2 = 0; k2 < D; ++k2)
+      if (k2 != k && (li[k2] != 0 || mi[k2] != 0)) base = false;
+    if (base) S1[s1off[4 * s + k] + (int64_t)li[k] * nb[k] + mi[k]] = Sk[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Soft-Coulomb potential matrix (eq. pseudo): electron-nucleus terms as
+// one-dimensional Gauss-Legendre sums, the electron-electron term as the
+// contraction chain sum_{q0} F0[a0 b0, q0] sum_{q1} F1[a1 b1, q1] U(q0, q1).
+// One block per item; one space dimension per electron.
+__global__ void k_potential(Items it, Potential pot, const double* S1, const int64_t* s1off,
+                            double* V, double* scratch, const int64_t* scratch_off) {
+  const int s = blockIdx.x;
+  const int K = it.K[s];
+  const int D = it.D;
+  const int N = it.n_elec;
+  const int geom = s / it.n_sub;
+  const int32_t* nb = it.nb + 4 * s;
+  __shared__ double v1[2 * kSmallK * kSmallK];  // e-n tables, one per electron (D <= 2)
+  int v1off[4];
+  {
+    int o = 0;
+    for (int k = 0; k < D; ++k) { v1off[k] = o; o += nb[k] * nb[k]; }
+  }
+  // phase A: e-n one-dimensional tables
+  for (int el = 0; el < N; ++el) {
+    const int k = el;  // dim == 1
+    const int n = nb[k];
+    const double d = it.delta[4 * s + k];
+    const double* al = it.alpha + it.aoff[4 * s + k];
+    const double* qx = it.qx + it.qoff[4 * s + k];
+    const double* qw = it.qw + it.qoff[4 * s + k];
+    const int nq = it.qn[4 * s + k];
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+      const int a = e / n, b = e % n;
+      double acc = 0.0;
+      if (pot.n_nuc > 0) {
+        for (int q = 0; q < nq; ++q) {
+          const double x = qx[q];
+          double u = 0.0;
+          for (int A = 0; A < pot.n_nuc; ++A) {
+            const double r = x - pot.pos[(geom * pot.n_nuc + A) * it.dim];
+            u -= pot.charge[A] / sqrt(r * r + pot.eps_en * pot.eps_en);
+          }
+          acc += qw[q] * u * exp(-d * (x - al[a]) * (x - al[a])) * exp(-d * (x - al[b]) * (x - al[b]));
+        }
+      }
+      v1[v1off[k] + e] = acc;
+    }
+  }
+  // phase B: e-e contraction (two electrons in one dimension each)
+  double* T1 = scratch + scratch_off[s];
+  if (N == 2) {
+    const int n0 = nb[0], n1 = nb[1];
+    const double d0 = it.delta[4 * s + 0], d1 = it.delta[4 * s + 1];
+    const double* al1 = it.alpha + it.aoff[4 * s + 1];
+    const double* qx0 = it.qx + it.qoff[4 * s + 0];
+    const double* qx1 = it.qx + it.qoff[4 * s + 1];
+    const double* qw1 = it.qw + it.qoff[4 * s + 1];
+    const int nq0 = it.qn[4 * s + 0], nq1 = it.qn[4 * s + 1];
+    const double ee2 = pot.eps_ee * pot.eps_ee;
+    for (int e = threadIdx.x; e < nq0 * n1 * n1; e += blockDim.x) {
+      const int q0 = e / (n1 * n1), a1 = (e / n1) % n1, b1 = e % n1;
+      const double x0 = qx0[q0];
+      double acc = 0.0;
+      for (int q1 = 0; q1 < nq1; ++q1) {
+        const double x1 = qx1[q1];
+        const double r = x0 - x1;
+        acc += qw1[q1] * exp(-d1 * (x1 - al1[a1]) * (x1 - al1[a1])) *
+               exp(-d1 * (x1 - al1[b1]) * (x1 - al1[b1])) / sqrt(r * r + ee2);
+      }
+      T1[e] = acc;
+    }
+    (void)d0;
+    (void)n0;
+  }
+  __syncthreads();
+  // phase C: combine into the full matrix
+  for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
+    const int l = e / K, m = e % K;
+    int li[4], mi[4];
+    split_index(l, nb, D, li);
+    split_index(m, nb, D, mi);
+    double v = 0.0;
+    for (int el = 0; el < N; ++el) {
+      double t = v1[v1off[el] + li[el] * nb[el] + mi[el]];
+      for (int k2 = 0; k2 < D; ++k2)
+        if (k2 != el) t *= S1[s1off[4 * s + k2] + (int64_t)li[k2] * nb[k2] + mi[k2]];
+      v += t;
+    }
+    if (N == 2) {
+      const int n1 = nb[1];
+      const double d0 = it.delta[4 * s + 0];
+      const double* al0 = it.alpha + it.aoff[4 * s + 0];
+      const double* qx0 = it.qx + it.qoff[4 * s + 0];
+      const double* qw0 = it.qw + it.qoff[4 * s + 0];
+      const int nq0 = it.qn[4 * s + 0];
+      const int p1 = li[1] * n1 + mi[1];
+      double acc = 0.0;
+      for (int q0 = 0; q0 < nq0; ++q0) {
+        const double x0 = qx0[q0];
+        acc += qw0[q0] * exp(-d0 * (x0 - al0[li[0]]) * (x0 - al0[li[0]])) *
+               exp(-d0 * (x0 - al0[mi[0]]) * (x0 - al0[mi[0]])) * T1[(int64_t)q0 * n1 * n1 + p1];
+      }
+      v += acc;
+    }
+    V[it.off2[s] + e] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Basis values at a point: v_l(y) = prod_k phi_{l_k}(y_k)
+__device__ inline double basis_value(const Items& it, int s, int l, const double* y) {
+  const int32_t* nb = it.nb + 4 * s;
+  int li[4];
+  split_index(l, nb, it.D, li);
+  double v = 1.0;
+  for (int k = 0; k < it.D; ++k) {
+    const double a = it.alpha[it.aoff[4 * s + k] + li[k]];
+    const double d = it.delta[4 * s + k];
+    v *= exp(-d * (y[k] - a) * (y[k] - a));
+  }
+  return v;
+}
+
+// Robin transfer operators (Section 4.1: averaged Robin data over O(y),
+// eq. RTC with the outward normal of the receiving subdomain):
+// T_ij[l][m] = sum_{y: j in O(y)} w_y / |O(y)| v_l^i(y) (n.grad + mu) v_m^j(y)
+__global__ void k_transfer(Items it, Nodes nd, Pairs pr, double mu_re, double mu_im, double2* T) {
+  const int p = blockIdx.y;
+  const int i = pr.pi[p], j = pr.pj[p];
+  const int Ki = it.K[i], Kj = it.K[j];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= Ki * Kj) return;
+  const int l = e / Kj, m = e % Kj;
+  const int D = it.D;
+  int mi[4];
+  split_index(m, it.nb + 4 * j, D, mi);
+  double2 acc = make_double2(0.0, 0.0);
+  for (int64_t t = pr.noff[p]; t < pr.noff[p + 1]; ++t) {
+    const int q = pr.node[t];
+    const double* y = nd.x + 4 * (int64_t)q;
+    const int face = nd.face[q];
+    const int kf = face >> 1;
+    const double sign = (face & 1) ? 1.0 : -1.0;
+    const double vi = basis_value(it, i, l, y);
+    double vj = 1.0;
+    for (int k = 0; k < D; ++k) {
+      const double a = it.alpha[it.aoff[4 * j + k] + mi[k]];
+      const double d = it.delta[4 * j + k];
+      vj *= exp(-d * (y[k] - a) * (y[k] - a));
+    }
+    const double aj = it.alpha[it.aoff[4 * j + kf] + mi[kf]];
+    const double dj = -2.0 * it.delta[4 * j + kf] * (y[kf] - aj) * vj;
+    const double c = nd.w[q] / nd.count[q] * vi;
+    acc.x += c * (sign * dj + mu_re * vj);
+    acc.y += c * (mu_im * vj);
+  }
+  T[pr.toff[p] + e] = acc;
+}
+
+// Face Gram matrices G[l][m] = sum over every face node of w_y v_l v_m
+// (residual of eq. residueRT in coefficient form).
+__global__ void k_face_gram(Items it, Nodes nd, double* G) {
+  const int s = blockIdx.y;
+  const int K = it.K[s];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= K * K) return;
+  const int l = e / K, m = e % K;
+  double acc = 0.0;
+  for (int64_t q = nd.off[s]; q < nd.off[s + 1]; ++q) {
+    const double* y = nd.x + 4 * q;
+    acc += nd.w[q] * basis_value(it, s, l, y) * basis_value(it, s, m, y);
+  }
+  G[it.off2[s] + e] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Projection of the Gaussian Cauchy data (Section 4.4 step 1, Test 1.a):
+// c~_l = <phi_0, v_l>_{Omega_i}, then A c = c~ by elimination in LDS (A is
+// symmetric positive definite).
+__global__ void k_project(Items it, const double* A, double init_alpha, const double* center,
+                          double2* c0, int* flags) {
+  const int s = blockIdx.x;
+  const int K = it.K[s];
+  const int D = it.D;
+  __shared__ double a[kSmallK * kSmallK];
+  __shared__ double b[kSmallK];
+  for (int e = threadIdx.x; e < K * K; e += blockDim.x) a[e] = A[it.off2[s] + e];
+  const double norm = pow(2.0 * init_alpha / M_PI, 0.25 * D);
+  for (int l = threadIdx.x; l < K; l += blockDim.x) {
+    int li[4];
+    split_index(l, it.nb + 4 * s, D, li);
+    double v = norm;
+    for (int k = 0; k < D; ++k) {
+      const double al = it.alpha[it.aoff[4 * s + k] + li[k]];
+      v *= pair_overlap(al, it.delta[4 * s + k], center[k], init_alpha, it.lo[4 * s + k],
+                        it.hi[4 * s + k]);
+    }
+    b[l] = v;
+  }
+  __syncthreads();
+  // forward elimination without pivoting
+  for (int p = 0; p < K; ++p) {
+    const double piv = a[p * K + p];
+    if (threadIdx.x == 0 && !(fabs(piv) > 0.0)) atomicOr(flags, kFlagPivot);
+    for (int e = threadIdx.x; e < (K - p - 1) * (K - p); e += blockDim.x) {
+      const int r = p + 1 + e / (K - p);
+      const int c = p + e % (K - p);
+      if (c == p) continue;
+      a[r * K + c] -= a[r * K + p] / piv * a[p * K + c];
+    }
+    __syncthreads();
+    for (int r = p + 1 + threadIdx.x; r < K; r += blockDim.x) {
+      b[r] -= a[r * K + p] / piv * b[p];
+      a[r * K + p] = 0.0;
+    }
+    __syncthreads();
+  }
+  // back substitution (single thread: K <= 64, once per geometry)
+  if (threadIdx.x == 0) {
+    for (int r = K - 1; r >= 0; --r) {
+      double v = b[r];
+      for (int c = r + 1; c < K; ++c) v -= a[r * K + c] * b[c];
+      b[r] = v / a[r * K + r];
+    }
+  }
+  __syncthreads();
+  for (int l = threadIdx.x; l < K; l += blockDim.x) {
+    c0[it.off1[s] + l] = make_double2(b[l], 0.0);
+    if (!isfinite(b[l])) atomicOr(flags, kFlagNaN);
+  }
+}
+
+// Real parts of the Crank-Nicolson pencil (or the implicit Euler matrix):
+//   TDSE: Ar = A - (tau mu_im / 2) B, Ap = A + (tau mu_im / 2) B,
+//         Hr = Kin + V + (mu_re / 2) B, so that
+//         M^n = Ar + i tau (Hr + E_n Q), R^n = Ap - i tau (Hr + E_n Q);
+//   TISE: Hr as above, Ar = A + dt Hr, Ap = A.
+__global__ void k_cn_matrices(int64_t n, const double* A, const double* Kin, const double* V,
+                              const double* B, double tau, double mu_re, double mu_im,
+                              double* Ar, double* Ap, double* Hr, int tise, double dt) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const double h = Kin[e] + V[e] + 0.5 * mu_re * B[e];
+  Hr[e] = h;
+  if (tise) {
+    Ar[e] = A[e] + dt * h;
+    Ap[e] = A[e];
+  } else {
+    Ar[e] = A[e] - 0.5 * tau * mu_im * B[e];
+    Ap[e] = A[e] + 0.5 * tau * mu_im * B[e];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batched inversion of the local Crank-Nicolson matrices
+// M = Ar + i tau (Hr + E Q) (TDSE) or M = Ar (TISE), one block per (matrix,
+// item), Gauss-Jordan elimination in LDS without pivoting (the Hermitian part
+// Ar is positive definite, so every pivot is non-zero).  Stores the inverse
+// transposed: out[m*K + r] = Minv[r][m].
+__global__ void __launch_bounds__(kBlock) k_invert(Items it, int n_mats, const double* Ar,
+                                                   const double* Hr, const double* Q,
+                                                   const double* Eall, double tau, int tise,
+                                                   double2* Minv, int* flags) {
+  const int n = blockIdx.x;
+  const int s = blockIdx.y;
+  const int K = it.K[s];
+  __shared__ double2 a[kSmallK * kSmallK];
+  __shared__ double2 colp[kSmallK];
+  const int64_t o2 = it.off2[s];
+  const double E = tise ? 0.0 : Eall[n + 1];
+  for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
+    const double re = Ar[o2 + e];
+    const double im = tise ? 0.0 : tau * (Hr[o2 + e] + E * Q[o2 + e]);
+    a[e] = make_double2(re, im);
+  }
+  __syncthreads();
+  for (int p = 0; p < K; ++p) {
+    const double2 piv = a[p * K + p];
+    const double2 inv = crecip(piv);
+    if (threadIdx.x == 0 && !(piv.x != 0.0 || piv.y != 0.0)) atomicOr(flags, kFlagPivot);
+    // save column p, scale row p
+    for (int r = threadIdx.x; r < K; r += blockDim.x) colp[r] = a[r * K + p];
+    __syncthreads();
+    for (int c = threadIdx.x; c < K; c += blockDim.x)
+      a[p * K + c] = (c == p) ? inv : cmul(a[p * K + c], inv);
+    __syncthreads();
+    for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
+      const int r = e / K, c = e % K;
+      if (r == p) continue;
+      const double2 f = colp[r];
+      if (c == p)
+        a[e] = make_double2(-(f.x * inv.x - f.y * inv.y), -(f.x * inv.y + f.y * inv.x));
+      else
+        a[e] = csub(a[e], cmul(f, a[p * K + c]));
+    }
+    __syncthreads();
+  }
+  double2* out = Minv + (int64_t)n_mats * o2 + (int64_t)n * K * K;
+  for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
+    const int r = e / K, c = e % K;
+    out[(int64_t)c * K + r] = a[e];
+    if (!cfinite(a[e])) atomicOr(flags, kFlagNaN);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Crank-Nicolson recurrence over the window (Section 4.4 step 2), one block
+// per item, 4 waves: wave w owns a quarter of the columns of every product.
+//   rhs = Ap c^n - i tau (Hr + E_n Q) c^n + (i tau / 2)(f^n + f^{n+1})
+//   c^{n+1} = (M^{n+1})^{-1} rhs
+__global__ void __launch_bounds__(kBlock) k_cn_recur(Items it, int n_steps, const double* Ap,
+                                                     const double* Hr, const double* Q,
+                                                     const double* Eall, double tau,
+                                                     const double2* Minv, const double2* c0,
+                                                     const double2* F, double2* hist, int* flags) {
+  const int s = blockIdx.x;
+  const int K = it.K[s];
+  __shared__ double sA[kSmallK * kSmallK];
+  __shared__ double sH[kSmallK * kSmallK];
+  __shared__ double sQ[kSmallK * kSmallK];
+  __shared__ double2 c[kSmallK];
+  __shared__ double2 rhs[kSmallK];
+  __shared__ double2 part[4][kSmallK];
+  const int64_t o2 = it.off2[s];
+  for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
+    sA[e] = Ap[o2 + e];
+    sH[e] = Hr[o2 + e];
+    sQ[e] = Q[o2 + e];
+  }
+  const int64_t hbase = (int64_t)(n_steps + 1) * it.off1[s];
+  for (int r = threadIdx.x; r < K; r += blockDim.x) {
+    c[r] = c0[it.off1[s] + r];
+    hist[hbase + r] = c[r];
+  }
+  __syncthreads();
+  const int r = threadIdx.x & 63;
+  const int pw = threadIdx.x >> 6;
+  const int cs = (K + 3) / 4;
+  const int m0 = pw * cs, m1 = min(K, m0 + cs);
+  const double2* Mbase = Minv + (int64_t)n_steps * o2;
+  for (int n = 0; n < n_steps; ++n) {
+    const double E = Eall[n];
+    if (r < K) {
+      double2 a = make_double2(0.0, 0.0), h = make_double2(0.0, 0.0);
+      for (int m = m0; m < m1; ++m) {
+        const double2 cm = c[m];
+        const double am = sA[m * K + r];
+        const double hm = sH[m * K + r] + E * sQ[m * K + r];
+        a.x = fma(am, cm.x, a.x);
+        a.y = fma(am, cm.y, a.y);
+        h.x = fma(hm, cm.x, h.x);
+        h.y = fma(hm, cm.y, h.y);
+      }
+      // a - i tau h
+      part[pw][r] = make_double2(a.x + tau * h.y, a.y - tau * h.x);
+    }
+    __syncthreads();
+    if (pw == 0 && r < K) {
+      double2 v = cadd(cadd(part[0][r], part[1][r]), cadd(part[2][r], part[3][r]));
+      const double2 f0 = F[hbase + (int64_t)n * K + r];
+      const double2 f1 = F[hbase + (int64_t)(n + 1) * K + r];
+      const double2 fs = cadd(f0, f1);
+      // + (i tau / 2) fs
+      v.x -= 0.5 * tau * fs.y;
+      v.y += 0.5 * tau * fs.x;
+      rhs[r] = v;
+    }
+    __syncthreads();
+    if (r < K) {
+      const double2* Mn = Mbase + (int64_t)n * K * K;
+      double2 acc = make_double2(0.0, 0.0);
+      for (int m = m0; m < m1; ++m) acc = cfma(Mn[(int64_t)m * K + r], rhs[m], acc);
+      part[pw][r] = acc;
+    }
+    __syncthreads();
+    if (pw == 0 && r < K) {
+      const double2 v = cadd(cadd(part[0][r], part[1][r]), cadd(part[2][r], part[3][r]));
+      c[r] = v;
+      hist[hbase + (int64_t)(n + 1) * K + r] = v;
+      if (!cfinite(v)) atomicOr(flags, kFlagNaN);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Transmission as a batched complex product: for receiving item i and a tile
+// of time steps, F_i[n][l] = scale_n * sum_{pairs (i,j)} sum_m T_ij[l][m] C_j[n][m].
+constexpr int kTN = 32;
+__global__ void __launch_bounds__(kBlock) k_transmit(Items it, Pairs pr, int n_steps,
+                                                     const double2* T, const double2* hist,
+                                                     const double* scale, double2* F) {
+  const int i = blockIdx.y;
+  const int n0 = blockIdx.x * kTN;
+  const int Ki = it.K[i];
+  __shared__ double2 Ts[kSmallK * kSmallK];  // [m][l]
+  __shared__ double2 Cs[kTN * kSmallK];      // [nn][m]
+  const int l = threadIdx.x & 63;
+  const int nn0 = threadIdx.x >> 6;
+  double2 acc[kTN / 4];
+  for (int q = 0; q < kTN / 4; ++q) acc[q] = make_double2(0.0, 0.0);
+  for (int64_t p = pr.poff[i]; p < pr.poff[i + 1]; ++p) {
+    const int j = pr.pj[p];
+    const int Kj = it.K[j];
+    const double2* Tp = T + pr.toff[p];
+    __syncthreads();
+    for (int e = threadIdx.x; e < Ki * Kj; e += blockDim.x) {
+      const int ll = e / Kj, mm = e % Kj;
+      Ts[mm * Ki + ll] = Tp[e];
+    }
+    const int64_t hb = (int64_t)(n_steps + 1) * it.off1[j];
+    for (int e = threadIdx.x; e < kTN * Kj; e += blockDim.x) {
+      const int nn = e / Kj, mm = e % Kj;
+      const int n = n0 + nn;
+      Cs[e] = (n <= n_steps) ? hist[hb + (int64_t)n * Kj + mm] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    if (l < Ki) {
+      for (int mm = 0; mm < Kj; ++mm) {
+        const double2 t = Ts[mm * Ki + l];
+        for (int q = 0; q < kTN / 4; ++q) acc[q] = cfma(t, Cs[(nn0 + 4 * q) * Kj + mm], acc[q]);
+      }
+    }
+  }
+  if (l < Ki) {
+    const int64_t fb = (int64_t)(n_steps + 1) * it.off1[i];
+    for (int q = 0; q < kTN / 4; ++q) {
+      const int n = n0 + nn0 + 4 * q;
+      if (n > n_steps) continue;
+      const double sc = scale ? scale[n] : 1.0;
+      F[fb + (int64_t)n * Ki + l] = cscale(acc[q], sc);
+    }
+  }
+}
+
+// Robin data of a history that is constant in time (the plain warm start).
+__global__ void k_transmit_const(Items it, Pairs pr, int n_steps, const double2* T,
+                                 const double2* c0, double2* F) {
+  const int i = blockIdx.x;
+  const int Ki = it.K[i];
+  __shared__ double2 f[kSmallK];
+  for (int l = threadIdx.x; l < Ki; l += blockDim.x) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int64_t p = pr.poff[i]; p < pr.poff[i + 1]; ++p) {
+      const int j = pr.pj[p];
+      const int Kj = it.K[j];
+      const double2* Tp = T + pr.toff[p] + (int64_t)l * Kj;
+      const double2* cj = c0 + it.off1[j];
+      for (int m = 0; m < Kj; ++m) acc = cfma(Tp[m], cj[m], acc);
+    }
+    f[l] = acc;
+  }
+  __syncthreads();
+  const int64_t fb = (int64_t)(n_steps + 1) * it.off1[i];
+  for (int64_t e = threadIdx.x; e < (int64_t)(n_steps + 1) * Ki; e += blockDim.x)
+    F[fb + e] = f[e % Ki];
+}
+
+__global__ void k_fill_history(Items it, int n_steps, const double2* c0, double2* hist) {
+  const int s = blockIdx.x;
+  const int K = it.K[s];
+  const int64_t hb = (int64_t)(n_steps + 1) * it.off1[s];
+  for (int64_t e = threadIdx.x; e < (int64_t)(n_steps + 1) * K; e += blockDim.x)
+    hist[hb + e] = c0[it.off1[s] + e % K];
+}
+
+// Robin data given at the receiving face nodes (time-major [n_steps+1][n_nodes]):
+// f_i^n[l] = sum_y w_y g(y, t_n) v_l^i(y).
+__global__ void k_forcing_from_nodes(Items it, Nodes nd, int n_steps, const double2* g,
+                                     double2* F) {
+  const int s = blockIdx.y;
+  const int K = it.K[s];
+  const int n = blockIdx.x;
+  const int64_t fb = (int64_t)(n_steps + 1) * it.off1[s];
+  for (int l = threadIdx.x; l < K; l += blockDim.x) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int64_t q = nd.off[s]; q < nd.off[s + 1]; ++q) {
+      const double c = nd.w[q] * basis_value(it, s, l, nd.x + 4 * q);
+      const double2 gv = g[(int64_t)n * nd.n + q];
+      acc.x = fma(c, gv.x, acc.x);
+      acc.y = fma(c, gv.y, acc.y);
+    }
+    F[fb + (int64_t)n * K + l] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Residual Res(k)^2 = sum_n w_n dt sum_i dc_i^H G_i dc_i (eq. residueRT,
+// trapezoid in time, face Gauss-Legendre in space).  Deterministic two-pass
+// reduction: per (item, time tile) partials, then one block sums them.
+constexpr int kRN = 16;
+__global__ void __launch_bounds__(kBlock) k_residual(Items it, int n_steps, double dt,
+                                                     const double* G, const double2* cur,
+                                                     const double2* prev, double* partial,
+                                                     int n_tiles) {
+  const int s = blockIdx.y;
+  const int tile = blockIdx.x;
+  const int K = it.K[s];
+  __shared__ double g[kSmallK * kSmallK];
+  __shared__ double2 d[kRN][kSmallK];
+  __shared__ double red[kBlock];
+  for (int e = threadIdx.x; e < K * K; e += blockDim.x) g[e] = G[it.off2[s] + e];
+  const int64_t hb = (int64_t)(n_steps + 1) * it.off1[s];
+  for (int e = threadIdx.x; e < kRN * K; e += blockDim.x) {
+    const int nn = e / K, m = e % K;
+    const int n = tile * kRN + nn;
+    d[nn][m] = (n <= n_steps) ? csub(cur[hb + (int64_t)n * K + m], prev[hb + (int64_t)n * K + m])
+                              : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < kRN * K; e += blockDim.x) {
+    const int nn = e / K, r = e % K;
+    const int n = tile * kRN + nn;
+    if (n > n_steps) continue;
+    double2 y = make_double2(0.0, 0.0);
+    for (int m = 0; m < K; ++m) {
+      y.x = fma(g[r * K + m], d[nn][m].x, y.x);
+      y.y = fma(g[r * K + m], d[nn][m].y, y.y);
+    }
+    const double wn = (n == 0 || n == n_steps) ? 0.5 * dt : dt;
+    acc += wn * (d[nn][r].x * y.x + d[nn][r].y * y.y);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[(int64_t)s * n_tiles + tile] = red[0];
+}
+
+__global__ void k_sum_sqrt(const double* partial, int64_t n, double* out) {
+  __shared__ double red[kBlock];
+  double acc = 0.0;
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) acc += partial[e];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sqrt(red[0]);
+}
+
+// ---------------------------------------------------------------------------
+// Imaginary time (Section 4.2 eq. SIT, Section 4.4 step 2 / step 4).
+// One launch per step n -> n+1, one block per item:
+//   nu_n = sqrt(sum_i c~_i^T W_i c~_i) (every block sums the same partials in
+//   the same order), c^n = c~^n / nu_n, then
+//   c~^{n+1} = (A + dt H~)^{-1} (A c^n + (dt/2) f~^{n+1}) and its partial norm.
+__device__ inline double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ inline double norm_from_partials(const double* partial, int n_items, double* red) {
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < n_items; e += blockDim.x) acc += partial[e];
+  return sqrt(block_sum(acc, red));
+}
+
+__global__ void __launch_bounds__(kBlock) k_ie_step(Items it, int n, int n_steps, double dt,
+                                                    const double* A, const double* W,
+                                                    const double2* Minv, const double2* F,
+                                                    double2* hist, double* partial, double* nus,
+                                                    int* flags) {
+  const int s = blockIdx.x;
+  const int K = it.K[s];
+  __shared__ double c[kSmallK];
+  __shared__ double rhs[kSmallK];
+  __shared__ double ct[kSmallK];
+  __shared__ double red[kBlock];
+  const int64_t hb = (int64_t)(n_steps + 1) * it.off1[s];
+  double nu = 1.0;
+  if (n > 0) nu = norm_from_partials(partial + (int64_t)n * it.n_items, it.n_items, red);
+  if (s == 0 && threadIdx.x == 0) nus[n] = nu;
+  for (int r = threadIdx.x; r < K; r += blockDim.x) {
+    const double v = hist[hb + (int64_t)n * K + r].x / nu;
+    c[r] = v;
+    hist[hb + (int64_t)n * K + r] = make_double2(v, 0.0);
+  }
+  __syncthreads();
+  const int64_t o2 = it.off2[s];
+  for (int r = threadIdx.x; r < K; r += blockDim.x) {
+    double v = 0.0;
+    for (int m = 0; m < K; ++m) v = fma(A[o2 + (int64_t)r * K + m], c[m], v);
+    rhs[r] = v + 0.5 * dt * F[hb + (int64_t)(n + 1) * K + r].x;
+  }
+  __syncthreads();
+  const double2* Mi = Minv + o2;  // one (transposed) inverse per item
+  for (int r = threadIdx.x; r < K; r += blockDim.x) {
+    double v = 0.0;
+    for (int m = 0; m < K; ++m) v = fma(Mi[(int64_t)m * K + r].x, rhs[m], v);
+    ct[r] = v;
+    hist[hb + (int64_t)(n + 1) * K + r] = make_double2(v, 0.0);
+    if (!isfinite(v)) atomicOr(flags, kFlagNaN);
+  }
+  __syncthreads();
+  double acc = 0.0;
+  for (int r = threadIdx.x; r < K; r += blockDim.x) {
+    double v = 0.0;
+    for (int m = 0; m < K; ++m) v = fma(W[o2 + (int64_t)r * K + m], ct[m], v);
+    acc += ct[r] * v;
+  }
+  const double tot = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[(int64_t)(n + 1) * it.n_items + s] = tot;
+}
+
+__global__ void k_ie_finish(Items it, int n_steps, double2* hist, const double* partial,
+                            double* nus) {
+  const int s = blockIdx.x;
+  const int K = it.K[s];
+  __shared__ double red[kBlock];
+  const double nu = norm_from_partials(partial + (int64_t)n_steps * it.n_items, it.n_items, red);
+  if (s == 0 && threadIdx.x == 0) nus[n_steps] = nu;
+  const int64_t hb = (int64_t)(n_steps + 1) * it.off1[s];
+  for (int r = threadIdx.x; r < K; r += blockDim.x) {
+    const double v = hist[hb + (int64_t)n_steps * K + r].x / nu;
+    hist[hb + (int64_t)n_steps * K + r] = make_double2(v, 0.0);
+  }
+}
+
+__global__ void k_norm_partials(Items it, const double* W, const double2* c0, double* partial) {
+  const int s = blockIdx.x;
+  const int K = it.K[s];
+  __shared__ double red[kBlock];
+  double acc = 0.0;
+  for (int r = threadIdx.x; r < K; r += blockDim.x) {
+    double v = 0.0;
+    for (int m = 0; m < K; ++m) v = fma(W[it.off2[s] + (int64_t)r * K + m], c0[it.off1[s] + m].x, v);
+    acc += c0[it.off1[s] + r].x * v;
+  }
+  const double tot = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[s] = tot;
+}
+
+__global__ void k_norm_apply(Items it, double2* c0, const double* partial) {
+  const int s = blockIdx.x;
+  const int K = it.K[s];
+  __shared__ double red[kBlock];
+  const double nu = norm_from_partials(partial, it.n_items, red);
+  for (int r = threadIdx.x; r < K; r += blockDim.x) {
+    const double2 v = c0[it.off1[s] + r];
+    c0[it.off1[s] + r] = make_double2(v.x / nu, v.y / nu);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Local generalized eigenproblems H~ x = lambda A x (Section 4.2), one block
+// per item: Cholesky A = L L^T, C = L^{-1} H~ L^{-T}, cyclic Jacobi with a
+// round-robin ordering of disjoint rotations, X = L^{-T} V, ascending sort,
+// sign fixed by the largest-magnitude component.
+__global__ void __launch_bounds__(kBlock) k_geneig(Items it, const double* A, const double* Hr,
+                                                   double* lam, double* X, int* flags) {
+  const int s = blockIdx.x;
+  const int K = it.K[s];
+  __shared__ double L[kSmallK * kSmallK];
+  __shared__ double C[kSmallK * kSmallK];
+  __shared__ double Vv[kSmallK * kSmallK];
+  __shared__ double cs[2 * (kSmallK / 2 + 1)];
+  __shared__ int pp[2 * (kSmallK / 2 + 1)];
+  __shared__ double red[kBlock];
+  __shared__ double evals[kSmallK];
+  const int64_t o2 = it.off2[s];
+  for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
+    L[e] = A[o2 + e];
+    C[e] = Hr[o2 + e];
+    Vv[e] = (e / K == e % K) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  // Cholesky (lower) in place
+  for (int p = 0; p < K; ++p) {
+    if (threadIdx.x == 0) {
+      const double d = L[p * K + p];
+      if (!(d > 0.0)) atomicOr(flags, kFlagPivot);
+      L[p * K + p] = sqrt(d);
+    }
+    __syncthreads();
+    const double dp = L[p * K + p];
+    for (int r = p + 1 + threadIdx.x; r < K; r += blockDim.x) L[r * K + p] /= dp;
+    __syncthreads();
+    for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
+      const int r = e / K, c = e % K;
+      if (r > p && c > p && c <= r) L[e] -= L[r * K + p] * L[c * K + p];
+    }
+    __syncthreads();
+  }
+  // Y = L^{-1} H (columns in parallel), then C = L^{-1} Y^T (symmetric)
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int p = 0; p < K; ++p) {
+      const double dp = L[p * K + p];
+      for (int c = threadIdx.x; c < K; c += blockDim.x) C[p * K + c] /= dp;
+      __syncthreads();
+      for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
+        const int r = e / K, c = e % K;
+        if (r > p) C[e] -= L[r * K + p] * C[p * K + c];
+      }
+      __syncthreads();
+    }
+    // transpose C in place
+    for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
+      const int r = e / K, c = e % K;
+      if (r < c) {
+        const double t = C[e];
+        C[e] = C[c * K + r];
+        C[c * K + r] = t;
+      }
+    }
+    __syncthreads();
+  }
+  // symmetrise against rounding
+  for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
+    const int r = e / K, c = e % K;
+    if (r < c) {
+      const double v = 0.5 * (C[e] + C[c * K + r]);
+      C[e] = v;
+      C[c * K + r] = v;
+    }
+  }
+  __syncthreads();
+  // cyclic Jacobi, round-robin pairing of Kp = K rounded up to even players
+  const int Kp = K + (K & 1);
+  const int npair = Kp / 2;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
+      const int r = e / K, c = e % K;
+      if (r != c) off += C[e] * C[e];
+      else dia += C[e] * C[e];
+    }
+    off = block_sum(off, red);
+    dia = block_sum(dia, red);
+    if (off <= 1e-30 * dia) break;
+    for (int round = 0; round < Kp - 1; ++round) {
+      for (int q = threadIdx.x; q < npair; q += blockDim.x) {
+        auto player = [&](int pos) { return pos == 0 ? 0 : ((pos - 1 + round) % (Kp - 1)) + 1; };
+        int a = player(q), b = player(Kp - 1 - q);
+        if (a > b) { const int t = a; a = b; b = t; }
+        double c = 1.0, sn = 0.0;
+        if (b < K) {
+          const double apq = C[a * K + b];
+          if (apq != 0.0) {
+            const double theta = (C[b * K + b] - C[a * K + a]) / (2.0 * apq);
+            const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            sn = t * c;
+          }
+        }
+        pp[2 * q] = a;
+        pp[2 * q + 1] = b;
+        cs[2 * q] = c;
+        cs[2 * q + 1] = sn;
+      }
+      __syncthreads();
+      // columns of C and V
+      for (int e = threadIdx.x; e < npair * K; e += blockDim.x) {
+        const int q = e / K, r = e % K;
+        const int a = pp[2 * q], b = pp[2 * q + 1];
+        if (b >= K) continue;
+        const double c = cs[2 * q], sn = cs[2 * q + 1];
+        const double xa = C[r * K + a], xb = C[r * K + b];
+        C[r * K + a] = c * xa - sn * xb;
+        C[r * K + b] = sn * xa + c * xb;
+        const double va = Vv[r * K + a], vb = Vv[r * K + b];
+        Vv[r * K + a] = c * va - sn * vb;
+        Vv[r * K + b] = sn * va + c * vb;
+      }
+      __syncthreads();
+      // rows of C
+      for (int e = threadIdx.x; e < npair * K; e += blockDim.x) {
+        const int q = e / K, cc = e % K;
+        const int a = pp[2 * q], b = pp[2 * q + 1];
+        if (b >= K) continue;
+        const double c = cs[2 * q], sn = cs[2 * q + 1];
+        const double xa = C[a * K + cc], xb = C[b * K + cc];
+        C[a * K + cc] = c * xa - sn * xb;
+        C[b * K + cc] = sn * xa + c * xb;
+      }
+      __syncthreads();
+    }
+  }
+  // keep the eigenvalues (diagonal of the rotated matrix), then
+  // X = L^{-T} V by back substitution with the columns in parallel, into C
+  for (int c = threadIdx.x; c < K; c += blockDim.x) evals[c] = C[c * K + c];
+  __syncthreads();
+  for (int e = threadIdx.x; e < K * K; e += blockDim.x) C[e] = Vv[e];
+  __syncthreads();
+  for (int p = K - 1; p >= 0; --p) {
+    const double dp = L[p * K + p];
+    for (int c = threadIdx.x; c < K; c += blockDim.x) C[p * K + c] /= dp;
+    __syncthreads();
+    for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
+      const int r = e / K, c = e % K;
+      if (r < p) C[e] -= L[p * K + r] * C[p * K + c];
+    }
+    __syncthreads();
+  }
+  // ascending order (ties by index) and sign of the largest component
+  for (int c = threadIdx.x; c < K; c += blockDim.x) {
+    int rk = 0;
+    for (int c2 = 0; c2 < K; ++c2)
+      if (evals[c2] < evals[c] || (evals[c2] == evals[c] && c2 < c)) ++rk;
+    int arg = 0;
+    double best = -1.0;
+    for (int r = 0; r < K; ++r)
+      if (fabs(C[r * K + c]) > best) { best = fabs(C[r * K + c]); arg = r; }
+    const double sg = C[arg * K + c] < 0.0 ? -1.0 : 1.0;
+    lam[it.off1[s] + rk] = evals[c];
+    for (int r = 0; r < K; ++r) X[o2 + (int64_t)r * K + rk] = sg * C[r * K + c];
+    if (!isfinite(evals[c])) atomicOr(flags, kFlagNaN);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Reconstruction (Section 4.3): mean of the covering local functions.
+__global__ void k_reconstruct(Items it, int geom, int step, int n_steps, const double2* hist,
+                              const double* pts, int64_t n_pts, double2* out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_pts) return;
+  const int D = it.D;
+  double y[4];
+  for (int k = 0; k < D; ++k) y[k] = pts[t * D + k];
+  double2 acc = make_double2(0.0, 0.0);
+  int cnt = 0;
+  for (int i = 0; i < it.n_sub; ++i) {
+    const int s = geom * it.n_sub + i;
+    bool in = true;
+    for (int k = 0; k < D; ++k)
+      if (!(it.lo[4 * s + k] <= y[k] && y[k] <= it.hi[4 * s + k])) in = false;
+    if (!in) continue;
+    const int K = it.K[s];
+    const double2* c = hist + (int64_t)(n_steps + 1) * it.off1[s] + (int64_t)step * K;
+    double2 v = make_double2(0.0, 0.0);
+    for (int l = 0; l < K; ++l) {
+      const double b = basis_value(it, s, l, y);
+      v.x = fma(b, c[l].x, v.x);
+      v.y = fma(b, c[l].y, v.y);
+    }
+    acc = cadd(acc, v);
+    ++cnt;
+  }
+  out[t] = cnt ? cscale(acc, 1.0 / cnt) : make_double2(0.0, 0.0);
+}
+
+inline unsigned blocks_for(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+// ------------------------------- launchers ---------------------------------
+hipError_t launch_assemble(const Items& it, double* A, double* Kin, double* Q, double* B,
+                           double* W, double* S1, const int64_t* s1off, int K_max,
+                           hipStream_t st) {
+  dim3 grid(blocks_for((int64_t)K_max * K_max), it.n_items);
+  hipLaunchKernelGGL(k_assemble, grid, dim3(kBlock), 0, st, it, A, Kin, Q, B, W, S1, s1off);
+  return hipGetLastError();
+}
+
+hipError_t launch_potential(const Items& it, const Potential& pot, const double* S1,
+                            const int64_t* s1off, double* V, double* scratch,
+                            const int64_t* scratch_off, hipStream_t st) {
+  hipLaunchKernelGGL(k_potential, dim3(it.n_items), dim3(kBlock), 0, st, it, pot, S1, s1off, V,
+                     scratch, scratch_off);
+  return hipGetLastError();
+}
+
+hipError_t launch_transfer(const Items& it, const Nodes& nd, const Pairs& pr, double mu_re,
+                           double mu_im, double2* T, int K_max, hipStream_t st) {
+  if (pr.n == 0) return hipSuccess;
+  dim3 grid(blocks_for((int64_t)K_max * K_max), (unsigned)pr.n);
+  hipLaunchKernelGGL(k_transfer, grid, dim3(kBlock), 0, st, it, nd, pr, mu_re, mu_im, T);
+  return hipGetLastError();
+}
+
+hipError_t launch_face_gram(const Items& it, const Nodes& nd, double* G, int K_max,
+                            hipStream_t st) {
+  dim3 grid(blocks_for((int64_t)K_max * K_max), it.n_items);
+  hipLaunchKernelGGL(k_face_gram, grid, dim3(kBlock), 0, st, it, nd, G);
+  return hipGetLastError();
+}
+
+hipError_t launch_project(const Items& it, const double* A, double init_alpha,
+                          const double* init_center, double2* c0, int* flags, hipStream_t st) {
+  hipLaunchKernelGGL(k_project, dim3(it.n_items), dim3(kBlock), 0, st, it, A, init_alpha,
+                     init_center, c0, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_cn_matrices(int64_t n, const double* A, const double* Kin, const double* V,
+                              const double* B, double tau, double mu_re, double mu_im, double* Ar,
+                              double* Ap, double* Hr, int tise, double dt, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cn_matrices, dim3(blocks_for(n)), dim3(kBlock), 0, st, n, A, Kin, V, B,
+                     tau, mu_re, mu_im, Ar, Ap, Hr, tise, dt);
+  return hipGetLastError();
+}
+
+hipError_t launch_invert(const Items& it, int n_mats, const double* Ar, const double* Hr,
+                         const double* Q, const double* Eall, double tau, int tise,
+                         double2* Minv, int* flags, hipStream_t st) {
+  dim3 grid(n_mats, it.n_items);
+  hipLaunchKernelGGL(k_invert, grid, dim3(kBlock), 0, st, it, n_mats, Ar, Hr, Q, Eall, tau,
+                     tise, Minv, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_cn_recur(const Items& it, int n_steps, const double* Ap, const double* Hr,
+                           const double* Q, const double* Eall, double tau,
+                           const double2* Minv, const double2* c0, const double2* F,
+                           double2* hist, int* flags, hipStream_t st) {
+  hipLaunchKernelGGL(k_cn_recur, dim3(it.n_items), dim3(kBlock), 0, st, it, n_steps, Ap, Hr, Q,
+                     Eall, tau, Minv, c0, F, hist, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_transmit(const Items& it, const Pairs& pr, int n_steps, const double2* T,
+                           const double2* hist, const double* scale, double2* F,
+                           hipStream_t st) {
+  dim3 grid(blocks_for(n_steps + 1, kTN), it.n_items);
+  hipLaunchKernelGGL(k_transmit, grid, dim3(kBlock), 0, st, it, pr, n_steps, T, hist, scale, F);
+  return hipGetLastError();
+}
+
+hipError_t launch_transmit_const(const Items& it, const Pairs& pr, int n_steps,
+                                 const double2* T, const double2* c0, double2* F,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(k_transmit_const, dim3(it.n_items), dim3(kBlock), 0, st, it, pr, n_steps,
+                     T, c0, F);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_history(const Items& it, int n_steps, const double2* c0, double2* hist,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_history, dim3(it.n_items), dim3(kBlock), 0, st, it, n_steps, c0, hist);
+  return hipGetLastError();
+}
+
+hipError_t launch_forcing_from_nodes(const Items& it, const Nodes& nd, int n_steps,
+                                     const double2* g, double2* F, hipStream_t st) {
+  dim3 grid(n_steps + 1, it.n_items);
+  hipLaunchKernelGGL(k_forcing_from_nodes, grid, dim3(kBlock), 0, st, it, nd, n_steps, g, F);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(const Items& it, int n_steps, double dt, const double* G,
+                           const double2* cur, const double2* prev, double* partial,
+                           double* out, hipStream_t st) {
+  const int n_tiles = (n_steps + 1 + kRN - 1) / kRN;
+  dim3 grid(n_tiles, it.n_items);
+  hipLaunchKernelGGL(k_residual, grid, dim3(kBlock), 0, st, it, n_steps, dt, G, cur, prev,
+                     partial, n_tiles);
+  hipLaunchKernelGGL(k_sum_sqrt, dim3(1), dim3(kBlock), 0, st, partial,
+                     (int64_t)n_tiles * it.n_items, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ie_step(const Items& it, int n, int n_steps, double dt, const double* A,
+                          const double* W, const double2* Minv, const double2* F,
+                          double2* hist, double* partial, double* nus, int* flags,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_ie_step, dim3(it.n_items), dim3(kBlock), 0, st, it, n, n_steps, dt, A, W,
+                     Minv, F, hist, partial, nus, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_ie_finish(const Items& it, int n_steps, double2* hist, const double* partial,
+                            double* nus, hipStream_t st) {
+  hipLaunchKernelGGL(k_ie_finish, dim3(it.n_items), dim3(kBlock), 0, st, it, n_steps, hist,
+                     partial, nus);
+  return hipGetLastError();
+}
+
+hipError_t launch_global_normalise(const Items& it, const double* W, double2* c0,
+                                   double* partial, hipStream_t st) {
+  hipLaunchKernelGGL(k_norm_partials, dim3(it.n_items), dim3(kBlock), 0, st, it, W, c0, partial);
+  hipLaunchKernelGGL(k_norm_apply, dim3(it.n_items), dim3(kBlock), 0, st, it, c0, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_geneig(const Items& it, const double* A, const double* Hr, double* lam,
+                         double* X, int* flags, hipStream_t st) {
+  hipLaunchKernelGGL(k_geneig, dim3(it.n_items), dim3(kBlock), 0, st, it, A, Hr, lam, X, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_reconstruct(const Items& it, int geom, int step, int n_steps,
+                              const double2* hist, const double* pts, int64_t n_pts,
+                              double2* out, hipStream_t st) {
+  if (n_pts == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reconstruct, dim3(blocks_for(n_pts)), dim3(kBlock), 0, st, it, geom, step,
+                     n_steps, hist, pts, n_pts, out);
+  return hipGetLastError();
+}
+
+}  // namespace swr

@@ -1,0 +1,123 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, validates descriptions, and its host-built geometry and
+covering-set index maps equal the oracle's bit for bit."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle.geometry import Decomposition
+
+pytestmark = pytest.mark.filterwarnings("ignore")
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_1710_02401_amd import swr
+    if not os.path.exists(swr.LIB_PATH):
+        pytest.fail("libswr.so is not built: run __graft_entry__.build() first")
+    swr.load_library()
+    return swr
+
+
+def test_header_declarations_are_exported(S, repo_root):
+    hdr = open(os.path.join(repo_root, "include", "swr.h")).read()
+    declared = set(re.findall(r"\b(swr_[a-z_]+)\s*\(", hdr))
+    lib = S.load_library()
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(S.EXPORTS)
+
+
+def _create(S, cfg):
+    d, keep = S.desc_from_config(cfg)
+    h = ctypes.c_void_p()
+    rc = S.load_library().swr_create(ctypes.byref(d), ctypes.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (dict(L=[0]), -1),
+    (dict(overlap=[12.0]), -1),
+    (dict(dt=0.0), -1),
+    (dict(nbasis=[80]), -2),
+    (dict(mode="tise", mu=[0.0, -1.0]), -1),
+    (dict(field=dict(E0=0.1, omega=1.0, phase=0.0, axis=3)), -1),
+])
+def test_invalid_descriptions_rejected(S, mutate, code):
+    cfg = workloads.tiny_configs()[0]
+    cfg.update(mutate)
+    rc, h = _create(S, cfg)
+    assert rc == code
+    assert S.load_library().swr_last_error(None)
+
+
+def test_unbound_workspace_and_state_errors(S):
+    lib = S.load_library()
+    rc, h = _create(S, workloads.tiny_configs()[0])
+    assert rc == 0
+    assert lib.swr_assemble(h, None) == S.SWR_E_STATE
+    assert lib.swr_sweep(h, None) == S.SWR_E_STATE
+    r = ctypes.c_double()
+    assert lib.swr_transmit(h, ctypes.byref(r), None) == S.SWR_E_STATE
+    # misaligned / too small workspace
+    assert lib.swr_bind_workspace(h, ctypes.c_void_p(0x1001), 1 << 40) == S.SWR_E_ARG
+    assert lib.swr_bind_workspace(h, ctypes.c_void_p(0x100000), 16) == S.SWR_E_SIZE
+    lib.swr_destroy(h)
+
+
+def _oracle_maps(dec):
+    rows = []
+    for s in dec.subs:
+        for F in s.faces:
+            for q in range(F.nodes.shape[0]):
+                row = [-1] * 16
+                if not F.is_global:
+                    c = F.cover[q]
+                    row[0] = len(c)
+                    row[1:1 + len(c)] = [int(v) for v in c]
+                rows.append(row)
+    return np.array(rows, dtype=np.int32)
+
+
+@pytest.mark.parametrize("name", ["tiny-1d", "tiny-2d", "c1-1e-1d", "c2-2e-1d"])
+def test_index_maps_and_boxes_bit_exact(S, name):
+    cfgs = {c["name"]: c for c in workloads.tiny_configs()}
+    cfg = cfgs.get(name) or workloads.get_config(name)
+    lib = S.load_library()
+    rc, h = _create(S, cfg)
+    assert rc == 0
+    info = S.swr_info()
+    assert lib.swr_query(h, ctypes.byref(info)) == 0
+    dec = Decomposition(cfg)
+    assert info.n_items == dec.n_sub
+    bx = np.zeros(info.n_items * 8)
+    assert lib.swr_get_boxes(h, bx.ctypes.data_as(S._c_f64p), bx.size) == 0
+    bx = bx.reshape(-1, 4, 2)
+    for s in dec.subs:
+        for k in range(dec.D):
+            assert bx[s.lin, k, 0] == s.lo[k] and bx[s.lin, k, 1] == s.hi[k]
+    im = np.zeros(info.n_face_nodes * 16, dtype=np.int32)
+    assert lib.swr_get_index_maps(h, im.ctypes.data_as(S._c_i32p), im.size) == 0
+    assert np.array_equal(im.reshape(-1, 16), _oracle_maps(dec))
+    # face nodes: independent Gauss-Legendre constructions agree to rounding
+    x = np.zeros(info.n_face_nodes * 4)
+    w = np.zeros(info.n_face_nodes)
+    assert lib.swr_get_face_nodes(h, x.ctypes.data_as(S._c_f64p), w.ctypes.data_as(S._c_f64p),
+                                  info.n_face_nodes) == 0
+    xr = np.concatenate([F.nodes for s in dec.subs for F in s.faces])
+    wr = np.concatenate([F.weights for s in dec.subs for F in s.faces])
+    assert np.max(np.abs(x.reshape(-1, 4)[:, :dec.D] - xr)) < 1e-14
+    assert np.max(np.abs(w - wr)) < 1e-14
+    # items: sizes and multi-indices
+    it = np.zeros(info.n_items * 10, dtype=np.int32)
+    assert lib.swr_get_items(h, it.ctypes.data_as(S._c_i32p), it.size) == 0
+    it = it.reshape(-1, 10)
+    for s in dec.subs:
+        assert it[s.lin, 0] == s.K
+        assert tuple(it[s.lin, 2:2 + dec.D]) == s.idx
+        assert tuple(it[s.lin, 6:6 + dec.D]) == s.nb
+    lib.swr_destroy(h)
