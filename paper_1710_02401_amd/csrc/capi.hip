@@ -55,7 +55,7 @@ struct swr_handle_s {
   Buf bPI, bPJ, bPOff, bTOff, bPNode, bPNOff;
   Buf bPos, bCharge, bS1Off, bS1, bScrOff, bScr, bCenter;
   Buf bA, bKin, bV, bQ, bB, bW, bG, bAr, bAp, bHr;
-  Buf bT, bC0, bH[2], bF, bMinv, bE, bResPart, bResOut, bIePart, bNus, bFlags;
+  Buf bT, bC0, bH[2], bF, bFs, bMinv, bE, bResPart, bResOut, bIePart, bNus, bFlags;
 
   // state
   bool bound = false, assembled = false, initial = false, warm = false, factored = false;
@@ -196,6 +196,7 @@ void plan_layout(swr_handle h) {
   h->bH[0] = L.add(hist);
   h->bH[1] = L.add(hist);
   h->bF = L.add(hist);
+  h->bFs = L.add(hist);
   h->bMinv = L.add((size_t)h->n_mats * h->sum_K2 * 16);
   h->bE = L.add((h->n_T + 1) * 8);
   h->bResPart = L.add((size_t)h->n_res_tiles * NI * 8);
@@ -244,6 +245,11 @@ int32_t swr_create(const swr_desc* desc, swr_handle* out) {
   Geometry& g = h->g;
   if (g.K_max > swr::kSmallK) {
     g_create_error = "basis size per subdomain exceeds 64 in this build";
+    delete h;
+    return SWR_E_SIZE;
+  }
+  if (g.desc.n_steps > 16384) {
+    g_create_error = "n_steps above 16384 (the field table of a window is staged in LDS)";
     delete h;
     return SWR_E_SIZE;
   }
@@ -466,7 +472,8 @@ int32_t swr_factor(swr_handle h, double t0, void* stream) {
   HIPCHECK(h, swr::launch_invert(h->items(), h->n_mats, h->ptr<double>(h->bAr),
                                  h->ptr<double>(h->bHr), h->ptr<double>(h->bQ),
                                  h->ptr<double>(h->bE), 0.5 * h->g.desc.dt, tise,
-                                 h->ptr<double2>(h->bMinv), h->ptr<int>(h->bFlags), st));
+                                 h->ptr<double2>(h->bMinv), h->ptr<int>(h->bFlags), st,
+                                 h->g.K_max));
   h->factored = true;
   h->t0 = t0;
   return SWR_OK;
@@ -481,11 +488,13 @@ int32_t swr_sweep(swr_handle h, void* stream) {
   const int nxt = 1 - h->cur;
   const int nT = (int)h->n_T;
   if (h->g.desc.mode == SWR_TDSE) {
+    HIPCHECK(h, swr::launch_pair_sums(it, nT, h->g.K_max, h->ptr<double2>(h->bF),
+                                      h->ptr<double2>(h->bFs), st));
     HIPCHECK(h, swr::launch_cn_recur(it, nT, h->ptr<double>(h->bAp), h->ptr<double>(h->bHr),
                                      h->ptr<double>(h->bQ), h->ptr<double>(h->bE),
                                      0.5 * h->g.desc.dt, h->ptr<double2>(h->bMinv),
-                                     h->ptr<double2>(h->bC0), h->ptr<double2>(h->bF), h->hist(nxt),
-                                     h->ptr<int>(h->bFlags), st));
+                                     h->ptr<double2>(h->bC0), h->ptr<double2>(h->bFs),
+                                     h->hist(nxt), h->ptr<int>(h->bFlags), st));
   } else {
     // step 0 of every item is the (normalised) initial state
     HIPCHECK(h, swr::launch_fill_history(it, nT, h->ptr<double2>(h->bC0), h->hist(nxt), st));

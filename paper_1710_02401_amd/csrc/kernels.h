@@ -78,11 +78,14 @@ hipError_t launch_cn_matrices(int64_t n, const double* A, const double* Kin, con
                               double* Ap, double* Hr, int tise, double dt, hipStream_t st);
 hipError_t launch_invert(const Items& it, int n_mats, const double* Ar, const double* Hr,
                          const double* Q, const double* Efield, double tau, int tise,
-                         double2* Minv, int* flags, hipStream_t st);
+                         double2* Minv, int* flags, hipStream_t st, int K_max);
 hipError_t launch_cn_recur(const Items& it, int n_steps, const double* Ap, const double* Hr,
-                           const double* Q, const double* Efield, double tau,
-                           const double2* Minv, const double2* c0, const double2* F,
-                           double2* hist, int* flags, hipStream_t st);
+                           const double* Q, const double* Efield, double tau, const double2* Minv,
+                           const double2* c0, const double2* Fs, double2* hist, int* flags,
+                           hipStream_t st);
+hipError_t launch_pair_sums(const Items& it, int n_steps, int K_max, const double2* F,
+                            double2* Fs, hipStream_t st);
+hipError_t launch_sum_sqrt(const double* partial, int64_t n, double* out, hipStream_t st);
 hipError_t launch_transmit(const Items& it, const Pairs& pr, int n_steps, const double2* T,
                            const double2* hist, const double* scale, double2* F,
                            hipStream_t st);

@@ -393,10 +393,14 @@ __global__ void k_cn_matrices(int64_t n, const double* A, const double* Kin, con
 
 // ---------------------------------------------------------------------------
 // Batched inversion of the local Crank-Nicolson matrices
-// M = Ar + i tau (Hr + E Q) (TDSE) or M = Ar (TISE), one block per (matrix,
-// item), Gauss-Jordan elimination in LDS without pivoting (the Hermitian part
-// Ar is positive definite, so every pivot is non-zero).  Stores the inverse
-// transposed: out[m*K + r] = Minv[r][m].
+// M = Ar + i tau (Hr + E Q) (TDSE) or M = Ar (TISE), one block of 256 threads
+// per (matrix, item).  Gauss-Jordan elimination without pivoting (the
+// Hermitian part Ar is positive definite, so every pivot is non-zero) with
+// the matrix held in registers: thread (TR, TC) owns rows TR*T.., columns
+// TC*T.. (16T >= K; the padding is the identity and never changes).  Each
+// pivot broadcasts its row and column through LDS.  The inverse is stored
+// transposed, out[c*K + r] = Minv[r][c], so that column c is contiguous.
+template <int T>
 __global__ void __launch_bounds__(kBlock) k_invert(Items it, int n_mats, const double* Ar,
                                                    const double* Hr, const double* Q,
                                                    const double* Eall, double tau, int tise,
@@ -404,123 +408,247 @@ __global__ void __launch_bounds__(kBlock) k_invert(Items it, int n_mats, const d
   const int n = blockIdx.x;
   const int s = blockIdx.y;
   const int K = it.K[s];
-  __shared__ double2 a[kSmallK * kSmallK];
-  __shared__ double2 colp[kSmallK];
+  const int TR = threadIdx.x & 15, TC = threadIdx.x >> 4;
+  __shared__ double2 rowp[16 * T];
+  __shared__ double2 colp[16 * T];
   const int64_t o2 = it.off2[s];
   const double E = tise ? 0.0 : Eall[n + 1];
-  for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
-    const double re = Ar[o2 + e];
-    const double im = tise ? 0.0 : tau * (Hr[o2 + e] + E * Q[o2 + e]);
-    a[e] = make_double2(re, im);
-  }
-  __syncthreads();
-  for (int p = 0; p < K; ++p) {
-    const double2 piv = a[p * K + p];
-    const double2 inv = crecip(piv);
-    if (threadIdx.x == 0 && !(piv.x != 0.0 || piv.y != 0.0)) atomicOr(flags, kFlagPivot);
-    // save column p, scale row p
-    for (int r = threadIdx.x; r < K; r += blockDim.x) colp[r] = a[r * K + p];
-    __syncthreads();
-    for (int c = threadIdx.x; c < K; c += blockDim.x)
-      a[p * K + c] = (c == p) ? inv : cmul(a[p * K + c], inv);
-    __syncthreads();
-    for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
-      const int r = e / K, c = e % K;
-      if (r == p) continue;
-      const double2 f = colp[r];
-      if (c == p)
-        a[e] = make_double2(-(f.x * inv.x - f.y * inv.y), -(f.x * inv.y + f.y * inv.x));
-      else
-        a[e] = csub(a[e], cmul(f, a[p * K + c]));
+  double2 a[T][T];
+#pragma unroll
+  for (int i = 0; i < T; ++i) {
+    const int r = TR * T + i;
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+      const int c = TC * T + j;
+      if (r < K && c < K) {
+        const int64_t e = o2 + (int64_t)r * K + c;
+        a[i][j] = make_double2(Ar[e], tise ? 0.0 : tau * (Hr[e] + E * Q[e]));
+      } else {
+        a[i][j] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+      }
     }
-    __syncthreads();
   }
+  bool bad = false;
+  // pivots in groups of T so that the in-tile offset pi is a compile-time
+  // constant (a runtime index into the register tile would spill it)
+  for (int pt = 0; pt * T < K; ++pt) {
+#pragma unroll
+    for (int pi = 0; pi < T; ++pi) {
+      const int p = pt * T + pi;
+      if (p >= K) break;
+      if (TR == pt) {
+#pragma unroll
+        for (int j = 0; j < T; ++j) rowp[TC * T + j] = a[pi][j];
+      }
+      if (TC == pt) {
+#pragma unroll
+        for (int i = 0; i < T; ++i) colp[TR * T + i] = a[i][pi];
+      }
+      __syncthreads();
+      // In-place Gauss-Jordan step as one rank-1 update: with column p of
+      // the matrix replaced by e_p, u = col_p / piv except u_p = 1 - 1/piv,
+      // and v = row_p except v_p = 1, the new matrix is a - u v^T.
+      const double2 piv = rowp[p];
+      bad |= !(piv.x != 0.0 || piv.y != 0.0);
+      const double2 inv = crecip(piv);
+      double2 u[T], v[T];
+#pragma unroll
+      for (int i = 0; i < T; ++i) {
+        const int r = TR * T + i;
+        const double2 ui = cmul(colp[r], inv);
+        u[i] = (r == p) ? make_double2(1.0 - inv.x, -inv.y) : ui;
+      }
+#pragma unroll
+      for (int j = 0; j < T; ++j) {
+        const int c = TC * T + j;
+        v[j] = (c == p) ? make_double2(1.0, 0.0) : rowp[c];
+      }
+#pragma unroll
+      for (int i = 0; i < T; ++i) {
+        const int r = TR * T + i;
+#pragma unroll
+        for (int j = 0; j < T; ++j) {
+          const bool colpiv = (TC * T + j) == p;
+          const double2 base = colpiv ? make_double2(r == p ? 1.0 : 0.0, 0.0) : a[i][j];
+          a[i][j] = make_double2(fma(-u[i].x, v[j].x, fma(u[i].y, v[j].y, base.x)),
+                                 fma(-u[i].x, v[j].y, fma(-u[i].y, v[j].x, base.y)));
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (bad && threadIdx.x == 0) atomicOr(flags, kFlagPivot);
   double2* out = Minv + (int64_t)n_mats * o2 + (int64_t)n * K * K;
-  for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
-    const int r = e / K, c = e % K;
-    out[(int64_t)c * K + r] = a[e];
-    if (!cfinite(a[e])) atomicOr(flags, kFlagNaN);
+  bool nonfinite = false;
+#pragma unroll
+  for (int j = 0; j < T; ++j) {
+    const int c = TC * T + j;
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+      const int r = TR * T + i;
+      if (r < K && c < K) {
+        out[(int64_t)c * K + r] = a[i][j];
+        nonfinite |= !cfinite(a[i][j]);
+      }
+    }
   }
+  if (nonfinite) atomicOr(flags, kFlagNaN);
 }
 
 // ---------------------------------------------------------------------------
 // Crank-Nicolson recurrence over the window (Section 4.4 step 2), one block
-// per item, 4 waves: wave w owns a quarter of the columns of every product.
+// of 512 threads per item (K <= 64).  Thread (r, part) owns row r and the
+// eight columns m = 8 part + j: its entries of the real matrices Ap, Hr, Q
+// stay in registers for the whole window; the inverse matrix and the Robin
+// data sum of step n are prefetched at step n - 2 into the register buffer
+// of parity n % 2 (so no loaded register is ever moved: a move would wait
+// for the load); the sums over the eight parts are DPP butterflies inside
+// groups of eight lanes.
 //   rhs = Ap c^n - i tau (Hr + E_n Q) c^n + (i tau / 2)(f^n + f^{n+1})
 //   c^{n+1} = (M^{n+1})^{-1} rhs
-__global__ void __launch_bounds__(kBlock) k_cn_recur(Items it, int n_steps, const double* Ap,
-                                                     const double* Hr, const double* Q,
-                                                     const double* Eall, double tau,
-                                                     const double2* Minv, const double2* c0,
-                                                     const double2* F, double2* hist, int* flags) {
+constexpr int kRecThreads = 512;
+
+struct RecState {
+  double ap[8], hr[8], qq[8];
+  double2 cm[8];        // c^n at this thread's columns
+};
+
+struct RecPipe {
+  double2 m[8];         // inverse of M^{n+1}: row r, columns m (transposed storage)
+  double2 fs;           // f^n + f^{n+1} at row r
+};
+
+// cross-lane moves inside rows of the wave (DPP, no LDS traffic)
+template <int kCtrl>
+__device__ inline double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), kCtrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), kCtrl, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// sum over each group of eight consecutive lanes, result in every lane:
+// quad_perm [1,0,3,2], quad_perm [2,3,0,1], then row_half_mirror (lane i
+// of a half-row meets lane 7-i, i.e. the other quad)
+__device__ inline double group8_sum(double v) {
+  v += dpp_f64<0xB1>(v);
+  v += dpp_f64<0x4E>(v);
+  v += dpp_f64<0x141>(v);
+  return v;
+}
+
+// Loads of everything step n consumes.  Unconditional, from clamped
+// addresses: entries past K multiply the zero padding of the LDS vectors
+// (columns) or are discarded (rows).
+__device__ inline void prefetch(RecPipe& pp, const double2* Mb, const double2* Fs, int64_t hb,
+                                int n, int n_steps, int K, int r, int part) {
+  const int rr = r < K ? r : K - 1;
+  const int nn = n < n_steps ? n : n_steps - 1;
+  pp.fs = Fs[hb + (int64_t)nn * K + rr];
+  const double2* base = Mb + (int64_t)nn * K * K + rr;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int m = part * 8 + j;
+    pp.m[j] = base[(m < K ? m : K - 1) * K];
+  }
+}
+
+__device__ inline void cn_step(RecState& st, RecPipe& pp, int n, int n_steps, int K, int r,
+                               int part, double tau, const double* sE, const double2* Mb,
+                               const double2* Fs, double2* hist, int64_t hb, double2* sc,
+                               double2* srhs, bool& bad) {
+  const double E = sE[n];
+  double ax = 0.0, ay = 0.0, hx = 0.0, hy = 0.0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const double h = fma(E, st.qq[j], st.hr[j]);
+    ax = fma(st.ap[j], st.cm[j].x, ax);
+    ay = fma(st.ap[j], st.cm[j].y, ay);
+    hx = fma(h, st.cm[j].x, hx);
+    hy = fma(h, st.cm[j].y, hy);
+  }
+  double rx = fma(tau, hy, ax), ry = fma(-tau, hx, ay);  // a - i tau h
+  rx = group8_sum(rx);
+  ry = group8_sum(ry);
+  if (r < K)  // + (i tau / 2)(f^n + f^{n+1})
+    srhs[r] = make_double2(fma(-0.5 * tau, pp.fs.y, rx), fma(0.5 * tau, pp.fs.x, ry));
+  __syncthreads();
+  double ox = 0.0, oy = 0.0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const double2 rm = srhs[part * 8 + j];  // zero padded past K
+    ox = fma(pp.m[j].x, rm.x, fma(-pp.m[j].y, rm.y, ox));
+    oy = fma(pp.m[j].x, rm.y, fma(pp.m[j].y, rm.x, oy));
+  }
+  ox = group8_sum(ox);
+  oy = group8_sum(oy);
+  prefetch(pp, Mb, Fs, hb, n + 2, n_steps, K, r, part);
+  const double2 v = make_double2(ox, oy);
+  if (r < K) sc[r] = v;
+  // Every lane stores (no divergent branch around the store, which would
+  // make the memory-counter waits conservative): the eight lanes of a row
+  // hold the same value, and padding rows r >= K loaded row K-1's data, so
+  // they write bit-identical copies of row K-1.
+  hist[hb + (int64_t)(n + 1) * K + (r < K ? r : K - 1)] = v;
+  bad |= !cfinite(v);
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 8; ++j) st.cm[j] = sc[part * 8 + j];  // zero padded past K
+}
+
+__global__ void __launch_bounds__(kRecThreads) k_cn_recur(Items it, int n_steps, const double* Ap,
+                                                          const double* Hr, const double* Q,
+                                                          const double* Eall, double tau,
+                                                          const double2* Minv, const double2* c0,
+                                                          const double2* Fs, double2* hist,
+                                                          int* flags) {
   const int s = blockIdx.x;
   const int K = it.K[s];
-  __shared__ double sA[kSmallK * kSmallK];
-  __shared__ double sH[kSmallK * kSmallK];
-  __shared__ double sQ[kSmallK * kSmallK];
-  __shared__ double2 c[kSmallK];
-  __shared__ double2 rhs[kSmallK];
-  __shared__ double2 part[4][kSmallK];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int part = lane & 7;
+  const int r = wave * 8 + (lane >> 3);
+  __shared__ double2 sc[kSmallK];
+  __shared__ double2 srhs[kSmallK];
+  extern __shared__ double sE[];  // field at every time node
+  for (int q = threadIdx.x; q <= n_steps; q += blockDim.x) sE[q] = Eall[q];
   const int64_t o2 = it.off2[s];
-  for (int e = threadIdx.x; e < K * K; e += blockDim.x) {
-    sA[e] = Ap[o2 + e];
-    sH[e] = Hr[o2 + e];
-    sQ[e] = Q[o2 + e];
+  const int64_t hb = (int64_t)(n_steps + 1) * it.off1[s];
+  RecState st;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int m = part * 8 + j;
+    const bool v = r < K && m < K;
+    const int64_t e = o2 + (v ? (int64_t)m * K + r : 0);
+    // symmetric matrices: entry (m, r) = entry (r, m)
+    st.ap[j] = v ? Ap[e] : 0.0;
+    st.hr[j] = v ? Hr[e] : 0.0;
+    st.qq[j] = v ? Q[e] : 0.0;
   }
-  const int64_t hbase = (int64_t)(n_steps + 1) * it.off1[s];
-  for (int r = threadIdx.x; r < K; r += blockDim.x) {
-    c[r] = c0[it.off1[s] + r];
-    hist[hbase + r] = c[r];
+  if (threadIdx.x < K) {
+    const double2 v = c0[it.off1[s] + threadIdx.x];
+    sc[threadIdx.x] = v;
+    hist[hb + threadIdx.x] = v;
+  } else if (threadIdx.x < kSmallK) {
+    // padding past K stays zero for the whole window
+    sc[threadIdx.x] = make_double2(0.0, 0.0);
+    srhs[threadIdx.x] = make_double2(0.0, 0.0);
   }
+  const double2* Mb = Minv + (int64_t)n_steps * o2;
+  RecPipe pA, pB;
+  prefetch(pA, Mb, Fs, hb, 0, n_steps, K, r, part);
+  prefetch(pB, Mb, Fs, hb, 1, n_steps, K, r, part);
   __syncthreads();
-  const int r = threadIdx.x & 63;
-  const int pw = threadIdx.x >> 6;
-  const int cs = (K + 3) / 4;
-  const int m0 = pw * cs, m1 = min(K, m0 + cs);
-  const double2* Mbase = Minv + (int64_t)n_steps * o2;
-  for (int n = 0; n < n_steps; ++n) {
-    const double E = Eall[n];
-    if (r < K) {
-      double2 a = make_double2(0.0, 0.0), h = make_double2(0.0, 0.0);
-      for (int m = m0; m < m1; ++m) {
-        const double2 cm = c[m];
-        const double am = sA[m * K + r];
-        const double hm = sH[m * K + r] + E * sQ[m * K + r];
-        a.x = fma(am, cm.x, a.x);
-        a.y = fma(am, cm.y, a.y);
-        h.x = fma(hm, cm.x, h.x);
-        h.y = fma(hm, cm.y, h.y);
-      }
-      // a - i tau h
-      part[pw][r] = make_double2(a.x + tau * h.y, a.y - tau * h.x);
-    }
-    __syncthreads();
-    if (pw == 0 && r < K) {
-      double2 v = cadd(cadd(part[0][r], part[1][r]), cadd(part[2][r], part[3][r]));
-      const double2 f0 = F[hbase + (int64_t)n * K + r];
-      const double2 f1 = F[hbase + (int64_t)(n + 1) * K + r];
-      const double2 fs = cadd(f0, f1);
-      // + (i tau / 2) fs
-      v.x -= 0.5 * tau * fs.y;
-      v.y += 0.5 * tau * fs.x;
-      rhs[r] = v;
-    }
-    __syncthreads();
-    if (r < K) {
-      const double2* Mn = Mbase + (int64_t)n * K * K;
-      double2 acc = make_double2(0.0, 0.0);
-      for (int m = m0; m < m1; ++m) acc = cfma(Mn[(int64_t)m * K + r], rhs[m], acc);
-      part[pw][r] = acc;
-    }
-    __syncthreads();
-    if (pw == 0 && r < K) {
-      const double2 v = cadd(cadd(part[0][r], part[1][r]), cadd(part[2][r], part[3][r]));
-      c[r] = v;
-      hist[hbase + (int64_t)(n + 1) * K + r] = v;
-      if (!cfinite(v)) atomicOr(flags, kFlagNaN);
-    }
-    __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 8; ++j) st.cm[j] = sc[part * 8 + j];
+  bool bad = false;
+  // unconditional two-step body (a conditional second half would make the
+  // loop-header wait state assume the first buffer was loaded last)
+  int n = 0;
+  for (; n + 1 < n_steps; n += 2) {
+    cn_step(st, pA, n, n_steps, K, r, part, tau, sE, Mb, Fs, hist, hb, sc, srhs, bad);
+    cn_step(st, pB, n + 1, n_steps, K, r, part, tau, sE, Mb, Fs, hist, hb, sc, srhs, bad);
   }
+  if (n < n_steps) cn_step(st, pA, n, n_steps, K, r, part, tau, sE, Mb, Fs, hist, hb, sc, srhs, bad);
+  if (bad) atomicOr(flags, kFlagNaN);
 }
 
 // ---------------------------------------------------------------------------
@@ -571,6 +699,19 @@ __global__ void __launch_bounds__(kBlock) k_transmit(Items it, Pairs pr, int n_s
       F[fb + (int64_t)n * Ki + l] = cscale(acc[q], sc);
     }
   }
+}
+
+// Pair sums f^n + f^{n+1} of the Robin data vectors (the Crank-Nicolson
+// forcing of step n), one thread per entry.
+__global__ void k_pair_sums(int64_t n_entries, const Items it, int n_steps, const double2* F,
+                            double2* Fs) {
+  const int s = blockIdx.y;
+  const int K = it.K[s];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n_steps * K) return;
+  const int64_t b = (int64_t)(n_steps + 1) * it.off1[s];
+  Fs[b + e] = cadd(F[b + e], F[b + e + K]);
+  (void)n_entries;
 }
 
 // Robin data of a history that is constant in time (the plain warm start).
@@ -654,9 +795,9 @@ __global__ void __launch_bounds__(kBlock) k_residual(Items it, int n_steps, doub
     const int n = tile * kRN + nn;
     if (n > n_steps) continue;
     double2 y = make_double2(0.0, 0.0);
-    for (int m = 0; m < K; ++m) {
-      y.x = fma(g[r * K + m], d[nn][m].x, y.x);
-      y.y = fma(g[r * K + m], d[nn][m].y, y.y);
+    for (int m = 0; m < K; ++m) {  // G symmetric: read column m (lanes r contiguous)
+      y.x = fma(g[m * K + r], d[nn][m].x, y.x);
+      y.y = fma(g[m * K + r], d[nn][m].y, y.y);
     }
     const double wn = (n == 0 || n == n_steps) ? 0.5 * dt : dt;
     acc += wn * (d[nn][r].x * y.x + d[nn][r].y * y.y);
@@ -1044,19 +1185,43 @@ hipError_t launch_cn_matrices(int64_t n, const double* A, const double* Kin, con
 
 hipError_t launch_invert(const Items& it, int n_mats, const double* Ar, const double* Hr,
                          const double* Q, const double* Eall, double tau, int tise,
-                         double2* Minv, int* flags, hipStream_t st) {
+                         double2* Minv, int* flags, hipStream_t st, int K_max) {
   dim3 grid(n_mats, it.n_items);
-  hipLaunchKernelGGL(k_invert, grid, dim3(kBlock), 0, st, it, n_mats, Ar, Hr, Q, Eall, tau,
-                     tise, Minv, flags);
+  const int T = (K_max + 15) / 16;
+  if (T <= 1)
+    hipLaunchKernelGGL(k_invert<1>, grid, dim3(kBlock), 0, st, it, n_mats, Ar, Hr, Q, Eall, tau,
+                       tise, Minv, flags);
+  else if (T == 2)
+    hipLaunchKernelGGL(k_invert<2>, grid, dim3(kBlock), 0, st, it, n_mats, Ar, Hr, Q, Eall, tau,
+                       tise, Minv, flags);
+  else if (T == 3)
+    hipLaunchKernelGGL(k_invert<3>, grid, dim3(kBlock), 0, st, it, n_mats, Ar, Hr, Q, Eall, tau,
+                       tise, Minv, flags);
+  else
+    hipLaunchKernelGGL(k_invert<4>, grid, dim3(kBlock), 0, st, it, n_mats, Ar, Hr, Q, Eall, tau,
+                       tise, Minv, flags);
   return hipGetLastError();
 }
 
 hipError_t launch_cn_recur(const Items& it, int n_steps, const double* Ap, const double* Hr,
-                           const double* Q, const double* Eall, double tau,
-                           const double2* Minv, const double2* c0, const double2* F,
-                           double2* hist, int* flags, hipStream_t st) {
-  hipLaunchKernelGGL(k_cn_recur, dim3(it.n_items), dim3(kBlock), 0, st, it, n_steps, Ap, Hr, Q,
-                     Eall, tau, Minv, c0, F, hist, flags);
+                           const double* Q, const double* Eall, double tau, const double2* Minv,
+                           const double2* c0, const double2* Fs, double2* hist, int* flags,
+                           hipStream_t st) {
+  const size_t lds = (size_t)(n_steps + 1) * sizeof(double);
+  hipLaunchKernelGGL(k_cn_recur, dim3(it.n_items), dim3(kRecThreads), lds, st, it, n_steps, Ap, Hr,
+                     Q, Eall, tau, Minv, c0, Fs, hist, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_sums(const Items& it, int n_steps, int K_max, const double2* F,
+                            double2* Fs, hipStream_t st) {
+  dim3 grid(blocks_for((int64_t)n_steps * K_max), it.n_items);
+  hipLaunchKernelGGL(k_pair_sums, grid, dim3(kBlock), 0, st, (int64_t)0, it, n_steps, F, Fs);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_sqrt(const double* partial, int64_t n, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_sqrt, dim3(1), dim3(kBlock), 0, st, partial, n, out);
   return hipGetLastError();
 }
 
