@@ -17,7 +17,8 @@
  *     the default stream).  Calls that return host values (residuals,
  *     energies, run statistics) synchronise that stream before returning.
  *   - Complex numbers are interleaved (re, im) FP64 pairs.  Every floating
- *     point quantity is FP64.  Integers are int32 unless stated.
+ *     point quantity is FP64 except the warm-start network (FP32).  Integers
+ *     are int32 unless stated.
  *   - Items: with n_geom geometries of n_sub = prod(L) subdomains each, item
  *     s = g * n_sub + i (i = linear subdomain index, first dimension
  *     fastest, Section 3.4 / Section 5 indexing Omega_{i+Lj}).
@@ -220,6 +221,71 @@ int32_t swr_local_eigen(swr_handle h, void* lambda_dev, void* vectors_dev, void*
 /* Last TISE normaliser nu of every step of the current iterate, device
  * double [n_steps+1] (nu_0 = 1). */
 int32_t swr_get_norms(swr_handle h, void* dst_dev, uint64_t bytes, void* stream);
+
+/* ---- learned warm start (Section 4.1: psi^(0) of a window is free) ------
+ * The plain guess holds the window's initial Robin data g0 constant; the
+ * learned guess adds a correction predicted at eight time nodes (steps
+ * n_m = round(n_T (1 - cos(pi m/7))/2)) and interpolated to every step with
+ * the barycentric Lagrange form.  RMS_i = sqrt(mean |g0|^2) over item i's
+ * receiving nodes; the window scale S = max_i RMS_i (1 if g0 vanishes).
+ * Network input of item i (n_in entries): (Re, Im) of g0/S node by node,
+ * zero padding to n_in - 16, then 16 tail entries: 10 E(t0 + t_m) for the
+ * eight nodes; the item's box centre as (c_k - mid_k)/half_k of the global
+ * box for k < D, zero padded to four; RMS_i / S; t0 / (8 T) with T the
+ * window length; two zeros.
+ * Network output (n_out entries) = (g(t_m) - g0)/S as [m][node][re, im].
+ * Items' receiving nodes are contiguous in the canonical node order.
+ * The eight rounded nodes are distinct only for n_steps >= 11: on shorter
+ * windows swr_time_nodes and the three swr_learned_* calls return SWR_E_ARG. */
+
+/* Change the field E(t) = E0 sin(omega t + phase) used by later swr_factor. */
+int32_t swr_set_field(swr_handle h, double E0, double omega, double phase);
+/* Start the next window: initial coefficients := last step of the current
+ * iterate, then the plain warm start (as swr_set_initial). */
+int32_t swr_advance_window(swr_handle h, void* stream);
+/* The eight time-node steps (host int32 [8]). */
+int32_t swr_time_nodes(swr_handle h, int32_t* steps_host);
+/* Robin data g(y, t_n) at every receiving node for n_sel <= 16 steps of the
+ * current iterate (device complex [n_sel][n_face_nodes]); 0 on global faces. */
+int32_t swr_face_data(swr_handle h, int32_t n_sel, const int32_t* steps_host, void* g_dev,
+                      void* stream);
+/* Network input (device float [n_items][n_in]) and scale (device double
+ * [n_items], every entry S) from g0 (device complex [n_face_nodes]) for the
+ * window starting at t0.  SWR_E_SIZE if n_in < 2 * max nodes per item + 16. */
+int32_t swr_learned_features(swr_handle h, const void* g0_dev, double t0, int32_t n_in,
+                             float* x_dev, double* scale_dev, void* stream);
+/* Training targets (device float [n_items][n_out]) from the Robin data at
+ * the eight time nodes (device complex [8][n_face_nodes], node 0 = g0). */
+int32_t swr_learned_targets(swr_handle h, const void* g_nodes_dev, const double* scale_dev,
+                            int32_t n_out, float* y_dev, void* stream);
+/* Robin data of the learned guess at every step (device complex
+ * [n_steps+1][n_face_nodes]) from network outputs (device float
+ * [n_items][n_out]); feed it to swr_warm_start(SWR_WARM_GIVEN). */
+int32_t swr_learned_apply(swr_handle h, const float* y_dev, const double* scale_dev,
+                          const void* g0_dev, int32_t n_out, void* g_all_dev, void* stream);
+
+/* Network of the learned warm start: n_layers hidden layers of width
+ * n_hidden with exact-erf GELU, linear output; FP32.  Parameters are one
+ * flat vector, layer by layer: weight (out x in, row-major), then bias.
+ * These calls need no SWR handle; device buffers are caller-owned and the
+ * workspace size comes from swr_mlp_workspace_bytes.  Errors: SWR_E_ARG for
+ * null pointers or invalid sizes, SWR_E_SIZE for a small workspace. */
+typedef struct swr_mlp_desc {
+  int32_t n_in, n_hidden, n_layers, n_out;
+} swr_mlp_desc;
+int32_t swr_mlp_param_count(const swr_mlp_desc* d, int64_t* count);
+int32_t swr_mlp_workspace_bytes(const swr_mlp_desc* d, int32_t batch, uint64_t* bytes);
+/* y = network(x) for a batch (device float [batch][n_in] -> [batch][n_out]). */
+int32_t swr_mlp_forward(const swr_mlp_desc* d, const float* params, const float* x, int32_t batch,
+                        float* y, void* ws_dev, uint64_t ws_bytes, void* stream);
+/* Mean-squared-error loss against t (written to loss_dev[0]) and its
+ * gradient with respect to every parameter (device float [n_params]). */
+int32_t swr_mlp_loss_grad(const swr_mlp_desc* d, const float* params, const float* x,
+                          const float* t, int32_t batch, float* loss_dev, float* grad,
+                          void* ws_dev, uint64_t ws_bytes, void* stream);
+/* One Adam step (step >= 1 for the bias corrections) over n parameters. */
+int32_t swr_mlp_adam(int64_t n, float* params, const float* grad, float* m, float* v,
+                     int32_t step, float lr, float b1, float b2, float eps, void* stream);
 
 /* Pending device error flags (NaN / zero pivot) since the last call:
  * synchronises the stream, returns SWR_E_NAN / SWR_E_SINGULAR or SWR_OK,

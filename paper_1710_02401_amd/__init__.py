@@ -6,5 +6,5 @@ include/swr.h); `swr.Solver` is the thin Python binding.
 """
 from .swr import (  # noqa: F401
     SWR_TDSE, SWR_TISE, SWR_WARM_GIVEN, SWR_WARM_PLAIN, SWR_WARM_ZERO,
-    Solver, SWRError, load_library, desc_from_config, EXPORTS,
+    Solver, Mlp, SWRError, load_library, desc_from_config, EXPORTS,
 )

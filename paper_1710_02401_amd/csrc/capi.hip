@@ -19,6 +19,27 @@ namespace {
 
 thread_local std::string g_create_error;
 
+constexpr int kNodesT = 8;          // time nodes of the learned warm start
+constexpr double kFieldScale = 10.0;  // field feature = 10 E(t)
+
+std::vector<int> time_nodes(int n_T) {
+  std::vector<int> n(kNodesT);
+  const double pi = 3.14159265358979323846;
+  for (int m = 0; m < kNodesT; ++m)
+    n[m] = (int)std::lround(n_T * (1.0 - std::cos(pi * m / (kNodesT - 1))) / 2.0);
+  return n;
+}
+
+// the interpolation needs eight distinct nodes: true for n_T >= 11
+bool distinct_time_nodes(int n_T) {
+  const std::vector<int> n = time_nodes(n_T);
+  for (int m = 1; m < kNodesT; ++m)
+    if (n[m] <= n[m - 1]) return false;
+  return true;
+}
+
+const char* const kShortWindow = "the learned warm start needs n_steps >= 11 (distinct time nodes)";
+
 struct Buf {
   size_t off = 0, bytes = 0;
 };
@@ -45,13 +66,14 @@ struct swr_handle_s {
   int n_res_tiles = 0;
   std::vector<int64_t> s1off, scratch_off;
   std::vector<double> E_host;   // field table, kept alive for the async upload
+  std::vector<double> lag_host; // Lagrange rows of the learned warm start
 
   // workspace
   char* ws = nullptr;
   uint64_t ws_bytes = 0;
   Layout lay;
   Buf bK, bOff1, bOff2, bIdx, bNb, bL, bLo, bHi, bEps, bDelta, bAoff, bAlpha, bQoff, bQn, bQx, bQw;
-  Buf bNItem, bNFace, bNCount, bNX, bNW, bNOff;
+  Buf bNItem, bNFace, bNCount, bNCover, bNX, bNW, bNOff, bLag, bLMax;
   Buf bPI, bPJ, bPOff, bTOff, bPNode, bPNOff;
   Buf bPos, bCharge, bS1Off, bS1, bScrOff, bScr, bCenter;
   Buf bA, bKin, bV, bQ, bB, bW, bG, bAr, bAp, bHr;
@@ -163,6 +185,7 @@ void plan_layout(swr_handle h) {
   h->bNItem = L.add(nn * 4);
   h->bNFace = L.add(nn * 4);
   h->bNCount = L.add(nn * 4);
+  h->bNCover = L.add(nn * 15 * 4);
   h->bNX = L.add(nn * 32);
   h->bNW = L.add(nn * 8);
   h->bNOff = L.add((NI + 1) * 8);
@@ -204,6 +227,8 @@ void plan_layout(swr_handle h) {
   h->bIePart = L.add((size_t)(h->n_T + 1) * NI * 8);
   h->bNus = L.add((h->n_T + 1) * 8);
   h->bFlags = L.add(8);
+  h->bLag = L.add((h->n_T + 1) * kNodesT * 8);
+  h->bLMax = L.add(8);
 }
 
 int check_flags(swr_handle h, hipStream_t st) {
@@ -340,12 +365,13 @@ int32_t swr_assemble(swr_handle h, void* stream) {
     eps4[k] = g.eps[k];
     cen4[k] = g.desc.init_center[k];
   }
-  std::vector<int32_t> nitem, nface, ncount;
+  std::vector<int32_t> nitem, nface, ncount, ncover;
   std::vector<double> nx, nw;
   for (const auto& n : g.nodes) {
     nitem.push_back(n.item);
     nface.push_back(n.face);
     ncount.push_back(n.count);
+    for (int c = 0; c < swr::kMaxCover; ++c) ncover.push_back(n.cover[c]);
     for (int k = 0; k < 4; ++k) nx.push_back(n.x[k]);
     nw.push_back(n.w);
   }
@@ -368,6 +394,35 @@ int32_t swr_assemble(swr_handle h, void* stream) {
   HIPCHECK(h, upload(h, h->bNItem, nitem, st));
   HIPCHECK(h, upload(h, h->bNFace, nface, st));
   HIPCHECK(h, upload(h, h->bNCount, ncount, st));
+  HIPCHECK(h, upload(h, h->bNCover, ncover, st));
+  // barycentric Lagrange rows of the learned warm start's time nodes
+  if (distinct_time_nodes((int)h->n_T)) {
+    const std::vector<int> tn = time_nodes((int)h->n_T);
+    std::vector<double> ts(kNodesT), wb(kNodesT);
+    for (int m = 0; m < kNodesT; ++m) ts[m] = tn[m] * g.desc.dt;
+    for (int m = 0; m < kNodesT; ++m) {
+      double p = 1.0;
+      for (int k2 = 0; k2 < kNodesT; ++k2)
+        if (k2 != m) p *= ts[m] - ts[k2];
+      wb[m] = 1.0 / p;
+    }
+    h->lag_host.assign((size_t)(h->n_T + 1) * kNodesT, 0.0);
+    for (int64_t n = 0; n <= h->n_T; ++n) {
+      const double tt = n * g.desc.dt;
+      double* row = &h->lag_host[(size_t)n * kNodesT];
+      int hit = -1;
+      for (int m = 0; m < kNodesT; ++m)
+        if (tt - ts[m] == 0.0) hit = m;
+      if (hit >= 0) {
+        row[hit] = 1.0;
+      } else {
+        double sum = 0.0;
+        for (int m = 0; m < kNodesT; ++m) sum += (row[m] = wb[m] / (tt - ts[m]));
+        for (int m = 0; m < kNodesT; ++m) row[m] /= sum;
+      }
+    }
+    HIPCHECK(h, upload(h, h->bLag, h->lag_host, st));
+  }
   HIPCHECK(h, upload(h, h->bNX, nx, st));
   HIPCHECK(h, upload(h, h->bNW, nw, st));
   HIPCHECK(h, upload(h, h->bNOff, g.node_off, st));
@@ -674,6 +729,100 @@ int32_t swr_local_eigen(swr_handle h, void* lambda_dev, void* vectors_dev, void*
 int32_t swr_get_norms(swr_handle h, void* dst_dev, uint64_t bytes, void* stream) {
   if (!h) return SWR_E_ARG;
   return copy_out(h, h->bNus, (h->n_T + 1) * 8, dst_dev, bytes, stream);
+}
+
+int32_t swr_set_field(swr_handle h, double E0, double omega, double phase) {
+  if (!h) return SWR_E_ARG;
+  h->g.desc.E0 = E0;
+  h->g.desc.omega = omega;
+  h->g.desc.phase = phase;
+  h->factored = false;
+  return SWR_OK;
+}
+
+int32_t swr_advance_window(swr_handle h, void* stream) {
+  if (!h) return SWR_E_ARG;
+  if (!h->initial || h->k < 1) return fail(h, SWR_E_STATE, "no iterate to advance from");
+  HIPCHECK(h, swr::launch_last_step(h->items(), (int)h->n_T, h->hist(h->cur),
+                                    h->ptr<double2>(h->bC0), (hipStream_t)stream));
+  return swr_warm_start(h, SWR_WARM_PLAIN, nullptr, stream);
+}
+
+int32_t swr_time_nodes(swr_handle h, int32_t* steps_host) {
+  if (!h || !steps_host) return fail(h, SWR_E_ARG, "null argument");
+  if (!distinct_time_nodes((int)h->n_T)) return fail(h, SWR_E_ARG, kShortWindow);
+  const std::vector<int> tn = time_nodes((int)h->n_T);
+  for (int m = 0; m < kNodesT; ++m) steps_host[m] = tn[m];
+  return SWR_OK;
+}
+
+int32_t swr_face_data(swr_handle h, int32_t n_sel, const int32_t* steps_host, void* g_dev,
+                      void* stream) {
+  if (!h || !steps_host || !g_dev) return fail(h, SWR_E_ARG, "null argument");
+  if (n_sel < 1 || n_sel > 16) return fail(h, SWR_E_ARG, "n_sel must be in 1..16");
+  if (!h->initial) return fail(h, SWR_E_STATE, "no coefficients yet");
+  swr::StepList sl{};
+  sl.n = n_sel;
+  for (int i = 0; i < n_sel; ++i) {
+    if (steps_host[i] < 0 || steps_host[i] > h->n_T) return fail(h, SWR_E_ARG, "step out of range");
+    sl.step[i] = steps_host[i];
+  }
+  HIPCHECK(h, swr::launch_face_data(h->items(), h->nodes(), h->ptr<int32_t>(h->bNCover), sl,
+                                    (int)h->n_T, h->g.desc.mu_re, h->g.desc.mu_im,
+                                    h->hist(h->cur), (double2*)g_dev, (hipStream_t)stream));
+  return SWR_OK;
+}
+
+static int max_item_nodes(swr_handle h) {
+  int64_t mx = 0;
+  for (int s = 0; s < h->g.n_items; ++s)
+    mx = std::max<int64_t>(mx, h->g.node_off[s + 1] - h->g.node_off[s]);
+  return (int)mx;
+}
+
+int32_t swr_learned_features(swr_handle h, const void* g0_dev, double t0, int32_t n_in,
+                             float* x_dev, double* scale_dev, void* stream) {
+  if (!h || !g0_dev || !x_dev || !scale_dev) return fail(h, SWR_E_ARG, "null argument");
+  if (!h->assembled) return fail(h, SWR_E_STATE, "swr_assemble first");
+  if (!distinct_time_nodes((int)h->n_T)) return fail(h, SWR_E_ARG, kShortWindow);
+  if (n_in < 2 * max_item_nodes(h) + 16) return fail(h, SWR_E_SIZE, "n_in too small");
+  swr::FieldFeat ff{};
+  ff.n = kNodesT;
+  const std::vector<int> tn = time_nodes((int)h->n_T);
+  for (int m = 0; m < kNodesT; ++m) ff.v[m] = kFieldScale * field(h->g.desc, t0 + tn[m] * h->g.desc.dt);
+  for (int k = 0; k < 4; ++k) {
+    ff.mid[k] = 0.5 * (h->g.desc.box_lo[k] + h->g.desc.box_hi[k]);
+    ff.half[k] = k < h->g.D ? 0.5 * (h->g.desc.box_hi[k] - h->g.desc.box_lo[k]) : 1.0;
+  }
+  ff.t0w = t0 / (8.0 * h->n_T * h->g.desc.dt);
+  HIPCHECK(h, swr::launch_learned_features(h->items(), h->nodes(), (const double2*)g0_dev, ff,
+                                           n_in, x_dev, scale_dev, h->ptr<double>(h->bLMax),
+                                           (hipStream_t)stream));
+  return SWR_OK;
+}
+
+int32_t swr_learned_targets(swr_handle h, const void* g_nodes_dev, const double* scale_dev,
+                            int32_t n_out, float* y_dev, void* stream) {
+  if (!h || !g_nodes_dev || !scale_dev || !y_dev) return fail(h, SWR_E_ARG, "null argument");
+  if (!h->assembled) return fail(h, SWR_E_STATE, "swr_assemble first");
+  if (!distinct_time_nodes((int)h->n_T)) return fail(h, SWR_E_ARG, kShortWindow);
+  if (n_out < 2 * kNodesT * max_item_nodes(h)) return fail(h, SWR_E_SIZE, "n_out too small");
+  HIPCHECK(h, swr::launch_learned_targets(h->items(), h->nodes(), (const double2*)g_nodes_dev,
+                                          kNodesT, scale_dev, n_out, y_dev, (hipStream_t)stream));
+  return SWR_OK;
+}
+
+int32_t swr_learned_apply(swr_handle h, const float* y_dev, const double* scale_dev,
+                          const void* g0_dev, int32_t n_out, void* g_all_dev, void* stream) {
+  if (!h || !y_dev || !scale_dev || !g0_dev || !g_all_dev) return fail(h, SWR_E_ARG, "null argument");
+  if (!h->assembled) return fail(h, SWR_E_STATE, "swr_assemble first");
+  if (!distinct_time_nodes((int)h->n_T)) return fail(h, SWR_E_ARG, kShortWindow);
+  if (n_out < 2 * kNodesT * max_item_nodes(h)) return fail(h, SWR_E_SIZE, "n_out too small");
+  HIPCHECK(h, swr::launch_learned_apply(h->items(), h->nodes(), y_dev, scale_dev,
+                                        (const double2*)g0_dev, h->ptr<double>(h->bLag), kNodesT,
+                                        n_out, (int)h->n_T, (double2*)g_all_dev,
+                                        (hipStream_t)stream));
+  return SWR_OK;
 }
 
 int32_t swr_status_sync(swr_handle h, void* stream) {

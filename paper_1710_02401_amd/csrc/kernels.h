@@ -52,6 +52,19 @@ struct Pairs {
   const int64_t* noff;   // [n+1]
 };
 
+struct StepList {   // up to 16 selected time steps, passed by value
+  int n;
+  int step[16];
+};
+
+struct FieldFeat {  // tail features of the learned warm start, by value
+  int n;              // time nodes (field values in v)
+  double v[16];       // 10 E(t0 + t_m)
+  double mid[4];      // centre of the global box per dimension
+  double half[4];     // half width of the global box per dimension
+  double t0w;         // t0 / (8 T), T the window length
+};
+
 struct Potential {
   int n_nuc;
   const double* pos;     // [n_geom][n_nuc][dim]
@@ -112,5 +125,21 @@ hipError_t launch_geneig(const Items& it, const double* A, const double* Hr, dou
 hipError_t launch_reconstruct(const Items& it, int geom, int step, int n_steps,
                               const double2* hist, const double* pts, int64_t n_pts,
                               double2* out, hipStream_t st);
+
+hipError_t launch_face_data(const Items& it, const Nodes& nd, const int32_t* cover,
+                            const StepList& sl, int n_steps, double mu_re, double mu_im,
+                            const double2* hist, double2* g, hipStream_t st);
+hipError_t launch_learned_features(const Items& it, const Nodes& nd, const double2* g0,
+                                   const FieldFeat& ff, int n_in, float* x, double* scale,
+                                   double* wmax, hipStream_t st);
+hipError_t launch_learned_targets(const Items& it, const Nodes& nd, const double2* gm,
+                                  int n_nodes_t, const double* scale, int n_out, float* y,
+                                  hipStream_t st);
+hipError_t launch_learned_apply(const Items& it, const Nodes& nd, const float* y,
+                                const double* scale, const double2* g0, const double* lag,
+                                int n_nodes_t, int n_out, int n_steps, double2* g_all,
+                                hipStream_t st);
+hipError_t launch_last_step(const Items& it, int n_steps, const double2* hist, double2* c0,
+                            hipStream_t st);
 
 }  // namespace swr

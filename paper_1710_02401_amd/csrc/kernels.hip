@@ -1131,6 +1131,165 @@ __global__ void k_reconstruct(Items it, int geom, int step, int n_steps, const d
   out[t] = cnt ? cscale(acc, 1.0 / cnt) : make_double2(0.0, 0.0);
 }
 
+// ---------------------------------------------------------------------------
+// Learned warm start plumbing (Section 4.1: psi^(0) is a given function).
+// Robin data at the receiving face nodes for selected steps of a history:
+// g(y, t) = (1/|O(y)|) sum_{j in O(y)} (n.grad + mu) psi_j(y, t).
+__global__ void k_face_data(Items it, Nodes nd, const int32_t* cover, StepList sl, int n_steps,
+                            double mu_re, double mu_im, const double2* hist, double2* g) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int sel = blockIdx.y;
+  if (q >= nd.n) return;
+  const int cnt = nd.count[q];
+  double2 acc = make_double2(0.0, 0.0);
+  if (cnt > 0) {
+    const double* y = nd.x + 4 * q;
+    const int face = nd.face[q];
+    const int kf = face >> 1;
+    const double sign = (face & 1) ? 1.0 : -1.0;
+    for (int c = 0; c < cnt; ++c) {
+      const int j = cover[q * 15 + c];
+      const int Kj = it.K[j];
+      const double2* cj = hist + (int64_t)(n_steps + 1) * it.off1[j] + (int64_t)sl.step[sel] * Kj;
+      for (int m = 0; m < Kj; ++m) {
+        int mi[4];
+        split_index(m, it.nb + 4 * j, it.D, mi);
+        double v = 1.0;
+        for (int k = 0; k < it.D; ++k) {
+          const double a = it.alpha[it.aoff[4 * j + k] + mi[k]];
+          v *= exp(-it.delta[4 * j + k] * (y[k] - a) * (y[k] - a));
+        }
+        const double aj = it.alpha[it.aoff[4 * j + kf] + mi[kf]];
+        const double dv = -2.0 * it.delta[4 * j + kf] * (y[kf] - aj) * v;
+        const double2 b = make_double2(sign * dv + mu_re * v, mu_im * v);
+        acc = cfma(b, cj[m], acc);
+      }
+    }
+    acc = cscale(acc, 1.0 / cnt);
+  }
+  g[(int64_t)sel * nd.n + q] = acc;
+}
+
+// RMS of g0 over each item's receiving nodes (one block per item).
+__global__ void k_learned_rms(Nodes nd, const double2* g0, double* rms) {
+  const int s = blockIdx.x;
+  __shared__ double red[kBlock];
+  const int64_t a = nd.off[s];
+  const int n = (int)(nd.off[s + 1] - a);
+  double acc = 0.0;
+  for (int q = threadIdx.x; q < n; q += blockDim.x) {
+    const double2 v = g0[a + q];
+    acc += v.x * v.x + v.y * v.y;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) rms[s] = n > 0 ? sqrt(red[0] / n) : 0.0;
+}
+
+// Window scale: the largest item RMS, or 1 when g0 vanishes (one block).
+__global__ void k_learned_max(int n_items, const double* rms, double* wmax) {
+  __shared__ double red[kBlock];
+  double m = 0.0;
+  for (int s = threadIdx.x; s < n_items; s += blockDim.x) m = fmax(m, rms[s]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) wmax[0] = red[0] > 0.0 ? red[0] : 1.0;
+}
+
+// Network input per item: (Re, Im) of g0 / S at the item's nodes, zero
+// padding, then 16 tail entries: field features, the item's box centre in
+// global box coordinates, RMS_i / S, the window's start time, zeros.
+// scale[s] holds RMS_i on entry
+// and S on exit.
+__global__ void k_learned_features(Items it, Nodes nd, const double2* g0, FieldFeat ff, int n_in,
+                                   float* x, double* scale, const double* wmax) {
+  const int s = blockIdx.x;
+  const int64_t a = nd.off[s];
+  const int n = (int)(nd.off[s + 1] - a);
+  const double S = wmax[0];
+  const double rms = scale[s];
+  __syncthreads();  // every lane has read scale[s] before lane 0 overwrites it
+  float* xs = x + (int64_t)s * n_in;
+  const int tail = n_in - 16;
+  for (int e = threadIdx.x; e < tail; e += blockDim.x) {
+    const int q = e >> 1;
+    float v = 0.0f;
+    if (q < n) v = (float)(((e & 1) ? g0[a + q].y : g0[a + q].x) / S);
+    xs[e] = v;
+  }
+  for (int m = threadIdx.x; m < 16; m += blockDim.x) {
+    double v = 0.0;
+    if (m < ff.n) {
+      v = ff.v[m];
+    } else if (m >= 8 && m < 12) {
+      const int k = m - 8;
+      if (k < it.D) v = (0.5 * (it.lo[4 * s + k] + it.hi[4 * s + k]) - ff.mid[k]) / ff.half[k];
+    } else if (m == 12) {
+      v = rms / S;
+    } else if (m == 13) {
+      v = ff.t0w;
+    }
+    xs[tail + m] = (float)v;
+  }
+  if (threadIdx.x == 0) scale[s] = S;
+}
+
+// Training targets: (g(t_m) - g0) / scale, [m][node][re, im] per item.
+__global__ void k_learned_targets(Items it, Nodes nd, const double2* gm, int n_nodes_t,
+                                  const double* scale, int n_out, float* y) {
+  const int s = blockIdx.x;
+  const int64_t a = nd.off[s];
+  const int n = (int)(nd.off[s + 1] - a);
+  float* ys = y + (int64_t)s * n_out;
+  const int row = n > 0 ? 2 * n : 1;
+  for (int e = threadIdx.x; e < n_out; e += blockDim.x) {
+    const int m = e / row, r = e % row;
+    float v = 0.0f;
+    if (n > 0 && m < n_nodes_t) {
+      const int q = r >> 1;
+      const double2 d = csub(gm[(int64_t)m * nd.n + a + q], gm[a + q]);
+      v = (float)(((r & 1) ? d.y : d.x) / scale[s]);
+    }
+    ys[e] = v;
+  }
+}
+
+// Applied guess: g(t_n) = g0 + scale sum_m l_m(t_n) y_m at every node and step.
+__global__ void k_learned_apply(Items it, Nodes nd, const float* y, const double* scale,
+                                const double2* g0, const double* lag, int n_nodes_t, int n_out,
+                                int n_steps, double2* g_all) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = blockIdx.y;
+  if (q >= nd.n) return;
+  const int s = nd.item[q];
+  const int64_t a = nd.off[s];
+  const int nn = (int)(nd.off[s + 1] - a);
+  const int ql = (int)(q - a);
+  const float* ys = y + (int64_t)s * n_out;
+  double2 c = make_double2(0.0, 0.0);
+  for (int m = 0; m < n_nodes_t; ++m) {
+    const double l = lag[(int64_t)n * n_nodes_t + m];
+    c.x = fma(l, (double)ys[m * 2 * nn + 2 * ql], c.x);
+    c.y = fma(l, (double)ys[m * 2 * nn + 2 * ql + 1], c.y);
+  }
+  g_all[(int64_t)n * nd.n + q] = cadd(g0[q], cscale(c, scale[s]));
+}
+
+__global__ void k_last_step(Items it, int n_steps, const double2* hist, double2* c0) {
+  const int s = blockIdx.x;
+  const int K = it.K[s];
+  const int64_t hb = (int64_t)(n_steps + 1) * it.off1[s] + (int64_t)n_steps * K;
+  for (int r = threadIdx.x; r < K; r += blockDim.x) c0[it.off1[s] + r] = hist[hb + r];
+}
+
 inline unsigned blocks_for(int64_t n, int b = kBlock) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -1301,6 +1460,51 @@ hipError_t launch_reconstruct(const Items& it, int geom, int step, int n_steps,
   if (n_pts == 0) return hipSuccess;
   hipLaunchKernelGGL(k_reconstruct, dim3(blocks_for(n_pts)), dim3(kBlock), 0, st, it, geom, step,
                      n_steps, hist, pts, n_pts, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_face_data(const Items& it, const Nodes& nd, const int32_t* cover,
+                            const StepList& sl, int n_steps, double mu_re, double mu_im,
+                            const double2* hist, double2* g, hipStream_t st) {
+  if (nd.n == 0 || sl.n == 0) return hipSuccess;
+  dim3 grid(blocks_for(nd.n), sl.n);
+  hipLaunchKernelGGL(k_face_data, grid, dim3(kBlock), 0, st, it, nd, cover, sl, n_steps, mu_re,
+                     mu_im, hist, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_learned_features(const Items& it, const Nodes& nd, const double2* g0,
+                                   const FieldFeat& ff, int n_in, float* x, double* scale,
+                                   double* wmax, hipStream_t st) {
+  hipLaunchKernelGGL(k_learned_rms, dim3(it.n_items), dim3(kBlock), 0, st, nd, g0, scale);
+  hipLaunchKernelGGL(k_learned_max, dim3(1), dim3(kBlock), 0, st, it.n_items, scale, wmax);
+  hipLaunchKernelGGL(k_learned_features, dim3(it.n_items), dim3(kBlock), 0, st, it, nd, g0, ff,
+                     n_in, x, scale, wmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_learned_targets(const Items& it, const Nodes& nd, const double2* gm,
+                                  int n_nodes_t, const double* scale, int n_out, float* y,
+                                  hipStream_t st) {
+  hipLaunchKernelGGL(k_learned_targets, dim3(it.n_items), dim3(kBlock), 0, st, it, nd, gm,
+                     n_nodes_t, scale, n_out, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_learned_apply(const Items& it, const Nodes& nd, const float* y,
+                                const double* scale, const double2* g0, const double* lag,
+                                int n_nodes_t, int n_out, int n_steps, double2* g_all,
+                                hipStream_t st) {
+  if (nd.n == 0) return hipSuccess;
+  dim3 grid(blocks_for(nd.n), n_steps + 1);
+  hipLaunchKernelGGL(k_learned_apply, grid, dim3(kBlock), 0, st, it, nd, y, scale, g0, lag,
+                     n_nodes_t, n_out, n_steps, g_all);
+  return hipGetLastError();
+}
+
+hipError_t launch_last_step(const Items& it, int n_steps, const double2* hist, double2* c0,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_last_step, dim3(it.n_items), dim3(kBlock), 0, st, it, n_steps, hist, c0);
   return hipGetLastError();
 }
 

@@ -70,8 +70,16 @@ EXPORTS = [
     "swr_sweep", "swr_transmit", "swr_run", "swr_get_history", "swr_get_forcing",
     "swr_get_initial", "swr_get_matrix", "swr_get_items", "swr_get_boxes",
     "swr_get_index_maps", "swr_get_face_nodes", "swr_reconstruct", "swr_local_eigen",
-    "swr_get_norms", "swr_status_sync",
+    "swr_get_norms", "swr_status_sync", "swr_set_field", "swr_advance_window",
+    "swr_time_nodes", "swr_face_data", "swr_learned_features", "swr_learned_targets",
+    "swr_learned_apply", "swr_mlp_param_count", "swr_mlp_workspace_bytes", "swr_mlp_forward",
+    "swr_mlp_loss_grad", "swr_mlp_adam",
 ]
+
+
+class swr_mlp_desc(ctypes.Structure):
+    _fields_ = [("n_in", ctypes.c_int32), ("n_hidden", ctypes.c_int32),
+                ("n_layers", ctypes.c_int32), ("n_out", ctypes.c_int32)]
 
 _lib = None
 
@@ -111,6 +119,20 @@ def load_library(path=LIB_PATH):
         "swr_local_eigen": (i32, [vp, vp, vp, vp]),
         "swr_get_norms": (i32, [vp, vp, u64, vp]),
         "swr_status_sync": (i32, [vp, vp]),
+        "swr_set_field": (i32, [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+        "swr_advance_window": (i32, [vp, vp]),
+        "swr_time_nodes": (i32, [vp, _c_i32p]),
+        "swr_face_data": (i32, [vp, i32, _c_i32p, vp, vp]),
+        "swr_learned_features": (i32, [vp, vp, ctypes.c_double, i32, vp, vp, vp]),
+        "swr_learned_targets": (i32, [vp, vp, vp, i32, vp, vp]),
+        "swr_learned_apply": (i32, [vp, vp, vp, vp, i32, vp, vp]),
+        "swr_mlp_param_count": (i32, [ctypes.POINTER(swr_mlp_desc), ctypes.POINTER(i64)]),
+        "swr_mlp_workspace_bytes": (i32, [ctypes.POINTER(swr_mlp_desc), i32, ctypes.POINTER(u64)]),
+        "swr_mlp_forward": (i32, [ctypes.POINTER(swr_mlp_desc), vp, vp, i32, vp, vp, u64, vp]),
+        "swr_mlp_loss_grad": (i32, [ctypes.POINTER(swr_mlp_desc), vp, vp, vp, i32, vp, vp, vp, u64,
+                                    vp]),
+        "swr_mlp_adam": (i32, [i64, vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float,
+                               ctypes.c_float, ctypes.c_float, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -334,3 +356,103 @@ class Solver:
 
     def status(self):
         self._call("swr_status_sync", self._stream())
+
+    # -- learned warm start plumbing --------------------------------------------
+    @property
+    def n_face_nodes(self):
+        return int(self.info.n_face_nodes)
+
+    def set_field(self, E0, omega, phase):
+        self._call("swr_set_field", ctypes.c_double(E0), ctypes.c_double(omega),
+                   ctypes.c_double(phase))
+
+    def advance_window(self):
+        self._call("swr_advance_window", self._stream())
+
+    def time_nodes(self):
+        out = np.zeros(8, dtype=np.int32)
+        self._call("swr_time_nodes", out.ctypes.data_as(_c_i32p))
+        return [int(v) for v in out]
+
+    def face_data(self, steps):
+        steps = np.ascontiguousarray(np.array(steps, dtype=np.int32))
+        out = self._complex(len(steps) * self.n_face_nodes)
+        self._call("swr_face_data", ctypes.c_int32(len(steps)), steps.ctypes.data_as(_c_i32p),
+                   _vp(out), self._stream())
+        return out.view(len(steps), self.n_face_nodes)
+
+    def learned_features(self, g0, t0, n_in):
+        x = self.torch.empty((len(self.K), n_in), dtype=self.torch.float32, device=self.device)
+        sc = self.torch.empty(len(self.K), dtype=self.torch.float64, device=self.device)
+        self._call("swr_learned_features", _vp(g0), ctypes.c_double(t0), ctypes.c_int32(n_in),
+                   _vp(x), _vp(sc), self._stream())
+        return x, sc
+
+    def learned_targets(self, g_nodes, scale, n_out):
+        y = self.torch.empty((len(self.K), n_out), dtype=self.torch.float32, device=self.device)
+        self._call("swr_learned_targets", _vp(g_nodes), _vp(scale), ctypes.c_int32(n_out), _vp(y),
+                   self._stream())
+        return y
+
+    def learned_apply(self, y, scale, g0, n_out):
+        out = self._complex((self.n_steps + 1) * self.n_face_nodes)
+        self._call("swr_learned_apply", _vp(y), _vp(scale), _vp(g0), ctypes.c_int32(n_out),
+                   _vp(out), self._stream())
+        return out
+
+
+class Mlp:
+    """FP32 network of the learned warm start (kernels in libswr.so)."""
+
+    def __init__(self, n_in, n_hidden, n_layers, n_out, params, device="cuda", max_batch=512):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        self.d = swr_mlp_desc(n_in, n_hidden, n_layers, n_out)
+        cnt = ctypes.c_int64()
+        _check(self.lib, None, self.lib.swr_mlp_param_count(ctypes.byref(self.d), ctypes.byref(cnt)))
+        self.n_params = cnt.value
+        self.device = torch.device(device)
+        self.params = torch.as_tensor(params, dtype=torch.float32).to(self.device).contiguous()
+        assert self.params.numel() == self.n_params
+        self.grad = torch.zeros_like(self.params)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step = 0
+        self.loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+        self.max_batch = max_batch
+        b = ctypes.c_uint64()
+        _check(self.lib, None, self.lib.swr_mlp_workspace_bytes(ctypes.byref(self.d),
+                                                                 ctypes.c_int32(max_batch),
+                                                                 ctypes.byref(b)))
+        self.ws = torch.empty(int(b.value), dtype=torch.uint8, device=self.device)
+
+    def _s(self):
+        return ctypes.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def forward(self, x):
+        x = x.contiguous()
+        out = self.torch.empty((x.shape[0], self.d.n_out), dtype=self.torch.float32,
+                               device=self.device)
+        for a in range(0, x.shape[0], self.max_batch):
+            xb = x[a:a + self.max_batch]
+            yb = out[a:a + self.max_batch]
+            _check(self.lib, None, self.lib.swr_mlp_forward(
+                ctypes.byref(self.d), _vp(self.params), _vp(xb), ctypes.c_int32(xb.shape[0]),
+                _vp(yb), _vp(self.ws), ctypes.c_uint64(self.ws.numel()), self._s()))
+        return out
+
+    def loss_grad(self, x, t):
+        assert x.shape[0] <= self.max_batch
+        _check(self.lib, None, self.lib.swr_mlp_loss_grad(
+            ctypes.byref(self.d), _vp(self.params), _vp(x.contiguous()), _vp(t.contiguous()),
+            ctypes.c_int32(x.shape[0]), _vp(self.loss), _vp(self.grad), _vp(self.ws),
+            ctypes.c_uint64(self.ws.numel()), self._s()))
+        return self.loss, self.grad
+
+    def adam(self, lr, b1=0.9, b2=0.999, eps=1e-8):
+        self.step += 1
+        _check(self.lib, None, self.lib.swr_mlp_adam(
+            ctypes.c_int64(self.n_params), _vp(self.params), _vp(self.grad), _vp(self.m),
+            _vp(self.v), ctypes.c_int32(self.step), ctypes.c_float(lr), ctypes.c_float(b1),
+            ctypes.c_float(b2), ctypes.c_float(eps), self._s()))

@@ -121,3 +121,19 @@ def test_index_maps_and_boxes_bit_exact(S, name):
         assert tuple(it[s.lin, 2:2 + dec.D]) == s.idx
         assert tuple(it[s.lin, 6:6 + dec.D]) == s.nb
     lib.swr_destroy(h)
+
+
+def test_time_nodes_match_oracle_and_short_windows_are_rejected(S):
+    from oracle import learned as o_learned
+    lib = S.load_library()
+    out = np.zeros(8, dtype=np.int32)
+    for n_steps, ok in [(8, False), (10, False), (11, True), (200, True), (1000, True)]:
+        cfg = dict(workloads.tiny_configs()[1], n_steps=n_steps)
+        rc, h = _create(S, cfg)
+        assert rc == 0
+        rc = lib.swr_time_nodes(h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        if ok:
+            assert rc == 0 and list(out) == o_learned.time_nodes(n_steps)
+        else:
+            assert rc == -1 and b"n_steps >= 11" in lib.swr_last_error(h)
+        lib.swr_destroy(h)
