@@ -2,15 +2,17 @@
 
 A step is one SWR time window of the two-electron workload (2 electrons in
 one dimension each, 8x8 overlapping subdomains, 8x8 Gaussians per subdomain,
-1000 Crank-Nicolson steps, 20 Schwarz iterations): factorisation of every
-local Crank-Nicolson matrix of the window, then 20 iterations of local solves
-(recurrence), transmission and residual, with the residual read back after
-every iteration.  Inputs (assembled matrices, initial coefficients) are
-resident in HBM before the timed region.
+1000 Crank-Nicolson steps, 20 Schwarz iterations), run by swr_run: the
+factorisation of every local Crank-Nicolson matrix of the window, the plain
+warm start, then 20 Schwarz iterations of local solves (recurrence),
+transmission and residual, with P iterates in flight over chunks of the
+window (depth P, 4 here).  Inputs (assembled matrices, initial coefficients)
+are resident in HBM before the timed region.
 
 value = subdomain-solves per second = subdomains x Schwarz iterations x
 steps / seconds, where a subdomain-solve is one subdomain's whole-window
-local solve in one Schwarz iteration.
+local solve in one Schwarz iteration.  Kernel durations come from HIP events
+the library records around each launch on the run's stream.
 """
 import argparse
 import json
@@ -57,6 +59,7 @@ def main():
     ap.add_argument("--config", default="c2-2e-1d")
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--depth", type=int, default=0, help="iterates in flight (0: library choice)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -77,56 +80,53 @@ def main():
     n_sub = int(s.info.n_items)
     K = int(s.info.K_max)
     nT = int(s.n_steps)
-    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    c0 = s.initial().clone()
 
-    def window(record):
-        e0, e1 = ev(), ev()
-        e0.record()
-        s.factor(0.0)
-        e1.record()
-        s.warm_start(0)
-        sw, tr = [], []
-        res = None
-        for _ in range(iters):
-            a, b, c = ev(), ev(), ev()
-            a.record()
-            s.sweep()
-            b.record()
-            res = s.transmit()
-            c.record()
-            sw.append((a, b))
-            tr.append((b, c))
-        if record is not None:
-            record.append(((e0, e1), sw, tr, res))
+    def window():
+        s.set_initial(c0)
+        return s.run(k_max=iters, tol=0.0, depth=args.depth, timing=True)
 
     for _ in range(args.warmup):
-        window(None)
+        window()
     torch.cuda.synchronize()
-    rec = []
+    runs = []
     t = time.perf_counter()
     for _ in range(args.steps):
-        window(rec)
+        runs.append(window())
     torch.cuda.synchronize()
     wall = time.perf_counter() - t
-    f_ms = [r[0][0].elapsed_time(r[0][1]) for r in rec]
-    s_ms = [a.elapsed_time(b) for r in rec for (a, b) in r[1]]
-    t_ms = [a.elapsed_time(b) for r in rec for (a, b) in r[2]]
     ms_step = 1e3 * wall / args.steps
     value = n_sub * iters * args.steps / wall
 
-    # roofline of the two dominant kernels (algorithmic work per launch)
-    f_avg = sum(f_ms) / len(f_ms)
-    s_avg = sum(s_ms) / len(s_ms)
-    lu_flops = n_sub * nT * (8.0 / 3.0) * K ** 3           # LU-equivalent factorisation work
-    rec_bytes = n_sub * nT * (16.0 * K * K + 48.0 * K)     # factor read + vectors, per step
-    roof_factor = dict(kernel="k_invert", bound="alu", achieved=lu_flops / (f_avg * 1e-3) / 1e12,
-                       peak=FP64_PEAK_TFS, unit="TFLOP/s", traffic=None)
-    roof_factor["frac"] = roof_factor["achieved"] / roof_factor["peak"]
-    roof_rec = dict(kernel="k_cn_recur", bound="hbm", achieved=rec_bytes / (s_avg * 1e-3) / 1e9,
-                    peak=HBM_PEAK_GBS, unit="GB/s", traffic=None)
-    roof_rec["frac"] = roof_rec["achieved"] / roof_rec["peak"]
-    dominant = roof_rec if s_avg * iters >= f_avg else roof_factor
-    roofline = {k: v for k, v in dominant.items()}
+    kern = {k: dict(ms=sum(r["kernels"][k]["ms"] for r in runs) / args.steps,
+                    launches=sum(r["kernels"][k]["launches"] for r in runs) / args.steps)
+            for k in ("factor", "transmit", "recur", "residual")}
+    # algorithmic work per window of each kernel class
+    inv_flops = n_sub * nT * 8.0 * K ** 3                    # complex Gauss-Jordan inverses
+    rec_bytes = iters * n_sub * nT * (16.0 * K * K + 32.0 * K)   # inverse + f^{n+1} + c^{n+1}
+    hist_bytes = n_sub * (nT + 1) * K * 16.0
+    tx_bytes = (iters + 1) * 2.0 * hist_bytes                # read iterate, write Robin data
+    res_bytes = iters * 2.0 * hist_bytes                     # read two iterates
+    roofs = {
+        "factor": dict(kernel="k_invert", bound="alu", achieved=inv_flops / 1e12,
+                       peak=FP64_PEAK_TFS, unit="TFLOP/s"),
+        "recur": dict(kernel="k_cn_recur", bound="hbm", achieved=rec_bytes / 1e9,
+                      peak=HBM_PEAK_GBS, unit="GB/s"),
+        "transmit": dict(kernel="k_tx_send+k_tx_recv", bound="hbm", achieved=tx_bytes / 1e9,
+                         peak=HBM_PEAK_GBS, unit="GB/s"),
+        "residual": dict(kernel="k_residual", bound="hbm", achieved=res_bytes / 1e9,
+                         peak=HBM_PEAK_GBS, unit="GB/s"),
+    }
+    for k, r in roofs.items():
+        sec = kern[k]["ms"] * 1e-3
+        r["achieved"] = r["achieved"] / sec if sec > 0 else None
+        r["frac"] = r["achieved"] / r["peak"] if r["achieved"] else None
+        r["ms_per_window"] = kern[k]["ms"]
+        r["launches_per_window"] = kern[k]["launches"]
+        r["traffic"] = None
+    dom = max(roofs, key=lambda k: kern[k]["ms"])
+    roofline = {k: v for k, v in roofs[dom].items() if k in
+                ("kernel", "bound", "achieved", "peak", "unit", "frac", "traffic")}
 
     out = {
         "metric": "SWR sweep time & subdomain-solves/s; Schwarz iters to 1e-8, learned vs plain",
@@ -144,13 +144,12 @@ def main():
         "config": {"workload": f"{cfg['name']}: {cfg['n_elec']} electrons x {cfg['dim']}-D, "
                                f"{n_sub} subdomains, K={K} Gaussians each, {nT} Crank-Nicolson "
                                f"steps per window, {iters} Schwarz iterations per window",
-                   "subdomains": n_sub, "K": K, "n_steps": nT, "schwarz_iters": iters},
+                   "subdomains": n_sub, "K": K, "n_steps": nT, "schwarz_iters": iters,
+                   "depth": int(s.info.depth) if args.depth == 0 else args.depth},
         "roofline": roofline,
-        "phases_ms": {"factor_per_window": f_avg, "sweep_per_iter": s_avg,
-                      "transmit_residual_per_iter": sum(t_ms) / len(t_ms),
-                      "paper_literal_sweep": f_avg + s_avg + sum(t_ms) / len(t_ms)},
-        "roofline_all": [roof_factor, roof_rec],
-        "last_residual": rec[-1][3],
+        "kernels_per_window": roofs,
+        "sweep_ms_per_iteration": ms_step / iters,
+        "last_residual": runs[-1]["res"][-1],
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample)

@@ -97,7 +97,7 @@ typedef struct swr_info {
   int64_t n_pairs;           /* (item, neighbour) transfer pairs              */
   int64_t sum_KK_pairs;      /* entries of all transfer operators             */
   int32_t n_steps;
-  int32_t reserved;
+  int32_t depth;             /* Schwarz iterates swr_run keeps in flight      */
   uint64_t workspace_bytes;
 } swr_info;
 
@@ -162,19 +162,37 @@ int32_t swr_sweep(swr_handle h, void* stream);
 int32_t swr_transmit(swr_handle h, double* residual_host, void* stream);
 
 /* Whole window: factor, then sweep + transmit until Res(k) <= tol with
- * k >= 2, or k == k_max.  iters/res receive up to 64 entries. */
+ * k >= 2, or k == k_max.  iters/res receive up to 64 entries.
+ * TDSE with depth P > 1: the window is cut into P chunks of steps and
+ * iterate k works on chunk c while iterate k+1 works on chunk c-1 (each
+ * chunk of iterate k+1 needs only chunk c of iterate k and its own chunk
+ * c-1), so P iterates of every item run at once.  Every iterate is computed
+ * with the same arithmetic as at depth 1 (identical results); up to P-1
+ * iterates past the stopping one are started and discarded.  depth 0 takes
+ * swr_info.depth (sized at creation so that P x n_items fills the GPU,
+ * P <= 4); 1 runs one iterate at a time; larger values are capped at
+ * swr_info.depth.  TISE always runs at depth 1 (its global normalisation
+ * couples every item at every step). */
 typedef struct swr_run_opts {
   int32_t k_max;
   double tol;
   double t0;
   int32_t warm;              /* SWR_WARM_*                                    */
   const void* g_dev;         /* Robin data for SWR_WARM_GIVEN                 */
+  int32_t depth;             /* 0: swr_info.depth; 1: one iterate at a time   */
+  int32_t timing;            /* 1: time every kernel launch with HIP events    */
 } swr_run_opts;
+/* With timing, ms_* hold the summed durations (HIP events recorded on the
+ * run's stream around each launch) and n_* the launch counts of the
+ * factorisation, Robin data (transmission), recurrence and residual kernels;
+ * otherwise they are zero. */
 typedef struct swr_run_stats {
   int32_t iters;
   int32_t converged;
   double res[64];
   double energy;             /* TISE: (1/nu - 1)/dt at the last step          */
+  double ms_factor, ms_transmit, ms_recur, ms_residual;
+  int32_t n_factor, n_transmit, n_recur, n_residual;
 } swr_run_stats;
 int32_t swr_run(swr_handle h, const swr_run_opts* opts, swr_run_stats* stats, void* stream);
 
@@ -183,7 +201,7 @@ int32_t swr_run(swr_handle h, const swr_run_opts* opts, swr_run_stats* stats, vo
 /* Coefficient history of the current iterate: complex [item blocks], item s
  * occupying (n_steps+1) * K_s entries time-major, items in order. */
 int32_t swr_get_history(swr_handle h, void* dst_dev, uint64_t bytes, void* stream);
-/* Current Robin data vectors f: same layout as the history. */
+/* Robin data vectors f for the next sweep: same layout as the history. */
 int32_t swr_get_forcing(swr_handle h, void* dst_dev, uint64_t bytes, void* stream);
 /* Initial coefficients (complex, sum_K). */
 int32_t swr_get_initial(swr_handle h, void* dst_dev, uint64_t bytes, void* stream);

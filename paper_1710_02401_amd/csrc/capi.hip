@@ -38,6 +38,10 @@ bool distinct_time_nodes(int n_T) {
   return true;
 }
 
+constexpr int kMaxSlots = 6;    // depth <= 4, the previous iterate, one for the residual lag
+constexpr int kResEvents = 8;   // residual read-backs in flight
+constexpr int kGpuCUs = 256;    // MI355X compute units (one recurrence block each)
+
 const char* const kShortWindow = "the learned warm start needs n_steps >= 11 (distinct time nodes)";
 
 struct Buf {
@@ -77,13 +81,48 @@ struct swr_handle_s {
   Buf bPI, bPJ, bPOff, bTOff, bPNode, bPNOff;
   Buf bPos, bCharge, bS1Off, bS1, bScrOff, bScr, bCenter;
   Buf bA, bKin, bV, bQ, bB, bW, bG, bAr, bAp, bHr;
-  Buf bT, bC0, bH[2], bF, bFs, bMinv, bE, bResPart, bResOut, bIePart, bNus, bFlags;
+  Buf bTePair, bTeFace, bTeT0, bTeT1, bTeOff, bTeBoff, bTeAoff, bTeXoff, bTeBeta, bTeA, bTeX;
+  Buf bTeSoff, bTeSidx, bTeV, bTeBlobOff, bTeBlob, bTeSdesc, bTeGramOff, bTeGram, bTeFnode;
+  Buf bParts;                        // residual partials of the factored transmission
+  std::vector<int64_t> te_gram_off;  // per-item face Gram pieces (doubles, even)
+  std::vector<int64_t> te_fnode;     // [n_items][8][2] first node and count per face
+  std::vector<int64_t> te_blob_off;  // per-sender blob offsets (complex units)
+  Buf bT, bC0, bH[kMaxSlots], bF[kMaxSlots], bMinv, bE, bResPart, bResOut, bResv, bIePart, bNus,
+      bFlags;
 
   // state
   bool bound = false, assembled = false, initial = false, warm = false, factored = false;
-  int cur = 0;      // history holding the latest iterate
+  int cur = 0;      // history slot holding the latest iterate
   int k = 0;        // Schwarz iterations done in this window
   double t0 = 0.0;
+  int depth = 1;    // iterates swr_run keeps in flight (TDSE)
+  int nbt = 1;      // largest tangential basis size (factored transmission)
+  int64_t te_pieces = 0;  // largest LDS bytes of the pieces one item sends
+  int te_max_recv = 0;    // largest number of entries one item receives
+  int te_max_send = 0;    // largest number of entries one item sends
+  int64_t te_gram_max = 0;  // largest LDS bytes of one item's face Gram pieces
+  int tx_tt = 0;            // steps per block of the factored transmission
+  int part_stride = 0;      // residual partials per item and iterate slot
+  std::vector<int32_t> te_sdesc;  // sender-side entry descriptors
+  int n_slots = 2;  // history / Robin data slots: iterate k uses slot k % n_slots
+
+  // host side of the pipelined run's residual read-back
+  double* res_pinned = nullptr;
+  hipEvent_t ev[kResEvents] = {};
+  bool ev_ready = false;
+
+  // optional per-launch timing of swr_run: event pairs around each launch
+  bool timing = false;
+  std::vector<hipEvent_t> tev;        // pool, grown on demand, reused
+  std::vector<int> tkind;             // kind of pair q (events 2q, 2q+1)
+  size_t tused = 0;
+
+  ~swr_handle_s() {
+    if (res_pinned) (void)hipHostFree(res_pinned);
+    if (ev_ready)
+      for (auto& e : ev) (void)hipEventDestroy(e);
+    for (auto& e : tev) (void)hipEventDestroy(e);
+  }
 
   template <class T>
   T* ptr(const Buf& b) const { return reinterpret_cast<T*>(ws + b.off); }
@@ -137,9 +176,54 @@ struct swr_handle_s {
     return pr;
   }
   double2* hist(int which) const { return ptr<double2>(bH[which]); }
+  double2* hist_of(int k) const { return ptr<double2>(bH[k % n_slots]); }
+  double2* F_of(int k) const { return ptr<double2>(bF[k % n_slots]); }
+  double* parts_of(int k) const {
+    return ptr<double>(bParts) + (size_t)(k % n_slots) * g.n_items * part_stride;
+  }
+  bool fused_residual() const { return g.te_ok; }
+  swr::TEnt te() const {
+    swr::TEnt t{};
+    t.n = g.te_ok ? (int64_t)g.te_pair.size() : 0;
+    t.pair = ptr<int32_t>(bTePair);
+    t.face = ptr<int32_t>(bTeFace);
+    t.t0 = ptr<int64_t>(bTeT0);
+    t.t1 = ptr<int64_t>(bTeT1);
+    t.off = ptr<int64_t>(bTeOff);
+    t.boff = ptr<int64_t>(bTeBoff);
+    t.aoff = ptr<int64_t>(bTeAoff);
+    t.xoff = ptr<int64_t>(bTeXoff);
+    t.soff = ptr<int64_t>(bTeSoff);
+    t.sidx = ptr<int32_t>(bTeSidx);
+    t.v = ptr<double2>(bTeV);
+    t.blob_off = ptr<int64_t>(bTeBlobOff);
+    t.blob = ptr<double2>(bTeBlob);
+    t.sdesc = ptr<int32_t>(bTeSdesc);
+    t.gram_off = ptr<int64_t>(bTeGramOff);
+    t.gram = ptr<double>(bTeGram);
+    t.fnode = ptr<int64_t>(bTeFnode);
+    t.beta = ptr<double>(bTeBeta);
+    t.a = ptr<double2>(bTeA);
+    t.X = ptr<double>(bTeX);
+    return t;
+  }
 };
 
 namespace {
+
+// Residual partials per item for a run of depth at most P: the window
+// whole, or in p <= P chunks of ceil(n_T / p) steps (chunk 0 one step more).
+int parts_needed(swr_handle h, int P) {
+  const int tt = h->tx_tt, nT = (int)h->n_T;
+  int need = (nT + 1 + tt - 1) / tt;
+  for (int p = 2; p <= P; ++p) {
+    const int S = (nT + p - 1) / p;
+    const int n_chunks = (nT + S - 1) / S;
+    need = std::max(need, n_chunks * ((S + 1 + tt - 1) / tt));
+  }
+  return need;
+}
+
 
 int fail(swr_handle h, int code, const std::string& msg) {
   if (h) h->err = msg;
@@ -213,17 +297,43 @@ void plan_layout(swr_handle h) {
   h->bAr = L.add(m2);
   h->bAp = L.add(m2);
   h->bHr = L.add(m2);
-  h->bT = L.add(g.pair_toff.back() * 16);
+  // dense transfer operators only where the factored form does not apply
+  h->bT = L.add(g.te_ok ? 16 : g.pair_toff.back() * 16);
+  const size_t ne = g.te_pair.size();
+  h->bTePair = L.add(ne * 4);
+  h->bTeFace = L.add(ne * 4);
+  h->bTeT0 = L.add(ne * 8);
+  h->bTeT1 = L.add(ne * 8);
+  h->bTeOff = L.add((NI + 1) * 8);
+  h->bTeBoff = L.add(ne * 8);
+  h->bTeAoff = L.add(ne * 8);
+  h->bTeXoff = L.add(ne * 8);
+  h->bTeBeta = L.add(g.te_nb * 8);
+  h->bTeA = L.add(g.te_na * 16);
+  h->bTeX = L.add(g.te_nx * 8);
+  h->bTeSoff = L.add((NI + 1) * 8);
+  h->bTeSidx = L.add(ne * 4);
+  // tangential traces of every entry at every step (one buffer serves every
+  // job of a launch: their step ranges are disjoint)
+  h->bTeV = L.add(ne * (size_t)(h->n_T + 1) * h->nbt * 16);
+  h->bTeBlobOff = L.add((NI + 1) * 8);
+  h->bTeBlob = L.add((h->te_blob_off.empty() ? 1 : h->te_blob_off.back()) * 16);
+  h->bTeSdesc = L.add(h->te_sdesc.size() * 4);
+  h->bTeGramOff = L.add((NI + 1) * 8);
+  h->bTeGram = L.add((h->te_gram_off.empty() ? 1 : h->te_gram_off.back()) * 8);
+  h->bTeFnode = L.add(NI * 16 * 8);
+  h->bParts = L.add((size_t)h->n_slots * NI * std::max(1, h->part_stride) * 8);
   h->bC0 = L.add(h->sum_K * 16);
   const size_t hist = (size_t)(h->n_T + 1) * h->sum_K * 16;
-  h->bH[0] = L.add(hist);
-  h->bH[1] = L.add(hist);
-  h->bF = L.add(hist);
-  h->bFs = L.add(hist);
+  for (int q = 0; q < h->n_slots; ++q) {
+    h->bH[q] = L.add(hist);
+    h->bF[q] = L.add(hist);
+  }
   h->bMinv = L.add((size_t)h->n_mats * h->sum_K2 * 16);
   h->bE = L.add((h->n_T + 1) * 8);
   h->bResPart = L.add((size_t)h->n_res_tiles * NI * 8);
   h->bResOut = L.add(8);
+  h->bResv = L.add(64 * 8);
   h->bIePart = L.add((size_t)(h->n_T + 1) * NI * 8);
   h->bNus = L.add((h->n_T + 1) * 8);
   h->bFlags = L.add(8);
@@ -245,6 +355,49 @@ int check_flags(swr_handle h, hipStream_t st) {
 }
 
 double field(const swr_desc& d, double t) { return d.E0 * std::sin(d.omega * t + d.phase); }
+
+// kinds of timed launches
+enum { kTFactor = 0, kTTransmit = 1, kTRecur = 2, kTResidual = 3 };
+
+// Record the opening event of a timed launch (no-op unless timing).
+hipError_t tbegin(swr_handle h, hipStream_t st, int kind) {
+  if (!h->timing) return hipSuccess;
+  if (2 * h->tused + 2 > h->tev.size()) {
+    for (int q = 0; q < 64; ++q) {
+      hipEvent_t e;
+      const hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      h->tev.push_back(e);
+    }
+    h->tkind.resize(h->tev.size() / 2);
+  }
+  h->tkind[h->tused] = kind;
+  return hipEventRecord(h->tev[2 * h->tused], st);
+}
+
+hipError_t tend(swr_handle h, hipStream_t st) {
+  if (!h->timing) return hipSuccess;
+  const hipError_t r = hipEventRecord(h->tev[2 * h->tused + 1], st);
+  ++h->tused;
+  return r;
+}
+
+// Sum the recorded durations by kind into the run statistics.
+hipError_t tcollect(swr_handle h, swr_run_stats* s) {
+  if (!h->timing || h->tused == 0) return hipSuccess;
+  hipError_t r = hipEventSynchronize(h->tev[2 * h->tused - 1]);
+  if (r != hipSuccess) return r;
+  double* ms[4] = {&s->ms_factor, &s->ms_transmit, &s->ms_recur, &s->ms_residual};
+  int32_t* n[4] = {&s->n_factor, &s->n_transmit, &s->n_recur, &s->n_residual};
+  for (size_t q = 0; q < h->tused; ++q) {
+    float t = 0.0f;
+    r = hipEventElapsedTime(&t, h->tev[2 * q], h->tev[2 * q + 1]);
+    if (r != hipSuccess) return r;
+    *ms[h->tkind[q]] += t;
+    *n[h->tkind[q]] += 1;
+  }
+  return hipSuccess;
+}
 
 }  // namespace
 
@@ -305,6 +458,70 @@ int32_t swr_create(const swr_desc* desc, swr_handle* out) {
   }
   h->s1_total = s1;
   h->scratch_total = scr;
+  if (g.desc.mode == SWR_TDSE) {
+    const int fill = (kGpuCUs + g.n_items - 1) / g.n_items;
+    h->depth = std::max(1, std::min({4, fill, (int)h->n_T}));
+  }
+  // pipelined: depth iterates in flight, the one they read, and the one
+  // before it (the residual of iterate k-1 reads iterate k-2)
+  h->n_slots = h->depth > 1 ? h->depth + 2 : 2;
+  if (g.D == 2)
+    for (int q = 0; q < g.n_items; ++q)
+      h->nbt = std::max({h->nbt, g.nb[(size_t)q * 4], g.nb[(size_t)q * 4 + 1]});
+  if (g.te_ok) {
+    h->te_blob_off.assign(g.n_items + 1, 0);
+    h->te_sdesc.assign(g.te_sidx.size() * swr::kTxDesc, 0);
+    for (int j = 0; j < g.n_items; ++j) {
+      int64_t b = 0;
+      for (int64_t q = g.te_soff[j]; q < g.te_soff[j + 1]; ++q) {
+        const int e = g.te_sidx[q];
+        const int p = g.te_pair[e];
+        const int i = g.pair_i[p], jj = g.pair_j[p];
+        const int kf = g.te_face[e] >> 1;
+        const int na = g.nb[(size_t)jj * 4 + kf];
+        const int nx = g.D == 2 ? g.nb[(size_t)i * 4 + (1 - kf)] * g.nb[(size_t)jj * 4 + (1 - kf)] : 1;
+        const int nbj1 = g.D == 2 ? g.nb[(size_t)jj * 4 + 1] : 1;
+        int32_t* d = &h->te_sdesc[(size_t)q * swr::kTxDesc];
+        d[0] = e;
+        d[1] = kf;
+        d[2] = na;                                                       // sender normal size
+        d[3] = g.D == 2 ? g.nb[(size_t)jj * 4 + (1 - kf)] : 1;           // sender tangential
+        d[4] = g.D == 2 ? g.nb[(size_t)i * 4 + (1 - kf)] : 1;            // receiver tangential
+        d[5] = (g.D == 2 && kf == 0) ? nbj1 : 1;                         // stride of m_k
+        d[6] = (g.D == 2 && kf == 1) ? nbj1 : 1;                         // stride of m_t
+        d[7] = (int32_t)(b / 16);                                        // a in the blob
+        b += 16 * (na + (nx + 1) / 2);
+      }
+      h->te_max_send = std::max<int>(h->te_max_send, (int)(g.te_soff[j + 1] - g.te_soff[j]));
+      h->te_pieces = std::max(h->te_pieces, b);
+      h->te_blob_off[j + 1] = h->te_blob_off[j] + b / 16;
+      h->te_max_recv = std::max<int>(h->te_max_recv, (int)(g.te_off[j + 1] - g.te_off[j]));
+    }
+    // factored face Gram pieces and the node run of every face
+    h->te_gram_off.assign(g.n_items + 1, 0);
+    h->te_fnode.assign((size_t)g.n_items * 16, 0);
+    for (int j = 0; j < g.n_items; ++j) {
+      int64_t n = 0;
+      for (int f = 0; f < 2 * g.D; ++f) {
+        const int kf = f >> 1;
+        const int nt = g.D == 2 ? g.nb[(size_t)j * 4 + (1 - kf)] : 1;
+        n += g.nb[(size_t)j * 4 + kf] + nt * nt;
+      }
+      n += n & 1;
+      h->te_gram_off[j + 1] = h->te_gram_off[j] + n;
+      h->te_gram_max = std::max<int64_t>(h->te_gram_max, 8 * n);
+      for (int64_t q = g.node_off[j]; q < g.node_off[j + 1]; ++q) {
+        const int f = g.nodes[q].face;
+        int64_t* r = &h->te_fnode[((size_t)j * 8 + f) * 2];
+        if (r[1] == 0) r[0] = q;
+        ++r[1];
+      }
+    }
+    h->tx_tt = swr::transmit_tile_steps(h->nbt, h->te_pieces, h->te_max_send, h->te_gram_max);
+    if (h->te_max_recv > 64 || h->te_max_send > 64 || h->tx_tt == 0)
+      g.te_ok = false;  // dense fallback
+  }
+  if (g.te_ok) h->part_stride = parts_needed(h, h->depth);
   plan_layout(h);
   *out = h;
   return SWR_OK;
@@ -328,6 +545,7 @@ int32_t swr_query(swr_handle h, swr_info* info) {
   r.sum_K2 = h->sum_K2;
   r.n_face_nodes = (int64_t)h->g.nodes.size();
   r.n_pairs = (int64_t)h->g.pair_i.size();
+  r.depth = h->depth;
   r.sum_KK_pairs = h->g.pair_toff.back();
   r.n_steps = (int32_t)h->n_T;
   r.workspace_bytes = h->lay.total;
@@ -432,6 +650,22 @@ int32_t swr_assemble(swr_handle h, void* stream) {
   HIPCHECK(h, upload(h, h->bTOff, g.pair_toff, st));
   HIPCHECK(h, upload(h, h->bPNode, g.pnode, st));
   HIPCHECK(h, upload(h, h->bPNOff, g.pnode_off, st));
+  if (g.te_ok) {
+    HIPCHECK(h, upload(h, h->bTePair, g.te_pair, st));
+    HIPCHECK(h, upload(h, h->bTeFace, g.te_face, st));
+    HIPCHECK(h, upload(h, h->bTeT0, g.te_t0, st));
+    HIPCHECK(h, upload(h, h->bTeT1, g.te_t1, st));
+    HIPCHECK(h, upload(h, h->bTeOff, g.te_off, st));
+    HIPCHECK(h, upload(h, h->bTeBoff, g.te_boff, st));
+    HIPCHECK(h, upload(h, h->bTeAoff, g.te_aoff, st));
+    HIPCHECK(h, upload(h, h->bTeXoff, g.te_xoff, st));
+    HIPCHECK(h, upload(h, h->bTeSoff, g.te_soff, st));
+    HIPCHECK(h, upload(h, h->bTeSidx, g.te_sidx, st));
+    HIPCHECK(h, upload(h, h->bTeBlobOff, h->te_blob_off, st));
+    HIPCHECK(h, upload(h, h->bTeSdesc, h->te_sdesc, st));
+    HIPCHECK(h, upload(h, h->bTeGramOff, h->te_gram_off, st));
+    HIPCHECK(h, upload(h, h->bTeFnode, h->te_fnode, st));
+  }
   HIPCHECK(h, upload(h, h->bPos, g.nuc_pos, st));
   HIPCHECK(h, upload(h, h->bCharge, g.nuc_charge, st));
   HIPCHECK(h, upload(h, h->bS1Off, h->s1off, st));
@@ -457,8 +691,17 @@ int32_t swr_assemble(swr_handle h, void* stream) {
                                       h->ptr<double>(h->bV), h->ptr<double>(h->bB), 0.5 * dt,
                                       g.desc.mu_re, g.desc.mu_im, h->ptr<double>(h->bAr),
                                       h->ptr<double>(h->bAp), h->ptr<double>(h->bHr), tise, dt, st));
-  HIPCHECK(h, swr::launch_transfer(it, nd, pr, g.desc.mu_re, g.desc.mu_im, h->ptr<double2>(h->bT),
-                                   g.K_max, st));
+  if (g.te_ok) {
+    const swr::TEnt te = h->te();
+    HIPCHECK(h, swr::launch_transfer_tensor(it, nd, pr, te, g.desc.mu_re, g.desc.mu_im,
+                                            h->ptr<double>(h->bTeBeta), h->ptr<double2>(h->bTeA),
+                                            h->ptr<double>(h->bTeX), st));
+    HIPCHECK(h, swr::launch_tx_pack(it, pr, te, h->ptr<double2>(h->bTeBlob), st));
+    HIPCHECK(h, swr::launch_gram_tensor(it, nd, te, h->ptr<double>(h->bTeGram), st));
+  } else {
+    HIPCHECK(h, swr::launch_transfer(it, nd, pr, g.desc.mu_re, g.desc.mu_im,
+                                     h->ptr<double2>(h->bT), g.K_max, st));
+  }
   HIPCHECK(h, swr::launch_face_gram(it, nd, h->ptr<double>(h->bG), g.K_max, st));
   // the uploads above read host vectors local to this call
   HIPCHECK(h, hipStreamSynchronize(st));
@@ -488,6 +731,21 @@ int32_t swr_set_initial(swr_handle h, const void* c0_dev, void* stream) {
   return rc;
 }
 
+namespace {
+
+// one job over the whole window: Robin data of iterate k+1 from iterate k
+swr::TxJobs full_tx(const double2* src, double2* dst, int n_T) {
+  swr::TxJobs j{};
+  j.n = 1;
+  j.src[0] = src;
+  j.dst[0] = dst;
+  j.n_lo[0] = 0;
+  j.n_hi[0] = n_T;
+  return j;
+}
+
+}  // namespace
+
 int32_t swr_warm_start(swr_handle h, int32_t mode, const void* g_dev, void* stream) {
   if (!h) return SWR_E_ARG;
   if (!h->initial) return fail(h, SWR_E_STATE, "swr_set_initial first");
@@ -496,19 +754,20 @@ int32_t swr_warm_start(swr_handle h, int32_t mode, const void* g_dev, void* stre
     return fail(h, SWR_E_ARG, "unknown warm start mode");
   hipStream_t st = (hipStream_t)stream;
   const swr::Items it = h->items();
-  double2* F = h->ptr<double2>(h->bF);
-  if (mode == SWR_WARM_PLAIN) {
-    HIPCHECK(h, swr::launch_transmit_const(it, h->pairs(), (int)h->n_T, h->ptr<double2>(h->bT),
-                                           h->ptr<double2>(h->bC0), F, st));
-  } else if (mode == SWR_WARM_ZERO) {
-    HIPCHECK(h, hipMemsetAsync(F, 0, h->bF.bytes, st));
-  } else {
-    HIPCHECK(h, swr::launch_forcing_from_nodes(it, h->nodes(), (int)h->n_T,
-                                               (const double2*)g_dev, F, st));
-  }
+  const int nT = (int)h->n_T;
   // iterate 0 (residual reference) = the window's initial state held constant
+  HIPCHECK(h, swr::launch_fill_history(it, nT, h->ptr<double2>(h->bC0), h->hist_of(0), st));
+  double2* F = h->F_of(1);
+  if (mode == SWR_WARM_PLAIN) {
+    HIPCHECK(h, swr::launch_transmit(it, h->pairs(), h->te(), nT, h->ptr<double2>(h->bT),
+                                     full_tx(h->hist_of(0), F, nT), nullptr, h->nbt, h->te_pieces, h->te_max_recv, h->te_max_send,
+                                   h->te_gram_max, st));
+  } else if (mode == SWR_WARM_ZERO) {
+    HIPCHECK(h, hipMemsetAsync(F, 0, h->bF[0].bytes, st));
+  } else {
+    HIPCHECK(h, swr::launch_forcing_from_nodes(it, h->nodes(), nT, (const double2*)g_dev, F, st));
+  }
   h->cur = 0;
-  HIPCHECK(h, swr::launch_fill_history(it, (int)h->n_T, h->ptr<double2>(h->bC0), h->hist(0), st));
   h->k = 0;
   h->warm = true;
   return SWR_OK;
@@ -524,11 +783,13 @@ int32_t swr_factor(swr_handle h, double t0, void* stream) {
   for (int64_t n = 0; n <= h->n_T; ++n) h->E_host[n] = field(h->g.desc, t0 + n * h->g.desc.dt);
   HIPCHECK(h, upload(h, h->bE, h->E_host, st));
   const int tise = h->g.desc.mode == SWR_TISE;
+  HIPCHECK(h, tbegin(h, st, kTFactor));
   HIPCHECK(h, swr::launch_invert(h->items(), h->n_mats, h->ptr<double>(h->bAr),
                                  h->ptr<double>(h->bHr), h->ptr<double>(h->bQ),
                                  h->ptr<double>(h->bE), 0.5 * h->g.desc.dt, tise,
                                  h->ptr<double2>(h->bMinv), h->ptr<int>(h->bFlags), st,
                                  h->g.K_max));
+  HIPCHECK(h, tend(h, st));
   h->factored = true;
   h->t0 = t0;
   return SWR_OK;
@@ -540,61 +801,246 @@ int32_t swr_sweep(swr_handle h, void* stream) {
   if (!h->warm) return fail(h, SWR_E_STATE, "swr_warm_start (or swr_set_initial) first");
   hipStream_t st = (hipStream_t)stream;
   const swr::Items it = h->items();
-  const int nxt = 1 - h->cur;
+  const int k = h->k + 1;
   const int nT = (int)h->n_T;
+  double2* hist = h->hist_of(k);
   if (h->g.desc.mode == SWR_TDSE) {
-    HIPCHECK(h, swr::launch_pair_sums(it, nT, h->g.K_max, h->ptr<double2>(h->bF),
-                                      h->ptr<double2>(h->bFs), st));
+    swr::RecJobs jobs{};
+    jobs.n = 1;
+    jobs.hist[0] = hist;
+    jobs.F[0] = h->F_of(k);
+    jobs.n_lo[0] = 0;
+    jobs.n_cnt[0] = nT;
+    HIPCHECK(h, tbegin(h, st, kTRecur));
     HIPCHECK(h, swr::launch_cn_recur(it, nT, h->ptr<double>(h->bAp), h->ptr<double>(h->bHr),
                                      h->ptr<double>(h->bQ), h->ptr<double>(h->bE),
                                      0.5 * h->g.desc.dt, h->ptr<double2>(h->bMinv),
-                                     h->ptr<double2>(h->bC0), h->ptr<double2>(h->bFs),
-                                     h->hist(nxt), h->ptr<int>(h->bFlags), st));
+                                     h->ptr<double2>(h->bC0), jobs, h->ptr<int>(h->bFlags), st));
+    HIPCHECK(h, tend(h, st));
   } else {
     // step 0 of every item is the (normalised) initial state
-    HIPCHECK(h, swr::launch_fill_history(it, nT, h->ptr<double2>(h->bC0), h->hist(nxt), st));
+    HIPCHECK(h, swr::launch_fill_history(it, nT, h->ptr<double2>(h->bC0), hist, st));
     for (int n = 0; n < nT; ++n)
       HIPCHECK(h, swr::launch_ie_step(it, n, nT, h->g.desc.dt, h->ptr<double>(h->bA),
                                       h->ptr<double>(h->bW), h->ptr<double2>(h->bMinv),
-                                      h->ptr<double2>(h->bF), h->hist(nxt), h->ptr<double>(h->bIePart),
+                                      h->F_of(k), hist, h->ptr<double>(h->bIePart),
                                       h->ptr<double>(h->bNus), h->ptr<int>(h->bFlags), st));
-    HIPCHECK(h, swr::launch_ie_finish(it, nT, h->hist(nxt), h->ptr<double>(h->bIePart),
+    HIPCHECK(h, swr::launch_ie_finish(it, nT, hist, h->ptr<double>(h->bIePart),
                                       h->ptr<double>(h->bNus), st));
   }
-  h->cur = nxt;
-  h->k += 1;
+  h->cur = k % h->n_slots;
+  h->k = k;
   return SWR_OK;
 }
+
+namespace {
+
+// Robin data of iterate k+1 from iterate k over the whole window, and the
+// residual Res(k) against iterate k-1 into *res_dev (device).  The factored
+// transmission computes the residual in the same pass; the dense one uses
+// the face Gram matrices separately.
+int32_t transmit_and_residual(swr_handle h, int k, const double* scale, double* res_dev,
+                              hipStream_t st) {
+  const swr::Items it = h->items();
+  const int nT = (int)h->n_T;
+  swr::TxJobs tx = full_tx(h->hist_of(k), h->F_of(k + 1), nT);
+  tx.dt = h->g.desc.dt;
+  tx.part_stride = h->part_stride;
+  if (h->fused_residual() && res_dev) {
+    tx.prev[0] = h->hist_of(k - 1);
+    tx.part[0] = h->parts_of(k);
+    tx.part_base[0] = 0;
+  } else if (res_dev) {
+    HIPCHECK(h, tbegin(h, st, kTResidual));
+    HIPCHECK(h, swr::launch_residual(it, nT, h->g.desc.dt, h->ptr<double>(h->bG), h->hist_of(k),
+                                     h->hist_of(k - 1), h->ptr<double>(h->bResPart), res_dev, st));
+    HIPCHECK(h, tend(h, st));
+  }
+  HIPCHECK(h, tbegin(h, st, kTTransmit));
+  HIPCHECK(h, swr::launch_transmit(it, h->pairs(), h->te(), nT, h->ptr<double2>(h->bT), tx,
+                                   scale, h->nbt, h->te_pieces, h->te_max_recv, h->te_max_send,
+                                   h->te_gram_max, st));
+  if (h->fused_residual() && res_dev)
+    HIPCHECK(h, swr::launch_res_reduce(h->parts_of(k), h->g.n_items, h->part_stride, nT, nT, 1,
+                                       h->tx_tt, res_dev, st));
+  HIPCHECK(h, tend(h, st));
+  return SWR_OK;
+}
+
+}  // namespace
 
 int32_t swr_transmit(swr_handle h, double* residual_host, void* stream) {
   if (!h) return SWR_E_ARG;
   if (h->k < 1) return fail(h, SWR_E_STATE, "swr_sweep first");
   hipStream_t st = (hipStream_t)stream;
-  const swr::Items it = h->items();
-  const int nT = (int)h->n_T;
-  HIPCHECK(h, swr::launch_residual(it, nT, h->g.desc.dt, h->ptr<double>(h->bG), h->hist(h->cur),
-                                   h->hist(1 - h->cur), h->ptr<double>(h->bResPart),
-                                   h->ptr<double>(h->bResOut), st));
   const double* scale = h->g.desc.mode == SWR_TISE ? h->ptr<double>(h->bNus) : nullptr;
-  HIPCHECK(h, swr::launch_transmit(it, h->pairs(), nT, h->ptr<double2>(h->bT), h->hist(h->cur),
-                                   scale, h->ptr<double2>(h->bF), st));
+  int rc = transmit_and_residual(h, h->k, scale, h->ptr<double>(h->bResOut), st);
+  if (rc) return rc;
   double res = 0.0;
   HIPCHECK(h, hipMemcpyAsync(&res, h->ptr<double>(h->bResOut), 8, hipMemcpyDeviceToHost, st));
   HIPCHECK(h, hipStreamSynchronize(st));
-  int rc = check_flags(h, st);
+  rc = check_flags(h, st);
   if (rc != SWR_OK) return rc;
   if (residual_host) *residual_host = res;
   return SWR_OK;
 }
 
+namespace {
+
+// Pipelined window (TDSE, depth P > 1).  Chunk c of the window holds the
+// Crank-Nicolson steps [c S, min((c+1) S, n_T)).  Launch d advances every
+// iterate k with c = d - (k - 1) in [0, n_chunks) by its chunk c: first the
+// Robin data of iterate k on the chunk's steps from iterate k-1 (complete
+// there since launch d-1) -- the same pass adds the chunk's share of the
+// residual Res(k-1) -- then the recurrence of the chunk from the state the
+// previous launch left at step c S.  Res(k-1) is complete once chunk
+// n_chunks-1 of iterate k has been transmitted; it is reduced and copied to
+// pinned host memory before that launch's recurrence, so the host reads it
+// while the recurrence runs and never idles the GPU.
+int32_t run_pipelined(swr_handle h, const swr_run_opts* o, int P, swr_run_stats* out,
+                      hipStream_t st) {
+  const swr::Items it = h->items();
+  const int nT = (int)h->n_T;
+  const int S = (nT + P - 1) / P;
+  const int n_chunks = (nT + S - 1) / S;
+  const bool fused = h->fused_residual();
+  if (fused && parts_needed(h, P) > h->part_stride)
+    return fail(h, SWR_E_SIZE, "residual partials exceed their buffer");
+  if (!h->ev_ready) {
+    for (auto& e : h->ev) HIPCHECK(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    h->ev_ready = true;
+  }
+  if (!h->res_pinned) HIPCHECK(h, hipHostMalloc((void**)&h->res_pinned, 64 * sizeof(double), 0));
+  swr_run_stats s{};
+  int k_final = 0;
+  auto queue_read = [&](int k) -> int {  // Res(k) (already in bResv) to the host
+    double* dev = h->ptr<double>(h->bResv) + k % 64;
+    HIPCHECK(h, hipMemcpyAsync(h->res_pinned + k % 64, dev, 8, hipMemcpyDeviceToHost, st));
+    HIPCHECK(h, hipEventRecord(h->ev[k % kResEvents], st));
+    return SWR_OK;
+  };
+  auto read = [&](int k) -> int {
+    HIPCHECK(h, hipEventSynchronize(h->ev[k % kResEvents]));
+    const double r = h->res_pinned[k % 64];
+    if (k <= 64) s.res[k - 1] = r;
+    if (k >= 2 && r <= o->tol) {
+      k_final = k;
+      s.converged = 1;
+    }
+    return SWR_OK;
+  };
+  int last_read = 0;
+  for (int d = 0; k_final == 0; ++d) {
+    swr::TxJobs tx{};
+    tx.dt = h->g.desc.dt;
+    tx.part_stride = h->part_stride;
+    swr::RecJobs rec{};
+    for (int k = std::max(1, d - n_chunks + 2); k <= std::min(d + 1, o->k_max); ++k) {
+      const int c = d - (k - 1);
+      const int lo = c * S, cnt = std::min(S, nT - lo), hi = lo + cnt;
+      if (k >= 2) {
+        tx.src[tx.n] = h->hist_of(k - 1);
+        tx.dst[tx.n] = h->F_of(k);
+        tx.n_lo[tx.n] = c == 0 ? 0 : lo + 1;
+        tx.n_hi[tx.n] = hi;
+        if (fused) {
+          tx.prev[tx.n] = h->hist_of(k - 2);
+          tx.part[tx.n] = h->parts_of(k - 1);
+          tx.part_base[tx.n] = c * ((S + 1 + h->tx_tt - 1) / h->tx_tt);
+        }
+        ++tx.n;
+      }
+      rec.hist[rec.n] = h->hist_of(k);
+      rec.F[rec.n] = h->F_of(k);
+      rec.n_lo[rec.n] = lo;
+      rec.n_cnt[rec.n] = cnt;
+      ++rec.n;
+    }
+    if (rec.n == 0) break;
+    // Res(kr) is complete after this launch's transmission (fused), or its
+    // iterate completed in the previous launch (dense residual kernel)
+    const int kr = d - n_chunks + 1;
+    const bool res_now = kr >= 1 && kr + 1 <= o->k_max;
+    if (tx.n > 0) {
+      HIPCHECK(h, tbegin(h, st, kTTransmit));
+      HIPCHECK(h, swr::launch_transmit(it, h->pairs(), h->te(), nT, h->ptr<double2>(h->bT), tx,
+                                       nullptr, h->nbt, h->te_pieces, h->te_max_recv,
+                                       h->te_max_send, h->te_gram_max, st));
+      HIPCHECK(h, tend(h, st));
+    }
+    if (res_now) {
+      double* dev = h->ptr<double>(h->bResv) + kr % 64;
+      HIPCHECK(h, tbegin(h, st, kTResidual));
+      if (fused)
+        HIPCHECK(h, swr::launch_res_reduce(h->parts_of(kr), it.n_items, h->part_stride, nT, S,
+                                           n_chunks, h->tx_tt, dev, st));
+      else
+        HIPCHECK(h, swr::launch_residual(it, nT, h->g.desc.dt, h->ptr<double>(h->bG),
+                                         h->hist_of(kr), h->hist_of(kr - 1),
+                                         h->ptr<double>(h->bResPart), dev, st));
+      HIPCHECK(h, tend(h, st));
+      const int rc = queue_read(kr);
+      if (rc) return rc;
+    }
+    HIPCHECK(h, tbegin(h, st, kTRecur));
+    HIPCHECK(h, swr::launch_cn_recur(it, nT, h->ptr<double>(h->bAp), h->ptr<double>(h->bHr),
+                                     h->ptr<double>(h->bQ), h->ptr<double>(h->bE),
+                                     0.5 * h->g.desc.dt, h->ptr<double2>(h->bMinv),
+                                     h->ptr<double2>(h->bC0), rec, h->ptr<int>(h->bFlags), st));
+    HIPCHECK(h, tend(h, st));
+    if (res_now) {
+      const int rc = read(kr);
+      if (rc) return rc;
+      last_read = kr;
+    }
+  }
+  // iterates not checked inside the loop (the last one needs a transmission
+  // of its own: iterate k_max + 1 is never started)
+  for (int k = last_read + 1; k_final == 0 && k <= o->k_max; ++k) {
+    const int rc0 = transmit_and_residual(h, k, nullptr, h->ptr<double>(h->bResv) + k % 64, st);
+    if (rc0) return rc0;
+    int rc = queue_read(k);
+    if (rc) return rc;
+    rc = read(k);
+    if (rc) return rc;
+  }
+  if (k_final == 0) k_final = o->k_max;
+  s.iters = k_final;
+  // state as after sweep + transmit of iterate k_final at depth 1
+  h->k = k_final;
+  h->cur = k_final % h->n_slots;
+  const int rc0 = transmit_and_residual(h, k_final, nullptr, nullptr, st);
+  if (rc0) return rc0;
+  const int rc = check_flags(h, st);
+  if (rc != SWR_OK) return rc;
+  *out = s;
+  return SWR_OK;
+}
+
+}  // namespace
+
 int32_t swr_run(swr_handle h, const swr_run_opts* o, swr_run_stats* stats, void* stream) {
   if (!h || !o) return fail(h, SWR_E_ARG, "null argument");
   if (o->k_max < 1) return fail(h, SWR_E_ARG, "k_max must be >= 1");
+  h->timing = o->timing != 0;
+  h->tused = 0;
+  struct TimingOff {  // timing covers this call only
+    swr_handle h;
+    ~TimingOff() { h->timing = false; }
+  } timing_off{h};
   int rc = swr_factor(h, o->t0, stream);
   if (rc) return rc;
   rc = swr_warm_start(h, o->warm, o->g_dev, stream);
   if (rc) return rc;
   swr_run_stats s{};
+  const int P = o->depth <= 0 ? h->depth : std::min(o->depth, h->depth);
+  if (h->g.desc.mode == SWR_TDSE && P > 1) {
+    rc = run_pipelined(h, o, P, &s, (hipStream_t)stream);
+    if (rc) return rc;
+    HIPCHECK(h, tcollect(h, &s));
+    if (stats) *stats = s;
+    return SWR_OK;
+  }
   for (int k = 1; k <= o->k_max; ++k) {
     rc = swr_sweep(h, stream);
     if (rc) return rc;
@@ -615,6 +1061,7 @@ int32_t swr_run(swr_handle h, const swr_run_opts* o, swr_run_stats* stats, void*
     HIPCHECK(h, hipStreamSynchronize((hipStream_t)stream));
     s.energy = (1.0 / nu - 1.0) / h->g.desc.dt;
   }
+  HIPCHECK(h, tcollect(h, &s));
   if (stats) *stats = s;
   return SWR_OK;
 }
@@ -635,7 +1082,9 @@ int32_t swr_get_history(swr_handle h, void* dst_dev, uint64_t bytes, void* strea
 
 int32_t swr_get_forcing(swr_handle h, void* dst_dev, uint64_t bytes, void* stream) {
   if (!h) return SWR_E_ARG;
-  return copy_out(h, h->bF, h->bF.bytes, dst_dev, bytes, stream);
+  if (!h->warm) return fail(h, SWR_E_STATE, "no Robin data yet");
+  const Buf& b = h->bF[(h->k + 1) % h->n_slots];
+  return copy_out(h, b, b.bytes, dst_dev, bytes, stream);
 }
 
 int32_t swr_get_initial(swr_handle h, void* dst_dev, uint64_t bytes, void* stream) {

@@ -286,6 +286,57 @@ std::string build_geometry(const swr_desc& d, Geometry* g, int* code) {
     }
     g->pair_off[s + 1] = (int64_t)g->pair_i.size();
   }
+
+  // factored transfer entries: runs of equal face in each pair's node list
+  g->te_ok = D <= 2;
+  g->te_pair.clear();
+  g->te_face.clear();
+  g->te_t0.clear();
+  g->te_t1.clear();
+  g->te_boff.clear();
+  g->te_aoff.clear();
+  g->te_xoff.clear();
+  g->te_off.assign(NI + 1, 0);
+  g->te_soff.assign(NI + 1, 0);
+  g->te_sidx.clear();
+  g->te_nb = g->te_na = g->te_nx = 0;
+  if (g->te_ok) {
+    for (int s = 0; s < NI; ++s) {
+      for (int64_t p = g->pair_off[s]; p < g->pair_off[s + 1]; ++p) {
+        const int j = g->pair_j[p];
+        int64_t t = g->pnode_off[p];
+        while (t < g->pnode_off[p + 1]) {
+          const int face = g->nodes[g->pnode[t]].face;
+          int64_t t1 = t;
+          while (t1 < g->pnode_off[p + 1] && g->nodes[g->pnode[t1]].face == face) ++t1;
+          const int kf = face >> 1;
+          const int nbi_k = g->nb[(size_t)s * kMaxD + kf], nbj_k = g->nb[(size_t)j * kMaxD + kf];
+          int nx = 1;
+          if (D == 2) nx = g->nb[(size_t)s * kMaxD + (1 - kf)] * g->nb[(size_t)j * kMaxD + (1 - kf)];
+          g->te_pair.push_back((int32_t)p);
+          g->te_face.push_back(face);
+          g->te_t0.push_back(t);
+          g->te_t1.push_back(t1);
+          g->te_boff.push_back(g->te_nb);
+          g->te_aoff.push_back(g->te_na);
+          g->te_xoff.push_back(g->te_nx);
+          g->te_nb += nbi_k;
+          g->te_na += nbj_k;
+          g->te_nx += nx;
+          t = t1;
+        }
+      }
+      g->te_off[s + 1] = (int64_t)g->te_pair.size();
+    }
+    // the same entries grouped by sending item (counting sort, stable)
+    const size_t ne = g->te_pair.size();
+    g->te_soff.assign(NI + 1, 0);
+    for (size_t e = 0; e < ne; ++e) ++g->te_soff[g->pair_j[g->te_pair[e]] + 1];
+    for (int q = 0; q < NI; ++q) g->te_soff[q + 1] += g->te_soff[q];
+    g->te_sidx.assign(ne, 0);
+    std::vector<int64_t> fill(g->te_soff.begin(), g->te_soff.end() - 1);
+    for (size_t e = 0; e < ne; ++e) g->te_sidx[fill[g->pair_j[g->te_pair[e]]]++] = (int32_t)e;
+  }
   *code = SWR_OK;
   return "";
 }

@@ -62,6 +62,19 @@ struct Geometry {
   // nodes of i whose covering set holds j: list per pair
   std::vector<int32_t> pnode;     // node indices
   std::vector<int64_t> pnode_off; // (n_pairs + 1)
+  // Factored transfer operators (D <= 2): one entry per (pair, face of the
+  // receiving item that the sender covers); the entry's nodes are the run
+  // [te_t0, te_t1) of the pair's node list.  Per entry: beta (receiver's
+  // normal-dimension basis at the face), a (sender's Robin trace, complex)
+  // and X (tangential weighted overlap, receiver x sender rows).
+  bool te_ok = false;
+  std::vector<int32_t> te_pair, te_face;
+  std::vector<int64_t> te_t0, te_t1;
+  std::vector<int64_t> te_off;    // (n_items + 1): entries of item i
+  std::vector<int64_t> te_soff;   // (n_items + 1): entries whose sender is item j
+  std::vector<int32_t> te_sidx;   // entry indices grouped by sender
+  std::vector<int64_t> te_boff, te_aoff, te_xoff;  // offsets of beta, a, X
+  int64_t te_nb = 0, te_na = 0, te_nx = 0;         // totals
 
   // potential quadrature: per item per dim composite Gauss-Legendre rule
   std::vector<double> qx, qw;     // concatenated

@@ -52,6 +52,62 @@ struct Pairs {
   const int64_t* noff;   // [n+1]
 };
 
+// Factored transfer operators (D <= 2), one entry per (pair, face):
+// T_ij = sum over entries of (beta a^T) (x) X, beta/a on the face's normal
+// dimension, X on the tangential one (a 1 x 1 weight when D = 1).
+constexpr int kTxDesc = 8;  // ints per sender-side entry descriptor
+struct TEnt {
+  int64_t n;
+  const int32_t* pair;   // [n] pair index
+  const int32_t* face;   // [n] 2*k + side of the receiving item
+  const int64_t* t0;     // [n] run of the pair's node list
+  const int64_t* t1;
+  const int64_t* off;    // [n_items+1] entries of item i
+  const int64_t* boff;   // [n] offsets of beta (real)
+  const int64_t* aoff;   // [n] offsets of a (complex)
+  const int64_t* xoff;   // [n] offsets of X (real, receiver rows x sender columns)
+  const int64_t* soff;   // [n_items+1] entries whose sender is item j
+  const int32_t* sidx;   // entry indices grouped by sender
+  const int64_t* blob_off;  // [n_items+1] per-sender packed a/X pieces (complex units)
+  const double2* blob;
+  const int32_t* sdesc;  // [n][kTxDesc] per-entry descriptors in sender order
+  // factored face Gram matrices G_j = sum_F (b b^T) (x) W_F of every item:
+  // per face b (normal basis at the face) then W (tangential Gram, weights
+  // w_y); item j's faces at gram[gram_off[j] ..), face node runs in fnode
+  const int64_t* gram_off;  // [n_items+1] (doubles, even)
+  const double* gram;
+  const int64_t* fnode;     // [n_items][8][2] first node, node count
+  const double* beta;
+  const double2* a;
+  const double* X;
+  double2* v;            // scratch [n][n_steps+1][nbt]: tangential traces
+};
+
+// Work lists of the chunked sweep, passed by value: job q covers the steps
+// [n_lo, n_hi] (transmit) or the Crank-Nicolson steps n_lo .. n_lo+n_cnt-1
+// (recurrence) of one Schwarz iterate.
+constexpr int kMaxJobs = 8;
+struct TxJobs {
+  int n;
+  const double2* src[kMaxJobs];  // sending histories
+  double2* dst[kMaxJobs];        // Robin data vectors
+  int n_lo[kMaxJobs], n_hi[kMaxJobs];
+  // Optional residual of the sending history against prev over the job's
+  // steps (factored transmission only): one partial per block at
+  // part[item * part_stride + part_base + block]; null part: none.
+  const double2* prev[kMaxJobs];
+  double* part[kMaxJobs];
+  int part_base[kMaxJobs];
+  int part_stride;
+  double dt;
+};
+struct RecJobs {
+  int n;
+  double2* hist[kMaxJobs];       // history written (reads step n_lo unless n_lo == 0)
+  const double2* F[kMaxJobs];    // Robin data vectors of the iterate
+  int n_lo[kMaxJobs], n_cnt[kMaxJobs];
+};
+
 struct StepList {   // up to 16 selected time steps, passed by value
   int n;
   int step[16];
@@ -94,17 +150,34 @@ hipError_t launch_invert(const Items& it, int n_mats, const double* Ar, const do
                          double2* Minv, int* flags, hipStream_t st, int K_max);
 hipError_t launch_cn_recur(const Items& it, int n_steps, const double* Ap, const double* Hr,
                            const double* Q, const double* Efield, double tau, const double2* Minv,
-                           const double2* c0, const double2* Fs, double2* hist, int* flags,
-                           hipStream_t st);
-hipError_t launch_pair_sums(const Items& it, int n_steps, int K_max, const double2* F,
-                            double2* Fs, hipStream_t st);
+                           const double2* c0, const RecJobs& jobs, int* flags, hipStream_t st);
 hipError_t launch_sum_sqrt(const double* partial, int64_t n, double* out, hipStream_t st);
-hipError_t launch_transmit(const Items& it, const Pairs& pr, int n_steps, const double2* T,
-                           const double2* hist, const double* scale, double2* F,
+hipError_t launch_transfer_tensor(const Items& it, const Nodes& nd, const Pairs& pr,
+                                  const TEnt& te, double mu_re, double mu_im, double* beta,
+                                  double2* a, double* X, hipStream_t st);
+// Factored face Gram pieces of every item (assembly); no-op when te.n == 0.
+hipError_t launch_gram_tensor(const Items& it, const Nodes& nd, const TEnt& te, double* gram,
+                              hipStream_t st);
+// Steps per block of the factored transmission for these LDS needs (32 or
+// 16), or 0 if they do not fit.
+int transmit_tile_steps(int nbt, int64_t pieces, int max_send, int64_t gram);
+// Res = sqrt(sum of the valid block partials) of a window transmitted in
+// n_chunks jobs: chunk 0 holds steps [0, S], chunk c > 0 steps
+// (cS, min((c+1)S, n_T)], tiles of tt steps, item stride part_stride.
+hipError_t launch_res_reduce(const double* part, int n_items, int part_stride, int n_steps, int S,
+                             int n_chunks, int tt, double* out, hipStream_t st);
+// Pack the a and X pieces of every sending item into te.blob (assembly).
+hipError_t launch_tx_pack(const Items& it, const Pairs& pr, const TEnt& te, double2* blob,
+                          hipStream_t st);
+// Robin data vectors of every job; the factored operators when te.n > 0,
+// else the dense T.  scale (per step, may be null) multiplies the result;
+// nbt = largest tangential basis size over items (1 when D = 1); pieces =
+// largest LDS bytes of the a and X pieces an item sends; max_recv / max_send
+// = largest number of entries an item receives / sends.
+hipError_t launch_transmit(const Items& it, const Pairs& pr, const TEnt& te, int n_steps,
+                           const double2* T, const TxJobs& jobs, const double* scale, int nbt,
+                           int64_t pieces, int max_recv, int max_send, int64_t gram,
                            hipStream_t st);
-hipError_t launch_transmit_const(const Items& it, const Pairs& pr, int n_steps,
-                                 const double2* T, const double2* c0, double2* F,
-                                 hipStream_t st);
 hipError_t launch_fill_history(const Items& it, int n_steps, const double2* c0, double2* hist,
                                hipStream_t st);
 hipError_t launch_forcing_from_nodes(const Items& it, const Nodes& nd, int n_steps,

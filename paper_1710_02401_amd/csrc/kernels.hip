@@ -297,6 +297,107 @@ __global__ void k_transfer(Items it, Nodes nd, Pairs pr, double mu_re, double mu
   T[pr.toff[p] + e] = acc;
 }
 
+// Factored pieces of T_ij (D <= 2), one block per (pair, face) entry:
+// beta[l_k] = phi^i_{l_k}(x_F), a[m_k] = (sign d/dx + mu) phi^j_{m_k}(x_F),
+// X[l_t][m_t] = sum over the entry's nodes of w_y / |O(y)| phi^i_{l_t}(y_t)
+// phi^j_{m_t}(y_t) (D = 1: X = sum of w_y / |O(y)| over the one node).
+__global__ void k_transfer_tensor(Items it, Nodes nd, Pairs pr, TEnt te, double mu_re,
+                                  double mu_im, double* beta, double2* a, double* X) {
+  const int e = blockIdx.x;
+  const int p = te.pair[e];
+  const int i = pr.pi[p], j = pr.pj[p];
+  const int face = te.face[e];
+  const int kf = face >> 1;
+  const double sign = (face & 1) ? 1.0 : -1.0;
+  const double xF = nd.x[4 * (int64_t)pr.node[te.t0[e]] + kf];
+  const int nbik = it.nb[4 * i + kf], nbjk = it.nb[4 * j + kf];
+  for (int l = threadIdx.x; l < nbik; l += blockDim.x) {
+    const double c = it.alpha[it.aoff[4 * i + kf] + l];
+    beta[te.boff[e] + l] = exp(-it.delta[4 * i + kf] * (xF - c) * (xF - c));
+  }
+  for (int m = threadIdx.x; m < nbjk; m += blockDim.x) {
+    const double c = it.alpha[it.aoff[4 * j + kf] + m];
+    const double d = it.delta[4 * j + kf];
+    const double v = exp(-d * (xF - c) * (xF - c));
+    const double dv = -2.0 * d * (xF - c) * v;
+    a[te.aoff[e] + m] = make_double2(sign * dv + mu_re * v, mu_im * v);
+  }
+  if (it.D == 1) {
+    if (threadIdx.x == 0) {
+      double acc = 0.0;
+      for (int64_t t = te.t0[e]; t < te.t1[e]; ++t) {
+        const int q = pr.node[t];
+        acc += nd.w[q] / nd.count[q];
+      }
+      X[te.xoff[e]] = acc;
+    }
+    return;
+  }
+  const int tt = 1 - kf;
+  const int nbit = it.nb[4 * i + tt], nbjt = it.nb[4 * j + tt];
+  const double di = it.delta[4 * i + tt], dj = it.delta[4 * j + tt];
+  for (int x = threadIdx.x; x < nbit * nbjt; x += blockDim.x) {
+    const int lt = x / nbjt, mt = x % nbjt;
+    const double ci = it.alpha[it.aoff[4 * i + tt] + lt];
+    const double cj = it.alpha[it.aoff[4 * j + tt] + mt];
+    double acc = 0.0;
+    for (int64_t t = te.t0[e]; t < te.t1[e]; ++t) {
+      const int q = pr.node[t];
+      const double y = nd.x[4 * (int64_t)q + tt];
+      acc += nd.w[q] / nd.count[q] * exp(-di * (y - ci) * (y - ci)) * exp(-dj * (y - cj) * (y - cj));
+    }
+    X[te.xoff[e] + x] = acc;
+  }
+}
+
+// Factored face Gram pieces (D <= 2), one block per (item, face): face f
+// = 2k + side of item j, normal dimension k, tangential t:
+// b[l_k] = phi_{l_k}(x_F), W[l_t][m_t] = sum over the face's nodes of
+// w_y phi_{l_t}(y_t) phi_{m_t}(y_t) (D = 1: W = sum of w_y), so that
+// G_j = sum_F (b b^T) (x) W_F.
+__global__ void k_gram_tensor(Items it, Nodes nd, TEnt te, double* gram) {
+  const int j = blockIdx.x;
+  const int f = blockIdx.y;
+  const int D = it.D;
+  if (f >= 2 * D) return;
+  const int k = f >> 1;
+  int64_t off = te.gram_off[j];
+  for (int g = 0; g < f; ++g) {
+    const int kg = g >> 1;
+    const int nt = D == 2 ? it.nb[4 * j + (1 - kg)] : 1;
+    off += it.nb[4 * j + kg] + nt * nt;
+  }
+  const int64_t t0 = te.fnode[(j * 8 + f) * 2], cnt = te.fnode[(j * 8 + f) * 2 + 1];
+  const double xF = nd.x[4 * t0 + k];
+  const int nbk = it.nb[4 * j + k];
+  for (int l = threadIdx.x; l < nbk; l += blockDim.x) {
+    const double c = it.alpha[it.aoff[4 * j + k] + l];
+    gram[off + l] = exp(-it.delta[4 * j + k] * (xF - c) * (xF - c));
+  }
+  double* W = gram + off + nbk;
+  if (D == 1) {
+    if (threadIdx.x == 0) {
+      double acc = 0.0;
+      for (int64_t q = t0; q < t0 + cnt; ++q) acc += nd.w[q];
+      W[0] = acc;
+    }
+    return;
+  }
+  const int t = 1 - k;
+  const int nbt = it.nb[4 * j + t];
+  const double dl = it.delta[4 * j + t];
+  for (int x = threadIdx.x; x < nbt * nbt; x += blockDim.x) {
+    const int a = x / nbt, b = x - a * nbt;
+    const double ca = it.alpha[it.aoff[4 * j + t] + a], cb = it.alpha[it.aoff[4 * j + t] + b];
+    double acc = 0.0;
+    for (int64_t q = t0; q < t0 + cnt; ++q) {
+      const double y = nd.x[4 * q + t];
+      acc += nd.w[q] * exp(-dl * (y - ca) * (y - ca)) * exp(-dl * (y - cb) * (y - cb));
+    }
+    W[x] = acc;
+  }
+}
+
 // Face Gram matrices G[l][m] = sum over every face node of w_y v_l v_m
 // (residual of eq. residueRT in coefficient form).
 __global__ void k_face_gram(Items it, Nodes nd, double* G) {
@@ -410,7 +511,7 @@ __global__ void __launch_bounds__(kBlock) k_invert(Items it, int n_mats, const d
   const int K = it.K[s];
   const int TR = threadIdx.x & 15, TC = threadIdx.x >> 4;
   __shared__ double2 rowp[16 * T];
-  __shared__ double2 colp[16 * T];
+  __shared__ double2 colp[16 * (T + 1)];  // thread row TR at TR (T+1): no bank conflicts
   const int64_t o2 = it.off2[s];
   const double E = tise ? 0.0 : Eall[n + 1];
   double2 a[T][T];
@@ -442,7 +543,7 @@ __global__ void __launch_bounds__(kBlock) k_invert(Items it, int n_mats, const d
       }
       if (TC == pt) {
 #pragma unroll
-        for (int i = 0; i < T; ++i) colp[TR * T + i] = a[i][pi];
+        for (int i = 0; i < T; ++i) colp[TR * (T + 1) + i] = a[i][pi];
       }
       __syncthreads();
       // In-place Gauss-Jordan step as one rank-1 update: with column p of
@@ -455,7 +556,7 @@ __global__ void __launch_bounds__(kBlock) k_invert(Items it, int n_mats, const d
 #pragma unroll
       for (int i = 0; i < T; ++i) {
         const int r = TR * T + i;
-        const double2 ui = cmul(colp[r], inv);
+        const double2 ui = cmul(colp[TR * (T + 1) + i], inv);
         u[i] = (r == p) ? make_double2(1.0 - inv.x, -inv.y) : ui;
       }
 #pragma unroll
@@ -496,26 +597,32 @@ __global__ void __launch_bounds__(kBlock) k_invert(Items it, int n_mats, const d
 }
 
 // ---------------------------------------------------------------------------
-// Crank-Nicolson recurrence over the window (Section 4.4 step 2), one block
-// of 512 threads per item (K <= 64).  Thread (r, part) owns row r and the
-// eight columns m = 8 part + j: its entries of the real matrices Ap, Hr, Q
-// stay in registers for the whole window; the inverse matrix and the Robin
-// data sum of step n are prefetched at step n - 2 into the register buffer
-// of parity n % 2 (so no loaded register is ever moved: a move would wait
-// for the load); the sums over the eight parts are DPP butterflies inside
-// groups of eight lanes.
+// Crank-Nicolson recurrence (Section 4.4 step 2), one block of 512 threads
+// per (item, job); a job runs the steps n_lo .. n_lo+n_cnt-1 of one Schwarz
+// iterate (the whole window, or one chunk of it).  Thread (r, part) owns row
+// r and the eight columns m = 8 part + j: its entries of the real matrices
+// Ap, Hr, Q stay in registers; the inverse matrix and the Robin data vector
+// f^{n+1} of step n are prefetched at step n - 2 into the register buffer of
+// parity n % 2 (so no loaded register is ever moved before it is used: a
+// move would wait for the load); the sums over the eight parts are DPP
+// butterflies inside groups of eight lanes.
 //   rhs = Ap c^n - i tau (Hr + E_n Q) c^n + (i tau / 2)(f^n + f^{n+1})
 //   c^{n+1} = (M^{n+1})^{-1} rhs
 constexpr int kRecThreads = 512;
+// LDS vectors of the recurrence: entry m at (m / 8) * 9 + m % 8, so that the
+// eight column groups read by a wave fall in different banks
+constexpr int kVecPad = 9 * (kSmallK / 8);
+__device__ inline int vpos(int m) { return (m >> 3) * 9 + (m & 7); }
 
 struct RecState {
   double ap[8], hr[8], qq[8];
   double2 cm[8];        // c^n at this thread's columns
+  double2 fprev;        // f^n at row r
 };
 
 struct RecPipe {
   double2 m[8];         // inverse of M^{n+1}: row r, columns m (transposed storage)
-  double2 fs;           // f^n + f^{n+1} at row r
+  double2 f;            // f^{n+1} at row r
 };
 
 // cross-lane moves inside rows of the wave (DPP, no LDS traffic)
@@ -538,12 +645,13 @@ __device__ inline double group8_sum(double v) {
 
 // Loads of everything step n consumes.  Unconditional, from clamped
 // addresses: entries past K multiply the zero padding of the LDS vectors
-// (columns) or are discarded (rows).
-__device__ inline void prefetch(RecPipe& pp, const double2* Mb, const double2* Fs, int64_t hb,
-                                int n, int n_steps, int K, int r, int part) {
+// (columns) or are discarded (rows); steps past the job's end are never
+// consumed.
+__device__ inline void prefetch(RecPipe& pp, const double2* Mb, const double2* F, int64_t hb,
+                                int n, int n_end, int K, int r, int part) {
   const int rr = r < K ? r : K - 1;
-  const int nn = n < n_steps ? n : n_steps - 1;
-  pp.fs = Fs[hb + (int64_t)nn * K + rr];
+  const int nn = n < n_end ? n : n_end - 1;
+  pp.f = F[hb + (int64_t)(nn + 1) * K + rr];
   const double2* base = Mb + (int64_t)nn * K * K + rr;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
@@ -552,11 +660,11 @@ __device__ inline void prefetch(RecPipe& pp, const double2* Mb, const double2* F
   }
 }
 
-__device__ inline void cn_step(RecState& st, RecPipe& pp, int n, int n_steps, int K, int r,
-                               int part, double tau, const double* sE, const double2* Mb,
-                               const double2* Fs, double2* hist, int64_t hb, double2* sc,
+__device__ inline void cn_step(RecState& st, RecPipe& pp, int n, int n_lo, int n_end, int K,
+                               int r, int part, double tau, const double* sE, const double2* Mb,
+                               const double2* F, double2* hist, int64_t hb, double2* sc,
                                double2* srhs, bool& bad) {
-  const double E = sE[n];
+  const double E = sE[n - n_lo];
   double ax = 0.0, ay = 0.0, hx = 0.0, hy = 0.0;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
@@ -569,21 +677,23 @@ __device__ inline void cn_step(RecState& st, RecPipe& pp, int n, int n_steps, in
   double rx = fma(tau, hy, ax), ry = fma(-tau, hx, ay);  // a - i tau h
   rx = group8_sum(rx);
   ry = group8_sum(ry);
+  const double2 fs = cadd(st.fprev, pp.f);
+  st.fprev = pp.f;
   if (r < K)  // + (i tau / 2)(f^n + f^{n+1})
-    srhs[r] = make_double2(fma(-0.5 * tau, pp.fs.y, rx), fma(0.5 * tau, pp.fs.x, ry));
+    srhs[vpos(r)] = make_double2(fma(-0.5 * tau, fs.y, rx), fma(0.5 * tau, fs.x, ry));
   __syncthreads();
   double ox = 0.0, oy = 0.0;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const double2 rm = srhs[part * 8 + j];  // zero padded past K
+    const double2 rm = srhs[part * 9 + j];  // zero padded past K
     ox = fma(pp.m[j].x, rm.x, fma(-pp.m[j].y, rm.y, ox));
     oy = fma(pp.m[j].x, rm.y, fma(pp.m[j].y, rm.x, oy));
   }
   ox = group8_sum(ox);
   oy = group8_sum(oy);
-  prefetch(pp, Mb, Fs, hb, n + 2, n_steps, K, r, part);
+  prefetch(pp, Mb, F, hb, n + 2, n_end, K, r, part);
   const double2 v = make_double2(ox, oy);
-  if (r < K) sc[r] = v;
+  if (r < K) sc[vpos(r)] = v;
   // Every lane stores (no divergent branch around the store, which would
   // make the memory-counter waits conservative): the eight lanes of a row
   // hold the same value, and padding rows r >= K loaded row K-1's data, so
@@ -592,24 +702,28 @@ __device__ inline void cn_step(RecState& st, RecPipe& pp, int n, int n_steps, in
   bad |= !cfinite(v);
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < 8; ++j) st.cm[j] = sc[part * 8 + j];  // zero padded past K
+  for (int j = 0; j < 8; ++j) st.cm[j] = sc[part * 9 + j];  // zero padded past K
 }
 
 __global__ void __launch_bounds__(kRecThreads) k_cn_recur(Items it, int n_steps, const double* Ap,
                                                           const double* Hr, const double* Q,
                                                           const double* Eall, double tau,
                                                           const double2* Minv, const double2* c0,
-                                                          const double2* Fs, double2* hist,
-                                                          int* flags) {
+                                                          RecJobs jobs, int* flags) {
   const int s = blockIdx.x;
+  const int job = blockIdx.y;
   const int K = it.K[s];
+  const int n_lo = jobs.n_lo[job];
+  const int n_end = n_lo + jobs.n_cnt[job];
+  double2* hist = jobs.hist[job];
+  const double2* F = jobs.F[job];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int part = lane & 7;
   const int r = wave * 8 + (lane >> 3);
-  __shared__ double2 sc[kSmallK];
-  __shared__ double2 srhs[kSmallK];
-  extern __shared__ double sE[];  // field at every time node
-  for (int q = threadIdx.x; q <= n_steps; q += blockDim.x) sE[q] = Eall[q];
+  __shared__ double2 sc[kVecPad];
+  __shared__ double2 srhs[kVecPad];
+  extern __shared__ double sE[];  // field at the job's time nodes n_lo .. n_end
+  for (int q = threadIdx.x; q <= n_end - n_lo; q += blockDim.x) sE[q] = Eall[n_lo + q];
   const int64_t o2 = it.off2[s];
   const int64_t hb = (int64_t)(n_steps + 1) * it.off1[s];
   RecState st;
@@ -623,43 +737,56 @@ __global__ void __launch_bounds__(kRecThreads) k_cn_recur(Items it, int n_steps,
     st.hr[j] = v ? Hr[e] : 0.0;
     st.qq[j] = v ? Q[e] : 0.0;
   }
+  st.fprev = F[hb + (int64_t)n_lo * K + (r < K ? r : K - 1)];
   if (threadIdx.x < K) {
-    const double2 v = c0[it.off1[s] + threadIdx.x];
-    sc[threadIdx.x] = v;
-    hist[hb + threadIdx.x] = v;
+    double2 v;
+    if (n_lo == 0) {
+      v = c0[it.off1[s] + threadIdx.x];
+      hist[hb + threadIdx.x] = v;
+    } else {
+      v = hist[hb + (int64_t)n_lo * K + threadIdx.x];
+    }
+    sc[vpos(threadIdx.x)] = v;
   } else if (threadIdx.x < kSmallK) {
-    // padding past K stays zero for the whole window
-    sc[threadIdx.x] = make_double2(0.0, 0.0);
-    srhs[threadIdx.x] = make_double2(0.0, 0.0);
+    // padding past K stays zero for the whole job
+    sc[vpos(threadIdx.x)] = make_double2(0.0, 0.0);
+    srhs[vpos(threadIdx.x)] = make_double2(0.0, 0.0);
   }
   const double2* Mb = Minv + (int64_t)n_steps * o2;
   RecPipe pA, pB;
-  prefetch(pA, Mb, Fs, hb, 0, n_steps, K, r, part);
-  prefetch(pB, Mb, Fs, hb, 1, n_steps, K, r, part);
+  prefetch(pA, Mb, F, hb, n_lo, n_end, K, r, part);
+  prefetch(pB, Mb, F, hb, n_lo + 1, n_end, K, r, part);
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < 8; ++j) st.cm[j] = sc[part * 8 + j];
+  for (int j = 0; j < 8; ++j) st.cm[j] = sc[part * 9 + j];
   bool bad = false;
   // unconditional two-step body (a conditional second half would make the
   // loop-header wait state assume the first buffer was loaded last)
-  int n = 0;
-  for (; n + 1 < n_steps; n += 2) {
-    cn_step(st, pA, n, n_steps, K, r, part, tau, sE, Mb, Fs, hist, hb, sc, srhs, bad);
-    cn_step(st, pB, n + 1, n_steps, K, r, part, tau, sE, Mb, Fs, hist, hb, sc, srhs, bad);
+  int n = n_lo;
+  for (; n + 1 < n_end; n += 2) {
+    cn_step(st, pA, n, n_lo, n_end, K, r, part, tau, sE, Mb, F, hist, hb, sc, srhs, bad);
+    cn_step(st, pB, n + 1, n_lo, n_end, K, r, part, tau, sE, Mb, F, hist, hb, sc, srhs, bad);
   }
-  if (n < n_steps) cn_step(st, pA, n, n_steps, K, r, part, tau, sE, Mb, Fs, hist, hb, sc, srhs, bad);
+  if (n < n_end)
+    cn_step(st, pA, n, n_lo, n_end, K, r, part, tau, sE, Mb, F, hist, hb, sc, srhs, bad);
   if (bad) atomicOr(flags, kFlagNaN);
 }
 
 // ---------------------------------------------------------------------------
 // Transmission as a batched complex product: for receiving item i and a tile
 // of time steps, F_i[n][l] = scale_n * sum_{pairs (i,j)} sum_m T_ij[l][m] C_j[n][m].
+// Dense form (any D); one job per grid z.
 constexpr int kTN = 32;
 __global__ void __launch_bounds__(kBlock) k_transmit(Items it, Pairs pr, int n_steps,
-                                                     const double2* T, const double2* hist,
-                                                     const double* scale, double2* F) {
+                                                     const double2* T, TxJobs jobs,
+                                                     const double* scale) {
   const int i = blockIdx.y;
-  const int n0 = blockIdx.x * kTN;
+  const int job = blockIdx.z;
+  const int n0 = jobs.n_lo[job] + blockIdx.x * kTN;
+  const int n_hi = jobs.n_hi[job];
+  if (n0 > n_hi) return;  // uniform over the block
+  const double2* hist = jobs.src[job];
+  double2* F = jobs.dst[job];
   const int Ki = it.K[i];
   __shared__ double2 Ts[kSmallK * kSmallK];  // [m][l]
   __shared__ double2 Cs[kTN * kSmallK];      // [nn][m]
@@ -680,7 +807,7 @@ __global__ void __launch_bounds__(kBlock) k_transmit(Items it, Pairs pr, int n_s
     for (int e = threadIdx.x; e < kTN * Kj; e += blockDim.x) {
       const int nn = e / Kj, mm = e % Kj;
       const int n = n0 + nn;
-      Cs[e] = (n <= n_steps) ? hist[hb + (int64_t)n * Kj + mm] : make_double2(0.0, 0.0);
+      Cs[e] = (n <= n_hi) ? hist[hb + (int64_t)n * Kj + mm] : make_double2(0.0, 0.0);
     }
     __syncthreads();
     if (l < Ki) {
@@ -694,47 +821,296 @@ __global__ void __launch_bounds__(kBlock) k_transmit(Items it, Pairs pr, int n_s
     const int64_t fb = (int64_t)(n_steps + 1) * it.off1[i];
     for (int q = 0; q < kTN / 4; ++q) {
       const int n = n0 + nn0 + 4 * q;
-      if (n > n_steps) continue;
+      if (n > n_hi) continue;
       const double sc = scale ? scale[n] : 1.0;
       F[fb + (int64_t)n * Ki + l] = cscale(acc[q], sc);
     }
   }
 }
 
-// Pair sums f^n + f^{n+1} of the Robin data vectors (the Crank-Nicolson
-// forcing of step n), one thread per entry.
-__global__ void k_pair_sums(int64_t n_entries, const Items it, int n_steps, const double2* F,
-                            double2* Fs) {
-  const int s = blockIdx.y;
-  const int K = it.K[s];
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)n_steps * K) return;
-  const int64_t b = (int64_t)(n_steps + 1) * it.off1[s];
-  Fs[b + e] = cadd(F[b + e], F[b + e + K]);
-  (void)n_entries;
+// Factored form (D <= 2), in two passes.  Per entry e (pair (i,j), face of
+// i with normal dimension k and tangential dimension t) and step n:
+//   u_e[m_t] = sum_{m_k} a_e[m_k] C_j[n][m_k, m_t]   (sender's Robin trace)
+//   v_e[l_t] = sum_{m_t} X_e[l_t][m_t] u_e[m_t]      (tangential quadrature)
+//   F_i[n][l_k, l_t] = sum_{e of i} beta_e[l_k] v_e[l_t]
+// Flat basis indices put the last dimension fastest.  The sender pass reads
+// every coefficient tile once (staged in LDS, rows padded to 65 entries
+// against bank conflicts) and writes v for all entries the item sends; the
+// receiver pass streams v and writes F.
+constexpr int kCRow = kSmallK + 1;
+
+// Copy n complex values to LDS rows: dst[(x / row) * dst_row + x % row] =
+// src[x].  U loads per thread are issued before any store (a loop of
+// load-then-store would pay one memory latency per iteration).
+template <int U>
+__device__ inline void gather_rows(double2* dst, int dst_row, const double2* src, int n, int row) {
+  for (int base = 0; base < n; base += U * kBlock) {
+    double tx[U], ty[U];  // scalar arrays: a vector-typed array would live in scratch
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int x = base + u * kBlock + (int)threadIdx.x;
+      const double2 v = src[x < n ? x : 0];
+      tx[u] = v.x;
+      ty[u] = v.y;
+    }
+    __builtin_amdgcn_sched_barrier(0);  // keep every load ahead of the stores
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int x = base + u * kBlock + (int)threadIdx.x;
+      if (x < n) {
+        const int r = x / row;
+        dst[r * dst_row + (x - r * row)] = make_double2(tx[u], ty[u]);
+      }
+    }
+  }
 }
 
-// Robin data of a history that is constant in time (the plain warm start).
-__global__ void k_transmit_const(Items it, Pairs pr, int n_steps, const double2* T,
-                                 const double2* c0, double2* F) {
-  const int i = blockIdx.x;
-  const int Ki = it.K[i];
-  __shared__ double2 f[kSmallK];
-  for (int l = threadIdx.x; l < Ki; l += blockDim.x) {
-    double2 acc = make_double2(0.0, 0.0);
-    for (int64_t p = pr.poff[i]; p < pr.poff[i + 1]; ++p) {
-      const int j = pr.pj[p];
-      const int Kj = it.K[j];
-      const double2* Tp = T + pr.toff[p] + (int64_t)l * Kj;
-      const double2* cj = c0 + it.off1[j];
-      for (int m = 0; m < Kj; ++m) acc = cfma(Tp[m], cj[m], acc);
+template <int U>
+__device__ inline void gather_ints(int* dst, const int* src, int n) {
+  for (int base = 0; base < n; base += U * kBlock) {
+    int t[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int x = base + u * kBlock + (int)threadIdx.x;
+      t[u] = src[x < n ? x : 0];
     }
-    f[l] = acc;
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int x = base + u * kBlock + (int)threadIdx.x;
+      if (x < n) dst[x] = t[u];
+    }
+  }
+}
+
+// Sizes of entry e's pieces: a (sender's normal basis, complex), X
+// (receiver tangential x sender tangential, real).
+__device__ inline void entry_dims(const Items& it, const Pairs& pr, const TEnt& te, int64_t e,
+                                  int* na, int* nx) {
+  const int p = te.pair[e];
+  const int i = pr.pi[p], j = pr.pj[p];
+  const int kf = te.face[e] >> 1;
+  *na = it.nb[4 * j + kf];
+  *nx = it.D == 2 ? it.nb[4 * i + (1 - kf)] * it.nb[4 * j + (1 - kf)] : 1;
+}
+
+// Packs, per sending item, the a and X pieces of its entries (in sender
+// order, X padded to whole complex slots) into one blob, the LDS image the
+// sender pass copies.  One block per item (assembly time).
+__global__ void k_tx_pack(Items it, Pairs pr, TEnt te, double2* blob) {
+  const int j = blockIdx.x;
+  int64_t off = te.blob_off[j];
+  for (int64_t q = te.soff[j]; q < te.soff[j + 1]; ++q) {
+    const int e = te.sidx[q];
+    int na, nx;
+    entry_dims(it, pr, te, e, &na, &nx);
+    for (int x = threadIdx.x; x < na; x += blockDim.x) blob[off + x] = te.a[te.aoff[e] + x];
+    double* xs = reinterpret_cast<double*>(blob + off + na);
+    for (int x = threadIdx.x; x < 2 * ((nx + 1) / 2); x += blockDim.x)
+      xs[x] = x < nx ? te.X[te.xoff[e] + x] : 0.0;
+    off += na + (nx + 1) / 2;
+  }
+}
+
+// Sender pass: block = TT steps of sending item j.  Dynamic LDS:
+// C [TT][65], U [2][TT][nbt] complex (u double buffered: one barrier per
+// entry separates writing u from reading it), the item's blob, then the
+// descriptors of its entries (kTxDesc ints each: entry, normal dimension,
+// sender normal / tangential basis sizes, receiver tangential size, the two
+// sender strides, offset of a in the blob).  Everything the entry loop
+// reads is in LDS: per-entry reads of the global tables would be a chain of
+// dependent memory round trips.
+template <int TT>
+__global__ void __launch_bounds__(kBlock) k_tx_send(Items it, TEnt te, int n_steps, TxJobs jobs,
+                                                    int nbt, int64_t pieces, int64_t gram_max) {
+  const int j = blockIdx.y;
+  const int job = blockIdx.z;
+  const int n0 = jobs.n_lo[job] + blockIdx.x * TT;
+  const int n_hi = jobs.n_hi[job];
+  if (n0 > n_hi) return;  // uniform over the block
+  const int Kj = it.K[j];
+  extern __shared__ double2 smem[];
+  double2* Cs = smem;
+  double2* Ub = Cs + TT * kCRow;
+  double2* piece = Ub + 2 * TT * nbt;
+  double* gpiece = reinterpret_cast<double*>(piece + pieces / 16);
+  int* desc = reinterpret_cast<int*>(gpiece + gram_max);
+  const int nrow = min(TT, n_hi - n0 + 1);
+  const int64_t q0 = te.soff[j];
+  const int ne = (int)(te.soff[j + 1] - q0);
+  const int64_t hoff = (int64_t)(n_steps + 1) * it.off1[j] + (int64_t)n0 * Kj;
+  gather_rows<TT * kSmallK / kBlock>(Cs, kCRow, jobs.src[job] + hoff, nrow * Kj, Kj);
+  // residual: the previous iterate's tile, loaded now and consumed after the
+  // entries (its latency hides behind them)
+  double* part = jobs.part[job];
+  constexpr int kU = TT * kSmallK / kBlock;
+  double px[kU], py[kU];
+  if (part) {
+    const double2* prev = jobs.prev[job] + hoff;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int x = u * kBlock + (int)threadIdx.x;
+      const double2 v = prev[x < nrow * Kj ? x : 0];
+      px[u] = v.x;
+      py[u] = v.y;
+    }
+    const int ng = (int)(te.gram_off[j + 1] - te.gram_off[j]);
+    gather_rows<2>(reinterpret_cast<double2*>(gpiece), 0,
+                   reinterpret_cast<const double2*>(te.gram + te.gram_off[j]), ng / 2, 1 << 30);
+  }
+  gather_rows<4>(piece, 0, te.blob + te.blob_off[j], (int)(te.blob_off[j + 1] - te.blob_off[j]),
+                 1 << 30);
+  gather_ints<2>(desc, te.sdesc + q0 * kTxDesc, ne * kTxDesc);
+  __syncthreads();
+  for (int q = 0; q < ne; ++q) {
+    const int* d = desc + q * kTxDesc;
+    const int e = d[0], nbjk = d[2], nbjt = d[3], nbit = d[4], sk = d[5], stt = d[6];
+    const double2* a = piece + d[7];
+    const double* X = reinterpret_cast<const double*>(a + nbjk);
+    double2* U = Ub + (q & 1) * TT * nbt;
+    for (int x = threadIdx.x; x < nrow * nbjt; x += blockDim.x) {
+      const int nn = x / nbjt, mt = x - nn * nbjt;
+      const double2* c = Cs + nn * kCRow + mt * stt;
+      double2 u = make_double2(0.0, 0.0);
+      for (int mk = 0; mk < nbjk; ++mk) u = cfma(a[mk], c[mk * sk], u);
+      U[nn * nbt + mt] = u;
+    }
+    __syncthreads();
+    double2* vout = te.v + ((int64_t)e * (n_steps + 1) + n0) * nbt;
+    for (int x = threadIdx.x; x < nrow * nbit; x += blockDim.x) {
+      const int nn = x / nbit, lt = x - nn * nbit;
+      const double* xr = X + lt * nbjt;
+      const double2* ur = U + nn * nbt;
+      double2 v = make_double2(0.0, 0.0);
+      for (int mt = 0; mt < nbjt; ++mt) {
+        v.x = fma(xr[mt], ur[mt].x, v.x);
+        v.y = fma(xr[mt], ur[mt].y, v.y);
+      }
+      vout[nn * nbt + lt] = v;
+    }
+  }
+  if (!part) return;  // uniform over the block
+  // Res^2 partial of this tile: sum_n w_n dc^H G_j dc with G_j factored per
+  // face, dc = C - C_prev (formed in place of C, no longer read), and per
+  // face w[m_t] = sum_{m_k} b[m_k] dc[m_k, m_t], term w^H W w.
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int x = u * kBlock + (int)threadIdx.x;
+    if (x < nrow * Kj) {
+      const int r = x / Kj;
+      double2& c = Cs[r * kCRow + (x - r * Kj)];
+      c = make_double2(c.x - px[u], c.y - py[u]);
+    }
   }
   __syncthreads();
-  const int64_t fb = (int64_t)(n_steps + 1) * it.off1[i];
-  for (int64_t e = threadIdx.x; e < (int64_t)(n_steps + 1) * Ki; e += blockDim.x)
-    F[fb + e] = f[e % Ki];
+  const int D = it.D;
+  const int nbj1 = D == 2 ? it.nb[4 * j + 1] : 1;
+  double acc = 0.0;
+  int goff = 0;
+  for (int f = 0; f < 2 * D; ++f) {
+    const int kf = f >> 1;
+    const int nbk = it.nb[4 * j + kf];
+    const int nbf = D == 2 ? it.nb[4 * j + (1 - kf)] : 1;
+    const int sk = (D == 2 && kf == 0) ? nbj1 : 1;
+    const int stt = (D == 2 && kf == 1) ? nbj1 : 1;
+    const double* b = gpiece + goff;
+    const double* W = b + nbk;
+    goff += nbk + nbf * nbf;
+    for (int x = threadIdx.x; x < nrow * nbf; x += blockDim.x) {
+      const int nn = x / nbf, mt = x - nn * nbf;
+      const double2* c = Cs + nn * kCRow + mt * stt;
+      double2 w = make_double2(0.0, 0.0);
+      for (int mk = 0; mk < nbk; ++mk) {
+        w.x = fma(b[mk], c[mk * sk].x, w.x);
+        w.y = fma(b[mk], c[mk * sk].y, w.y);
+      }
+      Ub[nn * nbt + mt] = w;
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < nrow * nbf; x += blockDim.x) {
+      const int nn = x / nbf, lt = x - nn * nbf;
+      const double2* wr = Ub + nn * nbt;
+      double sx = 0.0, sy = 0.0;
+      for (int mt = 0; mt < nbf; ++mt) {
+        sx = fma(W[lt * nbf + mt], wr[mt].x, sx);
+        sy = fma(W[lt * nbf + mt], wr[mt].y, sy);
+      }
+      const int n = n0 + nn;
+      const double wn = (n == 0 || n == n_steps) ? 0.5 * jobs.dt : jobs.dt;
+      acc += wn * (wr[lt].x * sx + wr[lt].y * sy);
+    }
+    __syncthreads();
+  }
+  // block sum in a fixed order
+  __shared__ double red[kBlock];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(int64_t)j * jobs.part_stride + jobs.part_base[job] + blockIdx.x] = red[0];
+}
+
+// Receiver pass: block = TT steps of receiving item i, thread (l, step
+// phase), no LDS and no barriers.  Entries go four at a time so that their
+// loads are in flight together.
+constexpr int kMaxRecvEntries = 64;
+template <int TT>
+__global__ void __launch_bounds__(kBlock) k_tx_recv(Items it, TEnt te, int n_steps, TxJobs jobs,
+                                                    const double* scale, int nbt) {
+  const int i = blockIdx.y;
+  const int job = blockIdx.z;
+  const int n0 = jobs.n_lo[job] + blockIdx.x * TT;
+  const int n_hi = jobs.n_hi[job];
+  if (n0 > n_hi) return;
+  const int Ki = it.K[i];
+  const int l = threadIdx.x & 63;
+  if (l >= Ki) return;
+  const int nn0 = threadIdx.x >> 6;
+  const int D = it.D;
+  const int nbi1 = D == 2 ? it.nb[4 * i + 1] : 1;
+  // l = l_k * nbi1 + l_t for faces normal to dimension 0, l_t * nbi1 + l_k otherwise
+  const int l0 = D == 2 ? l / nbi1 : l, l1 = D == 2 ? l - (l / nbi1) * nbi1 : 0;
+  const int rem = n_hi - n0 - nn0;
+  const int nq = rem < 0 ? 0 : min(TT / 4, rem / 4 + 1);  // steps of this thread in range
+  constexpr int kQ = TT / 4;
+  double2 acc[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) acc[q] = make_double2(0.0, 0.0);
+  const int64_t e0 = te.off[i], e1 = te.off[i + 1];
+  const int64_t vstride = (int64_t)(n_steps + 1) * nbt;
+  const double2* vbase = te.v + (int64_t)(n0 + nn0) * nbt;
+  for (int64_t e = e0; e < e1; e += 4) {
+    double b[4];
+    double2 v[4][kQ];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t eu = e + u < e1 ? e + u : e1 - 1;  // clamped: weight 0 below
+      const int kf = te.face[eu] >> 1;
+      const int lk = kf == 0 ? l0 : l1, lt = kf == 0 ? l1 : l0;
+      b[u] = e + u < e1 ? te.beta[te.boff[eu] + lk] : 0.0;
+      const double2* vin = vbase + eu * vstride + (D == 2 ? lt : 0);
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) v[u][q] = q < nq ? vin[(int64_t)4 * q * nbt] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) {
+        acc[q].x = fma(b[u], v[u][q].x, acc[q].x);
+        acc[q].y = fma(b[u], v[u][q].y, acc[q].y);
+      }
+  }
+  double2* F = jobs.dst[job] + (int64_t)(n_steps + 1) * it.off1[i];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const int n = n0 + nn0 + 4 * q;
+    if (q >= nq) break;
+    const double sc = scale ? scale[n] : 1.0;
+    F[(int64_t)n * Ki + l] = cscale(acc[q], sc);
+  }
 }
 
 __global__ void k_fill_history(Items it, int n_steps, const double2* c0, double2* hist) {
@@ -769,7 +1145,7 @@ __global__ void k_forcing_from_nodes(Items it, Nodes nd, int n_steps, const doub
 // Residual Res(k)^2 = sum_n w_n dt sum_i dc_i^H G_i dc_i (eq. residueRT,
 // trapezoid in time, face Gauss-Legendre in space).  Deterministic two-pass
 // reduction: per (item, time tile) partials, then one block sums them.
-constexpr int kRN = 16;
+constexpr int kRN = 32;
 __global__ void __launch_bounds__(kBlock) k_residual(Items it, int n_steps, double dt,
                                                      const double* G, const double2* cur,
                                                      const double2* prev, double* partial,
@@ -780,18 +1156,51 @@ __global__ void __launch_bounds__(kBlock) k_residual(Items it, int n_steps, doub
   __shared__ double g[kSmallK * kSmallK];
   __shared__ double2 d[kRN][kSmallK];
   __shared__ double red[kBlock];
-  for (int e = threadIdx.x; e < K * K; e += blockDim.x) g[e] = G[it.off2[s] + e];
+  // loads first, stores after (one memory latency, not one per iteration)
+  {
+    constexpr int U = kSmallK * kSmallK / kBlock;
+    double t[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = u * kBlock + threadIdx.x;
+      t[u] = G[it.off2[s] + (e < K * K ? e : 0)];
+    }
+    __builtin_amdgcn_sched_barrier(0);  // keep every load ahead of the stores
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = u * kBlock + threadIdx.x;
+      if (e < K * K) g[e] = t[u];
+    }
+  }
   const int64_t hb = (int64_t)(n_steps + 1) * it.off1[s];
-  for (int e = threadIdx.x; e < kRN * K; e += blockDim.x) {
-    const int nn = e / K, m = e % K;
-    const int n = tile * kRN + nn;
-    d[nn][m] = (n <= n_steps) ? csub(cur[hb + (int64_t)n * K + m], prev[hb + (int64_t)n * K + m])
-                              : make_double2(0.0, 0.0);
+  {
+    constexpr int U = kRN * kSmallK / kBlock;
+    double ax[U], ay[U], bx[U], by[U];  // scalar arrays stay in registers
+    const int nrow = min(kRN, n_steps + 1 - tile * kRN);
+    const int64_t base = hb + (int64_t)tile * kRN * K;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = u * kBlock + threadIdx.x;
+      const int ec = e < nrow * K ? e : 0;
+      const double2 a = cur[base + ec], b = prev[base + ec];
+      ax[u] = a.x;
+      ay[u] = a.y;
+      bx[u] = b.x;
+      by[u] = b.y;
+    }
+    __builtin_amdgcn_sched_barrier(0);  // keep every load ahead of the stores
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = u * kBlock + threadIdx.x;
+      const int nn = e / K, m = e - nn * K;
+      if (e < nrow * K) d[nn][m] = make_double2(ax[u] - bx[u], ay[u] - by[u]);
+      else if (e < kRN * K) d[nn][m] = make_double2(0.0, 0.0);
+    }
   }
   __syncthreads();
   double acc = 0.0;
   for (int e = threadIdx.x; e < kRN * K; e += blockDim.x) {
-    const int nn = e / K, r = e % K;
+    const int nn = e / K, r = e - nn * K;
     const int n = tile * kRN + nn;
     if (n > n_steps) continue;
     double2 y = make_double2(0.0, 0.0);
@@ -1364,18 +1773,17 @@ hipError_t launch_invert(const Items& it, int n_mats, const double* Ar, const do
 
 hipError_t launch_cn_recur(const Items& it, int n_steps, const double* Ap, const double* Hr,
                            const double* Q, const double* Eall, double tau, const double2* Minv,
-                           const double2* c0, const double2* Fs, double2* hist, int* flags,
-                           hipStream_t st) {
-  const size_t lds = (size_t)(n_steps + 1) * sizeof(double);
-  hipLaunchKernelGGL(k_cn_recur, dim3(it.n_items), dim3(kRecThreads), lds, st, it, n_steps, Ap, Hr,
-                     Q, Eall, tau, Minv, c0, Fs, hist, flags);
-  return hipGetLastError();
-}
-
-hipError_t launch_pair_sums(const Items& it, int n_steps, int K_max, const double2* F,
-                            double2* Fs, hipStream_t st) {
-  dim3 grid(blocks_for((int64_t)n_steps * K_max), it.n_items);
-  hipLaunchKernelGGL(k_pair_sums, grid, dim3(kBlock), 0, st, (int64_t)0, it, n_steps, F, Fs);
+                           const double2* c0, const RecJobs& jobs, int* flags, hipStream_t st) {
+  if (jobs.n < 1 || jobs.n > kMaxJobs) return hipErrorInvalidValue;
+  int max_cnt = 0;
+  for (int q = 0; q < jobs.n; ++q) {
+    if (jobs.n_lo[q] < 0 || jobs.n_cnt[q] < 1 || jobs.n_lo[q] + jobs.n_cnt[q] > n_steps)
+      return hipErrorInvalidValue;
+    max_cnt = jobs.n_cnt[q] > max_cnt ? jobs.n_cnt[q] : max_cnt;
+  }
+  const size_t lds = (size_t)(max_cnt + 1) * sizeof(double);
+  hipLaunchKernelGGL(k_cn_recur, dim3(it.n_items, jobs.n), dim3(kRecThreads), lds, st, it, n_steps,
+                     Ap, Hr, Q, Eall, tau, Minv, c0, jobs, flags);
   return hipGetLastError();
 }
 
@@ -1384,19 +1792,107 @@ hipError_t launch_sum_sqrt(const double* partial, int64_t n, double* out, hipStr
   return hipGetLastError();
 }
 
-hipError_t launch_transmit(const Items& it, const Pairs& pr, int n_steps, const double2* T,
-                           const double2* hist, const double* scale, double2* F,
-                           hipStream_t st) {
-  dim3 grid(blocks_for(n_steps + 1, kTN), it.n_items);
-  hipLaunchKernelGGL(k_transmit, grid, dim3(kBlock), 0, st, it, pr, n_steps, T, hist, scale, F);
+hipError_t launch_transfer_tensor(const Items& it, const Nodes& nd, const Pairs& pr,
+                                  const TEnt& te, double mu_re, double mu_im, double* beta,
+                                  double2* a, double* X, hipStream_t st) {
+  if (te.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_transfer_tensor, dim3((unsigned)te.n), dim3(kBlock), 0, st, it, nd, pr, te,
+                     mu_re, mu_im, beta, a, X);
   return hipGetLastError();
 }
 
-hipError_t launch_transmit_const(const Items& it, const Pairs& pr, int n_steps,
-                                 const double2* T, const double2* c0, double2* F,
-                                 hipStream_t st) {
-  hipLaunchKernelGGL(k_transmit_const, dim3(it.n_items), dim3(kBlock), 0, st, it, pr, n_steps,
-                     T, c0, F);
+// dynamic LDS of the sender pass: C, two U buffers, pieces, Gram pieces,
+// entry descriptors
+size_t tx_send_lds(int tt, int nbt, int64_t pieces, int max_send, int64_t gram) {
+  return (size_t)tt * (kCRow + 2 * nbt) * sizeof(double2) + (size_t)pieces + (size_t)gram +
+         (size_t)max_send * kTxDesc * sizeof(int);
+}
+
+int transmit_tile_steps(int nbt, int64_t pieces, int max_send, int64_t gram) {
+  if (nbt < 1 || nbt > kSmallK || pieces < 0 || pieces % 16 || gram < 0 || gram % 16 ||
+      max_send < 1)
+    return 0;
+  // 2 KiB of static LDS (block sum) come on top
+  if (tx_send_lds(32, nbt, pieces, max_send, gram) <= 63488) return 32;
+  if (tx_send_lds(16, nbt, pieces, max_send, gram) <= 63488) return 16;
+  return 0;
+}
+
+hipError_t launch_gram_tensor(const Items& it, const Nodes& nd, const TEnt& te, double* gram,
+                              hipStream_t st) {
+  if (te.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gram_tensor, dim3(it.n_items, 2 * it.D), dim3(kBlock), 0, st, it, nd, te,
+                     gram);
+  return hipGetLastError();
+}
+
+__global__ void k_res_reduce(const double* part, int n_items, int part_stride, int n_steps, int S,
+                             int n_chunks, int tt, double* out) {
+  __shared__ double red[kBlock];
+  const int tpc = (S + 1 + tt - 1) / tt;
+  double acc = 0.0;
+  for (int j = threadIdx.x; j < n_items; j += blockDim.x) {
+    for (int c = 0; c < n_chunks; ++c) {
+      const int len = c == 0 ? S + 1 : min(S, n_steps - c * S);
+      const int tiles = (len + tt - 1) / tt;
+      for (int b = 0; b < tiles; ++b) acc += part[(int64_t)j * part_stride + c * tpc + b];
+    }
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sqrt(red[0]);
+}
+
+hipError_t launch_res_reduce(const double* part, int n_items, int part_stride, int n_steps, int S,
+                             int n_chunks, int tt, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_res_reduce, dim3(1), dim3(kBlock), 0, st, part, n_items, part_stride,
+                     n_steps, S, n_chunks, tt, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_tx_pack(const Items& it, const Pairs& pr, const TEnt& te, double2* blob,
+                          hipStream_t st) {
+  if (te.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tx_pack, dim3(it.n_items), dim3(kBlock), 0, st, it, pr, te, blob);
+  return hipGetLastError();
+}
+
+hipError_t launch_transmit(const Items& it, const Pairs& pr, const TEnt& te, int n_steps,
+                           const double2* T, const TxJobs& jobs, const double* scale, int nbt,
+                           int64_t pieces, int max_recv, int max_send, int64_t gram,
+                           hipStream_t st) {
+  if (jobs.n < 1 || jobs.n > kMaxJobs) return hipErrorInvalidValue;
+  int span = 0;
+  for (int q = 0; q < jobs.n; ++q) {
+    if (jobs.n_lo[q] < 0 || jobs.n_hi[q] < jobs.n_lo[q] || jobs.n_hi[q] > n_steps)
+      return hipErrorInvalidValue;
+    span = jobs.n_hi[q] - jobs.n_lo[q] + 1 > span ? jobs.n_hi[q] - jobs.n_lo[q] + 1 : span;
+  }
+  if (te.n > 0) {
+    if (nbt < 1 || nbt > kSmallK) return hipErrorInvalidValue;
+    const int tt = transmit_tile_steps(nbt, pieces, max_send, gram);
+    if (tt == 0 || max_recv < 1 || max_recv > kMaxRecvEntries) return hipErrorInvalidValue;
+    const size_t lds = tx_send_lds(tt, nbt, pieces, max_send, gram);
+    dim3 grid(blocks_for(span, tt), it.n_items, jobs.n);
+    if (tt == 32) {
+      hipLaunchKernelGGL(k_tx_send<32>, grid, dim3(kBlock), lds, st, it, te, n_steps, jobs, nbt,
+                         pieces, gram / 8);
+      hipLaunchKernelGGL(k_tx_recv<32>, grid, dim3(kBlock), 0, st, it, te, n_steps, jobs, scale,
+                         nbt);
+    } else {
+      hipLaunchKernelGGL(k_tx_send<16>, grid, dim3(kBlock), lds, st, it, te, n_steps, jobs, nbt,
+                         pieces, gram / 8);
+      hipLaunchKernelGGL(k_tx_recv<16>, grid, dim3(kBlock), 0, st, it, te, n_steps, jobs, scale,
+                         nbt);
+    }
+  } else {
+    dim3 grid(blocks_for(span, kTN), it.n_items, jobs.n);
+    hipLaunchKernelGGL(k_transmit, grid, dim3(kBlock), 0, st, it, pr, n_steps, T, jobs, scale);
+  }
   return hipGetLastError();
 }
 

@@ -50,18 +50,23 @@ class swr_info(ctypes.Structure):
         ("K_max", ctypes.c_int32), ("sum_K", ctypes.c_int64), ("sum_K2", ctypes.c_int64),
         ("n_face_nodes", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
         ("sum_KK_pairs", ctypes.c_int64), ("n_steps", ctypes.c_int32),
-        ("reserved", ctypes.c_int32), ("workspace_bytes", ctypes.c_uint64),
+        ("depth", ctypes.c_int32), ("workspace_bytes", ctypes.c_uint64),
     ]
 
 
 class swr_run_opts(ctypes.Structure):
     _fields_ = [("k_max", ctypes.c_int32), ("tol", ctypes.c_double), ("t0", ctypes.c_double),
-                ("warm", ctypes.c_int32), ("g_dev", ctypes.c_void_p)]
+                ("warm", ctypes.c_int32), ("g_dev", ctypes.c_void_p), ("depth", ctypes.c_int32),
+                ("timing", ctypes.c_int32)]
 
 
 class swr_run_stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
-                ("res", ctypes.c_double * 64), ("energy", ctypes.c_double)]
+                ("res", ctypes.c_double * 64), ("energy", ctypes.c_double),
+                ("ms_factor", ctypes.c_double), ("ms_transmit", ctypes.c_double),
+                ("ms_recur", ctypes.c_double), ("ms_residual", ctypes.c_double),
+                ("n_factor", ctypes.c_int32), ("n_transmit", ctypes.c_int32),
+                ("n_recur", ctypes.c_int32), ("n_residual", ctypes.c_int32)]
 
 
 EXPORTS = [
@@ -273,12 +278,17 @@ class Solver:
         self._call("swr_transmit", ctypes.byref(r), self._stream())
         return r.value
 
-    def run(self, k_max, tol=0.0, t0=0.0, warm=SWR_WARM_PLAIN, g=None):
-        o = swr_run_opts(k_max, tol, t0, warm, g.data_ptr() if g is not None else None)
+    def run(self, k_max, tol=0.0, t0=0.0, warm=SWR_WARM_PLAIN, g=None, depth=0, timing=False):
+        o = swr_run_opts(k_max, tol, t0, warm, g.data_ptr() if g is not None else None, depth,
+                         int(bool(timing)))
         s = swr_run_stats()
         self._call("swr_run", ctypes.byref(o), ctypes.byref(s), self._stream())
-        return dict(iters=s.iters, converged=bool(s.converged),
-                    res=[s.res[i] for i in range(min(s.iters, 64))], energy=s.energy)
+        out = dict(iters=s.iters, converged=bool(s.converged),
+                   res=[s.res[i] for i in range(min(s.iters, 64))], energy=s.energy)
+        if timing:
+            out["kernels"] = {k: dict(ms=getattr(s, "ms_" + k), launches=getattr(s, "n_" + k))
+                              for k in ("factor", "transmit", "recur", "residual")}
+        return out
 
     # -- outputs ---------------------------------------------------------------
     def _complex(self, n):
