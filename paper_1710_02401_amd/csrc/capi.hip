@@ -76,6 +76,8 @@ struct swr_handle_s {
   char* ws = nullptr;
   uint64_t ws_bytes = 0;
   Layout lay;
+  Buf bOffP;
+  std::vector<int64_t> offp;  // prefix sums of the packed symmetric sizes
   Buf bK, bOff1, bOff2, bIdx, bNb, bL, bLo, bHi, bEps, bDelta, bAoff, bAlpha, bQoff, bQn, bQx, bQw;
   Buf bNItem, bNFace, bNCount, bNCover, bNX, bNW, bNOff, bLag, bLMax;
   Buf bPI, bPJ, bPOff, bTOff, bPNode, bPNOff;
@@ -138,6 +140,7 @@ struct swr_handle_s {
     it.K = ptr<int32_t>(bK);
     it.off1 = ptr<int64_t>(bOff1);
     it.off2 = ptr<int64_t>(bOff2);
+    it.offp = ptr<int64_t>(bOffP);
     it.idx = ptr<int32_t>(bIdx);
     it.nb = ptr<int32_t>(bNb);
     it.L = ptr<int32_t>(bL);
@@ -329,7 +332,8 @@ void plan_layout(swr_handle h) {
     h->bH[q] = L.add(hist);
     h->bF[q] = L.add(hist);
   }
-  h->bMinv = L.add((size_t)h->n_mats * h->sum_K2 * 16);
+  h->bOffP = L.add((NI + 1) * 8);
+  h->bMinv = L.add((size_t)h->n_mats * std::max<int64_t>(h->sum_K2, h->offp.back()) * 16);
   h->bE = L.add((h->n_T + 1) * 8);
   h->bResPart = L.add((size_t)h->n_res_tiles * NI * 8);
   h->bResOut = L.add(8);
@@ -435,6 +439,11 @@ int32_t swr_create(const swr_desc* desc, swr_handle* out) {
     g_create_error = "this build assembles one space dimension per electron and at most 2 electrons";
     delete h;
     return SWR_E_SIZE;
+  }
+  h->offp.assign(g.n_items + 1, 0);
+  for (int q = 0; q < g.n_items; ++q) {
+    const int64_t T8 = (g.K[q] + 7) / 8;
+    h->offp[q + 1] = h->offp[q] + 32 * T8 * (T8 + 1);
   }
   h->sum_K = g.off1[g.n_items];
   h->sum_K2 = g.off2[g.n_items];
@@ -596,6 +605,7 @@ int32_t swr_assemble(swr_handle h, void* stream) {
   HIPCHECK(h, upload(h, h->bK, g.K, st));
   HIPCHECK(h, upload(h, h->bOff1, g.off1, st));
   HIPCHECK(h, upload(h, h->bOff2, g.off2, st));
+  HIPCHECK(h, upload(h, h->bOffP, h->offp, st));
   HIPCHECK(h, upload(h, h->bIdx, g.idx, st));
   HIPCHECK(h, upload(h, h->bNb, g.nb, st));
   HIPCHECK(h, upload(h, h->bL, L4, st));

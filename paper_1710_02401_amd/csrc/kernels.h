@@ -16,6 +16,8 @@ struct Items {
   const int32_t* K;      // [n_items]
   const int64_t* off1;   // [n_items+1] prefix sums of K
   const int64_t* off2;   // [n_items+1] prefix sums of K^2
+  const int64_t* offp;   // [n_items+1] prefix sums of the packed symmetric size
+                         // 64 T (T+1) / 2, T = ceil(K / 8) (upper 8x8 tiles)
   const int32_t* idx;    // [n_items][4] multi-index
   const int32_t* nb;     // [n_items][4] basis size per dimension
   const int32_t* L;      // [4]

@@ -4,8 +4,12 @@
 //   real matrices of item s: K_s x K_s row-major at off2[s];
 //   histories / Robin data vectors: item s block of (n_steps+1) x K_s
 //   entries, time-major, at (n_steps+1) * off1[s];
-//   inverse Crank-Nicolson matrices: item s, matrix n, stored transposed
-//   (column m of the inverse contiguous) at n_mats * off2[s] + n * K_s^2.
+//   inverse Crank-Nicolson matrices (complex symmetric): item s, matrix n
+//   at n_mats * offp[s] + n * P_s, P_s = 64 T (T+1) / 2 with T = ceil(K_s/8):
+//   the upper 8x8 tiles (I <= J) row by row, each column-major (entry (a, b)
+//   of tile (I, J) = M[8I+a][8J+b] at b * 8 + a), padding rows and columns
+//   of the last tiles holding the identity.  Imaginary-time inverses (one per
+//   item) are stored whole and transposed at off2[s].
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -38,6 +42,9 @@ __device__ inline double2 crecip(double2 a) {
   return make_double2(r / d, -1.0 / d);
 }
 __device__ inline bool cfinite(double2 a) { return isfinite(a.x) && isfinite(a.y); }
+
+// index of the upper tile (I, J), I <= J, among T x T tiles stored row by row
+__device__ inline int tile_index(int I, int J, int T) { return I * T - (I * (I - 1)) / 2 + (J - I); }
 
 // erf(uh) - erf(ul), ul <= uh, with the complementary function in the tails
 __device__ inline double erf_diff(double ul, double uh) {
@@ -579,17 +586,34 @@ __global__ void __launch_bounds__(kBlock) k_invert(Items it, int n_mats, const d
     }
   }
   if (bad && threadIdx.x == 0) atomicOr(flags, kFlagPivot);
-  double2* out = Minv + (int64_t)n_mats * o2 + (int64_t)n * K * K;
   bool nonfinite = false;
+  if (tise) {  // one whole inverse per item, transposed
+    double2* out = Minv + o2;
 #pragma unroll
-  for (int j = 0; j < T; ++j) {
-    const int c = TC * T + j;
+    for (int j = 0; j < T; ++j) {
+      const int c = TC * T + j;
 #pragma unroll
-    for (int i = 0; i < T; ++i) {
-      const int r = TR * T + i;
-      if (r < K && c < K) {
-        out[(int64_t)c * K + r] = a[i][j];
-        nonfinite |= !cfinite(a[i][j]);
+      for (int i = 0; i < T; ++i) {
+        const int r = TR * T + i;
+        if (r < K && c < K) {
+          out[(int64_t)c * K + r] = a[i][j];
+          nonfinite |= !cfinite(a[i][j]);
+        }
+      }
+    }
+  } else {  // packed upper 8x8 tiles (the inverse is complex symmetric)
+    const int T8 = (K + 7) >> 3;
+    double2* out = Minv + (int64_t)n_mats * it.offp[s] + (int64_t)n * 32 * T8 * (T8 + 1);
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+      const int c = TC * T + j;
+#pragma unroll
+      for (int i = 0; i < T; ++i) {
+        const int r = TR * T + i;
+        if (r < 8 * T8 && c < 8 * T8 && (r >> 3) <= (c >> 3)) {
+          out[(int64_t)tile_index(r >> 3, c >> 3, T8) * 64 + (c & 7) * 8 + (r & 7)] = a[i][j];
+          nonfinite |= !cfinite(a[i][j]);
+        }
       }
     }
   }
@@ -609,6 +633,7 @@ __global__ void __launch_bounds__(kBlock) k_invert(Items it, int n_mats, const d
 //   rhs = Ap c^n - i tau (Hr + E_n Q) c^n + (i tau / 2)(f^n + f^{n+1})
 //   c^{n+1} = (M^{n+1})^{-1} rhs
 constexpr int kRecThreads = 512;
+constexpr int kRecPrefetch = 3;  // steps between a load of the inverse and its use
 // LDS vectors of the recurrence: entry m at (m / 8) * 9 + m % 8, so that the
 // eight column groups read by a wave fall in different banks
 constexpr int kVecPad = 9 * (kSmallK / 8);
@@ -647,19 +672,32 @@ __device__ inline double group8_sum(double v) {
 // addresses: entries past K multiply the zero padding of the LDS vectors
 // (columns) or are discarded (rows); steps past the job's end are never
 // consumed.
+// The inverse of step n is read from the packed upper tiles: row rr of
+// column block J is row a of tile (I, J) when J >= I (eight entries that
+// neighbouring lanes read side by side), else column a of tile (J, I) (128
+// contiguous bytes per lane).  Row and tile indices are clamped, so padding
+// lanes read valid entries.
 __device__ inline void prefetch(RecPipe& pp, const double2* Mb, const double2* F, int64_t hb,
                                 int n, int n_end, int K, int r, int part) {
   const int rr = r < K ? r : K - 1;
   const int nn = n < n_end ? n : n_end - 1;
   pp.f = F[hb + (int64_t)(nn + 1) * K + rr];
-  const double2* base = Mb + (int64_t)nn * K * K + rr;
+  const int T8 = (K + 7) >> 3;
+  const int I = rr >> 3, a = rr & 7;
+  const int J = part < T8 ? part : T8 - 1;
+  const double2* base = Mb + (int64_t)nn * 32 * T8 * (T8 + 1);
+  if (J >= I) {
+    base += tile_index(I, J, T8) * 64 + a;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int m = part * 8 + j;
-    pp.m[j] = base[(m < K ? m : K - 1) * K];
+    for (int j = 0; j < 8; ++j) pp.m[j] = base[j * 8];
+  } else {
+    base += tile_index(J, I, T8) * 64 + a * 8;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) pp.m[j] = base[j];
   }
 }
 
+template <int PD>
 __device__ inline void cn_step(RecState& st, RecPipe& pp, int n, int n_lo, int n_end, int K,
                                int r, int part, double tau, const double* sE, const double2* Mb,
                                const double2* F, double2* hist, int64_t hb, double2* sc,
@@ -691,7 +729,7 @@ __device__ inline void cn_step(RecState& st, RecPipe& pp, int n, int n_lo, int n
   }
   ox = group8_sum(ox);
   oy = group8_sum(oy);
-  prefetch(pp, Mb, F, hb, n + 2, n_end, K, r, part);
+  prefetch(pp, Mb, F, hb, n + PD, n_end, K, r, part);
   const double2 v = make_double2(ox, oy);
   if (r < K) sc[vpos(r)] = v;
   // Every lane stores (no divergent branch around the store, which would
@@ -705,6 +743,8 @@ __device__ inline void cn_step(RecState& st, RecPipe& pp, int n, int n_lo, int n
   for (int j = 0; j < 8; ++j) st.cm[j] = sc[part * 9 + j];  // zero padded past K
 }
 
+// PD = prefetch distance in steps (register buffers in flight)
+template <int PD>
 __global__ void __launch_bounds__(kRecThreads) k_cn_recur(Items it, int n_steps, const double* Ap,
                                                           const double* Hr, const double* Q,
                                                           const double* Eall, double tau,
@@ -752,23 +792,28 @@ __global__ void __launch_bounds__(kRecThreads) k_cn_recur(Items it, int n_steps,
     sc[vpos(threadIdx.x)] = make_double2(0.0, 0.0);
     srhs[vpos(threadIdx.x)] = make_double2(0.0, 0.0);
   }
-  const double2* Mb = Minv + (int64_t)n_steps * o2;
-  RecPipe pA, pB;
+  const double2* Mb = Minv + (int64_t)n_steps * it.offp[s];
+  RecPipe pA, pB, pC;
   prefetch(pA, Mb, F, hb, n_lo, n_end, K, r, part);
   prefetch(pB, Mb, F, hb, n_lo + 1, n_end, K, r, part);
+  if (PD == 3) prefetch(pC, Mb, F, hb, n_lo + 2, n_end, K, r, part);
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < 8; ++j) st.cm[j] = sc[part * 9 + j];
   bool bad = false;
-  // unconditional two-step body (a conditional second half would make the
-  // loop-header wait state assume the first buffer was loaded last)
+  // unconditional PD-step body (a conditional tail inside the body would make
+  // the loop-header wait state assume the first buffer was loaded last)
   int n = n_lo;
-  for (; n + 1 < n_end; n += 2) {
-    cn_step(st, pA, n, n_lo, n_end, K, r, part, tau, sE, Mb, F, hist, hb, sc, srhs, bad);
-    cn_step(st, pB, n + 1, n_lo, n_end, K, r, part, tau, sE, Mb, F, hist, hb, sc, srhs, bad);
+  for (; n + PD - 1 < n_end; n += PD) {
+    cn_step<PD>(st, pA, n, n_lo, n_end, K, r, part, tau, sE, Mb, F, hist, hb, sc, srhs, bad);
+    cn_step<PD>(st, pB, n + 1, n_lo, n_end, K, r, part, tau, sE, Mb, F, hist, hb, sc, srhs, bad);
+    if (PD == 3)
+      cn_step<PD>(st, pC, n + 2, n_lo, n_end, K, r, part, tau, sE, Mb, F, hist, hb, sc, srhs, bad);
   }
   if (n < n_end)
-    cn_step(st, pA, n, n_lo, n_end, K, r, part, tau, sE, Mb, F, hist, hb, sc, srhs, bad);
+    cn_step<PD>(st, pA, n, n_lo, n_end, K, r, part, tau, sE, Mb, F, hist, hb, sc, srhs, bad);
+  if (n + 1 < n_end)
+    cn_step<PD>(st, pB, n + 1, n_lo, n_end, K, r, part, tau, sE, Mb, F, hist, hb, sc, srhs, bad);
   if (bad) atomicOr(flags, kFlagNaN);
 }
 
@@ -1782,8 +1827,8 @@ hipError_t launch_cn_recur(const Items& it, int n_steps, const double* Ap, const
     max_cnt = jobs.n_cnt[q] > max_cnt ? jobs.n_cnt[q] : max_cnt;
   }
   const size_t lds = (size_t)(max_cnt + 1) * sizeof(double);
-  hipLaunchKernelGGL(k_cn_recur, dim3(it.n_items, jobs.n), dim3(kRecThreads), lds, st, it, n_steps,
-                     Ap, Hr, Q, Eall, tau, Minv, c0, jobs, flags);
+  hipLaunchKernelGGL(k_cn_recur<kRecPrefetch>, dim3(it.n_items, jobs.n), dim3(kRecThreads), lds, st,
+                     it, n_steps, Ap, Hr, Q, Eall, tau, Minv, c0, jobs, flags);
   return hipGetLastError();
 }
 
