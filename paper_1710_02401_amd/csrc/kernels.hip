@@ -500,122 +500,215 @@ __global__ void k_cn_matrices(int64_t n, const double* A, const double* Kin, con
 }
 
 // ---------------------------------------------------------------------------
-// Batched inversion of the local Crank-Nicolson matrices
-// M = Ar + i tau (Hr + E Q) (TDSE) or M = Ar (TISE), one block of 256 threads
-// per (matrix, item).  Gauss-Jordan elimination without pivoting (the
-// Hermitian part Ar is positive definite, so every pivot is non-zero) with
-// the matrix held in registers: thread (TR, TC) owns rows TR*T.., columns
-// TC*T.. (16T >= K; the padding is the identity and never changes).  Each
-// pivot broadcasts its row and column through LDS.  The inverse is stored
-// transposed, out[c*K + r] = Minv[r][c], so that column c is contiguous.
-template <int T>
-__global__ void __launch_bounds__(kBlock) k_invert(Items it, int n_mats, const double* Ar,
-                                                   const double* Hr, const double* Q,
-                                                   const double* Eall, double tau, int tise,
-                                                   double2* Minv, int* flags) {
+// Batched inversion on the matrix cores: blocked Gauss-Jordan with 16 x 16
+// blocks, one wave per block row (NB = ceil(K/16) waves per matrix), complex
+// block products as four real v_mfma_f64_16x16x4f64 per k-chunk.
+// Block step k: the wave of block row k inverts its diagonal block D in
+// registers (unblocked Gauss-Jordan, rows and columns broadcast through
+// LDS), forms D A_kj for j != k and publishes the row; every other wave i
+// forms A_ij - A_ik (D A_kj) and -A_ik D.  No pivoting (the Hermitian part
+// of M is positive definite); padding rows and columns hold the identity.
+// Tile layout ("D layout" of the instruction): lane l, register r holds
+// entry (4r + l/16, l%16); register q of a tile is then exactly the B
+// operand of k-chunk q, and the A operand (entry (l%16, 4q + l/16)) is
+// read back from LDS.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ inline v4d mfma16(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <int NB>
+__global__ void __launch_bounds__(64 * NB) k_invert_mfma(Items it, int n_mats, const double* Ar,
+                                                         const double* Hr, const double* Q,
+                                                         const double* Eall, double tau, int tise,
+                                                         double2* Minv, int* flags) {
   const int n = blockIdx.x;
   const int s = blockIdx.y;
   const int K = it.K[s];
-  const int TR = threadIdx.x & 15, TC = threadIdx.x >> 4;
-  __shared__ double2 rowp[16 * T];
-  __shared__ double2 colp[16 * (T + 1)];  // thread row TR at TR (T+1): no bank conflicts
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int lr = l >> 4, lc = l & 15;
+  __shared__ double2 rowblk[NB][256];  // published block row, [position][r * 64 + lane]
+  __shared__ double2 aop[NB][256];     // per wave: a tile row-major, read back as A operand
+  __shared__ double2 prow[16], pcol[16];
   const int64_t o2 = it.off2[s];
   const double E = tise ? 0.0 : Eall[n + 1];
-  double2 a[T][T];
+  // the wave's block row; position t holds column block (k + t) mod NB at
+  // block step k (rotated after every step), so the pivot block is always
+  // position 0 and the step loop need not be unrolled
+  double re[NB][4], im[NB][4];
 #pragma unroll
-  for (int i = 0; i < T; ++i) {
-    const int r = TR * T + i;
+  for (int j = 0; j < NB; ++j)
 #pragma unroll
-    for (int j = 0; j < T; ++j) {
-      const int c = TC * T + j;
-      if (r < K && c < K) {
-        const int64_t e = o2 + (int64_t)r * K + c;
-        a[i][j] = make_double2(Ar[e], tise ? 0.0 : tau * (Hr[e] + E * Q[e]));
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * w + 4 * r + lr, col = 16 * j + lc;
+      if (row < K && col < K) {
+        const int64_t e = o2 + (int64_t)row * K + col;
+        re[j][r] = Ar[e];
+        im[j][r] = tise ? 0.0 : tau * (Hr[e] + E * Q[e]);
       } else {
-        a[i][j] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+        re[j][r] = row == col ? 1.0 : 0.0;
+        im[j][r] = 0.0;
       }
     }
-  }
   bool bad = false;
-  // pivots in groups of T so that the in-tile offset pi is a compile-time
-  // constant (a runtime index into the register tile would spill it)
-  for (int pt = 0; pt * T < K; ++pt) {
+#pragma unroll 1
+  for (int k = 0; k < NB; ++k) {
+    if (w == k) {
+      // unblocked Gauss-Jordan on the diagonal tile, in place
 #pragma unroll
-    for (int pi = 0; pi < T; ++pi) {
-      const int p = pt * T + pi;
-      if (p >= K) break;
-      if (TR == pt) {
+      for (int p = 0; p < 16; ++p) {
+        if (lr == (p & 3)) prow[lc] = make_double2(re[0][p >> 2], im[0][p >> 2]);
+        if (lc == p) {
 #pragma unroll
-        for (int j = 0; j < T; ++j) rowp[TC * T + j] = a[pi][j];
+          for (int r = 0; r < 4; ++r) pcol[4 * r + lr] = make_double2(re[0][r], im[0][r]);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const double2 piv = prow[p];
+        bad |= !(piv.x != 0.0 || piv.y != 0.0);
+        const double2 inv = crecip(piv);
+        const double2 v = lc == p ? make_double2(1.0, 0.0) : prow[lc];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 4 * r + lr;
+          const double2 u = i == p ? make_double2(1.0 - inv.x, -inv.y) : cmul(pcol[i], inv);
+          const double bx = lc == p ? (i == p ? 1.0 : 0.0) : re[0][r];
+          const double by = lc == p ? 0.0 : im[0][r];
+          re[0][r] = fma(-u.x, v.x, fma(u.y, v.y, bx));
+          im[0][r] = fma(-u.x, v.y, fma(-u.y, v.x, by));
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
-      if (TC == pt) {
+      // A operand of D
 #pragma unroll
-        for (int i = 0; i < T; ++i) colp[TR * (T + 1) + i] = a[i][pi];
+      for (int r = 0; r < 4; ++r) aop[w][(4 * r + lr) * 16 + lc] = make_double2(re[0][r], im[0][r]);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      double ar[4], ai[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double2 t = aop[w][lc * 16 + 4 * q + lr];
+        ar[q] = t.x;
+        ai[q] = t.y;
       }
-      __syncthreads();
-      // In-place Gauss-Jordan step as one rank-1 update: with column p of
-      // the matrix replaced by e_p, u = col_p / piv except u_p = 1 - 1/piv,
-      // and v = row_p except v_p = 1, the new matrix is a - u v^T.
-      const double2 piv = rowp[p];
-      bad |= !(piv.x != 0.0 || piv.y != 0.0);
-      const double2 inv = crecip(piv);
-      double2 u[T], v[T];
+      // row update D A_kj at positions 1 ..
 #pragma unroll
-      for (int i = 0; i < T; ++i) {
-        const int r = TR * T + i;
-        const double2 ui = cmul(colp[TR * (T + 1) + i], inv);
-        u[i] = (r == p) ? make_double2(1.0 - inv.x, -inv.y) : ui;
-      }
+      for (int t = 1; t < NB; ++t) {
+        v4d cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int j = 0; j < T; ++j) {
-        const int c = TC * T + j;
-        v[j] = (c == p) ? make_double2(1.0, 0.0) : rowp[c];
-      }
+        for (int q = 0; q < 4; ++q) {
+          cr = mfma16(ar[q], re[t][q], cr);
+          cr = mfma16(-ai[q], im[t][q], cr);
+          ci = mfma16(ar[q], im[t][q], ci);
+          ci = mfma16(ai[q], re[t][q], ci);
+        }
 #pragma unroll
-      for (int i = 0; i < T; ++i) {
-        const int r = TR * T + i;
-#pragma unroll
-        for (int j = 0; j < T; ++j) {
-          const bool colpiv = (TC * T + j) == p;
-          const double2 base = colpiv ? make_double2(r == p ? 1.0 : 0.0, 0.0) : a[i][j];
-          a[i][j] = make_double2(fma(-u[i].x, v[j].x, fma(u[i].y, v[j].y, base.x)),
-                                 fma(-u[i].x, v[j].y, fma(-u[i].y, v[j].x, base.y)));
+        for (int r = 0; r < 4; ++r) {
+          re[t][r] = cr[r];
+          im[t][r] = ci[r];
         }
       }
-      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < NB; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) rowblk[t][r * 64 + l] = make_double2(re[t][r], im[t][r]);
     }
+    __syncthreads();
+    if (w != k) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) aop[w][(4 * r + lr) * 16 + lc] = make_double2(re[0][r], im[0][r]);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      double ar[4], ai[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double2 t = aop[w][lc * 16 + 4 * q + lr];
+        ar[q] = t.x;
+        ai[q] = t.y;
+      }
+      // A_ij - A_ik (D A_kj) at positions 1 ..
+#pragma unroll
+      for (int t = 1; t < NB; ++t) {
+        v4d cr = {re[t][0], re[t][1], re[t][2], re[t][3]};
+        v4d ci = {im[t][0], im[t][1], im[t][2], im[t][3]};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double2 b = rowblk[t][q * 64 + l];
+          cr = mfma16(-ar[q], b.x, cr);
+          cr = mfma16(ai[q], b.y, cr);
+          ci = mfma16(-ar[q], b.y, ci);
+          ci = mfma16(-ai[q], b.x, ci);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          re[t][r] = cr[r];
+          im[t][r] = ci[r];
+        }
+      }
+      // -A_ik D at position 0
+      v4d cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double2 b = rowblk[0][q * 64 + l];
+        cr = mfma16(-ar[q], b.x, cr);
+        cr = mfma16(ai[q], b.y, cr);
+        ci = mfma16(-ar[q], b.y, ci);
+        ci = mfma16(-ai[q], b.x, ci);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        re[0][r] = cr[r];
+        im[0][r] = ci[r];
+      }
+    }
+    // rotate: position t <- t + 1 (the next pivot block comes to position 0)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double x0 = re[0][r], y0 = im[0][r];
+#pragma unroll
+      for (int t = 0; t + 1 < NB; ++t) {
+        re[t][r] = re[t + 1][r];
+        im[t][r] = im[t + 1][r];
+      }
+      re[NB - 1][r] = x0;
+      im[NB - 1][r] = y0;
+    }
+    __syncthreads();
   }
-  if (bad && threadIdx.x == 0) atomicOr(flags, kFlagPivot);
+  if (bad) atomicOr(flags, kFlagPivot);
   bool nonfinite = false;
   if (tise) {  // one whole inverse per item, transposed
     double2* out = Minv + o2;
 #pragma unroll
-    for (int j = 0; j < T; ++j) {
-      const int c = TC * T + j;
+    for (int j = 0; j < NB; ++j)
 #pragma unroll
-      for (int i = 0; i < T; ++i) {
-        const int r = TR * T + i;
-        if (r < K && c < K) {
-          out[(int64_t)c * K + r] = a[i][j];
-          nonfinite |= !cfinite(a[i][j]);
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * w + 4 * r + lr, col = 16 * j + lc;
+        if (row < K && col < K) {
+          out[(int64_t)col * K + row] = make_double2(re[j][r], im[j][r]);
+          nonfinite |= !(isfinite(re[j][r]) && isfinite(im[j][r]));
         }
       }
-    }
   } else {  // packed upper 8x8 tiles (the inverse is complex symmetric)
     const int T8 = (K + 7) >> 3;
     double2* out = Minv + (int64_t)n_mats * it.offp[s] + (int64_t)n * 32 * T8 * (T8 + 1);
 #pragma unroll
-    for (int j = 0; j < T; ++j) {
-      const int c = TC * T + j;
+    for (int j = 0; j < NB; ++j)
 #pragma unroll
-      for (int i = 0; i < T; ++i) {
-        const int r = TR * T + i;
-        if (r < 8 * T8 && c < 8 * T8 && (r >> 3) <= (c >> 3)) {
-          out[(int64_t)tile_index(r >> 3, c >> 3, T8) * 64 + (c & 7) * 8 + (r & 7)] = a[i][j];
-          nonfinite |= !cfinite(a[i][j]);
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * w + 4 * r + lr, col = 16 * j + lc;
+        if (row < 8 * T8 && col < 8 * T8 && (row >> 3) <= (col >> 3)) {
+          out[(int64_t)tile_index(row >> 3, col >> 3, T8) * 64 + (col & 7) * 8 + (row & 7)] =
+              make_double2(re[j][r], im[j][r]);
+          nonfinite |= !(isfinite(re[j][r]) && isfinite(im[j][r]));
         }
       }
-    }
   }
   if (nonfinite) atomicOr(flags, kFlagNaN);
 }
@@ -1800,18 +1893,18 @@ hipError_t launch_invert(const Items& it, int n_mats, const double* Ar, const do
                          const double* Q, const double* Eall, double tau, int tise,
                          double2* Minv, int* flags, hipStream_t st, int K_max) {
   dim3 grid(n_mats, it.n_items);
-  const int T = (K_max + 15) / 16;
-  if (T <= 1)
-    hipLaunchKernelGGL(k_invert<1>, grid, dim3(kBlock), 0, st, it, n_mats, Ar, Hr, Q, Eall, tau,
+  const int NB = (K_max + 15) / 16;
+  if (NB <= 1)
+    hipLaunchKernelGGL(k_invert_mfma<1>, grid, dim3(64), 0, st, it, n_mats, Ar, Hr, Q, Eall, tau,
                        tise, Minv, flags);
-  else if (T == 2)
-    hipLaunchKernelGGL(k_invert<2>, grid, dim3(kBlock), 0, st, it, n_mats, Ar, Hr, Q, Eall, tau,
+  else if (NB == 2)
+    hipLaunchKernelGGL(k_invert_mfma<2>, grid, dim3(128), 0, st, it, n_mats, Ar, Hr, Q, Eall, tau,
                        tise, Minv, flags);
-  else if (T == 3)
-    hipLaunchKernelGGL(k_invert<3>, grid, dim3(kBlock), 0, st, it, n_mats, Ar, Hr, Q, Eall, tau,
+  else if (NB == 3)
+    hipLaunchKernelGGL(k_invert_mfma<3>, grid, dim3(192), 0, st, it, n_mats, Ar, Hr, Q, Eall, tau,
                        tise, Minv, flags);
   else
-    hipLaunchKernelGGL(k_invert<4>, grid, dim3(kBlock), 0, st, it, n_mats, Ar, Hr, Q, Eall, tau,
+    hipLaunchKernelGGL(k_invert_mfma<4>, grid, dim3(256), 0, st, it, n_mats, Ar, Hr, Q, Eall, tau,
                        tise, Minv, flags);
   return hipGetLastError();
 }

@@ -137,3 +137,34 @@ def test_time_nodes_match_oracle_and_short_windows_are_rejected(S):
         else:
             assert rc == -1 and b"n_steps >= 11" in lib.swr_last_error(h)
         lib.swr_destroy(h)
+
+
+def test_batched_geometries_share_one_decomposition(S):
+    """Items are geometry-major copies of one decomposition: per-item sizes
+    repeat per geometry and the covering sets stay inside a geometry."""
+    cfg = workloads.get_config("c3-mini")
+    rc, h = _create(S, cfg)
+    assert rc == 0
+    lib = S.load_library()
+    n_sub, n_geom = 16, 4
+    items = np.zeros(n_sub * n_geom * 10, dtype=np.int32)
+    assert lib.swr_get_items(h, items.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), items.size) == 0
+    K = items.reshape(-1, 10)[:, 0]
+    assert list(K) == [nb[0] for nb in cfg["nbasis"]] * n_geom
+    info = S.swr_info()
+    assert lib.swr_query(h, ctypes.byref(info)) == 0
+    maps = np.zeros(info.n_face_nodes * 16, dtype=np.int32)
+    assert lib.swr_get_index_maps(h, maps.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), maps.size) == 0
+    maps = maps.reshape(-1, 16)
+    per_geom = maps.shape[0] // n_geom
+    assert np.array_equal(maps[:per_geom], maps[per_geom:2 * per_geom])
+    dec = Decomposition(dict(cfg, nuclei=cfg["geometries"][0]))
+    assert np.array_equal(maps[:per_geom], _oracle_maps(dec))
+    lib.swr_destroy(h)
+
+
+def test_bases_beyond_64_are_rejected_clearly(S):
+    cfg = workloads.get_config("c3-1e-1d-batched")
+    rc, h = _create(S, cfg)
+    assert rc == -2
+    assert b"exceeds 64" in S.load_library().swr_last_error(None)

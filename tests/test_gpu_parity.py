@@ -272,3 +272,34 @@ def test_pipelined_run_equals_one_iterate_at_a_time(name):
         assert np.array_equal(h, ref_h), depth
         assert np.array_equal(f, ref_f), depth
 
+
+
+def test_batched_geometries_match_independent_runs():
+    """Geometries batched into one handle give each geometry's own window
+    (the oracle runs them one by one); the residual is the root of the
+    summed squares."""
+    cfg = workloads.get_config("c3-mini")
+    s = _solver(cfg)
+    iters = 5
+    st = s.run(k_max=iters, tol=0.0)
+    hist = [_np(h) for h in s.split_history(s.history())]
+    n_sub = len(cfg["nbasis"])
+    res2 = np.zeros(iters)
+    for g, nuc in enumerate(cfg["geometries"]):
+        prob = o_swr.Problem(dict(cfg, nuclei=nuc, geometries=None))
+        h_o, res_o = o_swr.swr_window(prob, prob.initial_coeffs(), iters=iters)
+        assert a_norm_rel(prob, hist[g * n_sub:(g + 1) * n_sub], h_o) <= 1e-10, g
+        res2 += np.array(res_o) ** 2
+    assert np.allclose(st["res"], np.sqrt(res2), rtol=1e-8, atol=1e-14)
+
+
+def test_uneven_bases_in_two_dimensions():
+    cfg = dict(TINY["tiny-2d"], name="tiny-2d-uneven",
+               nbasis=[[5, 4], [4, 6], [6, 3], [3, 5], [5, 5], [4, 3]])
+    s = _solver(cfg)
+    prob = o_swr.Problem(cfg)
+    assert list(s.K) == [20, 24, 18, 15, 25, 12]
+    st = s.run(k_max=4, tol=0.0)
+    h_o, res_o = o_swr.swr_window(prob, prob.initial_coeffs(), iters=4)
+    assert a_norm_rel(prob, [_np(h) for h in s.split_history(s.history())], h_o) <= 1e-10
+    assert np.allclose(st["res"], res_o, rtol=1e-8, atol=1e-14)

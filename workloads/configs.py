@@ -70,7 +70,43 @@ _C5 = dict(
     iters=30, tol=1e-8, face_nodes=[2, 4], quad_nodes=16,
 )
 
-CONFIGS = {c["name"]: c for c in (_C1, _C2, _C2_TISE, _C4, _C5)}
+def _uneven_geometries(n_geom, L, box, k_lo, k_span, seed=1710):
+    """Seeded geometries of the batched one-electron workload: two unit
+    charges at +-R_g/2 with R_g = 1 + 2 u_g (u_g uniform), and per-subdomain
+    basis sizes round(k_lo + k_span exp(-d^2 / 8)) with d the distance from
+    the subdomain centre to the nearest nucleus (a density rule: more
+    Gaussians where the wells are).  The sizes of geometry 0 apply to all
+    geometries (one decomposition, batched)."""
+    import numpy as np
+    u = np.random.default_rng(seed).random(n_geom)
+    R = 1.0 + 2.0 * u
+    geoms = [[[float(-0.5 * r)], [float(0.5 * r)]] for r in R]
+    h = (box[1] - box[0]) / L
+    centres = box[0] + h * (np.arange(L) + 0.5)
+    d = np.min(np.abs(centres[:, None] - np.array([-0.5 * R[0], 0.5 * R[0]])[None, :]), axis=1)
+    nb = [[int(round(k_lo + k_span * np.exp(-di * di / 8.0)))] for di in d]
+    return geoms, nb
+
+
+_C3_GEOMS, _C3_NB = _uneven_geometries(64, 256, (-20.0, 20.0), 32, 224)
+_C3 = dict(
+    name="c3-1e-1d-batched", mode="tdse", n_elec=1, dim=1,
+    L=[256], box_lo=[-20.0], box_hi=[20.0], overlap=[0.2 * 40.0 / 256],
+    nbasis=_C3_NB, width=None, width_ratio=0.7, geometries=_C3_GEOMS,
+    nuclei=_C3_GEOMS[0], charges=[1.0, 1.0], eps_en=1.0, eps_ee=1.0,
+    dt=0.01, n_steps=200, mu=[0.0, -10.0],
+    field=dict(E0=0.05, omega=0.057, phase=0.0, axis=0),
+    init=dict(alpha=1.0, center=[0.0]),
+    iters=30, tol=1e-8, face_nodes=[16, 32], quad_nodes=16,
+)
+
+# The same recipe at sizes this build runs (K <= 64): 4 geometries, 16
+# subdomains, K from 8 to 40.
+_C3M_GEOMS, _C3M_NB = _uneven_geometries(4, 16, (-20.0, 20.0), 8, 32)
+_C3_MINI = dict(_C3, name="c3-mini", L=[16], overlap=[0.5], nbasis=_C3M_NB,
+                geometries=_C3M_GEOMS, nuclei=_C3M_GEOMS[0], iters=8)
+
+CONFIGS = {c["name"]: c for c in (_C1, _C2, _C2_TISE, _C3, _C3_MINI, _C4, _C5)}
 
 
 def get_config(name, **overrides):
