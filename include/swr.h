@@ -85,6 +85,7 @@ typedef struct swr_desc {
   double init_center[4];
   int32_t face_nodes_band, face_nodes_mid; /* GL nodes per tangential panel   */
   int32_t quad_nodes;        /* GL nodes per potential quadrature panel       */
+  int32_t learned_nodes;     /* time nodes M of the learned warm start, 2..64; 0 = 8 */
 } swr_desc;
 
 typedef struct swr_handle_s* swr_handle;
@@ -99,6 +100,8 @@ typedef struct swr_info {
   int32_t n_steps;
   int32_t depth;             /* Schwarz iterates swr_run keeps in flight      */
   uint64_t workspace_bytes;
+  int32_t learned_nodes;     /* M, time nodes of the learned warm start       */
+  int32_t reserved;
 } swr_info;
 
 /* ---- lifetime ------------------------------------------------------------*/
@@ -242,38 +245,39 @@ int32_t swr_get_norms(swr_handle h, void* dst_dev, uint64_t bytes, void* stream)
 
 /* ---- learned warm start (Section 4.1: psi^(0) of a window is free) ------
  * The plain guess holds the window's initial Robin data g0 constant; the
- * learned guess adds a correction predicted at eight time nodes (steps
- * n_m = round(n_T (1 - cos(pi m/7))/2)) and interpolated to every step with
- * the barycentric Lagrange form.  RMS_i = sqrt(mean |g0|^2) over item i's
+ * learned guess adds a correction predicted at M time nodes (steps
+ * n_m = round(n_T (1 - cos(pi m/(M-1)))/2), M = swr_info.learned_nodes) and
+ * interpolated to every step with the barycentric Lagrange form.  RMS_i = sqrt(mean |g0|^2) over item i's
  * receiving nodes; the window scale S = max_i RMS_i (1 if g0 vanishes).
  * Network input of item i (n_in entries): (Re, Im) of g0/S node by node,
- * zero padding to n_in - 16, then 16 tail entries: 10 E(t0 + t_m) for the
- * eight nodes; the item's box centre as (c_k - mid_k)/half_k of the global
+ * zero padding to n_in - (M + 8), then M + 8 tail entries: 10 E(t0 + t_m)
+ * for the M nodes; the item's box centre as (c_k - mid_k)/half_k of the global
  * box for k < D, zero padded to four; RMS_i / S; t0 / (8 T) with T the
  * window length; two zeros.
  * Network output (n_out entries) = (g(t_m) - g0)/S as [m][node][re, im].
  * Items' receiving nodes are contiguous in the canonical node order.
- * The eight rounded nodes are distinct only for n_steps >= 11: on shorter
- * windows swr_time_nodes and the three swr_learned_* calls return SWR_E_ARG. */
+ * The rounded nodes must be distinct (n_steps >= 11 for M = 8, >= 46 for
+ * M = 16, >= 195 for M = 32): on shorter windows swr_time_nodes and the
+ * three swr_learned_* calls return SWR_E_ARG. */
 
 /* Change the field E(t) = E0 sin(omega t + phase) used by later swr_factor. */
 int32_t swr_set_field(swr_handle h, double E0, double omega, double phase);
 /* Start the next window: initial coefficients := last step of the current
  * iterate, then the plain warm start (as swr_set_initial). */
 int32_t swr_advance_window(swr_handle h, void* stream);
-/* The eight time-node steps (host int32 [8]). */
+/* The M time-node steps (host int32 [M]). */
 int32_t swr_time_nodes(swr_handle h, int32_t* steps_host);
-/* Robin data g(y, t_n) at every receiving node for n_sel <= 16 steps of the
+/* Robin data g(y, t_n) at every receiving node for n_sel <= 64 steps of the
  * current iterate (device complex [n_sel][n_face_nodes]); 0 on global faces. */
 int32_t swr_face_data(swr_handle h, int32_t n_sel, const int32_t* steps_host, void* g_dev,
                       void* stream);
 /* Network input (device float [n_items][n_in]) and scale (device double
  * [n_items], every entry S) from g0 (device complex [n_face_nodes]) for the
- * window starting at t0.  SWR_E_SIZE if n_in < 2 * max nodes per item + 16. */
+ * window starting at t0.  SWR_E_SIZE if n_in < 2 * max nodes per item + M + 8. */
 int32_t swr_learned_features(swr_handle h, const void* g0_dev, double t0, int32_t n_in,
                              float* x_dev, double* scale_dev, void* stream);
 /* Training targets (device float [n_items][n_out]) from the Robin data at
- * the eight time nodes (device complex [8][n_face_nodes], node 0 = g0). */
+ * the M time nodes (device complex [M][n_face_nodes], node 0 = g0). */
 int32_t swr_learned_targets(swr_handle h, const void* g_nodes_dev, const double* scale_dev,
                             int32_t n_out, float* y_dev, void* stream);
 /* Robin data of the learned guess at every step (device complex

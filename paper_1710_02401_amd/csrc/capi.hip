@@ -19,21 +19,22 @@ namespace {
 
 thread_local std::string g_create_error;
 
-constexpr int kNodesT = 8;          // time nodes of the learned warm start
 constexpr double kFieldScale = 10.0;  // field feature = 10 E(t)
 
-std::vector<int> time_nodes(int n_T) {
-  std::vector<int> n(kNodesT);
+// time nodes of the learned warm start: M Chebyshev-Lobatto positions
+// rounded to the time grid
+std::vector<int> time_nodes(int n_T, int M) {
+  std::vector<int> n(M);
   const double pi = 3.14159265358979323846;
-  for (int m = 0; m < kNodesT; ++m)
-    n[m] = (int)std::lround(n_T * (1.0 - std::cos(pi * m / (kNodesT - 1))) / 2.0);
+  for (int m = 0; m < M; ++m)
+    n[m] = (int)std::lround(n_T * (1.0 - std::cos(pi * m / (M - 1))) / 2.0);
   return n;
 }
 
-// the interpolation needs eight distinct nodes: true for n_T >= 11
-bool distinct_time_nodes(int n_T) {
-  const std::vector<int> n = time_nodes(n_T);
-  for (int m = 1; m < kNodesT; ++m)
+// the interpolation needs distinct nodes (n_T >= 11 for M = 8)
+bool distinct_time_nodes(int n_T, int M) {
+  const std::vector<int> n = time_nodes(n_T, M);
+  for (int m = 1; m < M; ++m)
     if (n[m] <= n[m - 1]) return false;
   return true;
 }
@@ -42,7 +43,8 @@ constexpr int kMaxSlots = 6;    // depth <= 4, the previous iterate, one for the
 constexpr int kResEvents = 8;   // residual read-backs in flight
 constexpr int kGpuCUs = 256;    // MI355X compute units (one recurrence block each)
 
-const char* const kShortWindow = "the learned warm start needs n_steps >= 11 (distinct time nodes)";
+const char* const kShortWindow =
+    "the learned warm start's time nodes are not distinct: the window has too few steps";
 
 struct Buf {
   size_t off = 0, bytes = 0;
@@ -98,6 +100,7 @@ struct swr_handle_s {
   int k = 0;        // Schwarz iterations done in this window
   double t0 = 0.0;
   int depth = 1;    // iterates swr_run keeps in flight (TDSE)
+  int n_nodes_t = 8;  // time nodes M of the learned warm start
   int nbt = 1;      // largest tangential basis size (factored transmission)
   int64_t te_pieces = 0;  // largest LDS bytes of the pieces one item sends
   int te_max_recv = 0;    // largest number of entries one item receives
@@ -341,7 +344,7 @@ void plan_layout(swr_handle h) {
   h->bIePart = L.add((size_t)(h->n_T + 1) * NI * 8);
   h->bNus = L.add((h->n_T + 1) * 8);
   h->bFlags = L.add(8);
-  h->bLag = L.add((h->n_T + 1) * kNodesT * 8);
+  h->bLag = L.add((h->n_T + 1) * h->n_nodes_t * 8);
   h->bLMax = L.add(8);
 }
 
@@ -448,6 +451,7 @@ int32_t swr_create(const swr_desc* desc, swr_handle* out) {
   h->sum_K = g.off1[g.n_items];
   h->sum_K2 = g.off2[g.n_items];
   h->n_T = g.desc.n_steps;
+  h->n_nodes_t = g.desc.learned_nodes > 0 ? g.desc.learned_nodes : 8;
   h->n_mats = g.desc.mode == SWR_TDSE ? g.desc.n_steps : 1;
   h->n_res_tiles = (int)((h->n_T + 1 + 15) / 16);
   h->s1off.assign((size_t)g.n_items * 4, 0);
@@ -555,6 +559,7 @@ int32_t swr_query(swr_handle h, swr_info* info) {
   r.n_face_nodes = (int64_t)h->g.nodes.size();
   r.n_pairs = (int64_t)h->g.pair_i.size();
   r.depth = h->depth;
+  r.learned_nodes = h->n_nodes_t;
   r.sum_KK_pairs = h->g.pair_toff.back();
   r.n_steps = (int32_t)h->n_T;
   r.workspace_bytes = h->lay.total;
@@ -624,29 +629,30 @@ int32_t swr_assemble(swr_handle h, void* stream) {
   HIPCHECK(h, upload(h, h->bNCount, ncount, st));
   HIPCHECK(h, upload(h, h->bNCover, ncover, st));
   // barycentric Lagrange rows of the learned warm start's time nodes
-  if (distinct_time_nodes((int)h->n_T)) {
-    const std::vector<int> tn = time_nodes((int)h->n_T);
-    std::vector<double> ts(kNodesT), wb(kNodesT);
-    for (int m = 0; m < kNodesT; ++m) ts[m] = tn[m] * g.desc.dt;
-    for (int m = 0; m < kNodesT; ++m) {
+  const int M = h->n_nodes_t;
+  if (distinct_time_nodes((int)h->n_T, M)) {
+    const std::vector<int> tn = time_nodes((int)h->n_T, M);
+    std::vector<double> ts(M), wb(M);
+    for (int m = 0; m < M; ++m) ts[m] = tn[m] * g.desc.dt;
+    for (int m = 0; m < M; ++m) {
       double p = 1.0;
-      for (int k2 = 0; k2 < kNodesT; ++k2)
+      for (int k2 = 0; k2 < M; ++k2)
         if (k2 != m) p *= ts[m] - ts[k2];
       wb[m] = 1.0 / p;
     }
-    h->lag_host.assign((size_t)(h->n_T + 1) * kNodesT, 0.0);
+    h->lag_host.assign((size_t)(h->n_T + 1) * M, 0.0);
     for (int64_t n = 0; n <= h->n_T; ++n) {
       const double tt = n * g.desc.dt;
-      double* row = &h->lag_host[(size_t)n * kNodesT];
+      double* row = &h->lag_host[(size_t)n * M];
       int hit = -1;
-      for (int m = 0; m < kNodesT; ++m)
+      for (int m = 0; m < M; ++m)
         if (tt - ts[m] == 0.0) hit = m;
       if (hit >= 0) {
         row[hit] = 1.0;
       } else {
         double sum = 0.0;
-        for (int m = 0; m < kNodesT; ++m) sum += (row[m] = wb[m] / (tt - ts[m]));
-        for (int m = 0; m < kNodesT; ++m) row[m] /= sum;
+        for (int m = 0; m < M; ++m) sum += (row[m] = wb[m] / (tt - ts[m]));
+        for (int m = 0; m < M; ++m) row[m] /= sum;
       }
     }
     HIPCHECK(h, upload(h, h->bLag, h->lag_host, st));
@@ -1209,16 +1215,16 @@ int32_t swr_advance_window(swr_handle h, void* stream) {
 
 int32_t swr_time_nodes(swr_handle h, int32_t* steps_host) {
   if (!h || !steps_host) return fail(h, SWR_E_ARG, "null argument");
-  if (!distinct_time_nodes((int)h->n_T)) return fail(h, SWR_E_ARG, kShortWindow);
-  const std::vector<int> tn = time_nodes((int)h->n_T);
-  for (int m = 0; m < kNodesT; ++m) steps_host[m] = tn[m];
+  if (!distinct_time_nodes((int)h->n_T, h->n_nodes_t)) return fail(h, SWR_E_ARG, kShortWindow);
+  const std::vector<int> tn = time_nodes((int)h->n_T, h->n_nodes_t);
+  for (int m = 0; m < h->n_nodes_t; ++m) steps_host[m] = tn[m];
   return SWR_OK;
 }
 
 int32_t swr_face_data(swr_handle h, int32_t n_sel, const int32_t* steps_host, void* g_dev,
                       void* stream) {
   if (!h || !steps_host || !g_dev) return fail(h, SWR_E_ARG, "null argument");
-  if (n_sel < 1 || n_sel > 16) return fail(h, SWR_E_ARG, "n_sel must be in 1..16");
+  if (n_sel < 1 || n_sel > 64) return fail(h, SWR_E_ARG, "n_sel must be in 1..64");
   if (!h->initial) return fail(h, SWR_E_STATE, "no coefficients yet");
   swr::StepList sl{};
   sl.n = n_sel;
@@ -1243,12 +1249,13 @@ int32_t swr_learned_features(swr_handle h, const void* g0_dev, double t0, int32_
                              float* x_dev, double* scale_dev, void* stream) {
   if (!h || !g0_dev || !x_dev || !scale_dev) return fail(h, SWR_E_ARG, "null argument");
   if (!h->assembled) return fail(h, SWR_E_STATE, "swr_assemble first");
-  if (!distinct_time_nodes((int)h->n_T)) return fail(h, SWR_E_ARG, kShortWindow);
-  if (n_in < 2 * max_item_nodes(h) + 16) return fail(h, SWR_E_SIZE, "n_in too small");
+  if (!distinct_time_nodes((int)h->n_T, h->n_nodes_t)) return fail(h, SWR_E_ARG, kShortWindow);
+  const int M = h->n_nodes_t;
+  if (n_in < 2 * max_item_nodes(h) + M + 8) return fail(h, SWR_E_SIZE, "n_in too small");
   swr::FieldFeat ff{};
-  ff.n = kNodesT;
-  const std::vector<int> tn = time_nodes((int)h->n_T);
-  for (int m = 0; m < kNodesT; ++m) ff.v[m] = kFieldScale * field(h->g.desc, t0 + tn[m] * h->g.desc.dt);
+  ff.n = M;
+  const std::vector<int> tn = time_nodes((int)h->n_T, M);
+  for (int m = 0; m < M; ++m) ff.v[m] = kFieldScale * field(h->g.desc, t0 + tn[m] * h->g.desc.dt);
   for (int k = 0; k < 4; ++k) {
     ff.mid[k] = 0.5 * (h->g.desc.box_lo[k] + h->g.desc.box_hi[k]);
     ff.half[k] = k < h->g.D ? 0.5 * (h->g.desc.box_hi[k] - h->g.desc.box_lo[k]) : 1.0;
@@ -1264,10 +1271,10 @@ int32_t swr_learned_targets(swr_handle h, const void* g_nodes_dev, const double*
                             int32_t n_out, float* y_dev, void* stream) {
   if (!h || !g_nodes_dev || !scale_dev || !y_dev) return fail(h, SWR_E_ARG, "null argument");
   if (!h->assembled) return fail(h, SWR_E_STATE, "swr_assemble first");
-  if (!distinct_time_nodes((int)h->n_T)) return fail(h, SWR_E_ARG, kShortWindow);
-  if (n_out < 2 * kNodesT * max_item_nodes(h)) return fail(h, SWR_E_SIZE, "n_out too small");
+  if (!distinct_time_nodes((int)h->n_T, h->n_nodes_t)) return fail(h, SWR_E_ARG, kShortWindow);
+  if (n_out < 2 * h->n_nodes_t * max_item_nodes(h)) return fail(h, SWR_E_SIZE, "n_out too small");
   HIPCHECK(h, swr::launch_learned_targets(h->items(), h->nodes(), (const double2*)g_nodes_dev,
-                                          kNodesT, scale_dev, n_out, y_dev, (hipStream_t)stream));
+                                          h->n_nodes_t, scale_dev, n_out, y_dev, (hipStream_t)stream));
   return SWR_OK;
 }
 
@@ -1275,10 +1282,10 @@ int32_t swr_learned_apply(swr_handle h, const float* y_dev, const double* scale_
                           const void* g0_dev, int32_t n_out, void* g_all_dev, void* stream) {
   if (!h || !y_dev || !scale_dev || !g0_dev || !g_all_dev) return fail(h, SWR_E_ARG, "null argument");
   if (!h->assembled) return fail(h, SWR_E_STATE, "swr_assemble first");
-  if (!distinct_time_nodes((int)h->n_T)) return fail(h, SWR_E_ARG, kShortWindow);
-  if (n_out < 2 * kNodesT * max_item_nodes(h)) return fail(h, SWR_E_SIZE, "n_out too small");
+  if (!distinct_time_nodes((int)h->n_T, h->n_nodes_t)) return fail(h, SWR_E_ARG, kShortWindow);
+  if (n_out < 2 * h->n_nodes_t * max_item_nodes(h)) return fail(h, SWR_E_SIZE, "n_out too small");
   HIPCHECK(h, swr::launch_learned_apply(h->items(), h->nodes(), y_dev, scale_dev,
-                                        (const double2*)g0_dev, h->ptr<double>(h->bLag), kNodesT,
+                                        (const double2*)g0_dev, h->ptr<double>(h->bLag), h->n_nodes_t,
                                         n_out, (int)h->n_T, (double2*)g_all_dev,
                                         (hipStream_t)stream));
   return SWR_OK;

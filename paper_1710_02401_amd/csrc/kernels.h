@@ -110,14 +110,14 @@ struct RecJobs {
   int n_lo[kMaxJobs], n_cnt[kMaxJobs];
 };
 
-struct StepList {   // up to 16 selected time steps, passed by value
+struct StepList {   // up to 64 selected time steps, passed by value
   int n;
-  int step[16];
+  int step[64];
 };
 
 struct FieldFeat {  // tail features of the learned warm start, by value
-  int n;              // time nodes (field values in v)
-  double v[16];       // 10 E(t0 + t_m)
+  int n;              // time nodes M (field values in v)
+  double v[64];       // 10 E(t0 + t_m)
   double mid[4];      // centre of the global box per dimension
   double half[4];     // half width of the global box per dimension
   double t0w;         // t0 / (8 T), T the window length

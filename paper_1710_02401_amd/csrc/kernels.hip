@@ -1752,7 +1752,7 @@ __global__ void k_learned_max(int n_items, const double* rms, double* wmax) {
 }
 
 // Network input per item: (Re, Im) of g0 / S at the item's nodes, zero
-// padding, then 16 tail entries: field features, the item's box centre in
+// padding, then M + 8 tail entries: field features, the item's box centre in
 // global box coordinates, RMS_i / S, the window's start time, zeros.
 // scale[s] holds RMS_i on entry
 // and S on exit.
@@ -1765,23 +1765,23 @@ __global__ void k_learned_features(Items it, Nodes nd, const double2* g0, FieldF
   const double rms = scale[s];
   __syncthreads();  // every lane has read scale[s] before lane 0 overwrites it
   float* xs = x + (int64_t)s * n_in;
-  const int tail = n_in - 16;
+  const int tail = n_in - (ff.n + 8);
   for (int e = threadIdx.x; e < tail; e += blockDim.x) {
     const int q = e >> 1;
     float v = 0.0f;
     if (q < n) v = (float)(((e & 1) ? g0[a + q].y : g0[a + q].x) / S);
     xs[e] = v;
   }
-  for (int m = threadIdx.x; m < 16; m += blockDim.x) {
+  for (int m = threadIdx.x; m < ff.n + 8; m += blockDim.x) {
     double v = 0.0;
-    if (m < ff.n) {
+    const int m2 = m - ff.n;
+    if (m2 < 0) {
       v = ff.v[m];
-    } else if (m >= 8 && m < 12) {
-      const int k = m - 8;
-      if (k < it.D) v = (0.5 * (it.lo[4 * s + k] + it.hi[4 * s + k]) - ff.mid[k]) / ff.half[k];
-    } else if (m == 12) {
+    } else if (m2 < 4) {
+      if (m2 < it.D) v = (0.5 * (it.lo[4 * s + m2] + it.hi[4 * s + m2]) - ff.mid[m2]) / ff.half[m2];
+    } else if (m2 == 4) {
       v = rms / S;
-    } else if (m == 13) {
+    } else if (m2 == 5) {
       v = ff.t0w;
     }
     xs[tail + m] = (float)v;

@@ -20,13 +20,13 @@ import numpy as np
 
 from . import swr as S
 
-N_NODES_T = 8
-
-
 def net_sizes(solver):
-    """Input and output widths of the network for a solver's face nodes."""
+    """Input and output widths of the network for a solver's face nodes and
+    M time nodes: (Re, Im) per node plus the M + 8 tail entries in, M
+    corrections per node out."""
     n_max = int(max(solver.n_nodes))
-    return 2 * n_max + 16, N_NODES_T * 2 * n_max
+    M = int(solver.info.learned_nodes)
+    return 2 * n_max + M + 8, M * 2 * n_max
 
 
 def window_length(cfg):
@@ -104,7 +104,7 @@ def full_loss(net, X, Y):
 def evaluate(s, net, cfg, n_traj, n_win, seed, k_max, tol, log=None):
     """Iterations to the residual target for the plain, learned and zero
     guesses on the same windows, for the guess built from the converged
-    answer's own targets (the ceiling of the eight-node representation),
+    answer's own targets (the ceiling of the M-node representation),
     and the distance between the learned and plain answers."""
     import torch
     rng = np.random.default_rng(seed)

@@ -40,7 +40,7 @@ class swr_desc(ctypes.Structure):
         ("axis", ctypes.c_int32), ("init_alpha", ctypes.c_double),
         ("init_center", ctypes.c_double * 4),
         ("face_nodes_band", ctypes.c_int32), ("face_nodes_mid", ctypes.c_int32),
-        ("quad_nodes", ctypes.c_int32),
+        ("quad_nodes", ctypes.c_int32), ("learned_nodes", ctypes.c_int32),
     ]
 
 
@@ -51,6 +51,7 @@ class swr_info(ctypes.Structure):
         ("n_face_nodes", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
         ("sum_KK_pairs", ctypes.c_int64), ("n_steps", ctypes.c_int32),
         ("depth", ctypes.c_int32), ("workspace_bytes", ctypes.c_uint64),
+        ("learned_nodes", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -200,6 +201,7 @@ def desc_from_config(cfg):
         d.init_center[k] = float(cfg["init"]["center"][k])
     d.face_nodes_band, d.face_nodes_mid = int(cfg["face_nodes"][0]), int(cfg["face_nodes"][1])
     d.quad_nodes = int(cfg["quad_nodes"])
+    d.learned_nodes = int(cfg.get("learned_nodes", 0))
     return d, (arr, pos, chg)
 
 
@@ -380,7 +382,7 @@ class Solver:
         self._call("swr_advance_window", self._stream())
 
     def time_nodes(self):
-        out = np.zeros(8, dtype=np.int32)
+        out = np.zeros(int(self.info.learned_nodes), dtype=np.int32)
         self._call("swr_time_nodes", out.ctypes.data_as(_c_i32p))
         return [int(v) for v in out]
 

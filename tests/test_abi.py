@@ -46,6 +46,8 @@ def _create(S, cfg):
     (dict(nbasis=[80]), -2),
     (dict(mode="tise", mu=[0.0, -1.0]), -1),
     (dict(field=dict(E0=0.1, omega=1.0, phase=0.0, axis=3)), -1),
+    (dict(learned_nodes=1), -1),
+    (dict(learned_nodes=65), -1),
 ])
 def test_invalid_descriptions_rejected(S, mutate, code):
     cfg = workloads.tiny_configs()[0]
@@ -123,19 +125,30 @@ def test_index_maps_and_boxes_bit_exact(S, name):
     lib.swr_destroy(h)
 
 
-def test_time_nodes_match_oracle_and_short_windows_are_rejected(S):
+@pytest.mark.parametrize("M,cases", [
+    (0, [(8, False), (10, False), (11, True), (200, True), (1000, True)]),
+    (16, [(45, False), (46, True), (200, True)]),
+    (32, [(190, False), (195, True), (1000, True)]),
+    (64, [(1000, True)]),
+])
+def test_time_nodes_match_oracle_and_short_windows_are_rejected(S, M, cases):
     from oracle import learned as o_learned
     lib = S.load_library()
-    out = np.zeros(8, dtype=np.int32)
-    for n_steps, ok in [(8, False), (10, False), (11, True), (200, True), (1000, True)]:
-        cfg = dict(workloads.tiny_configs()[1], n_steps=n_steps)
+    for n_steps, ok in cases:
+        cfg = dict(workloads.tiny_configs()[1], n_steps=n_steps, learned_nodes=M)
         rc, h = _create(S, cfg)
         assert rc == 0
+        info = S.swr_info()
+        assert lib.swr_query(h, ctypes.byref(info)) == 0
+        assert info.learned_nodes == (M or 8)
+        out = np.zeros(info.learned_nodes, dtype=np.int32)
         rc = lib.swr_time_nodes(h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
         if ok:
-            assert rc == 0 and list(out) == o_learned.time_nodes(n_steps)
+            assert rc == 0 and list(out) == o_learned.time_nodes(n_steps, M or 8)
         else:
-            assert rc == -1 and b"n_steps >= 11" in lib.swr_last_error(h)
+            assert rc == -1 and b"not distinct" in lib.swr_last_error(h)
+            with pytest.raises(ValueError):
+                o_learned.time_nodes(n_steps, M or 8)
         lib.swr_destroy(h)
 
 

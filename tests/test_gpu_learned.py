@@ -76,10 +76,11 @@ def test_adam_matches_oracle():
         assert np.max(np.abs(got - p)) <= 1e-6 * np.max(np.abs(p))
 
 
-def _tiny():
+def _tiny(n_steps=24, M=0):
     import torch
     from paper_1710_02401_amd import Solver
-    cfg = dict(TINY["tiny-2d"], n_steps=24)     # eight distinct time nodes need >= 11 steps
+    # distinct time nodes need >= 11 steps for M = 8, >= 46 for M = 16
+    cfg = dict(TINY["tiny-2d"], n_steps=n_steps, learned_nodes=M)
     print(f"[gpu] solver {cfg['name']}", flush=True)
     s = Solver(cfg)
     s.assemble()
@@ -105,11 +106,12 @@ def test_face_data_after_two_iterations():
     assert np.max(np.abs(got - ref)) <= 1e-9 * np.max(np.abs(ref))
 
 
-def test_features_targets_and_interpolated_guess():
+@pytest.mark.parametrize("n_steps,M", [(24, 0), (60, 16)])
+def test_features_targets_and_interpolated_guess(n_steps, M):
     import torch
-    cfg, s, prob = _tiny()
+    cfg, s, prob = _tiny(n_steps, M)
     c0 = prob.initial_coeffs()
-    nodes = o_learned.time_nodes(prob.n_T)
+    nodes = o_learned.time_nodes(prob.n_T, M or 8)
     assert s.time_nodes() == nodes
     # interface data of the oracle's iterate 2 at step 0 and at the time nodes
     hists, _ = o_swr.swr_window(prob, c0, iters=2)
@@ -117,7 +119,8 @@ def test_features_targets_and_interpolated_guess():
     g_steps = [np.concatenate(gf, axis=1) for gf in g_items]         # per item (n_T+1, n_i)
     g0_items = [g[0] for g in g_steps]
     n_max = max(g.shape[1] for g in g_steps)
-    n_in, n_out = 2 * n_max + 16 + 3, 16 * n_max + 5                  # padded widths
+    M = len(nodes)
+    n_in, n_out = 2 * n_max + M + 8 + 3, 2 * M * n_max + 5           # padded widths
     t0 = 0.37
     E = o_swr.field(cfg, t0 + np.array(nodes) * cfg["dt"])
     X_ref, sc_ref = o_learned.features(g0_items, E, n_in, o_learned.item_positions(prob),
@@ -137,7 +140,7 @@ def test_features_targets_and_interpolated_guess():
     out = _np(s.learned_apply(torch.from_numpy(yp).cuda(), sc, g0_dev, n_out))
     out = out.reshape(prob.n_T + 1, -1)
     ref = np.concatenate(o_learned.apply(yp.astype(np.float64), sc_ref, g0_items, prob.n_T,
-                                         cfg["dt"]), axis=1)
+                                         cfg["dt"], M=len(nodes)), axis=1)
     assert np.max(np.abs(out - ref)) <= 1e-9 * np.max(np.abs(ref))
 
 
@@ -152,9 +155,10 @@ def test_given_guess_from_apply_runs_and_matches_plain_answer():
     n_max = int(max(s.n_nodes))
     g0 = s.face_data([0])[0].clone()
     s.set_initial(c0)
-    x, sc = s.learned_features(s.face_data([0])[0].clone(), 0.0, 2 * n_max + 16)
-    yp = torch.zeros((len(s.K), 16 * n_max), dtype=torch.float32, device="cuda")
-    g_all = s.learned_apply(yp, sc, g0, 16 * n_max)
+    M = len(s.time_nodes())
+    x, sc = s.learned_features(s.face_data([0])[0].clone(), 0.0, 2 * n_max + M + 8)
+    yp = torch.zeros((len(s.K), 2 * M * n_max), dtype=torch.float32, device="cuda")
+    g_all = s.learned_apply(yp, sc, g0, 2 * M * n_max)
     st2 = s.run(k_max=40, tol=1e-12, warm=2, g=g_all)
     assert st["converged"] and st2["converged"]
     d = torch.linalg.norm(s.history() - h_plain) / torch.linalg.norm(h_plain)

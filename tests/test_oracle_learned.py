@@ -12,6 +12,22 @@ def test_time_nodes_span_the_window():
     assert learned.time_nodes(11)[1] == 1
     with pytest.raises(ValueError):
         learned.time_nodes(10)
+    n32 = learned.time_nodes(1000, 32)
+    assert len(n32) == 32 and n32[0] == 0 and n32[-1] == 1000
+    with pytest.raises(ValueError):
+        learned.time_nodes(190, 32)
+
+
+def test_interpolation_with_32_nodes_reproduces_degree_31_polynomials():
+    n_T, dt = 1000, 0.005
+    ts = np.array(learned.time_nodes(n_T, 32)) * dt
+    w = learned.bary_weights(ts)
+    coef = np.random.default_rng(3).normal(size=32) / np.arange(1, 33) ** 2
+    x = lambda t: (t - 2.5) / 2.5                      # Chebyshev-friendly variable
+    poly = lambda t: np.polynomial.chebyshev.chebval(x(t), coef)
+    for k in (0, 1, 17, 333, 500, 999, 1000):
+        row = learned.lagrange_row(k * dt, ts, w)
+        assert row @ poly(ts) == pytest.approx(poly(k * dt), rel=1e-9, abs=1e-11)
 
 
 def test_interpolation_reproduces_degree_seven_polynomials():
@@ -33,7 +49,7 @@ def test_apply_of_targets_recovers_node_values():
     nodes = learned.time_nodes(n_T)
     gn = [np.vstack([g0[0]] + [rng.normal(size=5) + 1j * rng.normal(size=5) for _ in range(7)]),
           np.zeros((8, 3), dtype=complex)]
-    X, s = learned.features(g0, np.ones(8) * 0.05, 2 * 5 + 16, np.zeros((2, 4)))
+    X, s = learned.features(g0, np.ones(8) * 0.05, 2 * 5 + learned.tail_len(), np.zeros((2, 4)))
     assert np.all(s == learned.item_rms(g0[0])) and np.allclose(X[0, -16:-8], 0.5)
     assert X[0, -4] == 1.0 and X[1, -4] == 0.0 and not X[1, :-16].any()
     Y = learned.targets(gn, s, 8 * 2 * 5)

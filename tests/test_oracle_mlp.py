@@ -48,4 +48,4 @@ def test_adam_first_step_is_signed_learning_rate():
 
 def test_network_size_of_warm_start():
     n = mlp.param_count(mlp_init.N_IN, mlp_init.N_HIDDEN, mlp_init.N_LAYERS, mlp_init.N_OUT)
-    assert n == 528 * 256 + 256 + 2 * (256 * 256 + 256) + 256 * 4096 + 4096
+    assert n == 552 * 256 + 256 + 2 * (256 * 256 + 256) + 256 * 16384 + 16384

@@ -55,8 +55,9 @@ _C2_TISE = dict(_C2, name="c2-2e-1d-tise", mode="tise", mu=[10.0, 0.0],
                 dt=0.05, n_steps=400,
                 field=dict(E0=0.0, omega=0.0, phase=0.0, axis=0))
 
-# Learned warm start runs on the two-electron system with several windows.
-_C4 = dict(_C2, name="c4-2e-1d-learned", iters=60, tol=1e-8)
+# Learned warm start runs on the two-electron system with several windows;
+# 32 time nodes (windows of at least 195 steps).
+_C4 = dict(_C2, name="c4-2e-1d-learned", iters=60, tol=1e-8, learned_nodes=32)
 
 _C5 = dict(
     name="c5-2e-2d", mode="tdse", n_elec=2, dim=2,

@@ -7,7 +7,7 @@ vector, layer by layer, weight matrix (out x in, row-major) then bias.
 import numpy as np
 
 # network of the learned warm start of the two-electron workload
-N_IN, N_HIDDEN, N_LAYERS, N_OUT = 528, 256, 3, 4096
+N_IN, N_HIDDEN, N_LAYERS, N_OUT = 552, 256, 3, 16384
 
 
 def initial_params(n_in=N_IN, n_hidden=N_HIDDEN, n_layers=N_LAYERS, n_out=N_OUT, seed=2401):
