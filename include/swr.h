@@ -86,6 +86,7 @@ typedef struct swr_desc {
   int32_t face_nodes_band, face_nodes_mid; /* GL nodes per tangential panel   */
   int32_t quad_nodes;        /* GL nodes per potential quadrature panel       */
   int32_t learned_nodes;     /* time nodes M of the learned warm start, 2..64; 0 = 8 */
+  int32_t factor_mode;       /* SWR_FACTOR_AUTO or SWR_FACTOR_DIRECT (swr_factor) */
 } swr_desc;
 
 typedef struct swr_handle_s* swr_handle;
@@ -101,7 +102,8 @@ typedef struct swr_info {
   int32_t depth;             /* Schwarz iterates swr_run keeps in flight      */
   uint64_t workspace_bytes;
   int32_t learned_nodes;     /* M, time nodes of the learned warm start       */
-  int32_t reserved;
+  int32_t factor_terms;      /* series terms of the last swr_factor minus one;
+                                -1: direct inversion per step (or none yet)  */
 } swr_info;
 
 /* ---- lifetime ------------------------------------------------------------*/
@@ -147,8 +149,21 @@ int32_t swr_warm_start(swr_handle h, int32_t mode, const void* g_dev, void* stre
 
 /* Factor every Crank-Nicolson matrix of the window,
  * M^n = A + i dt/2 (Kin + V + mu/2 B + E(t_n) Q), n = 1..n_steps
- * (independent of the Schwarz iterate), starting at time t0.  TISE: the
- * implicit Euler matrix A + dt (Kin + V + mu/2 B) once per item. */
+ * (independent of the Schwarz iterate), starting at time t0: the library
+ * keeps the inverses (complex symmetric, packed upper 8 x 8 tiles).  TISE:
+ * the implicit Euler matrix A + dt (Kin + V + mu/2 B) once per item.
+ * The matrices differ only in the scalar E(t_n): on each chunk of 128
+ * consecutive steps, M^n = M_a + d_n C with C = i dt/2 Q, M_a the matrix at
+ * the midpoint E_a of the chunk's field range and d_n = E(t_n) - E_a.
+ * SWR_FACTOR_AUTO inverts one M_a per chunk and sums
+ * (M^n)^{-1} = sum_k (-d_n)^k (M_a^{-1} C)^k M_a^{-1}, k = 0..K: when
+ * Im mu <= 0 the Hermitian part of A^{-1/2} M_a A^{-1/2} is at least the
+ * identity, so in the A-norm |d_n M_a^{-1} C| <= rho = dt/2 max|d_n| X with
+ * X = max over items of sum_m max |x_m| along the field axis on the item's
+ * box, and the tail after K is at most rho^{K+1}/(1-rho); K is the least
+ * with that bound <= 2^-53 (reported in swr_info.factor_terms).  With
+ * Im mu > 0, K > 7, or SWR_FACTOR_DIRECT, every M^n is inverted. */
+enum { SWR_FACTOR_AUTO = 0, SWR_FACTOR_DIRECT = 1 };
 int32_t swr_factor(swr_handle h, double t0, void* stream);
 
 /* One Schwarz iteration of local solves for every item (Section 4.4 step 2):

@@ -39,9 +39,14 @@ bool distinct_time_nodes(int n_T, int M) {
   return true;
 }
 
-constexpr int kMaxSlots = 6;    // depth <= 4, the previous iterate, one for the residual lag
+constexpr int kMaxDepth = 8;    // iterates in flight at most (one job each per launch)
+constexpr int kMaxSlots = kMaxDepth + 2;  // + the previous iterate, + one for the residual lag
+static_assert(kMaxDepth <= swr::kMaxJobs, "one job per iterate in flight");
 constexpr int kResEvents = 8;   // residual read-backs in flight
-constexpr int kGpuCUs = 256;    // MI355X compute units (one recurrence block each)
+constexpr int kGpuCUs = 256;    // MI355X compute units
+constexpr int kRecPerCU = 2;    // recurrence blocks per compute unit the depth aims at
+// series inverses of the window (swr_factor): at most this many terms
+constexpr int kSeriesMaxTerms = 8;
 
 const char* const kShortWindow =
     "the learned warm start's time nodes are not distinct: the window has too few steps";
@@ -91,7 +96,11 @@ struct swr_handle_s {
   std::vector<int64_t> te_gram_off;  // per-item face Gram pieces (doubles, even)
   std::vector<int64_t> te_fnode;     // [n_items][8][2] first node and count per face
   std::vector<int64_t> te_blob_off;  // per-sender blob offsets (complex units)
-  Buf bT, bC0, bH[kMaxSlots], bF[kMaxSlots], bMinv, bE, bResPart, bResOut, bResv, bIePart, bNus,
+  // TDSE series inverses, per chunk of kSeriesChunk steps: G then P_0 ..
+  // P_{kSeriesMaxTerms-1}, each sum_K2 complex; the chunks' anchor fields
+  Buf bSeries, bEanchor;
+  std::vector<double> Ea_host;
+  Buf bT, bC0, bH[kMaxSlots], bF[kMaxSlots], bRc[kMaxSlots], bMinv, bE, bResPart, bResOut, bResv, bIePart, bNus,
       bFlags;
 
   // state
@@ -101,6 +110,8 @@ struct swr_handle_s {
   double t0 = 0.0;
   int depth = 1;    // iterates swr_run keeps in flight (TDSE)
   int n_nodes_t = 8;  // time nodes M of the learned warm start
+  double dipole_max = 0.0;  // max over items of sum_m max |x_m| along the field axis
+  int factor_terms = -1;    // series terms - 1 of the last swr_factor; -1: direct
   int nbt = 1;      // largest tangential basis size (factored transmission)
   int64_t te_pieces = 0;  // largest LDS bytes of the pieces one item sends
   int te_max_recv = 0;    // largest number of entries one item receives
@@ -184,6 +195,8 @@ struct swr_handle_s {
   double2* hist(int which) const { return ptr<double2>(bH[which]); }
   double2* hist_of(int k) const { return ptr<double2>(bH[k % n_slots]); }
   double2* F_of(int k) const { return ptr<double2>(bF[k % n_slots]); }
+  // right-hand side a chunk of iterate k leaves for the next chunk
+  double2* carry_of(int k) const { return ptr<double2>(bRc[k % n_slots]); }
   double* parts_of(int k) const {
     return ptr<double>(bParts) + (size_t)(k % n_slots) * g.n_items * part_stride;
   }
@@ -334,9 +347,15 @@ void plan_layout(swr_handle h) {
   for (int q = 0; q < h->n_slots; ++q) {
     h->bH[q] = L.add(hist);
     h->bF[q] = L.add(hist);
+    h->bRc[q] = L.add(h->sum_K * 16);
   }
   h->bOffP = L.add((NI + 1) * 8);
   h->bMinv = L.add((size_t)h->n_mats * std::max<int64_t>(h->sum_K2, h->offp.back()) * 16);
+  if (g.desc.mode == SWR_TDSE) {
+    const int n_chunks = (int)((h->n_mats + swr::kSeriesChunk - 1) / swr::kSeriesChunk);
+    h->bSeries = L.add((size_t)n_chunks * (kSeriesMaxTerms + 1) * h->sum_K2 * 16);
+    h->bEanchor = L.add((size_t)n_chunks * 8);
+  }
   h->bE = L.add((h->n_T + 1) * 8);
   h->bResPart = L.add((size_t)h->n_res_tiles * NI * 8);
   h->bResOut = L.add(8);
@@ -453,6 +472,14 @@ int32_t swr_create(const swr_desc* desc, swr_handle* out) {
   h->n_T = g.desc.n_steps;
   h->n_nodes_t = g.desc.learned_nodes > 0 ? g.desc.learned_nodes : 8;
   h->n_mats = g.desc.mode == SWR_TDSE ? g.desc.n_steps : 1;
+  for (int s = 0; s < g.n_items; ++s) {
+    double x = 0.0;
+    for (int el = 0; el < g.desc.n_elec; ++el) {
+      const int k = el * g.desc.dim + g.desc.axis;
+      x += std::max(std::fabs(g.lo[(size_t)s * 4 + k]), std::fabs(g.hi[(size_t)s * 4 + k]));
+    }
+    h->dipole_max = std::max(h->dipole_max, x);
+  }
   h->n_res_tiles = (int)((h->n_T + 1 + 15) / 16);
   h->s1off.assign((size_t)g.n_items * 4, 0);
   h->scratch_off.assign(g.n_items, 0);
@@ -472,8 +499,8 @@ int32_t swr_create(const swr_desc* desc, swr_handle* out) {
   h->s1_total = s1;
   h->scratch_total = scr;
   if (g.desc.mode == SWR_TDSE) {
-    const int fill = (kGpuCUs + g.n_items - 1) / g.n_items;
-    h->depth = std::max(1, std::min({4, fill, (int)h->n_T}));
+    const int fill = (kRecPerCU * kGpuCUs + g.n_items - 1) / g.n_items;
+    h->depth = std::max(1, std::min({kMaxDepth, fill, (int)h->n_T}));
   }
   // pipelined: depth iterates in flight, the one they read, and the one
   // before it (the residual of iterate k-1 reads iterate k-2)
@@ -560,6 +587,7 @@ int32_t swr_query(swr_handle h, swr_info* info) {
   r.n_pairs = (int64_t)h->g.pair_i.size();
   r.depth = h->depth;
   r.learned_nodes = h->n_nodes_t;
+  r.factor_terms = h->factor_terms;
   r.sum_KK_pairs = h->g.pair_toff.back();
   r.n_steps = (int32_t)h->n_T;
   r.workspace_bytes = h->lay.total;
@@ -799,13 +827,68 @@ int32_t swr_factor(swr_handle h, double t0, void* stream) {
   for (int64_t n = 0; n <= h->n_T; ++n) h->E_host[n] = field(h->g.desc, t0 + n * h->g.desc.dt);
   HIPCHECK(h, upload(h, h->bE, h->E_host, st));
   const int tise = h->g.desc.mode == SWR_TISE;
+  const double tau = 0.5 * h->g.desc.dt;
+  // series around the midpoint of each chunk's field range (TDSE)
+  int terms = 0;
+  const int n_chunks = (int)((h->n_mats + swr::kSeriesChunk - 1) / swr::kSeriesChunk);
+  if (!tise && h->g.desc.factor_mode == SWR_FACTOR_AUTO && h->g.desc.mu_im <= 0.0) {
+    h->Ea_host.assign(n_chunks, 0.0);
+    double half = 0.0;
+    for (int c = 0; c < n_chunks; ++c) {
+      const int64_t n0 = (int64_t)c * swr::kSeriesChunk;
+      const int64_t n1 = std::min<int64_t>(n0 + swr::kSeriesChunk, h->n_mats);
+      double lo = h->E_host[n0 + 1], hi = lo;
+      for (int64_t n = n0; n < n1; ++n) {
+        lo = std::min(lo, h->E_host[n + 1]);
+        hi = std::max(hi, h->E_host[n + 1]);
+      }
+      h->Ea_host[c] = 0.5 * (lo + hi);
+      half = std::max(half, 0.5 * (hi - lo));
+    }
+    const double rho = tau * half * h->dipole_max;
+    if (rho < 0.5) {
+      // least K with rho^{K+1} / (1 - rho) <= 2^-53
+      terms = 1;
+      for (double tail = rho / (1.0 - rho); tail > 0x1p-53 && terms <= kSeriesMaxTerms; ++terms)
+        tail *= rho;
+      if (terms > kSeriesMaxTerms) terms = 0;
+    }
+  }
+  const swr::Items it = h->items();
+  if (terms > 0) HIPCHECK(h, upload(h, h->bEanchor, h->Ea_host, st));
   HIPCHECK(h, tbegin(h, st, kTFactor));
-  HIPCHECK(h, swr::launch_invert(h->items(), h->n_mats, h->ptr<double>(h->bAr),
-                                 h->ptr<double>(h->bHr), h->ptr<double>(h->bQ),
-                                 h->ptr<double>(h->bE), 0.5 * h->g.desc.dt, tise,
-                                 h->ptr<double2>(h->bMinv), h->ptr<int>(h->bFlags), st,
-                                 h->g.K_max));
+  if (terms > 0) {
+    const int64_t cstride = (int64_t)(kSeriesMaxTerms + 1) * h->sum_K2;
+    double2* G = h->ptr<double2>(h->bSeries);
+    double2* P = G + h->sum_K2;  // chunk c: P_k at P + c cstride + k sum_K2
+    HIPCHECK(h, swr::launch_invert(it, n_chunks, h->ptr<double>(h->bAr), h->ptr<double>(h->bHr),
+                                   h->ptr<double>(h->bQ), h->ptr<double>(h->bEanchor), cstride,
+                                   tau, 2, P, h->ptr<int>(h->bFlags), st, h->g.K_max));
+    // one refinement step of each anchor inverse: R = I - M_c P_0 (in the G
+    // slot), P_0 += P_0 R
+    HIPCHECK(h, swr::launch_series_residual(it, n_chunks, h->ptr<double>(h->bAr),
+                                            h->ptr<double>(h->bHr), h->ptr<double>(h->bQ),
+                                            h->ptr<double>(h->bEanchor), tau, P, cstride, G, st));
+    HIPCHECK(h, swr::launch_series_product(it, n_chunks, P, G, nullptr, make_double2(1.0, 0.0), P,
+                                           cstride, P, st));
+    if (terms > 1)
+      HIPCHECK(h, swr::launch_series_product(it, n_chunks, P, nullptr, h->ptr<double>(h->bQ),
+                                             make_double2(0.0, tau), nullptr, cstride, G, st));
+    for (int k = 1; k < terms; ++k)
+      HIPCHECK(h, swr::launch_series_product(it, n_chunks, G, P + (k - 1) * h->sum_K2, nullptr,
+                                             make_double2(1.0, 0.0), nullptr, cstride,
+                                             P + k * h->sum_K2, st));
+    HIPCHECK(h, swr::launch_series_assemble(it, h->n_mats, terms, P, h->sum_K2, cstride,
+                                            h->ptr<double>(h->bE), h->ptr<double>(h->bEanchor),
+                                            h->ptr<double2>(h->bMinv), st));
+  } else {
+    HIPCHECK(h, swr::launch_invert(it, h->n_mats, h->ptr<double>(h->bAr), h->ptr<double>(h->bHr),
+                                   h->ptr<double>(h->bQ), h->ptr<double>(h->bE), 0, tau,
+                                   tise ? 1 : 0, h->ptr<double2>(h->bMinv),
+                                   h->ptr<int>(h->bFlags), st, h->g.K_max));
+  }
   HIPCHECK(h, tend(h, st));
+  h->factor_terms = terms - 1;
   h->factored = true;
   h->t0 = t0;
   return SWR_OK;
@@ -828,10 +911,11 @@ int32_t swr_sweep(swr_handle h, void* stream) {
     jobs.n_lo[0] = 0;
     jobs.n_cnt[0] = nT;
     HIPCHECK(h, tbegin(h, st, kTRecur));
-    HIPCHECK(h, swr::launch_cn_recur(it, nT, h->ptr<double>(h->bAp), h->ptr<double>(h->bHr),
-                                     h->ptr<double>(h->bQ), h->ptr<double>(h->bE),
-                                     0.5 * h->g.desc.dt, h->ptr<double2>(h->bMinv),
-                                     h->ptr<double2>(h->bC0), jobs, h->ptr<int>(h->bFlags), st));
+    HIPCHECK(h, swr::launch_cn_recur(it, nT, h->ptr<double>(h->bAr), h->ptr<double>(h->bAp),
+                                     h->ptr<double>(h->bHr), h->ptr<double>(h->bQ),
+                                     h->ptr<double>(h->bE), 0.5 * h->g.desc.dt,
+                                     h->ptr<double2>(h->bMinv), h->ptr<double2>(h->bC0), jobs,
+                                     h->ptr<int>(h->bFlags), st));
     HIPCHECK(h, tend(h, st));
   } else {
     // step 0 of every item is the (normalised) initial state
@@ -968,6 +1052,7 @@ int32_t run_pipelined(swr_handle h, const swr_run_opts* o, int P, swr_run_stats*
       }
       rec.hist[rec.n] = h->hist_of(k);
       rec.F[rec.n] = h->F_of(k);
+      rec.carry[rec.n] = h->carry_of(k);
       rec.n_lo[rec.n] = lo;
       rec.n_cnt[rec.n] = cnt;
       ++rec.n;
@@ -999,10 +1084,11 @@ int32_t run_pipelined(swr_handle h, const swr_run_opts* o, int P, swr_run_stats*
       if (rc) return rc;
     }
     HIPCHECK(h, tbegin(h, st, kTRecur));
-    HIPCHECK(h, swr::launch_cn_recur(it, nT, h->ptr<double>(h->bAp), h->ptr<double>(h->bHr),
-                                     h->ptr<double>(h->bQ), h->ptr<double>(h->bE),
-                                     0.5 * h->g.desc.dt, h->ptr<double2>(h->bMinv),
-                                     h->ptr<double2>(h->bC0), rec, h->ptr<int>(h->bFlags), st));
+    HIPCHECK(h, swr::launch_cn_recur(it, nT, h->ptr<double>(h->bAr), h->ptr<double>(h->bAp),
+                                     h->ptr<double>(h->bHr), h->ptr<double>(h->bQ),
+                                     h->ptr<double>(h->bE), 0.5 * h->g.desc.dt,
+                                     h->ptr<double2>(h->bMinv), h->ptr<double2>(h->bC0), rec,
+                                     h->ptr<int>(h->bFlags), st));
     HIPCHECK(h, tend(h, st));
     if (res_now) {
       const int rc = read(kr);

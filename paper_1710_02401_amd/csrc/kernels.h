@@ -107,6 +107,11 @@ struct RecJobs {
   int n;
   double2* hist[kMaxJobs];       // history written (reads step n_lo unless n_lo == 0)
   const double2* F[kMaxJobs];    // Robin data vectors of the iterate
+  // Right-hand side of the job's last step, M^{n_end} c^{n_end} ([sum K],
+  // item offsets off1): written at the end, read at the start when n_lo > 0
+  // (the previous chunk of the same iterate wrote it).  Null: not written,
+  // and recomputed from the matrices at the start.
+  double2* carry[kMaxJobs];
   int n_lo[kMaxJobs], n_cnt[kMaxJobs];
 };
 
@@ -147,12 +152,39 @@ hipError_t launch_project(const Items& it, const double* A, double init_alpha,
 hipError_t launch_cn_matrices(int64_t n, const double* A, const double* Kin, const double* V,
                               const double* B, double tau, double mu_re, double mu_im, double* Ar,
                               double* Ap, double* Hr, int tise, double dt, hipStream_t st);
+// mode: 0 every step's M^{n+1}, packed upper tiles (TDSE); 1 the real Ar once
+// per item, whole and transposed at the item's K^2 offset (TISE); 2 the
+// matrix at field Efield[n], n < n_mats, whole and row-major at
+// n * out_stride + the item's K^2 offset.
 hipError_t launch_invert(const Items& it, int n_mats, const double* Ar, const double* Hr,
-                         const double* Q, const double* Efield, double tau, int tise,
-                         double2* Minv, int* flags, hipStream_t st, int K_max);
-hipError_t launch_cn_recur(const Items& it, int n_steps, const double* Ap, const double* Hr,
-                           const double* Q, const double* Efield, double tau, const double2* Minv,
-                           const double2* c0, const RecJobs& jobs, int* flags, hipStream_t st);
+                         const double* Q, const double* Efield, int64_t out_stride, double tau,
+                         int mode, double2* Minv, int* flags, hipStream_t st, int K_max);
+// Series inverses: the steps of chunk c (kSeriesChunk of them) expand around
+// an anchor field of their own.
+constexpr int kSeriesChunk = 128;
+// out = scale * L R + add per item and chunk (K x K row-major at the item's
+// K^2 offset, chunk c at c * cstride); R is Rc (complex, chunk-strided) when
+// not null, else Rr (real, one for every chunk); add may be null; out may be L.
+hipError_t launch_series_product(const Items& it, int n_chunks, const double2* L,
+                                 const double2* Rc, const double* Rr, double2 scale,
+                                 const double2* add, int64_t cstride, double2* out,
+                                 hipStream_t st);
+// R = I - M_c X per item and chunk, M_c = Ar + i tau (Hr + Eanchor[c] Q), with
+// exact products and double-double sums (layout as above).
+hipError_t launch_series_residual(const Items& it, int n_chunks, const double* Ar,
+                                  const double* Hr, const double* Q, const double* Eanchor,
+                                  double tau, const double2* X, int64_t cstride, double2* R,
+                                  hipStream_t st);
+// Packed inverses of every step n < n_mats: sum_{k < terms} (Eanchor[c] -
+// E_{n+1})^k P_k with c = n / kSeriesChunk, P_k = P + c cstride + k stride
+// (1 <= terms <= 8).
+hipError_t launch_series_assemble(const Items& it, int n_mats, int terms, const double2* P,
+                                  int64_t stride, int64_t cstride, const double* Efield,
+                                  const double* Eanchor, double2* Minv, hipStream_t st);
+hipError_t launch_cn_recur(const Items& it, int n_steps, const double* Ar, const double* Ap,
+                           const double* Hr, const double* Q, const double* Efield, double tau,
+                           const double2* Minv, const double2* c0, const RecJobs& jobs, int* flags,
+                           hipStream_t st);
 hipError_t launch_sum_sqrt(const double* partial, int64_t n, double* out, hipStream_t st);
 hipError_t launch_transfer_tensor(const Items& it, const Nodes& nd, const Pairs& pr,
                                   const TEnt& te, double mu_re, double mu_im, double* beta,

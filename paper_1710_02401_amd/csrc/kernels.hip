@@ -518,11 +518,18 @@ __device__ inline v4d mfma16(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Modes: kInvSteps inverts M^{n+1} (field E_{n+1}) for n < n_mats into packed
+// upper tiles; kInvReal inverts the real matrix Ar once per item (TISE) and
+// writes it whole, transposed, at the item's K^2 offset; kInvAt inverts the
+// matrix at field Eall[n] for n < n_mats and writes it whole, row-major, at
+// n * out_stride + the item's K^2 offset.
+constexpr int kInvSteps = 0, kInvReal = 1, kInvAt = 2;
 template <int NB>
 __global__ void __launch_bounds__(64 * NB) k_invert_mfma(Items it, int n_mats, const double* Ar,
                                                          const double* Hr, const double* Q,
-                                                         const double* Eall, double tau, int tise,
-                                                         double2* Minv, int* flags) {
+                                                         const double* Eall, int64_t out_stride,
+                                                         double tau, int mode, double2* Minv,
+                                                         int* flags) {
   const int n = blockIdx.x;
   const int s = blockIdx.y;
   const int K = it.K[s];
@@ -532,7 +539,8 @@ __global__ void __launch_bounds__(64 * NB) k_invert_mfma(Items it, int n_mats, c
   __shared__ double2 aop[NB][256];     // per wave: a tile row-major, read back as A operand
   __shared__ double2 prow[16], pcol[16];
   const int64_t o2 = it.off2[s];
-  const double E = tise ? 0.0 : Eall[n + 1];
+  const bool tise = mode == kInvReal;
+  const double E = mode == kInvAt ? Eall[n] : (tise ? 0.0 : Eall[n + 1]);
   // the wave's block row; position t holds column block (k + t) mod NB at
   // block step k (rotated after every step), so the pivot block is always
   // position 0 and the step loop need not be unrolled
@@ -683,15 +691,16 @@ __global__ void __launch_bounds__(64 * NB) k_invert_mfma(Items it, int n_mats, c
   }
   if (bad) atomicOr(flags, kFlagPivot);
   bool nonfinite = false;
-  if (tise) {  // one whole inverse per item, transposed
-    double2* out = Minv + o2;
+  if (mode != kInvSteps) {  // whole inverses
+    double2* out = Minv + (int64_t)n * out_stride + o2;
 #pragma unroll
     for (int j = 0; j < NB; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * w + 4 * r + lr, col = 16 * j + lc;
         if (row < K && col < K) {
-          out[(int64_t)col * K + row] = make_double2(re[j][r], im[j][r]);
+          out[tise ? (int64_t)col * K + row : (int64_t)row * K + col] =
+              make_double2(re[j][r], im[j][r]);
           nonfinite |= !(isfinite(re[j][r]) && isfinite(im[j][r]));
         }
       }
@@ -714,17 +723,225 @@ __global__ void __launch_bounds__(64 * NB) k_invert_mfma(Items it, int n_mats, c
 }
 
 // ---------------------------------------------------------------------------
+// Inverses of the window's Crank-Nicolson matrices as series in the field.
+// Chunk c of kSeriesChunk steps has its own anchor field E_c; for its steps
+// M^n = M_c + d_n C with C = i tau Q, d_n = E_n - E_c, so
+//   (M^n)^{-1} = sum_k (-d_n)^k P_k,  P_0 = M_c^{-1},  P_{k+1} = G P_k,
+//   G = M_c^{-1} C = i tau P_0 Q.
+// The P_k are complex symmetric (as M^n is).  Each chunk's matrices sit in a
+// block of `cstride` complex entries: G, then P_0, P_1, ..., each whole and
+// row-major at the item's K^2 offset, `stride` apart.
+
+// out = scale * L R (+ add) for every item and chunk: L complex, R complex
+// (Rc, chunk-strided like L) or real (Rr, shared by the chunks), add complex
+// or null, all K x K row-major at the item's K^2 offset, K <= 64.  On the
+// matrix cores: block (item, chunk) of four waves, wave w forms rows 16 w ..
+// 16 w + 15 as four 16 x 16 tiles, each complex product four real
+// v_mfma_f64_16x16x4f64 per k-chunk; L and R are staged in LDS (rows padded
+// to 65 entries), zero past K.  A block reads only its own L and add, so out
+// may be L (in place).
+constexpr int kSerPad = kSmallK + 1;
+template <bool kRealR>
+__global__ void __launch_bounds__(kBlock) k_series_product(Items it, const double2* L,
+                                                           const double2* Rc, const double* Rr,
+                                                           double2 scale, const double2* add,
+                                                           int64_t cstride, double2* out) {
+  const int s = blockIdx.x;
+  const int K = it.K[s];
+  const int64_t o2 = it.off2[s];
+  const int64_t cz = (int64_t)blockIdx.y * cstride;
+  __shared__ double2 sl[kSmallK * kSerPad];
+  __shared__ double2 sr[kSmallK * kSerPad];
+  for (int e = threadIdx.x; e < kSmallK * kSmallK; e += blockDim.x) {
+    const int r = e >> 6, c = e & 63;
+    const bool in = r < K && c < K;
+    const int64_t g = o2 + (int64_t)r * K + c;
+    sl[r * kSerPad + c] = in ? L[cz + g] : make_double2(0.0, 0.0);
+    sr[r * kSerPad + c] = in ? (kRealR ? make_double2(Rr[g], 0.0) : Rc[cz + g])
+                             : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int lr = l >> 4, lc = l & 15;
+  v4d cr[4], ci[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    cr[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    ci[t] = v4d{0.0, 0.0, 0.0, 0.0};
+  }
+  for (int kk = 0; kk < kSmallK / 4; ++kk) {
+    // A operand: entry (16 w + lc, 4 kk + lr); B operand: (4 kk + lr, 16 t + lc)
+    const double2 a = sl[(16 * w + lc) * kSerPad + 4 * kk + lr];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const double2 b = sr[(4 * kk + lr) * kSerPad + 16 * t + lc];
+      cr[t] = mfma16(a.x, b.x, cr[t]);
+      ci[t] = mfma16(a.y, b.x, ci[t]);
+      if (!kRealR) {
+        cr[t] = mfma16(-a.y, b.y, cr[t]);
+        ci[t] = mfma16(a.x, b.y, ci[t]);
+      }
+    }
+  }
+  // D layout: register r of lane l is entry (4 r + l / 16, l % 16) of the tile
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * w + 4 * r + lr, col = 16 * t + lc;
+      if (row < K && col < K) {
+        const int64_t e = cz + o2 + (int64_t)row * K + col;
+        const double2 v = cmul(scale, make_double2(cr[t][r], ci[t][r]));
+        out[e] = add ? cadd(add[e], v) : v;
+      }
+    }
+}
+
+constexpr int kSerRows = 16;  // rows per block of the residual
+
+// Residual of an anchor inverse, R = I - M_c X for every item and chunk c,
+// M_c = Ar + i tau (Hr + E_c Q) formed entry by entry as the inversion forms
+// it, X the chunk's P_0.  The sums are compensated dot products (Ogita, Rump
+// and Oishi's Dot2: exact products by fma, error-free additions, errors
+// summed aside), as accurate as working in twice the precision, so R is
+// accurate although M_c X agrees with I to ~cond(M) eps; one step X + X R
+// then brings X to the inverse of M_c rounded to working precision.  Layout
+// and blocking as the product above.
+struct Dot2 {
+  double s, c;  // running sum, accumulated rounding errors
+};
+// (no contraction: a product fused into these sums would break the exact
+// error terms)
+__device__ inline void dot2_acc(Dot2& a, double x, double y) {  // a += x y
+#pragma clang fp contract(off)
+  const double p = x * y;
+  const double e = fma(x, y, -p);
+  const double t = a.s + p;
+  const double z = t - a.s;
+  a.c += ((a.s - (t - z)) + (p - z)) + e;
+  a.s = t;
+}
+__global__ void __launch_bounds__(kBlock) k_series_residual(Items it, const double* Ar,
+                                                            const double* Hr, const double* Q,
+                                                            const double* Eanchor, double tau,
+                                                            const double2* X, int64_t cstride,
+                                                            double2* R) {
+  const int s = blockIdx.x;
+  const int K = it.K[s];
+  const int r0 = blockIdx.y * kSerRows;
+  if (r0 >= K) return;  // uniform over the block
+  const int64_t o2 = it.off2[s];
+  const int64_t cz = (int64_t)blockIdx.z * cstride;
+  const double E = Eanchor[blockIdx.z];
+  __shared__ double2 sm[kSerRows * kSmallK];
+  __shared__ double2 sx[kSmallK * kSmallK];
+  const int nr = K - r0 < kSerRows ? K - r0 : kSerRows;
+  for (int e = threadIdx.x; e < nr * K; e += blockDim.x) {
+    const int64_t g = o2 + (int64_t)r0 * K + e;
+    sm[e] = make_double2(Ar[g], tau * (Hr[g] + E * Q[g]));
+  }
+  for (int e = threadIdx.x; e < K * K; e += blockDim.x) sx[e] = X[cz + o2 + e];
+  __syncthreads();
+  const int col = threadIdx.x & 63, rq = 4 * (threadIdx.x >> 6);
+  if (col >= K) return;
+  // four rows at once: eight independent accumulation chains per thread
+  // (rows past nr read row 0 of the block and are not stored)
+  Dot2 re[4], im[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    re[q] = Dot2{r0 + rq + q == col ? 1.0 : 0.0, 0.0};
+    im[q] = Dot2{0.0, 0.0};
+  }
+  for (int m = 0; m < K; ++m) {
+    const double2 b = sx[m * K + col];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double2 a = sm[(rq + q < nr ? rq + q : 0) * K + m];
+      dot2_acc(re[q], -a.x, b.x);
+      dot2_acc(re[q], a.y, b.y);
+      dot2_acc(im[q], -a.x, b.y);
+      dot2_acc(im[q], -a.y, b.x);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (rq + q < nr)
+      R[cz + o2 + (int64_t)(r0 + rq + q) * K + col] =
+          make_double2(re[q].s + re[q].c, im[q].s + im[q].c);
+}
+
+// (M^{n+1})^{-1} = sum_{k < NT} (-d)^k P_k, d = E_{n+1} - E_c, into the packed
+// upper tiles of every step n < n_mats (Horner in d).  Block (item, chunk c
+// of kSeriesChunk steps); thread t keeps the NT coefficients of packed
+// entries t, t + 256, ... in registers while it walks the chunk's steps.
+// Entries outside K (padding of the last tile) hold the identity.
+template <int NT>
+__global__ void __launch_bounds__(kBlock) k_series_assemble(Items it, int n_mats,
+                                                            const double2* P, int64_t stride,
+                                                            int64_t cstride, const double* Eall,
+                                                            const double* Eanchor,
+                                                            double2* Minv) {
+  const int s = blockIdx.x;
+  const int c = blockIdx.y;
+  const int K = it.K[s];
+  const int T8 = (K + 7) >> 3;
+  const int n_ent = 32 * T8 * (T8 + 1);
+  const int n0 = c * kSeriesChunk;
+  const int n1 = n0 + kSeriesChunk < n_mats ? n0 + kSeriesChunk : n_mats;
+  const int64_t o2 = it.off2[s];
+  const double2* Pc = P + (int64_t)c * cstride;
+  const double Ec = Eanchor[c];
+  double2* out = Minv + (int64_t)n_mats * it.offp[s];
+  for (int e = threadIdx.x; e < n_ent; e += blockDim.x) {
+    // tile (I, J), I <= J, of packed index e / 64; entry (a, b) at b 8 + a
+    const int t = e >> 6;
+    int I = 0;
+    while (I + 1 < T8 && tile_index(I + 1, I + 1, T8) <= t) ++I;
+    const int J = I + (t - tile_index(I, I, T8));
+    const int row = 8 * I + (e & 7), col = 8 * J + ((e >> 3) & 7);
+    const bool inside = row < K && col < K;
+    double cx[NT], cy[NT];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+      const double2 v = inside ? Pc[k * stride + o2 + (int64_t)row * K + col]
+                               : make_double2(k == 0 && row == col ? 1.0 : 0.0, 0.0);
+      cx[k] = v.x;
+      cy[k] = v.y;
+    }
+    for (int n = n0; n < n1; ++n) {
+      const double d = Ec - Eall[n + 1];  // -(E_{n+1} - E_c)
+      double vx = cx[NT - 1], vy = cy[NT - 1];
+#pragma unroll
+      for (int k = NT - 2; k >= 0; --k) {
+        vx = fma(d, vx, cx[k]);
+        vy = fma(d, vy, cy[k]);
+      }
+      out[(int64_t)n * n_ent + e] = make_double2(vx, vy);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Crank-Nicolson recurrence (Section 4.4 step 2), one block of 512 threads
 // per (item, job); a job runs the steps n_lo .. n_lo+n_cnt-1 of one Schwarz
-// iterate (the whole window, or one chunk of it).  Thread (r, part) owns row
-// r and the eight columns m = 8 part + j: its entries of the real matrices
-// Ap, Hr, Q stay in registers; the inverse matrix and the Robin data vector
-// f^{n+1} of step n are prefetched at step n - 2 into the register buffer of
-// parity n % 2 (so no loaded register is ever moved before it is used: a
-// move would wait for the load); the sums over the eight parts are DPP
-// butterflies inside groups of eight lanes.
-//   rhs = Ap c^n - i tau (Hr + E_n Q) c^n + (i tau / 2)(f^n + f^{n+1})
-//   c^{n+1} = (M^{n+1})^{-1} rhs
+// iterate (the whole window, or one chunk of it).  With
+// M^n = Ar + i tau (Hr + E_n Q) the matrix that was inverted and Ap the
+// mass part of the explicit half step, the explicit matrix is
+// Ap - i tau (Hr + E_n Q) = (Ar + Ap) - M^n, and M^n c^n is the right-hand
+// side of the previous step.  So every step after the first costs one real
+// product and the inverse:
+//   rhs^n   = (Ar + Ap) c^n - rhs^{n-1} + (i tau / 2)(f^n + f^{n+1})
+//   c^{n+1} = (M^{n+1})^{-1} rhs^n
+// The map rhs^{n-1} -> rhs^n is the Cayley transform of the step, so
+// rounding errors are carried, not amplified.  The first step of a job takes
+// rhs^{n_lo-1} = M^{n_lo} c^{n_lo} from the carry the previous chunk of the
+// iterate left, or forms it from the matrices at the start of the window.
+// Thread (r, part) owns row r and the eight columns m = 8 j + part, one in
+// each column block j: its entries of Ar + Ap stay in registers; the inverse matrix and the Robin
+// data vector f^{n+1} of step n are prefetched PD steps ahead into a
+// register buffer of their own (so no loaded register is ever moved before
+// it is used: a move would wait for the load); the sums over the eight parts
+// are DPP butterflies inside groups of eight lanes.
 constexpr int kRecThreads = 512;
 constexpr int kRecPrefetch = 3;  // steps between a load of the inverse and its use
 // LDS vectors of the recurrence: entry m at (m / 8) * 9 + m % 8, so that the
@@ -733,9 +950,10 @@ constexpr int kVecPad = 9 * (kSmallK / 8);
 __device__ inline int vpos(int m) { return (m >> 3) * 9 + (m & 7); }
 
 struct RecState {
-  double ap[8], hr[8], qq[8];
+  double s2[8];         // Ar + Ap at this thread's columns of row r
   double2 cm[8];        // c^n at this thread's columns
   double2 fprev;        // f^n at row r
+  double2 rprev;        // rhs^{n-1} = M^n c^n at row r
 };
 
 struct RecPipe {
@@ -743,11 +961,12 @@ struct RecPipe {
   double2 f;            // f^{n+1} at row r
 };
 
-// cross-lane moves inside rows of the wave (DPP, no LDS traffic)
+// cross-lane moves inside rows of the wave (DPP, no LDS traffic); every
+// lane's source is inside its row, so the value written is never the old one
 template <int kCtrl>
 __device__ inline double dpp_f64(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), kCtrl, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), kCtrl, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), kCtrl, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), kCtrl, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 
@@ -765,11 +984,12 @@ __device__ inline double group8_sum(double v) {
 // addresses: entries past K multiply the zero padding of the LDS vectors
 // (columns) or are discarded (rows); steps past the job's end are never
 // consumed.
-// The inverse of step n is read from the packed upper tiles: row rr of
-// column block J is row a of tile (I, J) when J >= I (eight entries that
-// neighbouring lanes read side by side), else column a of tile (J, I) (128
-// contiguous bytes per lane).  Row and tile indices are clamped, so padding
-// lanes read valid entries.
+// The inverse of step n is read from the packed upper tiles: entry
+// (8 I + a, 8 j + part) is entry (a, part) of tile (I, j) when j >= I, else
+// entry (part, a) of tile (j, I).  The 64 lanes of a wave share I (its eight
+// rows are one tile row), so each load reads one whole tile: 1 KB
+// contiguous.  Row and tile indices are clamped, so padding lanes read
+// valid entries.
 __device__ inline void prefetch(RecPipe& pp, const double2* Mb, const double2* F, int64_t hb,
                                 int n, int n_end, int K, int r, int part) {
   const int rr = r < K ? r : K - 1;
@@ -777,46 +997,38 @@ __device__ inline void prefetch(RecPipe& pp, const double2* Mb, const double2* F
   pp.f = F[hb + (int64_t)(nn + 1) * K + rr];
   const int T8 = (K + 7) >> 3;
   const int I = rr >> 3, a = rr & 7;
-  const int J = part < T8 ? part : T8 - 1;
   const double2* base = Mb + (int64_t)nn * 32 * T8 * (T8 + 1);
-  if (J >= I) {
-    base += tile_index(I, J, T8) * 64 + a;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) pp.m[j] = base[j * 8];
-  } else {
-    base += tile_index(J, I, T8) * 64 + a * 8;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) pp.m[j] = base[j];
+  for (int j = 0; j < 8; ++j) {
+    const int J = j < T8 ? j : T8 - 1;
+    pp.m[j] = J >= I ? base[tile_index(I, J, T8) * 64 + part * 8 + a]
+                     : base[tile_index(J, I, T8) * 64 + a * 8 + part];
   }
 }
 
 template <int PD>
-__device__ inline void cn_step(RecState& st, RecPipe& pp, int n, int n_lo, int n_end, int K,
-                               int r, int part, double tau, const double* sE, const double2* Mb,
-                               const double2* F, double2* hist, int64_t hb, double2* sc,
-                               double2* srhs, bool& bad) {
-  const double E = sE[n - n_lo];
-  double ax = 0.0, ay = 0.0, hx = 0.0, hy = 0.0;
+__device__ inline void cn_step(RecState& st, RecPipe& pp, int n, int n_end, int K, int r,
+                               int part, double tau, const double2* Mb, const double2* F,
+                               double2* hist, int64_t hb, double2* sc, double2* srhs, bool& bad) {
+  double ax = 0.0, ay = 0.0;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const double h = fma(E, st.qq[j], st.hr[j]);
-    ax = fma(st.ap[j], st.cm[j].x, ax);
-    ay = fma(st.ap[j], st.cm[j].y, ay);
-    hx = fma(h, st.cm[j].x, hx);
-    hy = fma(h, st.cm[j].y, hy);
+    ax = fma(st.s2[j], st.cm[j].x, ax);
+    ay = fma(st.s2[j], st.cm[j].y, ay);
   }
-  double rx = fma(tau, hy, ax), ry = fma(-tau, hx, ay);  // a - i tau h
-  rx = group8_sum(rx);
-  ry = group8_sum(ry);
+  ax = group8_sum(ax);
+  ay = group8_sum(ay);
   const double2 fs = cadd(st.fprev, pp.f);
   st.fprev = pp.f;
-  if (r < K)  // + (i tau / 2)(f^n + f^{n+1})
-    srhs[vpos(r)] = make_double2(fma(-0.5 * tau, fs.y, rx), fma(0.5 * tau, fs.x, ry));
+  const double2 rhs = make_double2(fma(-0.5 * tau, fs.y, ax - st.rprev.x),
+                                   fma(0.5 * tau, fs.x, ay - st.rprev.y));
+  st.rprev = rhs;
+  if (r < K) srhs[vpos(r)] = rhs;
   __syncthreads();
   double ox = 0.0, oy = 0.0;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const double2 rm = srhs[part * 9 + j];  // zero padded past K
+    const double2 rm = srhs[j * 9 + part];  // zero padded past K
     ox = fma(pp.m[j].x, rm.x, fma(-pp.m[j].y, rm.y, ox));
     oy = fma(pp.m[j].x, rm.y, fma(pp.m[j].y, rm.x, oy));
   }
@@ -833,16 +1045,17 @@ __device__ inline void cn_step(RecState& st, RecPipe& pp, int n, int n_lo, int n
   bad |= !cfinite(v);
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < 8; ++j) st.cm[j] = sc[part * 9 + j];  // zero padded past K
+  for (int j = 0; j < 8; ++j) st.cm[j] = sc[j * 9 + part];  // zero padded past K
 }
 
 // PD = prefetch distance in steps (register buffers in flight)
 template <int PD>
-__global__ void __launch_bounds__(kRecThreads) k_cn_recur(Items it, int n_steps, const double* Ap,
-                                                          const double* Hr, const double* Q,
-                                                          const double* Eall, double tau,
-                                                          const double2* Minv, const double2* c0,
-                                                          RecJobs jobs, int* flags) {
+__global__ void __launch_bounds__(kRecThreads) k_cn_recur(Items it, int n_steps, const double* Ar,
+                                                          const double* Ap, const double* Hr,
+                                                          const double* Q, const double* Eall,
+                                                          double tau, const double2* Minv,
+                                                          const double2* c0, RecJobs jobs,
+                                                          int* flags) {
   const int s = blockIdx.x;
   const int job = blockIdx.y;
   const int K = it.K[s];
@@ -850,27 +1063,29 @@ __global__ void __launch_bounds__(kRecThreads) k_cn_recur(Items it, int n_steps,
   const int n_end = n_lo + jobs.n_cnt[job];
   double2* hist = jobs.hist[job];
   const double2* F = jobs.F[job];
+  double2* carry = jobs.carry[job];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int part = lane & 7;
   const int r = wave * 8 + (lane >> 3);
   __shared__ double2 sc[kVecPad];
   __shared__ double2 srhs[kVecPad];
-  extern __shared__ double sE[];  // field at the job's time nodes n_lo .. n_end
-  for (int q = threadIdx.x; q <= n_end - n_lo; q += blockDim.x) sE[q] = Eall[n_lo + q];
   const int64_t o2 = it.off2[s];
   const int64_t hb = (int64_t)(n_steps + 1) * it.off1[s];
+  const int rr = r < K ? r : K - 1;
   RecState st;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const int m = part * 8 + j;
+    const int m = 8 * j + part;
     const bool v = r < K && m < K;
     const int64_t e = o2 + (v ? (int64_t)m * K + r : 0);
     // symmetric matrices: entry (m, r) = entry (r, m)
-    st.ap[j] = v ? Ap[e] : 0.0;
-    st.hr[j] = v ? Hr[e] : 0.0;
-    st.qq[j] = v ? Q[e] : 0.0;
+    st.s2[j] = v ? Ar[e] + Ap[e] : 0.0;
   }
-  st.fprev = F[hb + (int64_t)n_lo * K + (r < K ? r : K - 1)];
+  st.fprev = F[hb + (int64_t)n_lo * K + rr];
+  // The carried right-hand side goes through LDS, so that its load is waited
+  // for here: a load still pending when the loop starts would make the
+  // loop's memory waits drain every prefetch.
+  const bool use_carry = n_lo > 0 && carry != nullptr;
   if (threadIdx.x < K) {
     double2 v;
     if (n_lo == 0) {
@@ -880,6 +1095,7 @@ __global__ void __launch_bounds__(kRecThreads) k_cn_recur(Items it, int n_steps,
       v = hist[hb + (int64_t)n_lo * K + threadIdx.x];
     }
     sc[vpos(threadIdx.x)] = v;
+    if (use_carry) srhs[vpos(threadIdx.x)] = carry[it.off1[s] + threadIdx.x];
   } else if (threadIdx.x < kSmallK) {
     // padding past K stays zero for the whole job
     sc[vpos(threadIdx.x)] = make_double2(0.0, 0.0);
@@ -892,21 +1108,41 @@ __global__ void __launch_bounds__(kRecThreads) k_cn_recur(Items it, int n_steps,
   if (PD == 3) prefetch(pC, Mb, F, hb, n_lo + 2, n_end, K, r, part);
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < 8; ++j) st.cm[j] = sc[part * 9 + j];
+  for (int j = 0; j < 8; ++j) st.cm[j] = sc[j * 9 + part];
+  if (use_carry) {
+    // each wave reads only its own rows, which only it overwrites later
+    st.rprev = r < K ? srhs[vpos(r)] : make_double2(0.0, 0.0);
+  } else {
+    // M^{n_lo} c^{n_lo} = Ar c + i tau (Hr + E Q) c
+    const double E = Eall[n_lo];
+    double ax = 0.0, ay = 0.0, hx = 0.0, hy = 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int m = 8 * j + part;
+      const bool v = r < K && m < K;
+      const int64_t e = o2 + (v ? (int64_t)m * K + r : 0);
+      const double a = v ? Ar[e] : 0.0;
+      const double h = v ? fma(E, Q[e], Hr[e]) : 0.0;
+      ax = fma(a, st.cm[j].x, ax);
+      ay = fma(a, st.cm[j].y, ay);
+      hx = fma(h, st.cm[j].x, hx);
+      hy = fma(h, st.cm[j].y, hy);
+    }
+    st.rprev = make_double2(group8_sum(fma(-tau, hy, ax)), group8_sum(fma(tau, hx, ay)));
+  }
   bool bad = false;
   // unconditional PD-step body (a conditional tail inside the body would make
   // the loop-header wait state assume the first buffer was loaded last)
   int n = n_lo;
   for (; n + PD - 1 < n_end; n += PD) {
-    cn_step<PD>(st, pA, n, n_lo, n_end, K, r, part, tau, sE, Mb, F, hist, hb, sc, srhs, bad);
-    cn_step<PD>(st, pB, n + 1, n_lo, n_end, K, r, part, tau, sE, Mb, F, hist, hb, sc, srhs, bad);
-    if (PD == 3)
-      cn_step<PD>(st, pC, n + 2, n_lo, n_end, K, r, part, tau, sE, Mb, F, hist, hb, sc, srhs, bad);
+    cn_step<PD>(st, pA, n, n_end, K, r, part, tau, Mb, F, hist, hb, sc, srhs, bad);
+    cn_step<PD>(st, pB, n + 1, n_end, K, r, part, tau, Mb, F, hist, hb, sc, srhs, bad);
+    if (PD == 3) cn_step<PD>(st, pC, n + 2, n_end, K, r, part, tau, Mb, F, hist, hb, sc, srhs, bad);
   }
-  if (n < n_end)
-    cn_step<PD>(st, pA, n, n_lo, n_end, K, r, part, tau, sE, Mb, F, hist, hb, sc, srhs, bad);
-  if (n + 1 < n_end)
-    cn_step<PD>(st, pB, n + 1, n_lo, n_end, K, r, part, tau, sE, Mb, F, hist, hb, sc, srhs, bad);
+  if (n < n_end) cn_step<PD>(st, pA, n, n_end, K, r, part, tau, Mb, F, hist, hb, sc, srhs, bad);
+  if (n + 1 < n_end) cn_step<PD>(st, pB, n + 1, n_end, K, r, part, tau, Mb, F, hist, hb, sc, srhs, bad);
+  // rhs of the last step = M^{n_end} c^{n_end}, for the next chunk
+  if (carry && part == 0 && r < K) carry[it.off1[s] + r] = st.rprev;
   if (bad) atomicOr(flags, kFlagNaN);
 }
 
@@ -1890,38 +2126,76 @@ hipError_t launch_cn_matrices(int64_t n, const double* A, const double* Kin, con
 }
 
 hipError_t launch_invert(const Items& it, int n_mats, const double* Ar, const double* Hr,
-                         const double* Q, const double* Eall, double tau, int tise,
-                         double2* Minv, int* flags, hipStream_t st, int K_max) {
+                         const double* Q, const double* Eall, int64_t out_stride, double tau,
+                         int mode, double2* Minv, int* flags, hipStream_t st, int K_max) {
   dim3 grid(n_mats, it.n_items);
   const int NB = (K_max + 15) / 16;
   if (NB <= 1)
-    hipLaunchKernelGGL(k_invert_mfma<1>, grid, dim3(64), 0, st, it, n_mats, Ar, Hr, Q, Eall, tau,
-                       tise, Minv, flags);
+    hipLaunchKernelGGL(k_invert_mfma<1>, grid, dim3(64), 0, st, it, n_mats, Ar, Hr, Q, Eall,
+                       out_stride, tau, mode, Minv, flags);
   else if (NB == 2)
-    hipLaunchKernelGGL(k_invert_mfma<2>, grid, dim3(128), 0, st, it, n_mats, Ar, Hr, Q, Eall, tau,
-                       tise, Minv, flags);
+    hipLaunchKernelGGL(k_invert_mfma<2>, grid, dim3(128), 0, st, it, n_mats, Ar, Hr, Q, Eall,
+                       out_stride, tau, mode, Minv, flags);
   else if (NB == 3)
-    hipLaunchKernelGGL(k_invert_mfma<3>, grid, dim3(192), 0, st, it, n_mats, Ar, Hr, Q, Eall, tau,
-                       tise, Minv, flags);
+    hipLaunchKernelGGL(k_invert_mfma<3>, grid, dim3(192), 0, st, it, n_mats, Ar, Hr, Q, Eall,
+                       out_stride, tau, mode, Minv, flags);
   else
-    hipLaunchKernelGGL(k_invert_mfma<4>, grid, dim3(256), 0, st, it, n_mats, Ar, Hr, Q, Eall, tau,
-                       tise, Minv, flags);
+    hipLaunchKernelGGL(k_invert_mfma<4>, grid, dim3(256), 0, st, it, n_mats, Ar, Hr, Q, Eall,
+                       out_stride, tau, mode, Minv, flags);
   return hipGetLastError();
 }
 
-hipError_t launch_cn_recur(const Items& it, int n_steps, const double* Ap, const double* Hr,
-                           const double* Q, const double* Eall, double tau, const double2* Minv,
-                           const double2* c0, const RecJobs& jobs, int* flags, hipStream_t st) {
+hipError_t launch_series_product(const Items& it, int n_chunks, const double2* L,
+                                 const double2* Rc, const double* Rr, double2 scale,
+                                 const double2* add, int64_t cstride, double2* out,
+                                 hipStream_t st) {
+  if (Rc)
+    hipLaunchKernelGGL(k_series_product<false>, dim3(it.n_items, n_chunks), dim3(kBlock), 0, st,
+                       it, L, Rc, Rr, scale, add, cstride, out);
+  else
+    hipLaunchKernelGGL(k_series_product<true>, dim3(it.n_items, n_chunks), dim3(kBlock), 0, st,
+                       it, L, Rc, Rr, scale, add, cstride, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_series_residual(const Items& it, int n_chunks, const double* Ar,
+                                  const double* Hr, const double* Q, const double* Eanchor,
+                                  double tau, const double2* X, int64_t cstride, double2* R,
+                                  hipStream_t st) {
+  hipLaunchKernelGGL(k_series_residual, dim3(it.n_items, kSmallK / kSerRows, n_chunks),
+                     dim3(kBlock), 0, st, it, Ar, Hr, Q, Eanchor, tau, X, cstride, R);
+  return hipGetLastError();
+}
+
+hipError_t launch_series_assemble(const Items& it, int n_mats, int terms, const double2* P,
+                                  int64_t stride, int64_t cstride, const double* Eall,
+                                  const double* Eanchor, double2* Minv, hipStream_t st) {
+  dim3 grid(it.n_items, (n_mats + kSeriesChunk - 1) / kSeriesChunk);
+  switch (terms) {
+#define SWR_SERIES_CASE(T)                                                                  \
+  case T:                                                                                   \
+    hipLaunchKernelGGL(k_series_assemble<T>, grid, dim3(kBlock), 0, st, it, n_mats, P,     \
+                       stride, cstride, Eall, Eanchor, Minv);                               \
+    break;
+    SWR_SERIES_CASE(1) SWR_SERIES_CASE(2) SWR_SERIES_CASE(3) SWR_SERIES_CASE(4)
+    SWR_SERIES_CASE(5) SWR_SERIES_CASE(6) SWR_SERIES_CASE(7) SWR_SERIES_CASE(8)
+#undef SWR_SERIES_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cn_recur(const Items& it, int n_steps, const double* Ar, const double* Ap,
+                           const double* Hr, const double* Q, const double* Eall, double tau,
+                           const double2* Minv, const double2* c0, const RecJobs& jobs, int* flags,
+                           hipStream_t st) {
   if (jobs.n < 1 || jobs.n > kMaxJobs) return hipErrorInvalidValue;
-  int max_cnt = 0;
-  for (int q = 0; q < jobs.n; ++q) {
+  for (int q = 0; q < jobs.n; ++q)
     if (jobs.n_lo[q] < 0 || jobs.n_cnt[q] < 1 || jobs.n_lo[q] + jobs.n_cnt[q] > n_steps)
       return hipErrorInvalidValue;
-    max_cnt = jobs.n_cnt[q] > max_cnt ? jobs.n_cnt[q] : max_cnt;
-  }
-  const size_t lds = (size_t)(max_cnt + 1) * sizeof(double);
-  hipLaunchKernelGGL(k_cn_recur<kRecPrefetch>, dim3(it.n_items, jobs.n), dim3(kRecThreads), lds, st,
-                     it, n_steps, Ap, Hr, Q, Eall, tau, Minv, c0, jobs, flags);
+  hipLaunchKernelGGL(k_cn_recur<kRecPrefetch>, dim3(it.n_items, jobs.n), dim3(kRecThreads), 0, st,
+                     it, n_steps, Ar, Ap, Hr, Q, Eall, tau, Minv, c0, jobs, flags);
   return hipGetLastError();
 }
 

@@ -57,6 +57,21 @@ def test_invalid_descriptions_rejected(S, mutate, code):
     assert S.load_library().swr_last_error(None)
 
 
+def test_factor_mode_validated_and_reported(S):
+    lib = S.load_library()
+    cfg = workloads.tiny_configs()[0]
+    d, keep = S.desc_from_config(cfg)
+    d.factor_mode = 2
+    h = ctypes.c_void_p()
+    assert lib.swr_create(ctypes.byref(d), ctypes.byref(h)) == -1
+    assert b"factor_mode" in lib.swr_last_error(None)
+    rc, h = _create(S, dict(cfg, factor="direct"))
+    assert rc == 0
+    info = S.swr_info()
+    assert lib.swr_query(h, ctypes.byref(info)) == 0 and info.factor_terms == -1
+    lib.swr_destroy(h)
+
+
 def test_unbound_workspace_and_state_errors(S):
     lib = S.load_library()
     rc, h = _create(S, workloads.tiny_configs()[0])
