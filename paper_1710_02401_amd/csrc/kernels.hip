@@ -1294,7 +1294,11 @@ __global__ void k_tx_pack(Items it, Pairs pr, TEnt te, double2* blob) {
 // sender strides, offset of a in the blob).  Everything the entry loop
 // reads is in LDS: per-entry reads of the global tables would be a chain of
 // dependent memory round trips.
-template <int TT>
+// NT > 0 (every tangential basis size <= NT): one thread per (entry, step)
+// keeps u in registers and writes v directly, so the entry loop has no
+// barriers; the residual likewise runs one thread per (face, step).  NT = 0:
+// the general form above, u staged in LDS entry by entry.
+template <int TT, int NT>
 __global__ void __launch_bounds__(kBlock) k_tx_send(Items it, TEnt te, int n_steps, TxJobs jobs,
                                                     int nbt, int64_t pieces, int64_t gram_max) {
   const int j = blockIdx.y;
@@ -1336,7 +1340,43 @@ __global__ void __launch_bounds__(kBlock) k_tx_send(Items it, TEnt te, int n_ste
                  1 << 30);
   gather_ints<2>(desc, te.sdesc + q0 * kTxDesc, ne * kTxDesc);
   __syncthreads();
-  for (int q = 0; q < ne; ++q) {
+  if (NT > 0) {
+    for (int t = threadIdx.x; t < ne * nrow; t += blockDim.x) {
+      const int q = t / nrow, nn = t - q * nrow;
+      const int* d = desc + q * kTxDesc;
+      const int e = d[0], nbjk = d[2], nbjt = d[3], nbit = d[4], sk = d[5], stt = d[6];
+      const double2* a = piece + d[7];
+      const double* X = reinterpret_cast<const double*>(a + nbjk);
+      const double2* c = Cs + nn * kCRow;
+      double ux[NT > 0 ? NT : 1], uy[NT > 0 ? NT : 1];
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) ux[mt] = uy[mt] = 0.0;
+      for (int mk = 0; mk < nbjk; ++mk) {
+        const double2 am = a[mk];
+        const double2* cr = c + mk * sk;
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt)
+          if (mt < nbjt) {
+            const double2 cv = cr[mt * stt];
+            ux[mt] = fma(am.x, cv.x, fma(-am.y, cv.y, ux[mt]));
+            uy[mt] = fma(am.x, cv.y, fma(am.y, cv.x, uy[mt]));
+          }
+      }
+      double2* vout = te.v + ((int64_t)e * (n_steps + 1) + n0 + nn) * nbt;
+      for (int lt = 0; lt < nbit; ++lt) {
+        const double* xr = X + lt * nbjt;
+        double vx = 0.0, vy = 0.0;
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt)
+          if (mt < nbjt) {
+            vx = fma(xr[mt], ux[mt], vx);
+            vy = fma(xr[mt], uy[mt], vy);
+          }
+        vout[lt] = make_double2(vx, vy);
+      }
+    }
+  }
+  for (int q = 0; NT == 0 && q < ne; ++q) {
     const int* d = desc + q * kTxDesc;
     const int e = d[0], nbjk = d[2], nbjt = d[3], nbit = d[4], sk = d[5], stt = d[6];
     const double2* a = piece + d[7];
@@ -1381,8 +1421,56 @@ __global__ void __launch_bounds__(kBlock) k_tx_send(Items it, TEnt te, int n_ste
   const int D = it.D;
   const int nbj1 = D == 2 ? it.nb[4 * j + 1] : 1;
   double acc = 0.0;
+  if (NT > 0) {
+    for (int t = threadIdx.x; t < 2 * D * nrow; t += blockDim.x) {
+      const int f = t / nrow, nn = t - f * nrow;
+      const int kf = f >> 1;
+      const int nbk = it.nb[4 * j + kf];
+      const int nbf = D == 2 ? it.nb[4 * j + (1 - kf)] : 1;
+      const int sk = (D == 2 && kf == 0) ? nbj1 : 1;
+      const int stt = (D == 2 && kf == 1) ? nbj1 : 1;
+      int goff = 0;
+      for (int f2 = 0; f2 < f; ++f2) {
+        const int k2 = f2 >> 1;
+        const int m = D == 2 ? it.nb[4 * j + (1 - k2)] : 1;
+        goff += it.nb[4 * j + k2] + m * m;
+      }
+      const double* b = gpiece + goff;
+      const double* W = b + nbk;
+      const double2* c = Cs + nn * kCRow;
+      double wx[NT > 0 ? NT : 1], wy[NT > 0 ? NT : 1];
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) wx[mt] = wy[mt] = 0.0;
+      for (int mk = 0; mk < nbk; ++mk) {
+        const double bm = b[mk];
+        const double2* cr = c + mk * sk;
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt)
+          if (mt < nbf) {
+            const double2 cv = cr[mt * stt];
+            wx[mt] = fma(bm, cv.x, wx[mt]);
+            wy[mt] = fma(bm, cv.y, wy[mt]);
+          }
+      }
+      double term = 0.0;
+#pragma unroll
+      for (int lt = 0; lt < NT; ++lt)
+        if (lt < nbf) {
+          double sx = 0.0, sy = 0.0;
+#pragma unroll
+          for (int mt = 0; mt < NT; ++mt)
+            if (mt < nbf) {
+              sx = fma(W[lt * nbf + mt], wx[mt], sx);
+              sy = fma(W[lt * nbf + mt], wy[mt], sy);
+            }
+          term += wx[lt] * sx + wy[lt] * sy;
+        }
+      const int n = n0 + nn;
+      acc += ((n == 0 || n == n_steps) ? 0.5 * jobs.dt : jobs.dt) * term;
+    }
+  }
   int goff = 0;
-  for (int f = 0; f < 2 * D; ++f) {
+  for (int f = 0; NT == 0 && f < 2 * D; ++f) {
     const int kf = f >> 1;
     const int nbk = it.nb[4 * j + kf];
     const int nbf = D == 2 ? it.nb[4 * j + (1 - kf)] : 1;
@@ -2290,14 +2378,24 @@ hipError_t launch_transmit(const Items& it, const Pairs& pr, const TEnt& te, int
     if (tt == 0 || max_recv < 1 || max_recv > kMaxRecvEntries) return hipErrorInvalidValue;
     const size_t lds = tx_send_lds(tt, nbt, pieces, max_send, gram);
     dim3 grid(blocks_for(span, tt), it.n_items, jobs.n);
+    // register form when every tangential basis has at most 8 functions
+    const bool reg = nbt <= 8;
     if (tt == 32) {
-      hipLaunchKernelGGL(k_tx_send<32>, grid, dim3(kBlock), lds, st, it, te, n_steps, jobs, nbt,
-                         pieces, gram / 8);
+      if (reg)
+        hipLaunchKernelGGL((k_tx_send<32, 8>), grid, dim3(kBlock), lds, st, it, te, n_steps, jobs,
+                           nbt, pieces, gram / 8);
+      else
+        hipLaunchKernelGGL((k_tx_send<32, 0>), grid, dim3(kBlock), lds, st, it, te, n_steps, jobs,
+                           nbt, pieces, gram / 8);
       hipLaunchKernelGGL(k_tx_recv<32>, grid, dim3(kBlock), 0, st, it, te, n_steps, jobs, scale,
                          nbt);
     } else {
-      hipLaunchKernelGGL(k_tx_send<16>, grid, dim3(kBlock), lds, st, it, te, n_steps, jobs, nbt,
-                         pieces, gram / 8);
+      if (reg)
+        hipLaunchKernelGGL((k_tx_send<16, 8>), grid, dim3(kBlock), lds, st, it, te, n_steps, jobs,
+                           nbt, pieces, gram / 8);
+      else
+        hipLaunchKernelGGL((k_tx_send<16, 0>), grid, dim3(kBlock), lds, st, it, te, n_steps, jobs,
+                           nbt, pieces, gram / 8);
       hipLaunchKernelGGL(k_tx_recv<16>, grid, dim3(kBlock), 0, st, it, te, n_steps, jobs, scale,
                          nbt);
     }

@@ -305,6 +305,19 @@ def test_uneven_bases_in_two_dimensions():
     assert np.allclose(st["res"], res_o, rtol=1e-8, atol=1e-14)
 
 
+def test_tangential_bases_beyond_eight():
+    """Tangential basis sizes above 8 take the general sender (u staged in
+    LDS entry by entry) instead of the register form."""
+    cfg = dict(TINY["tiny-2d"], name="tiny-2d-wide",
+               nbasis=[[4, 10], [10, 4], [5, 9], [9, 5], [6, 10], [10, 6]])
+    s = _solver(cfg)
+    prob = o_swr.Problem(cfg)
+    st = s.run(k_max=4, tol=0.0)
+    h_o, res_o = o_swr.swr_window(prob, prob.initial_coeffs(), iters=4)
+    assert a_norm_rel(prob, [_np(h) for h in s.split_history(s.history())], h_o) <= 1e-10
+    assert np.allclose(st["res"], res_o, rtol=1e-8, atol=1e-14)
+
+
 def _a_norm_diff(h1, h2, A):
     """max over steps of the relative A-norm distance of two item histories."""
     num = sum(np.real(np.einsum("nk,kl,nl->n", np.conj(a - b), M, a - b))
