@@ -3,11 +3,12 @@
 A step is one SWR time window of the two-electron workload (2 electrons in
 one dimension each, 8x8 overlapping subdomains, 8x8 Gaussians per subdomain,
 1000 Crank-Nicolson steps, 20 Schwarz iterations), run by swr_run: the
-factorisation of every local Crank-Nicolson matrix of the window, the plain
-warm start, then 20 Schwarz iterations of local solves (recurrence),
-transmission and residual, with P iterates in flight over chunks of the
-window (depth P, 4 here).  Inputs (assembled matrices, initial coefficients)
-are resident in HBM before the timed region.
+inverses of every local Crank-Nicolson matrix of the window (series in the
+field around 128-step anchors, or one inversion per step where the series
+bound does not hold), the plain warm start, then 20 Schwarz iterations of
+local solves (recurrence), transmission and residual, with P iterates in
+flight over chunks of the window (depth P, 4 here).  Inputs (assembled
+matrices, initial coefficients) are resident in HBM before the timed region.
 
 value = subdomain-solves per second = subdomains x Schwarz iterations x
 steps / seconds, where a subdomain-solve is one subdomain's whole-window
@@ -31,9 +32,12 @@ FP64_PEAK_TFS = 78.6
 # to the counter's reading), per launch of that kernel in this benchmark's
 # window.  Valid only for the kernel source it was measured on.
 MEASURED_TRAFFIC = {
-    # profiles/k_cn_recur_c2-2e-1d_traffic.md: 23 launches per window,
-    # FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 (1 GiB copy calibration)
-    "k_cn_recur": {"kernels_sha256": "f6efa4a320be061a", "bytes_per_launch": 2.1726e9},
+    # profiles/c2-2e-1d_traffic.md: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000
+    # (1 GiB copy calibration) over the first window at depth 4: 23
+    # recurrence launches, 24 transmissions, one factorisation
+    "k_cn_recur": {"kernels_sha256": "ed47789c50af18a4", "bytes_per_launch": 2.1759e9},
+    "k_tx_send+k_tx_recv": {"kernels_sha256": "ed47789c50af18a4", "bytes_per_launch": 0.4571e9},
+    "k_series_assemble": {"kernels_sha256": "ed47789c50af18a4", "bytes_per_launch": 2.4357e9},
 }
 
 
@@ -74,7 +78,7 @@ def learned_summary(mode):
         kw = dict(n_traj=10, n_win=8, eval_traj=2, eval_win=4, steps=3000)
     else:
         cfg = workloads.get_config("c4-2e-1d-learned")
-        kw = dict(n_traj=40, n_win=8, eval_traj=2, eval_win=4, steps=20000)
+        kw = dict(n_traj=64, n_win=6, eval_traj=2, eval_win=4, steps=8000)
     out, _ = learned.experiment(cfg, batch=256, lr=1e-3, k_max=150, log=lambda m: None, **kw)
     keep = ("windows", "plain_mean", "learned_mean", "zero_mean", "ideal_mean",
             "iteration_reduction", "prediction_mse", "max_rel_diff", "all_converged",
@@ -138,15 +142,19 @@ def main():
                     launches=sum(r["kernels"][k]["launches"] for r in runs) / args.steps)
             for k in ("factor", "transmit", "recur", "residual")}
     # algorithmic work per window of each kernel class
+    series = s.factor_terms() >= 0
     inv_flops = n_sub * nT * 8.0 * K ** 3                    # complex Gauss-Jordan inverses
+    inv_bytes = n_sub * nT * 16.0 * K * (K + 1) / 2          # symmetric inverses written
     # per (item, step): the symmetric inverse's K(K+1)/2 entries, f^{n+1}, c^{n+1}
     rec_bytes = iters * n_sub * nT * (16.0 * K * (K + 1) / 2 + 32.0 * K)
     hist_bytes = n_sub * (nT + 1) * K * 16.0
     # Robin data (+ residual partials): read iterate and previous iterate, write f
     tx_bytes = (iters + 1) * 3.0 * hist_bytes
     roofs = {
-        "factor": dict(kernel="k_invert", bound="alu", achieved=inv_flops / 1e12,
-                       peak=FP64_PEAK_TFS, unit="TFLOP/s"),
+        "factor": (dict(kernel="k_series_assemble", bound="hbm", achieved=inv_bytes / 1e9,
+                        peak=HBM_PEAK_GBS, unit="GB/s") if series else
+                   dict(kernel="k_invert_mfma", bound="mfma", achieved=inv_flops / 1e12,
+                        peak=FP64_PEAK_TFS, unit="TFLOP/s")),
         "recur": dict(kernel="k_cn_recur", bound="hbm", achieved=rec_bytes / 1e9,
                       peak=HBM_PEAK_GBS, unit="GB/s"),
         "transmit": dict(kernel="k_tx_send+k_tx_recv", bound="hbm", achieved=tx_bytes / 1e9,
@@ -186,6 +194,7 @@ def main():
                    "subdomains": n_sub, "K": K, "n_steps": nT, "schwarz_iters": iters,
                    "depth": int(s.info.depth) if args.depth == 0 else args.depth},
         "roofline": roofline,
+        "factor_series_terms": s.factor_terms() + 1,
         "kernels_per_window": roofs,
         "sweep_ms_per_iteration": ms_step / iters,
         "last_residual": runs[-1]["res"][-1],

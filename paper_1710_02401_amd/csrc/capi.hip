@@ -44,7 +44,9 @@ constexpr int kMaxSlots = kMaxDepth + 2;  // + the previous iterate, + one for t
 static_assert(kMaxDepth <= swr::kMaxJobs, "one job per iterate in flight");
 constexpr int kResEvents = 8;   // residual read-backs in flight
 constexpr int kGpuCUs = 256;    // MI355X compute units
-constexpr int kRecPerCU = 2;    // recurrence blocks per compute unit the depth aims at
+// recurrence blocks per compute unit the depth aims at (its 512-thread block
+// needs more than 128 registers per lane, so a second one is not resident)
+constexpr int kRecPerCU = 1;
 // series inverses of the window (swr_factor): at most this many terms
 constexpr int kSeriesMaxTerms = 8;
 
