@@ -459,8 +459,8 @@ int32_t swr_create(const swr_desc* desc, swr_handle* out) {
     delete h;
     return SWR_E_SIZE;
   }
-  if (g.desc.dim != 1 || g.desc.n_elec > 2) {
-    g_create_error = "this build assembles one space dimension per electron and at most 2 electrons";
+  if (g.desc.dim > 2 || g.desc.n_elec > 2) {
+    g_create_error = "this build assembles at most two space dimensions per electron and 2 electrons";
     delete h;
     return SWR_E_SIZE;
   }
@@ -493,7 +493,16 @@ int32_t swr_create(const swr_desc* desc, swr_handle* out) {
       s1 += (int64_t)n * n;
     }
     h->scratch_off[s] = scr;
-    if (g.desc.n_elec == 2) {
+    if (g.desc.dim == 2) {
+      int32_t nb[4], qn[4];
+      for (int k = 0; k < 4; ++k) {
+        nb[k] = k < g.D ? g.nb[(size_t)s * 4 + k] : 1;
+        qn[k] = k < g.D ? g.qn[(size_t)s * 4 + k] : 1;
+      }
+      int64_t off[11];
+      swr::pot2_layout(nb, qn, g.desc.n_elec, off);
+      scr += off[10];
+    } else if (g.desc.n_elec == 2) {
       const int n1 = g.nb[(size_t)s * 4 + 1];
       scr += (int64_t)g.qn[(size_t)s * 4 + 0] * n1 * n1;
     }

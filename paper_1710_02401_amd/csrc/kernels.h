@@ -135,6 +135,41 @@ struct Potential {
   double eps_en, eps_ee;
 };
 
+// Scratch layout of the potential for two space dimensions per electron
+// (doubles, from the item's scratch offset): off[k] the weighted product
+// table F_k[a n_k + b][q] = w_q phi_a(x_q) phi_b(x_q) of dimension k < D;
+// off[4 + m] electron m's nucleus table over the pair indices of its two
+// dimensions; off[6..9] the stages of the electron-electron contraction
+// T3[q0 q1 q2][p3], T2[q0 q1][p2 p3], T1[q0][p1 p2 p3], Vee[p0 p1 p2 p3];
+// off[10] the total.  nb, qn: basis and quadrature sizes per dimension.
+__host__ __device__ inline void pot2_layout(const int32_t* nb, const int32_t* qn, int n_elec,
+                                            int64_t* off) {
+  const int D = 2 * n_elec;
+  int64_t o = 0;
+  int64_t P[4] = {1, 1, 1, 1};
+  for (int k = 0; k < 4; ++k) {
+    off[k] = o;
+    if (k < D) {
+      P[k] = (int64_t)nb[k] * nb[k];
+      o += P[k] * qn[k];
+    }
+  }
+  for (int m = 0; m < 2; ++m) {
+    off[4 + m] = o;
+    if (m < n_elec) o += P[2 * m] * P[2 * m + 1];
+  }
+  const bool ee = n_elec == 2;
+  off[6] = o;
+  if (ee) o += (int64_t)qn[0] * qn[1] * qn[2] * P[3];
+  off[7] = o;
+  if (ee) o += (int64_t)qn[0] * qn[1] * P[2] * P[3];
+  off[8] = o;
+  if (ee) o += (int64_t)qn[0] * P[1] * P[2] * P[3];
+  off[9] = o;
+  if (ee) o += P[0] * P[1] * P[2] * P[3];
+  off[10] = o;
+}
+
 // ---- launchers (return hipError_t of the launch) ----
 hipError_t launch_assemble(const Items& it, double* A, double* Kin, double* Q, double* B,
                            double* W, double* S1, const int64_t* s1off, int K_max,

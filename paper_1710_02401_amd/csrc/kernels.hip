@@ -254,6 +254,197 @@ __global__ void k_potential(Items it, Potential pot, const double* S1, const int
 }
 
 // ---------------------------------------------------------------------------
+// Soft-Coulomb potential with two space dimensions per electron (eq. pseudo,
+// D = 2 N): every term is a sum over the tensor Gauss-Legendre grid of its
+// dimensions, contracted one dimension at a time with the weighted product
+// tables F_k (layout in pot2_layout).  Grid: (blocks, item); each kernel is
+// one stage, grid-stride over the stage's outputs for its item.
+__device__ inline void pot2_item(const Items& it, int s, int64_t* off, int* nq) {
+  int32_t nb[4], qn[4];
+  for (int k = 0; k < 4; ++k) {
+    nb[k] = k < it.D ? it.nb[4 * s + k] : 1;
+    qn[k] = k < it.D ? it.qn[4 * s + k] : 1;
+    nq[k] = qn[k];
+  }
+  pot2_layout(nb, qn, it.n_elec, off);
+}
+
+__global__ void k_pot2_tables(Items it, double* scratch, const int64_t* scratch_off) {
+  const int s = blockIdx.y;
+  int64_t off[11];
+  int nq[4];
+  pot2_item(it, s, off, nq);
+  double* base = scratch + scratch_off[s];
+  for (int k = 0; k < it.D; ++k) {
+    const int n = it.nb[4 * s + k];
+    const double d = it.delta[4 * s + k];
+    const double* al = it.alpha + it.aoff[4 * s + k];
+    const double* qx = it.qx + it.qoff[4 * s + k];
+    const double* qw = it.qw + it.qoff[4 * s + k];
+    const int64_t tot = (int64_t)n * n * nq[k];
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
+         e += (int64_t)gridDim.x * blockDim.x) {
+      const int p = (int)(e / nq[k]), q = (int)(e - (int64_t)p * nq[k]);
+      const int a = p / n, b = p - a * n;
+      const double x = qx[q];
+      base[off[k] + e] = qw[q] * exp(-d * (x - al[a]) * (x - al[a])) * exp(-d * (x - al[b]) * (x - al[b]));
+    }
+  }
+}
+
+// electron m's nucleus term: Ten[p0 P1 + p1] = sum_{q0, q1} F[p0][q0] F'[p1][q1] U(x_q0, y_q1)
+__global__ void k_pot2_en(Items it, Potential pot, double* scratch, const int64_t* scratch_off) {
+  const int s = blockIdx.y;
+  int64_t off[11];
+  int nq[4];
+  pot2_item(it, s, off, nq);
+  double* base = scratch + scratch_off[s];
+  const int geom = s / it.n_sub;
+  const double e2 = pot.eps_en * pot.eps_en;
+  for (int m = 0; m < it.n_elec && pot.n_nuc > 0; ++m) {
+    const int k0 = 2 * m, k1 = 2 * m + 1;
+    const int P0 = it.nb[4 * s + k0] * it.nb[4 * s + k0], P1 = it.nb[4 * s + k1] * it.nb[4 * s + k1];
+    const double* x0 = it.qx + it.qoff[4 * s + k0];
+    const double* x1 = it.qx + it.qoff[4 * s + k1];
+    const double* F0 = base + off[k0];
+    const double* F1 = base + off[k1];
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)P0 * P1;
+         e += (int64_t)gridDim.x * blockDim.x) {
+      const int p0 = (int)(e / P1), p1 = (int)(e - (int64_t)p0 * P1);
+      double acc = 0.0;
+      for (int q0 = 0; q0 < nq[k0]; ++q0) {
+        double inner = 0.0;
+        for (int q1 = 0; q1 < nq[k1]; ++q1) {
+          double u = 0.0;
+          for (int A = 0; A < pot.n_nuc; ++A) {
+            const double* R = pot.pos + (geom * pot.n_nuc + A) * 2;
+            const double dx = x0[q0] - R[0], dy = x1[q1] - R[1];
+            u -= pot.charge[A] / sqrt(dx * dx + dy * dy + e2);
+          }
+          inner = fma(F1[(int64_t)p1 * nq[k1] + q1], u, inner);
+        }
+        acc = fma(F0[(int64_t)p0 * nq[k0] + q0], inner, acc);
+      }
+      base[off[4 + m] + e] = acc;
+    }
+  }
+}
+
+// electron-electron term, stage 3 - st (st = 0..3): contract q3, then q2, q1, q0
+__global__ void k_pot2_ee(Items it, Potential pot, int stage, double* scratch,
+                          const int64_t* scratch_off) {
+  const int s = blockIdx.y;
+  int64_t off[11];
+  int nq[4];
+  pot2_item(it, s, off, nq);
+  double* base = scratch + scratch_off[s];
+  int64_t P[4];
+  for (int k = 0; k < 4; ++k) P[k] = (int64_t)it.nb[4 * s + k] * it.nb[4 * s + k];
+  const double e2 = pot.eps_ee * pot.eps_ee;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t e0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (stage == 0) {  // T3[(q0 nq1 + q1) nq2 + q2][p3] = sum_q3 F3[p3][q3] u
+    const double* x0 = it.qx + it.qoff[4 * s + 0];
+    const double* x1 = it.qx + it.qoff[4 * s + 1];
+    const double* x2 = it.qx + it.qoff[4 * s + 2];
+    const double* x3 = it.qx + it.qoff[4 * s + 3];
+    const double* F3 = base + off[3];
+    const int64_t tot = (int64_t)nq[0] * nq[1] * nq[2] * P[3];
+    for (int64_t e = e0; e < tot; e += stride) {
+      const int64_t g = e / P[3];
+      const int p3 = (int)(e - g * P[3]);
+      const int q2 = (int)(g % nq[2]);
+      const int64_t g1 = g / nq[2];
+      const int q1 = (int)(g1 % nq[1]), q0 = (int)(g1 / nq[1]);
+      const double dx = x0[q0] - x2[q2];
+      const double c = dx * dx + e2;
+      double acc = 0.0;
+      for (int q3 = 0; q3 < nq[3]; ++q3) {
+        const double dy = x1[q1] - x3[q3];
+        acc = fma(F3[(int64_t)p3 * nq[3] + q3], 1.0 / sqrt(fma(dy, dy, c)), acc);
+      }
+      base[off[6] + e] = acc;
+    }
+  } else if (stage == 1) {  // T2[(q0 nq1 + q1)][p2 P3 + p3] = sum_q2 F2[p2][q2] T3
+    const double* F2 = base + off[2];
+    const double* T3 = base + off[6];
+    const int64_t tot = (int64_t)nq[0] * nq[1] * P[2] * P[3];
+    for (int64_t e = e0; e < tot; e += stride) {
+      const int64_t g = e / (P[2] * P[3]);
+      const int64_t r = e - g * P[2] * P[3];
+      const int p2 = (int)(r / P[3]), p3 = (int)(r - (int64_t)p2 * P[3]);
+      double acc = 0.0;
+      for (int q2 = 0; q2 < nq[2]; ++q2)
+        acc = fma(F2[(int64_t)p2 * nq[2] + q2], T3[(g * nq[2] + q2) * P[3] + p3], acc);
+      base[off[7] + e] = acc;
+    }
+  } else if (stage == 2) {  // T1[q0][p1 P2P3 + r] = sum_q1 F1[p1][q1] T2[q0 nq1 + q1][r]
+    const double* F1 = base + off[1];
+    const double* T2 = base + off[7];
+    const int64_t R = P[2] * P[3];
+    const int64_t tot = (int64_t)nq[0] * P[1] * R;
+    for (int64_t e = e0; e < tot; e += stride) {
+      const int64_t q0 = e / (P[1] * R);
+      const int64_t t = e - q0 * P[1] * R;
+      const int p1 = (int)(t / R);
+      const int64_t r = t - (int64_t)p1 * R;
+      double acc = 0.0;
+      for (int q1 = 0; q1 < nq[1]; ++q1)
+        acc = fma(F1[(int64_t)p1 * nq[1] + q1], T2[(q0 * nq[1] + q1) * R + r], acc);
+      base[off[8] + e] = acc;
+    }
+  } else {  // Vee[p0 P1P2P3 + r] = sum_q0 F0[p0][q0] T1[q0][r]
+    const double* F0 = base + off[0];
+    const double* T1 = base + off[8];
+    const int64_t R = P[1] * P[2] * P[3];
+    for (int64_t e = e0; e < P[0] * R; e += stride) {
+      const int p0 = (int)(e / R);
+      const int64_t r = e - (int64_t)p0 * R;
+      double acc = 0.0;
+      for (int q0 = 0; q0 < nq[0]; ++q0)
+        acc = fma(F0[(int64_t)p0 * nq[0] + q0], T1[(int64_t)q0 * R + r], acc);
+      base[off[9] + e] = acc;
+    }
+  }
+}
+
+// V[l][m] = sum_m' Ten_m'[pairs of its dims] prod_{other dims} S1 + Vee[pairs]
+__global__ void k_pot2_combine(Items it, const double* S1, const int64_t* s1off, double* V,
+                               const double* scratch, const int64_t* scratch_off) {
+  const int s = blockIdx.y;
+  int64_t off[11];
+  int nq[4];
+  pot2_item(it, s, off, nq);
+  const double* base = scratch + scratch_off[s];
+  const int K = it.K[s];
+  const int D = it.D;
+  const int32_t* nb = it.nb + 4 * s;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (int64_t)K * K;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int l = (int)(e / K), m = (int)(e - (int64_t)l * K);
+    int li[4], mi[4];
+    split_index(l, nb, D, li);
+    split_index(m, nb, D, mi);
+    int64_t p[4];
+    for (int k = 0; k < D; ++k) p[k] = (int64_t)li[k] * nb[k] + mi[k];
+    double v = 0.0;
+    for (int el = 0; el < it.n_elec; ++el) {
+      const int k0 = 2 * el, k1 = 2 * el + 1;
+      double t = base[off[4 + el] + p[k0] * ((int64_t)nb[k1] * nb[k1]) + p[k1]];
+      for (int k2 = 0; k2 < D; ++k2)
+        if (k2 != k0 && k2 != k1) t *= S1[s1off[4 * s + k2] + p[k2]];
+      v += t;
+    }
+    if (it.n_elec == 2) {
+      const int64_t P1 = (int64_t)nb[1] * nb[1], P2 = (int64_t)nb[2] * nb[2],
+                    P3 = (int64_t)nb[3] * nb[3];
+      v += base[off[9] + ((p[0] * P1 + p[1]) * P2 + p[2]) * P3 + p[3]];
+    }
+    V[it.off2[s] + e] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Basis values at a point: v_l(y) = prod_k phi_{l_k}(y_k)
 __device__ inline double basis_value(const Items& it, int s, int l, const double* y) {
   const int32_t* nb = it.nb + 4 * s;
@@ -2177,8 +2368,21 @@ hipError_t launch_assemble(const Items& it, double* A, double* Kin, double* Q, d
 hipError_t launch_potential(const Items& it, const Potential& pot, const double* S1,
                             const int64_t* s1off, double* V, double* scratch,
                             const int64_t* scratch_off, hipStream_t st) {
-  hipLaunchKernelGGL(k_potential, dim3(it.n_items), dim3(kBlock), 0, st, it, pot, S1, s1off, V,
-                     scratch, scratch_off);
+  if (it.dim == 1) {
+    hipLaunchKernelGGL(k_potential, dim3(it.n_items), dim3(kBlock), 0, st, it, pot, S1, s1off, V,
+                       scratch, scratch_off);
+    return hipGetLastError();
+  }
+  if (it.dim != 2 || it.n_elec < 1 || it.n_elec > 2) return hipErrorInvalidValue;
+  const dim3 grid(64, it.n_items);
+  hipLaunchKernelGGL(k_pot2_tables, grid, dim3(kBlock), 0, st, it, scratch, scratch_off);
+  hipLaunchKernelGGL(k_pot2_en, grid, dim3(kBlock), 0, st, it, pot, scratch, scratch_off);
+  if (it.n_elec == 2)
+    for (int stage = 0; stage < 4; ++stage)
+      hipLaunchKernelGGL(k_pot2_ee, dim3(stage == 0 ? 1024 : 64, it.n_items), dim3(kBlock), 0, st,
+                         it, pot, stage, scratch, scratch_off);
+  hipLaunchKernelGGL(k_pot2_combine, grid, dim3(kBlock), 0, st, it, S1, s1off, V, scratch,
+                     scratch_off);
   return hipGetLastError();
 }
 

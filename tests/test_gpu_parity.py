@@ -318,6 +318,25 @@ def test_tangential_bases_beyond_eight():
     assert np.allclose(st["res"], res_o, rtol=1e-8, atol=1e-14)
 
 
+@pytest.mark.parametrize("name", ["c5-mini", "c5-mini-1e"])
+def test_two_space_dimensions_per_electron(name):
+    """Two electrons in two dimensions (D = 4: 3-D faces, the dense transfer
+    operators and the dense residual, the 4-D electron-electron contraction),
+    and one electron in two dimensions (2-D nucleus term, factored
+    transmission)."""
+    cfg = workloads.get_config(name)
+    s = _solver(cfg)
+    prob = o_swr.Problem(cfg)
+    for name, M in (("A", "A"), ("V", "V"), ("Q", "Q")):
+        got = [_np(m) for m in s.matrix(name)]
+        ref = [getattr(sy, M) for sy in prob.sys]
+        assert max(np.max(np.abs(g - r)) / np.max(np.abs(r)) for g, r in zip(got, ref)) <= 1e-12
+    st = s.run(k_max=3, tol=0.0)
+    h_o, res_o = o_swr.swr_window(prob, prob.initial_coeffs(), iters=3)
+    assert a_norm_rel(prob, [_np(h) for h in s.split_history(s.history())], h_o) <= 1e-10
+    assert np.allclose(st["res"], res_o, rtol=1e-8, atol=1e-14)
+
+
 def _a_norm_diff(h1, h2, A):
     """max over steps of the relative A-norm distance of two item histories."""
     num = sum(np.real(np.einsum("nk,kl,nl->n", np.conj(a - b), M, a - b))

@@ -107,7 +107,30 @@ _C3M_GEOMS, _C3M_NB = _uneven_geometries(4, 16, (-20.0, 20.0), 8, 32)
 _C3_MINI = dict(_C3, name="c3-mini", L=[16], overlap=[0.5], nbasis=_C3M_NB,
                 geometries=_C3M_GEOMS, nuclei=_C3M_GEOMS[0], iters=8)
 
-CONFIGS = {c["name"]: c for c in (_C1, _C2, _C2_TISE, _C3, _C3_MINI, _C4, _C5)}
+# Two electrons in two dimensions at a size the oracle assembles in under a
+# minute: 2^4 subdomains of 3x2x2x3 Gaussians, unequal boxes, overlaps and
+# per-dimension sizes, field along the second spatial axis.
+_C5_MINI = dict(
+    name="c5-mini", mode="tdse", n_elec=2, dim=2,
+    L=[2, 2, 2, 2], box_lo=[-5.0, -4.0, -5.0, -4.5], box_hi=[5.0, 4.0, 4.5, 4.0],
+    overlap=[0.8, 0.7, 0.8, 0.6],
+    nbasis=[3, 2, 2, 3], width=None, width_ratio=0.7,
+    nuclei=[[-1.0, 0.0], [1.0, 0.2]], charges=[1.0, 1.0], eps_en=0.5, eps_ee=0.6,
+    dt=0.01, n_steps=6, mu=[0.3, -5.0],
+    field=dict(E0=0.2, omega=0.9, phase=0.1, axis=1),
+    init=dict(alpha=0.5, center=[0.2, -0.1, -0.2, 0.1]),
+    iters=3, tol=1e-8, face_nodes=[2, 2], quad_nodes=8,
+)
+
+# One electron in two dimensions (D = 2 with a two-dimensional nucleus term),
+# field along the second axis.
+_C5_MINI_1E = dict(
+    _C5_MINI, name="c5-mini-1e", n_elec=1, L=[3, 2], box_lo=[-6.0, -5.0], box_hi=[6.0, 5.5],
+    overlap=[0.8, 0.7], nbasis=[5, 4], init=dict(alpha=0.6, center=[0.3, -0.2]), n_steps=10,
+)
+
+CONFIGS = {c["name"]: c for c in (_C1, _C2, _C2_TISE, _C3, _C3_MINI, _C4, _C5, _C5_MINI,
+                                   _C5_MINI_1E)}
 
 
 def get_config(name, **overrides):
