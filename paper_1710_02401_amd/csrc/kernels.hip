@@ -1500,36 +1500,90 @@ __global__ void __launch_bounds__(kBlock) k_tx_send(Items it, TEnt te, int n_ste
   const int Kj = it.K[j];
   extern __shared__ double2 smem[];
   double2* Cs = smem;
-  double2* Ub = Cs + TT * kCRow;
-  double2* piece = Ub + 2 * TT * nbt;
+  double2* Ub = Cs + TT * kCRow;  // general form only
+  double2* piece = Ub + (NT > 0 ? 0 : 2 * TT * nbt);
   double* gpiece = reinterpret_cast<double*>(piece + pieces / 16);
   int* desc = reinterpret_cast<int*>(gpiece + gram_max);
   const int nrow = min(TT, n_hi - n0 + 1);
   const int64_t q0 = te.soff[j];
   const int ne = (int)(te.soff[j + 1] - q0);
   const int64_t hoff = (int64_t)(n_steps + 1) * it.off1[j] + (int64_t)n0 * Kj;
-  gather_rows<TT * kSmallK / kBlock>(Cs, kCRow, jobs.src[job] + hoff, nrow * Kj, Kj);
-  // residual: the previous iterate's tile, loaded now and consumed after the
-  // entries (its latency hides behind them)
+  // One memory round trip: the coefficient tile, the previous iterate's tile
+  // (kept in registers until the residual), the sender's pieces, its face
+  // Gram pieces and its descriptors are all requested before any is stored.
   double* part = jobs.part[job];
   constexpr int kU = TT * kSmallK / kBlock;
-  double px[kU], py[kU];
-  if (part) {
-    const double2* prev = jobs.prev[job] + hoff;
+  constexpr int kUB = 4, kUG = 2, kUD = 2;  // per-thread batches of pieces, Gram, descriptors
+  const int nC = nrow * Kj;
+  const int nB = (int)(te.blob_off[j + 1] - te.blob_off[j]);
+  const int nG = part ? (int)(te.gram_off[j + 1] - te.gram_off[j]) / 2 : 0;
+  const int nD = ne * kTxDesc;
+  const double2* csrc = jobs.src[job] + hoff;
+  const double2* psrc = part ? jobs.prev[job] + hoff : csrc;
+  const double2* bsrc = te.blob + te.blob_off[j];
+  const double2* gsrc = reinterpret_cast<const double2*>(te.gram + te.gram_off[j]);
+  const int* dsrc = te.sdesc + q0 * kTxDesc;
+  double cx[kU], cy[kU], px[kU], py[kU], bx[kUB], by[kUB], gx[kUG], gy[kUG];
+  int dv[kUD];
+  const double2 z2 = make_double2(0.0, 0.0);
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int x = u * kBlock + (int)threadIdx.x;
-      const double2 v = prev[x < nrow * Kj ? x : 0];
-      px[u] = v.x;
-      py[u] = v.y;
-    }
-    const int ng = (int)(te.gram_off[j + 1] - te.gram_off[j]);
-    gather_rows<2>(reinterpret_cast<double2*>(gpiece), 0,
-                   reinterpret_cast<const double2*>(te.gram + te.gram_off[j]), ng / 2, 1 << 30);
+  for (int u = 0; u < kU; ++u) {
+    const int x = u * kBlock + (int)threadIdx.x;
+    const double2 c = x < nC ? csrc[x] : z2;
+    const double2 v = (part && x < nC) ? psrc[x] : z2;
+    cx[u] = c.x;
+    cy[u] = c.y;
+    px[u] = v.x;
+    py[u] = v.y;
   }
-  gather_rows<4>(piece, 0, te.blob + te.blob_off[j], (int)(te.blob_off[j + 1] - te.blob_off[j]),
-                 1 << 30);
-  gather_ints<2>(desc, te.sdesc + q0 * kTxDesc, ne * kTxDesc);
+#pragma unroll
+  for (int u = 0; u < kUB; ++u) {
+    const int x = u * kBlock + (int)threadIdx.x;
+    const double2 v = x < nB ? bsrc[x] : z2;
+    bx[u] = v.x;
+    by[u] = v.y;
+  }
+#pragma unroll
+  for (int u = 0; u < kUG; ++u) {
+    const int x = u * kBlock + (int)threadIdx.x;
+    const double2 v = x < nG ? gsrc[x] : z2;
+    gx[u] = v.x;
+    gy[u] = v.y;
+  }
+#pragma unroll
+  for (int u = 0; u < kUD; ++u) {
+    const int x = u * kBlock + (int)threadIdx.x;
+    dv[u] = x < nD ? dsrc[x] : 0;
+  }
+  __builtin_amdgcn_sched_barrier(0);  // every load above ahead of the stores below
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int x = u * kBlock + (int)threadIdx.x;
+    if (x < nC) {
+      const int r = x / Kj;
+      Cs[r * kCRow + (x - r * Kj)] = make_double2(cx[u], cy[u]);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kUB; ++u) {
+    const int x = u * kBlock + (int)threadIdx.x;
+    if (x < nB) piece[x] = make_double2(bx[u], by[u]);
+  }
+#pragma unroll
+  for (int u = 0; u < kUG; ++u) {
+    const int x = u * kBlock + (int)threadIdx.x;
+    if (x < nG) reinterpret_cast<double2*>(gpiece)[x] = make_double2(gx[u], gy[u]);
+  }
+#pragma unroll
+  for (int u = 0; u < kUD; ++u) {
+    const int x = u * kBlock + (int)threadIdx.x;
+    if (x < nD) desc[x] = dv[u];
+  }
+  // senders larger than the batches: the rest element by element
+  for (int x = kUB * kBlock + (int)threadIdx.x; x < nB; x += kBlock) piece[x] = bsrc[x];
+  for (int x = kUG * kBlock + (int)threadIdx.x; x < nG; x += kBlock)
+    reinterpret_cast<double2*>(gpiece)[x] = gsrc[x];
+  for (int x = kUD * kBlock + (int)threadIdx.x; x < nD; x += kBlock) desc[x] = dsrc[x];
   __syncthreads();
   if (NT > 0) {
     for (int t = threadIdx.x; t < ne * nrow; t += blockDim.x) {
@@ -2580,10 +2634,11 @@ hipError_t launch_transmit(const Items& it, const Pairs& pr, const TEnt& te, int
     if (nbt < 1 || nbt > kSmallK) return hipErrorInvalidValue;
     const int tt = transmit_tile_steps(nbt, pieces, max_send, gram);
     if (tt == 0 || max_recv < 1 || max_recv > kMaxRecvEntries) return hipErrorInvalidValue;
-    const size_t lds = tx_send_lds(tt, nbt, pieces, max_send, gram);
-    dim3 grid(blocks_for(span, tt), it.n_items, jobs.n);
-    // register form when every tangential basis has at most 8 functions
+    // register form when every tangential basis has at most 8 functions (it
+    // needs no u buffer in LDS)
     const bool reg = nbt <= 8;
+    const size_t lds = tx_send_lds(tt, reg ? 0 : nbt, pieces, max_send, gram);
+    dim3 grid(blocks_for(span, tt), it.n_items, jobs.n);
     if (tt == 32) {
       if (reg)
         hipLaunchKernelGGL((k_tx_send<32, 8>), grid, dim3(kBlock), lds, st, it, te, n_steps, jobs,
