@@ -12,8 +12,11 @@ matrices, initial coefficients) are resident in HBM before the timed region.
 
 value = subdomain-solves per second = subdomains x Schwarz iterations x
 steps / seconds, where a subdomain-solve is one subdomain's whole-window
-local solve in one Schwarz iteration.  Kernel durations come from HIP events
-the library records around each launch on the run's stream.
+local solve in one Schwarz iteration.  The timed windows run exactly 20
+iterations each, their launches replayed from a HIP graph captured on the
+first window (--no-graph: launched one by one); kernel durations come from
+HIP events the library records around each launch on the run's stream, in a
+second pass over as many windows launched one by one.
 """
 import argparse
 import json
@@ -98,6 +101,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--depth", type=int, default=0, help="iterates in flight (0: library choice)")
     ap.add_argument("--learned", choices=("off", "quick", "full"), default="quick")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time the windows as eager launches instead of a replayed HIP graph")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="end with a device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -122,24 +127,30 @@ def main():
     nT = int(s.n_steps)
     c0 = s.initial().clone()
 
-    def window():
+    # exactly `iters` Schwarz iterations per window (tol < 0); the timed
+    # windows replay the window captured as a HIP graph, a second pass over as
+    # many windows records HIP events around every launch for the kernel times
+    def window(graph):
         s.set_initial(c0)
-        return s.run(k_max=iters, tol=0.0, depth=args.depth, timing=True)
+        return s.run(k_max=iters, tol=-1.0, depth=args.depth, timing=not graph,
+                     graph=graph and not args.no_graph)
 
     for _ in range(args.warmup):
-        window()
+        window(True)
     torch.cuda.synchronize()
     runs = []
     t = time.perf_counter()
     for _ in range(args.steps):
-        runs.append(window())
+        runs.append(window(True))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t
     ms_step = 1e3 * wall / args.steps
     value = n_sub * iters * args.steps / wall
+    truns = [window(False) for _ in range(args.steps)]
+    torch.cuda.synchronize()
 
-    kern = {k: dict(ms=sum(r["kernels"][k]["ms"] for r in runs) / args.steps,
-                    launches=sum(r["kernels"][k]["launches"] for r in runs) / args.steps)
+    kern = {k: dict(ms=sum(r["kernels"][k]["ms"] for r in truns) / args.steps,
+                    launches=sum(r["kernels"][k]["launches"] for r in truns) / args.steps)
             for k in ("factor", "transmit", "recur", "residual")}
     # algorithmic work per window of each kernel class
     series = s.factor_terms() >= 0
@@ -196,6 +207,7 @@ def main():
         "roofline": roofline,
         "factor_series_terms": s.factor_terms() + 1,
         "kernels_per_window": roofs,
+        "windows_launched_as": "eager" if args.no_graph else "hip_graph",
         "sweep_ms_per_iteration": ms_step / iters,
         "last_residual": runs[-1]["res"][-1],
     }

@@ -188,7 +188,7 @@ int32_t swr_transmit(swr_handle h, double* residual_host, void* stream);
  * with the same arithmetic as at depth 1 (identical results); up to P-1
  * iterates past the stopping one are started and discarded.  depth 0 takes
  * swr_info.depth (sized at creation so that P x n_items fills the GPU,
- * P <= 4); 1 runs one iterate at a time; larger values are capped at
+ * P <= 8); 1 runs one iterate at a time; larger values are capped at
  * swr_info.depth.  TISE always runs at depth 1 (its global normalisation
  * couples every item at every step). */
 typedef struct swr_run_opts {
@@ -199,6 +199,11 @@ typedef struct swr_run_opts {
   const void* g_dev;         /* Robin data for SWR_WARM_GIVEN                 */
   int32_t depth;             /* 0: swr_info.depth; 1: one iterate at a time   */
   int32_t timing;            /* 1: time every kernel launch with HIP events    */
+  int32_t graph;             /* 1: with tol < 0 (exactly k_max iterations),
+                                depth > 1 and no timing, the window's launches
+                                are captured once into a HIP graph (per k_max
+                                and depth) and replayed; the residuals are
+                                read after the window                        */
 } swr_run_opts;
 /* With timing, ms_* hold the summed durations (HIP events recorded on the
  * run's stream around each launch) and n_* the launch counts of the

@@ -135,7 +135,15 @@ struct swr_handle_s {
   std::vector<int> tkind;             // kind of pair q (events 2q, 2q+1)
   size_t tused = 0;
 
+  // a pipelined window captured as a HIP graph (fixed iteration count), for
+  // its iteration count and depth
+  hipGraphExec_t gexec = nullptr;
+  int g_kmax = 0, g_P = 0;
+  hipStream_t cap_stream = nullptr;  // capture only (the caller's may be the null stream)
+
   ~swr_handle_s() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (res_pinned) (void)hipHostFree(res_pinned);
     if (ev_ready)
       for (auto& e : ev) (void)hipEventDestroy(e);
@@ -619,6 +627,10 @@ int32_t swr_bind_workspace(swr_handle h, void* dev, uint64_t bytes) {
   h->ws = (char*)dev;
   h->ws_bytes = bytes;
   h->bound = true;
+  if (h->gexec) {  // its kernels hold addresses in the old workspace
+    (void)hipGraphExecDestroy(h->gexec);
+    h->gexec = nullptr;
+  }
   h->assembled = h->initial = h->warm = h->factored = false;
   return SWR_OK;
 }
@@ -1008,8 +1020,10 @@ namespace {
 // n_chunks-1 of iterate k has been transmitted; it is reduced and copied to
 // pinned host memory before that launch's recurrence, so the host reads it
 // while the recurrence runs and never idles the GPU.
+// capture: only enqueue (the stream is being captured into a graph): no host
+// reads of the residuals, every iterate up to k_max, no flag check.
 int32_t run_pipelined(swr_handle h, const swr_run_opts* o, int P, swr_run_stats* out,
-                      hipStream_t st) {
+                      hipStream_t st, bool capture = false) {
   const swr::Items it = h->items();
   const int nT = (int)h->n_T;
   const int S = (nT + P - 1) / P;
@@ -1017,20 +1031,23 @@ int32_t run_pipelined(swr_handle h, const swr_run_opts* o, int P, swr_run_stats*
   const bool fused = h->fused_residual();
   if (fused && parts_needed(h, P) > h->part_stride)
     return fail(h, SWR_E_SIZE, "residual partials exceed their buffer");
-  if (!h->ev_ready) {
+  if (!capture && !h->ev_ready) {
     for (auto& e : h->ev) HIPCHECK(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
     h->ev_ready = true;
   }
-  if (!h->res_pinned) HIPCHECK(h, hipHostMalloc((void**)&h->res_pinned, 64 * sizeof(double), 0));
+  if (!capture && !h->res_pinned)
+    HIPCHECK(h, hipHostMalloc((void**)&h->res_pinned, 64 * sizeof(double), 0));
   swr_run_stats s{};
   int k_final = 0;
   auto queue_read = [&](int k) -> int {  // Res(k) (already in bResv) to the host
+    if (capture) return SWR_OK;
     double* dev = h->ptr<double>(h->bResv) + k % 64;
     HIPCHECK(h, hipMemcpyAsync(h->res_pinned + k % 64, dev, 8, hipMemcpyDeviceToHost, st));
     HIPCHECK(h, hipEventRecord(h->ev[k % kResEvents], st));
     return SWR_OK;
   };
   auto read = [&](int k) -> int {
+    if (capture) return SWR_OK;
     HIPCHECK(h, hipEventSynchronize(h->ev[k % kResEvents]));
     const double r = h->res_pinned[k % 64];
     if (k <= 64) s.res[k - 1] = r;
@@ -1124,8 +1141,57 @@ int32_t run_pipelined(swr_handle h, const swr_run_opts* o, int P, swr_run_stats*
   h->cur = k_final % h->n_slots;
   const int rc0 = transmit_and_residual(h, k_final, nullptr, nullptr, st);
   if (rc0) return rc0;
-  const int rc = check_flags(h, st);
+  if (!capture) {
+    const int rc = check_flags(h, st);
+    if (rc != SWR_OK) return rc;
+  }
+  *out = s;
+  return SWR_OK;
+}
+
+// Fixed-iteration pipelined window through a HIP graph: captured on the first
+// call for (k_max, P) and replayed afterwards; the residuals are read once,
+// after the window.
+int32_t run_graph(swr_handle h, const swr_run_opts* o, int P, swr_run_stats* out,
+                  hipStream_t st) {
+  if (!h->res_pinned) HIPCHECK(h, hipHostMalloc((void**)&h->res_pinned, 64 * sizeof(double), 0));
+  if (!h->gexec || h->g_kmax != o->k_max || h->g_P != P) {
+    if (h->gexec) {
+      HIPCHECK(h, hipGraphExecDestroy(h->gexec));
+      h->gexec = nullptr;
+    }
+    // captured on a stream of the library's own (default priority): nothing
+    // runs there, the graph is launched on the caller's stream below
+    if (!h->cap_stream) HIPCHECK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    HIPCHECK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    swr_run_stats dummy{};
+    const int rc = run_pipelined(h, o, P, &dummy, h->cap_stream, true);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    HIPCHECK(h, e);
+    const hipError_t ei = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIPCHECK(h, ei);
+    h->g_kmax = o->k_max;
+    h->g_P = P;
+  } else {
+    // the state the captured window leaves (as run_pipelined sets it)
+    h->k = o->k_max;
+    h->cur = o->k_max % h->n_slots;
+  }
+  HIPCHECK(h, hipGraphLaunch(h->gexec, st));
+  HIPCHECK(h, hipMemcpyAsync(h->res_pinned, h->ptr<double>(h->bResv), 64 * sizeof(double),
+                             hipMemcpyDeviceToHost, st));
+  const int rc = check_flags(h, st);  // synchronises the stream
   if (rc != SWR_OK) return rc;
+  swr_run_stats s{};
+  s.iters = o->k_max;
+  for (int k = std::max(1, o->k_max - 63); k <= o->k_max; ++k)
+    if (k <= 64) s.res[k - 1] = h->res_pinned[k % 64];
   *out = s;
   return SWR_OK;
 }
@@ -1148,7 +1214,9 @@ int32_t swr_run(swr_handle h, const swr_run_opts* o, swr_run_stats* stats, void*
   swr_run_stats s{};
   const int P = o->depth <= 0 ? h->depth : std::min(o->depth, h->depth);
   if (h->g.desc.mode == SWR_TDSE && P > 1) {
-    rc = run_pipelined(h, o, P, &s, (hipStream_t)stream);
+    const bool graph = o->graph != 0 && o->tol < 0.0 && !h->timing;
+    rc = graph ? run_graph(h, o, P, &s, (hipStream_t)stream)
+               : run_pipelined(h, o, P, &s, (hipStream_t)stream);
     if (rc) return rc;
     HIPCHECK(h, tcollect(h, &s));
     if (stats) *stats = s;

@@ -60,7 +60,7 @@ class swr_info(ctypes.Structure):
 class swr_run_opts(ctypes.Structure):
     _fields_ = [("k_max", ctypes.c_int32), ("tol", ctypes.c_double), ("t0", ctypes.c_double),
                 ("warm", ctypes.c_int32), ("g_dev", ctypes.c_void_p), ("depth", ctypes.c_int32),
-                ("timing", ctypes.c_int32)]
+                ("timing", ctypes.c_int32), ("graph", ctypes.c_int32)]
 
 
 class swr_run_stats(ctypes.Structure):
@@ -283,9 +283,10 @@ class Solver:
         self._call("swr_transmit", ctypes.byref(r), self._stream())
         return r.value
 
-    def run(self, k_max, tol=0.0, t0=0.0, warm=SWR_WARM_PLAIN, g=None, depth=0, timing=False):
+    def run(self, k_max, tol=0.0, t0=0.0, warm=SWR_WARM_PLAIN, g=None, depth=0, timing=False,
+            graph=False):
         o = swr_run_opts(k_max, tol, t0, warm, g.data_ptr() if g is not None else None, depth,
-                         int(bool(timing)))
+                         int(bool(timing)), int(bool(graph)))
         s = swr_run_stats()
         self._call("swr_run", ctypes.byref(o), ctypes.byref(s), self._stream())
         out = dict(iters=s.iters, converged=bool(s.converged),

@@ -379,3 +379,26 @@ def test_series_falls_back_to_direct_inversion_for_strong_fields():
     s = _solver(cfg)
     st = s.run(k_max=2, tol=0.0)
     assert s.factor_terms() == -1 and st["iters"] == 2
+
+
+@pytest.mark.parametrize("name", ["tiny-2d", "c2-2e-1d"])
+def test_graph_replay_equals_eager_run(name):
+    """A fixed-iteration window captured as a HIP graph and replayed, with
+    eager runs of another length between the replays, gives the eager run's
+    histories, Robin data and residuals bit for bit on every replay."""
+    cfg = _cfg(name)
+    s = _solver(cfg)
+    c0 = s.initial().clone()
+    k = 6
+    s.set_initial(c0)
+    st_e = s.run(k_max=k, tol=-1.0)
+    h_e, f_e = _np(s.history()), _np(s.forcing())
+    for rep in range(3):
+        s.set_initial(c0)
+        st_g = s.run(k_max=k, tol=-1.0, graph=True)
+        assert st_g["iters"] == k and not st_g["converged"]
+        assert np.array_equal(_np(s.history()), h_e), rep
+        assert np.array_equal(_np(s.forcing()), f_e), rep
+        assert st_g["res"] == st_e["res"], rep
+        s.set_initial(c0)
+        s.run(k_max=2, tol=-1.0)  # eager work between the replays
