@@ -7,7 +7,8 @@ inverses of every local Crank-Nicolson matrix of the window (series in the
 field around 128-step anchors, or one inversion per step where the series
 bound does not hold), the plain warm start, then 20 Schwarz iterations of
 local solves (recurrence), transmission and residual, with P iterates in
-flight over chunks of the window (depth P, 4 here).  Inputs (assembled
+flight over chunks of the window (depth P and the transmission tile chosen
+by the library's autotuner on this window before timing).  Inputs (assembled
 matrices, initial coefficients) are resident in HBM before the timed region.
 
 value = subdomain-solves per second = subdomains x Schwarz iterations x
@@ -135,6 +136,8 @@ def main():
         return s.run(k_max=iters, tol=-1.0, depth=args.depth, timing=not graph,
                      graph=graph and not args.no_graph)
 
+    # the schedule (depth, transmission tile) by measurement, on this window
+    tuning = s.autotune(k_iters=iters) if args.depth == 0 else None
     for _ in range(args.warmup):
         window(True)
     torch.cuda.synchronize()
@@ -203,7 +206,9 @@ def main():
                                f"{n_sub} subdomains, K={K} Gaussians each, {nT} Crank-Nicolson "
                                f"steps per window, {iters} Schwarz iterations per window",
                    "subdomains": n_sub, "K": K, "n_steps": nT, "schwarz_iters": iters,
-                   "depth": int(s.info.depth) if args.depth == 0 else args.depth},
+                   "depth": int(s.info.depth_run) if args.depth == 0 else args.depth,
+                   "tx_tile": int(s.info.tx_tile),
+                   "autotuned": tuning is not None},
         "roofline": roofline,
         "factor_series_terms": s.factor_terms() + 1,
         "kernels_per_window": roofs,

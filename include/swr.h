@@ -104,6 +104,10 @@ typedef struct swr_info {
   int32_t learned_nodes;     /* M, time nodes of the learned warm start       */
   int32_t factor_terms;      /* series terms of the last swr_factor minus one;
                                 -1: direct inversion per step (or none yet)  */
+  int32_t tx_tile;           /* steps per block of the factored transmission
+                                in use (16 or 32; 0: dense transmission)     */
+  int32_t depth_run;         /* depth swr_run uses for opts.depth = 0
+                                (swr_info.depth until swr_autotune)          */
 } swr_info;
 
 /* ---- lifetime ------------------------------------------------------------*/
@@ -218,6 +222,25 @@ typedef struct swr_run_stats {
   int32_t n_factor, n_transmit, n_recur, n_residual;
 } swr_run_stats;
 int32_t swr_run(swr_handle h, const swr_run_opts* opts, swr_run_stats* stats, void* stream);
+
+/* ---- schedule autotuning ---------------------------------------------------*/
+
+/* Measures, on this problem and GPU, every pipeline depth 1..swr_info.depth
+ * (TDSE; 1 for TISE) and every transmission tile that fits (16 or 32 steps
+ * per block), each as a whole window of k_iters Schwarz iterations (swr_run
+ * with tol < 0 from the current initial coefficients, field origin t0, plain
+ * warm start; one untimed window first), timed with HIP events on the stream,
+ * and keeps the fastest: later swr_run calls with depth 0 use its depth, and
+ * every transmission its tile.  The choice only reorders the same arithmetic
+ * (results are unchanged; residuals to rounding).  The iteration state is
+ * left as after the last trial window.  Synchronises the stream. */
+typedef struct swr_tuning {
+  int32_t depth;             /* iterates in flight chosen                     */
+  int32_t tx_tile;           /* transmission tile chosen (0: dense)           */
+  double ms_per_window;      /* measured for the choice                       */
+  int32_t candidates;        /* schedules measured                            */
+} swr_tuning;
+int32_t swr_autotune(swr_handle h, int32_t k_iters, double t0, swr_tuning* out, void* stream);
 
 /* ---- outputs and inspection ------------------------------------------------*/
 

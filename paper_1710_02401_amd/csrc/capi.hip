@@ -119,7 +119,9 @@ struct swr_handle_s {
   int te_max_recv = 0;    // largest number of entries one item receives
   int te_max_send = 0;    // largest number of entries one item sends
   int64_t te_gram_max = 0;  // largest LDS bytes of one item's face Gram pieces
-  int tx_tt = 0;            // steps per block of the factored transmission
+  int tx_tt = 0;            // steps per block of the factored transmission (in use)
+  int tx_tt_max = 0;        // the largest whose LDS fits (16 or 32)
+  int depth_run = 1;        // depth swr_run uses when asked for depth 0 (autotuned)
   int part_stride = 0;      // residual partials per item and iterate slot
   std::vector<int32_t> te_sdesc;  // sender-side entry descriptors
   int n_slots = 2;  // history / Robin data slots: iterate k uses slot k % n_slots
@@ -242,8 +244,8 @@ namespace {
 
 // Residual partials per item for a run of depth at most P: the window
 // whole, or in p <= P chunks of ceil(n_T / p) steps (chunk 0 one step more).
-int parts_needed(swr_handle h, int P) {
-  const int tt = h->tx_tt, nT = (int)h->n_T;
+int parts_needed(swr_handle h, int P, int tt) {
+  const int nT = (int)h->n_T;
   int need = (nT + 1 + tt - 1) / tt;
   for (int p = 2; p <= P; ++p) {
     const int S = (nT + p - 1) / p;
@@ -577,10 +579,13 @@ int32_t swr_create(const swr_desc* desc, swr_handle* out) {
       }
     }
     h->tx_tt = swr::transmit_tile_steps(h->nbt, h->te_pieces, h->te_max_send, h->te_gram_max);
+    h->tx_tt_max = h->tx_tt;
     if (h->te_max_recv > 64 || h->te_max_send > 64 || h->tx_tt == 0)
       g.te_ok = false;  // dense fallback
   }
-  if (g.te_ok) h->part_stride = parts_needed(h, h->depth);
+  // residual partials for the smallest tile, so that either tile may be used
+  if (g.te_ok) h->part_stride = parts_needed(h, h->depth, 16);
+  h->depth_run = h->depth;
   plan_layout(h);
   *out = h;
   return SWR_OK;
@@ -607,6 +612,8 @@ int32_t swr_query(swr_handle h, swr_info* info) {
   r.depth = h->depth;
   r.learned_nodes = h->n_nodes_t;
   r.factor_terms = h->factor_terms;
+  r.tx_tile = h->g.te_ok ? h->tx_tt : 0;
+  r.depth_run = h->depth_run;
   r.sum_KK_pairs = h->g.pair_toff.back();
   r.n_steps = (int32_t)h->n_T;
   r.workspace_bytes = h->lay.total;
@@ -827,8 +834,9 @@ int32_t swr_warm_start(swr_handle h, int32_t mode, const void* g_dev, void* stre
   double2* F = h->F_of(1);
   if (mode == SWR_WARM_PLAIN) {
     HIPCHECK(h, swr::launch_transmit(it, h->pairs(), h->te(), nT, h->ptr<double2>(h->bT),
-                                     full_tx(h->hist_of(0), F, nT), nullptr, h->nbt, h->te_pieces, h->te_max_recv, h->te_max_send,
-                                   h->te_gram_max, st));
+                                     full_tx(h->hist_of(0), F, nT), nullptr, h->nbt,
+                                     h->te_pieces, h->te_max_recv, h->te_max_send,
+                                     h->te_gram_max, h->tx_tt, st));
   } else if (mode == SWR_WARM_ZERO) {
     HIPCHECK(h, hipMemsetAsync(F, 0, h->bF[0].bytes, st));
   } else {
@@ -982,7 +990,7 @@ int32_t transmit_and_residual(swr_handle h, int k, const double* scale, double* 
   HIPCHECK(h, tbegin(h, st, kTTransmit));
   HIPCHECK(h, swr::launch_transmit(it, h->pairs(), h->te(), nT, h->ptr<double2>(h->bT), tx,
                                    scale, h->nbt, h->te_pieces, h->te_max_recv, h->te_max_send,
-                                   h->te_gram_max, st));
+                                   h->te_gram_max, h->tx_tt, st));
   if (h->fused_residual() && res_dev)
     HIPCHECK(h, swr::launch_res_reduce(h->parts_of(k), h->g.n_items, h->part_stride, nT, nT, 1,
                                        h->tx_tt, res_dev, st));
@@ -1029,7 +1037,7 @@ int32_t run_pipelined(swr_handle h, const swr_run_opts* o, int P, swr_run_stats*
   const int S = (nT + P - 1) / P;
   const int n_chunks = (nT + S - 1) / S;
   const bool fused = h->fused_residual();
-  if (fused && parts_needed(h, P) > h->part_stride)
+  if (fused && parts_needed(h, P, h->tx_tt) > h->part_stride)
     return fail(h, SWR_E_SIZE, "residual partials exceed their buffer");
   if (!capture && !h->ev_ready) {
     for (auto& e : h->ev) HIPCHECK(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -1094,7 +1102,7 @@ int32_t run_pipelined(swr_handle h, const swr_run_opts* o, int P, swr_run_stats*
       HIPCHECK(h, tbegin(h, st, kTTransmit));
       HIPCHECK(h, swr::launch_transmit(it, h->pairs(), h->te(), nT, h->ptr<double2>(h->bT), tx,
                                        nullptr, h->nbt, h->te_pieces, h->te_max_recv,
-                                       h->te_max_send, h->te_gram_max, st));
+                                       h->te_max_send, h->te_gram_max, h->tx_tt, st));
       HIPCHECK(h, tend(h, st));
     }
     if (res_now) {
@@ -1212,7 +1220,7 @@ int32_t swr_run(swr_handle h, const swr_run_opts* o, swr_run_stats* stats, void*
   rc = swr_warm_start(h, o->warm, o->g_dev, stream);
   if (rc) return rc;
   swr_run_stats s{};
-  const int P = o->depth <= 0 ? h->depth : std::min(o->depth, h->depth);
+  const int P = o->depth <= 0 ? h->depth_run : std::min(o->depth, h->depth);
   if (h->g.desc.mode == SWR_TDSE && P > 1) {
     const bool graph = o->graph != 0 && o->tol < 0.0 && !h->timing;
     rc = graph ? run_graph(h, o, P, &s, (hipStream_t)stream)
@@ -1463,3 +1471,60 @@ int32_t swr_status_sync(swr_handle h, void* stream) {
 }
 
 }  // extern "C"
+
+int32_t swr_autotune(swr_handle h, int32_t k_iters, double t0, swr_tuning* out, void* stream) {
+  if (!h || !out) return fail(h, SWR_E_ARG, "null argument");
+  if (k_iters < 1) return fail(h, SWR_E_ARG, "k_iters must be >= 1");
+  if (!h->assembled || !h->initial) return fail(h, SWR_E_STATE, "swr_assemble and swr_set_initial first");
+  hipStream_t st = (hipStream_t)stream;
+  const bool tdse = h->g.desc.mode == SWR_TDSE;
+  std::vector<int> depths, tiles;
+  for (int d = 1; d <= (tdse ? h->depth : 1); ++d) depths.push_back(d);
+  if (h->g.te_ok) {
+    tiles.push_back(16);
+    if (h->tx_tt_max == 32) tiles.push_back(32);
+  } else {
+    tiles.push_back(h->tx_tt);
+  }
+  hipEvent_t e0, e1;
+  HIPCHECK(h, hipEventCreate(&e0));
+  HIPCHECK(h, hipEventCreate(&e1));
+  struct Ev {
+    hipEvent_t a, b;
+    ~Ev() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+  } ev{e0, e1};
+  double best = -1.0;
+  int best_d = h->depth_run, best_t = h->tx_tt;
+  for (const int t : tiles)
+    for (const int d : depths) {
+      h->tx_tt = t;
+      swr_run_opts o{};
+      o.k_max = k_iters;
+      o.tol = -1.0;
+      o.t0 = t0;
+      o.warm = SWR_WARM_PLAIN;
+      o.depth = d;
+      swr_run_stats s{};
+      int rc = swr_run(h, &o, &s, stream);  // warm-up
+      if (rc) return rc;
+      HIPCHECK(h, hipEventRecord(e0, st));
+      rc = swr_run(h, &o, &s, stream);
+      if (rc) return rc;
+      HIPCHECK(h, hipEventRecord(e1, st));
+      HIPCHECK(h, hipEventSynchronize(e1));
+      float ms = 0.0f;
+      HIPCHECK(h, hipEventElapsedTime(&ms, e0, e1));
+      if (best < 0.0 || ms < best) {
+        best = ms;
+        best_d = d;
+        best_t = t;
+      }
+    }
+  h->depth_run = best_d;
+  h->tx_tt = best_t;
+  out->depth = best_d;
+  out->tx_tile = h->g.te_ok ? best_t : 0;
+  out->ms_per_window = best;
+  out->candidates = (int32_t)(depths.size() * tiles.size());
+  return SWR_OK;
+}

@@ -242,10 +242,11 @@ hipError_t launch_tx_pack(const Items& it, const Pairs& pr, const TEnt& te, doub
 // else the dense T.  scale (per step, may be null) multiplies the result;
 // nbt = largest tangential basis size over items (1 when D = 1); pieces =
 // largest LDS bytes of the a and X pieces an item sends; max_recv / max_send
-// = largest number of entries an item receives / sends.
+// = largest number of entries an item receives / sends; tile = steps per
+// block of the factored form (16 or 32, and its LDS must fit).
 hipError_t launch_transmit(const Items& it, const Pairs& pr, const TEnt& te, int n_steps,
                            const double2* T, const TxJobs& jobs, const double* scale, int nbt,
-                           int64_t pieces, int max_recv, int max_send, int64_t gram,
+                           int64_t pieces, int max_recv, int max_send, int64_t gram, int tile,
                            hipStream_t st);
 hipError_t launch_fill_history(const Items& it, int n_steps, const double2* c0, double2* hist,
                                hipStream_t st);

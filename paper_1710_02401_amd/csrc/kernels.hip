@@ -2621,7 +2621,7 @@ hipError_t launch_tx_pack(const Items& it, const Pairs& pr, const TEnt& te, doub
 
 hipError_t launch_transmit(const Items& it, const Pairs& pr, const TEnt& te, int n_steps,
                            const double2* T, const TxJobs& jobs, const double* scale, int nbt,
-                           int64_t pieces, int max_recv, int max_send, int64_t gram,
+                           int64_t pieces, int max_recv, int max_send, int64_t gram, int tile,
                            hipStream_t st) {
   if (jobs.n < 1 || jobs.n > kMaxJobs) return hipErrorInvalidValue;
   int span = 0;
@@ -2632,8 +2632,10 @@ hipError_t launch_transmit(const Items& it, const Pairs& pr, const TEnt& te, int
   }
   if (te.n > 0) {
     if (nbt < 1 || nbt > kSmallK) return hipErrorInvalidValue;
-    const int tt = transmit_tile_steps(nbt, pieces, max_send, gram);
-    if (tt == 0 || max_recv < 1 || max_recv > kMaxRecvEntries) return hipErrorInvalidValue;
+    const int tt = tile;
+    if ((tt != 16 && tt != 32) || tx_send_lds(tt, nbt, pieces, max_send, gram) > 63488 ||
+        max_recv < 1 || max_recv > kMaxRecvEntries)
+      return hipErrorInvalidValue;
     // register form when every tangential basis has at most 8 functions (it
     // needs no u buffer in LDS)
     const bool reg = nbt <= 8;

@@ -54,6 +54,7 @@ class swr_info(ctypes.Structure):
         ("sum_KK_pairs", ctypes.c_int64), ("n_steps", ctypes.c_int32),
         ("depth", ctypes.c_int32), ("workspace_bytes", ctypes.c_uint64),
         ("learned_nodes", ctypes.c_int32), ("factor_terms", ctypes.c_int32),
+        ("tx_tile", ctypes.c_int32), ("depth_run", ctypes.c_int32),
     ]
 
 
@@ -61,6 +62,11 @@ class swr_run_opts(ctypes.Structure):
     _fields_ = [("k_max", ctypes.c_int32), ("tol", ctypes.c_double), ("t0", ctypes.c_double),
                 ("warm", ctypes.c_int32), ("g_dev", ctypes.c_void_p), ("depth", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("graph", ctypes.c_int32)]
+
+
+class swr_tuning(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_int32), ("tx_tile", ctypes.c_int32),
+                ("ms_per_window", ctypes.c_double), ("candidates", ctypes.c_int32)]
 
 
 class swr_run_stats(ctypes.Structure):
@@ -81,7 +87,7 @@ EXPORTS = [
     "swr_get_norms", "swr_status_sync", "swr_set_field", "swr_advance_window",
     "swr_time_nodes", "swr_face_data", "swr_learned_features", "swr_learned_targets",
     "swr_learned_apply", "swr_mlp_param_count", "swr_mlp_workspace_bytes", "swr_mlp_forward",
-    "swr_mlp_loss_grad", "swr_mlp_adam",
+    "swr_mlp_loss_grad", "swr_mlp_adam", "swr_autotune",
 ]
 
 
@@ -115,6 +121,7 @@ def load_library(path=LIB_PATH):
         "swr_sweep": (i32, [vp, vp]),
         "swr_transmit": (i32, [vp, ctypes.POINTER(ctypes.c_double), vp]),
         "swr_run": (i32, [vp, ctypes.POINTER(swr_run_opts), ctypes.POINTER(swr_run_stats), vp]),
+        "swr_autotune": (i32, [vp, i32, ctypes.c_double, ctypes.POINTER(swr_tuning), vp]),
         "swr_get_history": (i32, [vp, vp, u64, vp]),
         "swr_get_forcing": (i32, [vp, vp, u64, vp]),
         "swr_get_initial": (i32, [vp, vp, u64, vp]),
@@ -384,6 +391,16 @@ class Solver:
 
     def advance_window(self):
         self._call("swr_advance_window", self._stream())
+
+    def autotune(self, k_iters=3, t0=0.0):
+        """Measure every schedule (depth, transmission tile) on this problem and
+        keep the fastest for later runs with depth 0."""
+        t = swr_tuning()
+        self._call("swr_autotune", ctypes.c_int32(k_iters), ctypes.c_double(t0), ctypes.byref(t),
+                   self._stream())
+        self._call("swr_query", ctypes.byref(self.info))
+        return dict(depth=t.depth, tx_tile=t.tx_tile, ms_per_window=t.ms_per_window,
+                    candidates=t.candidates)
 
     def factor_terms(self):
         """Series terms - 1 used by the last factorisation (-1: direct inversion)."""

@@ -402,3 +402,24 @@ def test_graph_replay_equals_eager_run(name):
         assert st_g["res"] == st_e["res"], rep
         s.set_initial(c0)
         s.run(k_max=2, tol=-1.0)  # eager work between the replays
+
+
+@pytest.mark.parametrize("name", ["tiny-2d", "c2-2e-1d"])
+def test_autotuned_schedule_changes_no_result(name):
+    """The autotuner measures every depth and transmission tile and keeps the
+    fastest; the schedule only reorders the same arithmetic, so a run under
+    it gives the untuned run's histories bit for bit."""
+    cfg = _cfg(name)
+    s0 = _solver(cfg)
+    st0 = s0.run(k_max=6, tol=-1.0)
+    h0 = _np(s0.history())
+    s1 = _solver(cfg)
+    t = s1.autotune(k_iters=2)
+    print(f"[gpu] {name}: autotune {t}", flush=True)
+    assert 1 <= t["depth"] <= s1.info.depth and t["tx_tile"] in (0, 16, 32)
+    assert t["candidates"] >= 1 and t["ms_per_window"] > 0
+    assert s1.info.depth_run == t["depth"] and s1.info.tx_tile == t["tx_tile"]
+    s1.set_initial(s0.initial())
+    st1 = s1.run(k_max=6, tol=-1.0)
+    assert np.array_equal(_np(s1.history()), h0)
+    assert np.allclose(st1["res"], st0["res"], rtol=1e-12, atol=0)
