@@ -37,11 +37,13 @@ FP64_PEAK_TFS = 78.6
 # window.  Valid only for the kernel source it was measured on.
 MEASURED_TRAFFIC = {
     # profiles/c2-2e-1d_traffic.md: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000
-    # (1 GiB copy calibration) over the first window at depth 4: 23
-    # recurrence launches, 24 transmissions, one factorisation
-    "k_cn_recur": {"kernels_sha256": "ed47789c50af18a4", "bytes_per_launch": 2.1759e9},
-    "k_tx_send+k_tx_recv": {"kernels_sha256": "ed47789c50af18a4", "bytes_per_launch": 0.4571e9},
-    "k_series_assemble": {"kernels_sha256": "ed47789c50af18a4", "bytes_per_launch": 2.4357e9},
+    # (1 GiB copy calibration) over the first window at depth 4 with the
+    # 32-step transmission tile: 23 recurrence launches, 24 transmissions,
+    # one factorisation
+    "k_cn_recur": {"kernels_sha256": "6414fab4e6691dea", "bytes_per_launch": 2.1760e9},
+    "k_tx_send+k_tx_recv": {"kernels_sha256": "6414fab4e6691dea", "bytes_per_launch": 0.4593e9,
+                            "tx_tile": 32},
+    "k_series_assemble": {"kernels_sha256": "6414fab4e6691dea", "bytes_per_launch": 2.4357e9},
 }
 
 
@@ -184,7 +186,9 @@ def main():
         r["ms_per_window"] = kern[k]["ms"]
         r["launches_per_window"] = kern[k]["launches"]
         m = MEASURED_TRAFFIC.get(r["kernel"])
-        r["traffic"] = m["bytes_per_launch"] / 1e9 if m and m["kernels_sha256"] == digest else None
+        valid = (m and m["kernels_sha256"] == digest and
+                 m.get("tx_tile", s.info.tx_tile) == s.info.tx_tile)
+        r["traffic"] = m["bytes_per_launch"] / 1e9 if valid else None
     dom = max(roofs, key=lambda k: kern[k]["ms"])
     roofline = {k: v for k, v in roofs[dom].items() if k in
                 ("kernel", "bound", "achieved", "peak", "unit", "frac", "traffic")}
