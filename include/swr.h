@@ -86,7 +86,7 @@ typedef struct swr_desc {
   int32_t face_nodes_band, face_nodes_mid; /* GL nodes per tangential panel   */
   int32_t quad_nodes;        /* GL nodes per potential quadrature panel       */
   int32_t learned_nodes;     /* time nodes M of the learned warm start, 2..64; 0 = 8 */
-  int32_t factor_mode;       /* SWR_FACTOR_AUTO or SWR_FACTOR_DIRECT (swr_factor) */
+  int32_t factor_mode;       /* SWR_FACTOR_AUTO, _DIRECT or _WIDE (swr_factor) */
 } swr_desc;
 
 typedef struct swr_handle_s* swr_handle;
@@ -108,6 +108,7 @@ typedef struct swr_info {
                                 in use (16 or 32; 0: dense transmission)     */
   int32_t depth_run;         /* depth swr_run uses for opts.depth = 0
                                 (swr_info.depth until swr_autotune)          */
+  int32_t wide;              /* 1: the wide-basis path (see swr_factor)       */
 } swr_info;
 
 /* ---- lifetime ------------------------------------------------------------*/
@@ -115,8 +116,9 @@ typedef struct swr_info {
 /* Build the decomposition, bases, face quadrature nodes, covering sets O(y)
  * and neighbour lists on the host (Section 4.1 SWR setting; Section 5
  * decomposition).  Validates the description: SWR_E_ARG for inconsistent
- * fields, SWR_E_SIZE if a basis exceeds the kernels' limits
- * (K <= 64 per subdomain in this build).  *out receives a new handle. */
+ * fields, SWR_E_SIZE if a basis exceeds the kernels' limits: K <= 64 per
+ * subdomain, or K <= 256 for one electron in one dimension in real time
+ * (the wide-basis path, see swr_factor).  *out receives a new handle. */
 int32_t swr_create(const swr_desc* desc, swr_handle* out);
 void swr_destroy(swr_handle h);
 const char* swr_last_error(swr_handle h);
@@ -166,8 +168,14 @@ int32_t swr_warm_start(swr_handle h, int32_t mode, const void* g_dev, void* stre
  * X = max over items of sum_m max |x_m| along the field axis on the item's
  * box, and the tail after K is at most rho^{K+1}/(1-rho); K is the least
  * with that bound <= 2^-53 (reported in swr_info.factor_terms).  With
- * Im mu > 0, K > 7, or SWR_FACTOR_DIRECT, every M^n is inverted. */
-enum { SWR_FACTOR_AUTO = 0, SWR_FACTOR_DIRECT = 1 };
+ * Im mu > 0, K > 7, or SWR_FACTOR_DIRECT, every M^n is inverted.
+ * Wide-basis path (one electron in one dimension, real time; taken when some
+ * K > 64, or asked for with SWR_FACTOR_WIDE): the inverses of the steps are
+ * never formed.  Per chunk the library keeps M_a^{-1} (Gauss-Jordan) and the
+ * terms (M_a^{-1} C)^k M_a^{-1}, K x K each, and swr_sweep applies the sum
+ * to each step's right-hand side; the series bound above then must hold
+ * with K <= 5, else SWR_E_SIZE (as for Im mu > 0 or SWR_FACTOR_DIRECT). */
+enum { SWR_FACTOR_AUTO = 0, SWR_FACTOR_DIRECT = 1, SWR_FACTOR_WIDE = 2 };
 int32_t swr_factor(swr_handle h, double t0, void* stream);
 
 /* One Schwarz iteration of local solves for every item (Section 4.4 step 2):

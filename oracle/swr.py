@@ -59,13 +59,33 @@ def basis_derivative(s, pts, kd):
     return out
 
 
+class _LazySystems:
+    """Local systems assembled on first use (a sampled check of a large
+    decomposition assembles only the subdomains it touches)."""
+
+    def __init__(self, dec):
+        self.dec = dec
+        self.cache = {}
+
+    def __len__(self):
+        return len(self.dec.subs)
+
+    def __iter__(self):
+        return (self[i] for i in range(len(self)))
+
+    def __getitem__(self, i):
+        if i not in self.cache:
+            self.cache[i] = assemble.LocalSystem(self.dec, self.dec.subs[i])
+        return self.cache[i]
+
+
 class Problem:
     """Decomposition plus every subdomain's local matrices."""
 
     def __init__(self, cfg):
         self.cfg = cfg
         self.dec = Decomposition(cfg)
-        self.sys = [assemble.LocalSystem(self.dec, s) for s in self.dec.subs]
+        self.sys = _LazySystems(self.dec)
         self.mu = complex(cfg["mu"][0], cfg["mu"][1])
         self.dt = float(cfg["dt"])
         self.n_T = int(cfg["n_steps"])
@@ -83,9 +103,12 @@ class Problem:
                 out.update(int(j) for j in c)
         return sorted(out)
 
+    def initial_coeff(self, i):
+        s = self.dec.subs[i]
+        return assemble.project_initial(self.dec, s, self.sys[s.lin].A).astype(np.complex128)
+
     def initial_coeffs(self):
-        return [assemble.project_initial(self.dec, s, self.sys[s.lin].A).astype(np.complex128)
-                for s in self.dec.subs]
+        return [self.initial_coeff(s.lin) for s in self.dec.subs]
 
     def times(self, t0=0.0):
         return t0 + self.dt * np.arange(self.n_T + 1)
@@ -224,9 +247,12 @@ def swr_window(prob, c0, t0=0.0, iters=None, tol=None, warm="plain", g_faces=Non
 def swr_sampled(prob, c0, targets, k, t0=0.0):
     """Iterate k (plain warm start) of the subdomains in `targets` only,
     computing just the dependency cone (neighbours of neighbours ...).
+    c0 may be a list or a mapping holding at least the cone's subdomains.
     Returns dict i -> (n_T+1, K) history."""
     E = field(prob.cfg, prob.times(t0))
-    const = constant_history(prob, c0)
+
+    def const(j):
+        return np.repeat(c0[j][None, :], prob.n_T + 1, axis=0)
     need = [set(targets)]
     for _ in range(k - 1):
         nxt = set()
@@ -239,7 +265,7 @@ def swr_sampled(prob, c0, targets, k, t0=0.0):
         cur = {}
         for i in sorted(need[it]):
             if it == 0:
-                fi = forcing(prob, i, lambda j: const[j])
+                fi = forcing(prob, i, const)
             else:
                 fi = forcing(prob, i, lambda j: prev[j])
             cur[i] = local_cn(prob.sys[i], c0[i], fi, E, prob.dt)

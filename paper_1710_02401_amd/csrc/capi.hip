@@ -49,6 +49,9 @@ constexpr int kGpuCUs = 256;    // MI355X compute units
 constexpr int kRecPerCU = 1;
 // series inverses of the window (swr_factor): at most this many terms
 constexpr int kSeriesMaxTerms = 8;
+// K^2 slots per chunk of the wide path's series: G (or the refinement
+// residual), the unrefined anchor inverse, then the terms P_0, P_1, ...
+constexpr int kWideSlots = swr::kWideTerms + 2;
 
 const char* const kShortWindow =
     "the learned warm start's time nodes are not distinct: the window has too few steps";
@@ -102,6 +105,12 @@ struct swr_handle_s {
   // P_{kSeriesMaxTerms-1}, each sum_K2 complex; the chunks' anchor fields
   Buf bSeries, bEanchor;
   std::vector<double> Ea_host;
+  // wide-basis path (D = 1, K <= kWideK): S2 = Ar + Ap, a K^2 scratch of the
+  // projection, the items by decreasing K, prefix sums of the 64 x 64 tiles
+  bool wide = false;
+  Buf bS2, bScrW, bOrder, bTileOff;
+  std::vector<int32_t> order;
+  std::vector<int64_t> tile_off;
   Buf bT, bC0, bH[kMaxSlots], bF[kMaxSlots], bRc[kMaxSlots], bMinv, bE, bResPart, bResOut, bResv, bIePart, bNus,
       bFlags;
 
@@ -362,12 +371,22 @@ void plan_layout(swr_handle h) {
     h->bRc[q] = L.add(h->sum_K * 16);
   }
   h->bOffP = L.add((NI + 1) * 8);
-  h->bMinv = L.add((size_t)h->n_mats * std::max<int64_t>(h->sum_K2, h->offp.back()) * 16);
-  if (g.desc.mode == SWR_TDSE) {
-    const int n_chunks = (int)((h->n_mats + swr::kSeriesChunk - 1) / swr::kSeriesChunk);
-    h->bSeries = L.add((size_t)n_chunks * (kSeriesMaxTerms + 1) * h->sum_K2 * 16);
-    h->bEanchor = L.add((size_t)n_chunks * 8);
+  const int n_chunks = (int)((h->n_mats + swr::kSeriesChunk - 1) / swr::kSeriesChunk);
+  if (h->wide) {
+    // no per-step inverses: per chunk G (or the refinement residual), the
+    // anchor inverse before refinement, then P_0 .. P_{kWideTerms-1}
+    h->bMinv = L.add(16);
+    h->bSeries = L.add((size_t)n_chunks * kWideSlots * h->sum_K2 * 16);
+    h->bS2 = L.add(m2);
+    h->bScrW = L.add(m2);
+    h->bOrder = L.add(NI * 4);
+    h->bTileOff = L.add((NI + 1) * 8);
+  } else {
+    h->bMinv = L.add((size_t)h->n_mats * std::max<int64_t>(h->sum_K2, h->offp.back()) * 16);
+    if (g.desc.mode == SWR_TDSE)
+      h->bSeries = L.add((size_t)n_chunks * (kSeriesMaxTerms + 1) * h->sum_K2 * 16);
   }
+  if (g.desc.mode == SWR_TDSE) h->bEanchor = L.add((size_t)n_chunks * 8);
   h->bE = L.add((h->n_T + 1) * 8);
   h->bResPart = L.add((size_t)h->n_res_tiles * NI * 8);
   h->bResOut = L.add(8);
@@ -459,8 +478,24 @@ int32_t swr_create(const swr_desc* desc, swr_handle* out) {
     return code;
   }
   Geometry& g = h->g;
-  if (g.K_max > swr::kSmallK) {
-    g_create_error = "basis size per subdomain exceeds 64 in this build";
+  const bool wide_ok =
+      g.desc.dim == 1 && g.desc.n_elec == 1 && g.desc.mode == SWR_TDSE && g.te_ok;
+  if (g.K_max > (wide_ok ? swr::kWideK : swr::kSmallK)) {
+    g_create_error = wide_ok ? "basis size per subdomain exceeds 256"
+                             : "basis size per subdomain exceeds 64 (256 for one electron in "
+                               "one dimension in real time)";
+    delete h;
+    return SWR_E_SIZE;
+  }
+  if (g.desc.factor_mode == SWR_FACTOR_WIDE && !wide_ok) {
+    g_create_error = "the wide-basis path is for one electron in one dimension in real time";
+    delete h;
+    return SWR_E_ARG;
+  }
+  h->wide = wide_ok && (g.K_max > swr::kSmallK || g.desc.factor_mode == SWR_FACTOR_WIDE);
+  if (h->wide && (g.desc.factor_mode == SWR_FACTOR_DIRECT || g.desc.mu_im > 0.0)) {
+    g_create_error = "bases above 64 take the field series: factor_mode direct and Im mu > 0 "
+                     "are not available";
     delete h;
     return SWR_E_SIZE;
   }
@@ -493,6 +528,7 @@ int32_t swr_create(const swr_desc* desc, swr_handle* out) {
     h->dipole_max = std::max(h->dipole_max, x);
   }
   h->n_res_tiles = (int)((h->n_T + 1 + 15) / 16);
+  if (h->wide) h->n_res_tiles = std::max(h->n_res_tiles, swr::tx_wide_tiles((int)h->n_T));
   h->s1off.assign((size_t)g.n_items * 4, 0);
   h->scratch_off.assign(g.n_items, 0);
   int64_t s1 = 0, scr = 0;
@@ -519,9 +555,20 @@ int32_t swr_create(const swr_desc* desc, swr_handle* out) {
   }
   h->s1_total = s1;
   h->scratch_total = scr;
-  if (g.desc.mode == SWR_TDSE) {
+  if (g.desc.mode == SWR_TDSE && !h->wide) {
     const int fill = (kRecPerCU * kGpuCUs + g.n_items - 1) / g.n_items;
     h->depth = std::max(1, std::min({kMaxDepth, fill, (int)h->n_T}));
+  }
+  if (h->wide) {
+    h->order.resize(g.n_items);
+    for (int q = 0; q < g.n_items; ++q) h->order[q] = q;
+    std::stable_sort(h->order.begin(), h->order.end(),
+                     [&](int a, int b) { return g.K[a] > g.K[b]; });
+    h->tile_off.assign(g.n_items + 1, 0);
+    for (int q = 0; q < g.n_items; ++q) {
+      const int64_t t = (g.K[q] + 63) / 64;
+      h->tile_off[q + 1] = h->tile_off[q] + t * t;
+    }
   }
   // pipelined: depth iterates in flight, the one they read, and the one
   // before it (the residual of iterate k-1 reads iterate k-2)
@@ -580,11 +627,13 @@ int32_t swr_create(const swr_desc* desc, swr_handle* out) {
     }
     h->tx_tt = swr::transmit_tile_steps(h->nbt, h->te_pieces, h->te_max_send, h->te_gram_max);
     h->tx_tt_max = h->tx_tt;
-    if (h->te_max_recv > 64 || h->te_max_send > 64 || h->tx_tt == 0)
+    if (h->wide)
+      h->tx_tt = 16;  // the wide path has a transmission of its own
+    else if (h->te_max_recv > 64 || h->te_max_send > 64 || h->tx_tt == 0)
       g.te_ok = false;  // dense fallback
   }
   // residual partials for the smallest tile, so that either tile may be used
-  if (g.te_ok) h->part_stride = parts_needed(h, h->depth, 16);
+  if (g.te_ok && !h->wide) h->part_stride = parts_needed(h, h->depth, 16);
   h->depth_run = h->depth;
   plan_layout(h);
   *out = h;
@@ -612,7 +661,8 @@ int32_t swr_query(swr_handle h, swr_info* info) {
   r.depth = h->depth;
   r.learned_nodes = h->n_nodes_t;
   r.factor_terms = h->factor_terms;
-  r.tx_tile = h->g.te_ok ? h->tx_tt : 0;
+  r.tx_tile = h->g.te_ok && !h->wide ? h->tx_tt : 0;
+  r.wide = h->wide ? 1 : 0;
   r.depth_run = h->depth_run;
   r.sum_KK_pairs = h->g.pair_toff.back();
   r.n_steps = (int32_t)h->n_T;
@@ -745,6 +795,10 @@ int32_t swr_assemble(swr_handle h, void* stream) {
   HIPCHECK(h, upload(h, h->bS1Off, h->s1off, st));
   HIPCHECK(h, upload(h, h->bScrOff, h->scratch_off, st));
   HIPCHECK(h, upload(h, h->bCenter, cen4, st));
+  if (h->wide) {
+    HIPCHECK(h, upload(h, h->bOrder, h->order, st));
+    HIPCHECK(h, upload(h, h->bTileOff, h->tile_off, st));
+  }
   HIPCHECK(h, hipMemsetAsync(h->ptr<int>(h->bFlags), 0, 8, st));
 
   const swr::Items it = h->items();
@@ -756,15 +810,21 @@ int32_t swr_assemble(swr_handle h, void* stream) {
                                    h->ptr<int64_t>(h->bS1Off), g.K_max, st));
   swr::Potential pot{g.desc.n_nuc, h->ptr<double>(h->bPos), h->ptr<double>(h->bCharge),
                      g.desc.eps_en, g.desc.eps_ee};
-  HIPCHECK(h, swr::launch_potential(it, pot, h->ptr<double>(h->bS1), h->ptr<int64_t>(h->bS1Off),
-                                    h->ptr<double>(h->bV), h->ptr<double>(h->bScr),
-                                    h->ptr<int64_t>(h->bScrOff), st));
+  if (h->wide)
+    HIPCHECK(h, swr::launch_potential_wide(it, pot, h->ptr<double>(h->bV), g.K_max, st));
+  else
+    HIPCHECK(h, swr::launch_potential(it, pot, h->ptr<double>(h->bS1),
+                                      h->ptr<int64_t>(h->bS1Off), h->ptr<double>(h->bV),
+                                      h->ptr<double>(h->bScr), h->ptr<int64_t>(h->bScrOff), st));
   const double dt = g.desc.dt;
   const int tise = g.desc.mode == SWR_TISE;
   HIPCHECK(h, swr::launch_cn_matrices(h->sum_K2, h->ptr<double>(h->bA), h->ptr<double>(h->bKin),
                                       h->ptr<double>(h->bV), h->ptr<double>(h->bB), 0.5 * dt,
                                       g.desc.mu_re, g.desc.mu_im, h->ptr<double>(h->bAr),
                                       h->ptr<double>(h->bAp), h->ptr<double>(h->bHr), tise, dt, st));
+  if (h->wide)
+    HIPCHECK(h, swr::launch_add_wide(h->sum_K2, h->ptr<double>(h->bAr), h->ptr<double>(h->bAp),
+                                     h->ptr<double>(h->bS2), st));
   if (g.te_ok) {
     const swr::TEnt te = h->te();
     HIPCHECK(h, swr::launch_transfer_tensor(it, nd, pr, te, g.desc.mu_re, g.desc.mu_im,
@@ -792,6 +852,10 @@ int32_t swr_set_initial(swr_handle h, const void* c0_dev, void* stream) {
   if (c0_dev) {
     HIPCHECK(h, hipMemcpyAsync(h->ptr<double2>(h->bC0), c0_dev, h->sum_K * 16,
                                hipMemcpyDeviceToDevice, st));
+  } else if (h->wide) {
+    HIPCHECK(h, swr::launch_project_wide(it, h->ptr<double>(h->bA), h->g.desc.init_alpha,
+                                         h->ptr<double>(h->bCenter), h->ptr<double>(h->bScrW),
+                                         h->ptr<double2>(h->bC0), h->ptr<int>(h->bFlags), st));
   } else {
     HIPCHECK(h, swr::launch_project(it, h->ptr<double>(h->bA), h->g.desc.init_alpha,
                                     h->ptr<double>(h->bCenter), h->ptr<double2>(h->bC0),
@@ -832,7 +896,10 @@ int32_t swr_warm_start(swr_handle h, int32_t mode, const void* g_dev, void* stre
   // iterate 0 (residual reference) = the window's initial state held constant
   HIPCHECK(h, swr::launch_fill_history(it, nT, h->ptr<double2>(h->bC0), h->hist_of(0), st));
   double2* F = h->F_of(1);
-  if (mode == SWR_WARM_PLAIN) {
+  if (mode == SWR_WARM_PLAIN && h->wide) {
+    HIPCHECK(h, swr::launch_tx_wide(it, h->pairs(), h->te(), nT, h->hist_of(0), F, nullptr,
+                                    nullptr, h->g.desc.dt, st));
+  } else if (mode == SWR_WARM_PLAIN) {
     HIPCHECK(h, swr::launch_transmit(it, h->pairs(), h->te(), nT, h->ptr<double2>(h->bT),
                                      full_tx(h->hist_of(0), F, nT), nullptr, h->nbt,
                                      h->te_pieces, h->te_max_recv, h->te_max_send,
@@ -862,7 +929,8 @@ int32_t swr_factor(swr_handle h, double t0, void* stream) {
   // series around the midpoint of each chunk's field range (TDSE)
   int terms = 0;
   const int n_chunks = (int)((h->n_mats + swr::kSeriesChunk - 1) / swr::kSeriesChunk);
-  if (!tise && h->g.desc.factor_mode == SWR_FACTOR_AUTO && h->g.desc.mu_im <= 0.0) {
+  const int max_terms = h->wide ? swr::kWideTerms : kSeriesMaxTerms;
+  if (!tise && (h->g.desc.factor_mode == SWR_FACTOR_AUTO || h->wide) && h->g.desc.mu_im <= 0.0) {
     h->Ea_host.assign(n_chunks, 0.0);
     double half = 0.0;
     for (int c = 0; c < n_chunks; ++c) {
@@ -880,15 +948,43 @@ int32_t swr_factor(swr_handle h, double t0, void* stream) {
     if (rho < 0.5) {
       // least K with rho^{K+1} / (1 - rho) <= 2^-53
       terms = 1;
-      for (double tail = rho / (1.0 - rho); tail > 0x1p-53 && terms <= kSeriesMaxTerms; ++terms)
+      for (double tail = rho / (1.0 - rho); tail > 0x1p-53 && terms <= max_terms; ++terms)
         tail *= rho;
-      if (terms > kSeriesMaxTerms) terms = 0;
+      if (terms > max_terms) terms = 0;
     }
   }
   const swr::Items it = h->items();
+  if (h->wide && terms == 0)
+    return fail(h, SWR_E_SIZE, "the field varies too much within a chunk for the wide-basis "
+                               "series (more than 6 terms)");
   if (terms > 0) HIPCHECK(h, upload(h, h->bEanchor, h->Ea_host, st));
   HIPCHECK(h, tbegin(h, st, kTFactor));
-  if (terms > 0) {
+  if (h->wide) {
+    // per chunk: X = M_c^{-1} (Gauss-Jordan), R = I - M_c X (compensated),
+    // P_0 = X + X R, G = i tau P_0 Q, P_k = G P_{k-1}
+    const int64_t cstride = (int64_t)kWideSlots * h->sum_K2;
+    double2* G = h->ptr<double2>(h->bSeries);
+    double2* X = G + h->sum_K2;
+    double2* P = G + 2 * h->sum_K2;
+    const int64_t nt = h->tile_off.back();
+    const int64_t* toff = h->ptr<int64_t>(h->bTileOff);
+    const double* Ea = h->ptr<double>(h->bEanchor);
+    HIPCHECK(h, swr::launch_invert_wide(it, n_chunks, h->ptr<double>(h->bAr),
+                                        h->ptr<double>(h->bHr), h->ptr<double>(h->bQ), Ea, tau, X,
+                                        cstride, h->ptr<int>(h->bFlags), st));
+    HIPCHECK(h, swr::launch_residual_wide(it, toff, nt, n_chunks, h->ptr<double>(h->bAr),
+                                          h->ptr<double>(h->bHr), h->ptr<double>(h->bQ), Ea, tau,
+                                          X, cstride, G, st));
+    HIPCHECK(h, swr::launch_gemm_wide(it, toff, nt, n_chunks, X, G, nullptr,
+                                      make_double2(1.0, 0.0), X, cstride, P, st));
+    if (terms > 1)
+      HIPCHECK(h, swr::launch_gemm_wide(it, toff, nt, n_chunks, P, nullptr, h->ptr<double>(h->bQ),
+                                        make_double2(0.0, tau), nullptr, cstride, G, st));
+    for (int k = 1; k < terms; ++k)
+      HIPCHECK(h, swr::launch_gemm_wide(it, toff, nt, n_chunks, G, P + (k - 1) * h->sum_K2,
+                                        nullptr, make_double2(1.0, 0.0), nullptr, cstride,
+                                        P + k * h->sum_K2, st));
+  } else if (terms > 0) {
     const int64_t cstride = (int64_t)(kSeriesMaxTerms + 1) * h->sum_K2;
     double2* G = h->ptr<double2>(h->bSeries);
     double2* P = G + h->sum_K2;  // chunk c: P_k at P + c cstride + k sum_K2
@@ -934,7 +1030,17 @@ int32_t swr_sweep(swr_handle h, void* stream) {
   const int k = h->k + 1;
   const int nT = (int)h->n_T;
   double2* hist = h->hist_of(k);
-  if (h->g.desc.mode == SWR_TDSE) {
+  if (h->wide) {
+    const double2* P = h->ptr<double2>(h->bSeries) + 2 * h->sum_K2;
+    HIPCHECK(h, tbegin(h, st, kTRecur));
+    HIPCHECK(h, swr::launch_cn_recur_wide(
+                    it, h->ptr<int32_t>(h->bOrder), nT, h->ptr<double>(h->bS2),
+                    h->ptr<double>(h->bAr), h->ptr<double>(h->bHr), h->ptr<double>(h->bQ),
+                    h->ptr<double>(h->bE), h->ptr<double>(h->bEanchor), 0.5 * h->g.desc.dt, P,
+                    h->factor_terms + 1, h->sum_K2, (int64_t)kWideSlots * h->sum_K2,
+                    h->ptr<double2>(h->bC0), hist, h->F_of(k), h->ptr<int>(h->bFlags), st));
+    HIPCHECK(h, tend(h, st));
+  } else if (h->g.desc.mode == SWR_TDSE) {
     swr::RecJobs jobs{};
     jobs.n = 1;
     jobs.hist[0] = hist;
@@ -974,6 +1080,19 @@ int32_t transmit_and_residual(swr_handle h, int k, const double* scale, double* 
                               hipStream_t st) {
   const swr::Items it = h->items();
   const int nT = (int)h->n_T;
+  if (h->wide) {
+    double* part = res_dev ? h->ptr<double>(h->bResPart) : nullptr;
+    HIPCHECK(h, tbegin(h, st, kTTransmit));
+    HIPCHECK(h, swr::launch_tx_wide(it, h->pairs(), h->te(), nT, h->hist_of(k), h->F_of(k + 1),
+                                    res_dev ? h->hist_of(k - 1) : nullptr, part,
+                                    h->g.desc.dt, st));
+    if (res_dev)
+      HIPCHECK(h, swr::launch_sum_sqrt(part, (int64_t)it.n_items * swr::tx_wide_tiles(nT),
+                                       res_dev, st));
+    HIPCHECK(h, tend(h, st));
+    (void)scale;
+    return SWR_OK;
+  }
   swr::TxJobs tx = full_tx(h->hist_of(k), h->F_of(k + 1), nT);
   tx.dt = h->g.desc.dt;
   tx.part_stride = h->part_stride;
@@ -1357,6 +1476,7 @@ int32_t swr_local_eigen(swr_handle h, void* lambda_dev, void* vectors_dev, void*
   if (!h || !lambda_dev || !vectors_dev) return fail(h, SWR_E_ARG, "null argument");
   if (!h->assembled) return fail(h, SWR_E_STATE, "swr_assemble first");
   if (h->g.desc.mu_im != 0.0) return fail(h, SWR_E_ARG, "local eigenproblems need a real mu");
+  if (h->g.K_max > swr::kSmallK) return fail(h, SWR_E_SIZE, "local eigenproblems need K <= 64");
   hipStream_t st = (hipStream_t)stream;
   HIPCHECK(h, swr::launch_geneig(h->items(), h->ptr<double>(h->bA), h->ptr<double>(h->bHr),
                                  (double*)lambda_dev, (double*)vectors_dev, h->ptr<int>(h->bFlags),
@@ -1480,7 +1600,7 @@ int32_t swr_autotune(swr_handle h, int32_t k_iters, double t0, swr_tuning* out, 
   const bool tdse = h->g.desc.mode == SWR_TDSE;
   std::vector<int> depths, tiles;
   for (int d = 1; d <= (tdse ? h->depth : 1); ++d) depths.push_back(d);
-  if (h->g.te_ok) {
+  if (h->g.te_ok && !h->wide) {
     tiles.push_back(16);
     if (h->tx_tt_max == 32) tiles.push_back(32);
   } else {
@@ -1523,7 +1643,7 @@ int32_t swr_autotune(swr_handle h, int32_t k_iters, double t0, swr_tuning* out, 
   h->depth_run = best_d;
   h->tx_tt = best_t;
   out->depth = best_d;
-  out->tx_tile = h->g.te_ok ? best_t : 0;
+  out->tx_tile = h->g.te_ok && !h->wide ? best_t : 0;
   out->ms_per_window = best;
   out->candidates = (int32_t)(depths.size() * tiles.size());
   return SWR_OK;

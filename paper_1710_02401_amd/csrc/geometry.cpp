@@ -84,7 +84,8 @@ std::string build_geometry(const swr_desc& d, Geometry* g, int* code) {
   if (d.face_nodes_band < 1 || d.face_nodes_mid < 1 || d.quad_nodes < 1) return "node counts must be >= 1";
   if (d.learned_nodes != 0 && (d.learned_nodes < 2 || d.learned_nodes > 64))
     return "learned_nodes must be 0 (default 8) or in 2..64";
-  if (d.factor_mode != 0 && d.factor_mode != 1) return "factor_mode must be 0 (auto) or 1 (direct)";
+  if (d.factor_mode < 0 || d.factor_mode > 2)
+    return "factor_mode must be 0 (auto), 1 (direct) or 2 (wide)";
   if (!(d.eps_en > 0.0) || !(d.eps_ee > 0.0)) return "soft-Coulomb eps must be > 0";
   if (!(d.width > 0.0) && !(d.width_ratio > 0.0)) return "width or width_ratio must be > 0";
   if (d.basis_extend < 0) return "basis_extend must be >= 0";

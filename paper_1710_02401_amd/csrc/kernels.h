@@ -8,6 +8,8 @@
 namespace swr {
 
 constexpr int kSmallK = 64;      // in-LDS kernels handle K <= kSmallK
+constexpr int kWideK = 256;      // wide-basis path (one dimension): K <= kWideK
+constexpr int kWideTerms = 6;    // series terms the wide recurrence applies at most
 constexpr int kBlock = 256;      // threads per block of the batched kernels
 
 // Per-item tables (device pointers), passed by value to kernels.
@@ -282,6 +284,52 @@ hipError_t launch_learned_apply(const Items& it, const Nodes& nd, const float* y
                                 const double* scale, const double2* g0, const double* lag,
                                 int n_nodes_t, int n_out, int n_steps, double2* g_all,
                                 hipStream_t st);
+// ---- wide-basis path (D = 1, K <= kWideK; wide.hip) ----
+// One-electron soft-Coulomb matrix of every item, written whole.
+hipError_t launch_potential_wide(const Items& it, const Potential& pot, double* V, int K_max,
+                                 hipStream_t st);
+// S2 = Ar + Ap over n entries.
+hipError_t launch_add_wide(int64_t n, const double* Ar, const double* Ap, double* S2,
+                           hipStream_t st);
+// Projection of the Cauchy data; scr: scratch of sum K^2 doubles.
+hipError_t launch_project_wide(const Items& it, const double* A, double init_alpha,
+                               const double* center, double* scr, double2* c0, int* flags,
+                               hipStream_t st);
+// Anchor inverses (M_c at field Eanchor[c])^{-1} of every item and chunk,
+// K x K row-major at X + c cstride + the item's K^2 offset.
+hipError_t launch_invert_wide(const Items& it, int n_chunks, const double* Ar, const double* Hr,
+                              const double* Q, const double* Eanchor, double tau, double2* X,
+                              int64_t cstride, int* flags, hipStream_t st);
+// out = scale L R + add per item and chunk (layout as above; R = Rc complex
+// and chunk-strided when not null, else Rr real; add may be null or L); out
+// must not alias L or R.  toff: prefix sums of ceil(K/64)^2 over items,
+// n_tiles its last entry.
+hipError_t launch_gemm_wide(const Items& it, const int64_t* toff, int64_t n_tiles, int n_chunks,
+                            const double2* L, const double2* Rc, const double* Rr,
+                            double2 scale, const double2* add, int64_t cstride, double2* out,
+                            hipStream_t st);
+// R = I - M_c X per item and chunk (M_c at field Eanchor[c]; layout as
+// above), exact products and double-double sums; R must not alias X.
+hipError_t launch_residual_wide(const Items& it, const int64_t* toff, int64_t n_tiles,
+                                int n_chunks, const double* Ar, const double* Hr, const double* Q,
+                                const double* Eanchor, double tau, const double2* X,
+                                int64_t cstride, double2* R, hipStream_t st);
+// Whole-window recurrence of one iterate with the series applied per step:
+// P_k of chunk c at P + c cstride + k stride (1 <= terms <= kWideTerms);
+// order: the items by decreasing K (the launch order of the blocks).
+hipError_t launch_cn_recur_wide(const Items& it, const int32_t* order, int n_steps,
+                                const double* S2, const double* Ar, const double* Hr,
+                                const double* Q, const double* Efield, const double* Eanchor,
+                                double tau, const double2* P, int terms, int64_t stride,
+                                int64_t cstride, const double2* c0, double2* hist,
+                                const double2* F, int* flags, hipStream_t st);
+// Robin data of the whole window from src into dst; with prev, one residual
+// partial per (item, step tile) at part[item * tx_wide_tiles(n_steps) + tile].
+int tx_wide_tiles(int n_steps);
+hipError_t launch_tx_wide(const Items& it, const Pairs& pr, const TEnt& te, int n_steps,
+                          const double2* src, double2* dst, const double2* prev, double* part,
+                          double dt, hipStream_t st);
+
 hipError_t launch_last_step(const Items& it, int n_steps, const double2* hist, double2* c0,
                             hipStream_t st);
 

@@ -1,0 +1,644 @@
+// Wide-basis path of the SWR hot path (gfx950): one space dimension, up to
+// kWideK Gaussians per subdomain, uneven sizes, many geometries in one batch.
+//
+// The window's per-step inverses do not fit in memory at these sizes (a
+// 256-Gaussian subdomain's inverse is 1 MB per step), so the Crank-Nicolson
+// recurrence applies the field series of the inverse inside each step.  With
+// M^{n+1} = M_c + i tau (E_{n+1} - E_c) Q around the anchor field E_c of the
+// step's chunk and P_0 = M_c^{-1},
+//   (M^{n+1})^{-1} = sum_k (E_c - E_{n+1})^k P_k,   P_k = (i tau P_0 Q)^k P_0,
+// and the P_k of every chunk are formed once per window: the anchor inverse
+// by Gauss-Jordan (k_invert_wide), the terms by batched complex products
+// (k_gemm_wide).  All matrices here are K x K row-major at the item's K^2
+// offset; they are symmetric, so row m read at columns r = 0..K-1 is column
+// m, which is what makes the per-row accesses below coalesced.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "devmath.h"
+#include "kernels.h"
+
+namespace swr {
+namespace {
+
+constexpr int kWideThreads = 256;  // threads per block of the wide kernels
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Soft-Coulomb potential of one electron in one dimension (eq. pseudo):
+// V[a][b] = sum_q w_q u(x_q) phi_a(x_q) phi_b(x_q) with
+// u(x) = -sum_A Z_A / sqrt((x - X_A)^2 + eps^2) over the item's composite
+// Gauss-Legendre nodes.  phi_a phi_b = exp(-delta ((x-a)^2 + (x-b)^2)); nodes
+// where that exponent exceeds 746 contribute an exact zero and are skipped.
+// One thread per entry, grid (entry blocks, item).
+__global__ void k_potential_wide(Items it, Potential pot, double* V) {
+  const int s = blockIdx.y;
+  const int K = it.K[s];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= K * K) return;
+  const int a = e / K, b = e - a * K;
+  const int geom = s / it.n_sub;
+  const double d = it.delta[4 * s];
+  const double* al = it.alpha + it.aoff[4 * s];
+  const double* qx = it.qx + it.qoff[4 * s];
+  const double* qw = it.qw + it.qoff[4 * s];
+  const int nq = it.qn[4 * s];
+  const double ca = al[a], cb = al[b];
+  const double e2 = pot.eps_en * pot.eps_en;
+  double acc = 0.0;
+  for (int q = 0; q < nq; ++q) {
+    const double x = qx[q];
+    const double z = d * ((x - ca) * (x - ca) + (x - cb) * (x - cb));
+    if (z > 746.0) continue;
+    double u = 0.0;
+    for (int A = 0; A < pot.n_nuc; ++A) {
+      const double r = x - pot.pos[(geom * pot.n_nuc + A) * it.dim];
+      u -= pot.charge[A] / sqrt(r * r + e2);
+    }
+    acc += qw[q] * u * exp(-z);
+  }
+  V[it.off2[s] + e] = acc;
+}
+
+// S2 = Ar + Ap (the real matrix of the explicit half step's identity).
+__global__ void k_add_wide(int64_t n, const double* Ar, const double* Ap, double* S2) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) S2[e] = Ar[e] + Ap[e];
+}
+
+// ---------------------------------------------------------------------------
+// Projection of the Gaussian Cauchy data (Section 4.4 step 1): c~_l =
+// <phi_0, v_l>_{Omega_i}, then A c = c~ by elimination without pivoting (A is
+// symmetric positive definite) on a copy of A in scr (the item's K^2 block),
+// then back substitution by columns.  One block per item.
+__global__ void __launch_bounds__(kWideThreads) k_project_wide(Items it, const double* A,
+                                                               double init_alpha,
+                                                               const double* center, double* scr,
+                                                               double2* c0, int* flags) {
+  const int s = blockIdx.x;
+  const int K = it.K[s];
+  __shared__ double b[kWideK];
+  double* a = scr + it.off2[s];
+  for (int e = threadIdx.x; e < K * K; e += blockDim.x) a[e] = A[it.off2[s] + e];
+  const double norm = pow(2.0 * init_alpha / M_PI, 0.25);
+  for (int l = threadIdx.x; l < K; l += blockDim.x) {
+    const double al = it.alpha[it.aoff[4 * s] + l];
+    b[l] = norm * pair_overlap(al, it.delta[4 * s], center[0], init_alpha, it.lo[4 * s],
+                               it.hi[4 * s]);
+  }
+  __syncthreads();
+  for (int p = 0; p < K; ++p) {
+    const double piv = a[p * K + p];
+    if (threadIdx.x == 0 && !(fabs(piv) > 0.0)) atomicOr(flags, kFlagPivot);
+    const int w = K - p - 1;
+    // rows below the pivot: neither row p nor column p is written here
+    for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
+      const int r = p + 1 + e / w, c = p + 1 + e % w;
+      a[r * K + c] -= a[r * K + p] / piv * a[p * K + c];
+    }
+    for (int r = p + 1 + threadIdx.x; r < K; r += blockDim.x) b[r] -= a[r * K + p] / piv * b[p];
+    __syncthreads();
+  }
+  for (int p = K - 1; p >= 0; --p) {
+    const double x = b[p] / a[p * K + p];
+    __syncthreads();  // every thread has read b[p]
+    for (int r = threadIdx.x; r < p; r += blockDim.x) b[r] -= a[r * K + p] * x;
+    if (threadIdx.x == 0) b[p] = x;
+    __syncthreads();
+  }
+  for (int l = threadIdx.x; l < K; l += blockDim.x) {
+    c0[it.off1[s] + l] = make_double2(b[l], 0.0);
+    if (!isfinite(b[l])) atomicOr(flags, kFlagNaN);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Anchor inverses of the field series: X = M_c^{-1}, M_c = Ar + i tau (Hr +
+// E_c Q), by Gauss-Jordan in place without pivoting (the Hermitian part of
+// M_c, Ar, is positive definite for Im mu <= 0).  One block per (item,
+// chunk); the matrix lives at X + c cstride + the item's K^2 offset.  Pivot
+// p: column p and row p go to LDS, the row is scaled by 1 / x_pp, then every
+// entry is updated; wave w takes rows w, w + 4, ..., lanes the columns.
+__global__ void __launch_bounds__(kWideThreads) k_invert_wide(Items it, const double* Ar,
+                                                              const double* Hr, const double* Q,
+                                                              const double* Eanchor, double tau,
+                                                              double2* X, int64_t cstride,
+                                                              int* flags) {
+  const int s = blockIdx.x, c = blockIdx.y;
+  const int K = it.K[s];
+  const int64_t o2 = it.off2[s];
+  double2* x = X + (int64_t)c * cstride + o2;
+  const double E = Eanchor[c];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int e = threadIdx.x; e < K * K; e += blockDim.x)
+    x[e] = make_double2(Ar[o2 + e], tau * fma(E, Q[o2 + e], Hr[o2 + e]));
+  __shared__ double2 col[kWideK], rs[kWideK];
+  __shared__ double2 ipiv;
+  bool bad = false;
+  __syncthreads();
+  for (int p = 0; p < K; ++p) {
+    for (int i = threadIdx.x; i < K; i += blockDim.x) {
+      col[i] = x[(int64_t)i * K + p];
+      rs[i] = x[(int64_t)p * K + i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double2 pv = rs[p];
+      if (!(fabs(pv.x) > 0.0 || fabs(pv.y) > 0.0)) bad = true;
+      ipiv = crecip(pv);
+    }
+    __syncthreads();
+    const double2 ip = ipiv;
+    for (int j = threadIdx.x; j < K; j += blockDim.x) rs[j] = cmul(rs[j], ip);  // x_pj / x_pp
+    __syncthreads();
+    for (int i = w; i < K; i += 4) {
+      const double2 ci = col[i];
+      double2* xr = x + (int64_t)i * K;
+      for (int j = lane; j < K; j += 64) {
+        double2 v;
+        if (i == p)
+          v = j == p ? ip : rs[j];
+        else if (j == p)
+          v = cmul(make_double2(-ci.x, -ci.y), ip);
+        else
+          v = csub(xr[j], cmul(ci, rs[j]));
+        xr[j] = v;
+      }
+    }
+    __syncthreads();
+  }
+  if (bad) atomicOr(flags, kFlagPivot);
+  for (int e = threadIdx.x; e < K * K; e += blockDim.x)
+    if (!cfinite(x[e])) {
+      atomicOr(flags, kFlagNaN);
+      break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Batched complex products of the series terms: out = scale L R (+ add) per
+// item and chunk (chunk c of L, Rc, add and out at c cstride); R is Rc
+// (complex) when not null, else Rr (real, the same for every chunk).  64 x 64 output tiles, 256
+// threads of 4 x 4 outputs (rows ty + 16 u, columns tx + 16 v), k-slices of
+// 16 staged in LDS.  Grid (tiles over all items, chunks); toff holds the
+// prefix sums of ceil(K/64)^2, so a block finds its item by bisection.
+constexpr int kGT = 64, kGK = 16;
+template <bool kRealR>
+__global__ void __launch_bounds__(kWideThreads) k_gemm_wide(Items it, const int64_t* toff,
+                                                            const double2* L, const double2* Rc,
+                                                            const double* Rr, double2 scale,
+                                                            const double2* add, int64_t cstride,
+                                                            double2* out) {
+  const int64_t b = blockIdx.x;
+  int lo = 0, hi = it.n_items;  // toff[lo] <= b < toff[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (toff[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  const int s = lo;
+  const int K = it.K[s];
+  const int T = (K + kGT - 1) / kGT;
+  const int tile = (int)(b - toff[s]);
+  const int r0 = (tile / T) * kGT, q0 = (tile % T) * kGT;
+  const int64_t co = (int64_t)blockIdx.y * cstride + it.off2[s];
+  const double2* l = L + co;
+  const double2* rc = kRealR ? nullptr : Rc + co;
+  const double* rr = kRealR ? Rr + it.off2[s] : nullptr;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  __shared__ double2 Ls[kGT][kGK + 1];
+  __shared__ double2 Rs[kGK][kGT];
+  double2 acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = make_double2(0.0, 0.0);
+  for (int k0 = 0; k0 < K; k0 += kGK) {
+    // L slice: 64 rows x 16 columns; R slice: 16 rows x 64 columns
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = threadIdx.x + q * kWideThreads;
+      const int lr = e >> 4, lk = e & 15;
+      const int gr = r0 + lr, gk = k0 + lk;
+      Ls[lr][lk] = (gr < K && gk < K) ? l[(int64_t)gr * K + gk] : make_double2(0.0, 0.0);
+      const int rk = e >> 6, rq = e & 63;
+      const int gk2 = k0 + rk, gq = q0 + rq;
+      const bool in = gk2 < K && gq < K;
+      if (kRealR)
+        Rs[rk][rq] = make_double2(in ? rr[(int64_t)gk2 * K + gq] : 0.0, 0.0);
+      else
+        Rs[rk][rq] = in ? rc[(int64_t)gk2 * K + gq] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < kGK; ++kk) {
+      double2 av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) av[u] = Ls[ty + 16 * u][kk];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) bv[v] = Rs[kk][tx + 16 * v];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          if (kRealR) {
+            acc[u][v].x = fma(av[u].x, bv[v].x, acc[u][v].x);
+            acc[u][v].y = fma(av[u].y, bv[v].x, acc[u][v].y);
+          } else {
+            acc[u][v] = cfma(av[u], bv[v], acc[u][v]);
+          }
+        }
+    }
+    __syncthreads();
+  }
+  double2* o = out + co;
+  const double2* ad = add ? add + co : nullptr;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int gr = r0 + ty + 16 * u, gq = q0 + tx + 16 * v;
+      if (gr < K && gq < K) {
+        const int64_t e = (int64_t)gr * K + gq;
+        const double2 y = cmul(scale, acc[u][v]);
+        o[e] = ad ? cadd(y, ad[e]) : y;
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Residual of the anchor inverses, R = I - M_c X per item and chunk (M_c as
+// in k_invert_wide, X and R chunk-strided as there), with every product
+// exact (two-product by fma) and the sums in double-double (Ogita, Rump and
+// Oishi's Dot2): R is then accurate to a few units of its own size, so one
+// correction X + X R removes the inversion's error to first order.  Tiles
+// as in k_gemm_wide.
+__global__ void __launch_bounds__(kWideThreads) k_residual_wide(Items it, const int64_t* toff,
+                                                                const double* Ar, const double* Hr,
+                                                                const double* Q,
+                                                                const double* Eanchor, double tau,
+                                                                const double2* X, int64_t cstride,
+                                                                double2* R) {
+  const int64_t b = blockIdx.x;
+  int lo = 0, hi = it.n_items;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (toff[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  const int s = lo;
+  const int K = it.K[s];
+  const int T = (K + kGT - 1) / kGT;
+  const int tile = (int)(b - toff[s]);
+  const int r0 = (tile / T) * kGT, q0 = (tile % T) * kGT;
+  const int64_t o2 = it.off2[s];
+  const int64_t co = (int64_t)blockIdx.y * cstride + o2;
+  const double E = Eanchor[blockIdx.y];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  __shared__ double2 Ms[kGT][kGK + 1];
+  __shared__ double2 Xs[kGK][kGT];
+  Dot2 re[4][4], im[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      re[u][v] = Dot2{(r0 + ty + 16 * u == q0 + tx + 16 * v) ? 1.0 : 0.0, 0.0};
+      im[u][v] = Dot2{0.0, 0.0};
+    }
+  for (int k0 = 0; k0 < K; k0 += kGK) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = threadIdx.x + q * kWideThreads;
+      const int lr = e >> 4, lk = e & 15;
+      const int gr = r0 + lr, gk = k0 + lk;
+      if (gr < K && gk < K) {
+        const int64_t m = o2 + (int64_t)gr * K + gk;
+        Ms[lr][lk] = make_double2(Ar[m], tau * fma(E, Q[m], Hr[m]));
+      } else {
+        Ms[lr][lk] = make_double2(0.0, 0.0);
+      }
+      const int rk = e >> 6, rq = e & 63;
+      const int gk2 = k0 + rk, gq = q0 + rq;
+      Xs[rk][rq] = (gk2 < K && gq < K) ? X[co + (int64_t)gk2 * K + gq] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int kk = 0; kk < kGK; ++kk) {
+      double2 mv[4], xv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) mv[u] = Ms[ty + 16 * u][kk];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) xv[v] = Xs[kk][tx + 16 * v];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          // subtract (m.x + i m.y)(x.x + i x.y)
+          dot2_acc(re[u][v], -mv[u].x, xv[v].x);
+          dot2_acc(re[u][v], mv[u].y, xv[v].y);
+          dot2_acc(im[u][v], -mv[u].x, xv[v].y);
+          dot2_acc(im[u][v], -mv[u].y, xv[v].x);
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int gr = r0 + ty + 16 * u, gq = q0 + tx + 16 * v;
+      if (gr < K && gq < K)
+        R[co + (int64_t)gr * K + gq] =
+            make_double2(re[u][v].s + re[u][v].c, im[u][v].s + im[u][v].c);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Crank-Nicolson recurrence of the wide path (Section 4.4 step 2), the whole
+// window of one Schwarz iterate, one block per item (items in the order
+// given, largest first).  As in the narrow path, M^n c^n is the previous
+// step's right-hand side, so
+//   rhs^n   = S2 c^n - rhs^{n-1} + (i tau / 2)(f^n + f^{n+1}),  S2 = Ar + Ap,
+//   c^{n+1} = sum_k d^k (P_k rhs^n),  d = E_c - E_{n+1},
+// with rhs^{-1} = M^0 c^0 formed from the matrices.  Thread t owns row
+// r = t mod K and the columns m = part, part + np, ... (part = t / K,
+// np = 256 / K parts; threads with part >= np only join the barriers); the
+// parts' sums meet in LDS.
+__global__ void __launch_bounds__(kWideThreads) k_cn_recur_wide(
+    Items it, const int32_t* order, int n_steps, const double* S2, const double* Ar,
+    const double* Hr, const double* Q, const double* Eall, const double* Eanchor, double tau,
+    const double2* P, int terms, int64_t stride, int64_t cstride, const double2* c0,
+    double2* hist, const double2* F, int* flags) {
+  const int s = order[blockIdx.x];
+  const int K = it.K[s];
+  const int np = kWideThreads / K;
+  const int t = threadIdx.x;
+  const int part = t / K, r = t - part * K;
+  const bool act = part < np;
+  const int64_t o2 = it.off2[s];
+  const int64_t hb = (int64_t)(n_steps + 1) * it.off1[s];
+  __shared__ double2 sv[kWideK];        // c^n
+  __shared__ double2 sr[kWideK];        // rhs^n
+  __shared__ double2 sp[kWideThreads];  // partial sums, [part * K + r]
+  if (t < K) {
+    const double2 v = c0[it.off1[s] + t];
+    sv[t] = v;
+    hist[hb + t] = v;
+  }
+  __syncthreads();
+  if (act) {
+    const double E = Eall[0];
+    double ax = 0.0, ay = 0.0, hx = 0.0, hy = 0.0;
+    for (int m = part; m < K; m += np) {
+      const int64_t e = o2 + (int64_t)m * K + r;
+      const double a = Ar[e], h = fma(E, Q[e], Hr[e]);
+      const double2 cm = sv[m];
+      ax = fma(a, cm.x, ax);
+      ay = fma(a, cm.y, ay);
+      hx = fma(h, cm.x, hx);
+      hy = fma(h, cm.y, hy);
+    }
+    sp[t] = make_double2(fma(-tau, hy, ax), fma(tau, hx, ay));
+  }
+  __syncthreads();
+  double2 rprev = make_double2(0.0, 0.0), fprev = make_double2(0.0, 0.0);
+  if (part == 0) {
+    for (int q = 0; q < np; ++q) rprev = cadd(rprev, sp[q * K + r]);
+    fprev = F[hb + r];
+  }
+  bool bad = false;
+  for (int n = 0; n < n_steps; ++n) {
+    // rhs^n: the real product with S2
+    if (act) {
+      double ax = 0.0, ay = 0.0;
+      const double* srow = S2 + o2 + r;
+#pragma unroll 4
+      for (int m = part; m < K; m += np) {
+        const double a = srow[(int64_t)m * K];
+        const double2 cm = sv[m];
+        ax = fma(a, cm.x, ax);
+        ay = fma(a, cm.y, ay);
+      }
+      sp[t] = make_double2(ax, ay);
+    }
+    __syncthreads();
+    if (part == 0) {
+      double2 a = make_double2(0.0, 0.0);
+      for (int q = 0; q < np; ++q) a = cadd(a, sp[q * K + r]);
+      const double2 f1 = F[hb + (int64_t)(n + 1) * K + r];
+      const double2 fs = cadd(fprev, f1);
+      fprev = f1;
+      const double2 rhs = make_double2(fma(-0.5 * tau, fs.y, a.x - rprev.x),
+                                       fma(0.5 * tau, fs.x, a.y - rprev.y));
+      rprev = rhs;
+      sr[r] = rhs;
+    }
+    __syncthreads();
+    // c^{n+1}: the series terms of the step's chunk
+    if (act) {
+      const int c = n / kSeriesChunk;
+      const double d = Eanchor[c] - Eall[n + 1];
+      const double2* base = P + (int64_t)c * cstride + o2 + r;
+      double2 acc[kWideTerms];
+#pragma unroll
+      for (int j = 0; j < kWideTerms; ++j) acc[j] = make_double2(0.0, 0.0);
+#pragma unroll 2
+      for (int m = part; m < K; m += np) {
+        const double2 rm = sr[m];
+        const double2* pm = base + (int64_t)m * K;
+#pragma unroll
+        for (int j = 0; j < kWideTerms; ++j)
+          if (j < terms) acc[j] = cfma(pm[j * stride], rm, acc[j]);
+      }
+      double2 y = acc[kWideTerms - 1];
+#pragma unroll
+      for (int j = kWideTerms - 2; j >= 0; --j)
+        y = make_double2(fma(d, y.x, acc[j].x), fma(d, y.y, acc[j].y));
+      sp[t] = y;
+    }
+    __syncthreads();
+    if (part == 0) {
+      double2 v = make_double2(0.0, 0.0);
+      for (int q = 0; q < np; ++q) v = cadd(v, sp[q * K + r]);
+      sv[r] = v;
+      hist[hb + (int64_t)(n + 1) * K + r] = v;
+      bad |= !cfinite(v);
+    }
+    __syncthreads();
+  }
+  if (bad) atomicOr(flags, kFlagNaN);
+}
+
+// ---------------------------------------------------------------------------
+// Transmission and residual of the wide path (Section 4.1 eqs. (S1), (RTC),
+// multi-overlap average; Section 5 eq. (residueRT)).  In one dimension every
+// face is a single node, and the factored pieces give, for receiving item i
+// and step n,
+//   f_i^n[l] = sum over entries e of i of X_e beta_e[l] (a_e . c_{j(e)}^n)
+// (X_e = w_y / |O(y)|, beta_e = phi^i(x_F), a_e = (n.d/dx + mu) phi^j(x_F));
+// with prev, the residual partial sum_n w_n sum_F W_F |b_F . (c_i^n -
+// prev_i^n)|^2 of the block's steps (trapezoid weights w_n, face Gram pieces
+// b_F = phi^i(x_F), W_F = sum of the face's node weights) goes to
+// part[i * gridDim.y + blockIdx.y].  Grid (item, tiles of kTxWideSteps
+// steps); wave w takes the steps n0 + w, n0 + w + 4, ...
+constexpr int kTxWideSteps = 16;
+__global__ void __launch_bounds__(kWideThreads) k_tx_wide(Items it, Pairs pr, TEnt te, int n_steps,
+                                                          const double2* src, double2* dst,
+                                                          const double2* prev, double* part,
+                                                          double dt) {
+  const int i = blockIdx.x;
+  const int Ki = it.K[i];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int n0 = blockIdx.y * kTxWideSteps;
+  const int64_t hbi = (int64_t)(n_steps + 1) * it.off1[i];
+  __shared__ double red[kWideThreads / 64];
+  double racc = 0.0;
+  for (int q = w; q < kTxWideSteps; q += 4) {
+    const int n = n0 + q;
+    if (n > n_steps) break;
+    double2 fl[kWideK / 64];
+#pragma unroll
+    for (int u = 0; u < kWideK / 64; ++u) fl[u] = make_double2(0.0, 0.0);
+    for (int64_t e = te.off[i]; e < te.off[i + 1]; ++e) {
+      const int j = pr.pj[te.pair[e]];
+      const int Kj = it.K[j];
+      const double2* a = te.a + te.aoff[e];
+      const double2* cj = src + (int64_t)(n_steps + 1) * it.off1[j] + (int64_t)n * Kj;
+      double dx = 0.0, dy = 0.0;
+      for (int m = lane; m < Kj; m += 64) {
+        const double2 am = a[m], cm = cj[m];
+        dx = fma(am.x, cm.x, fma(-am.y, cm.y, dx));
+        dy = fma(am.x, cm.y, fma(am.y, cm.x, dy));
+      }
+      const double X = te.X[te.xoff[e]];
+      const double gx = X * wave_sum(dx), gy = X * wave_sum(dy);
+      const double* beta = te.beta + te.boff[e];
+#pragma unroll
+      for (int u = 0; u < kWideK / 64; ++u) {
+        const int l = lane + 64 * u;
+        if (l < Ki) {
+          const double bl = beta[l];
+          fl[u].x = fma(bl, gx, fl[u].x);
+          fl[u].y = fma(bl, gy, fl[u].y);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kWideK / 64; ++u) {
+      const int l = lane + 64 * u;
+      if (l < Ki) dst[hbi + (int64_t)n * Ki + l] = fl[u];
+    }
+    if (prev) {
+      double rs = 0.0;
+      for (int f = 0; f < 2; ++f) {
+        if (te.fnode[((int64_t)i * 8 + f) * 2 + 1] == 0) continue;
+        const double* bF = te.gram + te.gram_off[i] + (int64_t)f * (Ki + 1);
+        double dx = 0.0, dy = 0.0;
+        for (int l = lane; l < Ki; l += 64) {
+          const double2 cv = src[hbi + (int64_t)n * Ki + l], pv = prev[hbi + (int64_t)n * Ki + l];
+          dx = fma(bF[l], cv.x - pv.x, dx);
+          dy = fma(bF[l], cv.y - pv.y, dy);
+        }
+        dx = wave_sum(dx);
+        dy = wave_sum(dy);
+        rs = fma(bF[Ki], dx * dx + dy * dy, rs);
+      }
+      racc = fma((n == 0 || n == n_steps) ? 0.5 * dt : dt, rs, racc);
+    }
+  }
+  if (part) {
+    if (lane == 0) red[w] = racc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[(int64_t)i * gridDim.y + blockIdx.y] = red[0] + red[1] + red[2] + red[3];
+  }
+}
+
+}  // namespace
+
+// ---- launchers ----
+hipError_t launch_potential_wide(const Items& it, const Potential& pot, double* V, int K_max,
+                                 hipStream_t st) {
+  const unsigned bx = (unsigned)(((int64_t)K_max * K_max + kWideThreads - 1) / kWideThreads);
+  hipLaunchKernelGGL(k_potential_wide, dim3(bx, it.n_items), dim3(kWideThreads), 0, st, it, pot, V);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_wide(int64_t n, const double* Ar, const double* Ap, double* S2,
+                           hipStream_t st) {
+  const unsigned bx = (unsigned)((n + kWideThreads - 1) / kWideThreads);
+  hipLaunchKernelGGL(k_add_wide, dim3(bx), dim3(kWideThreads), 0, st, n, Ar, Ap, S2);
+  return hipGetLastError();
+}
+
+hipError_t launch_project_wide(const Items& it, const double* A, double init_alpha,
+                               const double* center, double* scr, double2* c0, int* flags,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_project_wide, dim3(it.n_items), dim3(kWideThreads), 0, st, it, A,
+                     init_alpha, center, scr, c0, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_invert_wide(const Items& it, int n_chunks, const double* Ar, const double* Hr,
+                              const double* Q, const double* Eanchor, double tau, double2* X,
+                              int64_t cstride, int* flags, hipStream_t st) {
+  hipLaunchKernelGGL(k_invert_wide, dim3(it.n_items, n_chunks), dim3(kWideThreads), 0, st, it, Ar,
+                     Hr, Q, Eanchor, tau, X, cstride, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_wide(const Items& it, const int64_t* toff, int64_t n_tiles, int n_chunks,
+                            const double2* L, const double2* Rc, const double* Rr,
+                            double2 scale, const double2* add, int64_t cstride, double2* out,
+                            hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  if (out == L || (Rc && out == Rc)) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)n_tiles, n_chunks);
+  if (Rc)
+    hipLaunchKernelGGL(k_gemm_wide<false>, grid, dim3(kWideThreads), 0, st, it, toff, L, Rc, Rr,
+                       scale, add, cstride, out);
+  else
+    hipLaunchKernelGGL(k_gemm_wide<true>, grid, dim3(kWideThreads), 0, st, it, toff, L, Rc, Rr,
+                       scale, add, cstride, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_wide(const Items& it, const int64_t* toff, int64_t n_tiles,
+                                int n_chunks, const double* Ar, const double* Hr, const double* Q,
+                                const double* Eanchor, double tau, const double2* X,
+                                int64_t cstride, double2* R, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  if (R == X) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_residual_wide, dim3((unsigned)n_tiles, n_chunks), dim3(kWideThreads), 0, st,
+                     it, toff, Ar, Hr, Q, Eanchor, tau, X, cstride, R);
+  return hipGetLastError();
+}
+
+hipError_t launch_cn_recur_wide(const Items& it, const int32_t* order, int n_steps,
+                                const double* S2, const double* Ar, const double* Hr,
+                                const double* Q, const double* Efield, const double* Eanchor,
+                                double tau, const double2* P, int terms, int64_t stride,
+                                int64_t cstride, const double2* c0, double2* hist,
+                                const double2* F, int* flags, hipStream_t st) {
+  if (terms < 1 || terms > kWideTerms) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cn_recur_wide, dim3(it.n_items), dim3(kWideThreads), 0, st, it, order,
+                     n_steps, S2, Ar, Hr, Q, Efield, Eanchor, tau, P, terms, stride, cstride, c0,
+                     hist, F, flags);
+  return hipGetLastError();
+}
+
+int tx_wide_tiles(int n_steps) { return (n_steps + 1 + kTxWideSteps - 1) / kTxWideSteps; }
+
+hipError_t launch_tx_wide(const Items& it, const Pairs& pr, const TEnt& te, int n_steps,
+                          const double2* src, double2* dst, const double2* prev, double* part,
+                          double dt, hipStream_t st) {
+  hipLaunchKernelGGL(k_tx_wide, dim3(it.n_items, tx_wide_tiles(n_steps)), dim3(kWideThreads), 0,
+                     st, it, pr, te, n_steps, src, dst, prev, part, dt);
+  return hipGetLastError();
+}
+
+}  // namespace swr

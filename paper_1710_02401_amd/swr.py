@@ -17,7 +17,7 @@ SWR_OK, SWR_E_ARG, SWR_E_SIZE, SWR_E_DEVICE, SWR_E_STATE, SWR_E_SINGULAR, SWR_E_
     0, -1, -2, -3, -4, -5, -6, -7)
 SWR_TDSE, SWR_TISE = 0, 1
 SWR_WARM_PLAIN, SWR_WARM_ZERO, SWR_WARM_GIVEN = 0, 1, 2
-SWR_FACTOR_AUTO, SWR_FACTOR_DIRECT = 0, 1
+SWR_FACTOR_AUTO, SWR_FACTOR_DIRECT, SWR_FACTOR_WIDE = 0, 1, 2
 MATRICES = {"A": 0, "Kin": 1, "V": 2, "Q": 3, "B": 4, "W": 5, "G": 6}
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
@@ -54,7 +54,7 @@ class swr_info(ctypes.Structure):
         ("sum_KK_pairs", ctypes.c_int64), ("n_steps", ctypes.c_int32),
         ("depth", ctypes.c_int32), ("workspace_bytes", ctypes.c_uint64),
         ("learned_nodes", ctypes.c_int32), ("factor_terms", ctypes.c_int32),
-        ("tx_tile", ctypes.c_int32), ("depth_run", ctypes.c_int32),
+        ("tx_tile", ctypes.c_int32), ("depth_run", ctypes.c_int32), ("wide", ctypes.c_int32),
     ]
 
 
@@ -211,7 +211,8 @@ def desc_from_config(cfg):
     d.face_nodes_band, d.face_nodes_mid = int(cfg["face_nodes"][0]), int(cfg["face_nodes"][1])
     d.quad_nodes = int(cfg["quad_nodes"])
     d.learned_nodes = int(cfg.get("learned_nodes", 0))
-    d.factor_mode = {"auto": SWR_FACTOR_AUTO, "direct": SWR_FACTOR_DIRECT}[cfg.get("factor", "auto")]
+    d.factor_mode = {"auto": SWR_FACTOR_AUTO, "direct": SWR_FACTOR_DIRECT,
+                     "wide": SWR_FACTOR_WIDE}[cfg.get("factor", "auto")]
     return d, (arr, pos, chg)
 
 

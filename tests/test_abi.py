@@ -43,7 +43,7 @@ def _create(S, cfg):
     (dict(L=[0]), -1),
     (dict(overlap=[12.0]), -1),
     (dict(dt=0.0), -1),
-    (dict(nbasis=[80]), -2),
+    (dict(nbasis=[257]), -2),
     (dict(mode="tise", mu=[0.0, -1.0]), -1),
     (dict(field=dict(E0=0.1, omega=1.0, phase=0.0, axis=3)), -1),
     (dict(learned_nodes=1), -1),
@@ -61,7 +61,7 @@ def test_factor_mode_validated_and_reported(S):
     lib = S.load_library()
     cfg = workloads.tiny_configs()[0]
     d, keep = S.desc_from_config(cfg)
-    d.factor_mode = 2
+    d.factor_mode = 3
     h = ctypes.c_void_p()
     assert lib.swr_create(ctypes.byref(d), ctypes.byref(h)) == -1
     assert b"factor_mode" in lib.swr_last_error(None)
@@ -191,8 +191,47 @@ def test_batched_geometries_share_one_decomposition(S):
     lib.swr_destroy(h)
 
 
-def test_bases_beyond_64_are_rejected_clearly(S):
+def test_wide_bases_take_the_wide_path(S):
+    """One electron in one dimension (real time) accepts up to 256 Gaussians
+    per subdomain on the wide-basis path: the full batched workload (64
+    geometries x 256 subdomains, K = 32..256) is created with depth 1 and no
+    per-step inverses in its workspace; the path can also be asked for at
+    K <= 64, and is refused elsewhere."""
+    lib = S.load_library()
     cfg = workloads.get_config("c3-1e-1d-batched")
     rc, h = _create(S, cfg)
+    assert rc == 0
+    info = S.swr_info()
+    assert lib.swr_query(h, ctypes.byref(info)) == 0
+    assert info.wide == 1 and info.K_max == 256 and info.n_items == 64 * 256
+    assert info.depth == 1 and info.tx_tile == 0
+    # matrices, series terms and histories, far below one inverse per step
+    # (200 x sum K^2 x 16 bytes)
+    assert info.workspace_bytes < 200 * info.sum_K2 * 16 / 4
+    lib.swr_destroy(h)
+    rc, h = _create(S, workloads.get_config("c1-1e-1d"))
+    info = S.swr_info()
+    assert rc == 0 and lib.swr_query(h, ctypes.byref(info)) == 0 and info.wide == 0
+    lib.swr_destroy(h)
+    rc, h = _create(S, dict(workloads.get_config("c1-1e-1d"), factor="wide"))
+    assert rc == 0 and lib.swr_query(h, ctypes.byref(info)) == 0 and info.wide == 1
+    lib.swr_destroy(h)
+
+
+@pytest.mark.parametrize("mutate,code,text", [
+    (dict(nbasis=[9, 9]), -2, b"exceeds 64"),
+    (dict(factor="wide"), -1, b"wide-basis path"),
+])
+def test_wide_bases_refused_beyond_one_dimension(S, mutate, code, text):
+    cfg = [c for c in workloads.tiny_configs() if c["name"] == "tiny-2d"][0]
+    rc, h = _create(S, dict(cfg, **mutate))
+    assert rc == code
+    assert text in S.load_library().swr_last_error(None)
+
+
+@pytest.mark.parametrize("mutate", [dict(factor="direct"), dict(mu=[0.0, 1.0])])
+def test_wide_bases_need_the_series(S, mutate):
+    cfg = dict(workloads.get_config("c3-wide"), **mutate)
+    rc, h = _create(S, cfg)
     assert rc == -2
-    assert b"exceeds 64" in S.load_library().swr_last_error(None)
+    assert b"field series" in S.load_library().swr_last_error(None)

@@ -1,0 +1,119 @@
+"""Wide-basis path (one electron in one dimension, up to 256 Gaussians per
+subdomain) against the CPU oracle through the C ABI: the batched uneven
+workload at a size the oracle runs whole, the same windows on the narrow
+path, and the full-size batched workload on sampled subdomains."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import swr as o_swr
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(cfg):
+    import torch
+    from paper_1710_02401_amd import Solver
+    print(f"[gpu] solver {cfg['name']} factor={cfg.get('factor', 'auto')}", flush=True)
+    s = Solver(cfg)
+    s.assemble()
+    s.set_initial()
+    torch.cuda.synchronize()
+    return s
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _a_norm_rel(prob, got, ref, items):
+    """max over time steps of sqrt(sum_i dc^H A dc / sum_i c^H A c)."""
+    num = den = 0.0
+    for i in items:
+        A = prob.sys[i].A
+        d = got[i] - ref[i]
+        num = num + np.real(np.einsum("nk,kl,nl->n", np.conj(d), A, d))
+        den = den + np.real(np.einsum("nk,kl,nl->n", np.conj(ref[i]), A, ref[i]))
+    return float(np.max(np.sqrt(num / den)))
+
+
+def test_wide_bases_match_the_oracle():
+    """Two geometries x 8 subdomains with 33..256 Gaussians, 200 steps (two
+    series chunks), 3 Schwarz iterations: every step of every subdomain
+    within 1e-10 (A-norm), and the residuals."""
+    cfg = workloads.get_config("c3-wide")
+    s = _solver(cfg)
+    assert s.info.wide == 1 and s.info.K_max == 256
+    iters = cfg["iters"]
+    st = s.run(k_max=iters, tol=0.0)
+    assert st["iters"] == iters and 1 <= s.factor_terms() + 1 <= 6
+    hist = [_np(h) for h in s.split_history(s.history())]
+    n_sub = len(cfg["nbasis"])
+    res2 = np.zeros(iters)
+    for g, nuc in enumerate(cfg["geometries"]):
+        prob = o_swr.Problem(dict(cfg, nuclei=nuc, geometries=None))
+        h_o, res_o = o_swr.swr_window(prob, prob.initial_coeffs(), iters=iters)
+        got = hist[g * n_sub:(g + 1) * n_sub]
+        err = _a_norm_rel(prob, got, h_o, range(n_sub))
+        print(f"[gpu] c3-wide geometry {g}: rel A-norm {err:.3e}", flush=True)
+        assert err <= 1e-10, g
+        res2 += np.array(res_o) ** 2
+    assert np.allclose(st["res"], np.sqrt(res2), rtol=1e-8, atol=1e-14)
+
+
+@pytest.mark.parametrize("name", ["c1-1e-1d", "c3-mini"])
+def test_wide_path_equals_narrow_path(name):
+    """The wide path asked for at K <= 64 against the narrow path (stored
+    inverses) and the oracle on the first geometry: both within 1e-10 of the
+    oracle, and the wide path no further from it than the narrow one."""
+    cfg = workloads.get_config(name)
+    iters = 4
+    ref = _solver(cfg)
+    st_r = ref.run(k_max=iters, tol=0.0)
+    h_r = [_np(h) for h in ref.split_history(ref.history())]
+    s = _solver(dict(cfg, factor="wide"))
+    assert s.info.wide == 1 and ref.info.wide == 0
+    st = s.run(k_max=iters, tol=0.0)
+    h = [_np(x) for x in s.split_history(s.history())]
+    prob = o_swr.Problem(dict(cfg, nuclei=cfg.get("geometries", [cfg["nuclei"]])[0],
+                              geometries=None))
+    h_o, _ = o_swr.swr_window(prob, prob.initial_coeffs(), iters=iters)
+    n_sub = prob.n_sub
+    e_wide = _a_norm_rel(prob, h[:n_sub], h_o, range(n_sub))
+    e_narrow = _a_norm_rel(prob, h_r[:n_sub], h_o, range(n_sub))
+    print(f"[gpu] {name}: rel A-norm to the oracle: wide {e_wide:.3e}, narrow {e_narrow:.3e}",
+          flush=True)
+    assert e_wide <= 1e-10 and e_narrow <= 1e-10
+    assert e_wide <= max(2.0 * e_narrow, 1e-12)
+    assert np.allclose(st["res"], st_r["res"], rtol=1e-8, atol=1e-14)
+
+
+def test_full_size_batched_workload_sampled_subdomains():
+    """Full batched workload (64 geometries x 256 subdomains, K = 32..256,
+    200 steps): iterate 2 of sampled subdomains of three geometries -- the
+    largest and smallest bases, and a geometry's first and last subdomain --
+    computed by the oracle from their dependency cone only."""
+    import torch
+    cfg = workloads.get_config("c3-1e-1d-batched")
+    s = _solver(cfg)
+    assert s.info.wide == 1 and s.info.n_items == 64 * 256
+    s.factor(0.0)
+    for _ in range(2):
+        s.sweep()
+        s.transmit()
+    torch.cuda.synchronize()
+    parts = s.split_history(s.history())
+    n_sub = 256
+    K = [nb[0] for nb in cfg["nbasis"]]
+    big = K.index(max(K))
+    for g, subs in ((0, [big, 0]), (37, [big + 1, 255]), (63, [K.index(min(K)), big])):
+        prob = o_swr.Problem(dict(cfg, nuclei=cfg["geometries"][g], geometries=None))
+        cone = set(subs)
+        for _ in range(2):
+            cone |= {j for i in cone for j in prob.neighbours(i)}
+        c0 = {j: prob.initial_coeff(j) for j in cone}
+        ref = o_swr.swr_sampled(prob, c0, subs, 2)
+        got = {i: _np(parts[g * n_sub + i]) for i in subs}
+        err = _a_norm_rel(prob, got, ref, subs)
+        print(f"[gpu] c3 full geometry {g} subdomains {subs}: rel A-norm {err:.3e}", flush=True)
+        assert err <= 1e-10, (g, subs)

@@ -107,6 +107,15 @@ _C3M_GEOMS, _C3M_NB = _uneven_geometries(4, 16, (-20.0, 20.0), 8, 32)
 _C3_MINI = dict(_C3, name="c3-mini", L=[16], overlap=[0.5], nbasis=_C3M_NB,
                 geometries=_C3M_GEOMS, nuclei=_C3M_GEOMS[0], iters=8)
 
+# Wide bases (the wide-basis path) at a size the oracle runs in seconds: two
+# geometries of the batched recipe on 8 subdomains with 33 to 256 Gaussians
+# (one to four 64-wide tiles, ragged ends), 200 steps (two chunks of the
+# field series, the second one ragged).
+_C3W_GEOMS, _ = _uneven_geometries(2, 8, (-20.0, 20.0), 32, 224)
+_C3_WIDE = dict(_C3, name="c3-wide", L=[8], overlap=[1.0],
+                nbasis=[[40], [72], [130], [256], [201], [97], [65], [33]],
+                geometries=_C3W_GEOMS, nuclei=_C3W_GEOMS[0], iters=3)
+
 # Two electrons in two dimensions at a size the oracle assembles in under a
 # minute: 2^4 subdomains of 3x2x2x3 Gaussians, unequal boxes, overlaps and
 # per-dimension sizes, field along the second spatial axis.
@@ -129,8 +138,8 @@ _C5_MINI_1E = dict(
     overlap=[0.8, 0.7], nbasis=[5, 4], init=dict(alpha=0.6, center=[0.3, -0.2]), n_steps=10,
 )
 
-CONFIGS = {c["name"]: c for c in (_C1, _C2, _C2_TISE, _C3, _C3_MINI, _C4, _C5, _C5_MINI,
-                                   _C5_MINI_1E)}
+CONFIGS = {c["name"]: c for c in (_C1, _C2, _C2_TISE, _C3, _C3_MINI, _C3_WIDE, _C4, _C5,
+                                   _C5_MINI, _C5_MINI_1E)}
 
 
 def get_config(name, **overrides):
