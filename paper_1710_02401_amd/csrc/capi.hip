@@ -105,10 +105,12 @@ struct swr_handle_s {
   // P_{kSeriesMaxTerms-1}, each sum_K2 complex; the chunks' anchor fields
   Buf bSeries, bEanchor;
   std::vector<double> Ea_host;
-  // wide-basis path (D = 1, K <= kWideK): S2 = Ar + Ap, a K^2 scratch of the
-  // projection, the items by decreasing K, prefix sums of the 64 x 64 tiles
+  // wide-basis path (D = 1, K <= kWideK): S2 = Ar + Ap packed, the series
+  // terms packed (per chunk kWideTerms slots of the packed size), a K^2
+  // scratch (projection, S2 before packing), the items by decreasing K,
+  // prefix sums of the 64 x 64 tiles of the products
   bool wide = false;
-  Buf bS2, bScrW, bOrder, bTileOff;
+  Buf bS2P, bSeriesP, bScrW, bOrder, bTileOff;
   std::vector<int32_t> order;
   std::vector<int64_t> tile_off;
   Buf bT, bC0, bH[kMaxSlots], bF[kMaxSlots], bRc[kMaxSlots], bMinv, bE, bResPart, bResOut, bResv, bIePart, bNus,
@@ -377,7 +379,8 @@ void plan_layout(swr_handle h) {
     // anchor inverse before refinement, then P_0 .. P_{kWideTerms-1}
     h->bMinv = L.add(16);
     h->bSeries = L.add((size_t)n_chunks * kWideSlots * h->sum_K2 * 16);
-    h->bS2 = L.add(m2);
+    h->bSeriesP = L.add((size_t)n_chunks * swr::kWideTerms * h->offp.back() * 16);
+    h->bS2P = L.add(h->offp.back() * 8);
     h->bScrW = L.add(m2);
     h->bOrder = L.add(NI * 4);
     h->bTileOff = L.add((NI + 1) * 8);
@@ -822,9 +825,11 @@ int32_t swr_assemble(swr_handle h, void* stream) {
                                       h->ptr<double>(h->bV), h->ptr<double>(h->bB), 0.5 * dt,
                                       g.desc.mu_re, g.desc.mu_im, h->ptr<double>(h->bAr),
                                       h->ptr<double>(h->bAp), h->ptr<double>(h->bHr), tise, dt, st));
-  if (h->wide)
+  if (h->wide) {
     HIPCHECK(h, swr::launch_add_wide(h->sum_K2, h->ptr<double>(h->bAr), h->ptr<double>(h->bAp),
-                                     h->ptr<double>(h->bS2), st));
+                                     h->ptr<double>(h->bScrW), st));
+    HIPCHECK(h, swr::launch_pack_wide(it, h->ptr<double>(h->bScrW), h->ptr<double>(h->bS2P), st));
+  }
   if (g.te_ok) {
     const swr::TEnt te = h->te();
     HIPCHECK(h, swr::launch_transfer_tensor(it, nd, pr, te, g.desc.mu_re, g.desc.mu_im,
@@ -984,6 +989,9 @@ int32_t swr_factor(swr_handle h, double t0, void* stream) {
       HIPCHECK(h, swr::launch_gemm_wide(it, toff, nt, n_chunks, G, P + (k - 1) * h->sum_K2,
                                         nullptr, make_double2(1.0, 0.0), nullptr, cstride,
                                         P + k * h->sum_K2, st));
+    const int64_t np = h->offp.back();
+    HIPCHECK(h, swr::launch_pack_wide(it, n_chunks, terms, P, cstride, h->sum_K2,
+                                      h->ptr<double2>(h->bSeriesP), swr::kWideTerms * np, np, st));
   } else if (terms > 0) {
     const int64_t cstride = (int64_t)(kSeriesMaxTerms + 1) * h->sum_K2;
     double2* G = h->ptr<double2>(h->bSeries);
@@ -1031,14 +1039,15 @@ int32_t swr_sweep(swr_handle h, void* stream) {
   const int nT = (int)h->n_T;
   double2* hist = h->hist_of(k);
   if (h->wide) {
-    const double2* P = h->ptr<double2>(h->bSeries) + 2 * h->sum_K2;
+    const int64_t np = h->offp.back();
     HIPCHECK(h, tbegin(h, st, kTRecur));
     HIPCHECK(h, swr::launch_cn_recur_wide(
-                    it, h->ptr<int32_t>(h->bOrder), nT, h->ptr<double>(h->bS2),
+                    it, h->ptr<int32_t>(h->bOrder), nT, h->ptr<double>(h->bS2P),
                     h->ptr<double>(h->bAr), h->ptr<double>(h->bHr), h->ptr<double>(h->bQ),
-                    h->ptr<double>(h->bE), h->ptr<double>(h->bEanchor), 0.5 * h->g.desc.dt, P,
-                    h->factor_terms + 1, h->sum_K2, (int64_t)kWideSlots * h->sum_K2,
-                    h->ptr<double2>(h->bC0), hist, h->F_of(k), h->ptr<int>(h->bFlags), st));
+                    h->ptr<double>(h->bE), h->ptr<double>(h->bEanchor), 0.5 * h->g.desc.dt,
+                    h->ptr<double2>(h->bSeriesP), h->factor_terms + 1, np,
+                    (int64_t)swr::kWideTerms * np, h->ptr<double2>(h->bC0), hist, h->F_of(k),
+                    h->ptr<int>(h->bFlags), st));
     HIPCHECK(h, tend(h, st));
   } else if (h->g.desc.mode == SWR_TDSE) {
     swr::RecJobs jobs{};

@@ -314,13 +314,22 @@ hipError_t launch_residual_wide(const Items& it, const int64_t* toff, int64_t n_
                                 int n_chunks, const double* Ar, const double* Hr, const double* Q,
                                 const double* Eanchor, double tau, const double2* X,
                                 int64_t cstride, double2* R, hipStream_t st);
-// Whole-window recurrence of one iterate with the series applied per step:
-// P_k of chunk c at P + c cstride + k stride (1 <= terms <= kWideTerms);
-// order: the items by decreasing K (the launch order of the blocks).
+// Packed upper 8 x 8 tiles (the inverses' layout, zero padding) of full
+// symmetric matrices: the real S2 of every item (src at off2, dst at offp),
+// and the complex series terms (c, j) < (n_chunks, terms) at src + c sc +
+// j sj (+ off2) to dst + c dc + j dj (+ offp).
+hipError_t launch_pack_wide(const Items& it, const double* src, double* dst, hipStream_t st);
+hipError_t launch_pack_wide(const Items& it, int n_chunks, int terms, const double2* src,
+                            int64_t sc, int64_t sj, double2* dst, int64_t dc, int64_t dj,
+                            hipStream_t st);
+// Whole-window recurrence of one iterate with the series applied per step,
+// from packed matrices: S2p (real), the term P_k of chunk c at Pp + c cstride
+// + k tstride (1 <= terms <= kWideTerms); order: the items by decreasing K
+// (the launch order of the blocks).
 hipError_t launch_cn_recur_wide(const Items& it, const int32_t* order, int n_steps,
-                                const double* S2, const double* Ar, const double* Hr,
+                                const double* S2p, const double* Ar, const double* Hr,
                                 const double* Q, const double* Efield, const double* Eanchor,
-                                double tau, const double2* P, int terms, int64_t stride,
+                                double tau, const double2* Pp, int terms, int64_t tstride,
                                 int64_t cstride, const double2* c0, double2* hist,
                                 const double2* F, int* flags, hipStream_t st);
 // Robin data of the whole window from src into dst; with prev, one residual

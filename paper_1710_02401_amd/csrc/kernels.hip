@@ -1072,24 +1072,6 @@ struct RecPipe {
   double2 f;            // f^{n+1} at row r
 };
 
-// cross-lane moves inside rows of the wave (DPP, no LDS traffic); every
-// lane's source is inside its row, so the value written is never the old one
-template <int kCtrl>
-__device__ inline double dpp_f64(double v) {
-  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), kCtrl, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), kCtrl, 0xF, 0xF, true);
-  return __hiloint2double(hi, lo);
-}
-
-// sum over each group of eight consecutive lanes, result in every lane:
-// quad_perm [1,0,3,2], quad_perm [2,3,0,1], then row_half_mirror (lane i
-// of a half-row meets lane 7-i, i.e. the other quad)
-__device__ inline double group8_sum(double v) {
-  v += dpp_f64<0xB1>(v);
-  v += dpp_f64<0x4E>(v);
-  v += dpp_f64<0x141>(v);
-  return v;
-}
 
 // Loads of everything step n consumes.  Unconditional, from clamped
 // addresses: entries past K multiply the zero padding of the LDS vectors

@@ -9,9 +9,9 @@
 //   (M^{n+1})^{-1} = sum_k (E_c - E_{n+1})^k P_k,   P_k = (i tau P_0 Q)^k P_0,
 // and the P_k of every chunk are formed once per window: the anchor inverse
 // by Gauss-Jordan (k_invert_wide), the terms by batched complex products
-// (k_gemm_wide).  All matrices here are K x K row-major at the item's K^2
-// offset; they are symmetric, so row m read at columns r = 0..K-1 is column
-// m, which is what makes the per-row accesses below coalesced.
+// (k_gemm_wide), then packed into symmetric tiles for the recurrence
+// (k_pack_wide).  Matrices are K x K row-major at the item's K^2 offset
+// unless said to be packed.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -359,114 +359,175 @@ __global__ void __launch_bounds__(kWideThreads) k_residual_wide(Items it, const 
 }
 
 // ---------------------------------------------------------------------------
+// Packed symmetric storage for the recurrence: the upper 8 x 8 tiles (I <= J)
+// row by row, each column-major (entry (a, b) of tile (I, J) = M[8I+a][8J+b]
+// at b * 8 + a), padding entries zero; item s at offp[s].  Full matrix
+// (c, j) of item s at src + c sc + j sj + off2[s] goes to dst + c dc + j dj +
+// offp[s]; grid (item, chunk, term).
+__device__ inline double zero_of(double) { return 0.0; }
+__device__ inline double2 zero_of(double2) { return make_double2(0.0, 0.0); }
+
+template <class T>
+__global__ void __launch_bounds__(kWideThreads) k_pack_wide(Items it, const T* src, int64_t sc,
+                                                            int64_t sj, T* dst, int64_t dc,
+                                                            int64_t dj) {
+  const int s = blockIdx.x;
+  const int K = it.K[s];
+  const int Tn = (K + 7) >> 3;
+  const int64_t n = 32 * (int64_t)Tn * (Tn + 1);
+  const T* a = src + blockIdx.y * sc + blockIdx.z * sj + it.off2[s];
+  T* o = dst + blockIdx.y * dc + blockIdx.z * dj + it.offp[s];
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+    int t = (int)(e >> 6);
+    const int l = (int)(e & 63);
+    int I = 0;
+    while (t >= Tn - I) {
+      t -= Tn - I;
+      ++I;
+    }
+    const int row = 8 * I + (l & 7), col = 8 * (I + t) + (l >> 3);
+    o[e] = (row < K && col < K) ? a[(int64_t)row * K + col] : zero_of(T());
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Crank-Nicolson recurrence of the wide path (Section 4.4 step 2), the whole
 // window of one Schwarz iterate, one block per item (items in the order
 // given, largest first).  As in the narrow path, M^n c^n is the previous
 // step's right-hand side, so
 //   rhs^n   = S2 c^n - rhs^{n-1} + (i tau / 2)(f^n + f^{n+1}),  S2 = Ar + Ap,
-//   c^{n+1} = sum_k d^k (P_k rhs^n),  d = E_c - E_{n+1},
-// with rhs^{-1} = M^0 c^0 formed from the matrices.  Thread t owns row
-// r = t mod K and the columns m = part, part + np, ... (part = t / K,
-// np = 256 / K parts; threads with part >= np only join the barriers); the
-// parts' sums meet in LDS.
+//   c^{n+1} = (sum_k d^k P_k) rhs^n,  d = E_c - E_{n+1},
+// with rhs^{-1} = M^0 c^0 formed from the full matrices.  Both products read
+// the packed symmetric tiles once: wave w walks strips of upper tiles (I,
+// I..T-1) (strips I = w and 7 - w of every group of eight, which balances
+// the strip lengths); lane (a, b) = (lane % 8, lane / 8) holds entry (a, b)
+// of the tile (one coalesced 1 KB load per term), keeps row I's sums over
+// the strip in registers (reduced over b at the strip's end) and adds the
+// transposed contribution to rows 8J + b (reduced over a by DPP) to the
+// wave's own vector in LDS; the four wave vectors are summed by row.
+template <bool kCplx>
+__device__ inline void strip_pass(int T, int w, int lane, const double2* x, double2* yw,
+                                  const double* Sp, const double2* Pp, int terms,
+                                  int64_t tstride, double d) {
+  const int a = lane & 7, b = lane >> 3;
+  for (int i = lane; i < 8 * T; i += 64) yw[i] = make_double2(0.0, 0.0);
+  for (int I0 = 0; I0 < T; I0 += 8)
+    for (int h = 0; h < 2; ++h) {
+      const int I = I0 + (h == 0 ? w : 7 - w);
+      if (I >= T) continue;
+      const double2 xa = x[8 * I + a];
+      double dx = 0.0, dy = 0.0;
+      const int t0 = tile_index(I, I, T);
+#pragma unroll 2
+      for (int J = I; J < T; ++J) {
+        const int64_t e = (int64_t)(t0 + J - I) * 64 + lane;
+        double2 m;
+        if (kCplx) {
+          double2 v[kWideTerms];
+#pragma unroll
+          for (int j = 0; j < kWideTerms; ++j)
+            v[j] = j < terms ? Pp[e + j * tstride] : make_double2(0.0, 0.0);
+          m = v[kWideTerms - 1];
+#pragma unroll
+          for (int j = kWideTerms - 2; j >= 0; --j)
+            m = make_double2(fma(d, m.x, v[j].x), fma(d, m.y, v[j].y));
+        } else {
+          m = make_double2(Sp[e], 0.0);
+        }
+        const double2 xb = x[8 * J + b];
+        double tx, ty;
+        if (kCplx) {
+          dx = fma(m.x, xb.x, fma(-m.y, xb.y, dx));
+          dy = fma(m.x, xb.y, fma(m.y, xb.x, dy));
+          tx = fma(m.x, xa.x, -m.y * xa.y);
+          ty = fma(m.x, xa.y, m.y * xa.x);
+        } else {
+          dx = fma(m.x, xb.x, dx);
+          dy = fma(m.x, xb.y, dy);
+          tx = m.x * xa.x;
+          ty = m.x * xa.y;
+        }
+        if (J > I) {
+          tx = group8_sum(tx);
+          ty = group8_sum(ty);
+          if (a == 0) {
+            const double2 y = yw[8 * J + b];
+            yw[8 * J + b] = make_double2(y.x + tx, y.y + ty);
+          }
+        }
+      }
+#pragma unroll
+      for (int o = 8; o < 64; o <<= 1) {
+        dx += __shfl_xor(dx, o, 64);
+        dy += __shfl_xor(dy, o, 64);
+      }
+      if (b == 0) {
+        const double2 y = yw[8 * I + a];
+        yw[8 * I + a] = make_double2(y.x + dx, y.y + dy);
+      }
+    }
+}
+
 __global__ void __launch_bounds__(kWideThreads) k_cn_recur_wide(
-    Items it, const int32_t* order, int n_steps, const double* S2, const double* Ar,
+    Items it, const int32_t* order, int n_steps, const double* S2p, const double* Ar,
     const double* Hr, const double* Q, const double* Eall, const double* Eanchor, double tau,
-    const double2* P, int terms, int64_t stride, int64_t cstride, const double2* c0,
+    const double2* Pp, int terms, int64_t tstride, int64_t cstride, const double2* c0,
     double2* hist, const double2* F, int* flags) {
   const int s = order[blockIdx.x];
   const int K = it.K[s];
-  const int np = kWideThreads / K;
-  const int t = threadIdx.x;
-  const int part = t / K, r = t - part * K;
-  const bool act = part < np;
-  const int64_t o2 = it.off2[s];
+  const int T = (K + 7) >> 3;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int64_t o2 = it.off2[s], op = it.offp[s];
   const int64_t hb = (int64_t)(n_steps + 1) * it.off1[s];
-  __shared__ double2 sv[kWideK];        // c^n
-  __shared__ double2 sr[kWideK];        // rhs^n
-  __shared__ double2 sp[kWideThreads];  // partial sums, [part * K + r]
-  if (t < K) {
-    const double2 v = c0[it.off1[s] + t];
-    sv[t] = v;
-    hist[hb + t] = v;
-  }
-  __syncthreads();
-  if (act) {
-    const double E = Eall[0];
-    double ax = 0.0, ay = 0.0, hx = 0.0, hy = 0.0;
-    for (int m = part; m < K; m += np) {
-      const int64_t e = o2 + (int64_t)m * K + r;
-      const double a = Ar[e], h = fma(E, Q[e], Hr[e]);
-      const double2 cm = sv[m];
-      ax = fma(a, cm.x, ax);
-      ay = fma(a, cm.y, ay);
-      hx = fma(h, cm.x, hx);
-      hy = fma(h, cm.y, hy);
-    }
-    sp[t] = make_double2(fma(-tau, hy, ax), fma(tau, hx, ay));
+  __shared__ double2 sv[kWideK];        // c^n, zero past K
+  __shared__ double2 sr[kWideK];        // rhs^n, zero past K
+  __shared__ double2 yw[4][kWideK];     // the waves' partial products
+  for (int i = t; i < 8 * T; i += kWideThreads) {
+    const double2 v = i < K ? c0[it.off1[s] + i] : make_double2(0.0, 0.0);
+    sv[i] = v;
+    sr[i] = make_double2(0.0, 0.0);
+    if (i < K) hist[hb + i] = v;
   }
   __syncthreads();
   double2 rprev = make_double2(0.0, 0.0), fprev = make_double2(0.0, 0.0);
-  if (part == 0) {
-    for (int q = 0; q < np; ++q) rprev = cadd(rprev, sp[q * K + r]);
-    fprev = F[hb + r];
+  if (t < K) {
+    const double E = Eall[0];
+    double ax = 0.0, ay = 0.0, hx = 0.0, hy = 0.0;
+    for (int m = 0; m < K; ++m) {
+      const int64_t e = o2 + (int64_t)m * K + t;
+      const double av = Ar[e], h = fma(E, Q[e], Hr[e]);
+      const double2 cm = sv[m];
+      ax = fma(av, cm.x, ax);
+      ay = fma(av, cm.y, ay);
+      hx = fma(h, cm.x, hx);
+      hy = fma(h, cm.y, hy);
+    }
+    rprev = make_double2(fma(-tau, hy, ax), fma(tau, hx, ay));
+    fprev = F[hb + t];
   }
   bool bad = false;
   for (int n = 0; n < n_steps; ++n) {
-    // rhs^n: the real product with S2
-    if (act) {
-      double ax = 0.0, ay = 0.0;
-      const double* srow = S2 + o2 + r;
-#pragma unroll 4
-      for (int m = part; m < K; m += np) {
-        const double a = srow[(int64_t)m * K];
-        const double2 cm = sv[m];
-        ax = fma(a, cm.x, ax);
-        ay = fma(a, cm.y, ay);
-      }
-      sp[t] = make_double2(ax, ay);
-    }
+    strip_pass<false>(T, w, lane, sv, yw[w], S2p + op, nullptr, 0, 0, 0.0);
     __syncthreads();
-    if (part == 0) {
-      double2 a = make_double2(0.0, 0.0);
-      for (int q = 0; q < np; ++q) a = cadd(a, sp[q * K + r]);
-      const double2 f1 = F[hb + (int64_t)(n + 1) * K + r];
+    if (t < K) {
+      const double2 u = cadd(cadd(yw[0][t], yw[1][t]), cadd(yw[2][t], yw[3][t]));
+      const double2 f1 = F[hb + (int64_t)(n + 1) * K + t];
       const double2 fs = cadd(fprev, f1);
       fprev = f1;
-      const double2 rhs = make_double2(fma(-0.5 * tau, fs.y, a.x - rprev.x),
-                                       fma(0.5 * tau, fs.x, a.y - rprev.y));
+      const double2 rhs = make_double2(fma(-0.5 * tau, fs.y, u.x - rprev.x),
+                                       fma(0.5 * tau, fs.x, u.y - rprev.y));
       rprev = rhs;
-      sr[r] = rhs;
+      sr[t] = rhs;
     }
     __syncthreads();
-    // c^{n+1}: the series terms of the step's chunk
-    if (act) {
-      const int c = n / kSeriesChunk;
-      const double d = Eanchor[c] - Eall[n + 1];
-      const double2* base = P + (int64_t)c * cstride + o2 + r;
-      double2 acc[kWideTerms];
-#pragma unroll
-      for (int j = 0; j < kWideTerms; ++j) acc[j] = make_double2(0.0, 0.0);
-#pragma unroll 2
-      for (int m = part; m < K; m += np) {
-        const double2 rm = sr[m];
-        const double2* pm = base + (int64_t)m * K;
-#pragma unroll
-        for (int j = 0; j < kWideTerms; ++j)
-          if (j < terms) acc[j] = cfma(pm[j * stride], rm, acc[j]);
-      }
-      double2 y = acc[kWideTerms - 1];
-#pragma unroll
-      for (int j = kWideTerms - 2; j >= 0; --j)
-        y = make_double2(fma(d, y.x, acc[j].x), fma(d, y.y, acc[j].y));
-      sp[t] = y;
-    }
+    const int c = n / kSeriesChunk;
+    strip_pass<true>(T, w, lane, sr, yw[w], nullptr, Pp + (int64_t)c * cstride + op, terms,
+                     tstride, Eanchor[c] - Eall[n + 1]);
     __syncthreads();
-    if (part == 0) {
-      double2 v = make_double2(0.0, 0.0);
-      for (int q = 0; q < np; ++q) v = cadd(v, sp[q * K + r]);
-      sv[r] = v;
-      hist[hb + (int64_t)(n + 1) * K + r] = v;
+    if (t < K) {
+      const double2 v = cadd(cadd(yw[0][t], yw[1][t]), cadd(yw[2][t], yw[3][t]));
+      sv[t] = v;
+      hist[hb + (int64_t)(n + 1) * K + t] = v;
       bad |= !cfinite(v);
     }
     __syncthreads();
@@ -618,16 +679,30 @@ hipError_t launch_residual_wide(const Items& it, const int64_t* toff, int64_t n_
   return hipGetLastError();
 }
 
+hipError_t launch_pack_wide(const Items& it, const double* src, double* dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_pack_wide<double>, dim3(it.n_items, 1, 1), dim3(kWideThreads), 0, st, it,
+                     src, (int64_t)0, (int64_t)0, dst, (int64_t)0, (int64_t)0);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_wide(const Items& it, int n_chunks, int terms, const double2* src,
+                            int64_t sc, int64_t sj, double2* dst, int64_t dc, int64_t dj,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_pack_wide<double2>, dim3(it.n_items, n_chunks, terms), dim3(kWideThreads),
+                     0, st, it, src, sc, sj, dst, dc, dj);
+  return hipGetLastError();
+}
+
 hipError_t launch_cn_recur_wide(const Items& it, const int32_t* order, int n_steps,
-                                const double* S2, const double* Ar, const double* Hr,
+                                const double* S2p, const double* Ar, const double* Hr,
                                 const double* Q, const double* Efield, const double* Eanchor,
-                                double tau, const double2* P, int terms, int64_t stride,
+                                double tau, const double2* Pp, int terms, int64_t tstride,
                                 int64_t cstride, const double2* c0, double2* hist,
                                 const double2* F, int* flags, hipStream_t st) {
   if (terms < 1 || terms > kWideTerms) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_cn_recur_wide, dim3(it.n_items), dim3(kWideThreads), 0, st, it, order,
-                     n_steps, S2, Ar, Hr, Q, Efield, Eanchor, tau, P, terms, stride, cstride, c0,
-                     hist, F, flags);
+                     n_steps, S2p, Ar, Hr, Q, Efield, Eanchor, tau, Pp, terms, tstride, cstride,
+                     c0, hist, F, flags);
   return hipGetLastError();
 }
 
