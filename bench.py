@@ -94,6 +94,64 @@ def learned_summary(mode):
     return res
 
 
+def batched_summary(iters):
+    """The batched uneven workload (64 geometries x 256 subdomains, 32..256
+    Gaussians per subdomain, 200 steps) on the wide-basis path: one window of
+    `iters` Schwarz iterations after a warm-up window, kernel times from HIP
+    events around every launch (one iterate at a time: the items fill the
+    GPU).  Recurrence bytes per sweep: per item and step the unique entries
+    K(K+1)/2 of S2 (8 B) and of each series term (16 B), f^{n+1} read and
+    c^{n+1} written (32 K B)."""
+    import torch
+
+    import workloads
+    from paper_1710_02401_amd import Solver
+    cfg = workloads.get_config("c3-1e-1d-batched")
+    s = Solver(cfg)
+    s.assemble()
+    s.set_initial()
+    torch.cuda.synchronize()
+    c0 = s.initial().clone()
+    s.run(k_max=2, tol=-1.0)
+    s.set_initial(c0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    st = s.run(k_max=iters, tol=-1.0, timing=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    Ks = [nb[0] for nb in cfg["nbasis"]] * len(cfg["geometries"])
+    n, nT, terms = len(Ks), int(s.n_steps), s.factor_terms() + 1
+    sym = sum(k * (k + 1) // 2 for k in Ks)
+    rec_bytes = iters * nT * (sym * (8.0 + 16.0 * terms) + 32.0 * sum(Ks))
+    kern = st["kernels"]
+    sec = kern["recur"]["ms"] * 1e-3
+    achieved = rec_bytes / sec / 1e9
+    m = MEASURED_TRAFFIC.get("k_cn_recur_wide")
+    valid = m and m["wide_sha256"] == wide_digest()
+    return {
+        "workload": f"{cfg['name']}: {len(cfg['geometries'])} geometries x {cfg['L'][0]} "
+                    f"subdomains, K={min(Ks)}..{max(Ks)} Gaussians (1-D), {nT} steps per "
+                    f"window, {iters} Schwarz iterations",
+        "value": n * iters / wall, "unit": "subdomain-solves/s",
+        "ms_per_window": 1e3 * wall, "ms_per_iteration": 1e3 * wall / iters,
+        "series_terms": terms,
+        "factor_ms": kern["factor"]["ms"],
+        "recur_ms_per_sweep": kern["recur"]["ms"] / iters,
+        "transmit_ms_per_sweep": kern["transmit"]["ms"] / iters,
+        "roofline": {"kernel": "k_cn_recur_wide", "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": m["bytes_per_launch"] / 1e9 if valid else None},
+        "last_residual": st["res"][min(iters, 64) - 1],
+    }
+
+
+def wide_digest():
+    import hashlib
+    path = os.path.join(HERE, "paper_1710_02401_amd", "csrc", "wide.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +162,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--depth", type=int, default=0, help="iterates in flight (0: library choice)")
     ap.add_argument("--learned", choices=("off", "quick", "full"), default="quick")
+    ap.add_argument("--batched-iters", type=int, default=30,
+                    help="Schwarz iterations of the batched wide-basis window (0: skip it)")
     ap.add_argument("--no-graph", action="store_true",
                     help="time the windows as eager launches instead of a replayed HIP graph")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
@@ -227,6 +287,10 @@ def main():
     per_it = sum(lit[k]["ms"] for k in ("recur", "transmit", "residual")) / 3
     out["paper_literal_sweep_ms"] = lit["factor"]["ms"] + per_it
     out["wavefront_ms_per_iteration"] = ms_step / iters
+    if args.batched_iters > 0:
+        del s
+        torch.cuda.empty_cache()
+        out["batched_wide_bases"] = batched_summary(args.batched_iters)
     if args.learned != "off":
         out["learned_warm_start"] = learned_summary(args.learned)
     if not args.no_cpu:

@@ -117,3 +117,24 @@ def test_full_size_batched_workload_sampled_subdomains():
         err = _a_norm_rel(prob, got, ref, subs)
         print(f"[gpu] c3 full geometry {g} subdomains {subs}: rel A-norm {err:.3e}", flush=True)
         assert err <= 1e-10, (g, subs)
+
+
+def test_full_geometry_of_the_batched_workload_residuals():
+    """Every subdomain of geometry 0 of the batched workload (256 subdomains,
+    K = 32..256), 6 Schwarz iterations: Res(k) against the oracle's sequence
+    (tests/golden/batched_geometry0_residuals.json, written by
+    make_batched_residuals.py from the oracle alone).  The sequence grows:
+    plain SWR diverges on this decomposition (cores 0.156 wide, overlap
+    0.031), and the GPU must follow it."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden",
+                           "batched_geometry0_residuals.json")) as f:
+        gold = json.load(f)
+    cfg = workloads.get_config("c3-1e-1d-batched")
+    g0 = cfg["geometries"][0]
+    s = _solver(dict(cfg, geometries=[g0], nuclei=g0))
+    assert s.info.n_items == 256
+    st = s.run(k_max=gold["iterations"], tol=0.0)
+    print("[gpu] batched geometry 0 residuals", st["res"][:gold["iterations"]], flush=True)
+    assert np.allclose(st["res"][:gold["iterations"]], gold["residuals"], rtol=1e-8, atol=0)
