@@ -40,10 +40,12 @@ MEASURED_TRAFFIC = {
     # (1 GiB copy calibration) over the first window at depth 4 with the
     # 32-step transmission tile: 23 recurrence launches, 24 transmissions,
     # one factorisation
-    "k_cn_recur": {"kernels_sha256": "6414fab4e6691dea", "bytes_per_launch": 2.1760e9},
-    "k_tx_send+k_tx_recv": {"kernels_sha256": "6414fab4e6691dea", "bytes_per_launch": 0.4593e9,
+    "k_cn_recur": {"kernels_sha256": "4fd85aa9ace08e52", "bytes_per_launch": 2.1760e9},
+    "k_tx_send+k_tx_recv": {"kernels_sha256": "4fd85aa9ace08e52", "bytes_per_launch": 0.4577e9,
                             "tx_tile": 32},
-    "k_series_assemble": {"kernels_sha256": "6414fab4e6691dea", "bytes_per_launch": 2.4357e9},
+    "k_series_assemble": {"kernels_sha256": "4fd85aa9ace08e52", "bytes_per_launch": 2.4357e9},
+    # profiles/c3-1e-1d-batched_traffic.md: one sweep of the batched workload
+    "k_cn_recur_wide": {"wide_sha256": "5ee48a398d94d741", "bytes_per_launch": 1349.25e9},
 }
 
 
@@ -100,8 +102,8 @@ def batched_summary(iters):
     `iters` Schwarz iterations after a warm-up window, kernel times from HIP
     events around every launch (one iterate at a time: the items fill the
     GPU).  Recurrence bytes per sweep: per item and step the unique entries
-    K(K+1)/2 of S2 (8 B) and of each series term (16 B), f^{n+1} read and
-    c^{n+1} written (32 K B)."""
+    K(K+1)/2 of S2 (8 B) and of each series term the item applies (16 B),
+    f^{n+1} read and c^{n+1} written (32 K B)."""
     import torch
 
     import workloads
@@ -121,8 +123,9 @@ def batched_summary(iters):
     wall = time.perf_counter() - t
     Ks = [nb[0] for nb in cfg["nbasis"]] * len(cfg["geometries"])
     n, nT, terms = len(Ks), int(s.n_steps), s.factor_terms() + 1
-    sym = sum(k * (k + 1) // 2 for k in Ks)
-    rec_bytes = iters * nT * (sym * (8.0 + 16.0 * terms) + 32.0 * sum(Ks))
+    per_item = s.item_terms()
+    rec_bytes = iters * nT * sum(k * (k + 1) / 2 * (8.0 + 16.0 * t) + 32.0 * k
+                                 for k, t in zip(Ks, per_item))
     kern = st["kernels"]
     sec = kern["recur"]["ms"] * 1e-3
     achieved = rec_bytes / sec / 1e9
@@ -135,6 +138,7 @@ def batched_summary(iters):
         "value": n * iters / wall, "unit": "subdomain-solves/s",
         "ms_per_window": 1e3 * wall, "ms_per_iteration": 1e3 * wall / iters,
         "series_terms": terms,
+        "series_terms_largest_bases": int(per_item[Ks.index(max(Ks))]),
         "factor_ms": kern["factor"]["ms"],
         "recur_ms_per_sweep": kern["recur"]["ms"] / iters,
         "transmit_ms_per_sweep": kern["transmit"]["ms"] / iters,

@@ -171,10 +171,13 @@ int32_t swr_warm_start(swr_handle h, int32_t mode, const void* g_dev, void* stre
  * Im mu > 0, K > 7, or SWR_FACTOR_DIRECT, every M^n is inverted.
  * Wide-basis path (one electron in one dimension, real time; taken when some
  * K > 64, or asked for with SWR_FACTOR_WIDE): the inverses of the steps are
- * never formed.  Per chunk the library keeps M_a^{-1} (Gauss-Jordan) and the
- * terms (M_a^{-1} C)^k M_a^{-1}, K x K each, and swr_sweep applies the sum
- * to each step's right-hand side; the series bound above then must hold
- * with K <= 5, else SWR_E_SIZE (as for Im mu > 0 or SWR_FACTOR_DIRECT). */
+ * never formed.  Per chunk the library keeps M_a^{-1} (Gauss-Jordan, then
+ * one correction X + X (I - M_a X) with the residual in compensated
+ * arithmetic) and the terms (M_a^{-1} C)^k M_a^{-1}, packed symmetric, and
+ * swr_sweep applies the sum to each step's right-hand side, each item with
+ * the terms its own box needs (the bound above with the item's X); the
+ * bound must hold with K <= 5, else SWR_E_SIZE (as for Im mu > 0 or
+ * SWR_FACTOR_DIRECT, which the wide path refuses at creation). */
 enum { SWR_FACTOR_AUTO = 0, SWR_FACTOR_DIRECT = 1, SWR_FACTOR_WIDE = 2 };
 int32_t swr_factor(swr_handle h, double t0, void* stream);
 
@@ -265,6 +268,11 @@ int32_t swr_get_matrix(swr_handle h, int32_t which, void* dst_dev, uint64_t byte
 /* Per-item sizes: host int32 [n_items][2 + 2*4]: K, n_face_nodes, then the
  * multi-index and the per-dimension basis sizes (padded with 0). */
 int32_t swr_get_items(swr_handle h, int32_t* dst_host, uint64_t n);
+/* Series terms each item applies per step after the last swr_factor (host
+ * int32 [n_items]): swr_info.factor_terms + 1 for every item on the narrow
+ * path (0 when every step was inverted), the item's own count on the
+ * wide-basis path.  SWR_E_STATE before the first swr_factor. */
+int32_t swr_get_terms(swr_handle h, int32_t* dst_host, uint64_t n);
 /* Subdomain boxes, host double [n_items][4][2] (lo, hi per dimension,
  * computed with the formula order of the geometry, no contraction). */
 int32_t swr_get_boxes(swr_handle h, double* dst_host, uint64_t n);

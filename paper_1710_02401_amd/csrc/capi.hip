@@ -124,6 +124,9 @@ struct swr_handle_s {
   int depth = 1;    // iterates swr_run keeps in flight (TDSE)
   int n_nodes_t = 8;  // time nodes M of the learned warm start
   double dipole_max = 0.0;  // max over items of sum_m max |x_m| along the field axis
+  std::vector<double> dipole;        // the same per item
+  std::vector<int32_t> terms_item;   // wide path: series terms each item needs
+  Buf bTermsW;
   int factor_terms = -1;    // series terms - 1 of the last swr_factor; -1: direct
   int nbt = 1;      // largest tangential basis size (factored transmission)
   int64_t te_pieces = 0;  // largest LDS bytes of the pieces one item sends
@@ -384,6 +387,7 @@ void plan_layout(swr_handle h) {
     h->bScrW = L.add(m2);
     h->bOrder = L.add(NI * 4);
     h->bTileOff = L.add((NI + 1) * 8);
+    h->bTermsW = L.add(NI * 4);
   } else {
     h->bMinv = L.add((size_t)h->n_mats * std::max<int64_t>(h->sum_K2, h->offp.back()) * 16);
     if (g.desc.mode == SWR_TDSE)
@@ -529,6 +533,7 @@ int32_t swr_create(const swr_desc* desc, swr_handle* out) {
       x += std::max(std::fabs(g.lo[(size_t)s * 4 + k]), std::fabs(g.hi[(size_t)s * 4 + k]));
     }
     h->dipole_max = std::max(h->dipole_max, x);
+    h->dipole.push_back(x);
   }
   h->n_res_tiles = (int)((h->n_T + 1 + 15) / 16);
   if (h->wide) h->n_res_tiles = std::max(h->n_res_tiles, swr::tx_wide_tiles((int)h->n_T));
@@ -949,13 +954,20 @@ int32_t swr_factor(swr_handle h, double t0, void* stream) {
       h->Ea_host[c] = 0.5 * (lo + hi);
       half = std::max(half, 0.5 * (hi - lo));
     }
-    const double rho = tau * half * h->dipole_max;
-    if (rho < 0.5) {
-      // least K with rho^{K+1} / (1 - rho) <= 2^-53
-      terms = 1;
-      for (double tail = rho / (1.0 - rho); tail > 0x1p-53 && terms <= max_terms; ++terms)
-        tail *= rho;
-      if (terms > max_terms) terms = 0;
+    // least K with rho^{K+1} / (1 - rho) <= 2^-53, as a number of terms K + 1
+    // (0: more than max_terms)
+    auto terms_for = [&](double rho) {
+      if (!(rho < 0.5)) return 0;
+      int t = 1;
+      for (double tail = rho / (1.0 - rho); tail > 0x1p-53 && t <= max_terms; ++t) tail *= rho;
+      return t > max_terms ? 0 : t;
+    };
+    terms = terms_for(tau * half * h->dipole_max);
+    if (h->wide && terms > 0) {
+      // the bound holds item by item with the item's own dipole extent
+      h->terms_item.resize(h->g.n_items);
+      for (int q = 0; q < h->g.n_items; ++q)
+        h->terms_item[q] = std::max(1, terms_for(tau * half * h->dipole[q]));
     }
   }
   const swr::Items it = h->items();
@@ -963,6 +975,7 @@ int32_t swr_factor(swr_handle h, double t0, void* stream) {
     return fail(h, SWR_E_SIZE, "the field varies too much within a chunk for the wide-basis "
                                "series (more than 6 terms)");
   if (terms > 0) HIPCHECK(h, upload(h, h->bEanchor, h->Ea_host, st));
+  if (h->wide) HIPCHECK(h, upload(h, h->bTermsW, h->terms_item, st));
   HIPCHECK(h, tbegin(h, st, kTFactor));
   if (h->wide) {
     // per chunk: X = M_c^{-1} (Gauss-Jordan), R = I - M_c X (compensated),
@@ -1045,7 +1058,7 @@ int32_t swr_sweep(swr_handle h, void* stream) {
                     it, h->ptr<int32_t>(h->bOrder), nT, h->ptr<double>(h->bS2P),
                     h->ptr<double>(h->bAr), h->ptr<double>(h->bHr), h->ptr<double>(h->bQ),
                     h->ptr<double>(h->bE), h->ptr<double>(h->bEanchor), 0.5 * h->g.desc.dt,
-                    h->ptr<double2>(h->bSeriesP), h->factor_terms + 1, np,
+                    h->ptr<double2>(h->bSeriesP), h->ptr<int32_t>(h->bTermsW), np,
                     (int64_t)swr::kWideTerms * np, h->ptr<double2>(h->bC0), hist, h->F_of(k),
                     h->ptr<int>(h->bFlags), st));
     HIPCHECK(h, tend(h, st));
@@ -1429,6 +1442,15 @@ int32_t swr_get_items(swr_handle h, int32_t* dst, uint64_t n) {
       r[6 + k] = k < g.D ? g.nb[(size_t)s * 4 + k] : 0;
     }
   }
+  return SWR_OK;
+}
+
+int32_t swr_get_terms(swr_handle h, int32_t* dst, uint64_t n) {
+  if (!h || !dst) return fail(h, SWR_E_ARG, "null argument");
+  if (!h->factored) return fail(h, SWR_E_STATE, "swr_factor first");
+  if (n < (uint64_t)h->g.n_items) return fail(h, SWR_E_SIZE, "destination too small");
+  for (int s = 0; s < h->g.n_items; ++s)
+    dst[s] = h->wide ? h->terms_item[s] : h->factor_terms + 1;
   return SWR_OK;
 }
 

@@ -324,14 +324,15 @@ hipError_t launch_pack_wide(const Items& it, int n_chunks, int terms, const doub
                             hipStream_t st);
 // Whole-window recurrence of one iterate with the series applied per step,
 // from packed matrices: S2p (real), the term P_k of chunk c at Pp + c cstride
-// + k tstride (1 <= terms <= kWideTerms); order: the items by decreasing K
-// (the launch order of the blocks).
+// + k tstride, item s using terms_item[s] terms (device, each in
+// 1..kWideTerms and at most the terms packed); order: the items by
+// decreasing K (the launch order of the blocks).
 hipError_t launch_cn_recur_wide(const Items& it, const int32_t* order, int n_steps,
                                 const double* S2p, const double* Ar, const double* Hr,
                                 const double* Q, const double* Efield, const double* Eanchor,
-                                double tau, const double2* Pp, int terms, int64_t tstride,
-                                int64_t cstride, const double2* c0, double2* hist,
-                                const double2* F, int* flags, hipStream_t st);
+                                double tau, const double2* Pp, const int32_t* terms_item,
+                                int64_t tstride, int64_t cstride, const double2* c0,
+                                double2* hist, const double2* F, int* flags, hipStream_t st);
 // Robin data of the whole window from src into dst; with prev, one residual
 // partial per (item, step tile) at part[item * tx_wide_tiles(n_steps) + tile].
 int tx_wide_tiles(int n_steps);

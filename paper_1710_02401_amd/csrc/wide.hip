@@ -471,11 +471,12 @@ __device__ inline void strip_pass(int T, int w, int lane, const double2* x, doub
 __global__ void __launch_bounds__(kWideThreads) k_cn_recur_wide(
     Items it, const int32_t* order, int n_steps, const double* S2p, const double* Ar,
     const double* Hr, const double* Q, const double* Eall, const double* Eanchor, double tau,
-    const double2* Pp, int terms, int64_t tstride, int64_t cstride, const double2* c0,
-    double2* hist, const double2* F, int* flags) {
+    const double2* Pp, const int32_t* terms_item, int64_t tstride, int64_t cstride,
+    const double2* c0, double2* hist, const double2* F, int* flags) {
   const int s = order[blockIdx.x];
   const int K = it.K[s];
   const int T = (K + 7) >> 3;
+  const int terms = terms_item[s];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int64_t o2 = it.off2[s], op = it.offp[s];
   const int64_t hb = (int64_t)(n_steps + 1) * it.off1[s];
@@ -696,13 +697,12 @@ hipError_t launch_pack_wide(const Items& it, int n_chunks, int terms, const doub
 hipError_t launch_cn_recur_wide(const Items& it, const int32_t* order, int n_steps,
                                 const double* S2p, const double* Ar, const double* Hr,
                                 const double* Q, const double* Efield, const double* Eanchor,
-                                double tau, const double2* Pp, int terms, int64_t tstride,
-                                int64_t cstride, const double2* c0, double2* hist,
-                                const double2* F, int* flags, hipStream_t st) {
-  if (terms < 1 || terms > kWideTerms) return hipErrorInvalidValue;
+                                double tau, const double2* Pp, const int32_t* terms_item,
+                                int64_t tstride, int64_t cstride, const double2* c0,
+                                double2* hist, const double2* F, int* flags, hipStream_t st) {
   hipLaunchKernelGGL(k_cn_recur_wide, dim3(it.n_items), dim3(kWideThreads), 0, st, it, order,
-                     n_steps, S2p, Ar, Hr, Q, Efield, Eanchor, tau, Pp, terms, tstride, cstride,
-                     c0, hist, F, flags);
+                     n_steps, S2p, Ar, Hr, Q, Efield, Eanchor, tau, Pp, terms_item, tstride,
+                     cstride, c0, hist, F, flags);
   return hipGetLastError();
 }
 

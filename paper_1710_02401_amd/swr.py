@@ -82,7 +82,7 @@ EXPORTS = [
     "swr_create", "swr_destroy", "swr_last_error", "swr_query", "swr_workspace_bytes",
     "swr_bind_workspace", "swr_assemble", "swr_set_initial", "swr_warm_start", "swr_factor",
     "swr_sweep", "swr_transmit", "swr_run", "swr_get_history", "swr_get_forcing",
-    "swr_get_initial", "swr_get_matrix", "swr_get_items", "swr_get_boxes",
+    "swr_get_initial", "swr_get_matrix", "swr_get_items", "swr_get_terms", "swr_get_boxes",
     "swr_get_index_maps", "swr_get_face_nodes", "swr_reconstruct", "swr_local_eigen",
     "swr_get_norms", "swr_status_sync", "swr_set_field", "swr_advance_window",
     "swr_time_nodes", "swr_face_data", "swr_learned_features", "swr_learned_targets",
@@ -127,6 +127,7 @@ def load_library(path=LIB_PATH):
         "swr_get_initial": (i32, [vp, vp, u64, vp]),
         "swr_get_matrix": (i32, [vp, i32, vp, u64, vp]),
         "swr_get_items": (i32, [vp, _c_i32p, u64]),
+        "swr_get_terms": (i32, [vp, _c_i32p, u64]),
         "swr_get_boxes": (i32, [vp, _c_f64p, u64]),
         "swr_get_index_maps": (i32, [vp, _c_i32p, u64]),
         "swr_get_face_nodes": (i32, [vp, _c_f64p, _c_f64p, u64]),
@@ -408,6 +409,12 @@ class Solver:
         info = swr_info()
         self._call("swr_query", ctypes.byref(info))
         return int(info.factor_terms)
+
+    def item_terms(self):
+        """Series terms each item applies per step after the last factorisation."""
+        out = np.zeros(int(self.info.n_items), dtype=np.int32)
+        self._call("swr_get_terms", out.ctypes.data_as(_c_i32p), ctypes.c_uint64(out.size))
+        return out
 
     def time_nodes(self):
         out = np.zeros(int(self.info.learned_nodes), dtype=np.int32)

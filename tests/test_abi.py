@@ -78,6 +78,8 @@ def test_unbound_workspace_and_state_errors(S):
     assert rc == 0
     assert lib.swr_assemble(h, None) == S.SWR_E_STATE
     assert lib.swr_sweep(h, None) == S.SWR_E_STATE
+    terms = np.zeros(64, dtype=np.int32)
+    assert lib.swr_get_terms(h, terms.ctypes.data_as(S._c_i32p), terms.size) == S.SWR_E_STATE
     r = ctypes.c_double()
     assert lib.swr_transmit(h, ctypes.byref(r), None) == S.SWR_E_STATE
     # misaligned / too small workspace

@@ -106,6 +106,11 @@ def test_full_size_batched_workload_sampled_subdomains():
     n_sub = 256
     K = [nb[0] for nb in cfg["nbasis"]]
     big = K.index(max(K))
+    # each item applies the terms its own box needs: fewer for the large
+    # bases near the nuclei than for the outermost boxes
+    terms = s.item_terms()
+    assert terms.max() == s.factor_terms() + 1 and terms.min() >= 1
+    assert terms[big] < terms[0] == terms.max()
     for g, subs in ((0, [big, 0]), (37, [big + 1, 255]), (63, [K.index(min(K)), big])):
         prob = o_swr.Problem(dict(cfg, nuclei=cfg["geometries"][g], geometries=None))
         cone = set(subs)
