@@ -226,7 +226,8 @@ hipError_t launch_sum_sqrt(const double* partial, int64_t n, double* out, hipStr
 hipError_t launch_transfer_tensor(const Items& it, const Nodes& nd, const Pairs& pr,
                                   const TEnt& te, double mu_re, double mu_im, double* beta,
                                   double2* a, double* X, hipStream_t st);
-// Factored face Gram pieces of every item (assembly); no-op when te.n == 0.
+// Factored face Gram pieces of every item and face (assembly), also when no
+// transfer entry exists.
 hipError_t launch_gram_tensor(const Items& it, const Nodes& nd, const TEnt& te, double* gram,
                               hipStream_t st);
 // Steps per block of the factored transmission for these LDS needs (32 or

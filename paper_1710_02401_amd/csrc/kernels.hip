@@ -2480,7 +2480,9 @@ int transmit_tile_steps(int nbt, int64_t pieces, int max_send, int64_t gram) {
 
 hipError_t launch_gram_tensor(const Items& it, const Nodes& nd, const TEnt& te, double* gram,
                               hipStream_t st) {
-  if (te.n == 0) return hipSuccess;
+  // per item and face, whether or not any transfer entry exists (a lone
+  // subdomain has only global faces, which the residual still covers)
+  if (te.gram_off == nullptr || te.fnode == nullptr) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_gram_tensor, dim3(it.n_items, 2 * it.D), dim3(kBlock), 0, st, it, nd, te,
                      gram);
   return hipGetLastError();
