@@ -77,6 +77,15 @@ __device__ inline void split_index(int l, const int32_t* nb, int D, int* li) {
   }
 }
 
+// FP64 matrix-core product D = A B + C of 16 x 16 x 4 tiles.  Operand
+// layouts: A entry (l % 16, l / 16) in lane l, B entry (l / 16, l % 16),
+// and register r of D entry (4 r + l / 16, l % 16).
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ inline v4d mfma16(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 // cross-lane moves inside rows of the wave (DPP, no LDS traffic); every
 // lane's source is inside its row, so the value written is never the old one
 template <int kCtrl>

@@ -637,11 +637,6 @@ __global__ void k_cn_matrices(int64_t n, const double* A, const double* Kin, con
 // entry (4r + l/16, l%16); register q of a tile is then exactly the B
 // operand of k-chunk q, and the A operand (entry (l%16, 4q + l/16)) is
 // read back from LDS.
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-__device__ inline v4d mfma16(double a, double b, v4d c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
 
 // Modes: kInvSteps inverts M^{n+1} (field E_{n+1}) for n < n_mats into packed
 // upper tiles; kInvReal inverts the real matrix Ar once per item (TISE) and

@@ -9,7 +9,8 @@
 //   (M^{n+1})^{-1} = sum_k (E_c - E_{n+1})^k P_k,   P_k = (i tau P_0 Q)^k P_0,
 // and the P_k of every chunk are formed once per window: the anchor inverse
 // by Gauss-Jordan (k_invert_wide), the terms by batched complex products
-// (k_gemm_wide), then packed into symmetric tiles for the recurrence
+// (k_gemm_wide), both blocked onto the matrix cores, then packed into
+// symmetric tiles for the recurrence
 // (k_pack_wide).  Matrices are K x K row-major at the item's K^2 offset
 // unless said to be packed.
 #include <hip/hip_runtime.h>
@@ -121,10 +122,19 @@ __global__ void __launch_bounds__(kWideThreads) k_project_wide(Items it, const d
 // ---------------------------------------------------------------------------
 // Anchor inverses of the field series: X = M_c^{-1}, M_c = Ar + i tau (Hr +
 // E_c Q), by Gauss-Jordan in place without pivoting (the Hermitian part of
-// M_c, Ar, is positive definite for Im mu <= 0).  One block per (item,
-// chunk); the matrix lives at X + c cstride + the item's K^2 offset.  Pivot
-// p: column p and row p go to LDS, the row is scaled by 1 / x_pp, then every
-// entry is updated; wave w takes rows w, w + 4, ..., lanes the columns.
+// M_c, Ar, is positive definite for Im mu <= 0), blocked in panels of 16
+// columns.  One block per (item, chunk); the matrix lives at X + c cstride +
+// the item's K^2 offset.  Panel P (columns and rows p0 .. p0+15): with C =
+// X[:, P], D = X[P, P] and R = D^{-1} X[P, :], every entry becomes
+//   X[i][j] - C[i] R[:, j]  (i, j outside P),   -C[i] D^{-1}  (column P),
+//   R[:, j]  (row P),   D^{-1}  (the pivot block),
+// i.e. Z - A B with Z the matrix with row and column panel zeroed, A = C
+// whose panel rows are -I, and B = R whose panel columns are D^{-1}.  A and B
+// are staged in LDS, D is inverted there (16 unblocked pivots), and the
+// update runs as 16 x 16 blocks on the matrix cores (wave w takes blocks w,
+// w + 4, ...), so the matrix is streamed once per panel instead of once per
+// pivot.  Padding rows and columns past K are zero in A and B, identity in D.
+constexpr int kGJ = 16;
 __global__ void __launch_bounds__(kWideThreads) k_invert_wide(Items it, const double* Ar,
                                                               const double* Hr, const double* Q,
                                                               const double* Eanchor, double tau,
@@ -132,49 +142,98 @@ __global__ void __launch_bounds__(kWideThreads) k_invert_wide(Items it, const do
                                                               int* flags) {
   const int s = blockIdx.x, c = blockIdx.y;
   const int K = it.K[s];
+  const int T = (K + kGJ - 1) / kGJ;
+  const int KP = T * kGJ;
   const int64_t o2 = it.off2[s];
   double2* x = X + (int64_t)c * cstride + o2;
   const double E = Eanchor[c];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int e = threadIdx.x; e < K * K; e += blockDim.x)
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int lr = lane >> 4, lc = lane & 15;
+  const double2 z2 = make_double2(0.0, 0.0);
+  __shared__ double2 As[kWideK][kGJ + 1];   // A = column panel, rows past K zero
+  __shared__ double2 Bs[kGJ][kWideK + 1];   // B = row panel, columns past K zero
+  __shared__ double2 Ds[kGJ][kGJ + 1];      // pivot block, inverted in place
+  for (int e = t; e < K * K; e += blockDim.x)
     x[e] = make_double2(Ar[o2 + e], tau * fma(E, Q[o2 + e], Hr[o2 + e]));
-  __shared__ double2 col[kWideK], rs[kWideK];
-  __shared__ double2 ipiv;
   bool bad = false;
   __syncthreads();
-  for (int p = 0; p < K; ++p) {
-    for (int i = threadIdx.x; i < K; i += blockDim.x) {
-      col[i] = x[(int64_t)i * K + p];
-      rs[i] = x[(int64_t)p * K + i];
+  for (int p = 0; p < T; ++p) {
+    const int p0 = p * kGJ;
+    for (int e = t; e < kGJ * KP; e += blockDim.x) {
+      const int i = e >> 4, q = e & 15;  // column panel entry (i, p0 + q)
+      As[i][q] = (i < K && p0 + q < K) ? x[(int64_t)i * K + p0 + q] : z2;
+      const int r = e / KP, j = e - r * KP;  // row panel entry (p0 + r, j)
+      Bs[r][j] = (p0 + r < K && j < K) ? x[(int64_t)(p0 + r) * K + j] : z2;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      const double2 pv = rs[p];
-      if (!(fabs(pv.x) > 0.0 || fabs(pv.y) > 0.0)) bad = true;
-      ipiv = crecip(pv);
+    const int a = t >> 4, b = t & 15;
+    Ds[a][b] = (p0 + a < K && p0 + b < K) ? As[p0 + a][b] : make_double2(a == b ? 1.0 : 0.0, 0.0);
+    __syncthreads();
+    for (int q = 0; q < kGJ; ++q) {
+      const double2 pv = Ds[q][q], ca = Ds[a][q], rb = Ds[q][b], v0 = Ds[a][b];
+      __syncthreads();
+      if (t == 0 && !(fabs(pv.x) > 0.0 || fabs(pv.y) > 0.0)) bad = true;
+      const double2 ip = crecip(pv);
+      double2 v;
+      if (a == q)
+        v = b == q ? ip : cmul(rb, ip);
+      else if (b == q)
+        v = cmul(make_double2(-ca.x, -ca.y), ip);
+      else
+        v = csub(v0, cmul(ca, cmul(rb, ip)));
+      Ds[a][b] = v;
+      __syncthreads();
     }
+    // B = D^{-1} (row panel), column by column; the panel's own columns take
+    // D^{-1}; A's panel rows become -I
+    for (int j = t; j < KP; j += blockDim.x) {
+      if (j >= p0 && j < p0 + kGJ) {
+        for (int k = 0; k < kGJ; ++k) Bs[k][j] = Ds[k][j - p0];
+      } else {
+        double2 col[kGJ];
+#pragma unroll
+        for (int m = 0; m < kGJ; ++m) col[m] = Bs[m][j];
+#pragma unroll
+        for (int k = 0; k < kGJ; ++k) {
+          double2 acc = z2;
+#pragma unroll
+          for (int m = 0; m < kGJ; ++m) acc = cfma(Ds[k][m], col[m], acc);
+          Bs[k][j] = acc;
+        }
+      }
+    }
+    As[p0 + a][b] = make_double2(a == b ? -1.0 : 0.0, 0.0);
     __syncthreads();
-    const double2 ip = ipiv;
-    for (int j = threadIdx.x; j < K; j += blockDim.x) rs[j] = cmul(rs[j], ip);  // x_pj / x_pp
-    __syncthreads();
-    for (int i = w; i < K; i += 4) {
-      const double2 ci = col[i];
-      double2* xr = x + (int64_t)i * K;
-      for (int j = lane; j < K; j += 64) {
-        double2 v;
-        if (i == p)
-          v = j == p ? ip : rs[j];
-        else if (j == p)
-          v = cmul(make_double2(-ci.x, -ci.y), ip);
-        else
-          v = csub(xr[j], cmul(ci, rs[j]));
-        xr[j] = v;
+    for (int blk = w; blk < T * T; blk += 4) {
+      const int ib = blk / T, jb = blk - ib * T;
+      const bool keep = ib != p && jb != p;
+      v4d cr, ci;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = ib * kGJ + 4 * r + lr, col = jb * kGJ + lc;
+        const double2 v = (keep && row < K && col < K) ? x[(int64_t)row * K + col] : z2;
+        cr[r] = v.x;
+        ci[r] = v.y;
+      }
+#pragma unroll
+      for (int kk = 0; kk < kGJ / 4; ++kk) {
+        const double2 av = As[ib * kGJ + lc][4 * kk + lr];
+        const double2 bv = Bs[4 * kk + lr][jb * kGJ + lc];
+        cr = mfma16(-av.x, bv.x, cr);
+        cr = mfma16(av.y, bv.y, cr);
+        ci = mfma16(-av.x, bv.y, ci);
+        ci = mfma16(-av.y, bv.x, ci);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = ib * kGJ + 4 * r + lr, col = jb * kGJ + lc;
+        if (row < K && col < K) x[(int64_t)row * K + col] = make_double2(cr[r], ci[r]);
       }
     }
     __syncthreads();
   }
   if (bad) atomicOr(flags, kFlagPivot);
-  for (int e = threadIdx.x; e < K * K; e += blockDim.x)
+  for (int e = t; e < K * K; e += blockDim.x)
     if (!cfinite(x[e])) {
       atomicOr(flags, kFlagNaN);
       break;
@@ -184,11 +243,23 @@ __global__ void __launch_bounds__(kWideThreads) k_invert_wide(Items it, const do
 // ---------------------------------------------------------------------------
 // Batched complex products of the series terms: out = scale L R (+ add) per
 // item and chunk (chunk c of L, Rc, add and out at c cstride); R is Rc
-// (complex) when not null, else Rr (real, the same for every chunk).  64 x 64 output tiles, 256
-// threads of 4 x 4 outputs (rows ty + 16 u, columns tx + 16 v), k-slices of
-// 16 staged in LDS.  Grid (tiles over all items, chunks); toff holds the
-// prefix sums of ceil(K/64)^2, so a block finds its item by bisection.
+// (complex) when not null, else Rr (real, the same for every chunk).  64 x 64
+// output tiles, k-slices of 16 staged in LDS; wave w computes rows 16 w ..
+// 16 w + 15 of the tile on the matrix cores (four real products per complex
+// 16 x 16 x 4 step, two for real R).  Grid (tiles over all items, chunks);
+// toff holds the prefix sums of ceil(K/64)^2, so a block finds its item by
+// bisection.
 constexpr int kGT = 64, kGK = 16;
+__device__ inline int item_of_tile(const Items& it, const int64_t* toff, int64_t b) {
+  int lo = 0, hi = it.n_items;  // toff[lo] <= b < toff[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (toff[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 template <bool kRealR>
 __global__ void __launch_bounds__(kWideThreads) k_gemm_wide(Items it, const int64_t* toff,
                                                             const double2* L, const double2* Rc,
@@ -196,13 +267,7 @@ __global__ void __launch_bounds__(kWideThreads) k_gemm_wide(Items it, const int6
                                                             const double2* add, int64_t cstride,
                                                             double2* out) {
   const int64_t b = blockIdx.x;
-  int lo = 0, hi = it.n_items;  // toff[lo] <= b < toff[hi]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (toff[mid] <= b) lo = mid;
-    else hi = mid;
-  }
-  const int s = lo;
+  const int s = item_of_tile(it, toff, b);
   const int K = it.K[s];
   const int T = (K + kGT - 1) / kGT;
   const int tile = (int)(b - toff[s]);
@@ -211,22 +276,24 @@ __global__ void __launch_bounds__(kWideThreads) k_gemm_wide(Items it, const int6
   const double2* l = L + co;
   const double2* rc = kRealR ? nullptr : Rc + co;
   const double* rr = kRealR ? Rr + it.off2[s] : nullptr;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lr = lane >> 4, lc = lane & 15;
   __shared__ double2 Ls[kGT][kGK + 1];
-  __shared__ double2 Rs[kGK][kGT];
-  double2 acc[4][4];
+  __shared__ double2 Rs[kGK][kGT + 1];
+  v4d cr[4], ci[4];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = make_double2(0.0, 0.0);
+  for (int t = 0; t < 4; ++t) {
+    cr[t] = v4d{0.0, 0.0, 0.0, 0.0};
+    ci[t] = v4d{0.0, 0.0, 0.0, 0.0};
+  }
   for (int k0 = 0; k0 < K; k0 += kGK) {
     // L slice: 64 rows x 16 columns; R slice: 16 rows x 64 columns
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = threadIdx.x + q * kWideThreads;
-      const int lr = e >> 4, lk = e & 15;
-      const int gr = r0 + lr, gk = k0 + lk;
-      Ls[lr][lk] = (gr < K && gk < K) ? l[(int64_t)gr * K + gk] : make_double2(0.0, 0.0);
+      const int lrw = e >> 4, lk = e & 15;
+      const int gr = r0 + lrw, gk = k0 + lk;
+      Ls[lrw][lk] = (gr < K && gk < K) ? l[(int64_t)gr * K + gk] : make_double2(0.0, 0.0);
       const int rk = e >> 6, rq = e & 63;
       const int gk2 = k0 + rk, gq = q0 + rq;
       const bool in = gk2 < K && gq < K;
@@ -236,37 +303,32 @@ __global__ void __launch_bounds__(kWideThreads) k_gemm_wide(Items it, const int6
         Rs[rk][rq] = in ? rc[(int64_t)gk2 * K + gq] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < kGK; ++kk) {
-      double2 av[4], bv[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) av[u] = Ls[ty + 16 * u][kk];
+    for (int kk = 0; kk < kGK / 4; ++kk) {
+      const double2 a = Ls[16 * w + lc][4 * kk + lr];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) bv[v] = Rs[kk][tx + 16 * v];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          if (kRealR) {
-            acc[u][v].x = fma(av[u].x, bv[v].x, acc[u][v].x);
-            acc[u][v].y = fma(av[u].y, bv[v].x, acc[u][v].y);
-          } else {
-            acc[u][v] = cfma(av[u], bv[v], acc[u][v]);
-          }
+      for (int t = 0; t < 4; ++t) {
+        const double2 bv = Rs[4 * kk + lr][16 * t + lc];
+        cr[t] = mfma16(a.x, bv.x, cr[t]);
+        ci[t] = mfma16(a.y, bv.x, ci[t]);
+        if (!kRealR) {
+          cr[t] = mfma16(-a.y, bv.y, cr[t]);
+          ci[t] = mfma16(a.x, bv.y, ci[t]);
         }
+      }
     }
     __syncthreads();
   }
   double2* o = out + co;
   const double2* ad = add ? add + co : nullptr;
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int t = 0; t < 4; ++t)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int gr = r0 + ty + 16 * u, gq = q0 + tx + 16 * v;
+    for (int r = 0; r < 4; ++r) {
+      const int gr = r0 + 16 * w + 4 * r + lr, gq = q0 + 16 * t + lc;
       if (gr < K && gq < K) {
         const int64_t e = (int64_t)gr * K + gq;
-        const double2 y = cmul(scale, acc[u][v]);
+        const double2 y = cmul(scale, make_double2(cr[t][r], ci[t][r]));
         o[e] = ad ? cadd(y, ad[e]) : y;
       }
     }
@@ -277,8 +339,9 @@ __global__ void __launch_bounds__(kWideThreads) k_gemm_wide(Items it, const int6
 // in k_invert_wide, X and R chunk-strided as there), with every product
 // exact (two-product by fma) and the sums in double-double (Ogita, Rump and
 // Oishi's Dot2): R is then accurate to a few units of its own size, so one
-// correction X + X R removes the inversion's error to first order.  Tiles
-// as in k_gemm_wide.
+// correction X + X R removes the inversion's error to first order.  64 x 64
+// output tiles of 256 threads (4 x 4 outputs each: rows ty + 16 u, columns
+// tx + 16 v), k-slices of 16 staged in LDS.
 __global__ void __launch_bounds__(kWideThreads) k_residual_wide(Items it, const int64_t* toff,
                                                                 const double* Ar, const double* Hr,
                                                                 const double* Q,
@@ -286,13 +349,7 @@ __global__ void __launch_bounds__(kWideThreads) k_residual_wide(Items it, const 
                                                                 const double2* X, int64_t cstride,
                                                                 double2* R) {
   const int64_t b = blockIdx.x;
-  int lo = 0, hi = it.n_items;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (toff[mid] <= b) lo = mid;
-    else hi = mid;
-  }
-  const int s = lo;
+  const int s = item_of_tile(it, toff, b);
   const int K = it.K[s];
   const int T = (K + kGT - 1) / kGT;
   const int tile = (int)(b - toff[s]);
