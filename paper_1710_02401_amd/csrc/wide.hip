@@ -286,23 +286,35 @@ __global__ void __launch_bounds__(kWideThreads) k_gemm_wide(Items it, const int6
     cr[t] = v4d{0.0, 0.0, 0.0, 0.0};
     ci[t] = v4d{0.0, 0.0, 0.0, 0.0};
   }
-  for (int k0 = 0; k0 < K; k0 += kGK) {
-    // L slice: 64 rows x 16 columns; R slice: 16 rows x 64 columns
+  // the next k-slice is loaded into registers while the current one is
+  // multiplied (L slice: 64 rows x 16 columns; R slice: 16 rows x 64 columns)
+  double2 pl[4], pr[4];
+  auto fetch = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = threadIdx.x + q * kWideThreads;
       const int lrw = e >> 4, lk = e & 15;
       const int gr = r0 + lrw, gk = k0 + lk;
-      Ls[lrw][lk] = (gr < K && gk < K) ? l[(int64_t)gr * K + gk] : make_double2(0.0, 0.0);
+      pl[q] = (gr < K && gk < K) ? l[(int64_t)gr * K + gk] : make_double2(0.0, 0.0);
       const int rk = e >> 6, rq = e & 63;
       const int gk2 = k0 + rk, gq = q0 + rq;
       const bool in = gk2 < K && gq < K;
       if (kRealR)
-        Rs[rk][rq] = make_double2(in ? rr[(int64_t)gk2 * K + gq] : 0.0, 0.0);
+        pr[q] = make_double2(in ? rr[(int64_t)gk2 * K + gq] : 0.0, 0.0);
       else
-        Rs[rk][rq] = in ? rc[(int64_t)gk2 * K + gq] : make_double2(0.0, 0.0);
+        pr[q] = in ? rc[(int64_t)gk2 * K + gq] : make_double2(0.0, 0.0);
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < K; k0 += kGK) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = threadIdx.x + q * kWideThreads;
+      Ls[e >> 4][e & 15] = pl[q];
+      Rs[e >> 6][e & 63] = pr[q];
     }
     __syncthreads();
+    if (k0 + kGK < K) fetch(k0 + kGK);
 #pragma unroll
     for (int kk = 0; kk < kGK / 4; ++kk) {
       const double2 a = Ls[16 * w + lc][4 * kk + lr];
