@@ -8,11 +8,11 @@
 // step's chunk and P_0 = M_c^{-1},
 //   (M^{n+1})^{-1} = sum_k (E_c - E_{n+1})^k P_k,   P_k = (i tau P_0 Q)^k P_0,
 // and the P_k of every chunk are formed once per window: the anchor inverse
-// by Gauss-Jordan (k_invert_wide), the terms by batched complex products
-// (k_gemm_wide), both blocked onto the matrix cores, then packed into
-// symmetric tiles for the recurrence
-// (k_pack_wide).  Matrices are K x K row-major at the item's K^2 offset
-// unless said to be packed.
+// by blocked Gauss-Jordan (k_invert_wide), refined once with a compensated
+// residual (k_residual_wide), the terms by batched complex products
+// (k_gemm_wide), inversion and products on the matrix cores, then packed into
+// symmetric tiles for the recurrence (k_pack_wide).  Matrices are K x K
+// row-major at the item's K^2 offset unless said to be packed.
 #include <hip/hip_runtime.h>
 
 #include <cmath>

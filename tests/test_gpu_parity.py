@@ -359,6 +359,8 @@ def test_series_inverses_match_direct_inversion(name):
         s = _solver(dict(cfg, factor=mode))
         s.run(k_max=3, tol=0.0)
         out[mode] = ([_np(h) for h in s.split_history(s.history())], s.factor_terms())
+        # every item applies the window's common number of terms (0: direct)
+        assert np.all(s.item_terms() == s.factor_terms() + 1)
     A = [_np(a) for a in s.matrix("A")]
     (h_s, terms), (h_d, none) = out["auto"], out["direct"]
     d = _a_norm_diff(h_s, h_d, A)

@@ -190,3 +190,30 @@ def test_wide_single_subdomain(K, n_steps):
     # difference, compared in absolute terms as the narrow tests do below 1e-9
     print(f"[gpu] Res(1) {st['res'][0]:.6e} oracle {res_o[0]:.6e}", flush=True)
     assert abs(st["res"][0] - res_o[0]) <= 1e-7 * res_o[0] + 1e-12
+
+
+def test_wide_reconstruction_matches_oracle():
+    """Reconstruction (Section 4.3) of iterate 1 at the last step of the
+    window, second geometry of the wide workload, at seeded points covering
+    the box (overlap zones included): the mean of the covering subdomains'
+    expansions with 33..256 Gaussians each."""
+    import torch
+    from oracle import reconstruct as o_rec
+    cfg = workloads.get_config("c3-wide")
+    s = _solver(cfg)
+    s.factor(0.0)
+    s.sweep()
+    s.transmit()
+    g = 1
+    prob = o_swr.Problem(dict(cfg, nuclei=cfg["geometries"][g], geometries=None))
+    c0 = prob.initial_coeffs()
+    pts = np.random.default_rng(11).uniform(-20.0, 20.0, size=(400, 1))
+    step = cfg["n_steps"]
+    got = _np(s.reconstruct(torch.from_numpy(pts), step, geom=g))
+    E = o_swr.field(cfg, prob.times())
+    f0 = o_swr.warm_forcing(prob, c0, "plain")
+    h_o = [o_swr.local_cn(prob.sys[i], c0[i], f0[i], E, prob.dt) for i in range(prob.n_sub)]
+    ref = o_rec.reconstruct(prob, [h[step] for h in h_o], pts)
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    print(f"[gpu] wide reconstruction: max rel {err:.3e}", flush=True)
+    assert err <= 1e-10
