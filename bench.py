@@ -92,6 +92,19 @@ def learned_summary(mode):
             "iteration_reduction", "prediction_mse", "max_rel_diff", "all_converged",
             "train_samples", "first_loss", "final_loss", "steps", "seconds")
     res = {k: out[k] for k in keep}
+    # plain SWR with other Robin constants on the same held-out windows: the
+    # optimised-mu baseline the learned guess is to be judged against
+    from paper_1710_02401_amd import studies
+    by_mu = studies.held_out_windows_by_mu(cfg, [-1j, -2.5j, -5j, -10j, -20j, -40j],
+                                           kw["eval_traj"], kw["eval_win"], 2402, 150, 1e-8)
+    res["plain_mean_by_mu"] = {f"{m['mu'][1]:g}i": m["mean_iters"] for m in by_mu}
+    best = min(by_mu, key=lambda m: m["mean_iters"])
+    res["best_mu"] = f"{best['mu'][1]:g}i"
+    # the network trained and evaluated again at that mu
+    out_b, _ = learned.experiment(dict(cfg, mu=best["mu"]), batch=256, lr=1e-3, k_max=150,
+                                  log=lambda m: None, **kw)
+    res["at_best_mu"] = {k: out_b[k] for k in ("plain_mean", "learned_mean", "zero_mean",
+                                              "iteration_reduction", "all_converged")}
     res["workload"] = f"{cfg['name']}, {cfg['n_steps']}-step windows, tol 1e-8"
     return res
 

@@ -1,0 +1,109 @@
+"""Parameter studies of the SWR iteration, run through the library (no
+arithmetic of their own): residual histories and iterations to the residual
+target as functions of the Robin constant mu and of the time step.
+
+Paper passages:
+  * Section 4.1, selection of the transmission conditions: Dirichlet data
+    (classical SWR) versus Robin data (d_n + mu) with mu interface
+    independent, mu > 0 in imaginary time and mu in i R_- in real time.  In
+    this Galerkin setting Dirichlet data has no weak form of its own; the
+    Robin operator divided by mu tends to the identity as |mu| grows, so the
+    classical method is studied as the large-|mu| end of the Robin sweep.
+  * Section 5 (the imaginary-time H2 experiment, figure DT): residual history
+    as a function of the time step at mu = 10, and as a function of mu at a
+    fixed time step.
+
+Run as a module for the figure-DT tables of the two-electron imaginary-time
+workload:  python -m paper_1710_02401_amd.studies
+"""
+import math
+
+import numpy as np
+
+from . import swr as S
+
+
+def residual_history(cfg, k_max, tol=-1.0, depth=0, t0=0.0):
+    """One window of the configuration from its projected initial state:
+    Res(k) for k = 1..iters and whether the target was reached."""
+    s = S.Solver(cfg)
+    try:
+        s.assemble()
+        s.set_initial()
+        st = s.run(k_max=k_max, tol=tol, depth=depth, t0=t0)
+        it = int(st["iters"])
+        return dict(iters=it, converged=bool(st["converged"]),
+                    res=[float(r) for r in st["res"][:min(it, 64)]],
+                    energy=float(st["energy"]) if cfg["mode"] == "tise" else None)
+    finally:
+        s.close()
+
+
+def mu_sweep(cfg, mus, k_max, tol=-1.0):
+    """residual_history for each Robin constant mu (complex)."""
+    out = []
+    for mu in mus:
+        mu = complex(mu)
+        r = residual_history(dict(cfg, mu=[mu.real, mu.imag]), k_max, tol)
+        out.append(dict(mu=[mu.real, mu.imag], **r))
+    return out
+
+
+def dt_sweep(cfg, dts, k_max, tol=-1.0):
+    """residual_history for each time step, the window length kept (the step
+    count rounded to it)."""
+    T = cfg["n_steps"] * cfg["dt"]
+    out = []
+    for dt in dts:
+        n = max(1, int(round(T / dt)))
+        r = residual_history(dict(cfg, dt=T / n, n_steps=n), k_max, tol)
+        out.append(dict(dt=T / n, n_steps=n, **r))
+    return out
+
+
+def held_out_windows_by_mu(cfg, mus, n_traj, n_win, seed, k_max, tol):
+    """Iterations of plain SWR to the residual target for each mu on the
+    learned warm start's held-out windows: the same fields (amplitude
+    U[0.03, 0.07], phase U[0, 2 pi) per trajectory, drawn from `seed` in the
+    same order) and the same windows along each trajectory."""
+    rng = np.random.default_rng(seed)
+    fields = [(float(rng.uniform(0.03, 0.07)), float(rng.uniform(0.0, 2.0 * math.pi)))
+              for _ in range(n_traj)]
+    T = cfg["n_steps"] * cfg["dt"]
+    omega = cfg["field"]["omega"]
+    out = []
+    for mu in mus:
+        mu = complex(mu)
+        s = S.Solver(dict(cfg, mu=[mu.real, mu.imag]))
+        try:
+            s.assemble()
+            iters, conv = [], True
+            for E0, phase in fields:
+                s.set_field(E0, omega, phase)
+                s.set_initial()
+                for w in range(n_win):
+                    st = s.run(k_max=k_max, tol=tol, t0=w * T, warm=S.SWR_WARM_PLAIN)
+                    iters.append(int(st["iters"]))
+                    conv = conv and bool(st["converged"])
+                    s.advance_window()
+        finally:
+            s.close()
+        out.append(dict(mu=[mu.real, mu.imag], mean_iters=float(np.mean(iters)), iters=iters,
+                        all_converged=conv))
+    return out
+
+
+def figure_dt(k_max=30):
+    """The figure-DT study on the two-electron imaginary-time workload:
+    residual histories for several time steps at mu = 10 and for several mu
+    at the workload's time step."""
+    import workloads
+    cfg = workloads.get_config("c2-2e-1d-tise")
+    by_dt = dt_sweep(cfg, [0.2, 0.1, 0.05, 0.025], k_max)
+    by_mu = mu_sweep(cfg, [1.0, 3.0, 10.0, 30.0, 100.0, 1000.0], k_max)
+    return dict(workload=cfg["name"], by_dt=by_dt, by_mu=by_mu)
+
+
+if __name__ == "__main__":
+    import json
+    print(json.dumps(figure_dt()))

@@ -1,0 +1,62 @@
+"""The Robin-constant and time-step studies (Section 4.1 transmission
+conditions; Section 5, figure DT) against the CPU oracle: the residual
+history of each swept value, in real and imaginary time."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import swr as o_swr
+from oracle import tise as o_tise
+
+pytestmark = pytest.mark.gpu
+
+TINY = {c["name"]: c for c in workloads.tiny_configs()}
+
+
+def _close(got, ref):
+    for a, b in zip(got, ref):
+        if b > 1e-9:
+            assert a == pytest.approx(b, rel=1e-7)
+        else:
+            assert abs(a - b) <= 1e-10
+
+
+@pytest.mark.parametrize("mu", [-2j, -20j, 0.5 - 6j, -400j])
+def test_mu_sweep_real_time(mu):
+    """Robin SWR in real time for several mu, including a large |mu| (the
+    Dirichlet end): residual histories as the oracle's."""
+    from paper_1710_02401_amd import studies
+    cfg = TINY["tiny-2d"]
+    out = studies.mu_sweep(cfg, [mu], k_max=5)[0]
+    prob = o_swr.Problem(dict(cfg, mu=[mu.real, mu.imag]))
+    _, res = o_swr.swr_window(prob, prob.initial_coeffs(), iters=5)
+    print(f"[gpu] mu {mu}: {out['res']}", flush=True)
+    assert out["iters"] == 5
+    _close(out["res"], res)
+
+
+@pytest.mark.parametrize("mu", [2.0, 20.0])
+def test_mu_sweep_imaginary_time(mu):
+    from paper_1710_02401_amd import studies
+    cfg = TINY["tiny-2d-tise"]
+    out = studies.mu_sweep(cfg, [mu], k_max=cfg["iters"])[0]
+    prob = o_swr.Problem(dict(cfg, mu=[mu, 0.0]))
+    _, res, en = o_tise.swr_tise(prob, iters=cfg["iters"])
+    print(f"[gpu] tise mu {mu}: energy {out['energy']:.12f} vs {en[-1]:.12f}", flush=True)
+    _close(out["res"], res)
+    assert out["energy"] == pytest.approx(en[-1], rel=1e-10)
+
+
+def test_dt_sweep_keeps_the_window():
+    """Halving the time step doubles the steps of the same window; each
+    history is the oracle's for that step."""
+    from paper_1710_02401_amd import studies
+    cfg = TINY["tiny-2d"]
+    T = cfg["n_steps"] * cfg["dt"]
+    outs = studies.dt_sweep(cfg, [cfg["dt"], cfg["dt"] / 2], k_max=4)
+    for o in outs:
+        assert o["n_steps"] * o["dt"] == pytest.approx(T, rel=1e-14)
+        c = dict(cfg, dt=o["dt"], n_steps=o["n_steps"])
+        prob = o_swr.Problem(c)
+        _, res = o_swr.swr_window(prob, prob.initial_coeffs(), iters=4)
+        _close(o["res"], res)
