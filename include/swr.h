@@ -291,6 +291,16 @@ int32_t swr_get_face_nodes(swr_handle h, double* coords_host, double* weights_ho
  * complex [n_pts] to out_dev (0 where no subdomain covers x). */
 int32_t swr_reconstruct(swr_handle h, int32_t geom, int32_t step, const void* pts_dev,
                         int64_t n_pts, void* out_dev, void* stream);
+/* Antisymmetric reconstruction of two electrons (Appendix A, mirrored
+ * subdomains; Section 5, a posteriori antisymmetrisation): where electron
+ * 2's coordinates come after electron 1's (lexicographic over the space
+ * dimensions), the value is minus swr_reconstruct at the point with the two
+ * electrons exchanged; elsewhere it is swr_reconstruct's.  The result is
+ * antisymmetric under exchange; for an exchange-symmetric state it is the
+ * sign change of Section 5.  Same arguments as swr_reconstruct; SWR_E_ARG
+ * unless there are two electrons. */
+int32_t swr_reconstruct_antisym(swr_handle h, int32_t geom, int32_t step, const void* pts_dev,
+                                int64_t n_pts, void* out_dev, void* stream);
 
 /* TISE local generalized eigenproblems H~_i x = lambda A_i x (Section 4.2):
  * eigenvalues ascending, device double [sum_K], and A-orthonormal

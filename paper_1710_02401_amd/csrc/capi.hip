@@ -1491,16 +1491,28 @@ int32_t swr_get_face_nodes(swr_handle h, double* coords, double* weights, uint64
   return SWR_OK;
 }
 
-int32_t swr_reconstruct(swr_handle h, int32_t geom, int32_t step, const void* pts_dev,
-                        int64_t n_pts, void* out_dev, void* stream) {
+static int32_t reconstruct(swr_handle h, int32_t geom, int32_t step, const void* pts_dev,
+                           int64_t n_pts, int antisym, void* out_dev, void* stream) {
   if (!h || (n_pts > 0 && (!pts_dev || !out_dev))) return fail(h, SWR_E_ARG, "null argument");
   if (geom < 0 || geom >= h->g.desc.n_geom) return fail(h, SWR_E_ARG, "geometry out of range");
   if (step < 0 || step > h->n_T) return fail(h, SWR_E_ARG, "step out of range");
+  if (antisym && h->g.desc.n_elec != 2)
+    return fail(h, SWR_E_ARG, "antisymmetric reconstruction needs two electrons");
   if (!h->initial) return fail(h, SWR_E_STATE, "no coefficients yet");
   HIPCHECK(h, swr::launch_reconstruct(h->items(), geom, step, (int)h->n_T, h->hist(h->cur),
-                                      (const double*)pts_dev, n_pts, (double2*)out_dev,
+                                      (const double*)pts_dev, n_pts, antisym, (double2*)out_dev,
                                       (hipStream_t)stream));
   return SWR_OK;
+}
+
+int32_t swr_reconstruct(swr_handle h, int32_t geom, int32_t step, const void* pts_dev,
+                        int64_t n_pts, void* out_dev, void* stream) {
+  return reconstruct(h, geom, step, pts_dev, n_pts, 0, out_dev, stream);
+}
+
+int32_t swr_reconstruct_antisym(swr_handle h, int32_t geom, int32_t step, const void* pts_dev,
+                                int64_t n_pts, void* out_dev, void* stream) {
+  return reconstruct(h, geom, step, pts_dev, n_pts, 1, out_dev, stream);
 }
 
 int32_t swr_local_eigen(swr_handle h, void* lambda_dev, void* vectors_dev, void* stream) {

@@ -268,8 +268,10 @@ hipError_t launch_global_normalise(const Items& it, const double* W, double2* c0
                                    double* partial, hipStream_t st);
 hipError_t launch_geneig(const Items& it, const double* A, const double* Hr, double* lam,
                          double* X, int* flags, hipStream_t st);
+// antisym: two electrons, the exchanged half from the mirrored point with
+// the sign reversed (points where electron 2 comes after electron 1).
 hipError_t launch_reconstruct(const Items& it, int geom, int step, int n_steps,
-                              const double2* hist, const double* pts, int64_t n_pts,
+                              const double2* hist, const double* pts, int64_t n_pts, int antisym,
                               double2* out, hipStream_t st);
 
 hipError_t launch_face_data(const Items& it, const Nodes& nd, const int32_t* cover,

@@ -2115,13 +2115,29 @@ __global__ void __launch_bounds__(kBlock) k_geneig(Items it, const double* A, co
 
 // ---------------------------------------------------------------------------
 // Reconstruction (Section 4.3): mean of the covering local functions.
+// antisym (two electrons, Appendix A): where electron 2's coordinates come
+// after electron 1's (lexicographically), the value is minus the
+// reconstruction at the point with the two electrons exchanged.
 __global__ void k_reconstruct(Items it, int geom, int step, int n_steps, const double2* hist,
-                              const double* pts, int64_t n_pts, double2* out) {
+                              const double* pts, int64_t n_pts, int antisym, double2* out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_pts) return;
   const int D = it.D;
   double y[4];
   for (int k = 0; k < D; ++k) y[k] = pts[t * D + k];
+  double sign = 1.0;
+  if (antisym) {
+    int a = 0;
+    while (a < it.dim && y[it.dim + a] == y[a]) ++a;
+    if (a < it.dim && y[it.dim + a] > y[a]) {
+      for (int b = 0; b < it.dim; ++b) {
+        const double u = y[b];
+        y[b] = y[it.dim + b];
+        y[it.dim + b] = u;
+      }
+      sign = -1.0;
+    }
+  }
   double2 acc = make_double2(0.0, 0.0);
   int cnt = 0;
   for (int i = 0; i < it.n_sub; ++i) {
@@ -2141,7 +2157,7 @@ __global__ void k_reconstruct(Items it, int geom, int step, int n_steps, const d
     acc = cadd(acc, v);
     ++cnt;
   }
-  out[t] = cnt ? cscale(acc, 1.0 / cnt) : make_double2(0.0, 0.0);
+  out[t] = cnt ? cscale(acc, sign / cnt) : make_double2(0.0, 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -2621,11 +2637,11 @@ hipError_t launch_geneig(const Items& it, const double* A, const double* Hr, dou
 }
 
 hipError_t launch_reconstruct(const Items& it, int geom, int step, int n_steps,
-                              const double2* hist, const double* pts, int64_t n_pts,
+                              const double2* hist, const double* pts, int64_t n_pts, int antisym,
                               double2* out, hipStream_t st) {
   if (n_pts == 0) return hipSuccess;
   hipLaunchKernelGGL(k_reconstruct, dim3(blocks_for(n_pts)), dim3(kBlock), 0, st, it, geom, step,
-                     n_steps, hist, pts, n_pts, out);
+                     n_steps, hist, pts, n_pts, antisym, out);
   return hipGetLastError();
 }
 

@@ -83,7 +83,8 @@ EXPORTS = [
     "swr_bind_workspace", "swr_assemble", "swr_set_initial", "swr_warm_start", "swr_factor",
     "swr_sweep", "swr_transmit", "swr_run", "swr_get_history", "swr_get_forcing",
     "swr_get_initial", "swr_get_matrix", "swr_get_items", "swr_get_terms", "swr_get_boxes",
-    "swr_get_index_maps", "swr_get_face_nodes", "swr_reconstruct", "swr_local_eigen",
+    "swr_get_index_maps", "swr_get_face_nodes", "swr_reconstruct", "swr_reconstruct_antisym",
+    "swr_local_eigen",
     "swr_get_norms", "swr_status_sync", "swr_set_field", "swr_advance_window",
     "swr_time_nodes", "swr_face_data", "swr_learned_features", "swr_learned_targets",
     "swr_learned_apply", "swr_mlp_param_count", "swr_mlp_workspace_bytes", "swr_mlp_forward",
@@ -132,6 +133,7 @@ def load_library(path=LIB_PATH):
         "swr_get_index_maps": (i32, [vp, _c_i32p, u64]),
         "swr_get_face_nodes": (i32, [vp, _c_f64p, _c_f64p, u64]),
         "swr_reconstruct": (i32, [vp, i32, i32, vp, i64, vp, vp]),
+        "swr_reconstruct_antisym": (i32, [vp, i32, i32, vp, i64, vp, vp]),
         "swr_local_eigen": (i32, [vp, vp, vp, vp]),
         "swr_get_norms": (i32, [vp, vp, u64, vp]),
         "swr_status_sync": (i32, [vp, vp]),
@@ -359,10 +361,11 @@ class Solver:
                    ctypes.c_uint64(n))
         return x.reshape(n, 4), w
 
-    def reconstruct(self, pts, step, geom=0):
+    def reconstruct(self, pts, step, geom=0, antisym=False):
         pts = pts.to(self.device, dtype=self.torch.float64).contiguous()
         out = self._complex(pts.shape[0])
-        self._call("swr_reconstruct", ctypes.c_int32(geom), ctypes.c_int32(step), _vp(pts),
+        fn = "swr_reconstruct_antisym" if antisym else "swr_reconstruct"
+        self._call(fn, ctypes.c_int32(geom), ctypes.c_int32(step), _vp(pts),
                    ctypes.c_int64(pts.shape[0]), _vp(out), self._stream())
         return out
 

@@ -197,6 +197,33 @@ def test_reconstruction_matches_oracle():
     assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref))
 
 
+def test_antisymmetric_reconstruction_matches_oracle():
+    """Two electrons (Appendix A): the exchanged half from the mirrored
+    point with the sign reversed, after one sweep, at seeded points of the
+    box; one electron is refused."""
+    import torch
+    from paper_1710_02401_amd.swr import SWRError
+    cfg = _cfg("tiny-2d")
+    s = _solver(cfg)
+    prob = o_swr.Problem(cfg)
+    c0 = prob.initial_coeffs()
+    s.factor(0.0)
+    s.sweep()
+    s.transmit()
+    pts = np.random.default_rng(8).uniform([-6.0, -5.0], [6.0, 5.5], size=(300, 2))
+    step = cfg["n_steps"]
+    got = _np(s.reconstruct(torch.from_numpy(pts), step, antisym=True))
+    E = o_swr.field(cfg, prob.times())
+    f0 = o_swr.warm_forcing(prob, c0, "plain")
+    h_o = [o_swr.local_cn(prob.sys[i], c0[i], f0[i], E, prob.dt) for i in range(prob.n_sub)]
+    ref = o_rec.reconstruct_antisym(prob, [h[step] for h in h_o], pts)
+    assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref))
+    one = _solver(_cfg("tiny-1d"))
+    with pytest.raises(SWRError) as e:
+        one.reconstruct(torch.zeros(4, 1, dtype=torch.float64), 0, antisym=True)
+    assert e.value.code == -1
+
+
 def test_zero_and_given_warm_starts():
     import torch
     cfg = _cfg("tiny-2d")

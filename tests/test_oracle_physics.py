@@ -9,6 +9,7 @@ import scipy.linalg
 import scipy.sparse as sp
 import scipy.sparse.linalg as spl
 
+import workloads
 from oracle import reconstruct, swr, tise
 
 
@@ -259,3 +260,52 @@ def test_swr_imaginary_time_energy_matches_finite_difference_ground_state():
     _, res, en = tise.swr_tise(p, tol=1e-11)
     e_fd = _fd_ground_energy(cfg)
     assert en[-1] == pytest.approx(e_fd, abs=2e-5)
+
+
+def _two_electron_states():
+    """Tiny two-electron decomposition (symmetric under exchange: the same
+    boxes and bases for both coordinates) with random local coefficients,
+    and their exchange-symmetrised copy."""
+    cfg = dict([c for c in workloads.tiny_configs() if c["name"] == "tiny-2d"][0],
+               L=[3, 3], box_lo=[-6.0, -6.0], box_hi=[6.0, 6.0], overlap=[0.8, 0.8],
+               nbasis=[4, 4])
+    p = swr.Problem(cfg)
+    rng = np.random.default_rng(5)
+    c = [rng.standard_normal(s.K) + 1j * rng.standard_normal(s.K) for s in p.dec.subs]
+    # subdomain (i, j) <-> (j, i), basis (a, b) <-> (b, a): the exchanged state
+    L = 3
+    cs = []
+    for s in p.dec.subs:
+        i, j = s.lin % L, s.lin // L
+        m = p.dec.subs[j + L * i]
+        cm = c[m.lin].reshape(4, 4).T.reshape(-1)
+        cs.append(0.5 * (c[s.lin] + cm))
+    return p, c, cs
+
+
+def test_antisymmetric_reconstruction_is_antisymmetric():
+    """Appendix A: psi_A(sigma x) = -psi_A(x) off the diagonal, for any local
+    coefficients; on the side where electron 2 does not come after electron
+    1 it is the plain reconstruction."""
+    p, c, _ = _two_electron_states()
+    x = np.random.default_rng(6).uniform(-6.0, 6.0, size=(300, 2))
+    x = x[np.abs(x[:, 0] - x[:, 1]) > 1e-3]
+    a = reconstruct.reconstruct_antisym(p, c, x)
+    b = reconstruct.reconstruct_antisym(p, c, reconstruct.exchange(x, 1))
+    assert np.allclose(a, -b, rtol=0, atol=1e-14 * np.max(np.abs(a)))
+    keep = ~reconstruct.after(x, 1)
+    assert np.array_equal(a[keep], reconstruct.reconstruct(p, c, x[keep]))
+    assert np.any(keep) and np.any(~keep)
+
+
+def test_antisymmetrisation_of_a_symmetric_state_is_the_sign_change():
+    """For an exchange-symmetric state the construction is Section 5's
+    a posteriori operator: psi where x2 <= x1, -psi where x2 > x1."""
+    p, _, cs = _two_electron_states()
+    x = np.random.default_rng(7).uniform(-6.0, 6.0, size=(300, 2))
+    plain = reconstruct.reconstruct(p, cs, x)
+    assert np.allclose(plain, reconstruct.reconstruct(p, cs, reconstruct.exchange(x, 1)),
+                       rtol=0, atol=1e-13 * np.max(np.abs(plain)))
+    sign = np.where(x[:, 1] > x[:, 0], -1.0, 1.0)
+    assert np.allclose(reconstruct.reconstruct_antisym(p, cs, x), sign * plain,
+                       rtol=0, atol=1e-13 * np.max(np.abs(plain)))
