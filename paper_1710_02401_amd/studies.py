@@ -14,7 +14,8 @@ Paper passages:
     fixed time step.
 
 Run as a module for the figure-DT tables of the two-electron imaginary-time
-workload:  python -m paper_1710_02401_amd.studies
+workload and the paper's ground-state experiments (Tests 2.a, 2.b):
+python -m paper_1710_02401_amd.studies
 """
 import math
 
@@ -104,6 +105,33 @@ def figure_dt(k_max=30):
     return dict(workload=cfg["name"], by_dt=by_dt, by_mu=by_mu)
 
 
+def paper_ground_states(k_max=30):
+    """Section 5, Tests 2.a and 2.b (imaginary-time H2): residual history,
+    energy and wall time per Schwarz iteration of each, k_max iterations."""
+    import time
+
+    import workloads
+    out = []
+    for name in ("paper-test-2a", "paper-test-2b"):
+        cfg = workloads.get_config(name)
+        s = S.Solver(cfg)
+        try:
+            s.assemble()
+            s.set_initial()
+            s.run(k_max=2, tol=-1.0)  # warm-up
+            s.set_initial()
+            s.torch.cuda.synchronize()
+            t = time.perf_counter()
+            st = s.run(k_max=k_max, tol=-1.0)
+            s.torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t) / k_max
+        finally:
+            s.close()
+        out.append(dict(workload=name, iters=int(st["iters"]), energy=float(st["energy"]),
+                        res=[float(r) for r in st["res"][:k_max]], ms_per_iteration=ms))
+    return out
+
+
 if __name__ == "__main__":
     import json
-    print(json.dumps(figure_dt()))
+    print(json.dumps(dict(figure_dt=figure_dt(), ground_states=paper_ground_states())))

@@ -60,3 +60,33 @@ def test_dt_sweep_keeps_the_window():
         prob = o_swr.Problem(c)
         _, res = o_swr.swr_window(prob, prob.initial_coeffs(), iters=4)
         _close(o["res"], res)
+
+
+@pytest.mark.parametrize("name", ["paper-test-2a", "paper-test-2b"])
+def test_paper_ground_state_experiments(name):
+    """Section 5, Tests 2.a and 2.b (imaginary-time H2, 5x5 subdomains of
+    6x6 Gaussians, mu = 10): 6 Schwarz iterations against the oracle --
+    every step of every subdomain, the residuals and the energy."""
+    import torch
+    from paper_1710_02401_amd import Solver
+    cfg = workloads.get_config(name)
+    s = Solver(cfg)
+    s.assemble()
+    s.set_initial()
+    st = s.run(k_max=6, tol=0.0)
+    torch.cuda.synchronize()
+    h_g = [np.real(h.cpu().numpy()) for h in s.split_history(s.history())]
+    prob = o_swr.Problem(cfg)
+    h_o, res, en = o_tise.swr_tise(prob, iters=6)
+    num = den = 0.0
+    for i in range(prob.n_sub):
+        A = prob.sys[i].A
+        d = h_g[i] - h_o[i]
+        num = num + np.einsum("nk,kl,nl->n", d, A, d)
+        den = den + np.einsum("nk,kl,nl->n", h_o[i], A, h_o[i])
+    err = float(np.max(np.sqrt(num / den)))
+    print(f"[gpu] {name}: rel A-norm {err:.3e}, energy {st['energy']:.10f} vs {en[-1]:.10f}",
+          flush=True)
+    assert err <= 1e-10
+    _close(st["res"][:6], res)
+    assert st["energy"] == pytest.approx(en[-1], rel=1e-10)
