@@ -87,6 +87,9 @@ typedef struct swr_desc {
   int32_t quad_nodes;        /* GL nodes per potential quadrature panel       */
   int32_t learned_nodes;     /* time nodes M of the learned warm start, 2..64; 0 = 8 */
   int32_t factor_mode;       /* SWR_FACTOR_AUTO, _DIRECT or _WIDE (swr_factor) */
+  int32_t unnormalized;      /* TISE only: 1 = imaginary-time steps without the
+                                global normalisation, i.e. the heat-type flow
+                                d_t phi = -H~ phi (swr_run reports no energy) */
 } swr_desc;
 
 typedef struct swr_handle_s* swr_handle;

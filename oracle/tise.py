@@ -24,11 +24,17 @@ Paper passages followed:
     A-normalised with the largest-magnitude component made positive.
   * Reading for the stopping rule: a fixed number of imaginary steps per
     Schwarz iteration, so that traces exist at every step.
+  * Without the normalisation (configuration key "unnormalized"), the same
+    steps integrate the heat-type flow d_t phi = -H~ phi; with no potential
+    that is Section 5 Test 1.b's heat equation phi_t = Lap phi in the time
+    variable 2t.
 
 Pinned by: harmonic-oscillator eigenvalues n + 1/2 (and the exact 1/2 of
 a single Gaussian of exponent 1/2), monotone energy decrease of the
-normalised flow on one domain (Section 1.3 proposition), and agreement of
-the SWR energy with a brute-force finite-difference ground state.
+normalised flow on one domain (Section 1.3 proposition), agreement of
+the SWR energy with a brute-force finite-difference ground state, and,
+without normalisation, first-order convergence in the step to the heat
+kernel's exact spreading of a Gaussian.
 """
 import numpy as np
 import scipy.linalg
@@ -40,10 +46,15 @@ def global_norm(prob, cs):
     return float(np.sqrt(sum(float(c @ prob.sys[i].W @ c) for i, c in enumerate(cs))))
 
 
+def normalized(prob):
+    return not prob.cfg.get("unnormalized", False)
+
+
 def initial_state(prob):
-    """Projected phi_0, divided by its global (partition-of-unity) norm."""
+    """Projected phi_0, divided by its global (partition-of-unity) norm
+    (kept as projected without normalisation)."""
     c0 = [np.real(c) for c in prob.initial_coeffs()]
-    nu = global_norm(prob, c0)
+    nu = global_norm(prob, c0) if normalized(prob) else 1.0
     return [c / nu for c in c0]
 
 
@@ -70,7 +81,7 @@ def ngf_iteration(prob, c0, f):
     for n in range(n_T):
         ct = [np.linalg.solve(Ms[i], prob.sys[i].A @ hists[i][n] + 0.5 * dt * f[i][n + 1])
               for i in range(prob.n_sub)]
-        nu = global_norm(prob, ct)
+        nu = global_norm(prob, ct) if normalized(prob) else 1.0
         nus[n + 1] = nu
         for i in range(prob.n_sub):
             hists[i][n + 1] = ct[i] / nu
@@ -96,7 +107,7 @@ def swr_tise(prob, iters=None, tol=None, warm="plain"):
     for k in range(1, iters + 1):
         hists, nus = ngf_iteration(prob, c0, f)
         res.append(swr_mod.residual(prob, hists, prev))
-        energies.append(energy_from_nu(nus[-1], prob.dt))
+        energies.append(energy_from_nu(nus[-1], prob.dt) if normalized(prob) else float("nan"))
         # the transmission condition holds on (t_n, t_{n+1}), before the
         # normalisation at t_{n+1}: neighbours send nu_{n+1} c^{n+1}
         pre = [h * nus[:, None] for h in hists]

@@ -871,7 +871,7 @@ int32_t swr_set_initial(swr_handle h, const void* c0_dev, void* stream) {
                                     h->ptr<double>(h->bCenter), h->ptr<double2>(h->bC0),
                                     h->ptr<int>(h->bFlags), st));
   }
-  if (h->g.desc.mode == SWR_TISE)
+  if (h->g.desc.mode == SWR_TISE && !h->g.desc.unnormalized)
     HIPCHECK(h, swr::launch_global_normalise(it, h->ptr<double>(h->bW), h->ptr<double2>(h->bC0),
                                              h->ptr<double>(h->bIePart), st));
   h->initial = true;
@@ -1079,13 +1079,14 @@ int32_t swr_sweep(swr_handle h, void* stream) {
   } else {
     // step 0 of every item is the (normalised) initial state
     HIPCHECK(h, swr::launch_fill_history(it, nT, h->ptr<double2>(h->bC0), hist, st));
+    const int norm = h->g.desc.unnormalized ? 0 : 1;
     for (int n = 0; n < nT; ++n)
       HIPCHECK(h, swr::launch_ie_step(it, n, nT, h->g.desc.dt, h->ptr<double>(h->bA),
                                       h->ptr<double>(h->bW), h->ptr<double2>(h->bMinv),
                                       h->F_of(k), hist, h->ptr<double>(h->bIePart),
-                                      h->ptr<double>(h->bNus), h->ptr<int>(h->bFlags), st));
+                                      h->ptr<double>(h->bNus), norm, h->ptr<int>(h->bFlags), st));
     HIPCHECK(h, swr::launch_ie_finish(it, nT, hist, h->ptr<double>(h->bIePart),
-                                      h->ptr<double>(h->bNus), st));
+                                      h->ptr<double>(h->bNus), norm, st));
   }
   h->cur = k % h->n_slots;
   h->k = k;
@@ -1389,7 +1390,7 @@ int32_t swr_run(swr_handle h, const swr_run_opts* o, swr_run_stats* stats, void*
     HIPCHECK(h, hipMemcpyAsync(&nu, h->ptr<double>(h->bNus) + h->n_T, 8, hipMemcpyDeviceToHost,
                                (hipStream_t)stream));
     HIPCHECK(h, hipStreamSynchronize((hipStream_t)stream));
-    s.energy = (1.0 / nu - 1.0) / h->g.desc.dt;
+    s.energy = h->g.desc.unnormalized ? std::nan("") : (1.0 / nu - 1.0) / h->g.desc.dt;
   }
   HIPCHECK(h, tcollect(h, &s));
   if (stats) *stats = s;

@@ -86,6 +86,8 @@ std::string build_geometry(const swr_desc& d, Geometry* g, int* code) {
     return "learned_nodes must be 0 (default 8) or in 2..64";
   if (d.factor_mode < 0 || d.factor_mode > 2)
     return "factor_mode must be 0 (auto), 1 (direct) or 2 (wide)";
+  if (d.unnormalized != 0 && d.unnormalized != 1) return "unnormalized must be 0 or 1";
+  if (d.unnormalized && d.mode != SWR_TISE) return "unnormalized applies to imaginary time only";
   if (!(d.eps_en > 0.0) || !(d.eps_ee > 0.0)) return "soft-Coulomb eps must be > 0";
   if (!(d.width > 0.0) && !(d.width_ratio > 0.0)) return "width or width_ratio must be > 0";
   if (d.basis_extend < 0) return "basis_extend must be >= 0";

@@ -258,12 +258,13 @@ hipError_t launch_forcing_from_nodes(const Items& it, const Nodes& nd, int n_ste
 hipError_t launch_residual(const Items& it, int n_steps, double dt, const double* G,
                            const double2* cur, const double2* prev, double* partial,
                            double* out, hipStream_t st);
+// normalize = 0: imaginary-time steps without the global normalisation
 hipError_t launch_ie_step(const Items& it, int n, int n_steps, double dt, const double* A,
                           const double* W, const double2* Minv, const double2* F,
-                          double2* hist, double* partial, double* nus, int* flags,
-                          hipStream_t st);
+                          double2* hist, double* partial, double* nus, int normalize,
+                          int* flags, hipStream_t st);
 hipError_t launch_ie_finish(const Items& it, int n_steps, double2* hist, const double* partial,
-                            double* nus, hipStream_t st);
+                            double* nus, int normalize, hipStream_t st);
 hipError_t launch_global_normalise(const Items& it, const double* W, double2* c0,
                                    double* partial, hipStream_t st);
 hipError_t launch_geneig(const Items& it, const double* A, const double* Hr, double* lam,

@@ -235,7 +235,9 @@ __global__ void k_pot2_en(Items it, Potential pot, double* scratch, const int64_
   double* base = scratch + scratch_off[s];
   const int geom = s / it.n_sub;
   const double e2 = pot.eps_en * pot.eps_en;
-  for (int m = 0; m < it.n_elec && pot.n_nuc > 0; ++m) {
+  // written for every electron, zero without nuclei (the combine stage
+  // reads every electron's table)
+  for (int m = 0; m < it.n_elec; ++m) {
     const int k0 = 2 * m, k1 = 2 * m + 1;
     const int P0 = it.nb[4 * s + k0] * it.nb[4 * s + k0], P1 = it.nb[4 * s + k1] * it.nb[4 * s + k1];
     const double* x0 = it.qx + it.qoff[4 * s + k0];
@@ -1861,11 +1863,12 @@ __device__ inline double norm_from_partials(const double* partial, int n_items, 
   return sqrt(block_sum(acc, red));
 }
 
+// normalize = 0: the flow without normalisation (nu = 1 at every step)
 __global__ void __launch_bounds__(kBlock) k_ie_step(Items it, int n, int n_steps, double dt,
                                                     const double* A, const double* W,
                                                     const double2* Minv, const double2* F,
                                                     double2* hist, double* partial, double* nus,
-                                                    int* flags) {
+                                                    int normalize, int* flags) {
   const int s = blockIdx.x;
   const int K = it.K[s];
   __shared__ double c[kSmallK];
@@ -1874,7 +1877,7 @@ __global__ void __launch_bounds__(kBlock) k_ie_step(Items it, int n, int n_steps
   __shared__ double red[kBlock];
   const int64_t hb = (int64_t)(n_steps + 1) * it.off1[s];
   double nu = 1.0;
-  if (n > 0) nu = norm_from_partials(partial + (int64_t)n * it.n_items, it.n_items, red);
+  if (n > 0 && normalize) nu = norm_from_partials(partial + (int64_t)n * it.n_items, it.n_items, red);
   if (s == 0 && threadIdx.x == 0) nus[n] = nu;
   for (int r = threadIdx.x; r < K; r += blockDim.x) {
     const double v = hist[hb + (int64_t)n * K + r].x / nu;
@@ -1909,11 +1912,12 @@ __global__ void __launch_bounds__(kBlock) k_ie_step(Items it, int n, int n_steps
 }
 
 __global__ void k_ie_finish(Items it, int n_steps, double2* hist, const double* partial,
-                            double* nus) {
+                            double* nus, int normalize) {
   const int s = blockIdx.x;
   const int K = it.K[s];
   __shared__ double red[kBlock];
-  const double nu = norm_from_partials(partial + (int64_t)n_steps * it.n_items, it.n_items, red);
+  const double nu =
+      normalize ? norm_from_partials(partial + (int64_t)n_steps * it.n_items, it.n_items, red) : 1.0;
   if (s == 0 && threadIdx.x == 0) nus[n_steps] = nu;
   const int64_t hb = (int64_t)(n_steps + 1) * it.off1[s];
   for (int r = threadIdx.x; r < K; r += blockDim.x) {
@@ -2609,17 +2613,17 @@ hipError_t launch_residual(const Items& it, int n_steps, double dt, const double
 
 hipError_t launch_ie_step(const Items& it, int n, int n_steps, double dt, const double* A,
                           const double* W, const double2* Minv, const double2* F,
-                          double2* hist, double* partial, double* nus, int* flags,
-                          hipStream_t st) {
+                          double2* hist, double* partial, double* nus, int normalize,
+                          int* flags, hipStream_t st) {
   hipLaunchKernelGGL(k_ie_step, dim3(it.n_items), dim3(kBlock), 0, st, it, n, n_steps, dt, A, W,
-                     Minv, F, hist, partial, nus, flags);
+                     Minv, F, hist, partial, nus, normalize, flags);
   return hipGetLastError();
 }
 
 hipError_t launch_ie_finish(const Items& it, int n_steps, double2* hist, const double* partial,
-                            double* nus, hipStream_t st) {
+                            double* nus, int normalize, hipStream_t st) {
   hipLaunchKernelGGL(k_ie_finish, dim3(it.n_items), dim3(kBlock), 0, st, it, n_steps, hist,
-                     partial, nus);
+                     partial, nus, normalize);
   return hipGetLastError();
 }
 

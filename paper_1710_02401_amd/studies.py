@@ -14,7 +14,7 @@ Paper passages:
     fixed time step.
 
 Run as a module for the figure-DT tables of the two-electron imaginary-time
-workload and the paper's ground-state experiments (Tests 2.a, 2.b):
+workload and the paper's imaginary-time experiments (Tests 1.b, 2.a, 2.b):
 python -m paper_1710_02401_amd.studies
 """
 import math
@@ -105,14 +105,16 @@ def figure_dt(k_max=30):
     return dict(workload=cfg["name"], by_dt=by_dt, by_mu=by_mu)
 
 
-def paper_ground_states(k_max=30):
-    """Section 5, Tests 2.a and 2.b (imaginary-time H2): residual history,
-    energy and wall time per Schwarz iteration of each, k_max iterations."""
+def paper_experiments(k_max=30):
+    """Section 5, Test 1.b (heat equation) and Tests 2.a and 2.b
+    (imaginary-time H2): residual history, energy (none for the heat
+    equation) and wall time per Schwarz iteration of each, k_max
+    iterations."""
     import time
 
     import workloads
     out = []
-    for name in ("paper-test-2a", "paper-test-2b"):
+    for name in ("paper-test-1b", "paper-test-2a", "paper-test-2b"):
         cfg = workloads.get_config(name)
         s = S.Solver(cfg)
         try:
@@ -134,4 +136,4 @@ def paper_ground_states(k_max=30):
 
 if __name__ == "__main__":
     import json
-    print(json.dumps(dict(figure_dt=figure_dt(), ground_states=paper_ground_states())))
+    print(json.dumps(dict(figure_dt=figure_dt(), experiments=paper_experiments())))

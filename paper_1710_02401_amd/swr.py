@@ -42,7 +42,7 @@ class swr_desc(ctypes.Structure):
         ("init_center", ctypes.c_double * 4),
         ("face_nodes_band", ctypes.c_int32), ("face_nodes_mid", ctypes.c_int32),
         ("quad_nodes", ctypes.c_int32), ("learned_nodes", ctypes.c_int32),
-        ("factor_mode", ctypes.c_int32),
+        ("factor_mode", ctypes.c_int32), ("unnormalized", ctypes.c_int32),
     ]
 
 
@@ -216,6 +216,7 @@ def desc_from_config(cfg):
     d.learned_nodes = int(cfg.get("learned_nodes", 0))
     d.factor_mode = {"auto": SWR_FACTOR_AUTO, "direct": SWR_FACTOR_DIRECT,
                      "wide": SWR_FACTOR_WIDE}[cfg.get("factor", "auto")]
+    d.unnormalized = 1 if cfg.get("unnormalized", False) else 0
     return d, (arr, pos, chg)
 
 

@@ -309,3 +309,33 @@ def test_antisymmetrisation_of_a_symmetric_state_is_the_sign_change():
     sign = np.where(x[:, 1] > x[:, 0], -1.0, 1.0)
     assert np.allclose(reconstruct.reconstruct_antisym(p, cs, x), sign * plain,
                        rtol=0, atol=1e-13 * np.max(np.abs(plain)))
+
+
+def test_unnormalized_flow_is_the_heat_equation():
+    """Without normalisation and without potential, the imaginary-time steps
+    solve phi_t = 1/2 Lap phi (Test 1.b's phi_t = Lap phi in the time 2t):
+    exp(-a x^2) spreads as (1 + 2 a t)^(-1/2) exp(-a x^2 / (1 + 2 a t)).  One
+    subdomain on a box wide enough for the absorbing faces not to matter;
+    the error at t = 1 falls by about half when the step halves (implicit
+    Euler), so the flow, not just its shape, is the heat flow."""
+    a, T = 0.5, 1.0
+    base = dict(mode="tise", unnormalized=True, n_elec=1, dim=1, L=[1], box_lo=[-14.0],
+                box_hi=[14.0], overlap=[0.0], nbasis=[60], width=None, width_ratio=0.7,
+                nuclei=[], charges=[], eps_en=1.0, eps_ee=1.0, mu=[1.0, 0.0],
+                field=dict(E0=0.0, omega=0.0, phase=0.0, axis=0),
+                init=dict(alpha=a, center=[0.0]), iters=1, tol=None, face_nodes=[1, 1],
+                quad_nodes=16, name="heat-pin")
+    x = np.linspace(-3.0, 3.0, 61)
+    norm0 = (2.0 * a / math.pi) ** 0.25
+    exact = norm0 * (1 + 2 * a * T) ** -0.5 * np.exp(-a * x ** 2 / (1 + 2 * a * T))
+    errs = []
+    for n in (20, 40, 80):
+        cfg = dict(base, dt=T / n, n_steps=n)
+        p = swr.Problem(cfg)
+        h, _, en = tise.swr_tise(p, iters=1)
+        assert math.isnan(en[0])
+        psi = reconstruct.reconstruct(p, [hh[-1] for hh in h], x[:, None])
+        errs.append(float(np.max(np.abs(psi - exact)) / np.max(exact)))
+    assert errs[0] < 2e-2
+    for e1, e2 in zip(errs, errs[1:]):
+        assert 1.7 < e1 / e2 < 2.3

@@ -160,8 +160,25 @@ _T2B = dict(_T2A, name="paper-test-2b", box_lo=[-6.5, -6.5], box_hi=[6.5, 6.5],
             nuclei=[[-0.5], [0.5]], dt=0.01, n_steps=400,
             init=dict(alpha=0.8, center=[0.0, 0.0]))
 
+# Section 5, Test 1.b: the heat equation phi_t = Lap phi on (-15, 15)^2, 5x5
+# subdomains of 6x6 Gaussians, mu = 1, phi_0 = exp(-0.2 |x|^2), T = 16 with
+# steps of about 0.213 (75 steps).  It is run as the imaginary-time flow
+# without normalisation and without potential, d_t phi = 1/2 Lap phi, over
+# the time 2t (so dt = 2 x 16/75).  Readings: overlap 10 % of box/L, widths
+# 0.7 x spacing (the test gives neither).
+_T1B = dict(
+    name="paper-test-1b", mode="tise", unnormalized=True, n_elec=1, dim=2,
+    L=[5, 5], box_lo=[-15.0, -15.0], box_hi=[15.0, 15.0], overlap=[0.6, 0.6],
+    nbasis=[6, 6], width=None, width_ratio=0.7,
+    nuclei=[], charges=[], eps_en=1.0, eps_ee=1.0,
+    dt=2.0 * 16.0 / 75.0, n_steps=75, mu=[1.0, 0.0],
+    field=dict(E0=0.0, omega=0.0, phase=0.0, axis=0),
+    init=dict(alpha=0.2, center=[0.0, 0.0]),
+    iters=30, tol=1e-8, face_nodes=[16, 32], quad_nodes=16,
+)
+
 CONFIGS = {c["name"]: c for c in (_C1, _C2, _C2_TISE, _C3, _C3_MINI, _C3_WIDE, _C4, _C5,
-                                   _C5_MINI, _C5_MINI_1E, _T2A, _T2B)}
+                                   _C5_MINI, _C5_MINI_1E, _T1B, _T2A, _T2B)}
 
 
 def get_config(name, **overrides):
