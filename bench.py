@@ -192,6 +192,51 @@ def batched_summary(iters, cpu=True):
     return out
 
 
+def tise_summary(iters=20):
+    """Imaginary time on the two-electron workload (row a10): the ground
+    state window (400 normalised implicit-Euler steps per Schwarz
+    iteration, one launch per step: the normalisation couples every item at
+    every step) and the local generalised eigenproblems.  Step bytes per
+    (item, step): A, the inverse (complex storage, real part used) and W,
+    K^2 entries each (8 + 16 + 8 B), the coefficients in and out (16 K B);
+    the sweep's HIP-event time includes the gaps between its launches."""
+    import torch
+
+    import workloads
+    from paper_1710_02401_amd import Solver
+    cfg = workloads.get_config("c2-2e-1d-tise")
+    s = Solver(cfg)
+    s.assemble()
+    s.set_initial()
+    s.run(k_max=2, tol=-1.0)
+    s.set_initial()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    st = s.run(k_max=iters, tol=-1.0, timing=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    n, K, nT = int(s.info.n_items), int(s.info.K_max), int(s.n_steps)
+    sweep_ms = st["kernels"]["recur"]["ms"] / st["kernels"]["recur"]["launches"]
+    step_bytes = n * nT * (32.0 * K * K + 16.0 * K)
+    achieved = step_bytes / (sweep_ms * 1e-3) / 1e9
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    s.local_eigen()
+    torch.cuda.synchronize()
+    eig_ms = 1e3 * (time.perf_counter() - t)
+    return {
+        "workload": f"{cfg['name']}: {n} subdomains, K={K}, {nT} imaginary-time steps of "
+                    f"{cfg['dt']} per Schwarz iteration, mu = {cfg['mu'][0]:g}",
+        "ms_per_iteration": 1e3 * wall / iters, "energy": st["energy"],
+        "last_residual": st["res"][iters - 1],
+        "subdomain_solves_per_s": n * iters / wall,
+        "roofline": {"kernel": "k_ie_step (one sweep)", "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None},
+        "local_eigen_ms": eig_ms,
+    }
+
+
 def wide_digest():
     import hashlib
     path = os.path.join(HERE, "paper_1710_02401_amd", "csrc", "wide.hip")
@@ -334,6 +379,7 @@ def main():
     per_it = sum(lit[k]["ms"] for k in ("recur", "transmit", "residual")) / 3
     out["paper_literal_sweep_ms"] = lit["factor"]["ms"] + per_it
     out["wavefront_ms_per_iteration"] = ms_step / iters
+    out["imaginary_time"] = tise_summary()
     if args.batched_iters > 0:
         del s
         torch.cuda.empty_cache()

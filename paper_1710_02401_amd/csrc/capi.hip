@@ -1080,6 +1080,7 @@ int32_t swr_sweep(swr_handle h, void* stream) {
     // step 0 of every item is the (normalised) initial state
     HIPCHECK(h, swr::launch_fill_history(it, nT, h->ptr<double2>(h->bC0), hist, st));
     const int norm = h->g.desc.unnormalized ? 0 : 1;
+    HIPCHECK(h, tbegin(h, st, kTRecur));  // the sweep's n_T step launches
     for (int n = 0; n < nT; ++n)
       HIPCHECK(h, swr::launch_ie_step(it, n, nT, h->g.desc.dt, h->ptr<double>(h->bA),
                                       h->ptr<double>(h->bW), h->ptr<double2>(h->bMinv),
@@ -1087,6 +1088,7 @@ int32_t swr_sweep(swr_handle h, void* stream) {
                                       h->ptr<double>(h->bNus), norm, h->ptr<int>(h->bFlags), st));
     HIPCHECK(h, swr::launch_ie_finish(it, nT, hist, h->ptr<double>(h->bIePart),
                                       h->ptr<double>(h->bNus), norm, st));
+    HIPCHECK(h, tend(h, st));
   }
   h->cur = k % h->n_slots;
   h->k = k;
