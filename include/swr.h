@@ -90,7 +90,22 @@ typedef struct swr_desc {
   int32_t unnormalized;      /* TISE only: 1 = imaginary-time steps without the
                                 global normalisation, i.e. the heat-type flow
                                 d_t phi = -H~ phi (swr_run reports no energy) */
+  /* Field shape (SWR_FIELD_SINE: the single component above along `axis` of
+   * every electron).  SWR_FIELD_CIRCULAR, the circular pulse of Section 5
+   * Test 3: two components
+   *   E_1(t) = E0 cos(omega t + phase) exp(-pulse_nu (t - pulse_center)^2),
+   *   E_2(t) = E0 sin(omega t + phase) exp(-pulse_nu (t - pulse_center)^2),
+   * component c coupling to the sum of the configuration coordinates whose
+   * bits (el * dim + a) are set in field_mask[c] (non-empty, disjoint masks
+   * within the D coordinates; real time only).  Every M^n then carries
+   * E_1(t_n) Q_1 + E_2(t_n) Q_2, so swr_factor inverts every step (the
+   * series in one scalar E does not apply) and `axis` is not used. */
+  int32_t field_shape;
+  double pulse_nu, pulse_center;
+  int32_t field_mask[2];
 } swr_desc;
+
+enum { SWR_FIELD_SINE = 0, SWR_FIELD_CIRCULAR = 1 };
 
 typedef struct swr_handle_s* swr_handle;
 
@@ -180,7 +195,9 @@ int32_t swr_warm_start(swr_handle h, int32_t mode, const void* g_dev, void* stre
  * swr_sweep applies the sum to each step's right-hand side, each item with
  * the terms its own box needs (the bound above with the item's X); the
  * bound must hold with K <= 5, else SWR_E_SIZE (as for Im mu > 0 or
- * SWR_FACTOR_DIRECT, which the wide path refuses at creation). */
+ * SWR_FACTOR_DIRECT, which the wide path refuses at creation).
+ * A circular field (SWR_FIELD_CIRCULAR) has two scalars per step: every M^n
+ * is inverted. */
 enum { SWR_FACTOR_AUTO = 0, SWR_FACTOR_DIRECT = 1, SWR_FACTOR_WIDE = 2 };
 int32_t swr_factor(swr_handle h, double t0, void* stream);
 
@@ -266,7 +283,8 @@ int32_t swr_get_forcing(swr_handle h, void* dst_dev, uint64_t bytes, void* strea
 /* Initial coefficients (complex, sum_K). */
 int32_t swr_get_initial(swr_handle h, void* dst_dev, uint64_t bytes, void* stream);
 /* Assembled real matrices, which = 0 A, 1 Kin, 2 V, 3 Q, 4 B, 5 W, 6 face
- * Gram G; item s occupies K_s*K_s row-major entries, items in order. */
+ * Gram G, 7 Q2 (the second component's dipole, circular field only, else
+ * SWR_E_ARG); item s occupies K_s*K_s row-major entries, items in order. */
 int32_t swr_get_matrix(swr_handle h, int32_t which, void* dst_dev, uint64_t bytes, void* stream);
 /* Per-item sizes: host int32 [n_items][2 + 2*4]: K, n_face_nodes, then the
  * multi-index and the per-dimension basis sizes (padded with 0). */
@@ -332,7 +350,8 @@ int32_t swr_get_norms(swr_handle h, void* dst_dev, uint64_t bytes, void* stream)
  * M = 16, >= 195 for M = 32): on shorter windows swr_time_nodes and the
  * three swr_learned_* calls return SWR_E_ARG. */
 
-/* Change the field E(t) = E0 sin(omega t + phase) used by later swr_factor. */
+/* Change E0, omega and phase of the field (either shape; the pulse envelope
+ * and the masks are kept) used by later swr_factor. */
 int32_t swr_set_field(swr_handle h, double E0, double omega, double phase);
 /* Start the next window: initial coefficients := last step of the current
  * iterate, then the plain warm start (as swr_set_initial). */

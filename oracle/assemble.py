@@ -83,9 +83,16 @@ class LocalSystem:
         self.Kin = sum(embed(k, Kin[k]) for k in range(D))
         self.B = sum(embed(k, Bk[k]) for k in range(D))
         self.W = kron_all(Wk)
-        ax = int(cfg["field"]["axis"])
-        dim = cfg["dim"]
-        self.Q = sum(embed(m * dim + ax, X[m * dim + ax]) for m in range(cfg["n_elec"]))
+        # dipole matrices: x_k summed over the coordinates the field couples
+        # to -- the field axis of every electron (eq. (LG)), or for the
+        # circular field of Section 5, Test 3, each component's own list of
+        # configuration coordinates k = electron * dim + axis
+        f = cfg["field"]
+        if f.get("shape", "sine") == "circular":
+            self.Q, self.Q2 = (sum(embed(k, X[k]) for k in f["coords"][c]) for c in range(2))
+        else:
+            ax, dim = int(f["axis"]), cfg["dim"]
+            self.Q = sum(embed(m * dim + ax, X[m * dim + ax]) for m in range(cfg["n_elec"]))
         self.V = potential_matrix(dec, s)
         mu = complex(cfg["mu"][0], cfg["mu"][1])
         self.mu = mu

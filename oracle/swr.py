@@ -33,9 +33,26 @@ from .geometry import Decomposition
 
 
 def field(cfg, t):
-    """E(t) = E0 sin(omega t + phase) (dipole approximation, eq. (LG))."""
+    """E(t) = E0 sin(omega t + phase) (dipole approximation, eq. (LG)): one
+    value per time.  The circular pulse of Section 5, Test 3, has two
+    components, E0 cos(omega t + phase) g(t) and E0 sin(omega t + phase) g(t)
+    with the envelope g(t) = exp(-nu (t - center)^2) (the test centres it at
+    T/2): an array [n][2]."""
     f = cfg["field"]
-    return f["E0"] * np.sin(f["omega"] * np.asarray(t, dtype=np.float64) + f["phase"])
+    t = np.asarray(t, dtype=np.float64)
+    if f.get("shape", "sine") == "circular":
+        g = np.exp(-f["nu"] * (t - f["center"]) ** 2)
+        arg = f["omega"] * t + f["phase"]
+        return np.stack([f["E0"] * np.cos(arg) * g, f["E0"] * np.sin(arg) * g], axis=-1)
+    return f["E0"] * np.sin(f["omega"] * t + f["phase"])
+
+
+def field_term(sy, En):
+    """T(t_n) = sum over components of E_c(t_n) Q_c (eq. (Q), the dipole
+    matrix of each component's coordinates)."""
+    if np.ndim(En) == 0:
+        return En * sy.Q
+    return En[0] * sy.Q + En[1] * sy.Q2
 
 
 def basis_values(s, pts):
@@ -118,14 +135,15 @@ def local_cn(sy, c0, f, E, dt):
     """Crank-Nicolson over one window for one subdomain.
 
     c0: (K,) initial coefficients; f: (n_T+1, K) Robin data vectors;
-    E: (n_T+1,) field at the time nodes.  Returns (n_T+1, K) history."""
+    E: field at the time nodes, (n_T+1,) or (n_T+1, 2) for a two-component
+    field.  Returns (n_T+1, K) history."""
     tau = 0.5 * dt
     n_T = len(E) - 1
     hist = np.empty((n_T + 1, sy.K), dtype=np.complex128)
     hist[0] = c0
     for n in range(n_T):
-        M = sy.A + 1j * tau * (sy.Htilde + E[n + 1] * sy.Q)
-        R = sy.A - 1j * tau * (sy.Htilde + E[n] * sy.Q)
+        M = sy.A + 1j * tau * (sy.Htilde + field_term(sy, E[n + 1]))
+        R = sy.A - 1j * tau * (sy.Htilde + field_term(sy, E[n]))
         rhs = R @ hist[n] + 0.5j * tau * (f[n] + f[n + 1])
         hist[n + 1] = np.linalg.solve(M, rhs)
     return hist

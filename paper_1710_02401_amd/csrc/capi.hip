@@ -82,6 +82,7 @@ struct swr_handle_s {
   int n_res_tiles = 0;
   std::vector<int64_t> s1off, scratch_off;
   std::vector<double> E_host;   // field table, kept alive for the async upload
+  std::vector<double> E2_host;  // the second component's (circular field)
   std::vector<double> lag_host; // Lagrange rows of the learned warm start
 
   // workspace
@@ -95,6 +96,7 @@ struct swr_handle_s {
   Buf bPI, bPJ, bPOff, bTOff, bPNode, bPNOff;
   Buf bPos, bCharge, bS1Off, bS1, bScrOff, bScr, bCenter;
   Buf bA, bKin, bV, bQ, bB, bW, bG, bAr, bAp, bHr;
+  Buf bQ2, bE2;  // second component of a circular field (else unallocated)
   Buf bTePair, bTeFace, bTeT0, bTeT1, bTeOff, bTeBoff, bTeAoff, bTeXoff, bTeBeta, bTeA, bTeX;
   Buf bTeSoff, bTeSidx, bTeV, bTeBlobOff, bTeBlob, bTeSdesc, bTeGramOff, bTeGram, bTeFnode;
   Buf bParts;                        // residual partials of the factored transmission
@@ -176,7 +178,14 @@ struct swr_handle_s {
     it.D = g.D;
     it.n_elec = g.desc.n_elec;
     it.dim = g.desc.dim;
-    it.axis = g.desc.axis;
+    if (g.desc.field_shape == SWR_FIELD_CIRCULAR) {
+      it.qmask0 = g.desc.field_mask[0];
+      it.qmask1 = g.desc.field_mask[1];
+      it.Q2 = ptr<double>(bQ2);
+      it.E2 = ptr<double>(bE2);
+    } else {
+      for (int el = 0; el < g.desc.n_elec; ++el) it.qmask0 |= 1 << (el * g.desc.dim + g.desc.axis);
+    }
     it.K = ptr<int32_t>(bK);
     it.off1 = ptr<int64_t>(bOff1);
     it.off2 = ptr<int64_t>(bOff2);
@@ -336,6 +345,10 @@ void plan_layout(swr_handle h) {
   h->bKin = L.add(m2);
   h->bV = L.add(m2);
   h->bQ = L.add(m2);
+  if (g.desc.field_shape == SWR_FIELD_CIRCULAR) {
+    h->bQ2 = L.add(m2);
+    h->bE2 = L.add((h->n_T + 1) * 8);
+  }
   h->bB = L.add(m2);
   h->bW = L.add(m2);
   h->bG = L.add(m2);
@@ -418,7 +431,18 @@ int check_flags(swr_handle h, hipStream_t st) {
   return SWR_OK;
 }
 
-double field(const swr_desc& d, double t) { return d.E0 * std::sin(d.omega * t + d.phase); }
+// The field's first (or only) component at time t, and the second of a
+// circular pulse (Section 5 Test 3).
+double field(const swr_desc& d, double t) {
+  if (d.field_shape == SWR_FIELD_CIRCULAR)
+    return d.E0 * std::cos(d.omega * t + d.phase) *
+           std::exp(-d.pulse_nu * (t - d.pulse_center) * (t - d.pulse_center));
+  return d.E0 * std::sin(d.omega * t + d.phase);
+}
+double field2(const swr_desc& d, double t) {
+  return d.E0 * std::sin(d.omega * t + d.phase) *
+         std::exp(-d.pulse_nu * (t - d.pulse_center) * (t - d.pulse_center));
+}
 
 // kinds of timed launches
 enum { kTFactor = 0, kTTransmit = 1, kTRecur = 2, kTResidual = 3 };
@@ -813,8 +837,9 @@ int32_t swr_assemble(swr_handle h, void* stream) {
   const swr::Nodes nd = h->nodes();
   const swr::Pairs pr = h->pairs();
   HIPCHECK(h, swr::launch_assemble(it, h->ptr<double>(h->bA), h->ptr<double>(h->bKin),
-                                   h->ptr<double>(h->bQ), h->ptr<double>(h->bB),
-                                   h->ptr<double>(h->bW), h->ptr<double>(h->bS1),
+                                   h->ptr<double>(h->bQ), it.Q2 ? h->ptr<double>(h->bQ2) : nullptr,
+                                   h->ptr<double>(h->bB), h->ptr<double>(h->bW),
+                                   h->ptr<double>(h->bS1),
                                    h->ptr<int64_t>(h->bS1Off), g.K_max, st));
   swr::Potential pot{g.desc.n_nuc, h->ptr<double>(h->bPos), h->ptr<double>(h->bCharge),
                      g.desc.eps_en, g.desc.eps_ee};
@@ -934,13 +959,21 @@ int32_t swr_factor(swr_handle h, double t0, void* stream) {
   h->E_host.assign(h->n_T + 1, 0.0);
   for (int64_t n = 0; n <= h->n_T; ++n) h->E_host[n] = field(h->g.desc, t0 + n * h->g.desc.dt);
   HIPCHECK(h, upload(h, h->bE, h->E_host, st));
+  const bool circular = h->g.desc.field_shape == SWR_FIELD_CIRCULAR;
+  if (circular) {
+    h->E2_host.assign(h->n_T + 1, 0.0);
+    for (int64_t n = 0; n <= h->n_T; ++n)
+      h->E2_host[n] = field2(h->g.desc, t0 + n * h->g.desc.dt);
+    HIPCHECK(h, upload(h, h->bE2, h->E2_host, st));
+  }
   const int tise = h->g.desc.mode == SWR_TISE;
   const double tau = 0.5 * h->g.desc.dt;
   // series around the midpoint of each chunk's field range (TDSE)
   int terms = 0;
   const int n_chunks = (int)((h->n_mats + swr::kSeriesChunk - 1) / swr::kSeriesChunk);
   const int max_terms = h->wide ? swr::kWideTerms : kSeriesMaxTerms;
-  if (!tise && (h->g.desc.factor_mode == SWR_FACTOR_AUTO || h->wide) && h->g.desc.mu_im <= 0.0) {
+  if (!tise && !circular && (h->g.desc.factor_mode == SWR_FACTOR_AUTO || h->wide) &&
+      h->g.desc.mu_im <= 0.0) {
     h->Ea_host.assign(n_chunks, 0.0);
     double half = 0.0;
     for (int c = 0; c < n_chunks; ++c) {
@@ -1427,8 +1460,10 @@ int32_t swr_get_initial(swr_handle h, void* dst_dev, uint64_t bytes, void* strea
 
 int32_t swr_get_matrix(swr_handle h, int32_t which, void* dst_dev, uint64_t bytes, void* stream) {
   if (!h) return SWR_E_ARG;
-  const Buf* bs[] = {&h->bA, &h->bKin, &h->bV, &h->bQ, &h->bB, &h->bW, &h->bG};
-  if (which < 0 || which > 6) return fail(h, SWR_E_ARG, "matrix index out of range");
+  const Buf* bs[] = {&h->bA, &h->bKin, &h->bV, &h->bQ, &h->bB, &h->bW, &h->bG, &h->bQ2};
+  if (which < 0 || which > 7) return fail(h, SWR_E_ARG, "matrix index out of range");
+  if (which == 7 && h->g.desc.field_shape != SWR_FIELD_CIRCULAR)
+    return fail(h, SWR_E_ARG, "Q2 exists for a circular field only");
   return copy_out(h, *bs[which], bs[which]->bytes, dst_dev, bytes, stream);
 }
 

@@ -88,6 +88,17 @@ std::string build_geometry(const swr_desc& d, Geometry* g, int* code) {
     return "factor_mode must be 0 (auto), 1 (direct) or 2 (wide)";
   if (d.unnormalized != 0 && d.unnormalized != 1) return "unnormalized must be 0 or 1";
   if (d.unnormalized && d.mode != SWR_TISE) return "unnormalized applies to imaginary time only";
+  if (d.field_shape != SWR_FIELD_SINE && d.field_shape != SWR_FIELD_CIRCULAR)
+    return "field_shape must be SWR_FIELD_SINE or SWR_FIELD_CIRCULAR";
+  if (d.field_shape == SWR_FIELD_CIRCULAR) {
+    if (d.mode != SWR_TDSE) return "a circular field applies to real time only";
+    const int all = (1 << D) - 1;
+    const int m0 = d.field_mask[0], m1 = d.field_mask[1];
+    if (m0 <= 0 || m1 <= 0 || (m0 & ~all) || (m1 & ~all) || (m0 & m1))
+      return "field_mask must be two non-empty, disjoint sets of the D coordinates";
+    if (!(d.pulse_nu >= 0.0) || !std::isfinite(d.pulse_center))
+      return "pulse_nu must be >= 0 and pulse_center finite";
+  }
   if (!(d.eps_en > 0.0) || !(d.eps_ee > 0.0)) return "soft-Coulomb eps must be > 0";
   if (!(d.width > 0.0) && !(d.width_ratio > 0.0)) return "width or width_ratio must be > 0";
   if (d.basis_extend < 0) return "basis_extend must be >= 0";

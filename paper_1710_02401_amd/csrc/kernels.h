@@ -14,7 +14,15 @@ constexpr int kBlock = 256;      // threads per block of the batched kernels
 
 // Per-item tables (device pointers), passed by value to kernels.
 struct Items {
-  int n_items, n_sub, D, n_elec, dim, axis;
+  int n_items, n_sub, D, n_elec, dim;
+  // configuration coordinates (bit el * dim + a) the field couples to: the
+  // first (or only) component and the second of a circular field (0: none)
+  int qmask0, qmask1;
+  // second field component (circular field only, else null): its dipole
+  // matrix [sum K^2] and its value at the time nodes [n_T + 1]; every M^n
+  // then carries E(t_n) Q + E2(t_n) Q2
+  const double* Q2;
+  const double* E2;
   const int32_t* K;      // [n_items]
   const int64_t* off1;   // [n_items+1] prefix sums of K
   const int64_t* off2;   // [n_items+1] prefix sums of K^2
@@ -173,8 +181,9 @@ __host__ __device__ inline void pot2_layout(const int32_t* nb, const int32_t* qn
 }
 
 // ---- launchers (return hipError_t of the launch) ----
-hipError_t launch_assemble(const Items& it, double* A, double* Kin, double* Q, double* B,
-                           double* W, double* S1, const int64_t* s1off, int K_max,
+// Q2: the second component's dipole matrix (it.qmask1), or null.
+hipError_t launch_assemble(const Items& it, double* A, double* Kin, double* Q, double* Q2,
+                           double* B, double* W, double* S1, const int64_t* s1off, int K_max,
                            hipStream_t st);
 hipError_t launch_potential(const Items& it, const Potential& pot, const double* S1,
                             const int64_t* s1off, double* V, double* scratch,

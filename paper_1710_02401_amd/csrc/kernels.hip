@@ -23,8 +23,8 @@ namespace {
 // ---------------------------------------------------------------------------
 // Assembly of the separable matrices (Section 1.2 Galerkin form, Section 4.1
 // eq. Q, Robin boundary mass, partition-of-unity mass).
-__global__ void k_assemble(Items it, double* A, double* Kin, double* Q, double* B, double* W,
-                           double* S1, const int64_t* s1off) {
+__global__ void k_assemble(Items it, double* A, double* Kin, double* Q, double* Q2, double* B,
+                           double* W, double* S1, const int64_t* s1off) {
   const int s = blockIdx.y;
   const int K = it.K[s];
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -60,17 +60,22 @@ __global__ void k_assemble(Items it, double* A, double* Kin, double* Q, double* 
     kin += tk;
     bsum += bk;
   }
-  for (int el = 0; el < it.n_elec; ++el) {
-    const int km = el * it.dim + it.axis;
+  // dipole of the coordinates in a mask: sum over them of x_k with the
+  // overlaps of the other dimensions
+  double q2 = 0.0;
+  for (int km = 0; km < D; ++km) {
+    if (!((it.qmask0 | it.qmask1) >> km & 1)) continue;
     double x = Xk[km];
     for (int k2 = 0; k2 < D; ++k2)
       if (k2 != km) x *= Sk[k2];
-    q += x;
+    if (it.qmask0 >> km & 1) q += x;
+    if (it.qmask1 >> km & 1) q2 += x;
   }
   const int64_t o = it.off2[s] + (int64_t)l * K + m;
   A[o] = a;
   Kin[o] = kin;
   Q[o] = q;
+  if (Q2) Q2[o] = q2;
   B[o] = bsum;
   W[o] = wprod;
   // per-dimension overlap factors, written by the entry whose other indices are 0
@@ -663,6 +668,10 @@ __global__ void __launch_bounds__(64 * NB) k_invert_mfma(Items it, int n_mats, c
   const int64_t o2 = it.off2[s];
   const bool tise = mode == kInvReal;
   const double E = mode == kInvAt ? Eall[n] : (tise ? 0.0 : Eall[n + 1]);
+  // second component of a circular field (steps only: the series, which
+  // uses the kInvAt mode, is never taken with one)
+  const double* Q2 = mode == kInvSteps ? it.Q2 : nullptr;
+  const double E2 = Q2 ? it.E2[n + 1] : 0.0;
   // the wave's block row; position t holds column block (k + t) mod NB at
   // block step k (rotated after every step), so the pivot block is always
   // position 0 and the step loop need not be unrolled
@@ -675,7 +684,7 @@ __global__ void __launch_bounds__(64 * NB) k_invert_mfma(Items it, int n_mats, c
       if (row < K && col < K) {
         const int64_t e = o2 + (int64_t)row * K + col;
         re[j][r] = Ar[e];
-        im[j][r] = tise ? 0.0 : tau * (Hr[e] + E * Q[e]);
+        im[j][r] = tise ? 0.0 : tau * (Hr[e] + E * Q[e] + (Q2 ? E2 * Q2[e] : 0.0));
       } else {
         re[j][r] = row == col ? 1.0 : 0.0;
         im[j][r] = 0.0;
@@ -1203,8 +1212,9 @@ __global__ void __launch_bounds__(kRecThreads) k_cn_recur(Items it, int n_steps,
     // each wave reads only its own rows, which only it overwrites later
     st.rprev = r < K ? srhs[vpos(r)] : make_double2(0.0, 0.0);
   } else {
-    // M^{n_lo} c^{n_lo} = Ar c + i tau (Hr + E Q) c
+    // M^{n_lo} c^{n_lo} = Ar c + i tau (Hr + E Q + E2 Q2) c
     const double E = Eall[n_lo];
+    const double E2 = it.Q2 ? it.E2[n_lo] : 0.0;
     double ax = 0.0, ay = 0.0, hx = 0.0, hy = 0.0;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -1212,7 +1222,7 @@ __global__ void __launch_bounds__(kRecThreads) k_cn_recur(Items it, int n_steps,
       const bool v = r < K && m < K;
       const int64_t e = o2 + (v ? (int64_t)m * K + r : 0);
       const double a = v ? Ar[e] : 0.0;
-      const double h = v ? fma(E, Q[e], Hr[e]) : 0.0;
+      const double h = v ? fma(E, Q[e], Hr[e]) + (it.Q2 ? E2 * it.Q2[e] : 0.0) : 0.0;
       ax = fma(a, st.cm[j].x, ax);
       ay = fma(a, st.cm[j].y, ay);
       hx = fma(h, st.cm[j].x, hx);
@@ -2328,11 +2338,11 @@ inline unsigned blocks_for(int64_t n, int b = kBlock) { return (unsigned)((n + b
 }  // namespace
 
 // ------------------------------- launchers ---------------------------------
-hipError_t launch_assemble(const Items& it, double* A, double* Kin, double* Q, double* B,
-                           double* W, double* S1, const int64_t* s1off, int K_max,
+hipError_t launch_assemble(const Items& it, double* A, double* Kin, double* Q, double* Q2,
+                           double* B, double* W, double* S1, const int64_t* s1off, int K_max,
                            hipStream_t st) {
   dim3 grid(blocks_for((int64_t)K_max * K_max), it.n_items);
-  hipLaunchKernelGGL(k_assemble, grid, dim3(kBlock), 0, st, it, A, Kin, Q, B, W, S1, s1off);
+  hipLaunchKernelGGL(k_assemble, grid, dim3(kBlock), 0, st, it, A, Kin, Q, Q2, B, W, S1, s1off);
   return hipGetLastError();
 }
 

@@ -14,7 +14,7 @@ Paper passages:
     fixed time step.
 
 Run as a module for the figure-DT tables of the two-electron imaginary-time
-workload and the paper's imaginary-time experiments (Tests 1.b, 2.a, 2.b):
+workload and the paper's Gaussian-basis experiments (Tests 1.b, 2.a, 2.b, 3):
 python -m paper_1710_02401_amd.studies
 """
 import math
@@ -106,15 +106,15 @@ def figure_dt(k_max=30):
 
 
 def paper_experiments(k_max=30):
-    """Section 5, Test 1.b (heat equation) and Tests 2.a and 2.b
-    (imaginary-time H2): residual history, energy (none for the heat
-    equation) and wall time per Schwarz iteration of each, k_max
-    iterations."""
+    """Section 5, Test 1.b (heat equation), Tests 2.a and 2.b
+    (imaginary-time H2) and Test 3 (real time, circular pulse): residual
+    history, energy (imaginary time with normalisation only) and wall time
+    per Schwarz iteration of each, k_max iterations."""
     import time
 
     import workloads
     out = []
-    for name in ("paper-test-1b", "paper-test-2a", "paper-test-2b"):
+    for name in ("paper-test-1b", "paper-test-2a", "paper-test-2b", "paper-test-3"):
         cfg = workloads.get_config(name)
         s = S.Solver(cfg)
         try:
@@ -129,7 +129,8 @@ def paper_experiments(k_max=30):
             ms = 1e3 * (time.perf_counter() - t) / k_max
         finally:
             s.close()
-        out.append(dict(workload=name, iters=int(st["iters"]), energy=float(st["energy"]),
+        energy = float(st["energy"]) if cfg["mode"] == "tise" else None
+        out.append(dict(workload=name, iters=int(st["iters"]), energy=energy,
                         res=[float(r) for r in st["res"][:k_max]], ms_per_iteration=ms))
     return out
 

@@ -18,7 +18,8 @@ SWR_OK, SWR_E_ARG, SWR_E_SIZE, SWR_E_DEVICE, SWR_E_STATE, SWR_E_SINGULAR, SWR_E_
 SWR_TDSE, SWR_TISE = 0, 1
 SWR_WARM_PLAIN, SWR_WARM_ZERO, SWR_WARM_GIVEN = 0, 1, 2
 SWR_FACTOR_AUTO, SWR_FACTOR_DIRECT, SWR_FACTOR_WIDE = 0, 1, 2
-MATRICES = {"A": 0, "Kin": 1, "V": 2, "Q": 3, "B": 4, "W": 5, "G": 6}
+SWR_FIELD_SINE, SWR_FIELD_CIRCULAR = 0, 1
+MATRICES = {"A": 0, "Kin": 1, "V": 2, "Q": 3, "B": 4, "W": 5, "G": 6, "Q2": 7}
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
 _c_f64p = ctypes.POINTER(ctypes.c_double)
@@ -43,6 +44,8 @@ class swr_desc(ctypes.Structure):
         ("face_nodes_band", ctypes.c_int32), ("face_nodes_mid", ctypes.c_int32),
         ("quad_nodes", ctypes.c_int32), ("learned_nodes", ctypes.c_int32),
         ("factor_mode", ctypes.c_int32), ("unnormalized", ctypes.c_int32),
+        ("field_shape", ctypes.c_int32), ("pulse_nu", ctypes.c_double),
+        ("pulse_center", ctypes.c_double), ("field_mask", ctypes.c_int32 * 2),
     ]
 
 
@@ -208,6 +211,14 @@ def desc_from_config(cfg):
     d.mu_re, d.mu_im = float(cfg["mu"][0]), float(cfg["mu"][1])
     f = cfg["field"]
     d.E0, d.omega, d.phase, d.axis = float(f["E0"]), float(f["omega"]), float(f["phase"]), int(f["axis"])
+    if f.get("shape", "sine") == "circular":
+        # components coupling to the configuration coordinates listed in coords
+        d.field_shape = SWR_FIELD_CIRCULAR
+        d.pulse_nu, d.pulse_center = float(f["nu"]), float(f["center"])
+        for c in range(2):
+            d.field_mask[c] = sum(1 << int(k) for k in f["coords"][c])
+    elif f.get("shape", "sine") != "sine":
+        raise ValueError(f"unknown field shape {f['shape']!r}")
     d.init_alpha = float(cfg["init"]["alpha"])
     for k in range(D):
         d.init_center[k] = float(cfg["init"]["center"][k])

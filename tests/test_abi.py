@@ -72,6 +72,44 @@ def test_factor_mode_validated_and_reported(S):
     lib.swr_destroy(h)
 
 
+def _circ(coords, **kw):
+    f = dict(shape="circular", E0=1.0, omega=8.0, phase=0.0, nu=10.0, center=1.25,
+             coords=coords, axis=0)
+    f.update(kw)
+    return f
+
+
+@pytest.mark.parametrize("cfg_name,field,mode,ok,text", [
+    ("paper-test-3", _circ([[0], [1]]), "tdse", True, None),
+    ("c5-mini", _circ([[0, 2], [1, 3]]), "tdse", True, None),   # x.E of both electrons
+    ("paper-test-3", _circ([[0], [0]]), "tdse", False, b"disjoint"),
+    ("paper-test-3", _circ([[0, 1], []]), "tdse", False, b"disjoint"),
+    ("paper-test-3", _circ([[0], [2]]), "tdse", False, b"disjoint"),
+    ("paper-test-3", _circ([[0], [1]], nu=-1.0), "tdse", False, b"pulse_nu"),
+    ("paper-test-2a", _circ([[0], [1]]), "tise", False, b"real time"),
+])
+def test_circular_field_validated(S, cfg_name, field, mode, ok, text):
+    """The two-component field of Section 5, Test 3: masks within the
+    configuration coordinates and disjoint, a non-negative envelope rate,
+    real time only; a valid one inverts every step."""
+    lib = S.load_library()
+    cfg = workloads.get_config(cfg_name, field=field)
+    assert cfg["mode"] == mode
+    rc, h = _create(S, cfg)
+    if not ok:
+        assert rc == S.SWR_E_ARG and text in lib.swr_last_error(None)
+        return
+    assert rc == 0
+    info = S.swr_info()
+    assert lib.swr_query(h, ctypes.byref(info)) == 0 and info.wide == 0
+    lib.swr_destroy(h)
+    d, keep = S.desc_from_config(cfg)
+    d.field_shape = 2
+    h = ctypes.c_void_p()
+    assert lib.swr_create(ctypes.byref(d), ctypes.byref(h)) == S.SWR_E_ARG
+    assert b"field_shape" in lib.swr_last_error(None)
+
+
 def test_unbound_workspace_and_state_errors(S):
     lib = S.load_library()
     rc, h = _create(S, workloads.tiny_configs()[0])

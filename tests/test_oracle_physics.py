@@ -93,6 +93,54 @@ def test_ehrenfest_drift_in_uniform_field():
     assert np.max(np.abs(xs + E0 * (t / w - np.sin(w * t) / w ** 2))) < 3e-6
 
 
+def _circular(**kw):
+    f = dict(shape="circular", E0=1.0, omega=3.0, phase=0.3, nu=2.0, center=0.5,
+             coords=[[0], [1]], axis=0)
+    f.update(kw)
+    return f
+
+
+def test_ehrenfest_drift_in_circular_field():
+    """Section 5, Test 3's circular pulse on a free particle in two
+    dimensions: each mean coordinate follows its own component,
+    <x_c>(t) = x_c(0) - int_0^t (t - s) E_c(s) ds (quadrature), the two
+    drifts differing (a swapped component, sign or envelope fails)."""
+    from scipy.integrate import quad
+    cfg = base(dim=2, L=[1, 1], box_lo=[-8.0, -8.0], box_hi=[8.0, 8.0], overlap=[0.0, 0.0],
+               nbasis=[17, 17], width=None, width_ratio=1.0, dt=0.01, n_steps=100,
+               field=_circular(), init=dict(alpha=0.5, center=[0.5, -0.3]))
+    p = swr.Problem(cfg)
+    h, _ = swr.swr_window(p, p.initial_coeffs(), iters=1)
+    sy = p.sys[0]
+    t = p.times()
+    drift = []
+    for c, Qc in enumerate((sy.Q, sy.Q2)):
+        xs = np.array([np.real(np.conj(v) @ Qc @ v) / np.real(np.conj(v) @ sy.A @ v) for v in h[0]])
+        ref = np.array([cfg["init"]["center"][c] -
+                        quad(lambda s: (tt - s) * swr.field(cfg, s)[c], 0.0, tt,
+                             epsabs=1e-13, epsrel=1e-12)[0] for tt in t])
+        assert np.max(np.abs(xs - ref)) < 2e-4, c
+        drift.append(ref[-1] - ref[0])
+    assert abs(drift[0] - drift[1]) > 0.1
+
+
+def test_cn_time_reversal_with_circular_field():
+    """The two-component field term in both Crank-Nicolson matrices: stepping
+    back over the reversed field and data recovers c0 (one electron in two
+    dimensions with a nucleus, one component per axis)."""
+    cfg = workloads.get_config("c5-mini-1e", field=_circular(E0=0.7, omega=5.0, center=0.05))
+    p = swr.Problem(cfg)
+    sy = p.sys[2]
+    rng = np.random.default_rng(5)
+    c0 = p.initial_coeffs()[2]
+    f = rng.standard_normal((p.n_T + 1, sy.K)) + 1j * rng.standard_normal((p.n_T + 1, sy.K))
+    E = swr.field(cfg, p.times())
+    assert E.shape == (p.n_T + 1, 2) and np.ptp(E[:, 0]) > 0.1 and np.ptp(E[:, 1]) > 0.1
+    h = swr.local_cn(sy, c0, f, E, p.dt)
+    back = swr.local_cn(sy, h[-1], f[::-1], E[::-1], -p.dt)
+    assert np.max(np.abs(back[-1] - c0)) < 1e-11 * np.max(np.abs(c0))
+
+
 def test_cn_conserves_a_norm_for_hermitian_static_hamiltonian():
     from workloads import tiny_configs
     cfg = tiny_configs()[0]

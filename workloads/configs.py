@@ -177,8 +177,28 @@ _T1B = dict(
     iters=30, tol=1e-8, face_nodes=[16, 32], quad_nodes=16,
 )
 
+# Section 5, Test 3 (real time): two electrons in one dimension each on
+# (-10, 10)^2, 5x5 subdomains of 6x6 Gaussians, mu = -10i, steps of 0.05 to
+# T = 2.5, phi_0 = exp(-|x|^2), softening eta = 0.5, and the circular pulse
+# E0 = 1, omega = 8, nu = 10 centred at T/2 whose two components act on the
+# two coordinates of the configuration plane (x1 and x2).  Readings where the
+# test is silent: the H2 nuclei at -0.5 and 0.5 (Section 6 places H2
+# there), Test 2.a's Gaussian width (delta = 0.5), overlap 10 % of box/L,
+# eta for both the nucleus and the electron-electron terms.
+_T3 = dict(
+    name="paper-test-3", mode="tdse", n_elec=2, dim=1,
+    L=[5, 5], box_lo=[-10.0, -10.0], box_hi=[10.0, 10.0], overlap=[0.4, 0.4],
+    nbasis=[6, 6], width=1.0, width_ratio=None,
+    nuclei=[[-0.5], [0.5]], charges=[1.0, 1.0], eps_en=0.5, eps_ee=0.5,
+    dt=0.05, n_steps=50, mu=[0.0, -10.0],
+    field=dict(shape="circular", E0=1.0, omega=8.0, phase=0.0, nu=10.0, center=1.25,
+               coords=[[0], [1]], axis=0),
+    init=dict(alpha=1.0, center=[0.0, 0.0]),
+    iters=30, tol=1e-8, face_nodes=[16, 32], quad_nodes=16,
+)
+
 CONFIGS = {c["name"]: c for c in (_C1, _C2, _C2_TISE, _C3, _C3_MINI, _C3_WIDE, _C4, _C5,
-                                   _C5_MINI, _C5_MINI_1E, _T1B, _T2A, _T2B)}
+                                   _C5_MINI, _C5_MINI_1E, _T1B, _T2A, _T2B, _T3)}
 
 
 def get_config(name, **overrides):
