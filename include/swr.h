@@ -205,7 +205,11 @@ int32_t swr_factor(swr_handle h, double t0, void* stream);
  * TDSE Crank-Nicolson
  *   M^{n+1} c^{n+1} = (A - i dt/2 (H~ + E_n Q)) c^n + (i dt/4)(f^n + f^{n+1}),
  * TISE implicit Euler with global normalisation (eq. SIT),
- * using the current Robin data f.  Requires swr_factor for the window. */
+ * using the current Robin data f.  Requires swr_factor for the window.
+ * Accuracy: M^n c^n is taken from the previous step's right-hand side, so
+ * the stored inverses' residual (about cond(M) eps) enters every later step:
+ * the error per step is about cond(M)^2 eps.  Bases whose Gram matrices are
+ * nearly singular (condition above about 1e6) lose accuracy. */
 int32_t swr_sweep(swr_handle h, void* stream);
 
 /* Transmission (Section 4.1, averaged Robin TC in multi-overlap zones, eq.

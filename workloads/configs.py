@@ -183,12 +183,14 @@ _T1B = dict(
 # E0 = 1, omega = 8, nu = 10 centred at T/2 whose two components act on the
 # two coordinates of the configuration plane (x1 and x2).  Readings where the
 # test is silent: the H2 nuclei at -0.5 and 0.5 (Section 6 places H2
-# there), Test 2.a's Gaussian width (delta = 0.5), overlap 10 % of box/L,
-# eta for both the nucleus and the electron-electron terms.
+# there), widths 0.7 x spacing as for Test 1.b (Test 2.a's delta = 0.5 on
+# these smaller boxes makes the Gram matrices nearly singular, condition
+# 1.6e8), overlap 10 % of box/L, eta for both the nucleus and the
+# electron-electron terms.
 _T3 = dict(
     name="paper-test-3", mode="tdse", n_elec=2, dim=1,
     L=[5, 5], box_lo=[-10.0, -10.0], box_hi=[10.0, 10.0], overlap=[0.4, 0.4],
-    nbasis=[6, 6], width=1.0, width_ratio=None,
+    nbasis=[6, 6], width=None, width_ratio=0.7,
     nuclei=[[-0.5], [0.5]], charges=[1.0, 1.0], eps_en=0.5, eps_ee=0.5,
     dt=0.05, n_steps=50, mu=[0.0, -10.0],
     field=dict(shape="circular", E0=1.0, omega=8.0, phase=0.0, nu=10.0, center=1.25,
