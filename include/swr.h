@@ -65,7 +65,8 @@ enum { SWR_WARM_PLAIN = 0, SWR_WARM_ZERO = 1, SWR_WARM_GIVEN = 2 };
 typedef struct swr_desc {
   int32_t mode;              /* SWR_TDSE or SWR_TISE                          */
   int32_t n_elec, dim;       /* N electrons in d dimensions; D = N*d <= 4     */
-  int32_t n_geom;            /* independent geometries batched together (>=1) */
+  int32_t n_geom;            /* independent geometries batched together (>=1;
+                                imaginary time: 1)                           */
   int32_t L[4];              /* subdomains per configuration dimension        */
   double box_lo[4], box_hi[4], overlap[4];
   const int32_t* nbasis;     /* host: [D], or [n_sub][D] if per_subdomain     */

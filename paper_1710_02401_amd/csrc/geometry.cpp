@@ -77,6 +77,8 @@ std::string build_geometry(const swr_desc& d, Geometry* g, int* code) {
   if (d.n_geom < 1) return "n_geom must be >= 1";
   if (d.mode != SWR_TDSE && d.mode != SWR_TISE) return "mode must be SWR_TDSE or SWR_TISE";
   if (d.mode == SWR_TISE && d.mu_im != 0.0) return "imaginary time needs a real Robin coefficient";
+  if (d.mode == SWR_TISE && d.n_geom != 1)
+    return "imaginary time takes one geometry (its normalisation spans every subdomain)";
   if (!(d.dt != 0.0) || d.n_steps < 1) return "dt must be non-zero and n_steps >= 1";
   if (d.axis < 0 || d.axis >= d.dim) return "field axis out of range";
   if (d.n_nuc < 0 || (d.n_nuc > 0 && (!d.nuc_pos || !d.nuc_charge))) return "nuclei arrays missing";

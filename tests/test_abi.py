@@ -45,6 +45,7 @@ def _create(S, cfg):
     (dict(dt=0.0), -1),
     (dict(nbasis=[257]), -2),
     (dict(mode="tise", mu=[0.0, -1.0]), -1),
+    (dict(mode="tise", mu=[1.0, 0.0], geometries=[[[0.0]], [[0.5]]]), -1),
     (dict(field=dict(E0=0.1, omega=1.0, phase=0.0, axis=3)), -1),
     (dict(learned_nodes=1), -1),
     (dict(learned_nodes=65), -1),

@@ -153,6 +153,25 @@ def test_imaginary_time_swr_energy_and_states():
         assert a == pytest.approx(b, rel=1e-7, abs=1e-12)
 
 
+def test_imaginary_time_with_more_subdomains_than_compute_units():
+    """272 subdomains (17 x 16 of 3 x 3 Gaussians), more than the chip's
+    256 compute units, normalised over all of them at every step: states,
+    residuals and energy as the oracle's."""
+    cfg = dict(_cfg("tiny-2d-tise"), name="tise-272", L=[17, 16], box_lo=[-17.0, -16.0],
+               box_hi=[17.0, 16.0], overlap=[0.5, 0.5], nbasis=[3, 3], n_steps=6, iters=3,
+               face_nodes=[2, 2])
+    s = _solver(cfg)
+    prob = o_swr.Problem(cfg)
+    assert s.info.n_items == 272
+    st = s.run(k_max=3, tol=0.0)
+    h_o, res_o, en_o = o_tise.swr_tise(prob, iters=3)
+    h_g = [np.real(_np(h)) for h in s.split_history(s.history())]
+    assert a_norm_rel(prob, h_g, h_o) <= 1e-10
+    assert st["energy"] == pytest.approx(en_o[-1], rel=1e-10)
+    for a, b in zip(st["res"], res_o):
+        assert a == pytest.approx(b, rel=1e-7, abs=1e-12)
+
+
 @pytest.mark.parametrize("name", ["tiny-2d-tise", "c2-2e-1d-tise"])
 def test_local_generalized_eigenproblems(name):
     cfg = _cfg(name)
