@@ -1873,50 +1873,80 @@ __device__ inline double norm_from_partials(const double* partial, int n_items, 
   return sqrt(block_sum(acc, red));
 }
 
-// normalize = 0: the flow without normalisation (nu = 1 at every step)
+// normalize = 0: the flow without normalisation (nu = 1 at every step).
+// Every product uses all four waves: lanes over rows r (contiguous reads of
+// the symmetric A and W by column, and of the inverse, stored transposed),
+// the columns m = w, w + 4, ... of wave w, partial sums added in LDS.  The
+// three matrices' slices are loaded into registers first, so their latency
+// overlaps the wait for the previous step's partial norms.
 __global__ void __launch_bounds__(kBlock) k_ie_step(Items it, int n, int n_steps, double dt,
                                                     const double* A, const double* W,
                                                     const double2* Minv, const double2* F,
                                                     double2* hist, double* partial, double* nus,
                                                     int normalize, int* flags) {
+  constexpr int kWaves = kBlock / 64;
+  constexpr int kCols = kSmallK / kWaves;
   const int s = blockIdx.x;
   const int K = it.K[s];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   __shared__ double c[kSmallK];
   __shared__ double rhs[kSmallK];
   __shared__ double ct[kSmallK];
+  __shared__ double part[kWaves][kSmallK];
   __shared__ double red[kBlock];
   const int64_t hb = (int64_t)(n_steps + 1) * it.off1[s];
+  const int64_t o2 = it.off2[s];
+  const bool on = lane < K;
+  double ra[kCols], rm[kCols], rw[kCols];
+#pragma unroll
+  for (int j = 0; j < kCols; ++j) {
+    const int m = w + kWaves * j;
+    const bool v = on && m < K;
+    const int64_t e = o2 + (v ? (int64_t)m * K + lane : 0);
+    ra[j] = v ? A[e] : 0.0;
+    rm[j] = v ? Minv[e].x : 0.0;
+    rw[j] = v ? W[e] : 0.0;
+  }
+  const double hn = threadIdx.x < K ? hist[hb + (int64_t)n * K + threadIdx.x].x : 0.0;
+  const double fn = threadIdx.x < K ? F[hb + (int64_t)(n + 1) * K + threadIdx.x].x : 0.0;
   double nu = 1.0;
   if (n > 0 && normalize) nu = norm_from_partials(partial + (int64_t)n * it.n_items, it.n_items, red);
   if (s == 0 && threadIdx.x == 0) nus[n] = nu;
-  for (int r = threadIdx.x; r < K; r += blockDim.x) {
-    const double v = hist[hb + (int64_t)n * K + r].x / nu;
-    c[r] = v;
-    hist[hb + (int64_t)n * K + r] = make_double2(v, 0.0);
+  if (threadIdx.x < K) {
+    const double v = hn / nu;
+    c[threadIdx.x] = v;
+    hist[hb + (int64_t)n * K + threadIdx.x] = make_double2(v, 0.0);
   }
   __syncthreads();
-  const int64_t o2 = it.off2[s];
-  for (int r = threadIdx.x; r < K; r += blockDim.x) {
+  auto split = [&](const double* reg, const double* x) {
     double v = 0.0;
-    for (int m = 0; m < K; ++m) v = fma(A[o2 + (int64_t)r * K + m], c[m], v);
-    rhs[r] = v + 0.5 * dt * F[hb + (int64_t)(n + 1) * K + r].x;
-  }
+#pragma unroll
+    for (int j = 0; j < kCols; ++j) {
+      const int m = w + kWaves * j;
+      if (m < K) v = fma(reg[j], x[m], v);
+    }
+    part[w][lane] = v;
+    __syncthreads();
+  };
+  auto gather = [&]() {
+    double v = part[0][threadIdx.x];
+#pragma unroll
+    for (int q = 1; q < kWaves; ++q) v += part[q][threadIdx.x];
+    return v;
+  };
+  split(ra, c);
+  if (threadIdx.x < K) rhs[threadIdx.x] = gather() + 0.5 * dt * fn;
   __syncthreads();
-  const double2* Mi = Minv + o2;  // one (transposed) inverse per item
-  for (int r = threadIdx.x; r < K; r += blockDim.x) {
-    double v = 0.0;
-    for (int m = 0; m < K; ++m) v = fma(Mi[(int64_t)m * K + r].x, rhs[m], v);
-    ct[r] = v;
-    hist[hb + (int64_t)(n + 1) * K + r] = make_double2(v, 0.0);
+  split(rm, rhs);
+  if (threadIdx.x < K) {
+    const double v = gather();
+    ct[threadIdx.x] = v;
+    hist[hb + (int64_t)(n + 1) * K + threadIdx.x] = make_double2(v, 0.0);
     if (!isfinite(v)) atomicOr(flags, kFlagNaN);
   }
   __syncthreads();
-  double acc = 0.0;
-  for (int r = threadIdx.x; r < K; r += blockDim.x) {
-    double v = 0.0;
-    for (int m = 0; m < K; ++m) v = fma(W[o2 + (int64_t)r * K + m], ct[m], v);
-    acc += ct[r] * v;
-  }
+  split(rw, ct);
+  const double acc = threadIdx.x < K ? ct[threadIdx.x] * gather() : 0.0;
   const double tot = block_sum(acc, red);
   if (threadIdx.x == 0) partial[(int64_t)(n + 1) * it.n_items + s] = tot;
 }
