@@ -111,6 +111,16 @@ def test_circular_field_validated(S, cfg_name, field, mode, ok, text):
     assert b"field_shape" in lib.swr_last_error(None)
 
 
+def test_random_small_configurations_accepted(S):
+    """The seeded configurations of the GPU parity sweep are valid
+    descriptions (checked here, on the CPU, before any GPU run)."""
+    lib = S.load_library()
+    for cfg in workloads.random_small_configs(10):
+        rc, h = _create(S, cfg)
+        assert rc == 0, (cfg["name"], lib.swr_last_error(None))
+        lib.swr_destroy(h)
+
+
 def test_unbound_workspace_and_state_errors(S):
     lib = S.load_library()
     rc, h = _create(S, workloads.tiny_configs()[0])

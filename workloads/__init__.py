@@ -9,5 +9,6 @@ any code path with each other.
 from .configs import (  # noqa: F401
     CONFIGS,
     get_config,
+    random_small_configs,
     tiny_configs,
 )

@@ -241,3 +241,49 @@ def tiny_configs():
               dt=0.05, n_steps=10,
               field=dict(E0=0.0, omega=0.0, phase=0.0, axis=0))
     return [copy.deepcopy(t) for t in (t1, t2, t3)]
+
+
+def random_small_configs(n, seed=4021):
+    """Seeded small real-time configurations for broad parity checks: one
+    electron in one or two dimensions or two electrons in one, 1 to 3
+    subdomains per dimension (one subdomain included), 2 to 6 Gaussians per
+    dimension (per subdomain in one dimension), 1 to 33 steps, a complex
+    Robin constant of either sign of Im mu, and a sine or (two coordinates)
+    circular field; each with a pipeline depth to run it at."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = []
+    for q in range(n):
+        n_elec, dim = [(1, 1), (2, 1), (1, 2)][q % 3]
+        D = n_elec * dim
+        L = [int(rng.integers(1, 4)) for _ in range(D)]
+        lo = [float(-rng.uniform(5.0, 8.0)) for _ in range(D)]
+        hi = [float(rng.uniform(5.0, 8.0)) for _ in range(D)]
+        overlap = [float(rng.uniform(0.3, 0.9)) if L[k] > 1 else 0.0 for k in range(D)]
+        if D == 1 and L[0] > 1:
+            nbasis = [[int(rng.integers(2, 7))] for _ in range(L[0])]
+        else:
+            nbasis = [int(rng.integers(2, 7)) for _ in range(D)]
+        n_nuc = int(rng.integers(0, 3))
+        nuclei = [[float(rng.uniform(-1.5, 1.5)) for _ in range(dim)] for _ in range(n_nuc)]
+        charges = [float(rng.uniform(0.5, 1.0)) for _ in range(n_nuc)]
+        mu = [float(rng.uniform(-0.5, 0.5)), float(rng.choice([-1.0, 1.0]) * rng.uniform(0.5, 8.0))]
+        if D >= 2 and q % 2 == 0:
+            field = dict(shape="circular", E0=float(rng.uniform(0.1, 0.5)),
+                         omega=float(rng.uniform(0.5, 4.0)), phase=float(rng.uniform(0, 6.28)),
+                         nu=float(rng.uniform(0.0, 5.0)), center=float(rng.uniform(0.0, 0.2)),
+                         coords=[[0], [1]], axis=0)
+        else:
+            field = dict(E0=float(rng.uniform(0.0, 0.3)), omega=float(rng.uniform(0.5, 2.0)),
+                         phase=float(rng.uniform(0, 6.28)), axis=int(rng.integers(0, dim)))
+        out.append(dict(
+            name=f"random-{q}", mode="tdse", n_elec=n_elec, dim=dim, L=L, box_lo=lo, box_hi=hi,
+            overlap=overlap, nbasis=nbasis, width=None, width_ratio=float(rng.uniform(0.6, 0.9)),
+            nuclei=nuclei, charges=charges, eps_en=float(rng.uniform(0.5, 1.2)),
+            eps_ee=float(rng.uniform(0.5, 1.2)), dt=float(rng.uniform(0.005, 0.03)),
+            n_steps=int(rng.choice([1, 2, 7, 16, 33])), mu=mu, field=field,
+            init=dict(alpha=float(rng.uniform(0.4, 1.0)),
+                      center=[float(rng.uniform(-0.5, 0.5)) for _ in range(D)]),
+            iters=3, tol=1e-8, face_nodes=[int(rng.integers(2, 6)), int(rng.integers(2, 8))],
+            quad_nodes=12, depth=int(rng.choice([1, 2, 4]))))
+    return out
