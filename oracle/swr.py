@@ -22,9 +22,11 @@ Paper passages followed:
     3.2) -- a reading.
 
 Pinned by: Crank-Nicolson invariants (A-norm conservation for Hermitian
-H~, time reversal, second order), free Gaussian packet spreading,
-Ehrenfest drift in a uniform field, and converged SWR against a
-brute-force finite-difference solution of the same boundary value problem.
+H~, time reversal -- with the two-component field too -- and second order),
+free Gaussian packet spreading, Ehrenfest drift in a uniform field and, per
+coordinate, in the circular pulse of Section 5 Test 3, and converged SWR
+against a brute-force finite-difference solution of the same boundary value
+problem.
 """
 import numpy as np
 

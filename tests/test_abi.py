@@ -111,6 +111,17 @@ def test_circular_field_validated(S, cfg_name, field, mode, ok, text):
     assert b"field_shape" in lib.swr_last_error(None)
 
 
+def test_second_dipole_only_for_circular_fields(S):
+    """swr_get_matrix's Q2 (index 7) exists for a circular field only;
+    indices past it are rejected (both before any device work)."""
+    lib = S.load_library()
+    rc, h = _create(S, workloads.tiny_configs()[0])
+    assert rc == 0
+    for which in (7, 8, -1):
+        assert lib.swr_get_matrix(h, which, None, 0, None) == S.SWR_E_ARG
+    lib.swr_destroy(h)
+
+
 def test_random_small_configurations_accepted(S):
     """The seeded configurations of the GPU parity sweep are valid
     descriptions (checked here, on the CPU, before any GPU run)."""
