@@ -97,6 +97,9 @@ struct swr_handle_s {
   Buf bPos, bCharge, bS1Off, bS1, bScrOff, bScr, bCenter;
   Buf bA, bKin, bV, bQ, bB, bW, bG, bAr, bAp, bHr;
   Buf bQ2, bE2;  // second component of a circular field (else unallocated)
+  // imaginary time, per history slot: partial norms [n_T + 1][n_items] and
+  // normalisation factors [n_T + 1] of the iterate in the slot
+  Buf bIePart[kMaxSlots], bNus[kMaxSlots];
   Buf bTePair, bTeFace, bTeT0, bTeT1, bTeOff, bTeBoff, bTeAoff, bTeXoff, bTeBeta, bTeA, bTeX;
   Buf bTeSoff, bTeSidx, bTeV, bTeBlobOff, bTeBlob, bTeSdesc, bTeGramOff, bTeGram, bTeFnode;
   Buf bParts;                        // residual partials of the factored transmission
@@ -115,7 +118,7 @@ struct swr_handle_s {
   Buf bS2P, bSeriesP, bScrW, bOrder, bTileOff;
   std::vector<int32_t> order;
   std::vector<int64_t> tile_off;
-  Buf bT, bC0, bH[kMaxSlots], bF[kMaxSlots], bRc[kMaxSlots], bMinv, bE, bResPart, bResOut, bResv, bIePart, bNus,
+  Buf bT, bC0, bH[kMaxSlots], bF[kMaxSlots], bRc[kMaxSlots], bMinv, bE, bResPart, bResOut, bResv,
       bFlags;
 
   // state
@@ -230,6 +233,8 @@ struct swr_handle_s {
   double2* hist(int which) const { return ptr<double2>(bH[which]); }
   double2* hist_of(int k) const { return ptr<double2>(bH[k % n_slots]); }
   double2* F_of(int k) const { return ptr<double2>(bF[k % n_slots]); }
+  double* nus_of(int k) const { return ptr<double>(bNus[k % n_slots]); }
+  double* iepart_of(int k) const { return ptr<double>(bIePart[k % n_slots]); }
   // right-hand side a chunk of iterate k leaves for the next chunk
   double2* carry_of(int k) const { return ptr<double2>(bRc[k % n_slots]); }
   double* parts_of(int k) const {
@@ -411,8 +416,10 @@ void plan_layout(swr_handle h) {
   h->bResPart = L.add((size_t)h->n_res_tiles * NI * 8);
   h->bResOut = L.add(8);
   h->bResv = L.add(64 * 8);
-  h->bIePart = L.add((size_t)(h->n_T + 1) * NI * 8);
-  h->bNus = L.add((h->n_T + 1) * 8);
+  for (int q = 0; q < h->n_slots; ++q) {
+    h->bIePart[q] = L.add((size_t)(h->n_T + 1) * NI * 8);
+    h->bNus[q] = L.add((h->n_T + 1) * 8);
+  }
   h->bFlags = L.add(8);
   h->bLag = L.add((h->n_T + 1) * h->n_nodes_t * 8);
   h->bLMax = L.add(8);
@@ -587,7 +594,9 @@ int32_t swr_create(const swr_desc* desc, swr_handle* out) {
   }
   h->s1_total = s1;
   h->scratch_total = scr;
-  if (g.desc.mode == SWR_TDSE && !h->wide) {
+  if (!h->wide) {
+    // iterates in flight: enough blocks of one per item to fill the chip
+    // (the real-time recurrence and the imaginary-time steps alike)
     const int fill = (kRecPerCU * kGpuCUs + g.n_items - 1) / g.n_items;
     h->depth = std::max(1, std::min({kMaxDepth, fill, (int)h->n_T}));
   }
@@ -898,7 +907,7 @@ int32_t swr_set_initial(swr_handle h, const void* c0_dev, void* stream) {
   }
   if (h->g.desc.mode == SWR_TISE && !h->g.desc.unnormalized)
     HIPCHECK(h, swr::launch_global_normalise(it, h->ptr<double>(h->bW), h->ptr<double2>(h->bC0),
-                                             h->ptr<double>(h->bIePart), st));
+                                             h->iepart_of(0), st));
   h->initial = true;
   int rc = swr_warm_start(h, SWR_WARM_PLAIN, nullptr, stream);
   return rc;
@@ -936,7 +945,7 @@ int32_t swr_warm_start(swr_handle h, int32_t mode, const void* g_dev, void* stre
                                     nullptr, h->g.desc.dt, st));
   } else if (mode == SWR_WARM_PLAIN) {
     HIPCHECK(h, swr::launch_transmit(it, h->pairs(), h->te(), nT, h->ptr<double2>(h->bT),
-                                     full_tx(h->hist_of(0), F, nT), nullptr, h->nbt,
+                                     full_tx(h->hist_of(0), F, nT), h->nbt,
                                      h->te_pieces, h->te_max_recv, h->te_max_send,
                                      h->te_gram_max, h->tx_tt, st));
   } else if (mode == SWR_WARM_ZERO) {
@@ -1114,13 +1123,19 @@ int32_t swr_sweep(swr_handle h, void* stream) {
     HIPCHECK(h, swr::launch_fill_history(it, nT, h->ptr<double2>(h->bC0), hist, st));
     const int norm = h->g.desc.unnormalized ? 0 : 1;
     HIPCHECK(h, tbegin(h, st, kTRecur));  // the sweep's n_T step launches
-    for (int n = 0; n < nT; ++n)
-      HIPCHECK(h, swr::launch_ie_step(it, n, nT, h->g.desc.dt, h->ptr<double>(h->bA),
-                                      h->ptr<double>(h->bW), h->ptr<double2>(h->bMinv),
-                                      h->F_of(k), hist, h->ptr<double>(h->bIePart),
-                                      h->ptr<double>(h->bNus), norm, h->ptr<int>(h->bFlags), st));
-    HIPCHECK(h, swr::launch_ie_finish(it, nT, hist, h->ptr<double>(h->bIePart),
-                                      h->ptr<double>(h->bNus), norm, st));
+    swr::IeJobs jobs{};
+    jobs.n = 1;
+    jobs.hist[0] = hist;
+    jobs.F[0] = h->F_of(k);
+    jobs.partial[0] = h->iepart_of(k);
+    jobs.nus[0] = h->nus_of(k);
+    for (int n = 0; n < nT; ++n) {
+      jobs.step[0] = n;
+      HIPCHECK(h, swr::launch_ie_step(it, jobs, nT, h->g.desc.dt, h->ptr<double>(h->bA),
+                                      h->ptr<double>(h->bW), h->ptr<double2>(h->bMinv), norm,
+                                      h->ptr<int>(h->bFlags), st));
+    }
+    HIPCHECK(h, swr::launch_ie_finish(it, nT, hist, h->iepart_of(k), h->nus_of(k), norm, st));
     HIPCHECK(h, tend(h, st));
   }
   h->cur = k % h->n_slots;
@@ -1152,6 +1167,7 @@ int32_t transmit_and_residual(swr_handle h, int k, const double* scale, double* 
     return SWR_OK;
   }
   swr::TxJobs tx = full_tx(h->hist_of(k), h->F_of(k + 1), nT);
+  tx.scale[0] = scale;
   tx.dt = h->g.desc.dt;
   tx.part_stride = h->part_stride;
   if (h->fused_residual() && res_dev) {
@@ -1166,7 +1182,7 @@ int32_t transmit_and_residual(swr_handle h, int k, const double* scale, double* 
   }
   HIPCHECK(h, tbegin(h, st, kTTransmit));
   HIPCHECK(h, swr::launch_transmit(it, h->pairs(), h->te(), nT, h->ptr<double2>(h->bT), tx,
-                                   scale, h->nbt, h->te_pieces, h->te_max_recv, h->te_max_send,
+                                   h->nbt, h->te_pieces, h->te_max_recv, h->te_max_send,
                                    h->te_gram_max, h->tx_tt, st));
   if (h->fused_residual() && res_dev)
     HIPCHECK(h, swr::launch_res_reduce(h->parts_of(k), h->g.n_items, h->part_stride, nT, nT, 1,
@@ -1181,7 +1197,7 @@ int32_t swr_transmit(swr_handle h, double* residual_host, void* stream) {
   if (!h) return SWR_E_ARG;
   if (h->k < 1) return fail(h, SWR_E_STATE, "swr_sweep first");
   hipStream_t st = (hipStream_t)stream;
-  const double* scale = h->g.desc.mode == SWR_TISE ? h->ptr<double>(h->bNus) : nullptr;
+  const double* scale = h->g.desc.mode == SWR_TISE ? h->nus_of(h->k) : nullptr;
   int rc = transmit_and_residual(h, h->k, scale, h->ptr<double>(h->bResOut), st);
   if (rc) return rc;
   double res = 0.0;
@@ -1207,13 +1223,55 @@ namespace {
 // while the recurrence runs and never idles the GPU.
 // capture: only enqueue (the stream is being captured into a graph): no host
 // reads of the residuals, every iterate up to k_max, no flag check.
+// Imaginary-time chunks of one pipelined launch: each job is a Schwarz
+// iterate (rec_k) at its chunk [n_lo, n_lo + n_cnt); an iterate starting
+// (n_lo = 0) gets the initial state in its history and factors of 1; then
+// one launch per step for all jobs, and the final normalisation of the
+// iterates that reach the window's end.
+int32_t ie_chunks(swr_handle h, const swr::RecJobs& rec, const int* rec_k, int S, hipStream_t st) {
+  const swr::Items it = h->items();
+  const int nT = (int)h->n_T;
+  const int norm = h->g.desc.unnormalized ? 0 : 1;
+  for (int j = 0; j < rec.n; ++j)
+    if (rec.n_lo[j] == 0) {
+      HIPCHECK(h, swr::launch_fill_history(it, nT, h->ptr<double2>(h->bC0), rec.hist[j], st));
+      HIPCHECK(h, swr::launch_fill_f64(h->nus_of(rec_k[j]), nT + 1, 1.0, st));
+    }
+  HIPCHECK(h, tbegin(h, st, kTRecur));
+  for (int q = 0; q < S; ++q) {
+    swr::IeJobs ie{};
+    for (int j = 0; j < rec.n; ++j) {
+      if (q >= rec.n_cnt[j]) continue;
+      ie.hist[ie.n] = rec.hist[j];
+      ie.F[ie.n] = rec.F[j];
+      ie.partial[ie.n] = h->iepart_of(rec_k[j]);
+      ie.nus[ie.n] = h->nus_of(rec_k[j]);
+      ie.step[ie.n] = rec.n_lo[j] + q;
+      ++ie.n;
+    }
+    if (ie.n == 0) break;
+    HIPCHECK(h, swr::launch_ie_step(it, ie, nT, h->g.desc.dt, h->ptr<double>(h->bA),
+                                    h->ptr<double>(h->bW), h->ptr<double2>(h->bMinv), norm,
+                                    h->ptr<int>(h->bFlags), st));
+  }
+  for (int j = 0; j < rec.n; ++j)
+    if (rec.n_lo[j] + rec.n_cnt[j] == nT)
+      HIPCHECK(h, swr::launch_ie_finish(it, nT, rec.hist[j], h->iepart_of(rec_k[j]),
+                                        h->nus_of(rec_k[j]), norm, st));
+  HIPCHECK(h, tend(h, st));
+  return SWR_OK;
+}
+
 int32_t run_pipelined(swr_handle h, const swr_run_opts* o, int P, swr_run_stats* out,
                       hipStream_t st, bool capture = false) {
   const swr::Items it = h->items();
   const int nT = (int)h->n_T;
   const int S = (nT + P - 1) / P;
   const int n_chunks = (nT + S - 1) / S;
-  const bool fused = h->fused_residual();
+  // Imaginary time: one launch per step, every iterate in flight in it; the
+  // residual of an iterate is taken once it is complete (and normalised)
+  const bool tise = h->g.desc.mode == SWR_TISE;
+  const bool fused = h->fused_residual() && !tise;
   if (fused && parts_needed(h, P, h->tx_tt) > h->part_stride)
     return fail(h, SWR_E_SIZE, "residual partials exceed their buffer");
   if (!capture && !h->ev_ready) {
@@ -1248,6 +1306,7 @@ int32_t run_pipelined(swr_handle h, const swr_run_opts* o, int P, swr_run_stats*
     tx.dt = h->g.desc.dt;
     tx.part_stride = h->part_stride;
     swr::RecJobs rec{};
+    int rec_k[swr::kMaxJobs] = {};
     for (int k = std::max(1, d - n_chunks + 2); k <= std::min(d + 1, o->k_max); ++k) {
       const int c = d - (k - 1);
       const int lo = c * S, cnt = std::min(S, nT - lo), hi = lo + cnt;
@@ -1256,6 +1315,10 @@ int32_t run_pipelined(swr_handle h, const swr_run_opts* o, int P, swr_run_stats*
         tx.dst[tx.n] = h->F_of(k);
         tx.n_lo[tx.n] = c == 0 ? 0 : lo + 1;
         tx.n_hi[tx.n] = hi;
+        // imaginary time: the Robin data of the unnormalised states; step
+        // hi of iterate k - 1 is normalised only by its next chunk, which
+        // runs after this transmission, and its factor there is still 1
+        tx.scale[tx.n] = tise ? h->nus_of(k - 1) : nullptr;
         if (fused) {
           tx.prev[tx.n] = h->hist_of(k - 2);
           tx.part[tx.n] = h->parts_of(k - 1);
@@ -1268,6 +1331,7 @@ int32_t run_pipelined(swr_handle h, const swr_run_opts* o, int P, swr_run_stats*
       rec.carry[rec.n] = h->carry_of(k);
       rec.n_lo[rec.n] = lo;
       rec.n_cnt[rec.n] = cnt;
+      rec_k[rec.n] = k;
       ++rec.n;
     }
     if (rec.n == 0) break;
@@ -1278,8 +1342,8 @@ int32_t run_pipelined(swr_handle h, const swr_run_opts* o, int P, swr_run_stats*
     if (tx.n > 0) {
       HIPCHECK(h, tbegin(h, st, kTTransmit));
       HIPCHECK(h, swr::launch_transmit(it, h->pairs(), h->te(), nT, h->ptr<double2>(h->bT), tx,
-                                       nullptr, h->nbt, h->te_pieces, h->te_max_recv,
-                                       h->te_max_send, h->te_gram_max, h->tx_tt, st));
+                                       h->nbt, h->te_pieces, h->te_max_recv, h->te_max_send,
+                                       h->te_gram_max, h->tx_tt, st));
       HIPCHECK(h, tend(h, st));
     }
     if (res_now) {
@@ -1296,13 +1360,18 @@ int32_t run_pipelined(swr_handle h, const swr_run_opts* o, int P, swr_run_stats*
       const int rc = queue_read(kr);
       if (rc) return rc;
     }
-    HIPCHECK(h, tbegin(h, st, kTRecur));
-    HIPCHECK(h, swr::launch_cn_recur(it, nT, h->ptr<double>(h->bAr), h->ptr<double>(h->bAp),
-                                     h->ptr<double>(h->bHr), h->ptr<double>(h->bQ),
-                                     h->ptr<double>(h->bE), 0.5 * h->g.desc.dt,
-                                     h->ptr<double2>(h->bMinv), h->ptr<double2>(h->bC0), rec,
-                                     h->ptr<int>(h->bFlags), st));
-    HIPCHECK(h, tend(h, st));
+    if (tise) {
+      const int rc = ie_chunks(h, rec, rec_k, S, st);
+      if (rc) return rc;
+    } else {
+      HIPCHECK(h, tbegin(h, st, kTRecur));
+      HIPCHECK(h, swr::launch_cn_recur(it, nT, h->ptr<double>(h->bAr), h->ptr<double>(h->bAp),
+                                       h->ptr<double>(h->bHr), h->ptr<double>(h->bQ),
+                                       h->ptr<double>(h->bE), 0.5 * h->g.desc.dt,
+                                       h->ptr<double2>(h->bMinv), h->ptr<double2>(h->bC0), rec,
+                                       h->ptr<int>(h->bFlags), st));
+      HIPCHECK(h, tend(h, st));
+    }
     if (res_now) {
       const int rc = read(kr);
       if (rc) return rc;
@@ -1312,7 +1381,8 @@ int32_t run_pipelined(swr_handle h, const swr_run_opts* o, int P, swr_run_stats*
   // iterates not checked inside the loop (the last one needs a transmission
   // of its own: iterate k_max + 1 is never started)
   for (int k = last_read + 1; k_final == 0 && k <= o->k_max; ++k) {
-    const int rc0 = transmit_and_residual(h, k, nullptr, h->ptr<double>(h->bResv) + k % 64, st);
+    const int rc0 = transmit_and_residual(h, k, tise ? h->nus_of(k) : nullptr,
+                                          h->ptr<double>(h->bResv) + k % 64, st);
     if (rc0) return rc0;
     int rc = queue_read(k);
     if (rc) return rc;
@@ -1324,7 +1394,8 @@ int32_t run_pipelined(swr_handle h, const swr_run_opts* o, int P, swr_run_stats*
   // state as after sweep + transmit of iterate k_final at depth 1
   h->k = k_final;
   h->cur = k_final % h->n_slots;
-  const int rc0 = transmit_and_residual(h, k_final, nullptr, nullptr, st);
+  const int rc0 = transmit_and_residual(h, k_final, tise ? h->nus_of(k_final) : nullptr, nullptr,
+                                        st);
   if (rc0) return rc0;
   if (!capture) {
     const int rc = check_flags(h, st);
@@ -1383,6 +1454,10 @@ int32_t run_graph(swr_handle h, const swr_run_opts* o, int P, swr_run_stats* out
 
 }  // namespace
 
+namespace {
+int32_t run_steps(swr_handle h, const swr_run_opts* o, swr_run_stats* out, void* stream);
+}  // namespace
+
 int32_t swr_run(swr_handle h, const swr_run_opts* o, swr_run_stats* stats, void* stream) {
   if (!h || !o) return fail(h, SWR_E_ARG, "null argument");
   if (o->k_max < 1) return fail(h, SWR_E_ARG, "k_max must be >= 1");
@@ -1398,15 +1473,34 @@ int32_t swr_run(swr_handle h, const swr_run_opts* o, swr_run_stats* stats, void*
   if (rc) return rc;
   swr_run_stats s{};
   const int P = o->depth <= 0 ? h->depth_run : std::min(o->depth, h->depth);
-  if (h->g.desc.mode == SWR_TDSE && P > 1) {
-    const bool graph = o->graph != 0 && o->tol < 0.0 && !h->timing;
+  const bool tise = h->g.desc.mode == SWR_TISE;
+  if (P > 1) {
+    const bool graph = o->graph != 0 && o->tol < 0.0 && !h->timing && !tise;
     rc = graph ? run_graph(h, o, P, &s, (hipStream_t)stream)
                : run_pipelined(h, o, P, &s, (hipStream_t)stream);
     if (rc) return rc;
-    HIPCHECK(h, tcollect(h, &s));
-    if (stats) *stats = s;
-    return SWR_OK;
+  } else {
+    rc = run_steps(h, o, &s, stream);
+    if (rc) return rc;
   }
+  if (tise) {
+    double nu = 1.0;
+    HIPCHECK(h, hipMemcpyAsync(&nu, h->nus_of(h->k) + h->n_T, 8, hipMemcpyDeviceToHost,
+                               (hipStream_t)stream));
+    HIPCHECK(h, hipStreamSynchronize((hipStream_t)stream));
+    s.energy = h->g.desc.unnormalized ? std::nan("") : (1.0 / nu - 1.0) / h->g.desc.dt;
+  }
+  HIPCHECK(h, tcollect(h, &s));
+  if (stats) *stats = s;
+  return SWR_OK;
+}
+
+namespace {
+
+// One Schwarz iterate at a time: sweep, then transmission and residual.
+int32_t run_steps(swr_handle h, const swr_run_opts* o, swr_run_stats* out, void* stream) {
+  swr_run_stats& s = *out;
+  int rc = SWR_OK;
   for (int k = 1; k <= o->k_max; ++k) {
     rc = swr_sweep(h, stream);
     if (rc) return rc;
@@ -1420,17 +1514,10 @@ int32_t swr_run(swr_handle h, const swr_run_opts* o, swr_run_stats* stats, void*
       break;
     }
   }
-  if (h->g.desc.mode == SWR_TISE) {
-    double nu = 1.0;
-    HIPCHECK(h, hipMemcpyAsync(&nu, h->ptr<double>(h->bNus) + h->n_T, 8, hipMemcpyDeviceToHost,
-                               (hipStream_t)stream));
-    HIPCHECK(h, hipStreamSynchronize((hipStream_t)stream));
-    s.energy = h->g.desc.unnormalized ? std::nan("") : (1.0 / nu - 1.0) / h->g.desc.dt;
-  }
-  HIPCHECK(h, tcollect(h, &s));
-  if (stats) *stats = s;
   return SWR_OK;
 }
+
+}  // namespace
 
 static int32_t copy_out(swr_handle h, const Buf& b, size_t bytes, void* dst, uint64_t cap,
                         void* stream) {
@@ -1567,7 +1654,8 @@ int32_t swr_local_eigen(swr_handle h, void* lambda_dev, void* vectors_dev, void*
 
 int32_t swr_get_norms(swr_handle h, void* dst_dev, uint64_t bytes, void* stream) {
   if (!h) return SWR_E_ARG;
-  return copy_out(h, h->bNus, (h->n_T + 1) * 8, dst_dev, bytes, stream);
+  const Buf& b = h->bNus[h->k % h->n_slots];
+  return copy_out(h, b, b.bytes, dst_dev, bytes, stream);
 }
 
 int32_t swr_set_field(swr_handle h, double E0, double omega, double phase) {
@@ -1678,9 +1766,8 @@ int32_t swr_autotune(swr_handle h, int32_t k_iters, double t0, swr_tuning* out, 
   if (k_iters < 1) return fail(h, SWR_E_ARG, "k_iters must be >= 1");
   if (!h->assembled || !h->initial) return fail(h, SWR_E_STATE, "swr_assemble and swr_set_initial first");
   hipStream_t st = (hipStream_t)stream;
-  const bool tdse = h->g.desc.mode == SWR_TDSE;
   std::vector<int> depths, tiles;
-  for (int d = 1; d <= (tdse ? h->depth : 1); ++d) depths.push_back(d);
+  for (int d = 1; d <= h->depth; ++d) depths.push_back(d);
   if (h->g.te_ok && !h->wide) {
     tiles.push_back(16);
     if (h->tx_tt_max == 32) tiles.push_back(32);

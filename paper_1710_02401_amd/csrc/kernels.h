@@ -112,6 +112,9 @@ struct TxJobs {
   int part_base[kMaxJobs];
   int part_stride;
   double dt;
+  // Optional per-step factor of the job's Robin data (imaginary time: the
+  // sending iterate's normalisation factors); null: 1.
+  const double* scale[kMaxJobs];
 };
 struct RecJobs {
   int n;
@@ -251,13 +254,13 @@ hipError_t launch_res_reduce(const double* part, int n_items, int part_stride, i
 hipError_t launch_tx_pack(const Items& it, const Pairs& pr, const TEnt& te, double2* blob,
                           hipStream_t st);
 // Robin data vectors of every job; the factored operators when te.n > 0,
-// else the dense T.  scale (per step, may be null) multiplies the result;
-// nbt = largest tangential basis size over items (1 when D = 1); pieces =
+// else the dense T.  jobs.scale (per job and step, may be null) multiplies
+// the result; nbt = largest tangential basis size over items (1 when D = 1); pieces =
 // largest LDS bytes of the a and X pieces an item sends; max_recv / max_send
 // = largest number of entries an item receives / sends; tile = steps per
 // block of the factored form (16 or 32, and its LDS must fit).
 hipError_t launch_transmit(const Items& it, const Pairs& pr, const TEnt& te, int n_steps,
-                           const double2* T, const TxJobs& jobs, const double* scale, int nbt,
+                           const double2* T, const TxJobs& jobs, int nbt,
                            int64_t pieces, int max_recv, int max_send, int64_t gram, int tile,
                            hipStream_t st);
 hipError_t launch_fill_history(const Items& it, int n_steps, const double2* c0, double2* hist,
@@ -268,12 +271,24 @@ hipError_t launch_residual(const Items& it, int n_steps, double dt, const double
                            const double2* cur, const double2* prev, double* partial,
                            double* out, hipStream_t st);
 // normalize = 0: imaginary-time steps without the global normalisation
-hipError_t launch_ie_step(const Items& it, int n, int n_steps, double dt, const double* A,
-                          const double* W, const double2* Minv, const double2* F,
-                          double2* hist, double* partial, double* nus, int normalize,
+// One imaginary-time step of each job (a Schwarz iterate: its history, Robin
+// data, partial norms [n_T + 1][n_items] and normalisation factors
+// [n_T + 1], at its own step n), every item; one launch for all jobs.
+struct IeJobs {
+  int n;
+  double2* hist[kMaxJobs];
+  const double2* F[kMaxJobs];
+  double* partial[kMaxJobs];
+  double* nus[kMaxJobs];
+  int step[kMaxJobs];
+};
+hipError_t launch_ie_step(const Items& it, const IeJobs& jobs, int n_steps, double dt,
+                          const double* A, const double* W, const double2* Minv, int normalize,
                           int* flags, hipStream_t st);
 hipError_t launch_ie_finish(const Items& it, int n_steps, double2* hist, const double* partial,
                             double* nus, int normalize, hipStream_t st);
+// p[0..n) = v
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t st);
 hipError_t launch_global_normalise(const Items& it, const double* W, double2* c0,
                                    double* partial, hipStream_t st);
 hipError_t launch_geneig(const Items& it, const double* A, const double* Hr, double* lam,

@@ -1252,10 +1252,10 @@ __global__ void __launch_bounds__(kRecThreads) k_cn_recur(Items it, int n_steps,
 // Dense form (any D); one job per grid z.
 constexpr int kTN = 32;
 __global__ void __launch_bounds__(kBlock) k_transmit(Items it, Pairs pr, int n_steps,
-                                                     const double2* T, TxJobs jobs,
-                                                     const double* scale) {
+                                                     const double2* T, TxJobs jobs) {
   const int i = blockIdx.y;
   const int job = blockIdx.z;
+  const double* scale = jobs.scale[job];
   const int n0 = jobs.n_lo[job] + blockIdx.x * kTN;
   const int n_hi = jobs.n_hi[job];
   if (n0 > n_hi) return;  // uniform over the block
@@ -1675,9 +1675,10 @@ __global__ void __launch_bounds__(kBlock) k_tx_send(Items it, TEnt te, int n_ste
 constexpr int kMaxRecvEntries = 64;
 template <int TT>
 __global__ void __launch_bounds__(kBlock) k_tx_recv(Items it, TEnt te, int n_steps, TxJobs jobs,
-                                                    const double* scale, int nbt) {
+                                                    int nbt) {
   const int i = blockIdx.y;
   const int job = blockIdx.z;
+  const double* scale = jobs.scale[job];
   const int n0 = jobs.n_lo[job] + blockIdx.x * TT;
   const int n_hi = jobs.n_hi[job];
   if (n0 > n_hi) return;
@@ -1879,14 +1880,19 @@ __device__ inline double norm_from_partials(const double* partial, int n_items, 
 // the columns m = w, w + 4, ... of wave w, partial sums added in LDS.  The
 // three matrices' slices are loaded into registers first, so their latency
 // overlaps the wait for the previous step's partial norms.
-__global__ void __launch_bounds__(kBlock) k_ie_step(Items it, int n, int n_steps, double dt,
+__global__ void __launch_bounds__(kBlock) k_ie_step(Items it, IeJobs jobs, int n_steps, double dt,
                                                     const double* A, const double* W,
-                                                    const double2* Minv, const double2* F,
-                                                    double2* hist, double* partial, double* nus,
-                                                    int normalize, int* flags) {
+                                                    const double2* Minv, int normalize,
+                                                    int* flags) {
   constexpr int kWaves = kBlock / 64;
   constexpr int kCols = kSmallK / kWaves;
   const int s = blockIdx.x;
+  const int job = blockIdx.y;
+  const int n = jobs.step[job];
+  double2* hist = jobs.hist[job];
+  const double2* F = jobs.F[job];
+  double* partial = jobs.partial[job];
+  double* nus = jobs.nus[job];
   const int K = it.K[s];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   __shared__ double c[kSmallK];
@@ -2579,7 +2585,7 @@ hipError_t launch_tx_pack(const Items& it, const Pairs& pr, const TEnt& te, doub
 }
 
 hipError_t launch_transmit(const Items& it, const Pairs& pr, const TEnt& te, int n_steps,
-                           const double2* T, const TxJobs& jobs, const double* scale, int nbt,
+                           const double2* T, const TxJobs& jobs, int nbt,
                            int64_t pieces, int max_recv, int max_send, int64_t gram, int tile,
                            hipStream_t st) {
   if (jobs.n < 1 || jobs.n > kMaxJobs) return hipErrorInvalidValue;
@@ -2607,8 +2613,7 @@ hipError_t launch_transmit(const Items& it, const Pairs& pr, const TEnt& te, int
       else
         hipLaunchKernelGGL((k_tx_send<32, 0>), grid, dim3(kBlock), lds, st, it, te, n_steps, jobs,
                            nbt, pieces, gram / 8);
-      hipLaunchKernelGGL(k_tx_recv<32>, grid, dim3(kBlock), 0, st, it, te, n_steps, jobs, scale,
-                         nbt);
+      hipLaunchKernelGGL(k_tx_recv<32>, grid, dim3(kBlock), 0, st, it, te, n_steps, jobs, nbt);
     } else {
       if (reg)
         hipLaunchKernelGGL((k_tx_send<16, 8>), grid, dim3(kBlock), lds, st, it, te, n_steps, jobs,
@@ -2616,12 +2621,11 @@ hipError_t launch_transmit(const Items& it, const Pairs& pr, const TEnt& te, int
       else
         hipLaunchKernelGGL((k_tx_send<16, 0>), grid, dim3(kBlock), lds, st, it, te, n_steps, jobs,
                            nbt, pieces, gram / 8);
-      hipLaunchKernelGGL(k_tx_recv<16>, grid, dim3(kBlock), 0, st, it, te, n_steps, jobs, scale,
-                         nbt);
+      hipLaunchKernelGGL(k_tx_recv<16>, grid, dim3(kBlock), 0, st, it, te, n_steps, jobs, nbt);
     }
   } else {
     dim3 grid(blocks_for(span, kTN), it.n_items, jobs.n);
-    hipLaunchKernelGGL(k_transmit, grid, dim3(kBlock), 0, st, it, pr, n_steps, T, jobs, scale);
+    hipLaunchKernelGGL(k_transmit, grid, dim3(kBlock), 0, st, it, pr, n_steps, T, jobs);
   }
   return hipGetLastError();
 }
@@ -2651,12 +2655,25 @@ hipError_t launch_residual(const Items& it, int n_steps, double dt, const double
   return hipGetLastError();
 }
 
-hipError_t launch_ie_step(const Items& it, int n, int n_steps, double dt, const double* A,
-                          const double* W, const double2* Minv, const double2* F,
-                          double2* hist, double* partial, double* nus, int normalize,
+hipError_t launch_ie_step(const Items& it, const IeJobs& jobs, int n_steps, double dt,
+                          const double* A, const double* W, const double2* Minv, int normalize,
                           int* flags, hipStream_t st) {
-  hipLaunchKernelGGL(k_ie_step, dim3(it.n_items), dim3(kBlock), 0, st, it, n, n_steps, dt, A, W,
-                     Minv, F, hist, partial, nus, normalize, flags);
+  if (jobs.n < 1 || jobs.n > kMaxJobs) return hipErrorInvalidValue;
+  for (int j = 0; j < jobs.n; ++j)
+    if (jobs.step[j] < 0 || jobs.step[j] >= n_steps) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_ie_step, dim3(it.n_items, jobs.n), dim3(kBlock), 0, st, it, jobs, n_steps,
+                     dt, A, W, Minv, normalize, flags);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_f64(double* p, int64_t n, double v) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) p[e] = v;
+}
+
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f64, dim3(blocks_for(n)), dim3(kBlock), 0, st, p, n, v);
   return hipGetLastError();
 }
 

@@ -140,11 +140,14 @@ def test_full_size_two_electron_sampled_subdomains():
     assert a_norm_rel(prob, got, ref, items=targets) <= 1e-10
 
 
-def test_imaginary_time_swr_energy_and_states():
+@pytest.mark.parametrize("depth", [1, 2, 0])
+def test_imaginary_time_swr_energy_and_states(depth):
+    """One iterate at a time (depth 1) and several in flight, each step
+    launch advancing every iterate (depth 2, and the library's choice)."""
     cfg = _cfg("tiny-2d-tise")
     s = _solver(cfg)
     prob = o_swr.Problem(cfg)
-    st = s.run(k_max=cfg["iters"], tol=0.0)
+    st = s.run(k_max=cfg["iters"], tol=0.0, depth=depth)
     h_o, res_o, en_o = o_tise.swr_tise(prob, iters=cfg["iters"])
     h_g = [np.real(_np(h)) for h in s.split_history(s.history())]
     assert a_norm_rel(prob, h_g, h_o) <= 1e-10
