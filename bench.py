@@ -40,12 +40,12 @@ MEASURED_TRAFFIC = {
     # (1 GiB copy calibration) over the first window at depth 4 with the
     # 32-step transmission tile: 23 recurrence launches, 24 transmissions,
     # one factorisation
-    "k_cn_recur": {"kernels_sha256": "fa4654efb45359d9", "bytes_per_launch": 2.1760e9},
-    "k_tx_send+k_tx_recv": {"kernels_sha256": "fa4654efb45359d9", "bytes_per_launch": 0.4601e9,
+    "k_cn_recur": {"kernels_sha256": "5fc6438905beeb77", "bytes_per_launch": 2.1760e9},
+    "k_tx_send+k_tx_recv": {"kernels_sha256": "5fc6438905beeb77", "bytes_per_launch": 0.4583e9,
                             "tx_tile": 32},
-    "k_series_assemble": {"kernels_sha256": "fa4654efb45359d9", "bytes_per_launch": 2.4356e9},
+    "k_series_assemble": {"kernels_sha256": "5fc6438905beeb77", "bytes_per_launch": 2.4357e9},
     # profiles/c3-1e-1d-batched_traffic.md: one sweep of the batched workload
-    "k_cn_recur_wide": {"wide_sha256": "b8ae3eabd3030a28", "bytes_per_launch": 1349.19e9},
+    "k_cn_recur_wide": {"wide_sha256": "b8ae3eabd3030a28", "bytes_per_launch": 1349.16e9},
 }
 
 
