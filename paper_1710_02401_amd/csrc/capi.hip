@@ -47,6 +47,8 @@ constexpr int kGpuCUs = 256;    // MI355X compute units
 // recurrence blocks per compute unit the depth aims at (its 512-thread block
 // needs more than 128 registers per lane, so a second one is not resident)
 constexpr int kRecPerCU = 1;
+// imaginary-time step blocks resident per CU (256 threads, < 128 registers)
+constexpr int kIePerCU = 4;
 // series inverses of the window (swr_factor): at most this many terms
 constexpr int kSeriesMaxTerms = 8;
 // K^2 slots per chunk of the wide path's series: G (or the refinement
@@ -596,8 +598,8 @@ int32_t swr_create(const swr_desc* desc, swr_handle* out) {
   h->scratch_total = scr;
   if (!h->wide) {
     // iterates in flight: enough blocks of one per item to fill the chip
-    // (the real-time recurrence and the imaginary-time steps alike)
-    const int fill = (kRecPerCU * kGpuCUs + g.n_items - 1) / g.n_items;
+    const int per_cu = g.desc.mode == SWR_TISE ? kIePerCU : kRecPerCU;
+    const int fill = (per_cu * kGpuCUs + g.n_items - 1) / g.n_items;
     h->depth = std::max(1, std::min({kMaxDepth, fill, (int)h->n_T}));
   }
   if (h->wide) {
