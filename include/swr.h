@@ -229,8 +229,12 @@ int32_t swr_transmit(swr_handle h, double* residual_host, void* stream);
  * iterates past the stopping one are started and discarded.  depth 0 takes
  * swr_info.depth (sized at creation so that P x n_items fills the GPU,
  * P <= 8); 1 runs one iterate at a time; larger values are capped at
- * swr_info.depth.  TISE always runs at depth 1 (its global normalisation
- * couples every item at every step). */
+ * swr_info.depth.  TISE pipelines the same way, with one launch per step
+ * (its global normalisation couples every item at every step) advancing
+ * every iterate in flight; each iterate keeps its own normalisation
+ * factors, and its residual is taken once it is complete.  Results agree
+ * with depth 1 to rounding (the residual is summed in another order).
+ * The HIP graph (opts.graph) is for TDSE only. */
 typedef struct swr_run_opts {
   int32_t k_max;
   double tol;
