@@ -93,7 +93,7 @@ def learned_summary(mode):
             "train_samples", "first_loss", "final_loss", "steps", "seconds")
     res = {k: out[k] for k in keep}
     # plain SWR with other Robin constants on the same held-out windows: the
-    # optimised-mu baseline the learned guess is to be judged against
+    # optimised-mu baseline the learned guess is compared against
     from paper_1710_02401_amd import studies
     by_mu = studies.held_out_windows_by_mu(cfg, [-1j, -2.5j, -5j, -10j, -20j, -40j],
                                            kw["eval_traj"], kw["eval_win"], 2402, 150, 1e-8)

@@ -545,7 +545,7 @@ int32_t swr_create(const swr_desc* desc, swr_handle* out) {
     return SWR_E_SIZE;
   }
   if (g.desc.dim > 2 || g.desc.n_elec > 2) {
-    g_create_error = "this build assembles at most two space dimensions per electron and 2 electrons";
+    g_create_error = "the library assembles at most two space dimensions per electron and 2 electrons";
     delete h;
     return SWR_E_SIZE;
   }

@@ -101,7 +101,7 @@ _C3 = dict(
     iters=30, tol=1e-8, face_nodes=[16, 32], quad_nodes=16,
 )
 
-# The same recipe at sizes this build runs (K <= 64): 4 geometries, 16
+# The same recipe at sizes the narrow path takes (K <= 64): 4 geometries, 16
 # subdomains, K from 8 to 40.
 _C3M_GEOMS, _C3M_NB = _uneven_geometries(4, 16, (-20.0, 20.0), 8, 32)
 _C3_MINI = dict(_C3, name="c3-mini", L=[16], overlap=[0.5], nbasis=_C3M_NB,
