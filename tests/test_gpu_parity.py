@@ -474,3 +474,26 @@ def test_autotuned_schedule_changes_no_result(name):
     st1 = s1.run(k_max=6, tol=-1.0)
     assert np.array_equal(_np(s1.history()), h0)
     assert np.allclose(st1["res"], st0["res"], rtol=1e-12, atol=0)
+
+
+def test_imaginary_time_pipelined_stops_where_depth_one_stops():
+    """With a residual target, the pipelined imaginary-time window stops at
+    the same iterate as one iterate at a time (the iterates started past it
+    are discarded) and returns its states and energy."""
+    cfg = _cfg("tiny-2d-tise")
+    s = _solver(cfg)
+    ref = s.run(k_max=cfg["iters"], tol=-1.0, depth=1)
+    tol = ref["res"][2] * (1.0 + 1e-9)  # above rounding differences of the two residual sums
+    stop = next(k for k in range(2, cfg["iters"] + 1) if ref["res"][k - 1] <= tol)
+    s.set_initial()
+    st1 = s.run(k_max=cfg["iters"], tol=tol, depth=1)
+    s.set_initial()
+    st = s.run(k_max=cfg["iters"], tol=tol, depth=0)
+    assert s.info.depth_run > 1
+    assert st1["iters"] == stop and st["iters"] == stop and st["converged"]
+    h = [_np(x) for x in s.split_history(s.history())]
+    prob = o_swr.Problem(cfg)
+    h_o, res_o, en_o = o_tise.swr_tise(prob, iters=stop)
+    assert a_norm_rel(prob, [np.real(x) for x in h], h_o) <= 1e-10
+    assert st["energy"] == pytest.approx(en_o[-1], rel=1e-10)
+    assert np.allclose(st["res"][:stop], ref["res"][:stop], rtol=1e-9, atol=1e-14)
