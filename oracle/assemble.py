@@ -31,7 +31,11 @@ Paper passages followed:
 Pinned by: closed forms of the one-dimensional factors, the co-centred
 soft-Coulomb identity with the modified Bessel function K_0, harmonic
 oscillator spectra (the oracle also accepts a harmonic potential for that
-pin), and Gram-matrix symmetry/positivity.
+pin), Gram-matrix symmetry/positivity, and, in more than one
+configuration dimension, adaptive two-dimensional quadrature of the
+two-electron potential on an off-diagonal subdomain and the unstaged sum
+over the whole four-dimensional grid of the two-electron, two-dimension
+potential (tests/test_oracle_potential_md.py).
 """
 import math
 

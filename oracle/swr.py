@@ -24,9 +24,12 @@ Paper passages followed:
 Pinned by: Crank-Nicolson invariants (A-norm conservation for Hermitian
 H~, time reversal -- with the two-component field too -- and second order),
 free Gaussian packet spreading, Ehrenfest drift in a uniform field and, per
-coordinate, in the circular pulse of Section 5 Test 3, and converged SWR
+coordinate, in the circular pulse of Section 5 Test 3, converged SWR
 against a brute-force finite-difference solution of the same boundary value
-problem.
+problem in one dimension and, on a 2 x 2 decomposition with corner zones
+of three covering neighbours, in two (tests/test_oracle_swr_md.py), and
+the residual Res(k) against its closed form for basis functions switched on
+with a known time profile (same file).
 """
 import numpy as np
 
