@@ -42,7 +42,9 @@ enum {
   SWR_E_STATE = -4,    /* call out of order (e.g. sweep before assemble)       */
   SWR_E_SINGULAR = -5, /* zero pivot met in a device factorisation             */
   SWR_E_NAN = -6,      /* non-finite value produced on the device              */
-  SWR_E_NOCONV = -7    /* iteration cap reached above the residual target      */
+  SWR_E_NOCONV = -7,   /* iteration cap reached above the residual target      */
+  SWR_E_COND = -8      /* a local Gram matrix is too ill-conditioned for the
+                          accuracy of the path (see swr_create)               */
 };
 
 enum { SWR_TDSE = 0, SWR_TISE = 1 };
@@ -137,7 +139,12 @@ typedef struct swr_info {
  * decomposition).  Validates the description: SWR_E_ARG for inconsistent
  * fields, SWR_E_SIZE if a basis exceeds the kernels' limits: K <= 64 per
  * subdomain, or K <= 256 for one electron in one dimension in real time
- * (the wide-basis path, see swr_factor).  *out receives a new handle. */
+ * (the wide-basis path, see swr_factor).  SWR_E_COND if the Gram matrix A
+ * of some subdomain has a condition number above 1e6: the recurrence of
+ * swr_sweep reuses the previous right-hand side as M^n c^n, which feeds the
+ * stored inverses' residual (about cond(M) eps) into every later step, and
+ * such bases would end measurably away from the LU-solved answer while
+ * reporting success.  *out receives a new handle. */
 int32_t swr_create(const swr_desc* desc, swr_handle* out);
 void swr_destroy(swr_handle h);
 const char* swr_last_error(swr_handle h);
@@ -210,7 +217,7 @@ int32_t swr_factor(swr_handle h, double t0, void* stream);
  * Accuracy: M^n c^n is taken from the previous step's right-hand side, so
  * the stored inverses' residual (about cond(M) eps) enters every later step:
  * the error per step is about cond(M)^2 eps.  Bases whose Gram matrices are
- * nearly singular (condition above about 1e6) lose accuracy. */
+ * nearly singular (condition above 1e6) are refused by swr_create. */
 int32_t swr_sweep(swr_handle h, void* stream);
 
 /* Transmission (Section 4.1, averaged Robin TC in multi-overlap zones, eq.

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -54,6 +55,98 @@ constexpr int kSeriesMaxTerms = 8;
 // K^2 slots per chunk of the wide path's series: G (or the refinement
 // residual), the unrefined anchor inverse, then the terms P_0, P_1, ...
 constexpr int kWideSlots = swr::kWideTerms + 2;
+
+// Largest condition number of a subdomain's Gram matrix A that the stored-
+// inverse recurrence serves: it takes M^n c^n from the previous step's
+// right-hand side, so the explicit inverses' residual (about cond eps)
+// enters every later step.  Validated to agree with the oracle to 1e-10 up
+// to 2e5 (the paper's Test 2.b boxes); the Test 3 boxes with delta = 0.5
+// (condition 1.6e8) end 3 % away.
+constexpr double kCondLimit = 1e6;
+
+// Condition number (2-norm) of the one-dimensional Gram matrix
+// S_ab = int_lo^hi exp(-d (x - a_a)^2) exp(-d (x - a_b)^2) dx: Cholesky,
+// then power iteration for the largest eigenvalue and inverse iteration for
+// the smallest (an estimate within a small factor, enough for a limit
+// check); infinity when S is not numerically positive definite.
+double gram_condition_1d(const double* al, int n, double d, double lo, double hi) {
+  if (n <= 1) return 1.0;
+  std::vector<double> S((size_t)n * n), L((size_t)n * n, 0.0);
+  const double pi = 3.14159265358979323846;
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) {
+      const double p = 2.0 * d, P = 0.5 * (al[a] + al[b]);
+      const double E = std::exp(-0.5 * d * (al[a] - al[b]) * (al[a] - al[b]));
+      const double r = std::sqrt(p);
+      S[(size_t)a * n + b] = E * 0.5 * std::sqrt(pi / p) * (std::erf(r * (hi - P)) - std::erf(r * (lo - P)));
+    }
+  for (int j = 0; j < n; ++j) {
+    double v = S[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) v -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+    if (!(v > 0.0)) return INFINITY;
+    const double ljj = std::sqrt(v);
+    L[(size_t)j * n + j] = ljj;
+    for (int i = j + 1; i < n; ++i) {
+      double u = S[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) u -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+      L[(size_t)i * n + j] = u / ljj;
+    }
+  }
+  auto normalise = [n](std::vector<double>& x) {
+    double s = 0.0;
+    for (double v : x) s += v * v;
+    s = std::sqrt(s);
+    for (double& v : x) v /= s;
+    return s;
+  };
+  std::vector<double> x(n), y(n);
+  for (int i = 0; i < n; ++i) x[i] = 1.0 + 0.25 * (i % 3);
+  normalise(x);
+  double lmax = 0.0;
+  for (int it = 0; it < 30; ++it) {
+    for (int i = 0; i < n; ++i) {
+      double v = 0.0;
+      for (int j = 0; j < n; ++j) v += S[(size_t)i * n + j] * x[j];
+      y[i] = v;
+    }
+    lmax = normalise(y);
+    x.swap(y);
+  }
+  for (int i = 0; i < n; ++i) x[i] = 1.0 - 0.5 * (i % 2);
+  normalise(x);
+  double inv = 0.0;
+  for (int it = 0; it < 30; ++it) {
+    for (int i = 0; i < n; ++i) {  // L z = x
+      double v = x[i];
+      for (int k = 0; k < i; ++k) v -= L[(size_t)i * n + k] * y[k];
+      y[i] = v / L[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {  // L^T w = z
+      double v = y[i];
+      for (int k = i + 1; k < n; ++k) v -= L[(size_t)k * n + i] * y[k];
+      y[i] = v / L[(size_t)i * n + i];
+    }
+    inv = normalise(y);
+    x.swap(y);
+  }
+  return lmax * inv;
+}
+
+// Largest Gram condition over the subdomains of one geometry (the boxes and
+// bases are shared by every geometry): the product of the per-dimension
+// conditions, exact for tensor bases.
+double max_gram_condition(const Geometry& g) {
+  double worst = 1.0;
+  for (int s = 0; s < g.n_sub; ++s) {
+    double c = 1.0;
+    for (int k = 0; k < g.D; ++k) {
+      const size_t q = (size_t)s * 4 + k;
+      c *= gram_condition_1d(&g.alpha[g.aoff[q]], g.nb[q], g.delta[q], g.lo[q], g.hi[q]);
+    }
+    worst = std::max(worst, c);
+  }
+  return worst;
+}
 
 const char* const kShortWindow =
     "the learned warm start's time nodes are not distinct: the window has too few steps";
@@ -538,6 +631,19 @@ int32_t swr_create(const swr_desc* desc, swr_handle* out) {
                      "are not available";
     delete h;
     return SWR_E_SIZE;
+  }
+  {
+    const double cond = max_gram_condition(g);
+    if (!(cond <= kCondLimit)) {
+      char buf[200];
+      std::snprintf(buf, sizeof buf,
+                    "a subdomain's Gram matrix has condition %.3g, above the %.0e the "
+                    "stored-inverse recurrence keeps to 1e-10 (widen the Gaussians or use "
+                    "fewer per subdomain)", cond, kCondLimit);
+      g_create_error = buf;
+      delete h;
+      return SWR_E_COND;
+    }
   }
   if (g.desc.n_steps > 16384) {
     g_create_error = "n_steps above 16384 (the field table of a window is staged in LDS)";

@@ -13,8 +13,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libswr.so")
 
-SWR_OK, SWR_E_ARG, SWR_E_SIZE, SWR_E_DEVICE, SWR_E_STATE, SWR_E_SINGULAR, SWR_E_NAN, SWR_E_NOCONV = (
-    0, -1, -2, -3, -4, -5, -6, -7)
+(SWR_OK, SWR_E_ARG, SWR_E_SIZE, SWR_E_DEVICE, SWR_E_STATE, SWR_E_SINGULAR, SWR_E_NAN, SWR_E_NOCONV,
+ SWR_E_COND) = (0, -1, -2, -3, -4, -5, -6, -7, -8)
 SWR_TDSE, SWR_TISE = 0, 1
 SWR_WARM_PLAIN, SWR_WARM_ZERO, SWR_WARM_GIVEN = 0, 1, 2
 SWR_FACTOR_AUTO, SWR_FACTOR_DIRECT, SWR_FACTOR_WIDE = 0, 1, 2

@@ -297,3 +297,19 @@ def test_wide_bases_need_the_series(S, mutate):
     rc, h = _create(S, cfg)
     assert rc == -2
     assert b"field series" in S.load_library().swr_last_error(None)
+
+
+def test_ill_conditioned_gram_refused(S):
+    """The paper's Test 3 boxes with Test 2.a's delta = 0.5 make the Gram
+    matrices nearly singular (condition 1.6e8): swr_create refuses them with
+    SWR_E_COND instead of running a recurrence whose stored inverses would
+    put the answer measurably off; the same boxes with widths 0.7 x spacing
+    (condition 2.2e3) are accepted."""
+    cfg = workloads.get_config("paper-test-3", width=1.0, width_ratio=None)
+    rc, h = _create(S, cfg)
+    assert rc == S.SWR_E_COND
+    msg = S.load_library().swr_last_error(None).decode()
+    assert "condition" in msg and "1.6" in msg
+    rc, h = _create(S, workloads.get_config("paper-test-3"))
+    assert rc == 0
+    S.load_library().swr_destroy(h)
