@@ -130,6 +130,7 @@ typedef struct swr_info {
   int32_t depth_run;         /* depth swr_run uses for opts.depth = 0
                                 (swr_info.depth until swr_autotune)          */
   int32_t wide;              /* 1: the wide-basis path (see swr_factor)       */
+  int32_t block;             /* 1: the block path (see swr_factor)            */
 } swr_info;
 
 /* ---- lifetime ------------------------------------------------------------*/
@@ -206,7 +207,7 @@ int32_t swr_warm_start(swr_handle h, int32_t mode, const void* g_dev, void* stre
  * SWR_FACTOR_DIRECT, which the wide path refuses at creation).
  * A circular field (SWR_FIELD_CIRCULAR) has two scalars per step: every M^n
  * is inverted. */
-enum { SWR_FACTOR_AUTO = 0, SWR_FACTOR_DIRECT = 1, SWR_FACTOR_WIDE = 2 };
+enum { SWR_FACTOR_AUTO = 0, SWR_FACTOR_DIRECT = 1, SWR_FACTOR_WIDE = 2, SWR_FACTOR_BLOCK = 3 };
 int32_t swr_factor(swr_handle h, double t0, void* stream);
 
 /* One Schwarz iteration of local solves for every item (Section 4.4 step 2):

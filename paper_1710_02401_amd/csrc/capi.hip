@@ -12,6 +12,7 @@
 
 #include "../../include/swr.h"
 #include "geometry.h"
+#include "block.h"
 #include "kernels.h"
 
 using swr::Geometry;
@@ -240,6 +241,31 @@ struct swr_handle_s {
   std::vector<int32_t> te_sdesc;  // sender-side entry descriptors
   int n_slots = 2;  // history / Robin data slots: iterate k uses slot k % n_slots
 
+  // block path (tensor bases in two or four dimensions up to K = 1536,
+  // orthonormalised per dimension; block.hip)
+  bool block = false;
+  std::vector<swr::BlkDim> bdim;       // [n_items][4] (host part)
+  std::vector<int64_t> pot_off;        // [n_items + 1] potential scratch (doubles)
+  std::vector<int64_t> blk_foff;       // [n_items + 1] packed-term offsets (complex)
+  std::vector<int32_t> blk_terms;      // [n_items] series terms of the last factor
+  std::vector<int64_t> blk_toff;       // [n_items + 1] 64 x 64 tiles
+  std::vector<double> blk_Ea;          // anchor field per chunk
+  Buf bBd, bBlkPotOff, bBlkVp, bBlkY0, bBlkF0, bBlkF1, bBlkRing, bBlkPart, bBlkRb, bBlkTr,
+      bBlkFrag, bBlkTerms, bBlkFoff, bBlkTileOff, bBlkEa, bBlkCp, bBlkRp, bBlkCvec, bBlkRegion;
+  int blk_depth = 1;       // iterates in flight at most
+  int blk_slots = 2;       // history slots (depth + 1)
+  int blk_chunks = 1;      // anchors per window
+  int blk_chunk_len = 1;   // steps per anchor
+  int blk_pot_batch = 1;   // items per batch of the four-dimensional potential stage
+  int64_t blk_stage_item = 0;  // doubles of one item's potential stage
+  int blk_qmax = 1, blk_qqmax = 1;
+  int blk_fstride = 1;     // face nodes per face (trace scratch stride)
+  int64_t blk_pot_total = 0;   // doubles of the potential scratch
+  int blk_k = 0;           // Schwarz iterations done in the window
+  int blk_cur = 0;         // history slot of iterate blk_k
+  int blk_warm = SWR_WARM_PLAIN;
+  double blk_last_res = 0.0;
+
   // host side of the pipelined run's residual read-back
   double* res_pinned = nullptr;
   hipEvent_t ev[kResEvents] = {};
@@ -336,6 +362,32 @@ struct swr_handle_s {
     return ptr<double>(bParts) + (size_t)(k % n_slots) * g.n_items * part_stride;
   }
   bool fused_residual() const { return g.te_ok; }
+  swr::BlkItems blk_items() const {
+    swr::BlkItems b{};
+    b.it = items();
+    b.bd = ptr<swr::BlkDim>(bBd);
+    b.terms = ptr<int32_t>(bBlkTerms);
+    b.foff = ptr<int64_t>(bBlkFoff);
+    b.fmask = b.it.qmask0;
+    b.fstride = blk_fstride;
+    b.tau = 0.5 * g.desc.dt;
+    b.mu_re = g.desc.mu_re;
+    b.mu_im = g.desc.mu_im;
+    return b;
+  }
+  swr::BlkState blk_state() const {
+    swr::BlkState S{};
+    S.hist = ptr<double2>(bBlkRegion);
+    S.hstride = (n_T + 1) * sum_K;
+    S.ring = ptr<double2>(bBlkRing);
+    S.F1 = ptr<double2>(bBlkF1);
+    S.F0 = ptr<double2>(bBlkF0);
+    S.y0 = ptr<double2>(bBlkY0);
+    S.part = ptr<double>(bBlkPart);
+    S.pstride = (int64_t)g.n_items * (n_T + 1);
+    S.n_steps = (int)n_T;
+    return S;
+  }
   swr::TEnt te() const {
     swr::TEnt t{};
     t.n = g.te_ok ? (int64_t)g.te_pair.size() : 0;
@@ -589,6 +641,516 @@ hipError_t tcollect(swr_handle h, swr_run_stats* s) {
   return hipSuccess;
 }
 
+// ---------------------------------------------------------------------------
+// Block path (block.hip): host side.
+
+constexpr int kBlkDepth = swr::kBlkCols - 1;  // iterates in flight, + the one they follow
+constexpr int kBlkPotBatch = 16;               // items per four-dimensional potential batch
+
+// least number of series terms K + 1 with rho^{K+1}/(1 - rho) <= 2^-53; 0
+// when more than max_terms would be needed
+int series_terms(double rho, int max_terms) {
+  if (!(rho < 0.5)) return 0;
+  int t = 1;
+  for (double tail = rho / (1.0 - rho); tail > 0x1p-53 && t <= max_terms; ++t) tail *= rho;
+  return t > max_terms ? 0 : t;
+}
+
+// Empty when the block path can take the description, else the reason.
+std::string blk_unsupported(const Geometry& g) {
+  const swr_desc& d = g.desc;
+  if (!(g.D == 2 || g.D == 4)) return "the block path takes two or four configuration dimensions";
+  if (d.mode != SWR_TDSE) return "the block path is for real time";
+  if (d.field_shape != SWR_FIELD_SINE) return "the block path takes the sine field";
+  if (d.mu_im > 0.0) return "the block path needs Im mu <= 0 (the field series)";
+  if (g.K_max > swr::kBlkK) return "basis size per subdomain above 1536 (block path)";
+  const int nt = 2 * d.face_nodes_band + d.face_nodes_mid;
+  if (nt > swr::kBlkNt) return "more than 32 face nodes per tangential dimension (block path)";
+  int face = 1;
+  for (int k = 1; k < g.D; ++k) face *= nt;
+  if (face > swr::kBlkFace) return "more than 512 nodes per face (block path)";
+  for (int k = 0; k < g.D; ++k) {
+    const double width = g.hi1[k][0] - g.lo1[k][0];
+    if (g.L[k] > 1 && !(g.eps[k] > 0.0 && 2.0 * g.eps[k] < width))
+      return "the block path needs overlaps 0 < eps < core width";
+  }
+  for (int s = 0; s < g.n_items; ++s)
+    for (int k = 0; k < g.D; ++k) {
+      if (g.nb[(size_t)s * 4 + k] > swr::kBlkN) return "more than 8 Gaussians per dimension (block path)";
+      if (g.qn[(size_t)s * 4 + k] > 4096) return "potential quadrature too fine (block path)";
+    }
+  if (g.D == 4)
+    for (int s = 0; s < g.n_items; ++s) {
+      const int q1 = g.qn[(size_t)s * 4 + 1], n3 = g.nb[(size_t)s * 4 + 3];
+      if (q1 > swr::kEeQ || q1 * n3 * n3 > swr::kEeZ)
+        return "potential quadrature too fine for the four-dimensional stage (block path)";
+    }
+  return "";
+}
+
+void plan_block_layout(swr_handle h) {
+  const Geometry& g = h->g;
+  const size_t NI = g.n_items;
+  Layout& L = h->lay;
+  L = Layout();
+  h->bK = L.add(NI * 4);
+  h->bOff1 = L.add((NI + 1) * 8);
+  h->bOff2 = L.add((NI + 1) * 8);
+  h->bOffP = L.add((NI + 1) * 8);
+  h->bIdx = L.add(NI * 16);
+  h->bNb = L.add(NI * 16);
+  h->bL = L.add(16);
+  h->bLo = L.add(NI * 32);
+  h->bHi = L.add(NI * 32);
+  h->bEps = L.add(32);
+  h->bDelta = L.add(NI * 32);
+  h->bAoff = L.add(NI * 32);
+  h->bAlpha = L.add(g.alpha.size() * 8);
+  h->bQoff = L.add(NI * 32);
+  h->bQn = L.add(NI * 16);
+  h->bQx = L.add(g.qx.size() * 8);
+  h->bQw = L.add(g.qw.size() * 8);
+  h->bPos = L.add(std::max<size_t>(1, g.nuc_pos.size()) * 8);
+  h->bCharge = L.add(std::max<size_t>(1, g.nuc_charge.size()) * 8);
+  h->bCenter = L.add(32);
+  h->bFlags = L.add(8);
+  h->bResOut = L.add(8);
+  h->bResv = L.add(64 * 8);
+  h->bE = L.add((h->n_T + 1) * 8);
+  h->bBd = L.add(NI * 4 * sizeof(swr::BlkDim));
+  h->bBlkPotOff = L.add((NI + 1) * 8);
+  h->bBlkVp = L.add(h->sum_K2 * 8);
+  h->bBlkY0 = L.add(h->sum_K * 16);
+  h->bBlkF0 = L.add(h->sum_K * 16);
+  h->bBlkF1 = L.add(h->sum_K * 16);
+  h->bBlkRing = L.add((size_t)h->blk_slots * 2 * h->sum_K * 16);
+  h->bBlkPart = L.add((size_t)h->blk_slots * NI * (h->n_T + 1) * 8);
+  h->bBlkRb = L.add(h->sum_K * swr::kBlkCols * 16);
+  h->bBlkTr = L.add((size_t)swr::kBlkCols * NI * g.D * swr::kBlkPos * h->blk_fstride * 16);
+  h->bBlkFrag = L.add((size_t)h->blk_chunks * h->blk_foff.back() * 16);
+  h->bBlkTerms = L.add(NI * 4);
+  h->bBlkFoff = L.add((NI + 1) * 8);
+  h->bBlkTileOff = L.add((NI + 1) * 8);
+  h->bBlkEa = L.add((size_t)h->blk_chunks * 8);
+  h->bBlkCp = L.add((size_t)h->blk_chunks * swr::kBlkGJ * h->sum_K * 16);
+  h->bBlkRp = L.add((size_t)h->blk_chunks * swr::kBlkGJ * h->sum_K * 16);
+  h->bBlkCvec = L.add(h->sum_K * 16);
+  // one region for the iterates' histories, reused (outside a window's
+  // iterations) by the potential's scratch at assembly and by the anchor
+  // matrices and series products at factorisation
+  const size_t hist = (size_t)h->blk_slots * (h->n_T + 1) * h->sum_K * 16;
+  const size_t pot = (size_t)(h->blk_pot_total + (int64_t)h->blk_pot_batch * h->blk_stage_item) * 8 + 256;
+  const size_t fac = (size_t)3 * h->blk_chunks * h->sum_K2 * 16;
+  h->bBlkRegion = L.add(std::max({hist, pot, fac}));
+}
+
+// Per-item sizes the block path derives at creation.
+int blk_prepare(swr_handle h, std::string* msg) {
+  const Geometry& g = h->g;
+  const int NI = g.n_items;
+  h->block = true;
+  h->blk_depth = kBlkDepth;
+  h->blk_slots = kBlkDepth + 1;
+  // anchors per window: the field moves by at most E0 |omega| per unit time,
+  // so a chunk of T_c has a half range <= E0 |omega| T_c / 2
+  const double tau = 0.5 * g.desc.dt;
+  const double slope = std::fabs(g.desc.E0 * g.desc.omega);
+  int nc = 1;
+  for (; nc <= 64; ++nc) {
+    const int64_t cl = (h->n_T + nc - 1) / nc;
+    const double half = 0.5 * slope * cl * g.desc.dt;
+    if (series_terms(tau * half * h->dipole_max, swr::kBlkTerms) > 0) break;
+  }
+  if (nc > 64) {
+    *msg = "the field varies too fast for the block path's series (64 anchors per window)";
+    return SWR_E_SIZE;
+  }
+  h->blk_chunk_len = (int)((h->n_T + nc - 1) / nc);
+  h->blk_chunks = (int)((h->n_T + h->blk_chunk_len - 1) / h->blk_chunk_len);
+  // potential scratch, packed terms, tiles, face stride
+  h->pot_off.assign(NI + 1, 0);
+  h->blk_foff.assign(NI + 1, 0);
+  h->blk_toff.assign(NI + 1, 0);
+  h->blk_stage_item = 0;
+  h->blk_qmax = h->blk_qqmax = 1;
+  for (int s = 0; s < NI; ++s) {
+    int32_t nb[4], qn[4];
+    for (int k = 0; k < 4; ++k) {
+      nb[k] = k < g.D ? g.nb[(size_t)s * 4 + k] : 1;
+      qn[k] = k < g.D ? g.qn[(size_t)s * 4 + k] : 1;
+      h->blk_qmax = std::max(h->blk_qmax, qn[k]);
+    }
+    if (g.D == 4) h->blk_qqmax = std::max(h->blk_qqmax, qn[0] * qn[2]);
+    h->pot_off[s + 1] = h->pot_off[s] + swr::blk_pot_item_doubles(nb, qn, g.D);
+    h->blk_stage_item =
+        std::max(h->blk_stage_item, swr::blk_pot_stage_doubles(nb, qn, g.D, g.desc.n_elec));
+    const int K = g.K[s];
+    const int64_t fs = (int64_t)((K + 15) / 16) * ((K + 3) / 4) * 64;
+    h->blk_foff[s + 1] = h->blk_foff[s] + swr::kBlkTerms * fs;
+    const int64_t t = (K + 63) / 64;
+    h->blk_toff[s + 1] = h->blk_toff[s] + t * t;
+  }
+  h->blk_pot_total = h->pot_off.back();
+  h->blk_pot_batch = std::max(1, std::min(NI, kBlkPotBatch));
+  const int nt = 2 * g.desc.face_nodes_band + g.desc.face_nodes_mid;
+  h->blk_fstride = 1;
+  for (int k = 1; k < g.D; ++k) h->blk_fstride *= nt;
+  h->blk_terms.assign(NI, 1);
+  h->depth = h->depth_run = h->blk_depth;
+  plan_block_layout(h);
+  return SWR_OK;
+}
+
+int32_t blk_assemble(swr_handle h, hipStream_t st) {
+  const Geometry& g = h->g;
+  const int NI = g.n_items;
+  std::vector<int32_t> L4(4, 1);
+  std::vector<double> eps4(4, 0.0), cen4(4, 0.0);
+  for (int k = 0; k < g.D; ++k) {
+    L4[k] = g.L[k];
+    eps4[k] = g.eps[k];
+    cen4[k] = g.desc.init_center[k];
+  }
+  std::vector<int64_t> zoffp(NI + 1, 0);
+  HIPCHECK(h, upload(h, h->bK, g.K, st));
+  HIPCHECK(h, upload(h, h->bOff1, g.off1, st));
+  HIPCHECK(h, upload(h, h->bOff2, g.off2, st));
+  HIPCHECK(h, upload(h, h->bOffP, zoffp, st));
+  HIPCHECK(h, upload(h, h->bIdx, g.idx, st));
+  HIPCHECK(h, upload(h, h->bNb, g.nb, st));
+  HIPCHECK(h, upload(h, h->bL, L4, st));
+  HIPCHECK(h, upload(h, h->bLo, g.lo, st));
+  HIPCHECK(h, upload(h, h->bHi, g.hi, st));
+  HIPCHECK(h, upload(h, h->bEps, eps4, st));
+  HIPCHECK(h, upload(h, h->bDelta, g.delta, st));
+  HIPCHECK(h, upload(h, h->bAoff, g.aoff, st));
+  HIPCHECK(h, upload(h, h->bAlpha, g.alpha, st));
+  HIPCHECK(h, upload(h, h->bQoff, g.qoff, st));
+  HIPCHECK(h, upload(h, h->bQn, g.qn, st));
+  HIPCHECK(h, upload(h, h->bQx, g.qx, st));
+  HIPCHECK(h, upload(h, h->bQw, g.qw, st));
+  HIPCHECK(h, upload(h, h->bPos, g.nuc_pos, st));
+  HIPCHECK(h, upload(h, h->bCharge, g.nuc_charge, st));
+  HIPCHECK(h, upload(h, h->bCenter, cen4, st));
+  // per (item, dimension) one-dimensional data: sizes and the face rule
+  h->bdim.assign((size_t)NI * 4, swr::BlkDim{});
+  for (int s = 0; s < NI; ++s)
+    for (int k = 0; k < g.D; ++k) {
+      swr::BlkDim& d = h->bdim[(size_t)s * 4 + k];
+      d.n = g.nb[(size_t)s * 4 + k];
+      d.band = g.desc.face_nodes_band;
+      d.mid = g.desc.face_nodes_mid;
+      d.nt = 2 * d.band + d.mid;
+      d.lo = g.lo[(size_t)s * 4 + k];
+      d.hi = g.hi[(size_t)s * 4 + k];
+      d.eps = g.eps[k];
+      std::vector<double> x, w;
+      swr::face_rule_1d(g, s, k, &x, &w);
+      for (int t = 0; t < d.nt; ++t) {
+        d.tx[t] = x[t];
+        d.tw[t] = w[t];
+      }
+    }
+  HIPCHECK(h, upload(h, h->bBd, h->bdim, st));
+  HIPCHECK(h, upload(h, h->bBlkPotOff, h->pot_off, st));
+  HIPCHECK(h, upload(h, h->bBlkFoff, h->blk_foff, st));
+  HIPCHECK(h, upload(h, h->bBlkTileOff, h->blk_toff, st));
+  HIPCHECK(h, upload(h, h->bBlkTerms, h->blk_terms, st));
+  HIPCHECK(h, hipMemsetAsync(h->ptr<int>(h->bFlags), 0, 8, st));
+  HIPCHECK(h, hipMemsetAsync(h->ptr<double2>(h->bBlkRb), 0, h->bBlkRb.bytes, st));
+  const swr::Items it = h->items();
+  HIPCHECK(h, swr::launch_blk_dims(it, h->ptr<swr::BlkDim>(h->bBd), g.desc.mu_re, g.desc.mu_im,
+                                   g.desc.init_alpha, h->ptr<double>(h->bCenter),
+                                   h->ptr<int>(h->bFlags), st));
+  const swr::BlkItems b = h->blk_items();
+  swr::Potential pot{g.desc.n_nuc, h->ptr<double>(h->bPos), h->ptr<double>(h->bCharge),
+                     g.desc.eps_en, g.desc.eps_ee};
+  double* scratch = h->ptr<double>(h->bBlkRegion);
+  HIPCHECK(h, swr::launch_blk_potential(b, pot, h->ptr<int64_t>(h->bBlkPotOff), scratch,
+                                        scratch + h->blk_pot_total, h->blk_stage_item,
+                                        h->blk_pot_batch, h->blk_qmax, h->blk_qqmax, g.K_max,
+                                        h->ptr<double>(h->bBlkVp), st));
+  HIPCHECK(h, hipStreamSynchronize(st));
+  const int rc = check_flags(h, st);
+  if (rc != SWR_OK)
+    return fail(h, rc, "a one-dimensional Gram matrix is not positive definite (Cholesky)");
+  h->assembled = true;
+  h->initial = h->warm = h->factored = false;
+  h->blk_k = 0;
+  return SWR_OK;
+}
+
+int32_t blk_set_initial(swr_handle h, const void* c0_dev, hipStream_t st) {
+  const swr::BlkItems b = h->blk_items();
+  double2* y0 = h->ptr<double2>(h->bBlkY0);
+  if (c0_dev) {
+    HIPCHECK(h, swr::launch_blk_kron(b, 0, (const double2*)c0_dev, 1, 0, y0, 1, 1, st));
+  } else {
+    const double norm = std::pow(2.0 * h->g.desc.init_alpha / 3.14159265358979323846, 0.25 * h->g.D);
+    HIPCHECK(h, swr::launch_blk_project(b, norm, h->g.K_max, y0, st));
+  }
+  h->initial = true;
+  h->warm = false;
+  h->blk_k = 0;
+  return SWR_OK;
+}
+
+swr::BlkTx blk_tx_one(int slot, int step, int prev, int dst) {
+  swr::BlkTx tx{};
+  tx.n = 1;
+  tx.slot[0] = slot;
+  tx.step[0] = step;
+  tx.prev[0] = prev;
+  tx.dst[0] = dst;
+  return tx;
+}
+
+int32_t blk_warm_start(swr_handle h, int mode, hipStream_t st) {
+  if (mode == SWR_WARM_GIVEN)
+    return fail(h, SWR_E_ARG, "the block path takes the plain or the zero warm start");
+  if (mode != SWR_WARM_PLAIN && mode != SWR_WARM_ZERO) return fail(h, SWR_E_ARG, "unknown warm start");
+  const swr::BlkItems b = h->blk_items();
+  const swr::BlkState S = h->blk_state();
+  // F0: Robin data of the initial state (every iterate's step 0 after the
+  // first; the plain guess holds it for the first iterate's whole window)
+  HIPCHECK(h, swr::launch_blk_transmit(b, S, blk_tx_one(-1, 0, -2, swr::kBlkF0),
+                                       h->ptr<double2>(h->bBlkTr), h->g.K_max,
+                                       h->ptr<int>(h->bFlags), st));
+  if (mode == SWR_WARM_PLAIN)
+    HIPCHECK(h, hipMemcpyAsync(S.F1, S.F0, h->sum_K * 16, hipMemcpyDeviceToDevice, st));
+  else
+    HIPCHECK(h, hipMemsetAsync(S.F1, 0, h->sum_K * 16, st));
+  h->blk_warm = mode;
+  h->blk_k = 0;
+  h->warm = true;
+  return SWR_OK;
+}
+
+int32_t blk_factor(swr_handle h, double t0, hipStream_t st) {
+  const Geometry& g = h->g;
+  HIPCHECK(h, hipStreamSynchronize(st));
+  h->E_host.assign(h->n_T + 1, 0.0);
+  for (int64_t n = 0; n <= h->n_T; ++n) h->E_host[n] = field(g.desc, t0 + n * g.desc.dt);
+  HIPCHECK(h, upload(h, h->bE, h->E_host, st));
+  const double tau = 0.5 * g.desc.dt;
+  const int nc = h->blk_chunks, cl = h->blk_chunk_len;
+  h->blk_Ea.assign(nc, 0.0);
+  double half = 0.0;
+  for (int c = 0; c < nc; ++c) {
+    const int64_t n0 = (int64_t)c * cl, n1 = std::min<int64_t>(n0 + cl, h->n_T);
+    double lo = h->E_host[n0 + 1], hi = lo;
+    for (int64_t n = n0; n < n1; ++n) {
+      lo = std::min(lo, h->E_host[n + 1]);
+      hi = std::max(hi, h->E_host[n + 1]);
+    }
+    h->blk_Ea[c] = 0.5 * (lo + hi);
+    half = std::max(half, 0.5 * (hi - lo));
+  }
+  int t_max = 1;
+  for (int s = 0; s < g.n_items; ++s) {
+    const int t = series_terms(tau * half * h->dipole[s], swr::kBlkTerms);
+    if (t == 0)
+      return fail(h, SWR_E_SIZE, "the field varies too much per anchor for the block path's "
+                                 "series (the workspace was sized for the creation's field)");
+    h->blk_terms[s] = t;
+    t_max = std::max(t_max, t);
+  }
+  HIPCHECK(h, upload(h, h->bBlkEa, h->blk_Ea, st));
+  HIPCHECK(h, upload(h, h->bBlkTerms, h->blk_terms, st));
+  HIPCHECK(h, tbegin(h, st, kTFactor));
+  const swr::BlkItems b = h->blk_items();
+  const int64_t cs = h->sum_K2;
+  double2* Z = h->ptr<double2>(h->bBlkRegion);
+  double2* Zq = Z + (size_t)nc * cs;
+  double2* Pk = Zq + (size_t)nc * cs;
+  const int64_t* toff = h->ptr<int64_t>(h->bBlkTileOff);
+  const int64_t nt = h->blk_toff.back();
+  const int64_t fcs = h->blk_foff.back();
+  double2* frag = h->ptr<double2>(h->bBlkFrag);
+  HIPCHECK(h, swr::launch_blk_anchor(b, h->ptr<double>(h->bBlkVp), h->ptr<double>(h->bBlkEa), nc,
+                                     cs, Z, g.K_max, st));
+  HIPCHECK(h, swr::launch_blk_invert(b, nc, cs, Z, h->ptr<double2>(h->bBlkCp),
+                                     h->ptr<double2>(h->bBlkRp), (int64_t)swr::kBlkGJ * h->sum_K,
+                                     toff, nt, g.K_max, h->ptr<int>(h->bFlags), st));
+  HIPCHECK(h, swr::launch_blk_pack(b, nc, cs, Z, 0, fcs, frag, g.K_max, st));
+  for (int k = 1; k < t_max; ++k) {
+    HIPCHECK(h, swr::launch_blk_qapply(b, nc, cs, k == 1 ? Z : Pk, Zq, g.K_max, st));
+    HIPCHECK(h, swr::launch_gemm_wide(b.it, toff, nt, nc, Z, Zq, nullptr, make_double2(1.0, 0.0),
+                                      nullptr, cs, Pk, st));
+    HIPCHECK(h, swr::launch_blk_pack(b, nc, cs, Pk, k, fcs, frag, g.K_max, st));
+  }
+  HIPCHECK(h, tend(h, st));
+  h->factor_terms = t_max - 1;
+  h->factored = true;
+  h->t0 = t0;
+  return SWR_OK;
+}
+
+// Iterates k0 .. k0 + P - 1 of the window, all in flight: launch l advances
+// iterate k0 + i from step l - i (lag one step: iterate k at step n needs
+// iterate k - 1's Robin data up to step n + 1).  Iterate k0 - 1, complete,
+// sends its data one step ahead as an extra transmission column.  With
+// tol >= 0 the launches stop once an iterate k >= 2 has Res(k) <= tol.
+int32_t blk_batch(swr_handle h, int k0, int P, double tol, hipStream_t st, swr_run_stats* out,
+                  bool* stop) {
+  const Geometry& g = h->g;
+  const int NS = h->blk_slots;
+  const int nT = (int)h->n_T;
+  auto slot = [NS](int k) { return k % NS; };
+  const swr::BlkItems b = h->blk_items();
+  const swr::BlkState S = h->blk_state();
+  double2* Tr = h->ptr<double2>(h->bBlkTr);
+  double2* Rb = h->ptr<double2>(h->bBlkRb);
+  const double2* frag = h->ptr<double2>(h->bBlkFrag);
+  const int64_t fcs = h->blk_foff.back();
+  double* resv = h->ptr<double>(h->bResv);
+  int* flags = h->ptr<int>(h->bFlags);
+  if (!h->res_pinned) HIPCHECK(h, hipHostMalloc((void**)&h->res_pinned, 64 * sizeof(double), 0));
+  if (!h->ev_ready) {
+    for (auto& e : h->ev) HIPCHECK(h, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    h->ev_ready = true;
+  }
+  // every iterate of the batch starts from the window's initial state
+  for (int i = 0; i < P; ++i) {
+    HIPCHECK(h, hipMemsetAsync(S.part + slot(k0 + i) * S.pstride, 0, S.pstride * 8, st));
+    HIPCHECK(h, swr::launch_blk_kron(b, 3, S.y0, 1, 0, S.hist + slot(k0 + i) * S.hstride,
+                                     h->n_T + 1, 1, st));
+  }
+  const bool pseudo = k0 > 1;
+  if (pseudo && nT >= 1) {
+    HIPCHECK(h, tbegin(h, st, kTTransmit));
+    HIPCHECK(h, swr::launch_blk_transmit(b, S, blk_tx_one(slot(k0 - 1), 1, -2, 2 * slot(k0) + 1),
+                                         Tr, g.K_max, flags, st));
+    HIPCHECK(h, tend(h, st));
+  }
+  std::vector<int> pending;  // completed iterates not yet checked
+  int k_done = k0 - 1, k_stop = 0;
+  auto check = [&](bool wait_all) -> int32_t {
+    while (!pending.empty()) {
+      const int k = pending.front();
+      hipEvent_t e = h->ev[k % kResEvents];
+      if (!wait_all && pending.size() < 3) {
+        const hipError_t q = hipEventQuery(e);
+        if (q == hipErrorNotReady) break;
+        if (q != hipSuccess) return fail(h, SWR_E_DEVICE, "hipEventQuery failed");
+      } else {
+        HIPCHECK(h, hipEventSynchronize(e));
+      }
+      pending.erase(pending.begin());
+      const double r = h->res_pinned[k % 64];
+      if (k <= 64) out->res[k - 1] = r;
+      out->iters = k;
+      h->blk_last_res = r;
+      if (tol >= 0.0 && k >= 2 && r <= tol) {
+        out->converged = 1;
+        k_stop = k;
+        return SWR_OK;
+      }
+    }
+    return SWR_OK;
+  };
+  const int n_launch = nT + P - 1;
+  for (int l = 0; l < n_launch && !k_stop; ++l) {
+    // columns grouped by series chunk (one solve launch per chunk present)
+    std::vector<swr::BlkCols> cols;
+    std::vector<int> cchunk;
+    swr::BlkTx tx{};
+    for (int i = 0; i < P; ++i) {
+      const int n = l - i;
+      if (n < 0 || n >= nT) continue;
+      const int k = k0 + i;
+      const int ch = n / h->blk_chunk_len;
+      size_t gsel = 0;
+      while (gsel < cchunk.size() && cchunk[gsel] != ch) ++gsel;
+      if (gsel == cchunk.size()) {
+        cchunk.push_back(ch);
+        cols.push_back(swr::BlkCols{});
+      }
+      swr::BlkCols& c = cols[gsel];
+      const int j = c.n++;
+      c.step[j] = n;
+      c.slot[j] = slot(k);
+      c.fa[j] = k == 1 ? swr::kBlkF1 : (n == 0 ? swr::kBlkF0 : 2 * slot(k) + (n & 1));
+      c.fb[j] = k == 1 ? swr::kBlkF1 : 2 * slot(k) + ((n + 1) & 1);
+      c.dE[j] = h->E_host[n + 1] - h->E_host[n];
+      const double d = h->E_host[n + 1] - h->blk_Ea[ch];
+      double pw = 1.0;
+      for (int q = 0; q < swr::kBlkTerms; ++q) {
+        c.w[q][j] = pw;
+        pw *= -d;
+      }
+      const int t = tx.n++;
+      tx.slot[t] = slot(k);
+      tx.step[t] = n + 1;
+      tx.prev[t] = k == 1 ? -1 : slot(k - 1);
+      tx.dst[t] = 2 * slot(k + 1) + ((n + 1) & 1);
+    }
+    if (pseudo && l + 2 <= nT) {
+      const int t = tx.n++;
+      tx.slot[t] = slot(k0 - 1);
+      tx.step[t] = l + 2;
+      tx.prev[t] = -2;
+      tx.dst[t] = 2 * slot(k0) + ((l + 2) & 1);
+    }
+    HIPCHECK(h, tbegin(h, st, kTRecur));
+    for (size_t q = 0; q < cols.size(); ++q)
+      HIPCHECK(h, swr::launch_blk_step(b, S, cols[q], frag + (size_t)cchunk[q] * fcs, Rb,
+                                       g.K_max, st));
+    HIPCHECK(h, tend(h, st));
+    HIPCHECK(h, tbegin(h, st, kTTransmit));
+    HIPCHECK(h, swr::launch_blk_transmit(b, S, tx, Tr, g.K_max, flags, st));
+    HIPCHECK(h, tend(h, st));
+    const int i_done = l - (nT - 1);
+    if (i_done >= 0 && i_done < P) {
+      const int k = k0 + i_done;
+      HIPCHECK(h, tbegin(h, st, kTResidual));
+      HIPCHECK(h, swr::launch_blk_res_reduce(S.part + slot(k) * S.pstride, g.n_items, nT,
+                                             g.desc.dt, resv + (k % 64), st));
+      HIPCHECK(h, tend(h, st));
+      HIPCHECK(h, hipMemcpyAsync(h->res_pinned + (k % 64), resv + (k % 64), 8,
+                                 hipMemcpyDeviceToHost, st));
+      HIPCHECK(h, hipEventRecord(h->ev[k % kResEvents], st));
+      pending.push_back(k);
+      k_done = k;
+      if (tol >= 0.0) {
+        const int32_t rc = check(false);
+        if (rc) return rc;
+      }
+    }
+  }
+  {
+    const int32_t rc = check(true);
+    if (rc) return rc;
+  }
+  const int k_last = k_stop ? k_stop : k_done;
+  h->blk_k = k_last;
+  h->blk_cur = slot(k_last);
+  *stop = k_stop != 0;
+  return SWR_OK;
+}
+
+int32_t blk_run(swr_handle h, const swr_run_opts* o, swr_run_stats* stats, hipStream_t st) {
+  int32_t rc = blk_factor(h, o->t0, st);
+  if (rc) return rc;
+  rc = blk_warm_start(h, o->warm, st);
+  if (rc) return rc;
+  swr_run_stats s{};
+  int P = o->depth > 0 ? std::min(o->depth, h->blk_depth) : h->blk_depth;
+  P = std::max(1, std::min(P, o->k_max));
+  bool stop = false;
+  for (int k0 = 1; k0 <= o->k_max && !stop;) {
+    const int Pb = std::min(P, o->k_max - k0 + 1);
+    rc = blk_batch(h, k0, Pb, o->tol, st, &s, &stop);
+    if (rc) return rc;
+    k0 += Pb;
+  }
+  rc = check_flags(h, st);
+  if (rc) return rc;
+  HIPCHECK(h, tcollect(h, &s));
+  if (stats) *stats = s;
+  return SWR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -611,6 +1173,42 @@ int32_t swr_create(const swr_desc* desc, swr_handle* out) {
     return code;
   }
   Geometry& g = h->g;
+  if (g.desc.factor_mode == SWR_FACTOR_BLOCK || (g.D == 4 && g.K_max > swr::kSmallK)) {
+    const std::string why = blk_unsupported(g);
+    if (!why.empty()) {
+      g_create_error = why;
+      delete h;
+      return SWR_E_SIZE;
+    }
+    if (g.desc.n_steps > 16384) {
+      g_create_error = "n_steps above 16384";
+      delete h;
+      return SWR_E_SIZE;
+    }
+    h->sum_K = g.off1[g.n_items];
+    h->sum_K2 = g.off2[g.n_items];
+    h->n_T = g.desc.n_steps;
+    h->n_mats = g.desc.n_steps;
+    h->offp.assign(g.n_items + 1, 0);
+    for (int s = 0; s < g.n_items; ++s) {
+      double x = 0.0;
+      for (int el = 0; el < g.desc.n_elec; ++el) {
+        const int k = el * g.desc.dim + g.desc.axis;
+        x += std::max(std::fabs(g.lo[(size_t)s * 4 + k]), std::fabs(g.hi[(size_t)s * 4 + k]));
+      }
+      h->dipole_max = std::max(h->dipole_max, x);
+      h->dipole.push_back(x);
+    }
+    std::string msg;
+    const int rc = blk_prepare(h, &msg);
+    if (rc) {
+      g_create_error = msg;
+      delete h;
+      return rc;
+    }
+    *out = h;
+    return SWR_OK;
+  }
   const bool wide_ok =
       g.desc.dim == 1 && g.desc.n_elec == 1 && g.desc.mode == SWR_TDSE && g.te_ok;
   if (g.K_max > (wide_ok ? swr::kWideK : swr::kSmallK)) {
@@ -812,6 +1410,7 @@ int32_t swr_query(swr_handle h, swr_info* info) {
   r.factor_terms = h->factor_terms;
   r.tx_tile = h->g.te_ok && !h->wide ? h->tx_tt : 0;
   r.wide = h->wide ? 1 : 0;
+  r.block = h->block ? 1 : 0;
   r.depth_run = h->depth_run;
   r.sum_KK_pairs = h->g.pair_toff.back();
   r.n_steps = (int32_t)h->n_T;
@@ -845,6 +1444,7 @@ int32_t swr_assemble(swr_handle h, void* stream) {
   if (!h) return SWR_E_ARG;
   if (!h->bound) return fail(h, SWR_E_STATE, "no workspace bound");
   hipStream_t st = (hipStream_t)stream;
+  if (h->block) return blk_assemble(h, st);
   const Geometry& g = h->g;
   const size_t NI = g.n_items;
   std::vector<int32_t> L4(4, 1);
@@ -1000,6 +1600,7 @@ int32_t swr_set_initial(swr_handle h, const void* c0_dev, void* stream) {
   if (!h) return SWR_E_ARG;
   if (!h->assembled) return fail(h, SWR_E_STATE, "swr_assemble first");
   hipStream_t st = (hipStream_t)stream;
+  if (h->block) return blk_set_initial(h, c0_dev, st);
   const swr::Items it = h->items();
   if (c0_dev) {
     HIPCHECK(h, hipMemcpyAsync(h->ptr<double2>(h->bC0), c0_dev, h->sum_K * 16,
@@ -1043,6 +1644,7 @@ int32_t swr_warm_start(swr_handle h, int32_t mode, const void* g_dev, void* stre
   if (mode != SWR_WARM_PLAIN && mode != SWR_WARM_ZERO && mode != SWR_WARM_GIVEN)
     return fail(h, SWR_E_ARG, "unknown warm start mode");
   hipStream_t st = (hipStream_t)stream;
+  if (h->block) return blk_warm_start(h, mode, st);
   const swr::Items it = h->items();
   const int nT = (int)h->n_T;
   // iterate 0 (residual reference) = the window's initial state held constant
@@ -1071,6 +1673,7 @@ int32_t swr_factor(swr_handle h, double t0, void* stream) {
   if (!h) return SWR_E_ARG;
   if (!h->assembled) return fail(h, SWR_E_STATE, "swr_assemble first");
   hipStream_t st = (hipStream_t)stream;
+  if (h->block) return blk_factor(h, t0, st);
   // the previous upload of the field table must have been consumed
   HIPCHECK(h, hipStreamSynchronize(st));
   h->E_host.assign(h->n_T + 1, 0.0);
@@ -1197,6 +1800,14 @@ int32_t swr_sweep(swr_handle h, void* stream) {
   if (!h->factored) return fail(h, SWR_E_STATE, "swr_factor first");
   if (!h->warm) return fail(h, SWR_E_STATE, "swr_warm_start (or swr_set_initial) first");
   hipStream_t st = (hipStream_t)stream;
+  if (h->block) {
+    // one iterate, its transmission and its residual (swr_transmit reports it)
+    swr_run_stats s{};
+    bool stop = false;
+    const int rc = blk_batch(h, h->blk_k + 1, 1, -1.0, st, &s, &stop);
+    if (rc) return rc;
+    return check_flags(h, st);
+  }
   const swr::Items it = h->items();
   const int k = h->k + 1;
   const int nT = (int)h->n_T;
@@ -1303,6 +1914,13 @@ int32_t transmit_and_residual(swr_handle h, int k, const double* scale, double* 
 
 int32_t swr_transmit(swr_handle h, double* residual_host, void* stream) {
   if (!h) return SWR_E_ARG;
+  if (h->block) {
+    // the block path sends each iterate's Robin data during its own sweep
+    if (h->blk_k < 1) return fail(h, SWR_E_STATE, "swr_sweep first");
+    HIPCHECK(h, hipStreamSynchronize((hipStream_t)stream));
+    if (residual_host) *residual_host = h->blk_last_res;
+    return SWR_OK;
+  }
   if (h->k < 1) return fail(h, SWR_E_STATE, "swr_sweep first");
   hipStream_t st = (hipStream_t)stream;
   const double* scale = h->g.desc.mode == SWR_TISE ? h->nus_of(h->k) : nullptr;
@@ -1575,6 +2193,10 @@ int32_t swr_run(swr_handle h, const swr_run_opts* o, swr_run_stats* stats, void*
     swr_handle h;
     ~TimingOff() { h->timing = false; }
   } timing_off{h};
+  if (h->block) {
+    if (!h->initial) return fail(h, SWR_E_STATE, "swr_set_initial first");
+    return blk_run(h, o, stats, (hipStream_t)stream);
+  }
   int rc = swr_factor(h, o->t0, stream);
   if (rc) return rc;
   rc = swr_warm_start(h, o->warm, o->g_dev, stream);
@@ -1638,11 +2260,23 @@ static int32_t copy_out(swr_handle h, const Buf& b, size_t bytes, void* dst, uin
 
 int32_t swr_get_history(swr_handle h, void* dst_dev, uint64_t bytes, void* stream) {
   if (!h) return SWR_E_ARG;
+  if (h->block) {
+    if (!dst_dev) return fail(h, SWR_E_ARG, "null argument");
+    if (h->blk_k < 1) return fail(h, SWR_E_STATE, "no iterate computed yet");
+    if (bytes < (uint64_t)(h->n_T + 1) * h->sum_K * 16) return fail(h, SWR_E_SIZE, "destination too small");
+    const swr::BlkState S = h->blk_state();
+    HIPCHECK(h, swr::launch_blk_kron(h->blk_items(), 1, S.hist + h->blk_cur * S.hstride, h->n_T + 1,
+                                     0, (double2*)dst_dev, h->n_T + 1, (int)h->n_T + 1,
+                                     (hipStream_t)stream));
+    return SWR_OK;
+  }
   return copy_out(h, h->bH[h->cur], h->bH[h->cur].bytes, dst_dev, bytes, stream);
 }
 
 int32_t swr_get_forcing(swr_handle h, void* dst_dev, uint64_t bytes, void* stream) {
   if (!h) return SWR_E_ARG;
+  if (h->block)
+    return fail(h, SWR_E_STATE, "the block path keeps only the two latest Robin data vectors");
   if (!h->warm) return fail(h, SWR_E_STATE, "no Robin data yet");
   const Buf& b = h->bF[(h->k + 1) % h->n_slots];
   return copy_out(h, b, b.bytes, dst_dev, bytes, stream);
@@ -1650,6 +2284,14 @@ int32_t swr_get_forcing(swr_handle h, void* dst_dev, uint64_t bytes, void* strea
 
 int32_t swr_get_initial(swr_handle h, void* dst_dev, uint64_t bytes, void* stream) {
   if (!h) return SWR_E_ARG;
+  if (h->block) {
+    if (!dst_dev) return fail(h, SWR_E_ARG, "null argument");
+    if (!h->initial) return fail(h, SWR_E_STATE, "swr_set_initial first");
+    if (bytes < (uint64_t)h->sum_K * 16) return fail(h, SWR_E_SIZE, "destination too small");
+    HIPCHECK(h, swr::launch_blk_kron(h->blk_items(), 1, h->ptr<double2>(h->bBlkY0), 1, 0,
+                                     (double2*)dst_dev, 1, 1, (hipStream_t)stream));
+    return SWR_OK;
+  }
   return copy_out(h, h->bC0, h->bC0.bytes, dst_dev, bytes, stream);
 }
 
@@ -1657,6 +2299,15 @@ int32_t swr_get_matrix(swr_handle h, int32_t which, void* dst_dev, uint64_t byte
   if (!h) return SWR_E_ARG;
   const Buf* bs[] = {&h->bA, &h->bKin, &h->bV, &h->bQ, &h->bB, &h->bW, &h->bG, &h->bQ2};
   if (which < 0 || which > 7) return fail(h, SWR_E_ARG, "matrix index out of range");
+  if (h->block) {
+    if (!dst_dev) return fail(h, SWR_E_ARG, "null argument");
+    if (which > 4) return fail(h, SWR_E_ARG, "the block path forms A, Kin, V, Q and B only");
+    if (!h->assembled) return fail(h, SWR_E_STATE, "swr_assemble first");
+    if (bytes < (uint64_t)h->sum_K2 * 8) return fail(h, SWR_E_SIZE, "destination too small");
+    HIPCHECK(h, swr::launch_blk_dense(h->blk_items(), which, h->ptr<double>(h->bBlkVp),
+                                      (double*)dst_dev, h->g.K_max, (hipStream_t)stream));
+    return SWR_OK;
+  }
   if (which == 7 && h->g.desc.field_shape != SWR_FIELD_CIRCULAR)
     return fail(h, SWR_E_ARG, "Q2 exists for a circular field only");
   return copy_out(h, *bs[which], bs[which]->bytes, dst_dev, bytes, stream);
@@ -1683,7 +2334,7 @@ int32_t swr_get_terms(swr_handle h, int32_t* dst, uint64_t n) {
   if (!h->factored) return fail(h, SWR_E_STATE, "swr_factor first");
   if (n < (uint64_t)h->g.n_items) return fail(h, SWR_E_SIZE, "destination too small");
   for (int s = 0; s < h->g.n_items; ++s)
-    dst[s] = h->wide ? h->terms_item[s] : h->factor_terms + 1;
+    dst[s] = h->block ? h->blk_terms[s] : (h->wide ? h->terms_item[s] : h->factor_terms + 1);
   return SWR_OK;
 }
 
@@ -1732,6 +2383,17 @@ static int32_t reconstruct(swr_handle h, int32_t geom, int32_t step, const void*
   if (antisym && h->g.desc.n_elec != 2)
     return fail(h, SWR_E_ARG, "antisymmetric reconstruction needs two electrons");
   if (!h->initial) return fail(h, SWR_E_STATE, "no coefficients yet");
+  if (h->block) {
+    if (h->blk_k < 1) return fail(h, SWR_E_STATE, "no iterate computed yet");
+    // the step's coefficients in the Gaussians' basis, then the common kernel
+    const swr::BlkState S = h->blk_state();
+    double2* cv = h->ptr<double2>(h->bBlkCvec);
+    HIPCHECK(h, swr::launch_blk_kron(h->blk_items(), 1, S.hist + h->blk_cur * S.hstride,
+                                     h->n_T + 1, step, cv, 1, 1, (hipStream_t)stream));
+    HIPCHECK(h, swr::launch_reconstruct(h->items(), geom, 0, 0, cv, (const double*)pts_dev, n_pts,
+                                        antisym, (double2*)out_dev, (hipStream_t)stream));
+    return SWR_OK;
+  }
   HIPCHECK(h, swr::launch_reconstruct(h->items(), geom, step, (int)h->n_T, h->hist(h->cur),
                                       (const double*)pts_dev, n_pts, antisym, (double2*)out_dev,
                                       (hipStream_t)stream));
@@ -1751,6 +2413,7 @@ int32_t swr_reconstruct_antisym(swr_handle h, int32_t geom, int32_t step, const 
 int32_t swr_local_eigen(swr_handle h, void* lambda_dev, void* vectors_dev, void* stream) {
   if (!h || !lambda_dev || !vectors_dev) return fail(h, SWR_E_ARG, "null argument");
   if (!h->assembled) return fail(h, SWR_E_STATE, "swr_assemble first");
+  if (h->block) return fail(h, SWR_E_STATE, "the block path is for real time");
   if (h->g.desc.mu_im != 0.0) return fail(h, SWR_E_ARG, "local eigenproblems need a real mu");
   if (h->g.K_max > swr::kSmallK) return fail(h, SWR_E_SIZE, "local eigenproblems need K <= 64");
   hipStream_t st = (hipStream_t)stream;
@@ -1762,6 +2425,7 @@ int32_t swr_local_eigen(swr_handle h, void* lambda_dev, void* vectors_dev, void*
 
 int32_t swr_get_norms(swr_handle h, void* dst_dev, uint64_t bytes, void* stream) {
   if (!h) return SWR_E_ARG;
+  if (h->block) return fail(h, SWR_E_STATE, "the block path is for real time");
   const Buf& b = h->bNus[h->k % h->n_slots];
   return copy_out(h, b, b.bytes, dst_dev, bytes, stream);
 }
@@ -1777,6 +2441,14 @@ int32_t swr_set_field(swr_handle h, double E0, double omega, double phase) {
 
 int32_t swr_advance_window(swr_handle h, void* stream) {
   if (!h) return SWR_E_ARG;
+  if (h->block) {
+    if (!h->initial || h->blk_k < 1) return fail(h, SWR_E_STATE, "no iterate to advance from");
+    const swr::BlkState S = h->blk_state();
+    HIPCHECK(h, swr::launch_blk_kron(h->blk_items(), 3, S.hist + h->blk_cur * S.hstride,
+                                     h->n_T + 1, (int)h->n_T, h->ptr<double2>(h->bBlkY0), 1, 1,
+                                     (hipStream_t)stream));
+    return blk_warm_start(h, SWR_WARM_PLAIN, (hipStream_t)stream);
+  }
   if (!h->initial || h->k < 1) return fail(h, SWR_E_STATE, "no iterate to advance from");
   HIPCHECK(h, swr::launch_last_step(h->items(), (int)h->n_T, h->hist(h->cur),
                                     h->ptr<double2>(h->bC0), (hipStream_t)stream));
@@ -1795,6 +2467,7 @@ int32_t swr_face_data(swr_handle h, int32_t n_sel, const int32_t* steps_host, vo
                       void* stream) {
   if (!h || !steps_host || !g_dev) return fail(h, SWR_E_ARG, "null argument");
   if (n_sel < 1 || n_sel > 64) return fail(h, SWR_E_ARG, "n_sel must be in 1..64");
+  if (h->block) return fail(h, SWR_E_STATE, "the learned warm start is not on the block path");
   if (!h->initial) return fail(h, SWR_E_STATE, "no coefficients yet");
   swr::StepList sl{};
   sl.n = n_sel;
@@ -1818,6 +2491,7 @@ static int max_item_nodes(swr_handle h) {
 int32_t swr_learned_features(swr_handle h, const void* g0_dev, double t0, int32_t n_in,
                              float* x_dev, double* scale_dev, void* stream) {
   if (!h || !g0_dev || !x_dev || !scale_dev) return fail(h, SWR_E_ARG, "null argument");
+  if (h->block) return fail(h, SWR_E_STATE, "the learned warm start is not on the block path");
   if (!h->assembled) return fail(h, SWR_E_STATE, "swr_assemble first");
   if (!distinct_time_nodes((int)h->n_T, h->n_nodes_t)) return fail(h, SWR_E_ARG, kShortWindow);
   const int M = h->n_nodes_t;
@@ -1840,6 +2514,7 @@ int32_t swr_learned_features(swr_handle h, const void* g0_dev, double t0, int32_
 int32_t swr_learned_targets(swr_handle h, const void* g_nodes_dev, const double* scale_dev,
                             int32_t n_out, float* y_dev, void* stream) {
   if (!h || !g_nodes_dev || !scale_dev || !y_dev) return fail(h, SWR_E_ARG, "null argument");
+  if (h->block) return fail(h, SWR_E_STATE, "the learned warm start is not on the block path");
   if (!h->assembled) return fail(h, SWR_E_STATE, "swr_assemble first");
   if (!distinct_time_nodes((int)h->n_T, h->n_nodes_t)) return fail(h, SWR_E_ARG, kShortWindow);
   if (n_out < 2 * h->n_nodes_t * max_item_nodes(h)) return fail(h, SWR_E_SIZE, "n_out too small");
@@ -1851,6 +2526,7 @@ int32_t swr_learned_targets(swr_handle h, const void* g_nodes_dev, const double*
 int32_t swr_learned_apply(swr_handle h, const float* y_dev, const double* scale_dev,
                           const void* g0_dev, int32_t n_out, void* g_all_dev, void* stream) {
   if (!h || !y_dev || !scale_dev || !g0_dev || !g_all_dev) return fail(h, SWR_E_ARG, "null argument");
+  if (h->block) return fail(h, SWR_E_STATE, "the learned warm start is not on the block path");
   if (!h->assembled) return fail(h, SWR_E_STATE, "swr_assemble first");
   if (!distinct_time_nodes((int)h->n_T, h->n_nodes_t)) return fail(h, SWR_E_ARG, kShortWindow);
   if (n_out < 2 * h->n_nodes_t * max_item_nodes(h)) return fail(h, SWR_E_SIZE, "n_out too small");
@@ -1873,6 +2549,32 @@ int32_t swr_autotune(swr_handle h, int32_t k_iters, double t0, swr_tuning* out, 
   if (!h || !out) return fail(h, SWR_E_ARG, "null argument");
   if (k_iters < 1) return fail(h, SWR_E_ARG, "k_iters must be >= 1");
   if (!h->assembled || !h->initial) return fail(h, SWR_E_STATE, "swr_assemble and swr_set_initial first");
+  if (h->block) {
+    // nothing to reorder on the block path: time one window at its depth
+    swr_run_opts o{};
+    o.k_max = k_iters;
+    o.tol = -1.0;
+    o.t0 = t0;
+    o.warm = SWR_WARM_PLAIN;
+    hipEvent_t e0, e1;
+    HIPCHECK(h, hipEventCreate(&e0));
+    HIPCHECK(h, hipEventCreate(&e1));
+    HIPCHECK(h, hipEventRecord(e0, (hipStream_t)stream));
+    swr_run_stats rs{};
+    const int rc = swr_run(h, &o, &rs, stream);
+    HIPCHECK(h, hipEventRecord(e1, (hipStream_t)stream));
+    HIPCHECK(h, hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIPCHECK(h, hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    out->depth = h->blk_depth;
+    out->tx_tile = 0;
+    out->ms_per_window = ms;
+    out->candidates = 1;
+    return SWR_OK;
+  }
   hipStream_t st = (hipStream_t)stream;
   std::vector<int> depths, tiles;
   for (int d = 1; d <= h->depth; ++d) depths.push_back(d);

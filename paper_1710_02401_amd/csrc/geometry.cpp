@@ -69,6 +69,12 @@ void composite(const std::vector<double>& edges, const std::vector<int>& counts,
 
 }  // namespace
 
+void face_rule_1d(const Geometry& g, int s, int t, std::vector<double>* x, std::vector<double>* w) {
+  const double lo = g.lo[(size_t)s * kMaxD + t], hi = g.hi[(size_t)s * kMaxD + t];
+  std::vector<double> edges = {lo, lo + g.eps[t], hi - g.eps[t], hi};
+  composite(edges, {g.desc.face_nodes_band, g.desc.face_nodes_mid, g.desc.face_nodes_band}, x, w);
+}
+
 std::string build_geometry(const swr_desc& d, Geometry* g, int* code) {
   *code = SWR_E_ARG;
   if (d.n_elec < 1 || d.dim < 1) return "n_elec and dim must be >= 1";
@@ -86,8 +92,8 @@ std::string build_geometry(const swr_desc& d, Geometry* g, int* code) {
   if (d.face_nodes_band < 1 || d.face_nodes_mid < 1 || d.quad_nodes < 1) return "node counts must be >= 1";
   if (d.learned_nodes != 0 && (d.learned_nodes < 2 || d.learned_nodes > 64))
     return "learned_nodes must be 0 (default 8) or in 2..64";
-  if (d.factor_mode < 0 || d.factor_mode > 2)
-    return "factor_mode must be 0 (auto), 1 (direct) or 2 (wide)";
+  if (d.factor_mode < 0 || d.factor_mode > 3)
+    return "factor_mode must be 0 (auto), 1 (direct), 2 (wide) or 3 (block)";
   if (d.unnormalized != 0 && d.unnormalized != 1) return "unnormalized must be 0 or 1";
   if (d.unnormalized && d.mode != SWR_TISE) return "unnormalized applies to imaginary time only";
   if (d.field_shape != SWR_FIELD_SINE && d.field_shape != SWR_FIELD_CIRCULAR)

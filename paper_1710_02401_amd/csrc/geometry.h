@@ -86,6 +86,11 @@ struct Geometry {
 // the SWR_E_* status.
 std::string build_geometry(const swr_desc& d, Geometry* g, int* code);
 
+// Tangential face rule of item s in dimension t (composite Gauss-Legendre
+// over [lo, lo + eps], [lo + eps, hi - eps], [hi - eps, hi]), the same
+// nodes and weights as the face nodes of the geometry.
+void face_rule_1d(const Geometry& g, int s, int t, std::vector<double>* x, std::vector<double>* w);
+
 // n-point Gauss-Legendre rule on [-1, 1], ascending nodes (Newton on the
 // three-term recurrence of the Legendre polynomials).
 void gauss_legendre(int n, std::vector<double>* t, std::vector<double>* w);

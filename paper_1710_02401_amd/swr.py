@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libswr.so")
  SWR_E_COND) = (0, -1, -2, -3, -4, -5, -6, -7, -8)
 SWR_TDSE, SWR_TISE = 0, 1
 SWR_WARM_PLAIN, SWR_WARM_ZERO, SWR_WARM_GIVEN = 0, 1, 2
-SWR_FACTOR_AUTO, SWR_FACTOR_DIRECT, SWR_FACTOR_WIDE = 0, 1, 2
+SWR_FACTOR_AUTO, SWR_FACTOR_DIRECT, SWR_FACTOR_WIDE, SWR_FACTOR_BLOCK = 0, 1, 2, 3
 SWR_FIELD_SINE, SWR_FIELD_CIRCULAR = 0, 1
 MATRICES = {"A": 0, "Kin": 1, "V": 2, "Q": 3, "B": 4, "W": 5, "G": 6, "Q2": 7}
 
@@ -58,6 +58,7 @@ class swr_info(ctypes.Structure):
         ("depth", ctypes.c_int32), ("workspace_bytes", ctypes.c_uint64),
         ("learned_nodes", ctypes.c_int32), ("factor_terms", ctypes.c_int32),
         ("tx_tile", ctypes.c_int32), ("depth_run", ctypes.c_int32), ("wide", ctypes.c_int32),
+        ("block", ctypes.c_int32),
     ]
 
 
@@ -226,7 +227,7 @@ def desc_from_config(cfg):
     d.quad_nodes = int(cfg["quad_nodes"])
     d.learned_nodes = int(cfg.get("learned_nodes", 0))
     d.factor_mode = {"auto": SWR_FACTOR_AUTO, "direct": SWR_FACTOR_DIRECT,
-                     "wide": SWR_FACTOR_WIDE}[cfg.get("factor", "auto")]
+                     "wide": SWR_FACTOR_WIDE, "block": SWR_FACTOR_BLOCK}[cfg.get("factor", "auto")]
     d.unnormalized = 1 if cfg.get("unnormalized", False) else 0
     return d, (arr, pos, chg)
 
