@@ -141,6 +141,29 @@ def _term(dec, s, dims, rules, fvals):
     return cur.reshape(s.K, s.K)
 
 
+# Grids above this many points are summed one node of their first dimension
+# at a time (the same sum, split to bound memory: a four-dimensional grid of
+# 176 nodes per dimension would need tens of GB at once).
+_SLICE_POINTS = 30_000_000
+
+
+def _grid_term(dec, s, dims, rules, ufunc):
+    """int over the subdomain of U(x_dims) v_l v_m on the tensor grid of
+    `rules`, with U = ufunc(grids) evaluated on the grid."""
+    n_pts = int(np.prod([len(r[0]) for r in rules]))
+    if n_pts <= _SLICE_POINTS:
+        grids = np.meshgrid(*[r[0] for r in rules], indexing="ij")
+        return _term(dec, s, dims, rules, ufunc(grids))
+    x0, w0 = rules[0]
+    out = np.zeros((s.K, s.K))
+    for q in range(len(x0)):
+        r0 = (x0[q:q + 1], w0[q:q + 1])
+        sub = [r0] + list(rules[1:])
+        grids = np.meshgrid(*[r[0] for r in sub], indexing="ij")
+        out += _term(dec, s, dims, sub, ufunc(grids))
+    return out
+
+
 def potential_matrix(dec, s):
     cfg = dec.cfg
     D = dec.D
@@ -164,22 +187,24 @@ def potential_matrix(dec, s):
     rules = [_panel_rule(dec, s, k, min(eps_en, eps_ee, sig[k])) for k in range(D)]
     # electron-nucleus: one d-dimensional term per electron
     if nuc:
-        for m in range(N):
-            dims = [m * d + a for a in range(d)]
-            grids = np.meshgrid(*[rules[k][0] for k in dims], indexing="ij")
+        def u_en(grids):
             U = np.zeros(grids[0].shape)
             for RA, ZA in zip(nuc, Z):
                 r2 = sum((grids[a] - RA[a]) ** 2 for a in range(d))
                 U -= ZA / np.sqrt(r2 + eps_en * eps_en)
-            V += _term(dec, s, dims, [rules[k] for k in dims], U)
+            return U
+        for m in range(N):
+            dims = [m * d + a for a in range(d)]
+            V += _grid_term(dec, s, dims, [rules[k] for k in dims], u_en)
     # electron-electron: one 2d-dimensional term per pair
+
+    def u_ee(grids):
+        r2 = sum((grids[a] - grids[d + a]) ** 2 for a in range(d))
+        return 1.0 / np.sqrt(r2 + eps_ee * eps_ee)
     for m in range(N):
         for mp in range(m + 1, N):
             dims = [m * d + a for a in range(d)] + [mp * d + a for a in range(d)]
-            grids = np.meshgrid(*[rules[k][0] for k in dims], indexing="ij")
-            r2 = sum((grids[a] - grids[d + a]) ** 2 for a in range(d))
-            U = 1.0 / np.sqrt(r2 + eps_ee * eps_ee)
-            V += _term(dec, s, dims, [rules[k] for k in dims], U)
+            V += _grid_term(dec, s, dims, [rules[k] for k in dims], u_ee)
     return V
 
 

@@ -144,3 +144,96 @@ def test_block_reconstruction():
     import torch
     got = _np(s.reconstruct(torch.from_numpy(pts), step=3))
     assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
+def _golden(name):
+    import json
+    import os
+    return json.load(open(os.path.join(os.path.dirname(__file__), "golden", name)))
+
+
+def _cvec(v):
+    a = np.asarray(v, dtype=np.float64)
+    return a[:, 0] + 1j * a[:, 1]
+
+
+def test_block_four_dimensional_decomposition_matches_stored_oracle():
+    """The four-dimensional workload's 4^4 decomposition (interior subdomains
+    with all 80 neighbours, 16 items per potential batch) with 2^4 Gaussians:
+    residuals of 5 iterations and the final state of sampled subdomains
+    against the stored oracle run (tests/golden/make_c5_fixtures.py)."""
+    ref = _golden("c5_k16_window.json")
+    cfg = _cfg("c5-k16")
+    s = _solver(cfg)
+    st = s.run(k_max=ref["iterations"], tol=-1.0)
+    for a, b in zip(st["res"], ref["residuals"]):
+        assert a == pytest.approx(b, rel=1e-7)
+    h_g = [_np(h) for h in s.split_history(s.history())]
+    from oracle.geometry import Decomposition
+    from oracle import assemble, gauss1d
+    dec = Decomposition(cfg)
+    num = den = 0.0
+    for key, v in ref["samples"].items():
+        i = int(key)
+        sub = dec.subs[i]
+        A = assemble.kron_all([gauss1d.overlap(sub.alpha[k], sub.delta[k], sub.lo[k], sub.hi[k])
+                               for k in range(4)])
+        c_o = _cvec(v)
+        d = h_g[i][-1] - c_o
+        num += float(np.real(np.conj(d) @ A @ d))
+        den += float(np.real(np.conj(c_o) @ A @ c_o))
+    assert np.sqrt(num / den) <= 1e-10
+
+
+def test_full_size_four_dimensional_iterate1_sampled():
+    """The full four-dimensional workload (256 subdomains of 6^4 = 1296
+    Gaussians, 500 steps, every iterate in flight as in the benchmark):
+    iterate 1 of sampled subdomains at stored steps, their potential
+    matrices at sampled entries and their initial coefficients, against the
+    stored oracle values (tests/golden/make_c5_fixtures.py full)."""
+    ref = _golden("c5_iterate1.json")
+    cfg = workloads.get_config("c5-2e-2d")
+    s = _solver(cfg)
+    assert s.info.block == 1 and int(s.K.max()) == 1296
+    # the benchmark's launch configuration (30 iterates in flight): each
+    # iterate's arithmetic does not depend on the others in flight, so its
+    # Res(1) equals that of iterate 1 run alone, whose history is checked
+    st30 = s.run(k_max=30, tol=-1.0)
+    st = s.run(k_max=1, tol=-1.0)
+    assert st["iters"] == 1
+    assert st["res"][0] == st30["res"][0]
+    hist = s.history()
+    c0 = s.initial()
+    V = s.matrix("V")
+    from oracle.geometry import Decomposition
+    from oracle import assemble, gauss1d
+    dec = Decomposition(cfg)
+    nT1 = cfg["n_steps"] + 1
+    # relative L2 in function space over the sampled subdomains together
+    # (the corner subdomain's state is about 1e-12 of the interior's, so its
+    # own relative error is rounding noise; it enters through the sum)
+    num = {n: 0.0 for n in ref["steps"]}
+    den = {n: 0.0 for n in ref["steps"]}
+    for key, tgt in ref["targets"].items():
+        i = int(key)
+        sub = dec.subs[i]
+        A = assemble.kron_all([gauss1d.overlap(sub.alpha[k], sub.delta[k], sub.lo[k], sub.hi[k])
+                               for k in range(4)])
+        K = sub.K
+        h_i = _np(hist[nT1 * s.off1[i]: nT1 * s.off1[i + 1]]).reshape(nT1, K)
+        for n, v in tgt["c"].items():
+            c_o = _cvec(v)
+            d = h_i[int(n)] - c_o
+            num[int(n)] += float(np.real(np.conj(d) @ A @ d))
+            den[int(n)] += float(np.real(np.conj(c_o) @ A @ c_o))
+        c0_o = _cvec(tgt["c0"])
+        d = _np(c0[s.off1[i]: s.off1[i + 1]]) - c0_o
+        assert np.sqrt(np.real(np.conj(d) @ A @ d)) <= 1e-12 * max(1.0, np.sqrt(np.real(np.conj(c0_o) @ A @ c0_o)))
+        Vi = _np(V[i])
+        vmax = max(abs(e[2]) for e in tgt["V"])
+        for l, m, val in tgt["V"]:
+            assert abs(Vi[l, m] - val) <= 1e-12 * vmax
+    for n in ref["steps"]:
+        err = np.sqrt(num[n] / den[n])
+        print(f"[gpu] c5 sampled subdomains, step {n}: relative A-norm {err:.2e}", flush=True)
+        assert err <= 1e-10, (n, err)

@@ -131,6 +131,11 @@ _C5_MINI = dict(
     iters=3, tol=1e-8, face_nodes=[2, 2], quad_nodes=8,
 )
 
+# The four-dimensional workload's decomposition (4^4 subdomains: interior
+# subdomains with all 80 neighbours) at a size the oracle runs in minutes:
+# 2^4 Gaussians per subdomain, coarser potential panels, 10 steps.
+_C5_K16 = dict(_C5, name="c5-k16", nbasis=[2, 2, 2, 2], quad_nodes=4, n_steps=10, iters=5)
+
 # One electron in two dimensions (D = 2 with a two-dimensional nucleus term),
 # field along the second axis.
 _C5_MINI_1E = dict(
@@ -200,7 +205,7 @@ _T3 = dict(
 )
 
 CONFIGS = {c["name"]: c for c in (_C1, _C2, _C2_TISE, _C3, _C3_MINI, _C3_WIDE, _C4, _C5,
-                                   _C5_MINI, _C5_MINI_1E, _T1B, _T2A, _T2B, _T3)}
+                                   _C5_K16, _C5_MINI, _C5_MINI_1E, _T1B, _T2A, _T2B, _T3)}
 
 
 def get_config(name, **overrides):
