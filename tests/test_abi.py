@@ -62,10 +62,14 @@ def test_factor_mode_validated_and_reported(S):
     lib = S.load_library()
     cfg = workloads.tiny_configs()[0]
     d, keep = S.desc_from_config(cfg)
-    d.factor_mode = 3
+    d.factor_mode = 4
     h = ctypes.c_void_p()
     assert lib.swr_create(ctypes.byref(d), ctypes.byref(h)) == -1
     assert b"factor_mode" in lib.swr_last_error(None)
+    # the block path takes two or four configuration dimensions
+    d.factor_mode = 3
+    assert lib.swr_create(ctypes.byref(d), ctypes.byref(h)) == S.SWR_E_SIZE
+    assert b"block path" in lib.swr_last_error(None)
     rc, h = _create(S, dict(cfg, factor="direct"))
     assert rc == 0
     info = S.swr_info()
