@@ -408,6 +408,18 @@ int32_t swr_mlp_workspace_bytes(const swr_mlp_desc* d, int32_t batch, uint64_t* 
 /* y = network(x) for a batch (device float [batch][n_in] -> [batch][n_out]). */
 int32_t swr_mlp_forward(const swr_mlp_desc* d, const float* params, const float* x, int32_t batch,
                         float* y, void* ws_dev, uint64_t ws_bytes, void* stream);
+/* The same forward pass for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): no workspace argument and no allocation; the activations
+ * live in a 64 MiB array of the library, one per GPU, kept until the
+ * process ends.  SWR_E_SIZE when the batch's activations need more than
+ * that (2 x batch x (n_layers x n_hidden + n_out) floats, each layer's
+ * buffers aligned to 256 bytes, plus 4 KiB); the output equals
+ * swr_mlp_forward's.  Calls on one GPU share the array: calls that overlap
+ * in time on one GPU (several host threads or streams) race and must be
+ * serialised by the caller. */
+int32_t swr_mlp_forward_noalloc(const swr_mlp_desc* d, const float* params, const float* x,
+                                int32_t batch, float* y, void* stream);
 /* Mean-squared-error loss against t (written to loss_dev[0]) and its
  * gradient with respect to every parameter (device float [n_params]). */
 int32_t swr_mlp_loss_grad(const swr_mlp_desc* d, const float* params, const float* x,

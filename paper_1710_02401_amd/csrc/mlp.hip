@@ -6,6 +6,8 @@
 // one flat FP32 vector, layer by layer: weight (out x in, row-major), bias.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include <cmath>
 #include <cstdint>
 #include <vector>
@@ -219,6 +221,31 @@ void forward(const Net& net, const float* params, const float* x, int batch, con
   }
 }
 
+// Scratch of the allocation-free forward pass (swr_mlp_forward_noalloc):
+// the per-layer activations of one batch.  Each GPU the library runs on
+// holds its own copy until the process ends.  In host code `scratch` names a
+// host-side stand-in, never its device address: the address is looked up
+// once per device (hipGetSymbolAddress, with that device current) and kept.
+constexpr uint64_t kNoAllocScratchBytes = 64ull << 20;  // 64 MiB
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of the current device's scratch (null on a HIP error).
+void* scratch_address() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    g_scratch_dev[dev] = ptr;
+  }
+  return g_scratch_dev[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -244,6 +271,23 @@ int32_t swr_mlp_forward(const swr_mlp_desc* d, const float* params, const float*
   if (!params || !x || !y || !ws_dev || batch < 1 || make_net(d, &net) != SWR_OK) return SWR_E_ARG;
   Ws ws;
   if (plan_ws(net, batch, (char*)ws_dev, &ws) > ws_bytes) return SWR_E_SIZE;
+  hipStream_t st = (hipStream_t)stream;
+  forward(net, params, x, batch, ws, st);
+  if (hipMemcpyAsync(y, ws.h.back(), (size_t)batch * d->n_out * sizeof(float),
+                     hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return SWR_E_DEVICE;
+  return hipGetLastError() == hipSuccess ? SWR_OK : SWR_E_DEVICE;
+}
+
+int32_t swr_mlp_forward_noalloc(const swr_mlp_desc* d, const float* params, const float* x,
+                                int32_t batch, float* y, void* stream) {
+  Net net;
+  if (!params || !x || !y || batch < 1 || make_net(d, &net) != SWR_OK) return SWR_E_ARG;
+  Ws ws;
+  if (plan_ws(net, batch, nullptr, &ws) > kNoAllocScratchBytes) return SWR_E_SIZE;
+  void* base = scratch_address();
+  if (!base) return SWR_E_DEVICE;
+  plan_ws(net, batch, (char*)base, &ws);
   hipStream_t st = (hipStream_t)stream;
   forward(net, params, x, batch, ws, st);
   if (hipMemcpyAsync(y, ws.h.back(), (size_t)batch * d->n_out * sizeof(float),

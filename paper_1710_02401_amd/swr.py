@@ -92,6 +92,7 @@ EXPORTS = [
     "swr_get_norms", "swr_status_sync", "swr_set_field", "swr_advance_window",
     "swr_time_nodes", "swr_face_data", "swr_learned_features", "swr_learned_targets",
     "swr_learned_apply", "swr_mlp_param_count", "swr_mlp_workspace_bytes", "swr_mlp_forward",
+    "swr_mlp_forward_noalloc",
     "swr_mlp_loss_grad", "swr_mlp_adam", "swr_autotune",
 ]
 
@@ -151,6 +152,7 @@ def load_library(path=LIB_PATH):
         "swr_mlp_param_count": (i32, [ctypes.POINTER(swr_mlp_desc), ctypes.POINTER(i64)]),
         "swr_mlp_workspace_bytes": (i32, [ctypes.POINTER(swr_mlp_desc), i32, ctypes.POINTER(u64)]),
         "swr_mlp_forward": (i32, [ctypes.POINTER(swr_mlp_desc), vp, vp, i32, vp, vp, u64, vp]),
+        "swr_mlp_forward_noalloc": (i32, [ctypes.POINTER(swr_mlp_desc), vp, vp, i32, vp, vp]),
         "swr_mlp_loss_grad": (i32, [ctypes.POINTER(swr_mlp_desc), vp, vp, vp, i32, vp, vp, vp, u64,
                                     vp]),
         "swr_mlp_adam": (i32, [i64, vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float,
