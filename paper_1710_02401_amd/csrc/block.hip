@@ -805,45 +805,71 @@ __global__ void __launch_bounds__(kBT) k_blk_solve(BlkItems b, BlkState S, BlkCo
     w1[k] = cols.w[k][16 + lc];
   }
   const double2* rb = Rb + it.off1[s] * kBlkCols;
-  for (int k0 = 0; k0 < K; k0 += kSlice) {
-    __syncthreads();
+  // iterations (slice, term) in order; the next iteration's A fragments and
+  // the next slice of right-hand sides are loaded while the matrix cores
+  // work on the current one
+  const int n_slices = (K + kSlice - 1) / kSlice;
+  const int n_it = n_slices * t_s;
+  double2 pb[kSlice * kBlkCols / kBT];
+  auto load_b = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < kSlice * kBlkCols / kBT; ++q) {
       const int e = threadIdx.x + q * kBT;
       const int r = e / kBlkCols, c = e % kBlkCols;
-      Bs[r][c] = (k0 + r < K) ? rb[(int64_t)(k0 + r) * kBlkCols + c] : make_double2(0.0, 0.0);
+      pb[q] = (k0 + r < K) ? rb[(int64_t)(k0 + r) * kBlkCols + c] : make_double2(0.0, 0.0);
     }
-    __syncthreads();
-    if (!active) continue;
-    const int kt0 = k0 / 4;
+  };
+  auto load_a = [&](int itn, double2 (&a)[kSlice / 4]) {
+    const int sl = itn / t_s, k = itn - sl * t_s;
+    const int kt0 = sl * (kSlice / 4);
     const int ktn = min(kSlice / 4, KT - kt0);
-#pragma unroll 1
-    for (int k = 0; k < t_s; ++k) {
-      const double2* ap = fr + (int64_t)k * fs + (int64_t)kt0 * 64;
-      double2 a[kSlice / 4];
+    const double2* ap = fr + (int64_t)k * fs + (int64_t)kt0 * 64;
 #pragma unroll
-      for (int q = 0; q < kSlice / 4; ++q) a[q] = q < ktn ? ap[q * 64] : make_double2(0.0, 0.0);
-      double sw0 = 0.0, sw1 = 0.0;
+    for (int q = 0; q < kSlice / 4; ++q)
+      a[q] = (active && q < ktn) ? ap[q * 64] : make_double2(0.0, 0.0);
+  };
+  auto body = [&](int itc, double2 (&ac)[kSlice / 4], double2 (&an)[kSlice / 4]) {
+    const int sl = itc / t_s, k = itc - sl * t_s;
+    if (k == 0) {
+      __syncthreads();
 #pragma unroll
-      for (int kk = 0; kk < kBlkTerms; ++kk)
-        if (kk == k) {
-          sw0 = w0[kk];
-          sw1 = w1[kk];
-        }
-#pragma unroll
-      for (int q = 0; q < kSlice / 4; ++q) {
-        const double2 b0 = Bs[4 * q + lr][lc], b1 = Bs[4 * q + lr][16 + lc];
-        const double b0x = b0.x * sw0, b0y = b0.y * sw0, b1x = b1.x * sw1, b1y = b1.y * sw1;
-        cr0 = mfma16(a[q].x, b0x, cr0);
-        cr0 = mfma16(-a[q].y, b0y, cr0);
-        ci0 = mfma16(a[q].x, b0y, ci0);
-        ci0 = mfma16(a[q].y, b0x, ci0);
-        cr1 = mfma16(a[q].x, b1x, cr1);
-        cr1 = mfma16(-a[q].y, b1y, cr1);
-        ci1 = mfma16(a[q].x, b1y, ci1);
-        ci1 = mfma16(a[q].y, b1x, ci1);
+      for (int q = 0; q < kSlice * kBlkCols / kBT; ++q) {
+        const int e = threadIdx.x + q * kBT;
+        Bs[e / kBlkCols][e % kBlkCols] = pb[q];
       }
+      __syncthreads();
+      if (sl + 1 < n_slices) load_b((sl + 1) * kSlice);
     }
+    if (itc + 1 < n_it) load_a(itc + 1, an);
+    if (!active) return;
+    double sw0 = 0.0, sw1 = 0.0;
+#pragma unroll
+    for (int kk = 0; kk < kBlkTerms; ++kk)
+      if (kk == k) {
+        sw0 = w0[kk];
+        sw1 = w1[kk];
+      }
+#pragma unroll
+    for (int q = 0; q < kSlice / 4; ++q) {
+      const double2 b0 = Bs[4 * q + lr][lc], b1 = Bs[4 * q + lr][16 + lc];
+      const double b0x = b0.x * sw0, b0y = b0.y * sw0, b1x = b1.x * sw1, b1y = b1.y * sw1;
+      cr0 = mfma16(ac[q].x, b0x, cr0);
+      cr0 = mfma16(-ac[q].y, b0y, cr0);
+      ci0 = mfma16(ac[q].x, b0y, ci0);
+      ci0 = mfma16(ac[q].y, b0x, ci0);
+      cr1 = mfma16(ac[q].x, b1x, cr1);
+      cr1 = mfma16(-ac[q].y, b1y, cr1);
+      ci1 = mfma16(ac[q].x, b1y, ci1);
+      ci1 = mfma16(ac[q].y, b1x, ci1);
+    }
+  };
+  double2 a0[kSlice / 4], a1[kSlice / 4];
+  load_b(0);
+  load_a(0, a0);
+#pragma unroll 1
+  for (int itc = 0; itc < n_it; itc += 2) {
+    body(itc, a0, a1);
+    if (itc + 1 < n_it) body(itc + 1, a1, a0);
   }
   if (!active) return;
   const int64_t hoff = (int64_t)(S.n_steps + 1) * it.off1[s];
@@ -893,81 +919,82 @@ __device__ inline Tang tang_of(const BlkDim* bd, int D, int k) {
   return t;
 }
 
-// out[i0][i1][i2] (dimension c replaced by rows of M, M[row][a] with row
-// stride kBlkN, rows `nout`) = sum_a M[o_c][a] in[..a..]; transpose: M is
-// read as M[a][o_c] (row stride kBlkN; used to go from nodes to basis
-// indices with tables [node][a]).
-template <bool kTrans>
-__device__ inline void blk_mode(const double2* in, double2* out, const int* d, int c,
-                                const double* M, int nout) {
-  int o[3] = {d[0], d[1], d[2]};
-  o[c] = nout;
-  const int tot = o[0] * o[1] * o[2];
-  const int nin = d[c];
-  for (int e = threadIdx.x; e < tot; e += blockDim.x) {
-    int i[3];
-    i[2] = e % o[2];
-    i[1] = (e / o[2]) % o[1];
-    i[0] = e / (o[1] * o[2]);
-    const int oc = i[c];
+// Threads of the transmission kernels: one block per (item, column) holds
+// every face tensor of the item in LDS, so its latency is hidden by the
+// block's own waves (16 per CU).  Both kernels take the dimension D as a
+// template argument: every loop over dimensions unrolls and all per-
+// dimension sizes stay in registers.
+constexpr int kTxT = 1024;
+
+// One contraction stage over dimension C of np stacked face tensors
+// [d0][d1][d2] (last fastest; tensor p at in + p istr): dimension C becomes
+// nout long, out[..o..] = sum_a M(o, a) in[..a..] with M(o, a) = M[o][a]
+// (nodes from basis values), or M[a][o] when kT (basis from nodes); row
+// stride kBlkN.
+template <int C, bool kT>
+__device__ inline void tx_stage(const double2* in, int istr, double2* out, int ostr, int np,
+                                int d0, int d1, int d2, int nout, const double* M) {
+  const int o0 = C == 0 ? nout : d0, o1 = C == 1 ? nout : d1, o2 = C == 2 ? nout : d2;
+  const int tot = o0 * o1 * o2;
+  const int nin = C == 0 ? d0 : C == 1 ? d1 : d2;
+  const int sc = C == 0 ? d1 * d2 : C == 1 ? d2 : 1;
+  for (int e = threadIdx.x; e < np * tot; e += blockDim.x) {
+    const int p = e / tot, q = e - p * tot;
+    const int i2 = q % o2, i1 = (q / o2) % o1, i0 = q / (o1 * o2);
+    const int oc = C == 0 ? i0 : C == 1 ? i1 : i2;
+    const int base = (C == 0 ? 0 : i0 * d1 * d2) + (C == 1 ? 0 : i1 * d2) + (C == 2 ? 0 : i2);
+    const double2* src = in + p * istr + base;
     double2 acc = make_double2(0.0, 0.0);
     for (int a = 0; a < nin; ++a) {
-      i[c] = a;
-      const double mv = kTrans ? M[a * kBlkN + oc] : M[oc * kBlkN + a];
-      const double2 v = in[(i[0] * d[1] + i[1]) * d[2] + i[2]];
-      acc.x = fma(mv, v.x, acc.x);
-      acc.y = fma(mv, v.y, acc.y);
+      const double mv = kT ? M[a * kBlkN + oc] : M[oc * kBlkN + a];
+      const double2 u = src[a * sc];
+      acc.x = fma(mv, u.x, acc.x);
+      acc.y = fma(mv, u.y, acc.y);
     }
-    out[e] = acc;
+    out[p * ostr + q] = acc;
   }
-  __syncthreads();
 }
 
-// Contract dimension k of the coefficient tensor y with the complex vector
-// v (n_k), then every tangential dimension with its node table: nodes in
-// the returned buffer (A or B).
-__device__ inline double2* blk_face_trace(const BlkDim* bd, int D, int k, const double2* y,
-                                          const double2* v, double2* A, double2* B) {
-  const Tang t = tang_of(bd, D, k);
-  int st[4];
-  blk_strides(bd, D, st);
-  const int n_t = t.n[0] * t.n[1] * t.n[2];
-  for (int e = threadIdx.x; e < n_t; e += blockDim.x) {
-    const int i2 = e % t.n[2], i1 = (e / t.n[2]) % t.n[1], i0 = e / (t.n[1] * t.n[2]);
-    const int ii[3] = {i0, i1, i2};
-    int base = 0;
-    for (int c = 0; c < t.nd; ++c) base += ii[c] * st[t.dim[c]];
-    double2 acc = make_double2(0.0, 0.0);
-    for (int a = 0; a < bd[k].n; ++a) acc = cfma(v[a], y[base + a * st[k]], acc);
-    A[e] = acc;
+// The c-th tangential dimension of the normal dimension k (the others in
+// increasing order).
+__device__ constexpr int tdim(int k, int c) { return c < k ? c : c + 1; }
+
+// Per-dimension basis sizes (1 beyond D) and multi-index strides (last
+// dimension fastest; 0 beyond D).
+template <int D>
+__device__ inline void tx_sizes(const BlkDim* bd, int* nb, int* st) {
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    nb[m] = m < D ? bd[m].n : 1;
+    st[m] = 0;
   }
-  __syncthreads();
-  int d[3] = {t.n[0], t.n[1], t.n[2]};
-  double2* in = A;
-  double2* out = B;
-  for (int c = 0; c < t.nd; ++c) {
-    blk_mode<false>(in, out, d, c, &bd[t.dim[c]].phit[0][0], t.nt[c]);
-    d[c] = t.nt[c];
-    double2* tmp = in;
-    in = out;
-    out = tmp;
-  }
-  return in;
+  st[D - 1] = 1;
+#pragma unroll
+  for (int m = D - 2; m >= 0; --m) st[m] = st[m + 1] * nb[m + 1];
 }
 
-__global__ void __launch_bounds__(kBT) k_blk_send(BlkItems b, BlkState S, BlkTx tx, double2* Tr,
-                                                  int* flags) {
+// Sender: per normal dimension k the six traces of the state (the four
+// Robin positions of y, the values of y - y_prev at the two own faces for
+// the residual) go through the contraction together, stacked, so that one
+// barrier serves all six at every stage.
+constexpr int kSendStack = kBlkPos + 2;
+template <int D>
+__global__ void __launch_bounds__(kTxT) k_blk_send(BlkItems b, BlkState S, BlkTx tx, double2* Tr,
+                                                   int* flags) {
+  constexpr int kF = D == 2 ? kBlkNt : kBlkFace;      // face tensor size bound
+  constexpr int kKD = D == 2 ? kBlkN * kBlkN : kBlkK;  // basis size bound
   const Items& it = b.it;
   const int s = blockIdx.x, j = blockIdx.y;
   if (j >= tx.n) return;
   const BlkDim* bd = b.bd + 4 * s;
-  const int K = it.K[s], D = it.D;
-  __shared__ double2 y[kBlkK], dl[kBlkK], A[kBlkFace], B[kBlkFace];
-  __shared__ double red[kBT / 64];
+  const int K = it.K[s];
+  __shared__ double2 y[kKD], dl[kKD];
+  __shared__ double2 A[kSendStack * kF], B[kSendStack * kF];
+  __shared__ double red[kTxT / 64];
   const int64_t hoff = (int64_t)(S.n_steps + 1) * it.off1[s];
   const double2* ysrc = tx.slot[j] >= 0
-                          ? S.hist + tx.slot[j] * S.hstride + hoff + (int64_t)tx.step[j] * K
-                          : S.y0 + it.off1[s];
+                            ? S.hist + tx.slot[j] * S.hstride + hoff + (int64_t)tx.step[j] * K
+                            : S.y0 + it.off1[s];
   const bool resid = tx.prev[j] != -2;
   const double2* yp = nullptr;
   if (resid)
@@ -979,32 +1006,71 @@ __global__ void __launch_bounds__(kBT) k_blk_send(BlkItems b, BlkState S, BlkTx 
     if (resid) dl[l] = csub(v, yp[l]);
   }
   __syncthreads();
+  int nb[4], st[4];
+  tx_sizes<D>(bd, nb, st);
+  const int nt = bd[0].nt;  // face nodes per tangential dimension (all alike)
+  const int nn = D == 2 ? nt : nt * nt * nt;
   double2* tr = Tr + ((int64_t)j * it.n_items + s) * D * kBlkPos * b.fstride;
+  const int np = resid ? kSendStack : kBlkPos;
   double part = 0.0;
+#pragma unroll
   for (int k = 0; k < D; ++k) {
-    const Tang t = tang_of(bd, D, k);
-    const int nn = t.nt[0] * t.nt[1] * t.nt[2];
-    for (int p = 0; p < kBlkPos; ++p) {
-      const double2* f = blk_face_trace(bd, D, k, y, bd[k].rob[p], A, B);
-      double2* o = tr + (int64_t)(k * kBlkPos + p) * b.fstride;
-      for (int e = threadIdx.x; e < nn; e += blockDim.x) o[e] = f[e];
+    const int T0 = tdim(k, 0), T1 = tdim(k, 1), T2 = tdim(k, 2);
+    const int n0 = nb[T0], n1 = D > 2 ? nb[T1] : 1, n2 = D > 3 ? nb[T2] : 1;
+    const int s0 = st[T0], s1 = D > 2 ? st[T1] : 0, s2 = D > 3 ? st[T2] : 0;
+    const int n_t = n0 * n1 * n2;
+    const int sk = st[k], nk = nb[k];
+    // dimension k against the six vectors
+    for (int e = threadIdx.x; e < np * n_t; e += blockDim.x) {
+      const int p = e / n_t, i = e - p * n_t;
+      const int i2 = i % n2, i1 = (i / n2) % n1, i0 = i / (n1 * n2);
+      const int base = i0 * s0 + i1 * s1 + i2 * s2;
+      double2 acc = make_double2(0.0, 0.0);
+      if (p < kBlkPos) {
+        const double2* v = bd[k].rob[p];
+        for (int a = 0; a < nk; ++a) acc = cfma(v[a], y[base + a * sk], acc);
+      } else {
+        const double* v = bd[k].val[p - kBlkPos];
+        for (int a = 0; a < nk; ++a) {
+          const double2 u = dl[base + a * sk];
+          acc.x = fma(v[a], u.x, acc.x);
+          acc.y = fma(v[a], u.y, acc.y);
+        }
+      }
+      A[p * kF + i] = acc;
+    }
+    __syncthreads();
+    // tangential dimensions: basis values -> face nodes (A -> B -> A -> B)
+    tx_stage<0, false>(A, kF, B, kF, np, n0, n1, n2, nt, &bd[T0].phit[0][0]);
+    __syncthreads();
+    if (D > 2) {
+      tx_stage<1, false>(B, kF, A, kF, np, nt, n1, n2, nt, &bd[T1].phit[0][0]);
+      __syncthreads();
+      tx_stage<2, false>(A, kF, B, kF, np, nt, nt, n2, nt, &bd[T2].phit[0][0]);
       __syncthreads();
     }
+    for (int e = threadIdx.x; e < kBlkPos * nn; e += blockDim.x) {
+      const int p = e / nn, q = e - p * nn;
+      tr[(int64_t)(k * kBlkPos + p) * b.fstride + q] = B[p * kF + q];
+    }
     if (resid) {
-      for (int side = 0; side < 2; ++side) {
-        double2 vv[kBlkN];
-        for (int a = 0; a < kBlkN; ++a) vv[a] = make_double2(a < bd[k].n ? bd[k].val[side][a] : 0.0, 0.0);
-        const double2* f = blk_face_trace(bd, D, k, dl, vv, A, B);
-        for (int e = threadIdx.x; e < nn; e += blockDim.x) {
-          const int i2 = e % t.nt[2], i1 = (e / t.nt[2]) % t.nt[1], i0 = e / (t.nt[1] * t.nt[2]);
-          double wgt = 1.0;
-          const int ii[3] = {i0, i1, i2};
-          for (int c = 0; c < t.nd; ++c) wgt *= bd[t.dim[c]].tw[ii[c]];
-          part += wgt * (f[e].x * f[e].x + f[e].y * f[e].y);
+      const double* w0 = bd[T0].tw;
+      const double* w1 = bd[D > 2 ? T1 : T0].tw;
+      const double* w2 = bd[D > 3 ? T2 : T0].tw;
+      for (int e = threadIdx.x; e < 2 * nn; e += blockDim.x) {
+        const int p = e / nn, q = e - p * nn;
+        double wgt;
+        if (D == 2) {
+          wgt = w0[q];
+        } else {
+          const int i2 = q % nt, i1 = (q / nt) % nt, i0 = q / (nt * nt);
+          wgt = w0[i0] * w1[i1] * w2[i2];
         }
-        __syncthreads();
+        const double2 f = B[(kBlkPos + p) * kF + q];
+        part += wgt * (f.x * f.x + f.y * f.y);
       }
     }
+    __syncthreads();
   }
   if (resid) {
 #pragma unroll
@@ -1013,7 +1079,7 @@ __global__ void __launch_bounds__(kBT) k_blk_send(BlkItems b, BlkState S, BlkTx 
     __syncthreads();
     if (threadIdx.x == 0) {
       double v = 0.0;
-      for (int q = 0; q < kBT / 64; ++q) v += red[q];
+      for (int q = 0; q < kTxT / 64; ++q) v += red[q];
       if (!isfinite(v)) atomicOr(flags, kFlagNaN);
       const int q = tx.slot[j] >= 0 ? tx.slot[j] : 0;
       S.part[q * S.pstride + (int64_t)s * (S.n_steps + 1) + tx.step[j]] = v;
@@ -1026,102 +1092,124 @@ __global__ void __launch_bounds__(kBT) k_blk_send(BlkItems b, BlkState S, BlkTx 
 // prod_c phi'_{l_c}(y_c).  The covering set of a node (Section 4.1
 // multi-overlap zones, closed membership) is the subdomains at offsets o
 // with o_k in {0, toward the face} and o_c in {0, -1 in the lower band,
-// +1 in the upper band} (where the neighbour exists), o != 0.
-__global__ void __launch_bounds__(kBT) k_blk_recv(BlkItems b, BlkState S, BlkTx tx,
-                                                  const double2* Tr) {
+// +1 in the upper band} (where the neighbour exists), o != 0.  The two faces
+// of a normal dimension share their tables and go through each stage
+// stacked; the dimensions follow one another inside one barrier interval.
+template <int D>
+__global__ void __launch_bounds__(kTxT) k_blk_recv(BlkItems b, BlkState S, BlkTx tx,
+                                                   const double2* Tr) {
+  constexpr int kF = D == 2 ? kBlkNt : kBlkFace;
   const Items& it = b.it;
   const int s = blockIdx.x, j = blockIdx.y;
   if (j >= tx.n) return;
   const BlkDim* bd = b.bd + 4 * s;
-  const int K = it.K[s], D = it.D;
-  __shared__ double2 f[kBlkK], A[kBlkFace], B[kBlkFace];
-  for (int l = threadIdx.x; l < K; l += blockDim.x) f[l] = make_double2(0.0, 0.0);
+  const int K = it.K[s];
+  __shared__ double2 A[2 * D * kF], B[2 * D * kF];
   const int geom = s / it.n_sub, lin = s - geom * it.n_sub;
-  int idx[4], lstride[4];
+  int idx[4], lstr[4], Lm[4];
   {
-    int r = lin, st = 1;
-    for (int k = 0; k < D; ++k) {
-      idx[k] = r % it.L[k];
-      r /= it.L[k];
-      lstride[k] = st;
-      st *= it.L[k];
+    int r = lin, sv = 1;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      Lm[m] = m < D ? it.L[m] : 1;
+      idx[m] = r % Lm[m];
+      r /= Lm[m];
+      lstr[m] = sv;
+      sv *= Lm[m];
     }
   }
-  int st[4];
-  blk_strides(bd, D, st);
+  int nb[4], st[4];
+  tx_sizes<D>(bd, nb, st);
   const double2* trj = Tr + (int64_t)j * it.n_items * D * kBlkPos * b.fstride;
-  __syncthreads();
+  const int nt = bd[0].nt;
+  const int nn = D == 2 ? nt : nt * nt * nt;
+  // gather and average
+#pragma unroll
   for (int k = 0; k < D; ++k) {
-    const Tang t = tang_of(bd, D, k);
-    const int nn = t.nt[0] * t.nt[1] * t.nt[2];
-    for (int side = 0; side < 2; ++side) {
-      if ((side == 0 && idx[k] == 0) || (side == 1 && idx[k] == it.L[k] - 1)) continue;
+    const int T0 = tdim(k, 0), T1 = tdim(k, 1), T2 = tdim(k, 2);
+    const BlkDim& b0 = bd[T0];
+    const BlkDim& b1 = bd[D > 2 ? T1 : T0];
+    const BlkDim& b2 = bd[D > 3 ? T2 : T0];
+    const bool lo_open = idx[k] > 0, hi_open = idx[k] < Lm[k] - 1;
+    for (int e = threadIdx.x; e < 2 * nn; e += blockDim.x) {
+      const int side = e >= nn ? 1 : 0, q = e - side * nn;
+      if (!(side ? hi_open : lo_open)) continue;
+      int i0, i1 = 0, i2 = 0;
+      if (D == 2) {
+        i0 = q;
+      } else {
+        i2 = q % nt;
+        i1 = (q / nt) % nt;
+        i0 = q / (nt * nt);
+      }
+      // per tangential dimension the one possible nonzero offset (0: none)
+      auto sgn = [&](const BlkDim& dc, int ic, int m) {
+        if (ic < dc.band && idx[m] > 0) return -1;
+        if (ic >= dc.band + dc.mid && idx[m] < Lm[m] - 1) return 1;
+        return 0;
+      };
+      const int g0 = sgn(b0, i0, T0);
+      const int g1 = D > 2 ? sgn(b1, i1, T1) : 0;
+      const int g2 = D > 3 ? sgn(b2, i2, T2) : 0;
+      const int p0 = b0.band + b0.mid, p1 = b1.band + b1.mid, p2 = b2.band + b2.mid;
+      double wgt = b0.tw[i0];
+      if (D > 2) wgt *= b1.tw[i1] * b2.tw[i2];
       const int ok = side ? 1 : -1;
-      // gather and average
-      for (int e = threadIdx.x; e < nn; e += blockDim.x) {
-        const int i2 = e % t.nt[2], i1 = (e / t.nt[2]) % t.nt[1], i0 = e / (t.nt[1] * t.nt[2]);
-        const int ii[3] = {i0, i1, i2};
-        int opt[3][3], nopt[3];
-        double wgt = 1.0;
-        for (int c = 0; c < 3; ++c) {
-          opt[c][0] = 0;
-          nopt[c] = 1;
-          if (c >= t.nd) continue;
-          const BlkDim& dc = bd[t.dim[c]];
-          wgt *= dc.tw[ii[c]];
-          if (ii[c] < dc.band && idx[t.dim[c]] > 0) opt[c][nopt[c]++] = -1;
-          if (ii[c] >= dc.band + dc.mid && idx[t.dim[c]] < it.L[t.dim[c]] - 1) opt[c][nopt[c]++] = 1;
+      const int nt1 = D > 2 ? nt : 1, nt2 = D > 3 ? nt : 1;
+      double2 sum = make_double2(0.0, 0.0);
+      int cnt = 0;
+      for (int on = 0; on < 2; ++on)
+        for (int m = 0; m < 8; ++m) {
+          if (on == 0 && m == 0) continue;
+          if (((m & 1) && !g0) || ((m & 2) && !g1) || ((m & 4) && !g2)) continue;
+          const int o0 = (m & 1) ? g0 : 0, o1 = (m & 2) ? g1 : 0, o2 = (m & 4) ? g2 : 0;
+          const int sl = lin + (on ? ok * lstr[k] : 0) + o0 * lstr[T0] +
+                         (D > 2 ? o1 * lstr[T1] : 0) + (D > 3 ? o2 * lstr[T2] : 0);
+          const int node = ((i0 - o0 * p0) * nt1 + (i1 - o1 * p1)) * nt2 + (i2 - o2 * p2);
+          const int pos = on ? (side == 0 ? 2 : 3) : side;
+          const int sj = geom * it.n_sub + sl;
+          sum = cadd(sum, trj[((int64_t)sj * D + k) * kBlkPos * b.fstride +
+                              (int64_t)pos * b.fstride + node]);
+          ++cnt;
         }
-        double2 sum = make_double2(0.0, 0.0);
-        int cnt = 0;
-        for (int on = 0; on < 2; ++on)
-          for (int u0 = 0; u0 < nopt[0]; ++u0)
-            for (int u1 = 0; u1 < nopt[1]; ++u1)
-              for (int u2 = 0; u2 < nopt[2]; ++u2) {
-                const int o[3] = {opt[0][u0], opt[1][u1], opt[2][u2]};
-                if (on == 0 && o[0] == 0 && o[1] == 0 && o[2] == 0) continue;
-                int sl = lin + (on ? ok * lstride[k] : 0);
-                int node = 0;
-                for (int c = 0; c < 3; ++c) {
-                  const int span = c < t.nd ? bd[t.dim[c]].band + bd[t.dim[c]].mid : 0;
-                  if (c < t.nd) sl += o[c] * lstride[t.dim[c]];
-                  node = node * t.nt[c] + (ii[c] - o[c] * span);
-                }
-                const int pos = on ? (side == 0 ? 2 : 3) : side;
-                const int sj = geom * it.n_sub + sl;
-                sum = cadd(sum, trj[((int64_t)sj * D + k) * kBlkPos * b.fstride +
-                                    (int64_t)pos * b.fstride + node]);
-                ++cnt;
-              }
-        A[e] = cscale(sum, wgt / cnt);
-      }
-      __syncthreads();
-      // nodes -> tangential basis indices
-      int d[3] = {t.nt[0], t.nt[1], t.nt[2]};
-      double2* in = A;
-      double2* out = B;
-      for (int c = 0; c < t.nd; ++c) {
-        blk_mode<true>(in, out, d, c, &bd[t.dim[c]].phit[0][0], t.n[c]);
-        d[c] = t.n[c];
-        double2* tmp = in;
-        in = out;
-        out = tmp;
-      }
-      // f[l] += val'[side][l_k] tang[l_T]
-      for (int l = threadIdx.x; l < K; l += blockDim.x) {
-        int a[4];
-        blk_split(l, bd, D, a);
-        int ti = 0;
-        for (int c = 0; c < 3; ++c) ti = ti * t.n[c] + (c < t.nd ? a[t.dim[c]] : 0);
-        f[l] = cadd(f[l], cscale(in[ti], bd[k].val[side][a[k]]));
-      }
-      __syncthreads();
+      A[(2 * k + side) * kF + q] = cscale(sum, wgt / cnt);
     }
   }
+  __syncthreads();
+  // nodes -> tangential basis indices (A -> B -> A -> B); closed faces go
+  // through the stages too and are never read
+#pragma unroll
+  for (int k = 0; k < D; ++k)
+    tx_stage<0, true>(A + 2 * k * kF, kF, B + 2 * k * kF, kF, 2, nt, D > 2 ? nt : 1,
+                      D > 3 ? nt : 1, nb[tdim(k, 0)], &bd[tdim(k, 0)].phit[0][0]);
+  __syncthreads();
+  if (D > 2) {
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+      tx_stage<1, true>(B + 2 * k * kF, kF, A + 2 * k * kF, kF, 2, nb[tdim(k, 0)], nt, nt,
+                        nb[tdim(k, 1)], &bd[tdim(k, 1)].phit[0][0]);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+      tx_stage<2, true>(A + 2 * k * kF, kF, B + 2 * k * kF, kF, 2, nb[tdim(k, 0)],
+                        nb[tdim(k, 1)], nt, nb[tdim(k, 2)], &bd[tdim(k, 2)].phit[0][0]);
+    __syncthreads();
+  }
+  // f'[l] = sum over open faces of val'[side][l_k] tang_F[l without digit k]
   double2* dst = tx.dst[j] == kBlkF1   ? S.F1 + it.off1[s]
                  : tx.dst[j] == kBlkF0 ? S.F0 + it.off1[s]
                                        : S.ring + (int64_t)tx.dst[j] * it.off1[it.n_items] + it.off1[s];
-  for (int l = threadIdx.x; l < K; l += blockDim.x) dst[l] = f[l];
+  for (int l = threadIdx.x; l < K; l += blockDim.x) {
+    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      const int ak = (l / st[k]) % nb[k];
+      const int ti = (l / (st[k] * nb[k])) * st[k] + l % st[k];
+      if (idx[k] > 0) acc = cadd(acc, cscale(B[2 * k * kF + ti], bd[k].val[0][ak]));
+      if (idx[k] < Lm[k] - 1) acc = cadd(acc, cscale(B[(2 * k + 1) * kF + ti], bd[k].val[1][ak]));
+    }
+    dst[l] = acc;
+  }
 }
 
 __global__ void k_blk_res_reduce(const double* part, int n_items, int n_steps, double dt,
@@ -1380,10 +1468,17 @@ hipError_t launch_blk_transmit(const BlkItems& b, const BlkState& S, const BlkTx
                                int K_max, int* flags, hipStream_t st) {
   if (tx.n <= 0) return hipSuccess;
   (void)K_max;
-  hipLaunchKernelGGL(k_blk_send, dim3(b.it.n_items, tx.n), dim3(kBT), 0, st, b, S, tx, Tr, flags);
+  const dim3 grid(b.it.n_items, tx.n);
+  if (b.it.D == 2)
+    hipLaunchKernelGGL(k_blk_send<2>, grid, dim3(kTxT), 0, st, b, S, tx, Tr, flags);
+  else
+    hipLaunchKernelGGL(k_blk_send<4>, grid, dim3(kTxT), 0, st, b, S, tx, Tr, flags);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_blk_recv, dim3(b.it.n_items, tx.n), dim3(kBT), 0, st, b, S, tx, Tr);
+  if (b.it.D == 2)
+    hipLaunchKernelGGL(k_blk_recv<2>, grid, dim3(kTxT), 0, st, b, S, tx, Tr);
+  else
+    hipLaunchKernelGGL(k_blk_recv<4>, grid, dim3(kTxT), 0, st, b, S, tx, Tr);
   return hipGetLastError();
 }
 
