@@ -18,12 +18,21 @@ iterations each, their launches replayed from a HIP graph captured on the
 first window (--no-graph: launched one by one); kernel durations come from
 HIP events the library records around each launch on the run's stream, in a
 second pass over as many windows launched one by one.
+
+The same JSON line carries the other workloads as context objects (not the
+headline value): the imaginary-time window, the batched wide-basis windows,
+the two-electron two-dimension workload on the block path (256 subdomains of
+1296 Gaussians, 30 Schwarz iterations in flight) and the learned warm start.
+cpu_baseline is the oracle over the headline window on a process pool of the
+host's cores (at most 16).
 """
 import argparse
 import json
 import os
 import sys
 import time
+
+import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
@@ -49,25 +58,6 @@ MEASURED_TRAFFIC = {
     # profiles/c3-1e-1d-batched_traffic.md: one sweep of the batched workload
     "k_cn_recur_wide": {"wide_sha256": "b8ae3eabd3030a28", "bytes_per_launch": 1349.16e9},
 }
-
-
-def cpu_baseline(cfg, iters):
-    """The oracle as it stands, one thread, on a bounded sample: the first
-    `iters` Schwarz iterations of the same window (every subdomain, Robin
-    data and residual included)."""
-    from threadpoolctl import threadpool_limits
-
-    from oracle import swr as o_swr
-    with threadpool_limits(limits=1):
-        prob = o_swr.Problem(cfg)
-        c0 = prob.initial_coeffs()
-        t = time.perf_counter()
-        o_swr.swr_window(prob, c0, iters=iters)
-        dt = time.perf_counter() - t
-    return dict(value=prob.n_sub * iters / dt, unit="subdomain-solves/s", cores=1, kind="oracle",
-                sample=f"{iters} Schwarz iterations of the window, all {prob.n_sub} subdomains "
-                       f"({cfg['n_steps']} Crank-Nicolson steps each, Robin data and residual "
-                       f"included), NumPy/LAPACK FP64 on one host thread: {dt:.1f} s")
 
 
 def kernels_digest():
@@ -245,6 +235,207 @@ def tise_summary(iters=20):
     }
 
 
+def host_cpu():
+    """Host core count and CPU model (the GPU machine's host when run there)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return os.cpu_count() or 1, model
+
+
+_POOL = {}
+
+
+def _pool_init(cfg):
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(limits=1)
+    from oracle import swr as o_swr
+    p = o_swr.Problem(cfg)
+    for i in range(p.n_sub):  # every system assembled before the timing
+        p.sys[i]
+    _POOL["prob"] = p
+
+
+def _pool_view(name):
+    a = _POOL[name]
+    return np.frombuffer(a, dtype=np.complex128).reshape(_POOL["shape"])
+
+
+def _pool_cn(args):
+    """Iterate of subdomain i from its Robin data; its residual term."""
+    from oracle import swr as o_swr
+    i, cur = args
+    p = _POOL["prob"]
+    H = _pool_view(f"H{cur}")
+    Hp = _pool_view(f"H{1 - cur}")
+    F = _pool_view("F")
+    c0 = _pool_view("C0")[i, 0]
+    H[i] = o_swr.local_cn(p.sys[i], c0, F[i], _POOL["E"], p.dt)
+    return o_swr.residual_terms(p, {i: H[i]}, {i: Hp[i]}, subs=[i])[i]
+
+
+def _pool_tx(args):
+    """Robin data of subdomain i from its neighbours' iterates."""
+    from oracle import swr as o_swr
+    i, cur = args
+    H = _pool_view(f"H{cur}")
+    F = _pool_view("F")
+    F[i] = o_swr.forcing(_POOL["prob"], i, lambda j: H[j])
+    return 0
+
+
+def cpu_baseline_pool(cfg, iters, workers):
+    """The oracle as it stands on every host core: a process pool over the
+    subdomains runs, in each Schwarz iteration, their Crank-Nicolson windows
+    with the residual terms, then their Robin data (one single-threaded
+    LAPACK per process; the iterates live in shared memory).  The whole
+    window of `iters` iterations is timed (assembly and projection
+    outside)."""
+    import multiprocessing as mp
+
+    from threadpoolctl import threadpool_limits
+
+    from oracle import swr as o_swr
+    prob = o_swr.Problem(cfg)
+    with threadpool_limits(limits=1):
+        c0 = prob.initial_coeffs()
+    K = max(len(c) for c in c0)
+    assert all(len(c) == K for c in c0), "the pooled baseline takes uniform bases"
+    shape = (prob.n_sub, prob.n_T + 1, K)
+    n = int(np.prod(shape)) * 2
+    for name in ("H0", "H1", "F", "C0"):
+        _POOL[name] = mp.RawArray("d", n)
+    _POOL["shape"] = shape
+    _POOL["E"] = o_swr.field(cfg, prob.times(0.0))
+    C0 = _pool_view("C0")
+    for i in range(prob.n_sub):
+        C0[i] = c0[i][None, :]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers, initializer=_pool_init, initargs=(cfg,)) as pool:
+        pool.map(abs, range(workers))  # workers ready (systems assembled)
+        t = time.perf_counter()
+        # iterate 0: the initial state held constant; its Robin data
+        _pool_view("H1")[:] = C0
+        pool.map(_pool_tx, [(i, 1) for i in range(prob.n_sub)])
+        cur = 0
+        for _ in range(iters):
+            terms = pool.map(_pool_cn, [(i, cur) for i in range(prob.n_sub)])
+            float(np.sqrt(sum(terms)))
+            pool.map(_pool_tx, [(i, cur) for i in range(prob.n_sub)])
+            cur = 1 - cur
+        dt = time.perf_counter() - t
+    for name in ("H0", "H1", "F", "C0"):
+        _POOL.pop(name)
+    cores, model = host_cpu()
+    return dict(value=prob.n_sub * iters / dt, unit="subdomain-solves/s", cores=workers,
+                kind="oracle", host_cores=cores, cpu_model=model,
+                sample=f"the whole window: {iters} Schwarz iterations x {prob.n_sub} subdomains x "
+                       f"{cfg['n_steps']} Crank-Nicolson steps, Robin data and residual "
+                       f"included; a pool of {workers} processes (NumPy/LAPACK FP64, one "
+                       f"thread each) over the subdomains: {dt:.1f} s")
+
+
+def four_dimensional_cpu_baseline(cfg, steps=10):
+    """The oracle on a slice of the four-dimensional workload, extrapolated:
+    one interior subdomain's Crank-Nicolson steps (K = 1296, LAPACK using
+    every host core) and its Robin data for the window, scaled to 256
+    subdomains x 500 steps per iteration.  The potential of the sampled
+    subdomain is assembled with coarser panels outside the timing (its
+    values do not change the cost of a solve)."""
+    from oracle import swr as o_swr
+    from oracle import assemble, gauss1d
+    prob = o_swr.Problem(dict(cfg, quad_nodes=2))
+    i = 85
+    dec = prob.dec
+    sy = prob.sys[i]
+    need = prob.neighbours(i)
+    c0 = {j: assemble.project_initial(dec, dec.subs[j], assemble.kron_all(
+        [gauss1d.overlap(dec.subs[j].alpha[k], dec.subs[j].delta[k], dec.subs[j].lo[k],
+                         dec.subs[j].hi[k]) for k in range(4)])).astype(complex)
+          for j in need + [i]}
+    E = o_swr.field(cfg, prob.times(0.0))
+    t = time.perf_counter()
+    f = o_swr.forcing(prob, i, lambda j: np.repeat(c0[j][None, :], prob.n_T + 1, axis=0))
+    t_tx = time.perf_counter() - t
+    t = time.perf_counter()
+    o_swr.local_cn(sy, c0[i], f[:steps + 1], E[:steps + 1], prob.dt)
+    t_cn = time.perf_counter() - t
+    per_sub = t_cn * prob.n_T / steps + t_tx
+    cores, model = host_cpu()
+    return dict(value=1.0 / per_sub, unit="subdomain-solves/s", cores=cores, kind="oracle",
+                host_cores=cores, cpu_model=model,
+                sample=f"subdomain {i}: {steps} Crank-Nicolson steps with K = {sy.K} "
+                       f"({t_cn:.1f} s, NumPy/LAPACK FP64 on {cores} threads) and its Robin "
+                       f"data for the window ({t_tx:.1f} s), extrapolated to the window's "
+                       f"{prob.n_T} steps: {per_sub:.0f} s per subdomain-solve")
+
+
+def four_dimensional_summary(iters, cpu=True):
+    """The two-electron, two-dimension workload (4^4 = 256 subdomains of 6^4
+    = 1296 Gaussians, 500 steps) on the block path: one window of `iters`
+    Schwarz iterations, all in flight, after an untimed window; kernel times
+    from HIP events.  The step products' algorithmic work per window: per
+    item, iterate and step, t_s series terms applied to a K-vector, 8 K^2
+    real flops each (complex multiply-adds), on the FP64 matrix cores."""
+    import torch
+
+    import workloads
+    from paper_1710_02401_amd import Solver
+    cfg = workloads.get_config("c5-2e-2d")
+    t = time.perf_counter()
+    s = Solver(cfg)
+    s.assemble()
+    s.set_initial()
+    torch.cuda.synchronize()
+    t_asm = time.perf_counter() - t
+    s.run(k_max=iters, tol=-1.0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    st = s.run(k_max=iters, tol=-1.0)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    stt = s.run(k_max=iters, tol=-1.0, timing=True)
+    torch.cuda.synchronize()
+    n, K, nT = int(s.info.n_items), int(s.info.K_max), int(s.n_steps)
+    terms = s.item_terms()
+    flops = 8.0 * K * K * nT * iters * float(sum(terms))
+    kern = stt["kernels"]
+    sec = kern["recur"]["ms"] * 1e-3
+    achieved = flops / sec / 1e12
+    lit = s.run(k_max=1, tol=-1.0, depth=1, timing=True)["kernels"]
+    out = {
+        "workload": f"{cfg['name']}: 2 electrons x 2-D, {n} subdomains, K={K} Gaussians, "
+                    f"{nT} Crank-Nicolson steps per window, {iters} Schwarz iterations in "
+                    f"flight, mu = {cfg['mu'][0]:g}{cfg['mu'][1]:+g}i",
+        "value": n * iters / wall, "unit": "subdomain-solves/s",
+        "ms_per_window": 1e3 * wall, "ms_per_iteration": 1e3 * wall / iters,
+        "assembly_s": t_asm,
+        "series_terms": [int(terms.min()), int(terms.max())],
+        "factor_ms": kern["factor"]["ms"],
+        "step_ms_per_window": kern["recur"]["ms"], "step_launches": kern["recur"]["launches"],
+        "transmit_ms_per_window": kern["transmit"]["ms"],
+        "residual_ms_per_window": kern["residual"]["ms"],
+        "roofline": {"kernel": "k_blk_solve (+ k_blk_rhs)", "bound": "mfma",
+                     "achieved": achieved, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFS, "traffic": None},
+        "residuals": [st["res"][0], st["res"][min(iters, 64) - 1]],
+        "converged": st["converged"],
+        # the paper's schedule: the window's matrices refactored in each
+        # sweep, one iterate at a time
+        "paper_literal_sweep_ms": lit["factor"]["ms"] + lit["recur"]["ms"] + lit["transmit"]["ms"]
+                                  + lit["residual"]["ms"],
+    }
+    if cpu:
+        out["cpu_baseline"] = four_dimensional_cpu_baseline(cfg)
+    return out
+
+
 def wide_digest():
     import hashlib
     path = os.path.join(HERE, "paper_1710_02401_amd", "csrc", "wide.hip")
@@ -264,6 +455,14 @@ def main():
     ap.add_argument("--learned", choices=("off", "quick", "full"), default="quick")
     ap.add_argument("--batched-iters", type=int, default=30,
                     help="Schwarz iterations of the batched wide-basis window (0: skip it)")
+    ap.add_argument("--c5-iters", type=int, default=30,
+                    help="Schwarz iterations of the four-dimensional window (0: skip it)")
+    ap.add_argument("--only-c5", action="store_true",
+                    help="run the four-dimensional leg alone")
+    ap.add_argument("--c5-single", action="store_true",
+                    help="with --only-c5: assembly and one window only (profiling runs)")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="processes of the oracle's pool (0: every host core, at most 16)")
     ap.add_argument("--no-graph", action="store_true",
                     help="time the windows as eager launches instead of a replayed HIP graph")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
@@ -278,6 +477,23 @@ def main():
 
     import workloads
     from paper_1710_02401_amd import Solver
+
+    if args.only_c5:
+        if args.c5_single:
+            cfg = workloads.get_config("c5-2e-2d")
+            s = Solver(cfg)
+            s.assemble()
+            s.set_initial()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st = s.run(k_max=max(1, args.c5_iters), tol=-1.0)
+            torch.cuda.synchronize()
+            print(json.dumps({"four_dimensional_single_window_ms": 1e3 * (time.perf_counter() - t),
+                              "iters": st["iters"]}), flush=True)
+            return
+        print(json.dumps({"four_dimensional": four_dimensional_summary(
+            max(1, args.c5_iters), cpu=not args.no_cpu)}), flush=True)
+        return
 
     cfg = workloads.get_config(args.config)
     iters = int(cfg["iters"])
@@ -394,10 +610,14 @@ def main():
         del s
         torch.cuda.empty_cache()
         out["batched_wide_bases"] = batched_summary(args.batched_iters, cpu=not args.no_cpu)
+    if args.c5_iters > 0:
+        torch.cuda.empty_cache()
+        out["four_dimensional"] = four_dimensional_summary(args.c5_iters, cpu=not args.no_cpu)
     if args.learned != "off":
         out["learned_warm_start"] = learned_summary(args.learned)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_iters)
+        workers = args.cpu_workers or min(16, os.cpu_count() or 1)
+        out["cpu_baseline"] = cpu_baseline_pool(cfg, iters, workers)
     if args.copy_ref_mib > 0:
         a = torch.empty(args.copy_ref_mib * 2 ** 17, dtype=torch.float64, device="cuda").fill_(1.0)
         b = torch.empty_like(a)
