@@ -771,7 +771,8 @@ __global__ void __launch_bounds__(kBT) k_blk_rhs(BlkItems b, BlkState S, BlkCols
 // waves = 64 rows of one item, all columns; k-slices of 32 rows of Rb staged
 // in LDS.  Blocks of one item go to one XCD when the item count allows it.
 constexpr int kSlice = 32;
-__global__ void __launch_bounds__(kBT) k_blk_solve(BlkItems b, BlkState S, BlkCols cols,
+__global__ void __launch_bounds__(kBT)
+k_blk_solve(BlkItems b, BlkState S, BlkCols cols,
                                                    const double2* frag, const double2* Rb, int RB,
                                                    int xcd) {
   const Items& it = b.it;
@@ -797,7 +798,9 @@ __global__ void __launch_bounds__(kBT) k_blk_solve(BlkItems b, BlkState S, BlkCo
   const int t_s = b.terms[s];
   const double2* fr = frag + b.foff[s] + (int64_t)rt * KT * 64 + lane;
   __shared__ double2 Bs[kSlice][kBlkCols + 1];
-  v4d cr0 = {0.0, 0.0, 0.0, 0.0}, ci0 = cr0, cr1 = cr0, ci1 = cr0;
+  // complex products in three real ones: P1 = a c, P2 = b d, P3 = (a + b)(c + d)
+  // for A = a + i b, Y = c + i d; AY = (P1 - P2) + i (P3 - P1 - P2)
+  v4d p10 = {0.0, 0.0, 0.0, 0.0}, p20 = p10, p30 = p10, p11 = p10, p21 = p10, p31 = p10;
   double w0[kBlkTerms], w1[kBlkTerms];
 #pragma unroll
   for (int k = 0; k < kBlkTerms; ++k) {
@@ -853,14 +856,13 @@ __global__ void __launch_bounds__(kBT) k_blk_solve(BlkItems b, BlkState S, BlkCo
     for (int q = 0; q < kSlice / 4; ++q) {
       const double2 b0 = Bs[4 * q + lr][lc], b1 = Bs[4 * q + lr][16 + lc];
       const double b0x = b0.x * sw0, b0y = b0.y * sw0, b1x = b1.x * sw1, b1y = b1.y * sw1;
-      cr0 = mfma16(ac[q].x, b0x, cr0);
-      cr0 = mfma16(-ac[q].y, b0y, cr0);
-      ci0 = mfma16(ac[q].x, b0y, ci0);
-      ci0 = mfma16(ac[q].y, b0x, ci0);
-      cr1 = mfma16(ac[q].x, b1x, cr1);
-      cr1 = mfma16(-ac[q].y, b1y, cr1);
-      ci1 = mfma16(ac[q].x, b1y, ci1);
-      ci1 = mfma16(ac[q].y, b1x, ci1);
+      const double as = ac[q].x + ac[q].y;
+      p10 = mfma16(ac[q].x, b0x, p10);
+      p20 = mfma16(ac[q].y, b0y, p20);
+      p30 = mfma16(as, b0x + b0y, p30);
+      p11 = mfma16(ac[q].x, b1x, p11);
+      p21 = mfma16(ac[q].y, b1y, p21);
+      p31 = mfma16(as, b1x + b1y, p31);
     }
   };
   double2 a0[kSlice / 4], a1[kSlice / 4];
@@ -881,12 +883,12 @@ __global__ void __launch_bounds__(kBT) k_blk_solve(BlkItems b, BlkState S, BlkCo
     if (c0 < cols.n) {
       double2* h = S.hist + cols.slot[c0] * S.hstride + hoff + (int64_t)cols.step[c0] * K + row;
       const double2 yo = h[0];
-      h[K] = make_double2(cr0[r] - yo.x, ci0[r] - yo.y);
+      h[K] = make_double2(p10[r] - p20[r] - yo.x, p30[r] - p10[r] - p20[r] - yo.y);
     }
     if (c1 < cols.n) {
       double2* h = S.hist + cols.slot[c1] * S.hstride + hoff + (int64_t)cols.step[c1] * K + row;
       const double2 yo = h[0];
-      h[K] = make_double2(cr1[r] - yo.x, ci1[r] - yo.y);
+      h[K] = make_double2(p11[r] - p21[r] - yo.x, p31[r] - p11[r] - p21[r] - yo.y);
     }
   }
 }
