@@ -796,7 +796,12 @@ k_blk_solve(BlkItems b, BlkState S, BlkCols cols,
   const int KT = (K + 3) / 4;
   const int64_t fs = blk_fsize(K);
   const int t_s = b.terms[s];
-  const double2* fr = frag + b.foff[s] + (int64_t)rt * KT * 64 + lane;
+  // every load below is unconditional (no branch around a load, so the
+  // compiler's wait counts stay exact and the prefetch overlaps): a wave
+  // past the item's last row tile reads that tile and stores nothing, and
+  // k-tiles past the end read the last one, which meets zero rows of Rb
+  const int rt_ld = min(rt, (K + 15) / 16 - 1);
+  const double2* fr = frag + b.foff[s] + (int64_t)rt_ld * KT * 64 + lane;
   __shared__ double2 Bs[kSlice][kBlkCols + 1];
   // complex products in three real ones: P1 = a c, P2 = b d, P3 = (a + b)(c + d)
   // for A = a + i b, Y = c + i d; AY = (P1 - P2) + i (P3 - P1 - P2)
@@ -814,41 +819,49 @@ k_blk_solve(BlkItems b, BlkState S, BlkCols cols,
   const int n_slices = (K + kSlice - 1) / kSlice;
   const int n_it = n_slices * t_s;
   double2 pb[kSlice * kBlkCols / kBT];
+  int pk0 = 0;  // first row of the slice held in pb
   auto load_b = [&](int k0) {
+    pk0 = k0;
 #pragma unroll
     for (int q = 0; q < kSlice * kBlkCols / kBT; ++q) {
       const int e = threadIdx.x + q * kBT;
       const int r = e / kBlkCols, c = e % kBlkCols;
-      pb[q] = (k0 + r < K) ? rb[(int64_t)(k0 + r) * kBlkCols + c] : make_double2(0.0, 0.0);
+      pb[q] = rb[(int64_t)min(k0 + r, K - 1) * kBlkCols + c];
     }
   };
   auto load_a = [&](int itn, double2 (&a)[kSlice / 4]) {
     const int sl = itn / t_s, k = itn - sl * t_s;
     const int kt0 = sl * (kSlice / 4);
-    const int ktn = min(kSlice / 4, KT - kt0);
+    const int ktl = KT - 1 - kt0;  // last k-tile of the matrix, relative
     const double2* ap = fr + (int64_t)k * fs + (int64_t)kt0 * 64;
 #pragma unroll
-    for (int q = 0; q < kSlice / 4; ++q)
-      a[q] = (active && q < ktn) ? ap[q * 64] : make_double2(0.0, 0.0);
+    for (int q = 0; q < kSlice / 4; ++q) a[q] = ap[min(q, ktl) * 64];
   };
+  // an odd count gets one padding iteration (the last one again, weight 0),
+  // so the unrolled pair below runs without a branch around its second half
+  const int n_pad = (n_it + 1) & ~1;
   auto body = [&](int itc, double2 (&ac)[kSlice / 4], double2 (&an)[kSlice / 4]) {
-    const int sl = itc / t_s, k = itc - sl * t_s;
-    if (k == 0) {
+    const bool live = itc < n_it;
+    const int itv = min(itc, n_it - 1);
+    const int sl = itv / t_s, k = itv - sl * t_s;
+    if (live && k == 0) {
       __syncthreads();
 #pragma unroll
       for (int q = 0; q < kSlice * kBlkCols / kBT; ++q) {
         const int e = threadIdx.x + q * kBT;
-        Bs[e / kBlkCols][e % kBlkCols] = pb[q];
+        const int r = e / kBlkCols;
+        Bs[r][e % kBlkCols] = pk0 + r < K ? pb[q] : make_double2(0.0, 0.0);
       }
       __syncthreads();
-      if (sl + 1 < n_slices) load_b((sl + 1) * kSlice);
+      load_b(min(sl + 1, n_slices - 1) * kSlice);
     }
-    if (itc + 1 < n_it) load_a(itc + 1, an);
-    if (!active) return;
+    load_a(min(itc + 1, n_it - 1), an);
+    // keep the prefetch issued ahead of this iteration's products
+    __builtin_amdgcn_sched_barrier(0);
     double sw0 = 0.0, sw1 = 0.0;
 #pragma unroll
     for (int kk = 0; kk < kBlkTerms; ++kk)
-      if (kk == k) {
+      if (live && kk == k) {
         sw0 = w0[kk];
         sw1 = w1[kk];
       }
@@ -867,11 +880,12 @@ k_blk_solve(BlkItems b, BlkState S, BlkCols cols,
   };
   double2 a0[kSlice / 4], a1[kSlice / 4];
   load_b(0);
+  __builtin_amdgcn_sched_barrier(0);  // right-hand sides first, as in the loop
   load_a(0, a0);
 #pragma unroll 1
-  for (int itc = 0; itc < n_it; itc += 2) {
+  for (int itc = 0; itc < n_pad; itc += 2) {
     body(itc, a0, a1);
-    if (itc + 1 < n_it) body(itc + 1, a1, a0);
+    body(itc + 1, a1, a0);
   }
   if (!active) return;
   const int64_t hoff = (int64_t)(S.n_steps + 1) * it.off1[s];
