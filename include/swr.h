@@ -40,7 +40,9 @@ enum {
   SWR_E_SIZE = -2,     /* buffer too small / size beyond a kernel's limit      */
   SWR_E_DEVICE = -3,   /* HIP runtime error (launch, copy, no device)          */
   SWR_E_STATE = -4,    /* call out of order (e.g. sweep before assemble)       */
-  SWR_E_SINGULAR = -5, /* zero pivot met in a device factorisation             */
+  SWR_E_SINGULAR = -5, /* a matrix singular to working precision: a Gram
+                          matrix at swr_create, or a zero pivot met in a
+                          device factorisation                               */
   SWR_E_NAN = -6,      /* non-finite value produced on the device              */
   SWR_E_NOCONV = -7,   /* iteration cap reached above the residual target      */
   SWR_E_COND = -8      /* a local Gram matrix is too ill-conditioned for the
@@ -140,12 +142,17 @@ typedef struct swr_info {
  * decomposition).  Validates the description: SWR_E_ARG for inconsistent
  * fields, SWR_E_SIZE if a basis exceeds the kernels' limits: K <= 64 per
  * subdomain, or K <= 256 for one electron in one dimension in real time
- * (the wide-basis path, see swr_factor).  SWR_E_COND if the Gram matrix A
- * of some subdomain has a condition number above 1e6: the recurrence of
- * swr_sweep reuses the previous right-hand side as M^n c^n, which feeds the
- * stored inverses' residual (about cond(M) eps) into every later step, and
- * such bases would end measurably away from the LU-solved answer while
- * reporting success.  *out receives a new handle. */
+ * (the wide-basis path, see swr_factor), or the block path's limits
+ * (tensor bases in two or four dimensions up to K = 1536).  SWR_E_SINGULAR
+ * if some subdomain's Gram matrix A is singular to working precision (its
+ * Cholesky factorisation fails, or its condition exceeds 1e14: e.g. two
+ * coinciding or nearly constant Gaussians), on every path.  SWR_E_COND if
+ * it has a condition number above 1e6 on the narrow and wide paths: their
+ * recurrence (swr_sweep) reuses the previous right-hand side as M^n c^n,
+ * which feeds the stored inverses' residual (about cond(M) eps) into every
+ * later step, and such bases would end measurably away from the LU-solved
+ * answer while reporting success (the block path solves in orthonormalised
+ * coordinates and is not limited this way).  *out receives a new handle. */
 int32_t swr_create(const swr_desc* desc, swr_handle* out);
 void swr_destroy(swr_handle h);
 const char* swr_last_error(swr_handle h);
@@ -228,7 +235,17 @@ int32_t swr_sweep(swr_handle h, void* stream);
 int32_t swr_transmit(swr_handle h, double* residual_host, void* stream);
 
 /* Whole window: factor, then sweep + transmit until Res(k) <= tol with
- * k >= 2, or k == k_max.  iters/res receive up to 64 entries.
+ * k >= 2, or k == k_max.  iters/res receive up to 64 entries.  tol <= 0
+ * runs exactly k_max iterations; with tol > 0, reaching k_max above tol
+ * returns SWR_E_NOCONV, with *stats filled as on success (the state is the
+ * last iterate's, as after a success).
+ * Growth guard (GIVEN warm start only, whose Robin data came from outside
+ * the method, e.g. the learned predictor): growth_guard consecutive
+ * increases of Res(k) stop the run, and the window is run again from the
+ * PLAIN warm start, with the same options; stats then describe that run and
+ * fallback = 1.  The pipelined and one-at-a-time runs check as the
+ * residuals arrive; a graph-replayed window (residuals read after it) is
+ * checked afterwards.
  * TDSE with depth P > 1: the window is cut into P chunks of steps and
  * iterate k works on chunk c while iterate k+1 works on chunk c-1 (each
  * chunk of iterate k+1 needs only chunk c of iterate k and its own chunk
@@ -256,6 +273,9 @@ typedef struct swr_run_opts {
                                 are captured once into a HIP graph (per k_max
                                 and depth) and replayed; the residuals are
                                 read after the window                        */
+  int32_t growth_guard;      /* GIVEN warm start: consecutive increases of
+                                Res(k) that trigger the PLAIN fallback
+                                (0: 2; negative: never)                      */
 } swr_run_opts;
 /* With timing, ms_* hold the summed durations (HIP events recorded on the
  * run's stream around each launch) and n_* the launch counts of the
@@ -268,6 +288,8 @@ typedef struct swr_run_stats {
   double energy;             /* TISE: (1/nu - 1)/dt at the last step          */
   double ms_factor, ms_transmit, ms_recur, ms_residual;
   int32_t n_factor, n_transmit, n_recur, n_residual;
+  int32_t fallback;          /* 1: the GIVEN warm start was abandoned for the
+                                PLAIN one by the growth guard                */
 } swr_run_stats;
 int32_t swr_run(swr_handle h, const swr_run_opts* opts, swr_run_stats* stats, void* stream);
 

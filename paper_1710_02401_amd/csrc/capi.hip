@@ -64,6 +64,8 @@ constexpr int kWideSlots = swr::kWideTerms + 2;
 // to 2e5 (the paper's Test 2.b boxes); the Test 3 boxes with delta = 0.5
 // (condition 1.6e8) end 3 % away.
 constexpr double kCondLimit = 1e6;
+// Above this a Gram matrix is taken as singular to working precision.
+constexpr double kSingularLimit = 1e14;
 
 // Condition number (2-norm) of the one-dimensional Gram matrix
 // S_ab = int_lo^hi exp(-d (x - a_a)^2) exp(-d (x - a_b)^2) dx: Cholesky,
@@ -135,17 +137,21 @@ double gram_condition_1d(const double* al, int n, double d, double lo, double hi
 
 // Largest Gram condition over the subdomains of one geometry (the boxes and
 // bases are shared by every geometry): the product of the per-dimension
-// conditions, exact for tensor bases.
-double max_gram_condition(const Geometry& g) {
-  double worst = 1.0;
+// conditions, exact for tensor bases; *worst_1d receives the largest
+// one-dimensional factor's.
+double max_gram_condition(const Geometry& g, double* worst_1d) {
+  double worst = 1.0, w1 = 1.0;
   for (int s = 0; s < g.n_sub; ++s) {
     double c = 1.0;
     for (int k = 0; k < g.D; ++k) {
       const size_t q = (size_t)s * 4 + k;
-      c *= gram_condition_1d(&g.alpha[g.aoff[q]], g.nb[q], g.delta[q], g.lo[q], g.hi[q]);
+      const double c1 = gram_condition_1d(&g.alpha[g.aoff[q]], g.nb[q], g.delta[q], g.lo[q], g.hi[q]);
+      c *= c1;
+      w1 = std::isnan(c1) ? c1 : std::max(w1, c1);
     }
     worst = std::max(worst, c);
   }
+  *worst_1d = w1;
   return worst;
 }
 
@@ -170,9 +176,25 @@ struct Layout {
 
 }  // namespace
 
+// Growth guard of a GIVEN warm start: counts consecutive increases of the
+// residuals as they arrive; hit once `limit` of them are seen (limit 0: off).
+struct Growth {
+  int limit = 0;
+  int run = 0;
+  double last = -1.0;
+  bool hit = false;
+  bool step(double r) {
+    run = (last >= 0.0 && r > last) ? run + 1 : 0;
+    last = r;
+    hit = hit || (limit > 0 && run >= limit);
+    return hit;
+  }
+};
+
 struct swr_handle_s {
   Geometry g;
   std::string err;
+  Growth growth;  // the current swr_run's growth guard
   int n_mats = 0;
   int64_t sum_K = 0, sum_K2 = 0, n_T = 0, s1_total = 0, scratch_total = 0;
   int n_res_tiles = 0;
@@ -1148,6 +1170,8 @@ int32_t blk_run(swr_handle h, const swr_run_opts* o, swr_run_stats* stats, hipSt
   if (rc) return rc;
   HIPCHECK(h, tcollect(h, &s));
   if (stats) *stats = s;
+  if (o->tol > 0.0 && !s.converged)
+    return fail(h, SWR_E_NOCONV, "iteration cap reached above the residual target");
   return SWR_OK;
 }
 
@@ -1173,6 +1197,17 @@ int32_t swr_create(const swr_desc* desc, swr_handle* out) {
     return code;
   }
   Geometry& g = h->g;
+  double cond_1d = 1.0;
+  const double gram_cond = max_gram_condition(g, &cond_1d);
+  if (!(cond_1d <= kSingularLimit)) {
+    char buf[200];
+    std::snprintf(buf, sizeof buf,
+                  "a subdomain's one-dimensional Gram matrix is singular to working precision "
+                  "(condition %.3g): its Gaussians are linearly dependent at this width", cond_1d);
+    g_create_error = buf;
+    delete h;
+    return SWR_E_SINGULAR;
+  }
   if (g.desc.factor_mode == SWR_FACTOR_BLOCK || (g.D == 4 && g.K_max > swr::kSmallK)) {
     const std::string why = blk_unsupported(g);
     if (!why.empty()) {
@@ -1231,7 +1266,7 @@ int32_t swr_create(const swr_desc* desc, swr_handle* out) {
     return SWR_E_SIZE;
   }
   {
-    const double cond = max_gram_condition(g);
+    const double cond = gram_cond;
     if (!(cond <= kCondLimit)) {
       char buf[200];
       std::snprintf(buf, sizeof buf,
@@ -2024,6 +2059,7 @@ int32_t run_pipelined(swr_handle h, const swr_run_opts* o, int P, swr_run_stats*
       k_final = k;
       s.converged = 1;
     }
+    if (h->growth.step(r) && k_final == 0) k_final = k;  // the caller falls back
     return SWR_OK;
   };
   int last_read = 0;
@@ -2204,14 +2240,30 @@ int32_t swr_run(swr_handle h, const swr_run_opts* o, swr_run_stats* stats, void*
   swr_run_stats s{};
   const int P = o->depth <= 0 ? h->depth_run : std::min(o->depth, h->depth);
   const bool tise = h->g.desc.mode == SWR_TISE;
-  if (P > 1) {
-    const bool graph = o->graph != 0 && o->tol < 0.0 && !h->timing && !tise;
-    rc = graph ? run_graph(h, o, P, &s, (hipStream_t)stream)
-               : run_pipelined(h, o, P, &s, (hipStream_t)stream);
+  const bool graph = P > 1 && o->graph != 0 && o->tol < 0.0 && !h->timing && !tise;
+  h->growth = Growth{};
+  if (o->warm == SWR_WARM_GIVEN) h->growth.limit = o->growth_guard == 0 ? 2 : std::max(0, o->growth_guard);
+  auto iterate = [&]() -> int32_t {
+    if (graph) {
+      const int32_t r = run_graph(h, o, P, &s, (hipStream_t)stream);
+      // a replayed window's residuals arrive after it: the guard looks at them now
+      for (int k = 1; r == SWR_OK && k <= std::min(s.iters, 64); ++k) h->growth.step(s.res[k - 1]);
+      return r;
+    }
+    return P > 1 ? run_pipelined(h, o, P, &s, (hipStream_t)stream) : run_steps(h, o, &s, stream);
+  };
+  rc = iterate();
+  if (rc) return rc;
+  if (h->growth.hit) {
+    // the given Robin data made the iteration grow: the window again from
+    // the plain warm start (the factorisation stands)
+    rc = swr_warm_start(h, SWR_WARM_PLAIN, nullptr, stream);
     if (rc) return rc;
-  } else {
-    rc = run_steps(h, o, &s, stream);
+    h->growth = Growth{};
+    s = swr_run_stats{};
+    rc = iterate();
     if (rc) return rc;
+    s.fallback = 1;
   }
   if (tise) {
     double nu = 1.0;
@@ -2222,6 +2274,8 @@ int32_t swr_run(swr_handle h, const swr_run_opts* o, swr_run_stats* stats, void*
   }
   HIPCHECK(h, tcollect(h, &s));
   if (stats) *stats = s;
+  if (o->tol > 0.0 && !s.converged)
+    return fail(h, SWR_E_NOCONV, "iteration cap reached above the residual target");
   return SWR_OK;
 }
 
@@ -2243,6 +2297,7 @@ int32_t run_steps(swr_handle h, const swr_run_opts* o, swr_run_stats* out, void*
       s.converged = 1;
       break;
     }
+    if (h->growth.step(r)) break;  // the caller falls back
   }
   return SWR_OK;
 }

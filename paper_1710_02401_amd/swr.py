@@ -65,7 +65,8 @@ class swr_info(ctypes.Structure):
 class swr_run_opts(ctypes.Structure):
     _fields_ = [("k_max", ctypes.c_int32), ("tol", ctypes.c_double), ("t0", ctypes.c_double),
                 ("warm", ctypes.c_int32), ("g_dev", ctypes.c_void_p), ("depth", ctypes.c_int32),
-                ("timing", ctypes.c_int32), ("graph", ctypes.c_int32)]
+                ("timing", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("growth_guard", ctypes.c_int32)]
 
 
 class swr_tuning(ctypes.Structure):
@@ -79,7 +80,8 @@ class swr_run_stats(ctypes.Structure):
                 ("ms_factor", ctypes.c_double), ("ms_transmit", ctypes.c_double),
                 ("ms_recur", ctypes.c_double), ("ms_residual", ctypes.c_double),
                 ("n_factor", ctypes.c_int32), ("n_transmit", ctypes.c_int32),
-                ("n_recur", ctypes.c_int32), ("n_residual", ctypes.c_int32)]
+                ("n_recur", ctypes.c_int32), ("n_residual", ctypes.c_int32),
+                ("fallback", ctypes.c_int32)]
 
 
 EXPORTS = [
@@ -310,13 +312,18 @@ class Solver:
         return r.value
 
     def run(self, k_max, tol=0.0, t0=0.0, warm=SWR_WARM_PLAIN, g=None, depth=0, timing=False,
-            graph=False):
+            graph=False, growth_guard=0):
+        """swr_run.  Reaching k_max above tol > 0 (SWR_E_NOCONV) is returned as
+        converged=False, not raised."""
         o = swr_run_opts(k_max, tol, t0, warm, g.data_ptr() if g is not None else None, depth,
-                         int(bool(timing)), int(bool(graph)))
+                         int(bool(timing)), int(bool(graph)), int(growth_guard))
         s = swr_run_stats()
-        self._call("swr_run", ctypes.byref(o), ctypes.byref(s), self._stream())
+        rc = self.lib.swr_run(self.h, ctypes.byref(o), ctypes.byref(s), self._stream())
+        if rc != SWR_E_NOCONV:
+            _check(self.lib, self.h, rc)
         out = dict(iters=s.iters, converged=bool(s.converged),
-                   res=[s.res[i] for i in range(min(s.iters, 64))], energy=s.energy)
+                   res=[s.res[i] for i in range(min(s.iters, 64))], energy=s.energy,
+                   fallback=bool(s.fallback))
         if timing:
             out["kernels"] = {k: dict(ms=getattr(s, "ms_" + k), launches=getattr(s, "n_" + k))
                               for k in ("factor", "transmit", "recur", "residual")}

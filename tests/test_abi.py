@@ -32,6 +32,9 @@ def test_header_declarations_are_exported(S, repo_root):
     assert declared == set(S.EXPORTS)
 
 
+TINY = {c["name"]: c for c in workloads.tiny_configs()}
+
+
 def _create(S, cfg):
     d, keep = S.desc_from_config(cfg)
     h = ctypes.c_void_p()
@@ -301,6 +304,24 @@ def test_wide_bases_need_the_series(S, mutate):
     rc, h = _create(S, cfg)
     assert rc == -2
     assert b"field series" in S.load_library().swr_last_error(None)
+
+
+@pytest.mark.parametrize("name,extra", [("tiny-1d", {}), ("tiny-2d", {}),
+                                        ("tiny-2d", {"factor": "block"})])
+def test_singular_gram_refused(S, name, extra):
+    """Gaussians 30 wide on subdomains a few units across are linearly
+    dependent to working precision (their Gram matrix's Cholesky
+    factorisation fails): swr_create returns SWR_E_SINGULAR on the narrow
+    and the block path alike, naming the cause; the same boxes at their
+    workload's widths are accepted."""
+    cfg = dict(TINY[name], width=30.0, width_ratio=None, **extra)
+    rc, h = _create(S, cfg)
+    assert rc == S.SWR_E_SINGULAR
+    msg = S.load_library().swr_last_error(None).decode()
+    assert "singular to working precision" in msg
+    rc, h = _create(S, dict(TINY[name], **extra))
+    assert rc == 0
+    S.load_library().swr_destroy(h)
 
 
 def test_ill_conditioned_gram_refused(S):
