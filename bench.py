@@ -101,6 +101,12 @@ def learned_summary(mode):
     res["at_best_mu"] = {k: out_b[k] for k in ("plain_mean", "learned_mean", "zero_mean",
                                               "iteration_reduction", "all_converged")}
     res["workload"] = f"{cfg['name']}, {cfg['n_steps']}-step windows, tol 1e-8"
+    if mode == "quick":
+        # the default line's leg is a reduced configuration of the learned
+        # workload, so that the whole benchmark stays within minutes
+        res["reduced"] = ("200-step windows (the workload's are 1000 steps) and "
+                          f"{res['train_samples']} training samples (the workload plans about "
+                          "1e5); --learned full trains and evaluates on 1000-step windows")
     return res
 
 
