@@ -127,12 +127,17 @@ typedef struct swr_info {
   int32_t learned_nodes;     /* M, time nodes of the learned warm start       */
   int32_t factor_terms;      /* series terms of the last swr_factor minus one;
                                 -1: direct inversion per step (or none yet)  */
-  int32_t tx_tile;           /* steps per block of the factored transmission
-                                in use (16 or 32; 0: dense transmission)     */
+  int32_t tx_tile;           /* steps per block of the transmission in use:
+                                16 or 32 (narrow, factored), 8, 16 or 32
+                                (wide); 0: dense transmission / block path   */
   int32_t depth_run;         /* depth swr_run uses for opts.depth = 0
                                 (swr_info.depth until swr_autotune)          */
   int32_t wide;              /* 1: the wide-basis path (see swr_factor)       */
   int32_t block;             /* 1: the block path (see swr_factor)            */
+  int32_t wide_order;        /* wide path: the recurrence's item order, 0
+                                largest K first, 1 item order                */
+  int32_t tuned;             /* 1: the schedule was taken from the tuning
+                                table at swr_assemble (see swr_autotune)     */
 } swr_info;
 
 /* ---- lifetime ------------------------------------------------------------*/
@@ -295,20 +300,31 @@ int32_t swr_run(swr_handle h, const swr_run_opts* opts, swr_run_stats* stats, vo
 
 /* ---- schedule autotuning ---------------------------------------------------*/
 
-/* Measures, on this problem and GPU, every pipeline depth 1..swr_info.depth
- * (TDSE; 1 for TISE) and every transmission tile that fits (16 or 32 steps
- * per block), each as a whole window of k_iters Schwarz iterations (swr_run
- * with tol < 0 from the current initial coefficients, field origin t0, plain
- * warm start; one untimed window first), timed with HIP events on the stream,
- * and keeps the fastest: later swr_run calls with depth 0 use its depth, and
- * every transmission its tile.  The choice only reorders the same arithmetic
- * (results are unchanged; residuals to rounding).  The iteration state is
- * left as after the last trial window.  Synchronises the stream. */
+/* Measures, on this problem and GPU, every schedule: on the narrow path
+ * every pipeline depth 1..swr_info.depth (TDSE; 1 for TISE) and every
+ * transmission tile that fits (16 or 32 steps per block); on the wide path
+ * every transmission tile (8, 16 or 32 steps per block) and both
+ * recurrence orders (largest K first, item order).  Each is timed as a
+ * whole window of k_iters Schwarz iterations (swr_run with tol < 0 from the
+ * current initial coefficients, field origin t0, plain warm start; one
+ * untimed window first) with HIP events on the stream, and the fastest is
+ * kept: later swr_run calls with depth 0 use its depth, and every
+ * transmission and sweep its tile and order.  The choice only reorders the
+ * same arithmetic (results are unchanged; residuals to rounding).  The
+ * choice is also entered in the library's tuning table under (GPU
+ * architecture, path, dimensions, items, steps, counts of items per 64-wide
+ * band of basis sizes); swr_assemble of a later handle with the same key
+ * takes the schedule from the table without measuring (swr_info.tuned).
+ * With the environment variable SWR_TUNING_FILE naming a file, the table is
+ * read from it on first use and written back after each swr_autotune (one
+ * line per key: depth, tile, order, ms, a tab, the key).  The iteration
+ * state is left as after the last trial window.  Synchronises the stream. */
 typedef struct swr_tuning {
   int32_t depth;             /* iterates in flight chosen                     */
   int32_t tx_tile;           /* transmission tile chosen (0: dense)           */
   double ms_per_window;      /* measured for the choice                       */
   int32_t candidates;        /* schedules measured                            */
+  int32_t order;             /* wide path: recurrence order chosen            */
 } swr_tuning;
 int32_t swr_autotune(swr_handle h, int32_t k_iters, double t0, swr_tuning* out, void* stream);
 

@@ -5,6 +5,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -195,6 +200,9 @@ struct swr_handle_s {
   Geometry g;
   std::string err;
   Growth growth;  // the current swr_run's growth guard
+  int wide_tile = 16;     // wide path: steps per transmission block (8, 16, 32)
+  int wide_order = 0;     // wide path: recurrence order, 0 largest K first, 1 item order
+  bool tuned_cached = false;  // a schedule came from the tuning table
   int n_mats = 0;
   int64_t sum_K = 0, sum_K2 = 0, n_T = 0, s1_total = 0, scratch_total = 0;
   int n_res_tiles = 0;
@@ -234,7 +242,8 @@ struct swr_handle_s {
   // prefix sums of the 64 x 64 tiles of the products
   bool wide = false;
   Buf bS2P, bSeriesP, bScrW, bOrder, bTileOff;
-  std::vector<int32_t> order;
+  std::vector<int32_t> order;          // wide path: items by decreasing K
+  std::vector<int32_t> order_natural;  // wide path: items in their own order
   std::vector<int64_t> tile_off;
   Buf bT, bC0, bH[kMaxSlots], bF[kMaxSlots], bRc[kMaxSlots], bMinv, bE, bResPart, bResOut, bResv,
       bFlags;
@@ -592,6 +601,76 @@ void plan_layout(swr_handle h) {
   h->bFlags = L.add(8);
   h->bLag = L.add((h->n_T + 1) * h->n_nodes_t * 8);
   h->bLMax = L.add(8);
+}
+
+// ---------------------------------------------------------------------------
+// Tuning table: the schedule swr_autotune chose, per (GPU architecture, path,
+// dimensions, electrons, items, steps, items per 64-wide band of basis
+// sizes).  Later handles with the same key start from it (swr_assemble).
+// SWR_TUNING_FILE, when set, names a file the table is read from once and
+// written back to after every swr_autotune.
+struct TuneChoice {
+  int depth = 1, tile = 16, order = 0;
+  double ms = 0.0;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneChoice> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_key(swr_handle h) {
+  int dev = 0;
+  hipDeviceProp_t p{};
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess) {
+    arch = p.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+  }
+  const Geometry& g = h->g;
+  int bands[5] = {0, 0, 0, 0, 0};
+  for (int s = 0; s < g.n_items; ++s) ++bands[std::min(4, (g.K[s] - 1) / 64)];
+  std::ostringstream k;
+  k << arch << " " << (h->block ? "block" : h->wide ? "wide" : "narrow") << " D" << g.D << " e"
+    << g.desc.n_elec << " items" << g.n_items << " steps" << h->n_T << " K64";
+  for (int b : bands) k << ":" << b;
+  return k.str();
+}
+
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("SWR_TUNING_FILE");
+  if (!path) return;
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    const size_t tab = line.find('\t');
+    if (tab == std::string::npos) continue;
+    std::istringstream v(line.substr(0, tab));
+    TuneChoice c;
+    if (v >> c.depth >> c.tile >> c.order >> c.ms) g_tune[line.substr(tab + 1)] = c;
+  }
+}
+
+bool tune_lookup(const std::string& key, TuneChoice* c) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  tune_load_locked();
+  const auto it = g_tune.find(key);
+  if (it == g_tune.end()) return false;
+  *c = it->second;
+  return true;
+}
+
+void tune_store(const std::string& key, const TuneChoice& c) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  tune_load_locked();
+  g_tune[key] = c;
+  const char* path = std::getenv("SWR_TUNING_FILE");
+  if (!path) return;
+  std::ofstream f(path, std::ios::trunc);
+  for (const auto& e : g_tune)
+    f << e.second.depth << " " << e.second.tile << " " << e.second.order << " " << e.second.ms
+      << "\t" << e.first << "\n";
 }
 
 int check_flags(swr_handle h, hipStream_t st) {
@@ -1308,7 +1387,7 @@ int32_t swr_create(const swr_desc* desc, swr_handle* out) {
     h->dipole.push_back(x);
   }
   h->n_res_tiles = (int)((h->n_T + 1 + 15) / 16);
-  if (h->wide) h->n_res_tiles = std::max(h->n_res_tiles, swr::tx_wide_tiles((int)h->n_T));
+  if (h->wide) h->n_res_tiles = std::max(h->n_res_tiles, swr::tx_wide_tiles((int)h->n_T, 8));
   h->s1off.assign((size_t)g.n_items * 4, 0);
   h->scratch_off.assign(g.n_items, 0);
   int64_t s1 = 0, scr = 0;
@@ -1344,6 +1423,7 @@ int32_t swr_create(const swr_desc* desc, swr_handle* out) {
   if (h->wide) {
     h->order.resize(g.n_items);
     for (int q = 0; q < g.n_items; ++q) h->order[q] = q;
+    h->order_natural = h->order;
     std::stable_sort(h->order.begin(), h->order.end(),
                      [&](int a, int b) { return g.K[a] > g.K[b]; });
     h->tile_off.assign(g.n_items + 1, 0);
@@ -1443,7 +1523,9 @@ int32_t swr_query(swr_handle h, swr_info* info) {
   r.depth = h->depth;
   r.learned_nodes = h->n_nodes_t;
   r.factor_terms = h->factor_terms;
-  r.tx_tile = h->g.te_ok && !h->wide ? h->tx_tt : 0;
+  r.tx_tile = h->block ? 0 : h->wide ? h->wide_tile : (h->g.te_ok ? h->tx_tt : 0);
+  r.wide_order = h->wide_order;
+  r.tuned = h->tuned_cached ? 1 : 0;
   r.wide = h->wide ? 1 : 0;
   r.block = h->block ? 1 : 0;
   r.depth_run = h->depth_run;
@@ -1474,6 +1556,26 @@ int32_t swr_bind_workspace(swr_handle h, void* dev, uint64_t bytes) {
   h->assembled = h->initial = h->warm = h->factored = false;
   return SWR_OK;
 }
+
+namespace {
+// Takes a schedule (tuning table or autotuner): depth, transmission tile and,
+// on the wide path, the recurrence order (re-uploaded when it changes).
+int32_t apply_schedule(swr_handle h, const TuneChoice& c, hipStream_t st) {
+  h->g_kmax = -1;  // a captured window holds the old tile's kernels: capture again
+  h->depth_run = std::max(1, std::min(c.depth, h->depth));
+  if (h->wide) {
+    h->wide_tile = (c.tile == 8 || c.tile == 32) ? c.tile : 16;
+    const int order = c.order ? 1 : 0;
+    if (order != h->wide_order) {
+      h->wide_order = order;
+      HIPCHECK(h, upload(h, h->bOrder, order ? h->order_natural : h->order, st));
+    }
+  } else if (h->g.te_ok) {
+    h->tx_tt = (c.tile == 32 && h->tx_tt_max == 32) ? 32 : 16;
+  }
+  return SWR_OK;
+}
+}  // namespace
 
 int32_t swr_assemble(swr_handle h, void* stream) {
   if (!h) return SWR_E_ARG;
@@ -1580,7 +1682,7 @@ int32_t swr_assemble(swr_handle h, void* stream) {
   HIPCHECK(h, upload(h, h->bScrOff, h->scratch_off, st));
   HIPCHECK(h, upload(h, h->bCenter, cen4, st));
   if (h->wide) {
-    HIPCHECK(h, upload(h, h->bOrder, h->order, st));
+    HIPCHECK(h, upload(h, h->bOrder, h->wide_order ? h->order_natural : h->order, st));
     HIPCHECK(h, upload(h, h->bTileOff, h->tile_off, st));
   }
   HIPCHECK(h, hipMemsetAsync(h->ptr<int>(h->bFlags), 0, 8, st));
@@ -1628,6 +1730,13 @@ int32_t swr_assemble(swr_handle h, void* stream) {
   HIPCHECK(h, hipStreamSynchronize(st));
   h->assembled = true;
   h->initial = h->warm = h->factored = false;
+  // a schedule measured earlier for this kind of problem
+  TuneChoice c;
+  if (tune_lookup(tune_key(h), &c)) {
+    const int rc = apply_schedule(h, c, st);
+    if (rc) return rc;
+    h->tuned_cached = true;
+  }
   return SWR_OK;
 }
 
@@ -1687,7 +1796,7 @@ int32_t swr_warm_start(swr_handle h, int32_t mode, const void* g_dev, void* stre
   double2* F = h->F_of(1);
   if (mode == SWR_WARM_PLAIN && h->wide) {
     HIPCHECK(h, swr::launch_tx_wide(it, h->pairs(), h->te(), nT, h->hist_of(0), F, nullptr,
-                                    nullptr, h->g.desc.dt, st));
+                                    nullptr, h->g.desc.dt, h->wide_tile, st));
   } else if (mode == SWR_WARM_PLAIN) {
     HIPCHECK(h, swr::launch_transmit(it, h->pairs(), h->te(), nT, h->ptr<double2>(h->bT),
                                      full_tx(h->hist_of(0), F, nT), h->nbt,
@@ -1912,9 +2021,10 @@ int32_t transmit_and_residual(swr_handle h, int k, const double* scale, double* 
     HIPCHECK(h, tbegin(h, st, kTTransmit));
     HIPCHECK(h, swr::launch_tx_wide(it, h->pairs(), h->te(), nT, h->hist_of(k), h->F_of(k + 1),
                                     res_dev ? h->hist_of(k - 1) : nullptr, part,
-                                    h->g.desc.dt, st));
+                                    h->g.desc.dt, h->wide_tile, st));
     if (res_dev)
-      HIPCHECK(h, swr::launch_sum_sqrt(part, (int64_t)it.n_items * swr::tx_wide_tiles(nT),
+      HIPCHECK(h, swr::launch_sum_sqrt(part,
+                                       (int64_t)it.n_items * swr::tx_wide_tiles(nT, h->wide_tile),
                                        res_dev, st));
     HIPCHECK(h, tend(h, st));
     (void)scale;
@@ -2167,9 +2277,22 @@ int32_t run_pipelined(swr_handle h, const swr_run_opts* o, int P, swr_run_stats*
   return SWR_OK;
 }
 
-// Fixed-iteration pipelined window through a HIP graph: captured on the first
-// call for (k_max, P) and replayed afterwards; the residuals are read once,
-// after the window.
+// One iterate at a time, launches only (captured into the window's graph at
+// depth 1): every iterate's sweep, then its Robin data and Res(k) into the
+// device residual ring; the host reads them after the window.
+int32_t run_steps_launches(swr_handle h, const swr_run_opts* o, hipStream_t st) {
+  for (int k = 1; k <= o->k_max; ++k) {
+    int rc = swr_sweep(h, st);
+    if (rc) return rc;
+    rc = transmit_and_residual(h, k, nullptr, h->ptr<double>(h->bResv) + k % 64, st);
+    if (rc) return rc;
+  }
+  return SWR_OK;
+}
+
+// Fixed-iteration window through a HIP graph (pipelined, or one iterate at a
+// time): captured on the first call for (k_max, P) and replayed afterwards;
+// the residuals are read once, after the window.
 int32_t run_graph(swr_handle h, const swr_run_opts* o, int P, swr_run_stats* out,
                   hipStream_t st) {
   if (!h->res_pinned) HIPCHECK(h, hipHostMalloc((void**)&h->res_pinned, 64 * sizeof(double), 0));
@@ -2183,7 +2306,8 @@ int32_t run_graph(swr_handle h, const swr_run_opts* o, int P, swr_run_stats* out
     if (!h->cap_stream) HIPCHECK(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     HIPCHECK(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
     swr_run_stats dummy{};
-    const int rc = run_pipelined(h, o, P, &dummy, h->cap_stream, true);
+    const int rc = P > 1 ? run_pipelined(h, o, P, &dummy, h->cap_stream, true)
+                         : run_steps_launches(h, o, h->cap_stream);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
     if (rc) {
@@ -2240,7 +2364,7 @@ int32_t swr_run(swr_handle h, const swr_run_opts* o, swr_run_stats* stats, void*
   swr_run_stats s{};
   const int P = o->depth <= 0 ? h->depth_run : std::min(o->depth, h->depth);
   const bool tise = h->g.desc.mode == SWR_TISE;
-  const bool graph = P > 1 && o->graph != 0 && o->tol < 0.0 && !h->timing && !tise;
+  const bool graph = o->graph != 0 && o->tol < 0.0 && !h->timing && !tise;
   h->growth = Growth{};
   if (o->warm == SWR_WARM_GIVEN) h->growth.limit = o->growth_guard == 0 ? 2 : std::max(0, o->growth_guard);
   auto iterate = [&]() -> int32_t {
@@ -2631,9 +2755,12 @@ int32_t swr_autotune(swr_handle h, int32_t k_iters, double t0, swr_tuning* out, 
     return SWR_OK;
   }
   hipStream_t st = (hipStream_t)stream;
-  std::vector<int> depths, tiles;
+  std::vector<int> depths, tiles, orders{0};
   for (int d = 1; d <= h->depth; ++d) depths.push_back(d);
-  if (h->g.te_ok && !h->wide) {
+  if (h->wide) {
+    tiles = {8, 16, 32};
+    orders = {0, 1};
+  } else if (h->g.te_ok) {
     tiles.push_back(16);
     if (h->tx_tt_max == 32) tiles.push_back(32);
   } else {
@@ -2646,38 +2773,45 @@ int32_t swr_autotune(swr_handle h, int32_t k_iters, double t0, swr_tuning* out, 
     hipEvent_t a, b;
     ~Ev() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
   } ev{e0, e1};
-  double best = -1.0;
-  int best_d = h->depth_run, best_t = h->tx_tt;
-  for (const int t : tiles)
-    for (const int d : depths) {
-      h->tx_tt = t;
-      swr_run_opts o{};
-      o.k_max = k_iters;
-      o.tol = -1.0;
-      o.t0 = t0;
-      o.warm = SWR_WARM_PLAIN;
-      o.depth = d;
-      swr_run_stats s{};
-      int rc = swr_run(h, &o, &s, stream);  // warm-up
-      if (rc) return rc;
-      HIPCHECK(h, hipEventRecord(e0, st));
-      rc = swr_run(h, &o, &s, stream);
-      if (rc) return rc;
-      HIPCHECK(h, hipEventRecord(e1, st));
-      HIPCHECK(h, hipEventSynchronize(e1));
-      float ms = 0.0f;
-      HIPCHECK(h, hipEventElapsedTime(&ms, e0, e1));
-      if (best < 0.0 || ms < best) {
-        best = ms;
-        best_d = d;
-        best_t = t;
+  TuneChoice best;
+  best.ms = -1.0;
+  for (const int od : orders)
+    for (const int t : tiles)
+      for (const int d : depths) {
+        TuneChoice c;
+        c.depth = d;
+        c.tile = t;
+        c.order = od;
+        int rc = apply_schedule(h, c, st);
+        if (rc) return rc;
+        swr_run_opts o{};
+        o.k_max = k_iters;
+        o.tol = -1.0;
+        o.t0 = t0;
+        o.warm = SWR_WARM_PLAIN;
+        o.depth = d;
+        swr_run_stats s{};
+        rc = swr_run(h, &o, &s, stream);  // warm-up
+        if (rc) return rc;
+        HIPCHECK(h, hipEventRecord(e0, st));
+        rc = swr_run(h, &o, &s, stream);
+        if (rc) return rc;
+        HIPCHECK(h, hipEventRecord(e1, st));
+        HIPCHECK(h, hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIPCHECK(h, hipEventElapsedTime(&ms, e0, e1));
+        if (best.ms < 0.0 || ms < best.ms) {
+          best = c;
+          best.ms = ms;
+        }
       }
-    }
-  h->depth_run = best_d;
-  h->tx_tt = best_t;
-  out->depth = best_d;
-  out->tx_tile = h->g.te_ok && !h->wide ? best_t : 0;
-  out->ms_per_window = best;
-  out->candidates = (int32_t)(depths.size() * tiles.size());
+  const int rc = apply_schedule(h, best, st);
+  if (rc) return rc;
+  tune_store(tune_key(h), best);
+  out->depth = h->depth_run;
+  out->tx_tile = h->wide ? h->wide_tile : (h->g.te_ok ? h->tx_tt : 0);
+  out->order = h->wide_order;
+  out->ms_per_window = best.ms;
+  out->candidates = (int32_t)(depths.size() * tiles.size() * orders.size());
   return SWR_OK;
 }

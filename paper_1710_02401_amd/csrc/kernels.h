@@ -362,11 +362,12 @@ hipError_t launch_cn_recur_wide(const Items& it, const int32_t* order, int n_ste
                                 int64_t tstride, int64_t cstride, const double2* c0,
                                 double2* hist, const double2* F, int* flags, hipStream_t st);
 // Robin data of the whole window from src into dst; with prev, one residual
-// partial per (item, step tile) at part[item * tx_wide_tiles(n_steps) + tile].
-int tx_wide_tiles(int n_steps);
+// partial per (item, step tile) at part[item * tx_wide_tiles(n_steps, tile) +
+// tile index].  tile: steps per block, 8, 16 or 32.
+int tx_wide_tiles(int n_steps, int tile);
 hipError_t launch_tx_wide(const Items& it, const Pairs& pr, const TEnt& te, int n_steps,
                           const double2* src, double2* dst, const double2* prev, double* part,
-                          double dt, hipStream_t st);
+                          double dt, int tile, hipStream_t st);
 
 hipError_t launch_last_step(const Items& it, int n_steps, const double2* hist, double2* c0,
                             hipStream_t st);

@@ -615,9 +615,9 @@ __global__ void __launch_bounds__(kWideThreads) k_cn_recur_wide(
 // with prev, the residual partial sum_n w_n sum_F W_F |b_F . (c_i^n -
 // prev_i^n)|^2 of the block's steps (trapezoid weights w_n, face Gram pieces
 // b_F = phi^i(x_F), W_F = sum of the face's node weights) goes to
-// part[i * gridDim.y + blockIdx.y].  Grid (item, tiles of kTxWideSteps
-// steps); wave w takes the steps n0 + w, n0 + w + 4, ...
-constexpr int kTxWideSteps = 16;
+// part[i * gridDim.y + blockIdx.y].  Grid (item, tiles of TS steps; TS
+// chosen by the autotuner); wave w takes the steps n0 + w, n0 + w + 4, ...
+template <int TS>
 __global__ void __launch_bounds__(kWideThreads) k_tx_wide(Items it, Pairs pr, TEnt te, int n_steps,
                                                           const double2* src, double2* dst,
                                                           const double2* prev, double* part,
@@ -625,11 +625,11 @@ __global__ void __launch_bounds__(kWideThreads) k_tx_wide(Items it, Pairs pr, TE
   const int i = blockIdx.x;
   const int Ki = it.K[i];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int n0 = blockIdx.y * kTxWideSteps;
+  const int n0 = blockIdx.y * TS;
   const int64_t hbi = (int64_t)(n_steps + 1) * it.off1[i];
   __shared__ double red[kWideThreads / 64];
   double racc = 0.0;
-  for (int q = w; q < kTxWideSteps; q += 4) {
+  for (int q = w; q < TS; q += 4) {
     const int n = n0 + q;
     if (n > n_steps) break;
     double2 fl[kWideK / 64];
@@ -775,13 +775,21 @@ hipError_t launch_cn_recur_wide(const Items& it, const int32_t* order, int n_ste
   return hipGetLastError();
 }
 
-int tx_wide_tiles(int n_steps) { return (n_steps + 1 + kTxWideSteps - 1) / kTxWideSteps; }
+int tx_wide_tiles(int n_steps, int tile) { return (n_steps + 1 + tile - 1) / tile; }
 
 hipError_t launch_tx_wide(const Items& it, const Pairs& pr, const TEnt& te, int n_steps,
                           const double2* src, double2* dst, const double2* prev, double* part,
-                          double dt, hipStream_t st) {
-  hipLaunchKernelGGL(k_tx_wide, dim3(it.n_items, tx_wide_tiles(n_steps)), dim3(kWideThreads), 0,
-                     st, it, pr, te, n_steps, src, dst, prev, part, dt);
+                          double dt, int tile, hipStream_t st) {
+  const dim3 grid(it.n_items, tx_wide_tiles(n_steps, tile));
+  if (tile == 8)
+    hipLaunchKernelGGL(k_tx_wide<8>, grid, dim3(kWideThreads), 0, st, it, pr, te, n_steps, src,
+                       dst, prev, part, dt);
+  else if (tile == 32)
+    hipLaunchKernelGGL(k_tx_wide<32>, grid, dim3(kWideThreads), 0, st, it, pr, te, n_steps, src,
+                       dst, prev, part, dt);
+  else
+    hipLaunchKernelGGL(k_tx_wide<16>, grid, dim3(kWideThreads), 0, st, it, pr, te, n_steps, src,
+                       dst, prev, part, dt);
   return hipGetLastError();
 }
 

@@ -58,7 +58,7 @@ class swr_info(ctypes.Structure):
         ("depth", ctypes.c_int32), ("workspace_bytes", ctypes.c_uint64),
         ("learned_nodes", ctypes.c_int32), ("factor_terms", ctypes.c_int32),
         ("tx_tile", ctypes.c_int32), ("depth_run", ctypes.c_int32), ("wide", ctypes.c_int32),
-        ("block", ctypes.c_int32),
+        ("block", ctypes.c_int32), ("wide_order", ctypes.c_int32), ("tuned", ctypes.c_int32),
     ]
 
 
@@ -71,7 +71,8 @@ class swr_run_opts(ctypes.Structure):
 
 class swr_tuning(ctypes.Structure):
     _fields_ = [("depth", ctypes.c_int32), ("tx_tile", ctypes.c_int32),
-                ("ms_per_window", ctypes.c_double), ("candidates", ctypes.c_int32)]
+                ("ms_per_window", ctypes.c_double), ("candidates", ctypes.c_int32),
+                ("order", ctypes.c_int32)]
 
 
 class swr_run_stats(ctypes.Structure):
@@ -293,6 +294,8 @@ class Solver:
     # -- the method ------------------------------------------------------------
     def assemble(self):
         self._call("swr_assemble", self._stream())
+        # assembly may take a schedule from the tuning table
+        self._call("swr_query", ctypes.byref(self.info))
 
     def set_initial(self, c0=None):
         self._call("swr_set_initial", _vp(c0), self._stream())
@@ -427,7 +430,7 @@ class Solver:
                    self._stream())
         self._call("swr_query", ctypes.byref(self.info))
         return dict(depth=t.depth, tx_tile=t.tx_tile, ms_per_window=t.ms_per_window,
-                    candidates=t.candidates)
+                    candidates=t.candidates, order=t.order)
 
     def factor_terms(self):
         """Series terms - 1 used by the last factorisation (-1: direct inversion)."""

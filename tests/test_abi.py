@@ -273,7 +273,9 @@ def test_wide_bases_take_the_wide_path(S):
     info = S.swr_info()
     assert lib.swr_query(h, ctypes.byref(info)) == 0
     assert info.wide == 1 and info.K_max == 256 and info.n_items == 64 * 256
-    assert info.depth == 1 and info.tx_tile == 0
+    # one iterate at a time; the wide transmission's default tile (16 steps)
+    # and recurrence order (largest K first) until swr_autotune chooses
+    assert info.depth == 1 and info.tx_tile == 16 and info.wide_order == 0 and info.tuned == 0
     # matrices, series terms and histories, far below one inverse per step
     # (200 x sum K^2 x 16 bytes)
     assert info.workspace_bytes < 200 * info.sum_K2 * 16 / 4

@@ -217,3 +217,77 @@ def test_wide_reconstruction_matches_oracle():
     err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
     print(f"[gpu] wide reconstruction: max rel {err:.3e}", flush=True)
     assert err <= 1e-10
+
+
+def test_wide_window_graph_replay_and_autotuned_schedule():
+    """Batching on the wide path: the window (one iterate at a time) captured
+    as a HIP graph and replayed, with the program's own eager work between
+    the replays, gives the eager window's histories bit for bit and its
+    residuals; the autotuner measures the three transmission tiles and both
+    recurrence orders, and its choice changes no history bit (the residual
+    partials are summed per tile, so residuals agree to rounding); a second
+    handle of the same problem takes the choice from the tuning table."""
+    import torch
+    cfg = dict(_cfg("c3-mini"), factor="wide")
+    s = _solver(cfg)
+    c0 = s.initial().clone()
+    eager = s.run(k_max=4, tol=-1.0)
+    h_eager = s.history().clone()
+    for rep in range(3):  # capture, then replays
+        s.set_initial(c0)
+        g = s.run(k_max=4, tol=-1.0, graph=True)
+        torch.cuda.synchronize()
+        assert g["res"] == eager["res"], rep
+        assert torch.equal(s.history(), h_eager), rep
+        s.set_initial(c0)
+        s.run(k_max=2, tol=-1.0)  # eager work between the replays
+    s.set_initial(c0)
+    t = s.autotune(k_iters=2)
+    print(f"[gpu] wide autotune {t}", flush=True)
+    assert t["candidates"] == 6 and t["tx_tile"] in (8, 16, 32) and t["order"] in (0, 1)
+    assert s.info.tx_tile == t["tx_tile"] and s.info.wide_order == t["order"]
+    s.set_initial(c0)
+    tuned = s.run(k_max=4, tol=-1.0, graph=True)
+    assert torch.equal(s.history(), h_eager)
+    assert np.allclose(tuned["res"], eager["res"], rtol=1e-12, atol=0)
+    s2 = _solver(cfg)
+    assert s2.info.tuned == 1
+    assert (s2.info.tx_tile, s2.info.wide_order, s2.info.depth_run) == \
+        (t["tx_tile"], t["order"], t["depth"])
+    s2.set_initial(c0)
+    s2.run(k_max=4, tol=-1.0)
+    assert torch.equal(s2.history(), h_eager)
+
+
+def test_tuning_table_persists_through_a_file(tmp_path):
+    """With SWR_TUNING_FILE set, swr_autotune writes its choice there and a
+    new process's handle of the same problem starts from it (two child
+    processes, one after the other)."""
+    import os
+    import subprocess
+    import sys
+    path = tmp_path / "tuning.txt"
+    env = dict(os.environ, SWR_TUNING_FILE=str(path))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    prog = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import workloads\n"
+        "from paper_1710_02401_amd import Solver\n"
+        "base = {c['name']: c for c in workloads.tiny_configs()}['tiny-1d']\n"
+        "cfg = dict(base, field=dict(base['field'], E0=0.03), factor='wide')\n"
+        "s = Solver(cfg); s.assemble(); s.set_initial()\n"
+        "if sys.argv[1] == 'tune':\n"
+        "    t = s.autotune(k_iters=2); print('TUNED', t['tx_tile'], t['order'], s.info.tuned)\n"
+        "else:\n"
+        "    print('READ', s.info.tx_tile, s.info.wide_order, s.info.tuned)\n" % root)
+    out1 = subprocess.run([sys.executable, "-c", prog, "tune"], env=env, capture_output=True,
+                          text=True, timeout=240)
+    assert out1.returncode == 0, out1.stderr[-2000:]
+    tuned = next(l for l in out1.stdout.splitlines() if l.startswith("TUNED")).split()
+    text = path.read_text()
+    assert "wide" in text and "\t" in text
+    out2 = subprocess.run([sys.executable, "-c", prog, "read"], env=env, capture_output=True,
+                          text=True, timeout=240)
+    assert out2.returncode == 0, out2.stderr[-2000:]
+    read = next(l for l in out2.stdout.splitlines() if l.startswith("READ")).split()
+    assert read[1:3] == tuned[1:3] and read[3] == "1"
