@@ -41,7 +41,7 @@ import math
 
 import numpy as np
 
-from . import gauss1d, quadrature
+from . import gauss1d, quadrature, slater
 
 
 def kron_all(mats):
@@ -59,6 +59,18 @@ class LocalSystem:
         D = dec.D
         self.sub = s
         self.D = D
+        if slater.is_slater(s):
+            # Section 2, eq. (LSD): M = T M_E T^T over the extended tensor basis
+            ext = LocalSystem(dec, slater.extended(s))
+            T = slater.transform(s)
+            for name in ("A", "Kin", "B", "W", "Q", "V"):
+                setattr(self, name, T @ getattr(ext, name) @ T.T)
+            if hasattr(ext, "Q2"):
+                self.Q2 = T @ ext.Q2 @ T.T
+            self.mu = ext.mu
+            self.Htilde = self.Kin + self.V + 0.5 * self.mu * self.B
+            self.K = s.K
+            return
         S, Kin, X, Bk, Wk = [], [], [], [], []
         for k in range(D):
             a, d = s.alpha[k], s.delta[k]
@@ -209,11 +221,18 @@ def potential_matrix(dec, s):
 
 
 def projection_rhs(dec, s):
-    """c~_l = <phi_0, v_l>_{Omega_i} for the Gaussian initial state."""
+    """c~_l = <phi_0, v_l>_{Omega_i} for the Gaussian initial state (or, in
+    the Slater basis, its antisymmetrised form)."""
     cfg = dec.cfg
     D = dec.D
     alpha0 = float(cfg["init"]["alpha"])
     cen = [float(c) for c in cfg["init"]["center"]]
+    if slater.is_slater(s):
+        ext = slater.extended(s)
+        proj = [[gauss1d.gaussian_projection(ext.alpha[k], ext.delta[k], s.lo[k], s.hi[k],
+                                             alpha0, c) for c in cen] for k in range(2)]
+        b = np.kron(proj[0][0], proj[1][1]) - np.kron(proj[0][1], proj[1][0])
+        return slater.transform(s) @ (slater.initial_norm(alpha0, cen[0], cen[1]) * b)
     norm = (2.0 * alpha0 / math.pi) ** (0.25 * D)
     vecs = [gauss1d.gaussian_projection(s.alpha[k], s.delta[k], s.lo[k], s.hi[k],
                                         alpha0, cen[k]) for k in range(D)]

@@ -110,6 +110,12 @@ class Decomposition:
                 alpha.append(cen)
                 delta.append(np.full(n, 0.5 / (sigma * sigma)))
             self.subs.append(Subdomain(lin, idx, lo, hi, alpha, delta))
+        if cfg.get("basis", "gaussian") == "slater":
+            # Section 2, eq. (LSD): antisymmetrised pairs (oracle/slater.py)
+            from . import slater
+            for s in self.subs:
+                s.slater = True
+                s.K = len(slater.pairs(s))
         for s in self.subs:
             s.faces = self._faces(s)
 

@@ -10,5 +10,6 @@ from .configs import (  # noqa: F401
     CONFIGS,
     get_config,
     random_small_configs,
+    slater_configs,
     tiny_configs,
 )

@@ -204,8 +204,18 @@ _T3 = dict(
     iters=30, tol=1e-8, face_nodes=[16, 32], quad_nodes=16,
 )
 
+# The two-electron workload in the Slater-like antisymmetric basis of
+# Section 2 (eq. (LSD)): the same decomposition, 8 Gaussians per interval
+# (64 antisymmetrised pairs off the diagonal, 28 on it), started from the
+# antisymmetrised product of two Gaussians at -1 and +1.
+_C2_SLATER = dict(_C2, name="c2-2e-1d-slater", basis="slater",
+                  init=dict(alpha=1.0, center=[-1.0, 1.0]))
+_C2_SLATER_TISE = dict(_C2_TISE, name="c2-2e-1d-slater-tise", basis="slater",
+                       init=dict(alpha=1.0, center=[-1.0, 1.0]))
+
 CONFIGS = {c["name"]: c for c in (_C1, _C2, _C2_TISE, _C3, _C3_MINI, _C3_WIDE, _C4, _C5,
-                                   _C5_K16, _C5_MINI, _C5_MINI_1E, _T1B, _T2A, _T2B, _T3)}
+                                   _C5_K16, _C5_MINI, _C5_MINI_1E, _T1B, _T2A, _T2B, _T3,
+                                   _C2_SLATER, _C2_SLATER_TISE)}
 
 
 def get_config(name, **overrides):
@@ -246,6 +256,28 @@ def tiny_configs():
               dt=0.05, n_steps=10,
               field=dict(E0=0.0, omega=0.0, phase=0.0, axis=0))
     return [copy.deepcopy(t) for t in (t1, t2, t3)]
+
+
+def slater_configs():
+    """Small workloads in the Slater-like antisymmetric Gaussian basis of
+    Section 2 (eq. (LSD)): two electrons in one dimension each on a
+    decomposition symmetric under the exchange of the two coordinates (3 x 3
+    subdomains of equal intervals, 4 Gaussians per interval: 16 functions
+    off the diagonal, 6 on it), started from the antisymmetrised product of
+    two Gaussians; real and imaginary time."""
+    t1 = dict(
+        name="tiny-slater", mode="tdse", n_elec=2, dim=1, basis="slater",
+        L=[3, 3], box_lo=[-6.0, -6.0], box_hi=[6.0, 6.0], overlap=[0.8, 0.8],
+        nbasis=[4, 4], width=None, width_ratio=0.7,
+        nuclei=[[-0.7], [0.9]], charges=[1.0, 0.8], eps_en=1.0, eps_ee=0.9,
+        dt=0.01, n_steps=8, mu=[0.5, -6.0],
+        field=dict(E0=0.2, omega=0.9, phase=0.1, axis=0),
+        init=dict(alpha=0.6, center=[-0.8, 0.9]),
+        iters=4, tol=1e-8, face_nodes=[4, 6], quad_nodes=16,
+    )
+    t2 = dict(t1, name="tiny-slater-tise", mode="tise", mu=[6.0, 0.0], dt=0.05, n_steps=10,
+              field=dict(E0=0.0, omega=0.0, phase=0.0, axis=0))
+    return [copy.deepcopy(t) for t in (t1, t2)]
 
 
 def random_small_configs(n, seed=4021):
