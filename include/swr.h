@@ -108,9 +108,26 @@ typedef struct swr_desc {
   int32_t field_shape;
   double pulse_nu, pulse_center;
   int32_t field_mask[2];
+  /* Local basis (SWR_BASIS_GAUSSIAN: tensor products of one-dimensional
+   * Gaussians, Section 2).  SWR_BASIS_SLATER, the Slater-like antisymmetric
+   * Gaussian basis of Section 2 eq. (LSD), for two electrons in one
+   * dimension each on a decomposition symmetric under the exchange of the
+   * two coordinates (equal L, box, overlap and Gaussians per interval):
+   * with phi_l the Gaussians of the first coordinate's interval and phi_p
+   * those of the second's,
+   *   v_{l,p}(x1, x2) = (phi_l(x1) phi_p(x2) - phi_l(x2) phi_p(x1)) / sqrt(2),
+   * l slowest; n^2 functions off the diagonal of the decomposition, the
+   * n(n-1)/2 with l < p on it (the same interval twice).  The initial state
+   * is then the antisymmetrised product of two Gaussians,
+   *   phi_0 = N (g_c1(x1) g_c2(x2) - g_c2(x1) g_c1(x2)),
+   *   g_c(x) = exp(-init_alpha (x - c)^2), c1, c2 = init_center[0], [1],
+   * N normalising phi_0 on the whole plane.  Narrow path only (K <= 64;
+   * the transmission is formed densely), the sine field. */
+  int32_t basis_kind;
 } swr_desc;
 
 enum { SWR_FIELD_SINE = 0, SWR_FIELD_CIRCULAR = 1 };
+enum { SWR_BASIS_GAUSSIAN = 0, SWR_BASIS_SLATER = 1 };
 
 typedef struct swr_handle_s* swr_handle;
 

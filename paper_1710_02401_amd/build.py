@@ -33,7 +33,7 @@ def build(verbose=False):
     _run(["g++", "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-c",
           os.path.join(CSRC, "geometry.cpp"), "-o", geo], verbose)
     objs.append(geo)
-    for src in ("kernels.hip", "wide.hip", "block.hip", "capi.hip", "mlp.hip"):
+    for src in ("kernels.hip", "wide.hip", "block.hip", "slater.hip", "capi.hip", "mlp.hip"):
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
         _run(["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)

@@ -18,6 +18,7 @@
 #include "../../include/swr.h"
 #include "geometry.h"
 #include "block.h"
+#include "slater.h"
 #include "kernels.h"
 
 using swr::Geometry;
@@ -333,6 +334,7 @@ struct swr_handle_s {
     it.D = g.D;
     it.n_elec = g.desc.n_elec;
     it.dim = g.desc.dim;
+    it.slater = g.desc.basis_kind == SWR_BASIS_SLATER ? 1 : 0;
     if (g.desc.field_shape == SWR_FIELD_CIRCULAR) {
       it.qmask0 = g.desc.field_mask[0];
       it.qmask1 = g.desc.field_mask[1];
@@ -1398,7 +1400,10 @@ int32_t swr_create(const swr_desc* desc, swr_handle* out) {
       s1 += (int64_t)n * n;
     }
     h->scratch_off[s] = scr;
-    if (g.desc.dim == 2) {
+    if (g.desc.basis_kind == SWR_BASIS_SLATER) {
+      // staged electron-electron term over the extended Gaussian pairs
+      scr += swr::slater_pot_scratch(g.nb[(size_t)s * 4], g.qn[(size_t)s * 4 + 1]);
+    } else if (g.desc.dim == 2) {
       int32_t nb[4], qn[4];
       for (int k = 0; k < 4; ++k) {
         nb[k] = k < g.D ? g.nb[(size_t)s * 4 + k] : 1;
@@ -1690,14 +1695,32 @@ int32_t swr_assemble(swr_handle h, void* stream) {
   const swr::Items it = h->items();
   const swr::Nodes nd = h->nodes();
   const swr::Pairs pr = h->pairs();
-  HIPCHECK(h, swr::launch_assemble(it, h->ptr<double>(h->bA), h->ptr<double>(h->bKin),
-                                   h->ptr<double>(h->bQ), it.Q2 ? h->ptr<double>(h->bQ2) : nullptr,
-                                   h->ptr<double>(h->bB), h->ptr<double>(h->bW),
-                                   h->ptr<double>(h->bS1),
-                                   h->ptr<int64_t>(h->bS1Off), g.K_max, st));
   swr::Potential pot{g.desc.n_nuc, h->ptr<double>(h->bPos), h->ptr<double>(h->bCharge),
                      g.desc.eps_en, g.desc.eps_ee};
-  if (h->wide)
+  const bool slater = g.desc.basis_kind == SWR_BASIS_SLATER;
+  if (slater) {
+    // Section 2 eq. (LSD): the antisymmetrised pairs (slater.hip)
+    HIPCHECK(h, swr::launch_slater_assemble(it, h->ptr<double>(h->bA), h->ptr<double>(h->bKin),
+                                            h->ptr<double>(h->bQ), h->ptr<double>(h->bB),
+                                            h->ptr<double>(h->bW), g.K_max, st));
+    int n_max = 1, q_max = 1;
+    for (int s = 0; s < g.n_items; ++s) {
+      n_max = std::max(n_max, (int)g.nb[(size_t)s * 4]);
+      q_max = std::max(q_max, (int)g.qn[(size_t)s * 4 + 1]);
+    }
+    HIPCHECK(h, swr::launch_slater_potential(it, pot, h->ptr<int64_t>(h->bScrOff),
+                                             h->ptr<double>(h->bScr), n_max, q_max,
+                                             h->ptr<double>(h->bV), g.K_max, st));
+  } else {
+    HIPCHECK(h, swr::launch_assemble(it, h->ptr<double>(h->bA), h->ptr<double>(h->bKin),
+                                     h->ptr<double>(h->bQ), it.Q2 ? h->ptr<double>(h->bQ2) : nullptr,
+                                     h->ptr<double>(h->bB), h->ptr<double>(h->bW),
+                                     h->ptr<double>(h->bS1),
+                                     h->ptr<int64_t>(h->bS1Off), g.K_max, st));
+  }
+  if (slater) {
+    // V assembled above
+  } else if (h->wide)
     HIPCHECK(h, swr::launch_potential_wide(it, pot, h->ptr<double>(h->bV), g.K_max, st));
   else
     HIPCHECK(h, swr::launch_potential(it, pot, h->ptr<double>(h->bS1),
@@ -1754,9 +1777,14 @@ int32_t swr_set_initial(swr_handle h, const void* c0_dev, void* stream) {
                                          h->ptr<double>(h->bCenter), h->ptr<double>(h->bScrW),
                                          h->ptr<double2>(h->bC0), h->ptr<int>(h->bFlags), st));
   } else {
-    HIPCHECK(h, swr::launch_project(it, h->ptr<double>(h->bA), h->g.desc.init_alpha,
-                                    h->ptr<double>(h->bCenter), h->ptr<double2>(h->bC0),
-                                    h->ptr<int>(h->bFlags), st));
+    if (it.slater)
+      HIPCHECK(h, swr::launch_slater_project(it, h->ptr<double>(h->bA), h->g.desc.init_alpha,
+                                             h->ptr<double>(h->bCenter), h->ptr<double2>(h->bC0),
+                                             h->ptr<int>(h->bFlags), st));
+    else
+      HIPCHECK(h, swr::launch_project(it, h->ptr<double>(h->bA), h->g.desc.init_alpha,
+                                      h->ptr<double>(h->bCenter), h->ptr<double2>(h->bC0),
+                                      h->ptr<int>(h->bFlags), st));
   }
   if (h->g.desc.mode == SWR_TISE && !h->g.desc.unnormalized)
     HIPCHECK(h, swr::launch_global_normalise(it, h->ptr<double>(h->bW), h->ptr<double2>(h->bC0),

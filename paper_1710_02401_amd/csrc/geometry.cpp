@@ -110,6 +110,23 @@ std::string build_geometry(const swr_desc& d, Geometry* g, int* code) {
   if (!(d.eps_en > 0.0) || !(d.eps_ee > 0.0)) return "soft-Coulomb eps must be > 0";
   if (!(d.width > 0.0) && !(d.width_ratio > 0.0)) return "width or width_ratio must be > 0";
   if (d.basis_extend < 0) return "basis_extend must be >= 0";
+  if (d.basis_kind != SWR_BASIS_GAUSSIAN && d.basis_kind != SWR_BASIS_SLATER)
+    return "basis_kind must be SWR_BASIS_GAUSSIAN or SWR_BASIS_SLATER";
+  if (d.basis_kind == SWR_BASIS_SLATER) {
+    if (d.n_elec != 2 || d.dim != 1)
+      return "the Slater basis is for two electrons in one dimension each";
+    if (d.per_subdomain_basis || d.nbasis[0] != d.nbasis[1] || d.nbasis[0] < 2)
+      return "the Slater basis takes one basis size (>= 2) for every interval";
+    if (d.L[0] != d.L[1] || d.box_lo[0] != d.box_lo[1] || d.box_hi[0] != d.box_hi[1] ||
+        d.overlap[0] != d.overlap[1])
+      return "the Slater basis needs a decomposition symmetric under the exchange of the coordinates";
+    if (d.field_shape != SWR_FIELD_SINE) return "the Slater basis takes the sine field";
+    if (d.factor_mode == SWR_FACTOR_WIDE || d.factor_mode == SWR_FACTOR_BLOCK)
+      return "the Slater basis runs on the narrow path (factor_mode auto or direct)";
+    if (d.n_geom != 1) return "the Slater basis takes one geometry";
+    if (!(d.init_center[0] != d.init_center[1]))
+      return "the antisymmetrised initial state needs two distinct centres";
+  }
   g->desc = d;
   g->D = D;
   int n_sub = 1;
@@ -205,6 +222,11 @@ std::string build_geometry(const swr_desc& d, Geometry* g, int* code) {
       g->qn[(size_t)s * kMaxD + k] = (int32_t)x.size();
       g->qx.insert(g->qx.end(), x.begin(), x.end());
       g->qw.insert(g->qw.end(), w.begin(), w.end());
+    }
+    if (d.basis_kind == SWR_BASIS_SLATER) {
+      // Section 2 eq. (LSD): antisymmetrised pairs; l < p on the diagonal
+      const int n = g->nb[(size_t)s * kMaxD];
+      K = g->idx[(size_t)s * kMaxD] == g->idx[(size_t)s * kMaxD + 1] ? n * (n - 1) / 2 : n * n;
     }
     g->K[s] = K;
     g->K_max = std::max(g->K_max, K);
@@ -313,7 +335,7 @@ std::string build_geometry(const swr_desc& d, Geometry* g, int* code) {
   }
 
   // factored transfer entries: runs of equal face in each pair's node list
-  g->te_ok = D <= 2;
+  g->te_ok = D <= 2 && d.basis_kind == SWR_BASIS_GAUSSIAN;
   g->te_pair.clear();
   g->te_face.clear();
   g->te_t0.clear();

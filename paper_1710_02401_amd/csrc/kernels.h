@@ -15,6 +15,8 @@ constexpr int kBlock = 256;      // threads per block of the batched kernels
 // Per-item tables (device pointers), passed by value to kernels.
 struct Items {
   int n_items, n_sub, D, n_elec, dim;
+  // 1: the Slater-like antisymmetric basis (slater.h), 0: tensor Gaussians
+  int slater;
   // configuration coordinates (bit el * dim + a) the field couples to: the
   // first (or only) component and the second of a circular field (0: none)
   int qmask0, qmask1;

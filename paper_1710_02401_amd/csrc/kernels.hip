@@ -16,6 +16,7 @@
 
 #include "devmath.h"
 #include "kernels.h"
+#include "slater.h"
 
 namespace swr {
 namespace {
@@ -386,8 +387,10 @@ __global__ void k_pot2_combine(Items it, const double* S1, const int64_t* s1off,
 }
 
 // ---------------------------------------------------------------------------
-// Basis values at a point: v_l(y) = prod_k phi_{l_k}(y_k)
+// Basis values at a point: v_l(y) = prod_k phi_{l_k}(y_k) (or the Slater
+// pair of slater.h)
 __device__ inline double basis_value(const Items& it, int s, int l, const double* y) {
+  if (it.slater) return slater_value(it, s, l, y, nullptr);
   const int32_t* nb = it.nb + 4 * s;
   int li[4];
   split_index(l, nb, it.D, li);
@@ -397,6 +400,27 @@ __device__ inline double basis_value(const Items& it, int s, int l, const double
     const double d = it.delta[4 * s + k];
     v *= exp(-d * (y[k] - a) * (y[k] - a));
   }
+  return v;
+}
+
+// v_m(y) of item j and its derivative along dimension kf.
+__device__ inline double basis_value_deriv(const Items& it, int j, int m, const double* y, int kf,
+                                           double* dv) {
+  if (it.slater) {
+    double gr[2];
+    const double v = slater_value(it, j, m, y, gr);
+    *dv = gr[kf];
+    return v;
+  }
+  int mi[4];
+  split_index(m, it.nb + 4 * j, it.D, mi);
+  double v = 1.0;
+  for (int k = 0; k < it.D; ++k) {
+    const double a = it.alpha[it.aoff[4 * j + k] + mi[k]];
+    v *= exp(-it.delta[4 * j + k] * (y[k] - a) * (y[k] - a));
+  }
+  const double aj = it.alpha[it.aoff[4 * j + kf] + mi[kf]];
+  *dv = -2.0 * it.delta[4 * j + kf] * (y[kf] - aj) * v;
   return v;
 }
 
@@ -410,9 +434,6 @@ __global__ void k_transfer(Items it, Nodes nd, Pairs pr, double mu_re, double mu
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= Ki * Kj) return;
   const int l = e / Kj, m = e % Kj;
-  const int D = it.D;
-  int mi[4];
-  split_index(m, it.nb + 4 * j, D, mi);
   double2 acc = make_double2(0.0, 0.0);
   for (int64_t t = pr.noff[p]; t < pr.noff[p + 1]; ++t) {
     const int q = pr.node[t];
@@ -421,14 +442,8 @@ __global__ void k_transfer(Items it, Nodes nd, Pairs pr, double mu_re, double mu
     const int kf = face >> 1;
     const double sign = (face & 1) ? 1.0 : -1.0;
     const double vi = basis_value(it, i, l, y);
-    double vj = 1.0;
-    for (int k = 0; k < D; ++k) {
-      const double a = it.alpha[it.aoff[4 * j + k] + mi[k]];
-      const double d = it.delta[4 * j + k];
-      vj *= exp(-d * (y[k] - a) * (y[k] - a));
-    }
-    const double aj = it.alpha[it.aoff[4 * j + kf] + mi[kf]];
-    const double dj = -2.0 * it.delta[4 * j + kf] * (y[kf] - aj) * vj;
+    double dj;
+    const double vj = basis_value_deriv(it, j, m, y, kf, &dj);
     const double c = nd.w[q] / nd.count[q] * vi;
     acc.x += c * (sign * dj + mu_re * vj);
     acc.y += c * (mu_im * vj);
@@ -2231,15 +2246,8 @@ __global__ void k_face_data(Items it, Nodes nd, const int32_t* cover, StepList s
       const int Kj = it.K[j];
       const double2* cj = hist + (int64_t)(n_steps + 1) * it.off1[j] + (int64_t)sl.step[sel] * Kj;
       for (int m = 0; m < Kj; ++m) {
-        int mi[4];
-        split_index(m, it.nb + 4 * j, it.D, mi);
-        double v = 1.0;
-        for (int k = 0; k < it.D; ++k) {
-          const double a = it.alpha[it.aoff[4 * j + k] + mi[k]];
-          v *= exp(-it.delta[4 * j + k] * (y[k] - a) * (y[k] - a));
-        }
-        const double aj = it.alpha[it.aoff[4 * j + kf] + mi[kf]];
-        const double dv = -2.0 * it.delta[4 * j + kf] * (y[kf] - aj) * v;
+        double dv;
+        const double v = basis_value_deriv(it, j, m, y, kf, &dv);
         const double2 b = make_double2(sign * dv + mu_re * v, mu_im * v);
         acc = cfma(b, cj[m], acc);
       }

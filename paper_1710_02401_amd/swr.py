@@ -19,6 +19,7 @@ SWR_TDSE, SWR_TISE = 0, 1
 SWR_WARM_PLAIN, SWR_WARM_ZERO, SWR_WARM_GIVEN = 0, 1, 2
 SWR_FACTOR_AUTO, SWR_FACTOR_DIRECT, SWR_FACTOR_WIDE, SWR_FACTOR_BLOCK = 0, 1, 2, 3
 SWR_FIELD_SINE, SWR_FIELD_CIRCULAR = 0, 1
+SWR_BASIS_GAUSSIAN, SWR_BASIS_SLATER = 0, 1
 MATRICES = {"A": 0, "Kin": 1, "V": 2, "Q": 3, "B": 4, "W": 5, "G": 6, "Q2": 7}
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
@@ -46,6 +47,7 @@ class swr_desc(ctypes.Structure):
         ("factor_mode", ctypes.c_int32), ("unnormalized", ctypes.c_int32),
         ("field_shape", ctypes.c_int32), ("pulse_nu", ctypes.c_double),
         ("pulse_center", ctypes.c_double), ("field_mask", ctypes.c_int32 * 2),
+        ("basis_kind", ctypes.c_int32),
     ]
 
 
@@ -234,6 +236,8 @@ def desc_from_config(cfg):
     d.factor_mode = {"auto": SWR_FACTOR_AUTO, "direct": SWR_FACTOR_DIRECT,
                      "wide": SWR_FACTOR_WIDE, "block": SWR_FACTOR_BLOCK}[cfg.get("factor", "auto")]
     d.unnormalized = 1 if cfg.get("unnormalized", False) else 0
+    d.basis_kind = {"gaussian": SWR_BASIS_GAUSSIAN,
+                    "slater": SWR_BASIS_SLATER}[cfg.get("basis", "gaussian")]
     return d, (arr, pos, chg)
 
 

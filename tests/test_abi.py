@@ -169,9 +169,10 @@ def _oracle_maps(dec):
     return np.array(rows, dtype=np.int32)
 
 
-@pytest.mark.parametrize("name", ["tiny-1d", "tiny-2d", "c1-1e-1d", "c2-2e-1d"])
+@pytest.mark.parametrize("name", ["tiny-1d", "tiny-2d", "c1-1e-1d", "c2-2e-1d", "tiny-slater",
+                                  "c2-2e-1d-slater"])
 def test_index_maps_and_boxes_bit_exact(S, name):
-    cfgs = {c["name"]: c for c in workloads.tiny_configs()}
+    cfgs = {c["name"]: c for c in workloads.tiny_configs() + workloads.slater_configs()}
     cfg = cfgs.get(name) or workloads.get_config(name)
     lib = S.load_library()
     rc, h = _create(S, cfg)
@@ -306,6 +307,27 @@ def test_wide_bases_need_the_series(S, mutate):
     rc, h = _create(S, cfg)
     assert rc == -2
     assert b"field series" in S.load_library().swr_last_error(None)
+
+
+def test_slater_basis_needs_an_exchange_symmetric_two_electron_problem(S):
+    """The Slater-like basis (Section 2, eq. (LSD)) is for two electrons in
+    one dimension each on a decomposition symmetric under their exchange;
+    every other description is refused with the reason."""
+    lib = S.load_library()
+    base = workloads.slater_configs()[0]
+    rc, h = _create(S, base)
+    assert rc == 0
+    lib.swr_destroy(h)
+    for bad, why in [(dict(L=[3, 2]), "symmetric"), (dict(nbasis=[4, 3]), "one basis size"),
+                     (dict(overlap=[0.8, 0.7]), "symmetric"),
+                     (dict(factor="wide"), "narrow path"),
+                     (dict(init=dict(alpha=0.6, center=[0.5, 0.5])), "distinct centres")]:
+        rc, h = _create(S, dict(base, **bad))
+        assert rc == S.SWR_E_ARG, bad
+        assert why in lib.swr_last_error(None).decode(), bad
+    one = dict(TINY["tiny-1d"], basis="slater")
+    rc, h = _create(S, one)
+    assert rc == S.SWR_E_ARG and "two electrons" in lib.swr_last_error(None).decode()
 
 
 @pytest.mark.parametrize("name,extra", [("tiny-1d", {}), ("tiny-2d", {}),
