@@ -49,12 +49,12 @@ MEASURED_TRAFFIC = {
     # (1 GiB copy calibration) over the first window at depth 4 with the
     # 32-step transmission tile: 23 recurrence launches, 24 transmissions,
     # one factorisation
-    "k_cn_recur": {"kernels_sha256": "5fc6438905beeb77", "bytes_per_launch": 2.1760e9},
-    # per transmission tile: 32 steps at depth 4 as above; 16 steps (the
-    # autotuned choice) from the same counters over an autotuned run
-    "k_tx_send+k_tx_recv": {"kernels_sha256": "5fc6438905beeb77",
-                            "bytes_per_launch_by_tile": {32: 0.4583e9, 16: 0.4672e9}},
-    "k_series_assemble": {"kernels_sha256": "5fc6438905beeb77", "bytes_per_launch": 2.4357e9},
+    "k_cn_recur": {"kernels_sha256": "516c28280c7721aa", "bytes_per_launch": 2.1760e9},
+    # per transmission tile: 32 steps at depth 4 as above (the 16-step tile
+    # is not measured on this source)
+    "k_tx_send+k_tx_recv": {"kernels_sha256": "516c28280c7721aa",
+                            "bytes_per_launch_by_tile": {32: 0.4614e9}},
+    "k_series_assemble": {"kernels_sha256": "516c28280c7721aa", "bytes_per_launch": 2.4357e9},
     # profiles/c3-1e-1d-batched_traffic.md: one sweep of the batched workload
     "k_cn_recur_wide": {"wide_sha256": "8b17b20586e217b0", "bytes_per_launch": 1350.81e9},
     # profiles/c5-2e-2d_traffic.md: median over the 529 step launches of one
@@ -203,6 +203,46 @@ def batched_summary(iters, cpu=True):
     if cpu:
         out["cpu_baseline"] = batched_cpu_baseline(cfg)
     return out
+
+
+def slater_summary(iters=20):
+    """The two-electron window in the Slater-like antisymmetric basis of
+    Section 2 (eq. (LSD)): the same 8 x 8 decomposition and 1000 steps, 64
+    antisymmetrised pairs per subdomain off the diagonal and 28 on it, from
+    the antisymmetrised Gaussian pair; 20 Schwarz iterations after an
+    untimed window, the schedule autotuned (the transmission is formed
+    densely: the basis is not a tensor product)."""
+    import torch
+
+    import workloads
+    from paper_1710_02401_amd import Solver
+    cfg = workloads.get_config("c2-2e-1d-slater")
+    s = Solver(cfg)
+    s.assemble()
+    s.set_initial()
+    torch.cuda.synchronize()
+    c0 = s.initial().clone()
+    s.autotune(k_iters=2)
+    s.set_initial(c0)
+    s.run(k_max=iters, tol=-1.0, graph=True)
+    s.set_initial(c0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    st = s.run(k_max=iters, tol=-1.0, graph=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    s.set_initial(c0)
+    kern = s.run(k_max=iters, tol=-1.0, timing=True)["kernels"]
+    n = int(s.info.n_items)
+    return {
+        "workload": f"{cfg['name']}: 2 electrons x 1-D, {n} subdomains, K={int(s.K.min())}.."
+                    f"{int(s.K.max())} antisymmetrised Gaussian pairs, {int(s.n_steps)} steps, "
+                    f"{iters} Schwarz iterations, depth {int(s.info.depth_run)}",
+        "value": n * iters / wall, "unit": "subdomain-solves/s", "ms_per_window": 1e3 * wall,
+        "kernels_ms_per_window": {k: kern[k]["ms"] for k in ("factor", "transmit", "recur",
+                                                              "residual")},
+        "last_residual": st["res"][iters - 1],
+    }
 
 
 def tise_summary(iters=20):
@@ -653,6 +693,7 @@ def main():
     out["paper_literal_sweep_ms"] = lit["factor"]["ms"] + per_it
     out["wavefront_ms_per_iteration"] = ms_step / iters
     out["imaginary_time"] = tise_summary()
+    out["slater_basis"] = slater_summary()
     if args.batched_iters > 0:
         del s
         torch.cuda.empty_cache()
