@@ -39,6 +39,8 @@ sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
+# FP64 vector FMA issue: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz
+FP64_VALU_PEAK_TFS = 78.6
 
 # HBM traffic of the dominant kernel from rocprofv3 counters (FETCH_SIZE and
 # WRITE_SIZE, each scaled by the ratio of a plain device copy's known bytes
@@ -47,14 +49,13 @@ FP64_PEAK_TFS = 78.6
 MEASURED_TRAFFIC = {
     # profiles/c2-2e-1d_traffic.md: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000
     # (1 GiB copy calibration) over the first window at depth 4 with the
-    # 32-step transmission tile: 23 recurrence launches, 24 transmissions,
-    # one factorisation
-    "k_cn_recur": {"kernels_sha256": "516c28280c7721aa", "bytes_per_launch": 2.1760e9},
+    # 32-step transmission tile: 23 recurrence launches (the series evaluated
+    # in the step), 26 transmissions, one factorisation
+    "k_cn_recur_series": {"kernels_sha256": "1554c7afb0c7800d", "bytes_per_launch": 0.22198e9},
     # per transmission tile: 32 steps at depth 4 as above (the 16-step tile
     # is not measured on this source)
-    "k_tx_send+k_tx_recv": {"kernels_sha256": "516c28280c7721aa",
-                            "bytes_per_launch_by_tile": {32: 0.4614e9}},
-    "k_series_assemble": {"kernels_sha256": "516c28280c7721aa", "bytes_per_launch": 2.4357e9},
+    "k_tx_send+k_tx_recv": {"kernels_sha256": "1554c7afb0c7800d",
+                            "bytes_per_launch_by_tile": {32: 0.4513e9}},
     # profiles/c3-1e-1d-batched_traffic.md: one sweep of the batched workload
     "k_cn_recur_wide": {"wide_sha256": "8b17b20586e217b0", "bytes_per_launch": 1350.81e9},
     # profiles/c5-2e-2d_traffic.md: median over the 529 step launches of one
@@ -622,20 +623,39 @@ def main():
             for k in ("factor", "transmit", "recur", "residual")}
     # algorithmic work per window of each kernel class
     series = s.factor_terms() >= 0
+    rec_series = s.rec_series()
+    n_terms = s.factor_terms() + 1
+    n_chunks = -(-nT // 128)
     inv_flops = n_sub * nT * 8.0 * K ** 3                    # complex Gauss-Jordan inverses
     inv_bytes = n_sub * nT * 16.0 * K * (K + 1) / 2          # symmetric inverses written
+    # per (item, chunk): the anchor's inverse, its compensated residual and
+    # refinement (8 K^3 each), G = i tau P_0 Q (4 K^3) and the further terms
+    ser_flops = n_sub * n_chunks * (32.0 + 8.0 * (n_terms - 1)) * K ** 3
     # per (item, step): the symmetric inverse's K(K+1)/2 entries, f^{n+1}, c^{n+1}
     rec_bytes = iters * n_sub * nT * (16.0 * K * (K + 1) / 2 + 32.0 * K)
+    # series evaluated in the step, per (item, step) and entry: S2 c (4
+    # flops), Horner over the terms (4 per term after the first) and the
+    # complex product (8)
+    rec_flops = iters * n_sub * nT * (8.0 + 4.0 * n_terms) * K * K
     hist_bytes = n_sub * (nT + 1) * K * 16.0
     # Robin data (+ residual partials): read iterate and previous iterate, write f
     tx_bytes = (iters + 1) * 3.0 * hist_bytes
+    if rec_series:
+        factor_roof = dict(kernel="k_invert_mfma+k_series_residual+k_series_product",
+                           bound="mfma", achieved=ser_flops / 1e12, peak=FP64_PEAK_TFS,
+                           unit="TFLOP/s")
+        recur_roof = dict(kernel="k_cn_recur_series", bound="alu", achieved=rec_flops / 1e12,
+                          peak=FP64_VALU_PEAK_TFS, unit="TFLOP/s")
+    else:
+        factor_roof = (dict(kernel="k_series_assemble", bound="hbm", achieved=inv_bytes / 1e9,
+                            peak=HBM_PEAK_GBS, unit="GB/s") if series else
+                       dict(kernel="k_invert_mfma", bound="mfma", achieved=inv_flops / 1e12,
+                            peak=FP64_PEAK_TFS, unit="TFLOP/s"))
+        recur_roof = dict(kernel="k_cn_recur", bound="hbm", achieved=rec_bytes / 1e9,
+                          peak=HBM_PEAK_GBS, unit="GB/s")
     roofs = {
-        "factor": (dict(kernel="k_series_assemble", bound="hbm", achieved=inv_bytes / 1e9,
-                        peak=HBM_PEAK_GBS, unit="GB/s") if series else
-                   dict(kernel="k_invert_mfma", bound="mfma", achieved=inv_flops / 1e12,
-                        peak=FP64_PEAK_TFS, unit="TFLOP/s")),
-        "recur": dict(kernel="k_cn_recur", bound="hbm", achieved=rec_bytes / 1e9,
-                      peak=HBM_PEAK_GBS, unit="GB/s"),
+        "factor": factor_roof,
+        "recur": recur_roof,
         "transmit": dict(kernel="k_tx_send+k_tx_recv", bound="hbm", achieved=tx_bytes / 1e9,
                          peak=HBM_PEAK_GBS, unit="GB/s"),
         "residual": dict(kernel="k_res_reduce", bound="alu", achieved=None,
@@ -680,6 +700,7 @@ def main():
                    "autotuned": tuning is not None},
         "roofline": roofline,
         "factor_series_terms": s.factor_terms() + 1,
+        "series_in_step": rec_series,
         "kernels_per_window": roofs,
         "windows_launched_as": "eager" if args.no_graph else "hip_graph",
         "sweep_ms_per_iteration": ms_step / iters,

@@ -155,6 +155,9 @@ typedef struct swr_info {
                                 largest K first, 1 item order                */
   int32_t tuned;             /* 1: the schedule was taken from the tuning
                                 table at swr_assemble (see swr_autotune)     */
+  int32_t rec_series;        /* 1: the last swr_factor's series is evaluated
+                                in each recurrence step (no per-step inverses
+                                are formed; see swr_factor)                  */
 } swr_info;
 
 /* ---- lifetime ------------------------------------------------------------*/
@@ -224,7 +227,12 @@ int32_t swr_warm_start(swr_handle h, int32_t mode, const void* g_dev, void* stre
  * X = max over items of sum_m max |x_m| along the field axis on the item's
  * box, and the tail after K is at most rho^{K+1}/(1-rho); K is the least
  * with that bound <= 2^-53 (reported in swr_info.factor_terms).  With
- * Im mu > 0, K > 7, or SWR_FACTOR_DIRECT, every M^n is inverted.
+ * K <= 3 the inverses are not formed: the recurrence keeps each chunk's
+ * terms (M_a^{-1} C)^k M_a^{-1} and evaluates the sum in every step, entry
+ * by entry in the same order of operations as the formed inverses, so the
+ * result is the same (swr_info.rec_series); with K = 4..7 the inverses of
+ * every step are formed from the sum.  With Im mu > 0, K > 7, or
+ * SWR_FACTOR_DIRECT, every M^n is inverted.
  * Wide-basis path (one electron in one dimension, real time; taken when some
  * K > 64, or asked for with SWR_FACTOR_WIDE): the inverses of the steps are
  * never formed.  Per chunk the library keeps M_a^{-1} (Gauss-Jordan, then

@@ -235,8 +235,9 @@ struct swr_handle_s {
   std::vector<int64_t> te_blob_off;  // per-sender blob offsets (complex units)
   // TDSE series inverses, per chunk of kSeriesChunk steps: G then P_0 ..
   // P_{kSeriesMaxTerms-1}, each sum_K2 complex; the chunks' anchor fields
-  Buf bSeries, bEanchor;
+  Buf bSeries, bEanchor, bDser;
   std::vector<double> Ea_host;
+  std::vector<double> D_host;  // E_c - E_{n+1} per step n of chunk c (series recurrence)
   // wide-basis path (D = 1, K <= kWideK): S2 = Ar + Ap packed, the series
   // terms packed (per chunk kWideTerms slots of the packed size), a K^2
   // scratch (projection, S2 before packing), the items by decreasing K,
@@ -261,6 +262,14 @@ struct swr_handle_s {
   std::vector<int32_t> terms_item;   // wide path: series terms each item needs
   Buf bTermsW;
   int factor_terms = -1;    // series terms - 1 of the last swr_factor; -1: direct
+  // the recurrence evaluates the series in the step (terms <= kRecSeriesMax,
+  // narrow path): the per-step inverses are not assembled
+  bool rec_series = false;
+  swr::RecSeries rec_se() {
+    const int64_t cstride = (int64_t)(kSeriesMaxTerms + 1) * sum_K2;
+    return swr::RecSeries{ptr<double2>(bSeries) + sum_K2, sum_K2, cstride, ptr<double>(bDser),
+                          factor_terms + 1};
+  }
   int nbt = 1;      // largest tangential basis size (factored transmission)
   int64_t te_pieces = 0;  // largest LDS bytes of the pieces one item sends
   int te_max_recv = 0;    // largest number of entries one item receives
@@ -591,7 +600,10 @@ void plan_layout(swr_handle h) {
     if (g.desc.mode == SWR_TDSE)
       h->bSeries = L.add((size_t)n_chunks * (kSeriesMaxTerms + 1) * h->sum_K2 * 16);
   }
-  if (g.desc.mode == SWR_TDSE) h->bEanchor = L.add((size_t)n_chunks * 8);
+  if (g.desc.mode == SWR_TDSE) {
+    h->bEanchor = L.add((size_t)n_chunks * 8);
+    h->bDser = L.add((size_t)h->n_mats * 8);
+  }
   h->bE = L.add((h->n_T + 1) * 8);
   h->bResPart = L.add((size_t)h->n_res_tiles * NI * 8);
   h->bResOut = L.add(8);
@@ -1531,6 +1543,7 @@ int32_t swr_query(swr_handle h, swr_info* info) {
   r.tx_tile = h->block ? 0 : h->wide ? h->wide_tile : (h->g.te_ok ? h->tx_tt : 0);
   r.wide_order = h->wide_order;
   r.tuned = h->tuned_cached ? 1 : 0;
+  r.rec_series = h->rec_series ? 1 : 0;
   r.wide = h->wide ? 1 : 0;
   r.block = h->block ? 1 : 0;
   r.depth_run = h->depth_run;
@@ -1900,6 +1913,14 @@ int32_t swr_factor(swr_handle h, double t0, void* stream) {
     return fail(h, SWR_E_SIZE, "the field varies too much within a chunk for the wide-basis "
                                "series (more than 6 terms)");
   if (terms > 0) HIPCHECK(h, upload(h, h->bEanchor, h->Ea_host, st));
+  if (!h->wide && terms > 0 && terms <= swr::kRecSeriesMax) {
+    // the offsets of the series evaluated in the step, rounded as the
+    // assembly of the inverses rounds them
+    h->D_host.resize(h->n_mats);
+    for (int64_t n = 0; n < h->n_mats; ++n)
+      h->D_host[n] = h->Ea_host[n / swr::kSeriesChunk] - h->E_host[n + 1];
+    HIPCHECK(h, upload(h, h->bDser, h->D_host, st));
+  }
   if (h->wide) HIPCHECK(h, upload(h, h->bTermsW, h->terms_item, st));
   HIPCHECK(h, tbegin(h, st, kTFactor));
   if (h->wide) {
@@ -1951,9 +1972,11 @@ int32_t swr_factor(swr_handle h, double t0, void* stream) {
       HIPCHECK(h, swr::launch_series_product(it, n_chunks, G, P + (k - 1) * h->sum_K2, nullptr,
                                              make_double2(1.0, 0.0), nullptr, cstride,
                                              P + k * h->sum_K2, st));
-    HIPCHECK(h, swr::launch_series_assemble(it, h->n_mats, terms, P, h->sum_K2, cstride,
-                                            h->ptr<double>(h->bE), h->ptr<double>(h->bEanchor),
-                                            h->ptr<double2>(h->bMinv), st));
+    if (terms > swr::kRecSeriesMax)
+      HIPCHECK(h, swr::launch_series_assemble(it, h->n_mats, terms, P, h->sum_K2, cstride,
+                                              h->ptr<double>(h->bE),
+                                              h->ptr<double>(h->bEanchor),
+                                              h->ptr<double2>(h->bMinv), st));
   } else {
     HIPCHECK(h, swr::launch_invert(it, h->n_mats, h->ptr<double>(h->bAr), h->ptr<double>(h->bHr),
                                    h->ptr<double>(h->bQ), h->ptr<double>(h->bE), 0, tau,
@@ -1962,6 +1985,7 @@ int32_t swr_factor(swr_handle h, double t0, void* stream) {
   }
   HIPCHECK(h, tend(h, st));
   h->factor_terms = terms - 1;
+  h->rec_series = !h->wide && terms > 0 && terms <= swr::kRecSeriesMax;
   h->factored = true;
   h->t0 = t0;
   return SWR_OK;
@@ -2003,11 +2027,12 @@ int32_t swr_sweep(swr_handle h, void* stream) {
     jobs.n_lo[0] = 0;
     jobs.n_cnt[0] = nT;
     HIPCHECK(h, tbegin(h, st, kTRecur));
+    const swr::RecSeries se = h->rec_se();
     HIPCHECK(h, swr::launch_cn_recur(it, nT, h->ptr<double>(h->bAr), h->ptr<double>(h->bAp),
                                      h->ptr<double>(h->bHr), h->ptr<double>(h->bQ),
                                      h->ptr<double>(h->bE), 0.5 * h->g.desc.dt,
-                                     h->ptr<double2>(h->bMinv), h->ptr<double2>(h->bC0), jobs,
-                                     h->ptr<int>(h->bFlags), st));
+                                     h->ptr<double2>(h->bMinv), h->rec_series ? &se : nullptr,
+                                     h->ptr<double2>(h->bC0), jobs, h->ptr<int>(h->bFlags), st));
     HIPCHECK(h, tend(h, st));
   } else {
     // step 0 of every item is the (normalised) initial state
@@ -2265,11 +2290,13 @@ int32_t run_pipelined(swr_handle h, const swr_run_opts* o, int P, swr_run_stats*
       if (rc) return rc;
     } else {
       HIPCHECK(h, tbegin(h, st, kTRecur));
+      const swr::RecSeries se = h->rec_se();
       HIPCHECK(h, swr::launch_cn_recur(it, nT, h->ptr<double>(h->bAr), h->ptr<double>(h->bAp),
                                        h->ptr<double>(h->bHr), h->ptr<double>(h->bQ),
                                        h->ptr<double>(h->bE), 0.5 * h->g.desc.dt,
-                                       h->ptr<double2>(h->bMinv), h->ptr<double2>(h->bC0), rec,
-                                       h->ptr<int>(h->bFlags), st));
+                                       h->ptr<double2>(h->bMinv), h->rec_series ? &se : nullptr,
+                                       h->ptr<double2>(h->bC0), rec, h->ptr<int>(h->bFlags),
+                                       st));
       HIPCHECK(h, tend(h, st));
     }
     if (res_now) {

@@ -232,10 +232,25 @@ hipError_t launch_series_residual(const Items& it, int n_chunks, const double* A
 hipError_t launch_series_assemble(const Items& it, int n_mats, int terms, const double2* P,
                                   int64_t stride, int64_t cstride, const double* Efield,
                                   const double* Eanchor, double2* Minv, hipStream_t st);
+// The field series of a window as the recurrence reads it: chunk c's P_k at
+// P + c cstride + k stride + the item's K^2 offset (K x K row-major); D[n] =
+// E_c - E_{n+1} for step n of chunk c (the anchor field minus the step's).
+struct RecSeries {
+  const double2* P;
+  int64_t stride, cstride;
+  const double* D;
+  int terms;
+};
+// Most series terms the recurrence evaluates in the step (registers); with
+// more, the inverses are assembled and read.
+constexpr int kRecSeriesMax = 4;
+// Crank-Nicolson recurrence of the jobs: with se, each step's inverse is
+// evaluated from the series (1 <= se->terms <= kRecSeriesMax, one field
+// component); else read from Minv (packed, every step).
 hipError_t launch_cn_recur(const Items& it, int n_steps, const double* Ar, const double* Ap,
                            const double* Hr, const double* Q, const double* Efield, double tau,
-                           const double2* Minv, const double2* c0, const RecJobs& jobs, int* flags,
-                           hipStream_t st);
+                           const double2* Minv, const RecSeries* se, const double2* c0,
+                           const RecJobs& jobs, int* flags, hipStream_t st);
 hipError_t launch_sum_sqrt(const double* partial, int64_t n, double* out, hipStream_t st);
 hipError_t launch_transfer_tensor(const Items& it, const Nodes& nd, const Pairs& pr,
                                   const TEnt& te, double mu_re, double mu_im, double* beta,

@@ -1262,6 +1262,249 @@ __global__ void __launch_bounds__(kRecThreads) k_cn_recur(Items it, int n_steps,
 }
 
 // ---------------------------------------------------------------------------
+// The same recurrence with each step's inverse evaluated from the field
+// series inside the step instead of read from HBM.  The chunk's terms
+// P_0 .. P_{NT-1} at this thread's eight entries (row r, columns 8 j + part)
+// stay in registers while the block walks the chunk's steps, and step n forms
+// (M^{n+1})^{-1} entry by entry by Horner in d = E_c - E_{n+1}, as the packed
+// assembly does: the same entries (a tile below the diagonal takes the
+// transposed entry of the tile above it), the same operations in the same
+// order, so the result is the one the stored inverses give.  HBM carries per
+// step only the Robin data vector in and the coefficients out; the terms are
+// read once per chunk of kSeriesChunk steps.  The Robin data and the
+// offsets d (formed once per window, E_c - E_{n+1} rounded as the assembly
+// rounds it) of kRecTile steps are staged in LDS one tile ahead; tiles are
+// aligned to multiples of kRecTile, so every chunk starts on a tile.
+constexpr int kRecTile = 16;
+static_assert(kSeriesChunk % kRecTile == 0, "chunks start on tiles");
+
+// Pi: the chunk's P_0 at the item (uniform); entries by 32-bit lane offsets
+// (a 64-bit address per entry and term would be kept live across the loop)
+template <int NT>
+__device__ inline void load_terms(double2 (&p)[NT][8], const double2* Pi, int64_t stride, int K,
+                                  int r, int part) {
+  const int rr = r < K ? r : K - 1;
+  const int I = rr >> 3;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int m = 8 * j + part;
+    const int mm = m < K ? m : K - 1;
+    const unsigned e = j >= I ? (unsigned)(rr * K + mm) : (unsigned)(mm * K + rr);
+    // columns past K hold column K-1's (finite) entries: they meet the zero
+    // padding of the LDS vector
+#pragma unroll
+    for (int k = 0; k < NT; ++k) p[k][j] = (Pi + k * stride)[e];
+  }
+}
+
+// Staging registers of one tile: Robin data f^{n+1} of the tile's steps at
+// two (step, row) entries of this thread, and d of step tid (tid < kRecTile).
+// (Named fields, not an array: an array here is kept in scratch memory.)
+struct RecTileRegs {
+  double2 f0, f1;
+  double d;
+};
+static_assert(kRecTile * kSmallK == 2 * kRecThreads, "two staged entries per thread");
+
+__device__ inline double2 tile_entry(const double2* F, int64_t hb, int T, int e, int n_lo,
+                                     int n_end, int K) {
+  int n = T * kRecTile + (e >> 6);
+  n = n < n_lo ? n_lo : (n < n_end ? n : n_end - 1);
+  const int row = e & 63;
+  return F[hb + (int64_t)(n + 1) * K + (row < K ? row : K - 1)];
+}
+
+__device__ inline void load_tile(RecTileRegs& tr, const double2* F, int64_t hb, int T, int n_lo,
+                                 int n_end, int K, const double* D) {
+  tr.f0 = tile_entry(F, hb, T, threadIdx.x, n_lo, n_end, K);
+  tr.f1 = tile_entry(F, hb, T, threadIdx.x + kRecThreads, n_lo, n_end, K);
+  int n = T * kRecTile + (threadIdx.x & (kRecTile - 1));
+  n = n < n_lo ? n_lo : (n < n_end ? n : n_end - 1);
+  tr.d = D[n];
+}
+
+__device__ inline void store_tile(const RecTileRegs& tr, double2 (*sf)[kSmallK], double* sd) {
+  const int e0 = threadIdx.x, e1 = threadIdx.x + kRecThreads;
+  sf[e0 >> 6][e0 & 63] = tr.f0;
+  sf[e1 >> 6][e1 & 63] = tr.f1;
+  // every thread holds d of step threadIdx.x % kRecTile: equal values, and
+  // no branch (a store under a branch makes the memory waits conservative)
+  sd[threadIdx.x & (kRecTile - 1)] = tr.d;
+}
+
+template <int NT>
+__device__ inline void cn_step_series(RecState& st, const double2 (&p)[NT][8], double d,
+                                      double2 fn, int K, int r, int part, double tau,
+                                      double2* shrow, double2* sc, double2* srhs, bool& bad) {
+  double ax = 0.0, ay = 0.0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    ax = fma(st.s2[j], st.cm[j].x, ax);
+    ay = fma(st.s2[j], st.cm[j].y, ay);
+  }
+  ax = group8_sum(ax);
+  ay = group8_sum(ay);
+  const double2 fs = cadd(st.fprev, fn);
+  st.fprev = fn;
+  const double2 rhs = make_double2(fma(-0.5 * tau, fs.y, ax - st.rprev.x),
+                                   fma(0.5 * tau, fs.x, ay - st.rprev.y));
+  st.rprev = rhs;
+  if (r < K) srhs[vpos(r)] = rhs;
+  __syncthreads();
+  double ox = 0.0, oy = 0.0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    double mx = p[NT - 1][j].x, my = p[NT - 1][j].y;
+#pragma unroll
+    for (int k = NT - 2; k >= 0; --k) {
+      mx = fma(d, mx, p[k][j].x);
+      my = fma(d, my, p[k][j].y);
+    }
+    const double2 rm = srhs[j * 9 + part];  // zero padded past K
+    ox = fma(mx, rm.x, fma(-my, rm.y, ox));
+    oy = fma(mx, rm.y, fma(my, rm.x, oy));
+  }
+  ox = group8_sum(ox);
+  oy = group8_sum(oy);
+  const double2 v = make_double2(ox, oy);
+  if (r < K) sc[vpos(r)] = v;
+  // padding rows hold row K-1's entries: their value is row K-1's
+  if (part == 0) *shrow = v;
+  bad |= !cfinite(v);
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 8; ++j) st.cm[j] = sc[j * 9 + part];
+}
+
+// The coefficients of tile T's steps (staged in LDS by the steps) to the
+// history: two entries per thread, unconditional; entries outside the job's
+// steps or past K take the nearest valid entry of the tile (the same value
+// written twice).
+__device__ inline void flush_tile(double2* hist, int64_t hb, const double2 (*sh)[kSmallK], int T,
+                                  int n_lo, int n_end, int K) {
+  const int lo = T * kRecTile > n_lo ? T * kRecTile : n_lo;
+  const int hi = (T + 1) * kRecTile < n_end ? (T + 1) * kRecTile : n_end;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int e = threadIdx.x + h * kRecThreads;
+    int n = T * kRecTile + (e >> 6);
+    n = n < lo ? lo : (n < hi ? n : hi - 1);
+    const int row = (e & 63) < K ? (e & 63) : K - 1;
+    hist[hb + (int64_t)(n + 1) * K + row] = sh[n - T * kRecTile][row];
+  }
+}
+
+template <int NT>
+__global__ void __launch_bounds__(kRecThreads)
+    k_cn_recur_series(Items it, int n_steps, const double* Ar, const double* Ap, const double* Hr,
+                      const double* Q, const double* Eall, double tau, RecSeries se,
+                      const double2* c0, RecJobs jobs, int* flags) {
+  const int s = blockIdx.x;
+  const int job = blockIdx.y;
+  const int K = it.K[s];
+  const int n_lo = jobs.n_lo[job];
+  const int n_end = n_lo + jobs.n_cnt[job];
+  double2* hist = jobs.hist[job];
+  const double2* F = jobs.F[job];
+  double2* carry = jobs.carry[job];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int part = lane & 7;
+  const int r = wave * 8 + (lane >> 3);
+  __shared__ double2 sc[kVecPad];
+  __shared__ double2 srhs[kVecPad];
+  __shared__ double2 sf[2][kRecTile][kSmallK];
+  __shared__ double2 sh[2][kRecTile][kSmallK];
+  __shared__ double sd[2][kRecTile];
+  const int64_t o2 = it.off2[s];
+  const int64_t hb = (int64_t)(n_steps + 1) * it.off1[s];
+  const int rr = r < K ? r : K - 1;
+  RecState st;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int m = 8 * j + part;
+    const bool v = r < K && m < K;
+    const int64_t e = o2 + (v ? (int64_t)m * K + r : 0);
+    st.s2[j] = v ? Ar[e] + Ap[e] : 0.0;
+  }
+  st.fprev = F[hb + (int64_t)n_lo * K + rr];
+  const bool use_carry = n_lo > 0 && carry != nullptr;
+  if (threadIdx.x < K) {
+    double2 v;
+    if (n_lo == 0) {
+      v = c0[it.off1[s] + threadIdx.x];
+      hist[hb + threadIdx.x] = v;
+    } else {
+      v = hist[hb + (int64_t)n_lo * K + threadIdx.x];
+    }
+    sc[vpos(threadIdx.x)] = v;
+    if (use_carry) srhs[vpos(threadIdx.x)] = carry[it.off1[s] + threadIdx.x];
+  } else if (threadIdx.x < kSmallK) {
+    sc[vpos(threadIdx.x)] = make_double2(0.0, 0.0);
+    srhs[vpos(threadIdx.x)] = make_double2(0.0, 0.0);
+  }
+  int T = n_lo / kRecTile;
+  RecTileRegs tr;
+  load_tile(tr, F, hb, T, n_lo, n_end, K, se.D);
+  double2 p[NT][8];
+  load_terms<NT>(p, se.P + (int64_t)(n_lo / kSeriesChunk) * se.cstride + o2, se.stride, K, r,
+                 part);
+  store_tile(tr, sf[0], sd[0]);
+  load_tile(tr, F, hb, T + 1, n_lo, n_end, K, se.D);
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 8; ++j) st.cm[j] = sc[j * 9 + part];
+  if (use_carry) {
+    st.rprev = r < K ? srhs[vpos(r)] : make_double2(0.0, 0.0);
+  } else {
+    // M^{n_lo} c^{n_lo} = Ar c + i tau (Hr + E Q) c (the series path has one field)
+    const double E = Eall[n_lo];
+    double ax = 0.0, ay = 0.0, hx = 0.0, hy = 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int m = 8 * j + part;
+      const bool v = r < K && m < K;
+      const int64_t e = o2 + (v ? (int64_t)m * K + r : 0);
+      const double a = v ? Ar[e] : 0.0;
+      const double h = v ? fma(E, Q[e], Hr[e]) : 0.0;
+      ax = fma(a, st.cm[j].x, ax);
+      ay = fma(a, st.cm[j].y, ay);
+      hx = fma(h, st.cm[j].x, hx);
+      hy = fma(h, st.cm[j].y, hy);
+    }
+    st.rprev = make_double2(group8_sum(fma(-tau, hy, ax)), group8_sum(fma(tau, hx, ay)));
+  }
+  bool bad = false;
+  int buf = 0;
+  int n = n_lo;
+  // Global memory is touched only between tiles, in an order that keeps
+  // every wait the compiler inserts on older operations: the staged tile
+  // (loaded a tile ago) to LDS, the chunk's terms at a chunk start, the loads
+  // of the tile after next, then the finished tile's coefficients out.  No
+  // step waits on a load or a store.
+  while (true) {
+    const int te = (T + 1) * kRecTile < n_end ? (T + 1) * kRecTile : n_end;
+    for (; n < te; ++n) {
+      const int q = n - T * kRecTile;
+      cn_step_series<NT>(st, p, sd[buf][q], sf[buf][q][r], K, r, part, tau, &sh[buf][q][r], sc,
+                         srhs, bad);
+    }
+    if (n >= n_end) break;
+    store_tile(tr, sf[buf ^ 1], sd[buf ^ 1]);
+    if (n % kSeriesChunk == 0)
+      load_terms<NT>(p, se.P + (int64_t)(n / kSeriesChunk) * se.cstride + o2, se.stride, K, r,
+                     part);
+    load_tile(tr, F, hb, T + 2, n_lo, n_end, K, se.D);
+    flush_tile(hist, hb, sh[buf], T, n_lo, n_end, K);
+    ++T;
+    buf ^= 1;
+    __syncthreads();
+  }
+  flush_tile(hist, hb, sh[buf], T, n_lo, n_end, K);
+  if (carry && part == 0 && r < K) carry[it.off1[s] + r] = st.rprev;
+  if (bad) atomicOr(flags, kFlagNaN);
+}
+
+// ---------------------------------------------------------------------------
 // Transmission as a batched complex product: for receiving item i and a tile
 // of time steps, F_i[n][l] = scale_n * sum_{pairs (i,j)} sum_m T_ij[l][m] C_j[n][m].
 // Dense form (any D); one job per grid z.
@@ -2505,14 +2748,31 @@ hipError_t launch_series_assemble(const Items& it, int n_mats, int terms, const 
 
 hipError_t launch_cn_recur(const Items& it, int n_steps, const double* Ar, const double* Ap,
                            const double* Hr, const double* Q, const double* Eall, double tau,
-                           const double2* Minv, const double2* c0, const RecJobs& jobs, int* flags,
-                           hipStream_t st) {
+                           const double2* Minv, const RecSeries* se, const double2* c0,
+                           const RecJobs& jobs, int* flags, hipStream_t st) {
   if (jobs.n < 1 || jobs.n > kMaxJobs) return hipErrorInvalidValue;
   for (int q = 0; q < jobs.n; ++q)
     if (jobs.n_lo[q] < 0 || jobs.n_cnt[q] < 1 || jobs.n_lo[q] + jobs.n_cnt[q] > n_steps)
       return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_cn_recur<kRecPrefetch>, dim3(it.n_items, jobs.n), dim3(kRecThreads), 0, st,
-                     it, n_steps, Ar, Ap, Hr, Q, Eall, tau, Minv, c0, jobs, flags);
+  const dim3 grid(it.n_items, jobs.n);
+  if (se) {
+    if (!se->P || !se->D || it.Q2) return hipErrorInvalidValue;
+    switch (se->terms) {
+#define SWR_REC_SERIES_CASE(T)                                                                \
+  case T:                                                                                     \
+    hipLaunchKernelGGL(k_cn_recur_series<T>, grid, dim3(kRecThreads), 0, st, it, n_steps, Ar, \
+                       Ap, Hr, Q, Eall, tau, *se, c0, jobs, flags);                           \
+    break;
+      SWR_REC_SERIES_CASE(1) SWR_REC_SERIES_CASE(2) SWR_REC_SERIES_CASE(3)
+      SWR_REC_SERIES_CASE(4)
+#undef SWR_REC_SERIES_CASE
+      default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_cn_recur<kRecPrefetch>, grid, dim3(kRecThreads), 0, st, it, n_steps, Ar,
+                     Ap, Hr, Q, Eall, tau, Minv, c0, jobs, flags);
   return hipGetLastError();
 }
 

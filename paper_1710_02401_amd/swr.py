@@ -61,6 +61,7 @@ class swr_info(ctypes.Structure):
         ("learned_nodes", ctypes.c_int32), ("factor_terms", ctypes.c_int32),
         ("tx_tile", ctypes.c_int32), ("depth_run", ctypes.c_int32), ("wide", ctypes.c_int32),
         ("block", ctypes.c_int32), ("wide_order", ctypes.c_int32), ("tuned", ctypes.c_int32),
+        ("rec_series", ctypes.c_int32),
     ]
 
 
@@ -441,6 +442,13 @@ class Solver:
         info = swr_info()
         self._call("swr_query", ctypes.byref(info))
         return int(info.factor_terms)
+
+    def rec_series(self):
+        """True when the last factorisation's series is evaluated in each
+        recurrence step (no per-step inverses formed)."""
+        info = swr_info()
+        self._call("swr_query", ctypes.byref(info))
+        return bool(info.rec_series)
 
     def item_terms(self):
         """Series terms each item applies per step after the last factorisation."""

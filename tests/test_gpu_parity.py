@@ -410,6 +410,12 @@ def test_series_inverses_match_direct_inversion(name):
         out[mode] = ([_np(h) for h in s.split_history(s.history())], s.factor_terms())
         # every item applies the window's common number of terms (0: direct)
         assert np.all(s.item_terms() == s.factor_terms() + 1)
+        # up to four terms the recurrence evaluates the series in its steps
+        # (the two-electron window: four); five or more are assembled into
+        # stored inverses (the one-electron window: five)
+        assert s.rec_series() == (mode == "auto" and 0 <= s.factor_terms() <= 3)
+        if mode == "auto" and name in ("c2-2e-1d", "c1-1e-1d"):
+            assert s.rec_series() == (name == "c2-2e-1d")
     A = [_np(a) for a in s.matrix("A")]
     (h_s, terms), (h_d, none) = out["auto"], out["direct"]
     d = _a_norm_diff(h_s, h_d, A)
