@@ -116,6 +116,23 @@ class Decomposition:
             for s in self.subs:
                 s.slater = True
                 s.K = len(slater.pairs(s))
+        if cfg.get("basis", "gaussian") == "lsd":
+            # Section 3: determinants of local orbitals (oracle/lsd.py); the
+            # orbitals of interval i from its Gaussians in the first
+            # dimension (the decomposition is exchange-symmetric)
+            from . import lsd, slater
+            orb = {}
+            for s in self.subs:
+                for k in range(2):
+                    i = s.idx[k]
+                    if i not in orb and k == 0:
+                        orb[i] = lsd.orbitals(cfg, s.alpha[0], s.delta[0], s.lo[0], s.hi[0])
+            self.orbital_energies = {i: v[0] for i, v in orb.items()}
+            for s in self.subs:
+                s.slater = True
+                s.lsd = True
+                s.lo_coef = [orb[s.idx[0]][1], orb[s.idx[1]][1]]
+                s.K = len(slater.pairs(s))
         for s in self.subs:
             s.faces = self._faces(s)
 

@@ -43,6 +43,7 @@ import math
 
 import numpy as np
 
+from . import lsd
 from .geometry import Subdomain
 
 
@@ -52,6 +53,8 @@ def is_slater(s):
 
 def pairs(s):
     """(l, p) of every basis function of subdomain s, in basis order."""
+    if lsd.is_lsd(s):
+        return lsd.pairs(s)
     n = len(s.alpha[0])
     if s.idx[0] == s.idx[1]:
         return [(l, p) for l in range(n) for p in range(l + 1, n)]
@@ -66,7 +69,10 @@ def extended(s):
 
 
 def transform(s):
-    """T with v = T E (rows: basis functions, columns: extended tensor)."""
+    """T with v = T E (rows: basis functions, columns: extended tensor);
+    for local Slater determinants oracle/lsd.py's."""
+    if lsd.is_lsd(s):
+        return lsd.transform(s)
     n = len(s.alpha[0])
     m2 = 2 * n
     pr = pairs(s)

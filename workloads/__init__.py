@@ -11,5 +11,6 @@ from .configs import (  # noqa: F401
     get_config,
     random_small_configs,
     slater_configs,
+    lsd_configs,
     tiny_configs,
 )

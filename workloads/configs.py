@@ -160,6 +160,26 @@ _T2A = dict(
     init=dict(alpha=1.0, center=[0.0, 0.0]),
     iters=30, tol=1e-8, face_nodes=[16, 32], quad_nodes=16,
 )
+# The paper's determinant Test 2.a (Section 6): 5 x 5 subdomains of [-8, 8]^2
+# with overlap 0.32, nuclei at +-0.5, imaginary time with mu = 1 and
+# dt = 1.4e-3; 8 local orbitals per interval from 10 Gaussians (64
+# determinants off the diagonal, 28 on it: the paper's K = 28), the order-4
+# mollifier of width 0.1 (sigma = 315/256, eps = 0.1 as printed), a barrier
+# 0.32 beyond each box edge; eta = 0.5 for both soft-Coulomb terms (the test
+# gives none), the antisymmetrised Gaussian pair at +-1 as the start, 200
+# steps per window.
+_T2A_LSD = dict(
+    name="paper-lsd-test-2a", mode="tise", n_elec=2, dim=1, basis="lsd",
+    L=[5, 5], box_lo=[-8.0, -8.0], box_hi=[8.0, 8.0], overlap=[0.32, 0.32],
+    nbasis=[10, 10], width=None, width_ratio=0.7,
+    nuclei=[[-0.5], [0.5]], charges=[1.0, 1.0], eps_en=0.5, eps_ee=0.5,
+    dt=1.4e-3, n_steps=200, mu=[1.0, 0.0],
+    field=dict(E0=0.0, omega=0.0, phase=0.0, axis=0),
+    init=dict(alpha=0.5, center=[-1.0, 1.0]),
+    lsd=dict(orbitals=8, barrier=2.0, barrier_width=0.4, v_inf=30.0, moll_eps=0.1,
+             moll_order=4),
+    iters=20, tol=1e-8, face_nodes=[16, 32], quad_nodes=16,
+)
 _T2B = dict(_T2A, name="paper-test-2b", box_lo=[-6.5, -6.5], box_hi=[6.5, 6.5],
             overlap=[0.26, 0.26], width=0.5,                  # delta = 2
             nuclei=[[-0.5], [0.5]], dt=0.01, n_steps=400,
@@ -213,7 +233,7 @@ _C2_SLATER = dict(_C2, name="c2-2e-1d-slater", basis="slater",
 _C2_SLATER_TISE = dict(_C2_TISE, name="c2-2e-1d-slater-tise", basis="slater",
                        init=dict(alpha=1.0, center=[-1.0, 1.0]))
 
-CONFIGS = {c["name"]: c for c in (_C1, _C2, _C2_TISE, _C3, _C3_MINI, _C3_WIDE, _C4, _C5,
+CONFIGS = {c["name"]: c for c in (_C1, _C2, _C2_TISE, _C3, _C3_MINI, _C3_WIDE, _C4, _C5, _T2A_LSD,
                                    _C5_K16, _C5_MINI, _C5_MINI_1E, _T1B, _T2A, _T2B, _T3,
                                    _C2_SLATER, _C2_SLATER_TISE)}
 
@@ -278,6 +298,24 @@ def slater_configs():
     t2 = dict(t1, name="tiny-slater-tise", mode="tise", mu=[6.0, 0.0], dt=0.05, n_steps=10,
               field=dict(E0=0.0, omega=0.0, phase=0.0, axis=0))
     return [copy.deepcopy(t) for t in (t1, t2)]
+
+
+def lsd_configs():
+    """Small workloads in the local Slater determinant basis of Section 3:
+    the tiny Slater workloads' decomposition (3 x 3 equal intervals on
+    [-6, 6]^2, 6 Gaussians per interval) with 4 local orbitals per interval
+    (16 determinants off the diagonal, 6 on it), a barrier of half-width 2.8
+    about each interval's centre (the box's half-width is 2.4), transition
+    width 0.6, height 30, and the mollifier of order 4 (sigma = 315/256, as
+    in the paper's determinant tests) of width 0.3; real and imaginary time.
+    tiny-lsd-all keeps all 6 orbitals: the same function space as the
+    Slater-like basis of the same Gaussians."""
+    lsd = dict(orbitals=4, barrier=2.8, barrier_width=0.6, v_inf=30.0, moll_eps=0.3,
+               moll_order=4)
+    t1 = dict(slater_configs()[0], name="tiny-lsd", basis="lsd", nbasis=[6, 6], lsd=lsd)
+    t2 = dict(slater_configs()[1], name="tiny-lsd-tise", basis="lsd", nbasis=[6, 6], lsd=lsd)
+    t3 = dict(t1, name="tiny-lsd-all", lsd=dict(lsd, orbitals=6))
+    return [copy.deepcopy(t) for t in (t1, t2, t3)]
 
 
 def random_small_configs(n, seed=4021):
