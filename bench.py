@@ -539,7 +539,7 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=3, help="Schwarz iterations the oracle times")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--depth", type=int, default=0, help="iterates in flight (0: library choice)")
-    ap.add_argument("--learned", choices=("off", "quick", "full"), default="quick")
+    ap.add_argument("--learned", choices=("off", "quick", "full"), default="full")
     ap.add_argument("--batched-iters", type=int, default=30,
                     help="Schwarz iterations of the batched wide-basis window (0: skip it)")
     ap.add_argument("--c5-iters", type=int, default=30,
