@@ -122,12 +122,33 @@ typedef struct swr_desc {
    *   phi_0 = N (g_c1(x1) g_c2(x2) - g_c2(x1) g_c1(x2)),
    *   g_c(x) = exp(-init_alpha (x - c)^2), c1, c2 = init_center[0], [1],
    * N normalising phi_0 on the whole plane.  Narrow path only (K <= 64;
-   * the transmission is formed densely), the sine field. */
+   * the transmission is formed densely), the sine field.
+   * SWR_BASIS_LSD, local Slater determinants of local orbitals (Section 3):
+   * the same construction with phi_l, phi_p the interval's local orbitals
+   * instead of its Gaussians, lsd_orbitals (M) per interval: M^2 functions
+   * off the diagonal, M(M-1)/2 on it.  The orbitals of interval D_i are the
+   * M lowest eigenfunctions of
+   *   -1/2 d/dx (a(x) d/dx) + V_n(x) + V_inf s(|x - x_c| - x_b),
+   *   a(x) = 1 - s(|x - x_c| - x_b),
+   * in the interval's Gaussians over the real line (x_c the centre of the
+   * interval's box, x_b = lsd_barrier, s the C^2 quintic step from 0 to 1
+   * across [-lsd_barrier_width/2, lsd_barrier_width/2], V_inf = lsd_v_inf),
+   * S-normalised and signed so that sum_u (u + 1) C[u][l] > 0.  V_n sums the
+   * nuclei: a nucleus inside the interval's box contributes its
+   * soft-Coulomb term (eps_en) convolved with the mollifier of eq. (Beps),
+   *   B(x) = sigma_M / eps (1 - (x/eps)^2)^M on |x| <= eps,
+   * eps = lsd_moll_eps, M = lsd_moll_order, sigma_M normalising B; the
+   * others their soft-Coulomb term. */
   int32_t basis_kind;
+  /* Local orbitals (SWR_BASIS_LSD only; 2 <= M <= Gaussians per interval,
+   * M <= 8). */
+  int32_t lsd_orbitals;
+  double lsd_barrier, lsd_barrier_width, lsd_v_inf, lsd_moll_eps;
+  int32_t lsd_moll_order;
 } swr_desc;
 
 enum { SWR_FIELD_SINE = 0, SWR_FIELD_CIRCULAR = 1 };
-enum { SWR_BASIS_GAUSSIAN = 0, SWR_BASIS_SLATER = 1 };
+enum { SWR_BASIS_GAUSSIAN = 0, SWR_BASIS_SLATER = 1, SWR_BASIS_LSD = 2 };
 
 typedef struct swr_handle_s* swr_handle;
 

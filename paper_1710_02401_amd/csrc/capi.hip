@@ -219,6 +219,9 @@ struct swr_handle_s {
   Buf bOffP;
   std::vector<int64_t> offp;  // prefix sums of the packed symmetric sizes
   Buf bK, bOff1, bOff2, bIdx, bNb, bL, bLo, bHi, bEps, bDelta, bAoff, bAlpha, bQoff, bQn, bQx, bQw;
+  // local orbitals (SWR_BASIS_LSD): coefficients per interval, the items'
+  // one-dimensional orbital integrals, the orbital problem's rules
+  Buf bLoC, bLoTab, bLoQx, bLoQw, bLoQoff, bLoMx, bLoMw;
   Buf bNItem, bNFace, bNCount, bNCover, bNX, bNW, bNOff, bLag, bLMax;
   Buf bPI, bPJ, bPOff, bTOff, bPNode, bPNOff;
   Buf bPos, bCharge, bS1Off, bS1, bScrOff, bScr, bCenter;
@@ -343,7 +346,14 @@ struct swr_handle_s {
     it.D = g.D;
     it.n_elec = g.desc.n_elec;
     it.dim = g.desc.dim;
-    it.slater = g.desc.basis_kind == SWR_BASIS_SLATER ? 1 : 0;
+    it.slater =
+        g.desc.basis_kind == SWR_BASIS_SLATER || g.desc.basis_kind == SWR_BASIS_LSD ? 1 : 0;
+    if (g.desc.basis_kind == SWR_BASIS_LSD) {
+      it.lsd = 1;
+      it.n_orb = g.desc.lsd_orbitals;
+      it.lo_C = ptr<double>(bLoC);
+      it.lo_tab = ptr<double>(bLoTab);
+    }
     if (g.desc.field_shape == SWR_FIELD_CIRCULAR) {
       it.qmask0 = g.desc.field_mask[0];
       it.qmask1 = g.desc.field_mask[1];
@@ -534,6 +544,16 @@ void plan_layout(swr_handle h) {
   h->bScrOff = L.add(NI * 8);
   h->bScr = L.add(std::max<int64_t>(1, h->scratch_total) * 8);
   h->bCenter = L.add(32);
+  if (g.desc.basis_kind == SWR_BASIS_LSD) {
+    const int M = g.desc.lsd_orbitals;
+    h->bLoC = L.add((size_t)g.L[0] * g.nb[0] * M * 8);
+    h->bLoTab = L.add(NI * 2 * 5 * (size_t)(4 * M * M) * 8);
+    h->bLoQx = L.add(g.lo_qx.size() * 8);
+    h->bLoQw = L.add(g.lo_qw.size() * 8);
+    h->bLoQoff = L.add(g.lo_qoff.size() * 8);
+    h->bLoMx = L.add(g.lo_mx.size() * 8);
+    h->bLoMw = L.add(g.lo_mw.size() * 8);
+  }
   const size_t m2 = h->sum_K2 * 8;
   h->bA = L.add(m2);
   h->bKin = L.add(m2);
@@ -1412,9 +1432,12 @@ int32_t swr_create(const swr_desc* desc, swr_handle* out) {
       s1 += (int64_t)n * n;
     }
     h->scratch_off[s] = scr;
-    if (g.desc.basis_kind == SWR_BASIS_SLATER) {
-      // staged electron-electron term over the extended Gaussian pairs
-      scr += swr::slater_pot_scratch(g.nb[(size_t)s * 4], g.qn[(size_t)s * 4 + 1]);
+    if (g.desc.basis_kind == SWR_BASIS_SLATER || g.desc.basis_kind == SWR_BASIS_LSD) {
+      // staged electron-electron term over the extended pairs (Gaussians,
+      // or local orbitals)
+      const int half =
+          g.desc.basis_kind == SWR_BASIS_LSD ? g.desc.lsd_orbitals : g.nb[(size_t)s * 4];
+      scr += swr::slater_pot_scratch(half, g.qn[(size_t)s * 4 + 1]);
     } else if (g.desc.dim == 2) {
       int32_t nb[4], qn[4];
       for (int k = 0; k < 4; ++k) {
@@ -1636,6 +1659,13 @@ int32_t swr_assemble(swr_handle h, void* stream) {
   HIPCHECK(h, upload(h, h->bQn, g.qn, st));
   HIPCHECK(h, upload(h, h->bQx, g.qx, st));
   HIPCHECK(h, upload(h, h->bQw, g.qw, st));
+  if (g.desc.basis_kind == SWR_BASIS_LSD) {
+    HIPCHECK(h, upload(h, h->bLoQx, g.lo_qx, st));
+    HIPCHECK(h, upload(h, h->bLoQw, g.lo_qw, st));
+    HIPCHECK(h, upload(h, h->bLoQoff, g.lo_qoff, st));
+    HIPCHECK(h, upload(h, h->bLoMx, g.lo_mx, st));
+    HIPCHECK(h, upload(h, h->bLoMw, g.lo_mw, st));
+  }
   HIPCHECK(h, upload(h, h->bNItem, nitem, st));
   HIPCHECK(h, upload(h, h->bNFace, nface, st));
   HIPCHECK(h, upload(h, h->bNCount, ncount, st));
@@ -1710,7 +1740,24 @@ int32_t swr_assemble(swr_handle h, void* stream) {
   const swr::Pairs pr = h->pairs();
   swr::Potential pot{g.desc.n_nuc, h->ptr<double>(h->bPos), h->ptr<double>(h->bCharge),
                      g.desc.eps_en, g.desc.eps_ee};
-  const bool slater = g.desc.basis_kind == SWR_BASIS_SLATER;
+  const bool lsd = g.desc.basis_kind == SWR_BASIS_LSD;
+  const bool slater = g.desc.basis_kind == SWR_BASIS_SLATER || lsd;
+  if (lsd) {
+    // Section 3: the local orbitals of every interval, then the items'
+    // one-dimensional orbital integrals (slater.hip)
+    const int order = g.desc.lsd_moll_order;
+    double sig = 1.0;  // sigma_M = (2M+1)! / (2^(2M+1) (M!)^2)
+    for (int j = 1; j <= order; ++j) sig *= (2.0 * j + 1.0) / (2.0 * j);
+    sig *= 0.5;
+    const swr::LoParams lp{g.desc.lsd_barrier, g.desc.lsd_barrier_width, g.desc.lsd_v_inf,
+                           g.desc.lsd_moll_eps, sig, order};
+    HIPCHECK(h, swr::launch_lo_orbitals(it, g.L[0], pot, lp, h->ptr<double>(h->bLoQx),
+                                        h->ptr<double>(h->bLoQw), h->ptr<int64_t>(h->bLoQoff),
+                                        h->ptr<double>(h->bLoMx), h->ptr<double>(h->bLoMw),
+                                        (int)g.lo_mx.size(), h->ptr<double>(h->bLoC),
+                                        h->ptr<int>(h->bFlags), st));
+    HIPCHECK(h, swr::launch_lo_tables(it, h->ptr<double>(h->bLoTab), st));
+  }
   if (slater) {
     // Section 2 eq. (LSD): the antisymmetrised pairs (slater.hip)
     HIPCHECK(h, swr::launch_slater_assemble(it, h->ptr<double>(h->bA), h->ptr<double>(h->bKin),
@@ -1718,7 +1765,7 @@ int32_t swr_assemble(swr_handle h, void* stream) {
                                             h->ptr<double>(h->bW), g.K_max, st));
     int n_max = 1, q_max = 1;
     for (int s = 0; s < g.n_items; ++s) {
-      n_max = std::max(n_max, (int)g.nb[(size_t)s * 4]);
+      n_max = std::max(n_max, lsd ? g.desc.lsd_orbitals : (int)g.nb[(size_t)s * 4]);
       q_max = std::max(q_max, (int)g.qn[(size_t)s * 4 + 1]);
     }
     HIPCHECK(h, swr::launch_slater_potential(it, pot, h->ptr<int64_t>(h->bScrOff),

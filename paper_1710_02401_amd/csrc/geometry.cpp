@@ -110,9 +110,19 @@ std::string build_geometry(const swr_desc& d, Geometry* g, int* code) {
   if (!(d.eps_en > 0.0) || !(d.eps_ee > 0.0)) return "soft-Coulomb eps must be > 0";
   if (!(d.width > 0.0) && !(d.width_ratio > 0.0)) return "width or width_ratio must be > 0";
   if (d.basis_extend < 0) return "basis_extend must be >= 0";
-  if (d.basis_kind != SWR_BASIS_GAUSSIAN && d.basis_kind != SWR_BASIS_SLATER)
-    return "basis_kind must be SWR_BASIS_GAUSSIAN or SWR_BASIS_SLATER";
-  if (d.basis_kind == SWR_BASIS_SLATER) {
+  if (d.basis_kind != SWR_BASIS_GAUSSIAN && d.basis_kind != SWR_BASIS_SLATER &&
+      d.basis_kind != SWR_BASIS_LSD)
+    return "basis_kind must be SWR_BASIS_GAUSSIAN, SWR_BASIS_SLATER or SWR_BASIS_LSD";
+  if (d.basis_kind == SWR_BASIS_LSD) {
+    if (!(d.lsd_orbitals >= 2 && d.lsd_orbitals <= 8 && d.nbasis && d.lsd_orbitals <= d.nbasis[0]))
+      return "lsd_orbitals must be in 2..8 and at most the Gaussians per interval";
+    if (!(d.lsd_barrier > 0.0) || !(d.lsd_barrier_width > 0.0) || !(d.lsd_v_inf >= 0.0) ||
+        !(d.lsd_moll_eps > 0.0) || d.lsd_moll_order < 1 || d.lsd_moll_order > 8)
+      return "local orbitals need lsd_barrier, lsd_barrier_width, lsd_moll_eps > 0, "
+             "lsd_v_inf >= 0 and lsd_moll_order in 1..8";
+    if (d.nbasis && d.nbasis[0] > 16) return "local orbitals take at most 16 Gaussians per interval";
+  }
+  if (d.basis_kind == SWR_BASIS_SLATER || d.basis_kind == SWR_BASIS_LSD) {
     if (d.n_elec != 2 || d.dim != 1)
       return "the Slater basis is for two electrons in one dimension each";
     if (d.per_subdomain_basis || d.nbasis[0] != d.nbasis[1] || d.nbasis[0] < 2)
@@ -223,9 +233,10 @@ std::string build_geometry(const swr_desc& d, Geometry* g, int* code) {
       g->qx.insert(g->qx.end(), x.begin(), x.end());
       g->qw.insert(g->qw.end(), w.begin(), w.end());
     }
-    if (d.basis_kind == SWR_BASIS_SLATER) {
-      // Section 2 eq. (LSD): antisymmetrised pairs; l < p on the diagonal
-      const int n = g->nb[(size_t)s * kMaxD];
+    if (d.basis_kind == SWR_BASIS_SLATER || d.basis_kind == SWR_BASIS_LSD) {
+      // Section 2 eq. (LSD): antisymmetrised pairs of Gaussians (or, Section
+      // 3, of local orbitals); l < p on the diagonal
+      const int n = d.basis_kind == SWR_BASIS_LSD ? d.lsd_orbitals : g->nb[(size_t)s * kMaxD];
       K = g->idx[(size_t)s * kMaxD] == g->idx[(size_t)s * kMaxD + 1] ? n * (n - 1) / 2 : n * n;
     }
     g->K[s] = K;
@@ -332,6 +343,37 @@ std::string build_geometry(const swr_desc& d, Geometry* g, int* code) {
       g->pnode_off.push_back((int64_t)g->pnode.size());
     }
     g->pair_off[s + 1] = (int64_t)g->pair_i.size();
+  }
+
+  // local orbitals: the orbital problem's rule per interval (Section 3)
+  g->lo_qx.clear();
+  g->lo_qw.clear();
+  g->lo_qoff.assign(1, 0);
+  g->lo_mx.clear();
+  g->lo_mw.clear();
+  if (d.basis_kind == SWR_BASIS_LSD) {
+    for (int i = 0; i < g->L[0]; ++i) {  // item i: interval i in the first dimension
+      const double lo = g->lo[(size_t)i * kMaxD], hi = g->hi[(size_t)i * kMaxD];
+      const double xc = 0.5 * (lo + hi), dl = g->delta[(size_t)i * kMaxD];
+      const double xb = d.lsd_barrier, eb = d.lsd_barrier_width;
+      const double R = xb + 0.5 * eb + 10.0 / std::sqrt(dl), h = 0.25 / std::sqrt(dl);
+      std::vector<double> br = {xc - R, xc - xb - 0.5 * eb, xc - xb + 0.5 * eb,
+                                xc + xb - 0.5 * eb, xc + xb + 0.5 * eb, xc + R};
+      std::sort(br.begin(), br.end());
+      br.erase(std::unique(br.begin(), br.end()), br.end());
+      std::vector<double> edges;
+      for (size_t k = 0; k + 1 < br.size(); ++k) {
+        const int np = std::max(1, (int)std::ceil((br[k + 1] - br[k]) / h));
+        for (int j = 0; j < np; ++j) edges.push_back(br[k] + (br[k + 1] - br[k]) * j / np);
+      }
+      edges.push_back(br.back());
+      std::vector<double> x, w;
+      composite(edges, std::vector<int>(edges.size() - 1, 16), &x, &w);
+      g->lo_qx.insert(g->lo_qx.end(), x.begin(), x.end());
+      g->lo_qw.insert(g->lo_qw.end(), w.begin(), w.end());
+      g->lo_qoff.push_back((int64_t)g->lo_qx.size());
+    }
+    gauss_legendre(64, &g->lo_mx, &g->lo_mw);
   }
 
   // factored transfer entries: runs of equal face in each pair's node list

@@ -80,6 +80,14 @@ struct Geometry {
   std::vector<double> qx, qw;     // concatenated
   std::vector<int64_t> qoff;      // [n_items][kMaxD] offsets, plus count
   std::vector<int32_t> qn;        // [n_items][kMaxD] node counts
+  // local orbitals (SWR_BASIS_LSD): per interval i of the first dimension
+  // (item i) the orbital problem's rule over [x_c - R, x_c + R], R =
+  // barrier + width/2 + 10/sqrt(delta), composite 16-point Gauss-Legendre
+  // with breaks at the barrier's transition edges and panels no wider than
+  // 0.25/sqrt(delta); and the 64-point rule on [-1, 1] of the mollifier
+  std::vector<double> lo_qx, lo_qw;
+  std::vector<int64_t> lo_qoff;   // (L[0] + 1)
+  std::vector<double> lo_mx, lo_mw;
 };
 
 // Returns an empty string on success, else the error message; *code gets

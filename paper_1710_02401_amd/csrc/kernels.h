@@ -17,6 +17,14 @@ struct Items {
   int n_items, n_sub, D, n_elec, dim;
   // 1: the Slater-like antisymmetric basis (slater.h), 0: tensor Gaussians
   int slater;
+  // with slater: 1 for local Slater determinants of local orbitals (Section
+  // 3).  n_orb orbitals per interval; interval i's coefficients at lo_C +
+  // i * nb * n_orb, entry u * n_orb + l (Gaussian u of the interval, orbital
+  // l); lo_tab: per (item, dimension) the one-dimensional integrals of the
+  // item's extended orbitals (slater.hip)
+  int lsd, n_orb;
+  const double* lo_C;
+  const double* lo_tab;
   // configuration coordinates (bit el * dim + a) the field couples to: the
   // first (or only) component and the second of a circular field (0: none)
   int qmask0, qmask1;

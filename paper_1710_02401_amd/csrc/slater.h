@@ -16,9 +16,14 @@
 
 namespace swr {
 
+// Functions per interval in the pairs: Gaussians, or local orbitals.
+__device__ inline int slater_half(const Items& it, int s) {
+  return it.lsd ? it.n_orb : it.nb[4 * s];
+}
+
 // (l, p) of basis function m of Slater item s.
 __device__ inline void slater_pair(const Items& it, int s, int m, int* l, int* p) {
-  const int n = it.nb[4 * s];
+  const int n = slater_half(it, s);
   if (it.idx[4 * s] == it.idx[4 * s + 1]) {
     int r = m, ll = 0;
     while (r >= n - 1 - ll) {
@@ -41,19 +46,48 @@ __device__ inline void slater_gauss(const Items& it, int s, int u, double* a, do
   *d = it.delta[4 * s + k];
 }
 
+// Local orbital l of the interval of item s's dimension t at x, and its
+// derivative: sum_u C[u][l] g_u(x) over the interval's Gaussians.
+__device__ inline double lsd_orbital(const Items& it, int s, int t, int l, double x, double* d) {
+  const int n = it.nb[4 * s + t];
+  const double* C = it.lo_C + (int64_t)it.idx[4 * s + t] * n * it.n_orb;
+  const double* a = it.alpha + it.aoff[4 * s + t];
+  const double dl = it.delta[4 * s + t];
+  double v = 0.0, dv = 0.0;
+  for (int u = 0; u < n; ++u) {
+    const double g = exp(-dl * (x - a[u]) * (x - a[u]));
+    v = fma(C[u * it.n_orb + l], g, v);
+    dv = fma(C[u * it.n_orb + l], -2.0 * dl * (x - a[u]) * g, dv);
+  }
+  *d = dv;
+  return v;
+}
+
+// Extended one-dimensional function u of item s at x (and its derivative):
+// u < half from the first coordinate's interval, else from the second's;
+// Gaussians, or local orbitals.
+__device__ inline double slater_ext(const Items& it, int s, int u, double x, double* d) {
+  const int half = slater_half(it, s);
+  const int t = u < half ? 0 : 1;
+  if (it.lsd) return lsd_orbital(it, s, t, u - t * half, x, d);
+  const double a = it.alpha[it.aoff[4 * s + t] + (u - t * half)], dl = it.delta[4 * s + t];
+  const double g = exp(-dl * (x - a) * (x - a));
+  *d = -2.0 * dl * (x - a) * g;
+  return g;
+}
+
 // v_m(y) and, with grad, its partial derivatives along both coordinates.
 __device__ inline double slater_value(const Items& it, int s, int m, const double* y,
                                       double* grad) {
   int l, p;
   slater_pair(it, s, m, &l, &p);
-  const double a1 = it.alpha[it.aoff[4 * s] + l], d1 = it.delta[4 * s];
-  const double a2 = it.alpha[it.aoff[4 * s + 1] + p], d2 = it.delta[4 * s + 1];
-  const double g1x = exp(-d1 * (y[0] - a1) * (y[0] - a1)), g1y = exp(-d1 * (y[1] - a1) * (y[1] - a1));
-  const double g2x = exp(-d2 * (y[0] - a2) * (y[0] - a2)), g2y = exp(-d2 * (y[1] - a2) * (y[1] - a2));
+  const int half = slater_half(it, s);
+  double d1x, d1y, d2x, d2y;
+  const double g1x = slater_ext(it, s, l, y[0], &d1x), g1y = slater_ext(it, s, l, y[1], &d1y);
+  const double g2x = slater_ext(it, s, half + p, y[0], &d2x);
+  const double g2y = slater_ext(it, s, half + p, y[1], &d2y);
   const double r = 0.70710678118654752440;  // 1 / sqrt(2)
   if (grad) {
-    const double d1x = -2.0 * d1 * (y[0] - a1) * g1x, d1y = -2.0 * d1 * (y[1] - a1) * g1y;
-    const double d2x = -2.0 * d2 * (y[0] - a2) * g2x, d2y = -2.0 * d2 * (y[1] - a2) * g2y;
     grad[0] = r * (d1x * g2y - g1y * d2x);
     grad[1] = r * (g1x * d2y - d1y * g2x);
   }
@@ -74,5 +108,24 @@ hipError_t launch_slater_potential(const Items& it, const Potential& pot, const 
 // Initial coefficients: the antisymmetrised Gaussian pair projected (A c = b).
 hipError_t launch_slater_project(const Items& it, const double* A, double init_alpha,
                                  const double* center, double2* c0, int* flags, hipStream_t st);
+
+// Local orbitals (Section 3), one block per interval i of n_iv: the
+// orbital problem's S and H in the interval's Gaussians (those of item i's
+// first dimension) by the interval's quadrature rule (x, w at qoff[i] ..
+// qoff[i+1]), the nuclei inside the interval's box mollified with the
+// rule (mx, mw) on [-1, 1] scaled to the mollifier's support, then the
+// generalised eigenproblem (Cholesky, cyclic Jacobi): the n_orb lowest
+// orbitals into it.lo_C, S-normalised, signed so that sum_u (u+1) C[u][l] > 0.
+struct LoParams {
+  double barrier, width, v_inf, eps, sigma;
+  int order;
+};
+hipError_t launch_lo_orbitals(const Items& it, int n_iv, const Potential& pot, LoParams lp,
+                              const double* qx, const double* qw, const int64_t* qoff,
+                              const double* mx, const double* mw, int n_m, double* C_out,
+                              int* flags, hipStream_t st);
+// Per (item, dimension): the one-dimensional integrals of the item's
+// extended orbitals into it.lo_tab (needs it.lo_C).
+hipError_t launch_lo_tables(const Items& it, double* tab, hipStream_t st);
 
 }  // namespace swr

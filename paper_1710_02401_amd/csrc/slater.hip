@@ -41,6 +41,21 @@ __device__ inline OneD slater_1d(const Items& it, int s, int k, int u, int v) {
   return r;
 }
 
+// The same integrals for the extended functions of either basis: local
+// orbitals read them from the item's table (k_lo_tables).
+__device__ inline OneD ext_1d(const Items& it, int s, int k, int a, int b) {
+  if (!it.lsd) return slater_1d(it, s, k, a, b);
+  const int m2 = 2 * it.n_orb, sz = m2 * m2;
+  const double* t = it.lo_tab + ((int64_t)s * 2 + k) * 5 * sz + a * m2 + b;
+  OneD r;
+  r.S = t[0];
+  r.X = t[sz];
+  r.T = t[2 * sz];
+  r.B = t[3 * sz];
+  r.W = t[4 * sz];
+  return r;
+}
+
 __global__ void k_slater_assemble(Items it, double* A, double* Kin, double* Q, double* B,
                                   double* W) {
   const int s = blockIdx.y;
@@ -48,7 +63,7 @@ __global__ void k_slater_assemble(Items it, double* A, double* Kin, double* Q, d
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= K * K) return;
   const int m = e / K, m2 = e - m * K;
-  const int n = it.nb[4 * s];
+  const int n = slater_half(it, s);
   int l, p, l2, p2;
   slater_pair(it, s, m, &l, &p);
   slater_pair(it, s, m2, &l2, &p2);
@@ -58,8 +73,8 @@ __global__ void k_slater_assemble(Items it, double* A, double* Kin, double* Q, d
   for (int t = 0; t < 2; ++t)
     for (int t2 = 0; t2 < 2; ++t2) {
       const double sg = t == t2 ? 1.0 : -1.0;
-      const OneD x = slater_1d(it, s, 0, ua[t], va[t2]);
-      const OneD y = slater_1d(it, s, 1, ub[t], vb[t2]);
+      const OneD x = ext_1d(it, s, 0, ua[t], va[t2]);
+      const OneD y = ext_1d(it, s, 1, ub[t], vb[t2]);
       sa += sg * x.S * y.S;
       sk += sg * (x.T * y.S + x.S * y.T);
       sq += sg * (((it.qmask0 & 1) ? x.X * y.S : 0.0) + ((it.qmask0 & 2) ? x.S * y.X : 0.0));
@@ -84,20 +99,20 @@ __device__ inline double u_nuclei(const Potential& pot, double x) {
 }
 
 // Potential, stage 1: one block per (item, pair (u, v) of extended
-// Gaussians).  With the quadrature rules (x_q, w_q) of the first and (y_r,
+// functions).  With the quadrature rules (x_q, w_q) of the first and (y_r,
 // w'_r) of the second interval:
 //   G[u v][r] = sum_q w_q U_u(x_q) U_v(x_q) / sqrt((x_q - y_r)^2 + eps_ee^2),
 //   N0[u v] = sum_q w_q U_u U_v u_nuc(x_q),  N1[u v] = sum_r w'_r U_u U_v u_nuc(y_r).
+// w_q U_u(x_q) U_v(x_q) is formed once per node (in LDS up to kSlaterQ
+// nodes, else per use: the same values).
+constexpr int kSlaterQ = 2048;
 __global__ void __launch_bounds__(kST) k_slater_pot_stage(Items it, Potential pot,
                                                           const int64_t* soff, double* scratch) {
   const int s = blockIdx.x;
-  const int n2 = 2 * it.nb[4 * s];
+  const int n2 = 2 * slater_half(it, s);
   const int pr = blockIdx.y;
   if (pr >= n2 * n2) return;
   const int u = pr / n2, v = pr - u * n2;
-  double au, du, av, dv;
-  slater_gauss(it, s, u, &au, &du);
-  slater_gauss(it, s, v, &av, &dv);
   const int q0n = it.qn[4 * s], q1n = it.qn[4 * s + 1];
   const double* x = it.qx + it.qoff[4 * s];
   const double* wx = it.qw + it.qoff[4 * s];
@@ -107,23 +122,33 @@ __global__ void __launch_bounds__(kST) k_slater_pot_stage(Items it, Potential po
   double* N0 = scratch + soff[s] + (int64_t)n2 * n2 * q1n;
   double* N1 = N0 + n2 * n2;
   __shared__ double red0[kST], red1[kST];
+  __shared__ double fq[kSlaterQ];
+  auto f = [&](int q) {
+    double d;
+    return wx[q] * slater_ext(it, s, u, x[q], &d) * slater_ext(it, s, v, x[q], &d);
+  };
+  const bool staged = q0n <= kSlaterQ;  // uniform over the block
+  if (staged)
+    for (int q = threadIdx.x; q < q0n; q += blockDim.x) fq[q] = f(q);
+  __syncthreads();
   const double ee2 = pot.eps_ee * pot.eps_ee;
   for (int r = threadIdx.x; r < q1n; r += blockDim.x) {
     double acc = 0.0;
     for (int q = 0; q < q0n; ++q) {
-      const double f = wx[q] * exp(-du * (x[q] - au) * (x[q] - au)) * exp(-dv * (x[q] - av) * (x[q] - av));
+      const double fv = staged ? fq[q] : f(q);
       const double dxy = x[q] - y[r];
-      acc += f / sqrt(dxy * dxy + ee2);
+      acc += fv / sqrt(dxy * dxy + ee2);
     }
     G[r] = acc;
   }
   double a0 = 0.0, a1 = 0.0;
   for (int q = threadIdx.x; q < q0n; q += blockDim.x)
-    a0 += wx[q] * exp(-du * (x[q] - au) * (x[q] - au)) * exp(-dv * (x[q] - av) * (x[q] - av)) *
-          u_nuclei(pot, x[q]);
-  for (int r = threadIdx.x; r < q1n; r += blockDim.x)
-    a1 += wy[r] * exp(-du * (y[r] - au) * (y[r] - au)) * exp(-dv * (y[r] - av) * (y[r] - av)) *
+    a0 += (staged ? fq[q] : f(q)) * u_nuclei(pot, x[q]);
+  for (int r = threadIdx.x; r < q1n; r += blockDim.x) {
+    double d;
+    a1 += wy[r] * slater_ext(it, s, u, y[r], &d) * slater_ext(it, s, v, y[r], &d) *
           u_nuclei(pot, y[r]);
+  }
   red0[threadIdx.x] = a0;
   red1[threadIdx.x] = a1;
   __syncthreads();
@@ -150,7 +175,7 @@ __global__ void k_slater_pot_combine(Items it, const int64_t* soff, const double
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= K * K) return;
   const int m = e / K, m2 = e - m * K;
-  const int n = it.nb[4 * s], n2 = 2 * n;
+  const int n = slater_half(it, s), n2 = 2 * n;
   int l, p, l2, p2;
   slater_pair(it, s, m, &l, &p);
   slater_pair(it, s, m2, &l2, &p2);
@@ -166,14 +191,13 @@ __global__ void k_slater_pot_combine(Items it, const int64_t* soff, const double
     for (int t2 = 0; t2 < 2; ++t2) {
       const double sg = t == t2 ? 1.0 : -1.0;
       const int a = ua[t], a2 = va[t2], b = ub[t], b2 = vb[t2];
-      double ab, db, ab2, db2;
-      slater_gauss(it, s, b, &ab, &db);
-      slater_gauss(it, s, b2, &ab2, &db2);
       const double* G = scratch + soff[s] + (int64_t)(a * n2 + a2) * q1n;
       double ee = 0.0;
-      for (int r = 0; r < q1n; ++r)
-        ee += G[r] * wy[r] * exp(-db * (y[r] - ab) * (y[r] - ab)) * exp(-db2 * (y[r] - ab2) * (y[r] - ab2));
-      const double s0 = slater_1d(it, s, 0, a, a2).S, s1 = slater_1d(it, s, 1, b, b2).S;
+      for (int r = 0; r < q1n; ++r) {
+        double d;
+        ee += G[r] * wy[r] * slater_ext(it, s, b, y[r], &d) * slater_ext(it, s, b2, y[r], &d);
+      }
+      const double s0 = ext_1d(it, s, 0, a, a2).S, s1 = ext_1d(it, s, 1, b, b2).S;
       acc += sg * (N0[a * n2 + a2] * s1 + s0 * N1[b * n2 + b2] + ee);
     }
   V[it.off2[s] + e] = 0.5 * acc;
@@ -186,7 +210,7 @@ __global__ void k_slater_project(Items it, const double* A, double init_alpha, c
                                  double2* c0, int* flags) {
   const int s = blockIdx.x;
   const int K = it.K[s];
-  const int n = it.nb[4 * s];
+  const int n = slater_half(it, s);
   __shared__ double a[kSmallK * kSmallK];
   __shared__ double b[kSmallK];
   for (int e = threadIdx.x; e < K * K; e += blockDim.x) a[e] = A[it.off2[s] + e];
@@ -194,9 +218,21 @@ __global__ void k_slater_project(Items it, const double* A, double init_alpha, c
   const double g2 = M_PI / (2.0 * init_alpha);
   const double N = 1.0 / sqrt(2.0 * g2 * (1.0 - exp(-init_alpha * (c1 - c2) * (c1 - c2))));
   auto proj = [&](int k, int u, double c) {
+    const double lo = it.lo[4 * s + k], hi = it.hi[4 * s + k];
+    if (it.lsd) {
+      // orbital u: sum over its interval's Gaussians
+      const int t = u < n ? 0 : 1, l = u - t * n, ng = it.nb[4 * s + t];
+      const double* C = it.lo_C + (int64_t)it.idx[4 * s + t] * ng * it.n_orb;
+      const double* al = it.alpha + it.aoff[4 * s + t];
+      double acc = 0.0;
+      for (int w = 0; w < ng; ++w)
+        acc = fma(C[w * it.n_orb + l], pair_overlap(al[w], it.delta[4 * s + t], c, init_alpha, lo, hi),
+                  acc);
+      return acc;
+    }
     double au, du;
     slater_gauss(it, s, u, &au, &du);
-    return pair_overlap(au, du, c, init_alpha, it.lo[4 * s + k], it.hi[4 * s + k]);
+    return pair_overlap(au, du, c, init_alpha, lo, hi);
   };
   for (int m = threadIdx.x; m < K; m += blockDim.x) {
     int l, p;
@@ -240,6 +276,234 @@ __global__ void k_slater_project(Items it, const double* A, double init_alpha, c
   }
 }
 
+// ---------------------------------------------------------------------------
+// Local orbitals (Section 3): the orbital problem of interval i in its
+// Gaussians, and its generalised eigenproblem.
+
+constexpr int kLoN = 16;  // Gaussians per interval at most
+
+__device__ inline double lo_step(double t, double width) {
+  double u = t / width + 0.5;
+  u = u < 0.0 ? 0.0 : (u > 1.0 ? 1.0 : u);
+  return u * u * u * (10.0 - 15.0 * u + 6.0 * u * u);
+}
+
+// (V * B)(x) for V(r) = -Z / sqrt(r^2 + eta^2) and the order-`order`
+// mollifier of half-width eps: sum_k w_k sigma (1 - t_k^2)^order V(x - eps t_k)
+// over the rule (t_k, w_k) on [-1, 1].
+__device__ inline double lo_mollified(double x, double Z, double eta, const LoParams& lp,
+                                      const double* mx, const double* mw, int n_m) {
+  double acc = 0.0;
+  for (int k = 0; k < n_m; ++k) {
+    const double t = mx[k];
+    double b = 1.0;
+    for (int j = 0; j < lp.order; ++j) b *= 1.0 - t * t;
+    const double r = x - lp.eps * t;
+    acc += mw[k] * lp.sigma * b * (-Z / sqrt(r * r + eta * eta));
+  }
+  return acc;
+}
+
+// Generalised symmetric eigenproblem H c = lambda S c (n <= kLoN) by one
+// thread: Cholesky S = L L^T, A = L^{-1} H L^{-T}, cyclic Jacobi on A, the
+// M lowest eigenvectors back-transformed, C[u * M + l].
+__device__ void lo_eigen(int n, int M, double* S, double* H, double* V, double* C, int* flags) {
+  for (int j = 0; j < n; ++j) {
+    double d = S[j * n + j];
+    for (int k = 0; k < j; ++k) d -= S[j * n + k] * S[j * n + k];
+    if (!(d > 0.0)) {
+      atomicOr(flags, kFlagPivot);
+      return;
+    }
+    d = sqrt(d);
+    S[j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double v = S[i * n + j];
+      for (int k = 0; k < j; ++k) v -= S[i * n + k] * S[j * n + k];
+      S[i * n + j] = v / d;
+    }
+  }
+  // Y = L^{-1} H (columns), then A = L^{-1} Y^T (H symmetric)
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int c = 0; c < n; ++c)
+      for (int i = 0; i < n; ++i) {
+        double v = H[i * n + c];
+        for (int k = 0; k < i; ++k) v -= S[i * n + k] * H[k * n + c];
+        H[i * n + c] = v / S[i * n + i];
+      }
+    for (int i = 0; i < n; ++i)
+      for (int c = i + 1; c < n; ++c) {
+        const double t = H[i * n + c];
+        H[i * n + c] = H[c * n + i];
+        H[c * n + i] = t;
+      }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int c = 0; c < n; ++c) V[i * n + c] = i == c ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int i = 0; i < n; ++i) {
+      dia += H[i * n + i] * H[i * n + i];
+      for (int c = i + 1; c < n; ++c) off += H[i * n + c] * H[i * n + c];
+    }
+    if (off <= 1e-34 * dia) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = H[p * n + q];
+        if (apq == 0.0) continue;
+        const double th = (H[q * n + q] - H[p * n + p]) / (2.0 * apq);
+        const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < n; ++k) {
+          const double akp = H[k * n + p], akq = H[k * n + q];
+          H[k * n + p] = c * akp - sn * akq;
+          H[k * n + q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double apk = H[p * n + k], aqk = H[q * n + k];
+          H[p * n + k] = c * apk - sn * aqk;
+          H[q * n + k] = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double vkp = V[k * n + p], vkq = V[k * n + q];
+          V[k * n + p] = c * vkp - sn * vkq;
+          V[k * n + q] = sn * vkp + c * vkq;
+        }
+      }
+  }
+  bool used[kLoN] = {};
+  for (int l = 0; l < M; ++l) {
+    int best = -1;
+    for (int i = 0; i < n; ++i)
+      if (!used[i] && (best < 0 || H[i * n + i] < H[best * n + best])) best = i;
+    used[best] = true;
+    // c = L^{-T} v (back substitution)
+    double c[kLoN];
+    for (int i = n - 1; i >= 0; --i) {
+      double v = V[i * n + best];
+      for (int k = i + 1; k < n; ++k) v -= S[k * n + i] * c[k];
+      c[i] = v / S[i * n + i];
+    }
+    double sg = 0.0;
+    for (int u = 0; u < n; ++u) sg += (u + 1) * c[u];
+    const double f = sg < 0.0 ? -1.0 : 1.0;
+    for (int u = 0; u < n; ++u) {
+      C[u * M + l] = f * c[u];
+      if (!isfinite(c[u])) atomicOr(flags, kFlagNaN);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kST) k_lo_orbitals(Items it, Potential pot, LoParams lp,
+                                                     const double* qx, const double* qw,
+                                                     const int64_t* qoff, const double* mx,
+                                                     const double* mw, int n_m, double* C_out,
+                                                     int* flags) {
+  const int i = blockIdx.x;  // interval i: item i carries its Gaussians in dimension 0
+  const int n = it.nb[4 * i];
+  const int M = it.n_orb;
+  const double* al = it.alpha + it.aoff[4 * i];
+  const double dl = it.delta[4 * i];
+  const double lo = it.lo[4 * i], hi = it.hi[4 * i];
+  const double xc = 0.5 * (lo + hi);
+  __shared__ double sx[kST], sw[kST], sa[kST], sv[kST];
+  __shared__ double Sm[kLoN * kLoN], Hm[kLoN * kLoN], Vm[kLoN * kLoN];
+  const bool mine = (int)threadIdx.x < n * n;
+  const int u = mine ? threadIdx.x / n : 0, w = mine ? threadIdx.x % n : 0;
+  double accS = 0.0, accH = 0.0;
+  for (int64_t q0 = qoff[i]; q0 < qoff[i + 1]; q0 += kST) {
+    const int64_t q = q0 + threadIdx.x;
+    if (q < qoff[i + 1]) {
+      const double x = qx[q];
+      const double st = lo_step(fabs(x - xc) - lp.barrier, lp.width);
+      double v = lp.v_inf * st;
+      for (int A = 0; A < pot.n_nuc; ++A) {
+        const double R = pot.pos[A], Z = pot.charge[A];
+        if (lo <= R && R <= hi)
+          v += lo_mollified(x - R, Z, pot.eps_en, lp, mx, mw, n_m);
+        else
+          v += -Z / sqrt((x - R) * (x - R) + pot.eps_en * pot.eps_en);
+      }
+      sx[threadIdx.x] = x;
+      sw[threadIdx.x] = qw[q];
+      sa[threadIdx.x] = 1.0 - st;
+      sv[threadIdx.x] = v;
+    }
+    __syncthreads();
+    const int cnt = qoff[i + 1] - q0 < kST ? (int)(qoff[i + 1] - q0) : kST;
+    if (mine)
+      for (int k = 0; k < cnt; ++k) {
+        const double x = sx[k];
+        const double gu = exp(-dl * (x - al[u]) * (x - al[u]));
+        const double gw = exp(-dl * (x - al[w]) * (x - al[w]));
+        const double du = -2.0 * dl * (x - al[u]) * gu, dw = -2.0 * dl * (x - al[w]) * gw;
+        accS += sw[k] * gu * gw;
+        accH += sw[k] * (0.5 * sa[k] * du * dw + sv[k] * gu * gw);
+      }
+    __syncthreads();
+  }
+  if (mine) {
+    Sm[u * n + w] = accS;
+    Hm[u * n + w] = accH;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) lo_eigen(n, M, Sm, Hm, Vm, C_out + (int64_t)i * n * M, flags);
+}
+
+// Per (item s, dimension k): T[q][a][b] = sum_{u,w} Ce[u][a] Ce[w][b] G[q][u][w]
+// for the extended Gaussians' one-dimensional integrals G (slater_1d: S, X,
+// T, B, W over the item's box of dimension k) and Ce the block-diagonal
+// coefficients of the item's two intervals (orbitals a < M from the first
+// coordinate's interval, a >= M from the second's).
+__global__ void __launch_bounds__(kST) k_lo_tables(Items it, double* tab) {
+  const int s = blockIdx.x, k = blockIdx.y;
+  const int n = it.nb[4 * s], M = it.n_orb;
+  const int n2 = 2 * n, m2 = 2 * M;
+  __shared__ double G[5][4 * kLoN * kLoN];
+  __shared__ double Y[5][2 * kLoN * 2 * 8];
+  const double* C0 = it.lo_C + (int64_t)it.idx[4 * s] * n * M;
+  const double* C1 = it.lo_C + (int64_t)it.idx[4 * s + 1] * n * M;
+  auto ce = [&](int uu, int a) {  // Ce[uu][a]
+    if (uu < n) return a < M ? C0[uu * M + a] : 0.0;
+    return a >= M ? C1[(uu - n) * M + (a - M)] : 0.0;
+  };
+  for (int e = threadIdx.x; e < n2 * n2; e += blockDim.x) {
+    const OneD o = slater_1d(it, s, k, e / n2, e % n2);
+    G[0][e] = o.S;
+    G[1][e] = o.X;
+    G[2][e] = o.T;
+    G[3][e] = o.B;
+    G[4][e] = o.W;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n2 * m2; e += blockDim.x) {
+    const int uu = e / m2, b = e % m2;
+    const int w0 = b < M ? 0 : n;
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int w = w0; w < w0 + n; ++w) {
+      const double c = ce(w, b);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) acc[q] = fma(G[q][uu * n2 + w], c, acc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) Y[q][e] = acc[q];
+  }
+  __syncthreads();
+  double* out = tab + ((int64_t)s * 2 + k) * 5 * m2 * m2;
+  for (int e = threadIdx.x; e < m2 * m2; e += blockDim.x) {
+    const int a = e / m2, b = e % m2;
+    const int u0 = a < M ? 0 : n;
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int uu = u0; uu < u0 + n; ++uu) {
+      const double c = ce(uu, a);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) acc[q] = fma(c, Y[q][uu * m2 + b], acc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) out[(int64_t)q * m2 * m2 + e] = acc[q];
+  }
+}
+
 }  // namespace
 
 hipError_t launch_slater_assemble(const Items& it, double* A, double* Kin, double* Q, double* B,
@@ -269,6 +533,21 @@ hipError_t launch_slater_project(const Items& it, const double* A, double init_a
                                  const double* center, double2* c0, int* flags, hipStream_t st) {
   hipLaunchKernelGGL(k_slater_project, dim3(it.n_items), dim3(kST), 0, st, it, A, init_alpha,
                      center, c0, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_lo_orbitals(const Items& it, int n_iv, const Potential& pot, LoParams lp,
+                              const double* qx, const double* qw, const int64_t* qoff,
+                              const double* mx, const double* mw, int n_m, double* C_out,
+                              int* flags, hipStream_t st) {
+  if (n_iv < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_lo_orbitals, dim3(n_iv), dim3(kST), 0, st, it, pot, lp, qx, qw, qoff, mx,
+                     mw, n_m, C_out, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_lo_tables(const Items& it, double* tab, hipStream_t st) {
+  hipLaunchKernelGGL(k_lo_tables, dim3(it.n_items, 2), dim3(kST), 0, st, it, tab);
   return hipGetLastError();
 }
 

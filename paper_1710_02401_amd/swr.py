@@ -19,7 +19,7 @@ SWR_TDSE, SWR_TISE = 0, 1
 SWR_WARM_PLAIN, SWR_WARM_ZERO, SWR_WARM_GIVEN = 0, 1, 2
 SWR_FACTOR_AUTO, SWR_FACTOR_DIRECT, SWR_FACTOR_WIDE, SWR_FACTOR_BLOCK = 0, 1, 2, 3
 SWR_FIELD_SINE, SWR_FIELD_CIRCULAR = 0, 1
-SWR_BASIS_GAUSSIAN, SWR_BASIS_SLATER = 0, 1
+SWR_BASIS_GAUSSIAN, SWR_BASIS_SLATER, SWR_BASIS_LSD = 0, 1, 2
 MATRICES = {"A": 0, "Kin": 1, "V": 2, "Q": 3, "B": 4, "W": 5, "G": 6, "Q2": 7}
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
@@ -48,6 +48,9 @@ class swr_desc(ctypes.Structure):
         ("field_shape", ctypes.c_int32), ("pulse_nu", ctypes.c_double),
         ("pulse_center", ctypes.c_double), ("field_mask", ctypes.c_int32 * 2),
         ("basis_kind", ctypes.c_int32),
+        ("lsd_orbitals", ctypes.c_int32), ("lsd_barrier", ctypes.c_double),
+        ("lsd_barrier_width", ctypes.c_double), ("lsd_v_inf", ctypes.c_double),
+        ("lsd_moll_eps", ctypes.c_double), ("lsd_moll_order", ctypes.c_int32),
     ]
 
 
@@ -237,8 +240,16 @@ def desc_from_config(cfg):
     d.factor_mode = {"auto": SWR_FACTOR_AUTO, "direct": SWR_FACTOR_DIRECT,
                      "wide": SWR_FACTOR_WIDE, "block": SWR_FACTOR_BLOCK}[cfg.get("factor", "auto")]
     d.unnormalized = 1 if cfg.get("unnormalized", False) else 0
-    d.basis_kind = {"gaussian": SWR_BASIS_GAUSSIAN,
-                    "slater": SWR_BASIS_SLATER}[cfg.get("basis", "gaussian")]
+    d.basis_kind = {"gaussian": SWR_BASIS_GAUSSIAN, "slater": SWR_BASIS_SLATER,
+                    "lsd": SWR_BASIS_LSD}[cfg.get("basis", "gaussian")]
+    if "lsd" in cfg and d.basis_kind == SWR_BASIS_LSD:
+        p = cfg["lsd"]
+        d.lsd_orbitals = int(p["orbitals"])
+        d.lsd_barrier = float(p["barrier"])
+        d.lsd_barrier_width = float(p["barrier_width"])
+        d.lsd_v_inf = float(p["v_inf"])
+        d.lsd_moll_eps = float(p["moll_eps"])
+        d.lsd_moll_order = int(p["moll_order"])
     return d, (arr, pos, chg)
 
 

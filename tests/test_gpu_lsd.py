@@ -1,0 +1,131 @@
+"""GPU parity of local Slater determinants of local orbitals (Section 3)
+against the CPU oracle, through the C ABI: the orbitals (through every
+assembled matrix, which depends on their signs and values), the projected
+initial state, real- and imaginary-time windows (one iterate at a time and
+pipelined), the reconstruction, and the paper's determinant Test 2.a
+decomposition at full size on a shortened window.  The orbitals come from
+different eigensolvers on the two sides (cyclic Jacobi on the GPU, LAPACK in
+the oracle), so the matrices are held to 1e-11 of their largest entry;
+histories within 1e-10 relative A-norm at every step, residuals within 1e-7
+relative, energies within 1e-10."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import reconstruct as o_rec
+from oracle import swr as o_swr
+from oracle import tise as o_tise
+
+pytestmark = pytest.mark.gpu
+
+LS = {c["name"]: c for c in workloads.lsd_configs()}
+
+
+def _solver(cfg):
+    import torch
+    from paper_1710_02401_amd import Solver
+    print(f"[gpu] lsd solver {cfg['name']}", flush=True)
+    s = Solver(cfg)
+    s.assemble()
+    s.set_initial()
+    torch.cuda.synchronize()
+    return s
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _a_norm_rel(prob, got, ref):
+    num = den = 0.0
+    for i in range(prob.n_sub):
+        A = prob.sys[i].A
+        d = got[i] - ref[i]
+        num = num + np.real(np.einsum("nk,kl,nl->n", np.conj(d), A, d))
+        den = den + np.real(np.einsum("nk,kl,nl->n", np.conj(ref[i]), A, ref[i]))
+    return float(np.max(np.sqrt(num / den)))
+
+
+def _matrices_match(s, prob, items, bar):
+    for which in ("A", "Kin", "V", "Q", "B", "W"):
+        mats = s.matrix(which)
+        for i in items:
+            ref = getattr(prob.sys[i], which)
+            got = _np(mats[i])
+            assert np.max(np.abs(got - ref)) <= bar * max(np.max(np.abs(ref)), 1e-300), (which, i)
+
+
+@pytest.mark.parametrize("name", ["tiny-lsd", "tiny-lsd-tise", "tiny-lsd-all"])
+def test_lsd_matrices_and_initial_state(name):
+    cfg = LS[name]
+    s = _solver(cfg)
+    prob = o_swr.Problem(cfg)
+    assert list(s.K) == [sub.K for sub in prob.dec.subs]
+    _matrices_match(s, prob, range(prob.n_sub), 1e-11)
+    if cfg["mode"] == "tise":
+        return  # normalised globally on entry; the windows below compare it
+    c0 = prob.initial_coeffs()
+    got = [_np(v) for v in s.split_vector(s.initial())]
+    assert _a_norm_rel(prob, [g[None] for g in got], [c[None] for c in c0]) <= 1e-11
+
+
+@pytest.mark.parametrize("depth", [1, 0])
+def test_lsd_real_time_window(depth):
+    cfg = LS["tiny-lsd"]
+    s = _solver(cfg)
+    prob = o_swr.Problem(cfg)
+    st = s.run(k_max=cfg["iters"], tol=-1.0, depth=depth)
+    h_o, res_o = o_swr.swr_window(prob, prob.initial_coeffs(), iters=cfg["iters"])
+    h_g = [_np(h) for h in s.split_history(s.history())]
+    assert _a_norm_rel(prob, h_g, h_o) <= 1e-10
+    for a, b in zip(st["res"], res_o):
+        assert a == pytest.approx(b, rel=1e-7, abs=1e-12)
+
+
+@pytest.mark.parametrize("depth", [1, 0])
+def test_lsd_imaginary_time_window(depth):
+    cfg = LS["tiny-lsd-tise"]
+    s = _solver(cfg)
+    prob = o_swr.Problem(cfg)
+    st = s.run(k_max=cfg["iters"], tol=-1.0, depth=depth)
+    h_o, res_o, en_o = o_tise.swr_tise(prob, iters=cfg["iters"])
+    h_g = [np.real(_np(h)) for h in s.split_history(s.history())]
+    assert _a_norm_rel(prob, h_g, h_o) <= 1e-10
+    assert st["energy"] == pytest.approx(en_o[-1], rel=1e-10)
+    for a, b in zip(st["res"], res_o):
+        assert a == pytest.approx(b, rel=1e-7, abs=1e-12)
+
+
+def test_lsd_reconstruction_is_the_oracles_and_antisymmetric():
+    import torch
+    cfg = LS["tiny-lsd"]
+    s = _solver(cfg)
+    prob = o_swr.Problem(cfg)
+    s.run(k_max=3, tol=-1.0)
+    h_o, _ = o_swr.swr_window(prob, prob.initial_coeffs(), iters=3)
+    pts = np.random.default_rng(13).uniform(-5.7, 5.7, size=(300, 2))
+    ref = o_rec.reconstruct(prob, [h[5] for h in h_o], pts)
+    got = _np(s.reconstruct(torch.from_numpy(pts), step=5))
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(got - ref)) <= 1e-10 * scale
+    got_x = _np(s.reconstruct(torch.from_numpy(np.ascontiguousarray(pts[:, ::-1])), step=5))
+    assert np.max(np.abs(got + got_x)) <= 1e-9 * scale
+
+
+def test_paper_determinant_test_2a_decomposition():
+    """The paper's determinant Test 2.a (5 x 5 subdomains of [-8, 8]^2, 8
+    orbitals per interval from 10 Gaussians: 64 determinants off the
+    diagonal, 28 on it, imaginary time with mu = 1) on a 40-step window:
+    matrices of sampled subdomains and 3 Schwarz iterations."""
+    cfg = workloads.get_config("paper-lsd-test-2a", n_steps=40)
+    s = _solver(cfg)
+    prob = o_swr.Problem(cfg)
+    assert int(s.K.max()) == 64 and int(s.K.min()) == 28
+    _matrices_match(s, prob, [0, 6, 12, 7, 13, 24], 1e-11)
+    st = s.run(k_max=3, tol=-1.0)
+    h_o, res_o, en_o = o_tise.swr_tise(prob, iters=3)
+    h_g = [np.real(_np(h)) for h in s.split_history(s.history())]
+    assert _a_norm_rel(prob, h_g, h_o) <= 1e-10
+    assert st["energy"] == pytest.approx(en_o[-1], rel=1e-10)
+    for a, b in zip(st["res"], res_o):
+        assert a == pytest.approx(b, rel=1e-7, abs=1e-12)
