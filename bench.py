@@ -52,10 +52,10 @@ MEASURED_TRAFFIC = {
     # 32-step transmission tile: 23 recurrence launches (the series evaluated
     # in the step), 26 transmissions, one factorisation
     "k_cn_recur_series": {"kernels_sha256": "1554c7afb0c7800d", "bytes_per_launch": 0.22198e9},
-    # per transmission tile: 32 steps at depth 4 as above (the 16-step tile
-    # is not measured on this source)
+    # per transmission tile: 32 steps at depth 4 as above; 16 steps over the
+    # autotuned default run's depth-4 windows
     "k_tx_send+k_tx_recv": {"kernels_sha256": "1554c7afb0c7800d",
-                            "bytes_per_launch_by_tile": {32: 0.4513e9}},
+                            "bytes_per_launch_by_tile": {32: 0.4513e9, 16: 0.4521e9}},
     # profiles/c3-1e-1d-batched_traffic.md: one sweep of the batched workload
     "k_cn_recur_wide": {"wide_sha256": "8b17b20586e217b0", "bytes_per_launch": 1350.81e9},
     # profiles/c5-2e-2d_traffic.md: median over the 529 step launches of one
