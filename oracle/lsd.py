@@ -35,6 +35,14 @@ basis E_{a,b} = U_a(x1) U_b(x2) of the two intervals' Gaussians
 E_{n+w,u}) / sqrt(2), so the Galerkin matrices are T M_E T^T as for the
 Slater-like Gaussian basis.
 
+Augmented local bases (Section 3.3): the orbitals vanish near the ends of
+their interval, so the determinants are small in the overlaps and transmit
+little.  The interval's g Gaussians nearest each end of its box (its
+centres are equispaced with both ends, so g = 1 adds the Gaussians centred
+on the box's ends) join the orbitals as further one-electron functions; the
+pairs then run over the M + 2g functions, which keeps every basis function
+antisymmetric and puts functions along all four edges of the subdomain.
+
 Readings (listed in the design notes): the barrier is symmetric about the
 interval's centre; the garbled step definition is read as a C^2 quintic
 from 0 to 1 across [-eps_b/2, eps_b/2]; the one-dimensional Coulomb kernel
@@ -147,9 +155,18 @@ def orbital_matrices(cfg, cen, delta, lo, hi):
     return S, H
 
 
+def augment(cfg):
+    """Gaussians added per end of each interval (Section 3.3); 0 if absent."""
+    return int(cfg["lsd"].get("augment", 0))
+
+
 def orbitals(cfg, cen, delta, lo, hi):
-    """C (n x M): the M lowest orbitals, S-normalised, signed."""
+    """C (n x M'): the M lowest orbitals, S-normalised, signed, then (Section
+    3.3, augmented local bases) the interval's g Gaussians nearest each end
+    of its box as unit columns (the first g, then the last g from the end
+    inwards); M' = M + 2g."""
     M = _params(cfg)[0]
+    g = augment(cfg)
     S, H = orbital_matrices(cfg, cen, delta, lo, hi)
     lam, C = scipy.linalg.eigh(H, S)
     C = C[:, :M].copy()
@@ -157,7 +174,12 @@ def orbitals(cfg, cen, delta, lo, hi):
     for l in range(M):
         if wts @ C[:, l] < 0.0:
             C[:, l] = -C[:, l]
-    return lam[:M], C
+    n = C.shape[0]
+    extra = [a for a in range(g)] + [n - 1 - a for a in range(g)]
+    E = np.zeros((n, len(extra)))
+    for c, u in enumerate(extra):
+        E[u, c] = 1.0
+    return lam[:M], np.concatenate([C, E], axis=1)
 
 
 def is_lsd(s):

@@ -14,7 +14,12 @@ through its quadrature rules or its extended-basis transform:
   * the determinants are antisymmetric, and every matrix of an off-diagonal
     subdomain equals two-dimensional adaptive quadrature of its definition;
   * with as many orbitals as Gaussians the determinants span the Slater-like
-    basis's space: the SWR window reconstructs the same function.
+    basis's space: the SWR window reconstructs the same function;
+  * augmented bases (Section 3.3): the added functions are Gaussians of the
+    interval's exponent centred on its box's ends (built here from the box
+    and the exponent alone), their determinants' matrices equal quadrature,
+    and orbitals plus added Gaussians as many as the Gaussians span the
+    Slater-like basis's space again.
 """
 import math
 
@@ -129,11 +134,16 @@ def _phi(C, cen, dl, l, x):
     return float(C[:, l] @ g), float(C[:, l] @ (-2 * dl * (x - cen) * g))
 
 
-def test_determinants_antisymmetric_and_matrices_match_quadrature():
-    cfg = CF["tiny-lsd"]
+@pytest.mark.parametrize("name,K,checks", [
+    ("tiny-lsd", 16, [(0, 0), (5, 9), (15, 2)]),
+    # 3 orbitals + 2 end Gaussians: pairs (l, p) = m // 5, m % 5, functions
+    # 3 and 4 the added Gaussians
+    ("tiny-lsd-aug", 25, [(24, 0), (4, 23), (19, 12), (18, 18)])])
+def test_determinants_antisymmetric_and_matrices_match_quadrature(name, K, checks):
+    cfg = CF[name]
     prob = swr.Problem(cfg)
     s = prob.dec.subs[1]                       # intervals 1 (x1) and 0 (x2)
-    assert s.idx[0] != s.idx[1] and s.K == 16
+    assert s.idx[0] != s.idx[1] and s.K == K
     sy = prob.sys[1]
     pts = np.random.default_rng(3).uniform(-6, 6, size=(30, 2))
     v = swr.basis_values(s, pts)
@@ -159,7 +169,7 @@ def test_determinants_antisymmetric_and_matrices_match_quadrature():
             u -= Z / math.sqrt((x2 - R[0]) ** 2 + cfg["eps_en"] ** 2)
         return u
 
-    for m, n in [(0, 0), (5, 9), (15, 2)]:
+    for m, n in checks:
         def prod(x1, x2, kind):
             vm, am, bm = vfun(m, x1, x2)
             vn, an, bn = vfun(n, x1, x2)
@@ -172,11 +182,13 @@ def test_determinants_antisymmetric_and_matrices_match_quadrature():
             assert abs(got - ref) <= 1e-10 * np.max(np.abs(getattr(sy, kind))), (kind, m, n)
 
 
-def test_all_orbitals_span_the_slater_basis_space():
-    """With M = n orbitals per interval the determinants span exactly the
-    Slater-like pairs of the same Gaussians, so every SWR iterate is the same
-    function; compared through the reconstruction."""
-    cfg = CF["tiny-lsd-all"]
+@pytest.mark.parametrize("name", ["tiny-lsd-all", "tiny-lsd-aug-all"])
+def test_all_orbitals_span_the_slater_basis_space(name):
+    """With M = n orbitals per interval (or M + 2 = n with the two end
+    Gaussians added) the determinants span exactly the Slater-like pairs of
+    the same Gaussians, so every SWR iterate is the same function; compared
+    through the reconstruction."""
+    cfg = CF[name]
     cfg_s = dict(cfg, basis="slater")
     cfg_s.pop("lsd")
     out = []
@@ -189,3 +201,38 @@ def test_all_orbitals_span_the_slater_basis_space():
     scale = np.max(np.abs(f_s))
     assert np.max(np.abs(f_l - f_s)) <= 1e-10 * scale
     assert np.allclose(r_l, r_s, rtol=1e-8, atol=1e-14)
+
+
+def test_augmented_functions_are_the_gaussians_on_the_box_ends():
+    """Section 3.3: with augment = 1 the one-electron functions of an
+    interval are its orbitals and the Gaussians exp(-delta (x - e)^2) centred
+    on its box's ends e = lo, hi (delta the interval's exponent, 1/(2 w^2)
+    for the workload's width ratio); checked pointwise on the determinants of
+    a diagonal and an off-diagonal subdomain against those Gaussians written
+    out from the box alone, and the counts M + 2 per interval."""
+    cfg = CF["tiny-lsd-aug"]
+    prob = swr.Problem(cfg)
+    pts = np.random.default_rng(8).uniform(-6, 6, size=(40, 2))
+    r = 1 / math.sqrt(2)
+    M = cfg["lsd"]["orbitals"]
+    for lin in (0, 1):                          # (0, 0) diagonal, (1, 0) off it
+        s = prob.dec.subs[lin]
+        i, j = s.idx
+        n = cfg["nbasis"][0]
+
+        def fns(k, x):
+            lo, hi = prob.dec.lo1[0][s.idx[k]], prob.dec.hi1[0][s.idx[k]]
+            sp = (hi - lo) / (n - 1)
+            dl = 0.5 / (cfg["width_ratio"] * sp) ** 2
+            orb = s.lo_coef[k][:, :M].T @ np.exp(-s.delta[k][:, None] * (x[None, :] - s.alpha[k][:, None]) ** 2)
+            ends = np.exp(-dl * (x[None, :] - np.array([lo, hi])[:, None]) ** 2)
+            return np.concatenate([orb, ends])      # (M + 2, npts)
+
+        f1a, f1b = fns(0, pts[:, 0]), fns(0, pts[:, 1])
+        f2a, f2b = fns(1, pts[:, 0]), fns(1, pts[:, 1])
+        m5 = M + 2
+        pr = [(l, p) for l in range(m5) for p in range(m5) if i != j or l < p]
+        assert s.K == len(pr) == (25 if i != j else 10)
+        ref = np.stack([r * (f1a[l] * f2b[p] - f1b[l] * f2a[p]) for l, p in pr], axis=1)
+        got = swr.basis_values(s, pts)
+        assert np.max(np.abs(got - ref)) <= 1e-14, lin

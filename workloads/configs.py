@@ -27,6 +27,7 @@ Every workload is a dict with these keys:
   quad_nodes    Gauss-Legendre nodes per panel for the potential quadrature
 """
 import copy
+import math
 
 _C1 = dict(
     name="c1-1e-1d", mode="tdse", n_elec=1, dim=1,
@@ -180,6 +181,28 @@ _T2A_LSD = dict(
              moll_order=4),
     iters=20, tol=1e-8, face_nodes=[16, 32], quad_nodes=16,
 )
+# Section 5, determinant Test 2.b: H2 with x_A, x_B = -/+0.1 and eta = 0.6 in
+# eq. (pseudo) on (-4, 4)^2, 25 subdomains, mu = 10, the local basis
+# augmented (Section 3.3) by Gaussians of exponent 3 at the subdomains'
+# boundaries, 15 determinants on the diagonal subdomains.  Readings: the
+# intervals' Gaussians all have exponent 3 (width 1/sqrt(6)), so the added
+# ones are each interval's first and last Gaussian, centred on its box's
+# ends (augment = 1), and 15 = 6 * 5 / 2 gives 4 orbitals + 2 Gaussians
+# (36 determinants off the diagonal); 7 Gaussians per interval (the test
+# does not give the count; 6 would make the basis the Slater-like one);
+# Test 2.a's overlap 0.32 (0.16 puts the determinants' Gram condition at
+# 1.1e6, above the recurrence's limit; 0.32 gives 7.8e5); the barrier scaled with the
+# interval (half-width 1.0, transition 0.2); the printed initial guess
+# exp(-4 (x1^2 + x2^2)) is symmetric, so the antisymmetrised product of two
+# such Gaussians centred at -/+0.5; Test 2.a's time step.
+_T2B_LSD = dict(
+    _T2A_LSD, name="paper-lsd-test-2b", box_lo=[-4.0, -4.0], box_hi=[4.0, 4.0],
+    overlap=[0.32, 0.32], nbasis=[7, 7], width=1.0 / math.sqrt(6.0),
+    nuclei=[[-0.1], [0.1]], eps_en=0.6, eps_ee=0.6, mu=[10.0, 0.0],
+    init=dict(alpha=4.0, center=[-0.5, 0.5]),
+    lsd=dict(orbitals=4, augment=1, barrier=1.0, barrier_width=0.2, v_inf=30.0, moll_eps=0.1,
+             moll_order=4),
+)
 _T2B = dict(_T2A, name="paper-test-2b", box_lo=[-6.5, -6.5], box_hi=[6.5, 6.5],
             overlap=[0.26, 0.26], width=0.5,                  # delta = 2
             nuclei=[[-0.5], [0.5]], dt=0.01, n_steps=400,
@@ -234,6 +257,7 @@ _C2_SLATER_TISE = dict(_C2_TISE, name="c2-2e-1d-slater-tise", basis="slater",
                        init=dict(alpha=1.0, center=[-1.0, 1.0]))
 
 CONFIGS = {c["name"]: c for c in (_C1, _C2, _C2_TISE, _C3, _C3_MINI, _C3_WIDE, _C4, _C5, _T2A_LSD,
+                                   _T2B_LSD,
                                    _C5_K16, _C5_MINI, _C5_MINI_1E, _T1B, _T2A, _T2B, _T3,
                                    _C2_SLATER, _C2_SLATER_TISE)}
 
@@ -309,13 +333,20 @@ def lsd_configs():
     width 0.6, height 30, and the mollifier of order 4 (sigma = 315/256, as
     in the paper's determinant tests) of width 0.3; real and imaginary time.
     tiny-lsd-all keeps all 6 orbitals: the same function space as the
-    Slater-like basis of the same Gaussians."""
+    Slater-like basis of the same Gaussians.  tiny-lsd-aug and
+    tiny-lsd-aug-tise take 3 orbitals augmented (Section 3.3) by the first
+    and last Gaussian of each interval (5 functions: 25 determinants off the
+    diagonal, 10 on it); tiny-lsd-aug-all 4 orbitals and the same 2
+    Gaussians, the Slater-like basis's space again."""
     lsd = dict(orbitals=4, barrier=2.8, barrier_width=0.6, v_inf=30.0, moll_eps=0.3,
                moll_order=4)
     t1 = dict(slater_configs()[0], name="tiny-lsd", basis="lsd", nbasis=[6, 6], lsd=lsd)
     t2 = dict(slater_configs()[1], name="tiny-lsd-tise", basis="lsd", nbasis=[6, 6], lsd=lsd)
     t3 = dict(t1, name="tiny-lsd-all", lsd=dict(lsd, orbitals=6))
-    return [copy.deepcopy(t) for t in (t1, t2, t3)]
+    t4 = dict(t1, name="tiny-lsd-aug", lsd=dict(lsd, orbitals=3, augment=1))
+    t5 = dict(t2, name="tiny-lsd-aug-tise", lsd=dict(lsd, orbitals=3, augment=1))
+    t6 = dict(t1, name="tiny-lsd-aug-all", lsd=dict(lsd, orbitals=4, augment=1))
+    return [copy.deepcopy(t) for t in (t1, t2, t3, t4, t5, t6)]
 
 
 def random_small_configs(n, seed=4021):
