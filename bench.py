@@ -246,18 +246,20 @@ def slater_summary(iters=20):
     }
 
 
-def lsd_summary(iters=20):
-    """The paper's determinant Test 2.a in local Slater determinants of local
-    orbitals (Section 3): 5 x 5 subdomains, 8 orbitals per interval (64
-    determinants off the diagonal, 28 on it), imaginary time with mu = 1,
-    200 implicit-Euler steps per window; assembly (orbital problems,
-    tables, matrices) timed once, then 20 Schwarz iterations after an
-    untimed window."""
+def lsd_summary(name="paper-lsd-test-2a", iters=20):
+    """The paper's determinant Tests in local Slater determinants of local
+    orbitals (Section 3): 5 x 5 subdomains, imaginary time, 200
+    implicit-Euler steps per window; Test 2.a with 8 orbitals per interval
+    (64 determinants off the diagonal, 28 on it) and mu = 1, Test 2.b with 4
+    orbitals and the two end Gaussians of each interval (Section 3.3; 36
+    and 15) and mu = 10.  Assembly (orbital problems, tables, matrices, the
+    determinants' condition check) timed once, then 20 Schwarz iterations
+    after an untimed window."""
     import torch
 
     import workloads
     from paper_1710_02401_amd import Solver
-    cfg = workloads.get_config("paper-lsd-test-2a")
+    cfg = workloads.get_config(name)
     s = Solver(cfg)
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -753,6 +755,7 @@ def main():
     out["imaginary_time"] = tise_summary()
     out["slater_basis"] = slater_summary()
     out["local_slater_determinants"] = lsd_summary()
+    out["local_slater_determinants_augmented"] = lsd_summary("paper-lsd-test-2b")
     if args.batched_iters > 0:
         del s
         torch.cuda.empty_cache()

@@ -46,7 +46,8 @@ enum {
   SWR_E_NAN = -6,      /* non-finite value produced on the device              */
   SWR_E_NOCONV = -7,   /* iteration cap reached above the residual target      */
   SWR_E_COND = -8      /* a local Gram matrix is too ill-conditioned for the
-                          accuracy of the path (see swr_create)               */
+                          accuracy of the path (see swr_create and, for
+                          local Slater determinants, swr_assemble)           */
 };
 
 enum { SWR_TDSE = 0, SWR_TISE = 1 };
@@ -138,13 +139,19 @@ typedef struct swr_desc {
    * soft-Coulomb term (eps_en) convolved with the mollifier of eq. (Beps),
    *   B(x) = sigma_M / eps (1 - (x/eps)^2)^M on |x| <= eps,
    * eps = lsd_moll_eps, M = lsd_moll_order, sigma_M normalising B; the
-   * others their soft-Coulomb term. */
+   * others their soft-Coulomb term.  Augmented local bases (Section 3.3):
+   * lsd_augment = g > 0 adds the interval's g Gaussians nearest each end of
+   * its box (the first g, then the last g from the end inwards; g = 1 adds
+   * the two centred on the box's ends) to the orbitals as further
+   * one-electron functions, so the pairs run over M + 2g functions. */
   int32_t basis_kind;
   /* Local orbitals (SWR_BASIS_LSD only; 2 <= M <= Gaussians per interval,
-   * M <= 8). */
+   * M <= 8; 0 <= lsd_augment and M + 2 lsd_augment at most 8 and at most
+   * the Gaussians per interval). */
   int32_t lsd_orbitals;
   double lsd_barrier, lsd_barrier_width, lsd_v_inf, lsd_moll_eps;
   int32_t lsd_moll_order;
+  int32_t lsd_augment;
 } swr_desc;
 
 enum { SWR_FIELD_SINE = 0, SWR_FIELD_CIRCULAR = 1 };
@@ -216,7 +223,12 @@ int32_t swr_bind_workspace(swr_handle h, void* dev, uint64_t bytes);
  * kinetic matrix Kin = 1/2 <grad v, grad v>, soft-Coulomb matrix V
  * (Gauss-Legendre quadrature), dipole matrix Q = sum_m <x_m v, v>, boundary
  * mass B, partition-of-unity mass W, the Robin transfer operators and the
- * face Gram matrices used by the residual.  Requires a bound workspace. */
+ * face Gram matrices used by the residual.  Requires a bound workspace.
+ * Synchronises the stream.  In the local Slater determinant basis (not a
+ * tensor basis, its orbitals computed here) the condition limits of
+ * swr_create apply to the assembled determinants' Gram matrices instead:
+ * SWR_E_COND above 1e6, SWR_E_SINGULAR above 1e14 or when one is not
+ * positive definite; the handle then stays unassembled. */
 int32_t swr_assemble(swr_handle h, void* stream);
 
 /* Local Cauchy data (Section 4.4 step 1; Test 1.a): c0_dev == NULL projects

@@ -73,22 +73,14 @@ constexpr double kCondLimit = 1e6;
 // Above this a Gram matrix is taken as singular to working precision.
 constexpr double kSingularLimit = 1e14;
 
-// Condition number (2-norm) of the one-dimensional Gram matrix
-// S_ab = int_lo^hi exp(-d (x - a_a)^2) exp(-d (x - a_b)^2) dx: Cholesky,
-// then power iteration for the largest eigenvalue and inverse iteration for
-// the smallest (an estimate within a small factor, enough for a limit
-// check); infinity when S is not numerically positive definite.
-double gram_condition_1d(const double* al, int n, double d, double lo, double hi) {
+// Condition number (2-norm) of a symmetric positive definite n x n matrix
+// S (row-major): Cholesky, then power iteration for the largest eigenvalue
+// and inverse iteration for the smallest (an estimate within a small
+// factor, enough for a limit check); infinity when S is not numerically
+// positive definite.
+double spd_condition(const double* S, int n) {
   if (n <= 1) return 1.0;
-  std::vector<double> S((size_t)n * n), L((size_t)n * n, 0.0);
-  const double pi = 3.14159265358979323846;
-  for (int a = 0; a < n; ++a)
-    for (int b = 0; b < n; ++b) {
-      const double p = 2.0 * d, P = 0.5 * (al[a] + al[b]);
-      const double E = std::exp(-0.5 * d * (al[a] - al[b]) * (al[a] - al[b]));
-      const double r = std::sqrt(p);
-      S[(size_t)a * n + b] = E * 0.5 * std::sqrt(pi / p) * (std::erf(r * (hi - P)) - std::erf(r * (lo - P)));
-    }
+  std::vector<double> L((size_t)n * n, 0.0);
   for (int j = 0; j < n; ++j) {
     double v = S[(size_t)j * n + j];
     for (int k = 0; k < j; ++k) v -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
@@ -139,6 +131,22 @@ double gram_condition_1d(const double* al, int n, double d, double lo, double hi
     x.swap(y);
   }
   return lmax * inv;
+}
+
+// The same for the one-dimensional Gram matrix
+// S_ab = int_lo^hi exp(-d (x - a_a)^2) exp(-d (x - a_b)^2) dx.
+double gram_condition_1d(const double* al, int n, double d, double lo, double hi) {
+  if (n <= 1) return 1.0;
+  std::vector<double> S((size_t)n * n);
+  const double pi = 3.14159265358979323846;
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) {
+      const double p = 2.0 * d, P = 0.5 * (al[a] + al[b]);
+      const double E = std::exp(-0.5 * d * (al[a] - al[b]) * (al[a] - al[b]));
+      const double r = std::sqrt(p);
+      S[(size_t)a * n + b] = E * 0.5 * std::sqrt(pi / p) * (std::erf(r * (hi - P)) - std::erf(r * (lo - P)));
+    }
+  return spd_condition(S.data(), n);
 }
 
 // Largest Gram condition over the subdomains of one geometry (the boxes and
@@ -350,7 +358,7 @@ struct swr_handle_s {
         g.desc.basis_kind == SWR_BASIS_SLATER || g.desc.basis_kind == SWR_BASIS_LSD ? 1 : 0;
     if (g.desc.basis_kind == SWR_BASIS_LSD) {
       it.lsd = 1;
-      it.n_orb = g.desc.lsd_orbitals;
+      it.n_orb = swr::lsd_functions(g.desc);
       it.lo_C = ptr<double>(bLoC);
       it.lo_tab = ptr<double>(bLoTab);
     }
@@ -545,7 +553,7 @@ void plan_layout(swr_handle h) {
   h->bScr = L.add(std::max<int64_t>(1, h->scratch_total) * 8);
   h->bCenter = L.add(32);
   if (g.desc.basis_kind == SWR_BASIS_LSD) {
-    const int M = g.desc.lsd_orbitals;
+    const int M = swr::lsd_functions(g.desc);
     h->bLoC = L.add((size_t)g.L[0] * g.nb[0] * M * 8);
     h->bLoTab = L.add(NI * 2 * 5 * (size_t)(4 * M * M) * 8);
     h->bLoQx = L.add(g.lo_qx.size() * 8);
@@ -1378,7 +1386,10 @@ int32_t swr_create(const swr_desc* desc, swr_handle* out) {
     delete h;
     return SWR_E_SIZE;
   }
-  {
+  // Local Slater determinants are not a tensor basis: their Gram matrices
+  // are checked once assembled (swr_assemble), the orbitals being computed
+  // there.
+  if (g.desc.basis_kind != SWR_BASIS_LSD) {
     const double cond = gram_cond;
     if (!(cond <= kCondLimit)) {
       char buf[200];
@@ -1436,7 +1447,7 @@ int32_t swr_create(const swr_desc* desc, swr_handle* out) {
       // staged electron-electron term over the extended pairs (Gaussians,
       // or local orbitals)
       const int half =
-          g.desc.basis_kind == SWR_BASIS_LSD ? g.desc.lsd_orbitals : g.nb[(size_t)s * 4];
+          g.desc.basis_kind == SWR_BASIS_LSD ? swr::lsd_functions(g.desc) : g.nb[(size_t)s * 4];
       scr += swr::slater_pot_scratch(half, g.qn[(size_t)s * 4 + 1]);
     } else if (g.desc.dim == 2) {
       int32_t nb[4], qn[4];
@@ -1750,7 +1761,7 @@ int32_t swr_assemble(swr_handle h, void* stream) {
     for (int j = 1; j <= order; ++j) sig *= (2.0 * j + 1.0) / (2.0 * j);
     sig *= 0.5;
     const swr::LoParams lp{g.desc.lsd_barrier, g.desc.lsd_barrier_width, g.desc.lsd_v_inf,
-                           g.desc.lsd_moll_eps, sig, order};
+                           g.desc.lsd_moll_eps, sig, order, g.desc.lsd_orbitals};
     HIPCHECK(h, swr::launch_lo_orbitals(it, g.L[0], pot, lp, h->ptr<double>(h->bLoQx),
                                         h->ptr<double>(h->bLoQw), h->ptr<int64_t>(h->bLoQoff),
                                         h->ptr<double>(h->bLoMx), h->ptr<double>(h->bLoMw),
@@ -1765,7 +1776,7 @@ int32_t swr_assemble(swr_handle h, void* stream) {
                                             h->ptr<double>(h->bW), g.K_max, st));
     int n_max = 1, q_max = 1;
     for (int s = 0; s < g.n_items; ++s) {
-      n_max = std::max(n_max, lsd ? g.desc.lsd_orbitals : (int)g.nb[(size_t)s * 4]);
+      n_max = std::max(n_max, lsd ? swr::lsd_functions(g.desc) : (int)g.nb[(size_t)s * 4]);
       q_max = std::max(q_max, (int)g.qn[(size_t)s * 4 + 1]);
     }
     HIPCHECK(h, swr::launch_slater_potential(it, pot, h->ptr<int64_t>(h->bScrOff),
@@ -1811,6 +1822,25 @@ int32_t swr_assemble(swr_handle h, void* stream) {
   HIPCHECK(h, swr::launch_face_gram(it, nd, h->ptr<double>(h->bG), g.K_max, st));
   // the uploads above read host vectors local to this call
   HIPCHECK(h, hipStreamSynchronize(st));
+  if (lsd) {
+    // the determinants' Gram matrices A against the same limit as the
+    // tensor bases' at swr_create
+    std::vector<double> A(h->sum_K2);
+    HIPCHECK(h, hipMemcpy(A.data(), h->ptr<double>(h->bA), h->sum_K2 * 8, hipMemcpyDeviceToHost));
+    double worst = 1.0;
+    for (int s = 0; s < g.n_items; ++s) {
+      const double c = spd_condition(&A[g.off2[s]], g.K[s]);
+      worst = std::isnan(c) ? c : std::max(worst, c);
+    }
+    if (!(worst <= kCondLimit)) {
+      char buf[240];
+      std::snprintf(buf, sizeof buf,
+                    "a subdomain's determinant Gram matrix has condition %.3g, above the %.0e "
+                    "the stored-inverse recurrence keeps to 1e-10 (fewer orbitals or added "
+                    "Gaussians, or wider overlaps)", worst, kCondLimit);
+      return fail(h, worst <= kSingularLimit ? SWR_E_COND : SWR_E_SINGULAR, buf);
+    }
+  }
   h->assembled = true;
   h->initial = h->warm = h->factored = false;
   // a schedule measured earlier for this kind of problem

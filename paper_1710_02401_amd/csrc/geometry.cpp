@@ -121,6 +121,9 @@ std::string build_geometry(const swr_desc& d, Geometry* g, int* code) {
       return "local orbitals need lsd_barrier, lsd_barrier_width, lsd_moll_eps > 0, "
              "lsd_v_inf >= 0 and lsd_moll_order in 1..8";
     if (d.nbasis && d.nbasis[0] > 16) return "local orbitals take at most 16 Gaussians per interval";
+    if (d.lsd_augment < 0 || lsd_functions(d) > 8 || lsd_functions(d) > d.nbasis[0])
+      return "lsd_augment must be >= 0 with lsd_orbitals + 2 lsd_augment at most 8 and at most "
+             "the Gaussians per interval";
   }
   if (d.basis_kind == SWR_BASIS_SLATER || d.basis_kind == SWR_BASIS_LSD) {
     if (d.n_elec != 2 || d.dim != 1)
@@ -236,7 +239,7 @@ std::string build_geometry(const swr_desc& d, Geometry* g, int* code) {
     if (d.basis_kind == SWR_BASIS_SLATER || d.basis_kind == SWR_BASIS_LSD) {
       // Section 2 eq. (LSD): antisymmetrised pairs of Gaussians (or, Section
       // 3, of local orbitals); l < p on the diagonal
-      const int n = d.basis_kind == SWR_BASIS_LSD ? d.lsd_orbitals : g->nb[(size_t)s * kMaxD];
+      const int n = d.basis_kind == SWR_BASIS_LSD ? lsd_functions(d) : g->nb[(size_t)s * kMaxD];
       K = g->idx[(size_t)s * kMaxD] == g->idx[(size_t)s * kMaxD + 1] ? n * (n - 1) / 2 : n * n;
     }
     g->K[s] = K;

@@ -90,6 +90,10 @@ struct Geometry {
   std::vector<double> lo_mx, lo_mw;
 };
 
+// One-electron functions per interval of a local-orbital basis (Section 3):
+// the orbitals, then the Gaussians added at each end (Section 3.3).
+inline int lsd_functions(const swr_desc& d) { return d.lsd_orbitals + 2 * d.lsd_augment; }
+
 // Returns an empty string on success, else the error message; *code gets
 // the SWR_E_* status.
 std::string build_geometry(const swr_desc& d, Geometry* g, int* code);

@@ -114,11 +114,14 @@ hipError_t launch_slater_project(const Items& it, const double* A, double init_a
 // first dimension) by the interval's quadrature rule (x, w at qoff[i] ..
 // qoff[i+1]), the nuclei inside the interval's box mollified with the
 // rule (mx, mw) on [-1, 1] scaled to the mollifier's support, then the
-// generalised eigenproblem (Cholesky, cyclic Jacobi): the n_orb lowest
-// orbitals into it.lo_C, S-normalised, signed so that sum_u (u+1) C[u][l] > 0.
+// generalised eigenproblem (Cholesky, cyclic Jacobi): the n_eig lowest
+// orbitals into columns 0 .. n_eig-1 of it.lo_C (n x it.n_orb per interval),
+// S-normalised, signed so that sum_u (u+1) C[u][l] > 0; the remaining
+// it.n_orb - n_eig columns (an even count g2 = 2g, Section 3.3) are unit
+// vectors on Gaussians 0 .. g-1, then n-1 down to n-g.
 struct LoParams {
   double barrier, width, v_inf, eps, sigma;
-  int order;
+  int order, n_eig;
 };
 hipError_t launch_lo_orbitals(const Items& it, int n_iv, const Potential& pot, LoParams lp,
                               const double* qx, const double* qw, const int64_t* qoff,

@@ -306,8 +306,9 @@ __device__ inline double lo_mollified(double x, double Z, double eta, const LoPa
 
 // Generalised symmetric eigenproblem H c = lambda S c (n <= kLoN) by one
 // thread: Cholesky S = L L^T, A = L^{-1} H L^{-T}, cyclic Jacobi on A, the
-// M lowest eigenvectors back-transformed, C[u * M + l].
-__device__ void lo_eigen(int n, int M, double* S, double* H, double* V, double* C, int* flags) {
+// M lowest eigenvectors back-transformed, C[u * ld + l].
+__device__ void lo_eigen(int n, int M, int ld, double* S, double* H, double* V, double* C,
+                         int* flags) {
   for (int j = 0; j < n; ++j) {
     double d = S[j * n + j];
     for (int k = 0; k < j; ++k) d -= S[j * n + k] * S[j * n + k];
@@ -388,7 +389,7 @@ __device__ void lo_eigen(int n, int M, double* S, double* H, double* V, double* 
     for (int u = 0; u < n; ++u) sg += (u + 1) * c[u];
     const double f = sg < 0.0 ? -1.0 : 1.0;
     for (int u = 0; u < n; ++u) {
-      C[u * M + l] = f * c[u];
+      C[u * ld + l] = f * c[u];
       if (!isfinite(c[u])) atomicOr(flags, kFlagNaN);
     }
   }
@@ -447,7 +448,15 @@ __global__ void __launch_bounds__(kST) k_lo_orbitals(Items it, Potential pot, Lo
     Hm[u * n + w] = accH;
   }
   __syncthreads();
-  if (threadIdx.x == 0) lo_eigen(n, M, Sm, Hm, Vm, C_out + (int64_t)i * n * M, flags);
+  double* C = C_out + (int64_t)i * n * M;
+  if (threadIdx.x == 0) lo_eigen(n, lp.n_eig, M, Sm, Hm, Vm, C, flags);
+  // Section 3.3: the Gaussians added at the interval's ends, unit columns
+  const int g = (M - lp.n_eig) / 2;
+  for (int e = threadIdx.x; e < n * 2 * g; e += blockDim.x) {
+    const int uu = e / (2 * g), c = e % (2 * g);
+    const int at = c < g ? c : n - 1 - (c - g);
+    C[uu * M + lp.n_eig + c] = uu == at ? 1.0 : 0.0;
+  }
 }
 
 // Per (item s, dimension k): T[q][a][b] = sum_{u,w} Ce[u][a] Ce[w][b] G[q][u][w]

@@ -51,6 +51,7 @@ class swr_desc(ctypes.Structure):
         ("lsd_orbitals", ctypes.c_int32), ("lsd_barrier", ctypes.c_double),
         ("lsd_barrier_width", ctypes.c_double), ("lsd_v_inf", ctypes.c_double),
         ("lsd_moll_eps", ctypes.c_double), ("lsd_moll_order", ctypes.c_int32),
+        ("lsd_augment", ctypes.c_int32),
     ]
 
 
@@ -250,6 +251,7 @@ def desc_from_config(cfg):
         d.lsd_v_inf = float(p["v_inf"])
         d.lsd_moll_eps = float(p["moll_eps"])
         d.lsd_moll_order = int(p["moll_order"])
+        d.lsd_augment = int(p.get("augment", 0))
     return d, (arr, pos, chg)
 
 

@@ -170,7 +170,8 @@ def _oracle_maps(dec):
 
 
 @pytest.mark.parametrize("name", ["tiny-1d", "tiny-2d", "c1-1e-1d", "c2-2e-1d", "tiny-slater",
-                                  "c2-2e-1d-slater", "tiny-lsd", "paper-lsd-test-2a"])
+                                  "c2-2e-1d-slater", "tiny-lsd", "paper-lsd-test-2a",
+                                  "tiny-lsd-aug", "paper-lsd-test-2b"])
 def test_index_maps_and_boxes_bit_exact(S, name):
     cfgs = {c["name"]: c for c in workloads.tiny_configs() + workloads.slater_configs()
             + workloads.lsd_configs()}
@@ -333,8 +334,10 @@ def test_slater_basis_needs_an_exchange_symmetric_two_electron_problem(S):
 
 def test_local_orbital_parameters_are_validated(S):
     """Local Slater determinants (Section 3) take 2..8 orbitals, at most the
-    Gaussians per interval, positive barrier and mollifier widths, and the
-    Slater basis's conditions on the problem."""
+    Gaussians per interval, positive barrier and mollifier widths, at most 8
+    functions and at most the Gaussians per interval with the added end
+    Gaussians (Section 3.3), and the Slater basis's conditions on the
+    problem."""
     lib = S.load_library()
     base = workloads.lsd_configs()[0]
     rc, h = _create(S, base)
@@ -342,7 +345,8 @@ def test_local_orbital_parameters_are_validated(S):
     lib.swr_destroy(h)
     for bad, why in [(dict(orbitals=1), "lsd_orbitals"), (dict(orbitals=7), "lsd_orbitals"),
                      (dict(moll_eps=0.0), "lsd_moll_eps"), (dict(barrier_width=-1.0), "lsd_barrier"),
-                     (dict(moll_order=0), "lsd_moll_order")]:
+                     (dict(moll_order=0), "lsd_moll_order"), (dict(augment=-1), "lsd_augment"),
+                     (dict(augment=2), "lsd_augment"), (dict(orbitals=5, augment=1), "lsd_augment")]:
         rc, h = _create(S, dict(base, lsd=dict(base["lsd"], **bad)))
         assert rc == S.SWR_E_ARG, bad
         assert why in lib.swr_last_error(None).decode(), bad
