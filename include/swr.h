@@ -386,6 +386,15 @@ typedef struct swr_tuning {
 } swr_tuning;
 int32_t swr_autotune(swr_handle h, int32_t k_iters, double t0, swr_tuning* out, void* stream);
 
+/* Sets the schedule swr_autotune would choose, without measuring: depth in
+ * 1..swr_info.depth (1 for TISE), the transmission tile (narrow factored
+ * path: 16, or 32 where its LDS fits; wide path: 8, 16 or 32; otherwise
+ * the tile in use) and the recurrence order (wide path: 0
+ * largest K first, 1 item order; otherwise 0).  SWR_E_ARG for any other
+ * value, SWR_E_STATE before swr_assemble.  Like swr_autotune it only
+ * reorders the same arithmetic; the tuning table is not changed. */
+int32_t swr_set_schedule(swr_handle h, int32_t depth, int32_t tx_tile, int32_t order, void* stream);
+
 /* ---- outputs and inspection ------------------------------------------------*/
 
 /* Coefficient history of the current iterate: complex [item blocks], item s

@@ -1278,7 +1278,7 @@ int32_t blk_run(swr_handle h, const swr_run_opts* o, swr_run_stats* stats, hipSt
   rc = blk_warm_start(h, o->warm, st);
   if (rc) return rc;
   swr_run_stats s{};
-  int P = o->depth > 0 ? std::min(o->depth, h->blk_depth) : h->blk_depth;
+  int P = o->depth > 0 ? std::min(o->depth, h->blk_depth) : h->depth_run;
   P = std::max(1, std::min(P, o->k_max));
   bool stop = false;
   for (int k0 = 1; k0 <= o->k_max && !stop;) {
@@ -2855,6 +2855,36 @@ int32_t swr_status_sync(swr_handle h, void* stream) {
 }
 
 }  // extern "C"
+
+int32_t swr_set_schedule(swr_handle h, int32_t depth, int32_t tx_tile, int32_t order,
+                         void* stream) {
+  if (!h) return SWR_E_ARG;
+  if (!h->assembled) return fail(h, SWR_E_STATE, "swr_assemble first");
+  const int max_depth = h->block ? h->blk_depth : h->depth;
+  if (depth < 1 || depth > max_depth) return fail(h, SWR_E_ARG, "depth out of range");
+  bool tile_ok, order_ok = order == 0;
+  if (h->block) {
+    tile_ok = tx_tile == 0;
+  } else if (h->wide) {
+    tile_ok = tx_tile == 8 || tx_tile == 16 || tx_tile == 32;
+    order_ok = order == 0 || order == 1;
+  } else if (h->g.te_ok) {
+    tile_ok = tx_tile == 16 || (tx_tile == 32 && h->tx_tt_max == 32);
+  } else {
+    tile_ok = tx_tile == h->tx_tt;
+  }
+  if (!tile_ok) return fail(h, SWR_E_ARG, "transmission tile not available on this path");
+  if (!order_ok) return fail(h, SWR_E_ARG, "recurrence order not available on this path");
+  if (h->block) {
+    h->depth_run = depth;
+    return SWR_OK;
+  }
+  TuneChoice c;
+  c.depth = depth;
+  c.tile = tx_tile;
+  c.order = order;
+  return apply_schedule(h, c, (hipStream_t)stream);
+}
 
 int32_t swr_autotune(swr_handle h, int32_t k_iters, double t0, swr_tuning* out, void* stream) {
   if (!h || !out) return fail(h, SWR_E_ARG, "null argument");

@@ -103,7 +103,7 @@ EXPORTS = [
     "swr_time_nodes", "swr_face_data", "swr_learned_features", "swr_learned_targets",
     "swr_learned_apply", "swr_mlp_param_count", "swr_mlp_workspace_bytes", "swr_mlp_forward",
     "swr_mlp_forward_noalloc",
-    "swr_mlp_loss_grad", "swr_mlp_adam", "swr_autotune",
+    "swr_mlp_loss_grad", "swr_mlp_adam", "swr_autotune", "swr_set_schedule",
 ]
 
 
@@ -138,6 +138,7 @@ def load_library(path=LIB_PATH):
         "swr_transmit": (i32, [vp, ctypes.POINTER(ctypes.c_double), vp]),
         "swr_run": (i32, [vp, ctypes.POINTER(swr_run_opts), ctypes.POINTER(swr_run_stats), vp]),
         "swr_autotune": (i32, [vp, i32, ctypes.c_double, ctypes.POINTER(swr_tuning), vp]),
+        "swr_set_schedule": (i32, [vp, i32, i32, i32, vp]),
         "swr_get_history": (i32, [vp, vp, u64, vp]),
         "swr_get_forcing": (i32, [vp, vp, u64, vp]),
         "swr_get_initial": (i32, [vp, vp, u64, vp]),
@@ -449,6 +450,13 @@ class Solver:
         self._call("swr_query", ctypes.byref(self.info))
         return dict(depth=t.depth, tx_tile=t.tx_tile, ms_per_window=t.ms_per_window,
                     candidates=t.candidates, order=t.order)
+
+    def set_schedule(self, depth, tx_tile, order=0):
+        """Use this schedule (iterates in flight, transmission tile,
+        recurrence order) for later runs with depth 0, without measuring."""
+        self._call("swr_set_schedule", ctypes.c_int32(depth), ctypes.c_int32(tx_tile),
+                   ctypes.c_int32(order), self._stream())
+        self._call("swr_query", ctypes.byref(self.info))
 
     def factor_terms(self):
         """Series terms - 1 used by the last factorisation (-1: direct inversion)."""

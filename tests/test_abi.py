@@ -263,6 +263,18 @@ def test_batched_geometries_share_one_decomposition(S):
     lib.swr_destroy(h)
 
 
+def test_schedule_is_set_only_after_assembly(S):
+    """swr_set_schedule needs the assembled problem (SWR_E_STATE before
+    swr_assemble, checked without a device) and a handle (SWR_E_ARG)."""
+    lib = S.load_library()
+    rc, h = _create(S, workloads.tiny_configs()[0])
+    assert rc == 0
+    assert lib.swr_set_schedule(h, 1, 16, 0, None) == S.SWR_E_STATE
+    assert "swr_assemble" in lib.swr_last_error(h).decode()
+    assert lib.swr_set_schedule(None, 1, 16, 0, None) == S.SWR_E_ARG
+    lib.swr_destroy(h)
+
+
 def test_wide_bases_take_the_wide_path(S):
     """One electron in one dimension (real time) accepts up to 256 Gaussians
     per subdomain on the wide-basis path: the full batched workload (64

@@ -482,6 +482,38 @@ def test_autotuned_schedule_changes_no_result(name):
     assert np.allclose(st1["res"], st0["res"], rtol=1e-12, atol=0)
 
 
+@pytest.mark.parametrize("name", ["tiny-2d", "c2-2e-1d"])
+def test_every_transmission_tile_gives_the_same_histories(name):
+    """swr_set_schedule picks the transmission tile (16, or 32 steps per
+    block where it fits) without measuring: the tile only regroups the
+    senders' and receivers' work, so every tile and depth gives the same
+    histories bit for bit, and residuals to rounding; a tile the path does
+    not have is refused."""
+    from paper_1710_02401_amd import SWRError
+    from paper_1710_02401_amd import swr as S
+    cfg = _cfg(name)
+    s = _solver(cfg)
+    tiles = [16] + ([32] if s.info.tx_tile == 32 else [])
+    ref = None
+    for depth in sorted({1, int(s.info.depth)}):
+        for tile in tiles:
+            print(f"[gpu] {name}: depth {depth}, tile {tile}", flush=True)
+            s.set_schedule(depth, tile)
+            assert s.info.tx_tile == tile and s.info.depth_run == depth
+            s.set_initial()
+            st = s.run(k_max=5, tol=-1.0)
+            h = _np(s.history())
+            if ref is None:
+                ref = (h, st["res"])
+                continue
+            assert np.array_equal(h, ref[0]), (depth, tile)
+            assert np.allclose(st["res"], ref[1], rtol=1e-12, atol=0), (depth, tile)
+    for bad in ([int(s.info.depth) + 1, 16], [1, 8], [1, 16, 1]):
+        with pytest.raises(SWRError) as e:
+            s.set_schedule(*bad)
+        assert e.value.code == S.SWR_E_ARG, bad
+
+
 def test_imaginary_time_pipelined_stops_where_depth_one_stops():
     """With a residual target, the pipelined imaginary-time window stops at
     the same iterate as one iterate at a time (the iterates started past it
