@@ -1509,6 +1509,8 @@ __global__ void __launch_bounds__(kRecThreads)
 // of time steps, F_i[n][l] = scale_n * sum_{pairs (i,j)} sum_m T_ij[l][m] C_j[n][m].
 // Dense form (any D); one job per grid z.
 constexpr int kTN = 32;
+constexpr int kTM = 16;
+constexpr int kTRow = kSmallK + 1;
 __global__ void __launch_bounds__(kBlock) k_transmit(Items it, Pairs pr, int n_steps,
                                                      const double2* T, TxJobs jobs) {
   const int i = blockIdx.y;
@@ -1520,32 +1522,77 @@ __global__ void __launch_bounds__(kBlock) k_transmit(Items it, Pairs pr, int n_s
   const double2* hist = jobs.src[job];
   double2* F = jobs.dst[job];
   const int Ki = it.K[i];
-  __shared__ double2 Ts[kSmallK * kSmallK];  // [m][l]
-  __shared__ double2 Cs[kTN * kSmallK];      // [nn][m]
+  // T in slices of kTM columns: 48 KB of LDS per block instead of 96 KB, so
+  // that three blocks (three waves per SIMD) share a CU; every output still
+  // sums over the pairs, then the columns, in order
+  __shared__ double2 Ts[kTM * kTRow];  // [m - m0][l], rows padded against bank conflicts
+  __shared__ double2 Cs[kTN * kSmallK];  // [nn][m]
   const int l = threadIdx.x & 63;
   const int nn0 = threadIdx.x >> 6;
   double2 acc[kTN / 4];
   for (int q = 0; q < kTN / 4; ++q) acc[q] = make_double2(0.0, 0.0);
-  for (int64_t p = pr.poff[i]; p < pr.poff[i + 1]; ++p) {
+  // Stages (pair p, slice from column m0), each one's loads issued into
+  // registers while the previous one computes.
+  constexpr int kUT = kTM * kSmallK / kBlock, kUC = kTN * kSmallK / kBlock;
+  double tx[kUT], ty[kUT], cx[kUC], cy[kUC];
+  auto fetch = [&](int64_t p, int m0) {
     const int j = pr.pj[p];
     const int Kj = it.K[j];
+    const int cnt = Kj - m0 < kTM ? Kj - m0 : kTM;
     const double2* Tp = T + pr.toff[p];
-    __syncthreads();
-    for (int e = threadIdx.x; e < Ki * Kj; e += blockDim.x) {
-      const int ll = e / Kj, mm = e % Kj;
-      Ts[mm * Ki + ll] = Tp[e];
+#pragma unroll
+    for (int u = 0; u < kUT; ++u) {
+      const int e = u * kBlock + (int)threadIdx.x;
+      const int ll = e / cnt, mm = e - ll * cnt;
+      const double2 v = e < Ki * cnt ? Tp[(int64_t)ll * Kj + m0 + mm] : make_double2(0.0, 0.0);
+      tx[u] = v.x;
+      ty[u] = v.y;
     }
-    const int64_t hb = (int64_t)(n_steps + 1) * it.off1[j];
-    for (int e = threadIdx.x; e < kTN * Kj; e += blockDim.x) {
-      const int nn = e / Kj, mm = e % Kj;
-      const int n = n0 + nn;
-      Cs[e] = (n <= n_hi) ? hist[hb + (int64_t)n * Kj + mm] : make_double2(0.0, 0.0);
+    if (m0 == 0) {
+      const int64_t hb = (int64_t)(n_steps + 1) * it.off1[j];
+#pragma unroll
+      for (int u = 0; u < kUC; ++u) {
+        const int e = u * kBlock + (int)threadIdx.x;
+        const int nn = e / Kj, mm = e - nn * Kj;
+        const double2 v = (e < kTN * Kj && n0 + nn <= n_hi) ? hist[hb + (int64_t)(n0 + nn) * Kj + mm]
+                                                             : make_double2(0.0, 0.0);
+        cx[u] = v.x;
+        cy[u] = v.y;
+      }
     }
+  };
+  int64_t p = pr.poff[i];
+  int m0 = 0;
+  if (p < pr.poff[i + 1]) fetch(p, 0);
+  while (p < pr.poff[i + 1]) {
+    const int Kj = it.K[pr.pj[p]];
+    const int cnt = Kj - m0 < kTM ? Kj - m0 : kTM;
+    __syncthreads();  // the previous stage is read
+#pragma unroll
+    for (int u = 0; u < kUT; ++u) {
+      const int e = u * kBlock + (int)threadIdx.x;
+      const int ll = e / cnt, mm = e - ll * cnt;
+      if (e < Ki * cnt) Ts[mm * kTRow + ll] = make_double2(tx[u], ty[u]);
+    }
+    if (m0 == 0)
+#pragma unroll
+      for (int u = 0; u < kUC; ++u) {
+        const int e = u * kBlock + (int)threadIdx.x;
+        if (e < kTN * Kj) Cs[e] = make_double2(cx[u], cy[u]);
+      }
     __syncthreads();
+    const int cm0 = m0;
+    m0 += kTM;
+    if (m0 >= Kj) {
+      m0 = 0;
+      ++p;
+    }
+    if (p < pr.poff[i + 1]) fetch(p, m0);
     if (l < Ki) {
-      for (int mm = 0; mm < Kj; ++mm) {
-        const double2 t = Ts[mm * Ki + l];
-        for (int q = 0; q < kTN / 4; ++q) acc[q] = cfma(t, Cs[(nn0 + 4 * q) * Kj + mm], acc[q]);
+      for (int mm = 0; mm < cnt; ++mm) {
+        const double2 t = Ts[mm * kTRow + l];
+        for (int q = 0; q < kTN / 4; ++q)
+          acc[q] = cfma(t, Cs[(nn0 + 4 * q) * Kj + cm0 + mm], acc[q]);
       }
     }
   }
