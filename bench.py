@@ -49,13 +49,13 @@ FP64_VALU_PEAK_TFS = 78.6
 MEASURED_TRAFFIC = {
     # profiles/c2-2e-1d_traffic.md: FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000
     # (1 GiB copy calibration) over the first window at depth 4 with the
-    # 32-step transmission tile: 23 recurrence launches (the series evaluated
-    # in the step), 26 transmissions, one factorisation
-    "k_cn_recur_series": {"kernels_sha256": "1554c7afb0c7800d", "bytes_per_launch": 0.22198e9},
-    # per transmission tile: 32 steps at depth 4 as above; 16 steps over the
-    # autotuned default run's depth-4 windows
-    "k_tx_send+k_tx_recv": {"kernels_sha256": "1554c7afb0c7800d",
-                            "bytes_per_launch_by_tile": {32: 0.4513e9, 16: 0.4521e9}},
+    # 16-step transmission tile (the autotuned default): 23 recurrence
+    # launches (the series evaluated in the step), 27 transmissions, one
+    # factorisation
+    "k_cn_recur_series": {"kernels_sha256": "a7cdaef25f2c7e07", "bytes_per_launch": 0.22257e9},
+    # per transmission tile (only the measured one)
+    "k_tx_send+k_tx_recv": {"kernels_sha256": "a7cdaef25f2c7e07",
+                            "bytes_per_launch_by_tile": {16: 0.45217e9}},
     # profiles/c3-1e-1d-batched_traffic.md: one sweep of the batched workload
     "k_cn_recur_wide": {"wide_sha256": "8b17b20586e217b0", "bytes_per_launch": 1350.81e9},
     # profiles/c5-2e-2d_traffic.md: median over the 529 step launches of one
@@ -578,6 +578,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=3, help="Schwarz iterations the oracle times")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--depth", type=int, default=0, help="iterates in flight (0: library choice)")
+    ap.add_argument("--tile", type=int, default=0,
+                    help="with --depth: transmission steps per block (0: the library's default)")
     ap.add_argument("--learned", choices=("off", "quick", "full"), default="full")
     ap.add_argument("--batched-iters", type=int, default=30,
                     help="Schwarz iterations of the batched wide-basis window (0: skip it)")
@@ -641,8 +643,11 @@ def main():
         return s.run(k_max=iters, tol=-1.0, depth=args.depth, timing=not graph,
                      graph=graph and not args.no_graph)
 
-    # the schedule (depth, transmission tile) by measurement, on this window
+    # the schedule (depth, transmission tile) by measurement, on this window,
+    # or as given
     tuning = s.autotune(k_iters=iters) if args.depth == 0 else None
+    if args.depth > 0 and args.tile > 0:
+        s.set_schedule(args.depth, args.tile)
     for _ in range(args.warmup):
         window(True)
     torch.cuda.synchronize()
