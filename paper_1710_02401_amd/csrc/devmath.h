@@ -95,6 +95,15 @@ __device__ inline double dpp_f64(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// Block barrier for LDS traffic only: orders the block's LDS accesses as
+// __syncthreads() does, without waiting for the wave's outstanding global
+// stores (a workgroup fence over every address space waits for them).
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // sum over each group of eight consecutive lanes, result in every lane:
 // quad_perm [1,0,3,2], quad_perm [2,3,0,1], then row_half_mirror (lane i
 // of a half-row meets lane 7-i, i.e. the other quad)

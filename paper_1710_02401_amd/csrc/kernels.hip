@@ -1712,6 +1712,10 @@ __global__ void __launch_bounds__(kBlock) k_tx_send(Items it, TEnt te, int n_ste
   const int n_hi = jobs.n_hi[job];
   if (n0 > n_hi) return;  // uniform over the block
   const int Kj = it.K[j];
+  // the sender's basis sizes per dimension, read before any store: a global
+  // load after the trace stores would wait for them (one in-order counter)
+  const int D = it.D;
+  const int nbj0 = it.nb[4 * j], nbj1 = D == 2 ? it.nb[4 * j + 1] : 1;
   extern __shared__ double2 smem[];
   double2* Cs = smem;
   double2* Ub = Cs + TT * kCRow;  // general form only
@@ -1848,7 +1852,7 @@ __global__ void __launch_bounds__(kBlock) k_tx_send(Items it, TEnt te, int n_ste
       for (int mk = 0; mk < nbjk; ++mk) u = cfma(a[mk], c[mk * sk], u);
       U[nn * nbt + mt] = u;
     }
-    __syncthreads();
+    lds_barrier();
     double2* vout = te.v + ((int64_t)e * (n_steps + 1) + n0) * nbt;
     for (int x = threadIdx.x; x < nrow * nbit; x += blockDim.x) {
       const int nn = x / nbit, lt = x - nn * nbit;
@@ -1866,7 +1870,7 @@ __global__ void __launch_bounds__(kBlock) k_tx_send(Items it, TEnt te, int n_ste
   // Res^2 partial of this tile: sum_n w_n dc^H G_j dc with G_j factored per
   // face, dc = C - C_prev (formed in place of C, no longer read), and per
   // face w[m_t] = sum_{m_k} b[m_k] dc[m_k, m_t], term w^H W w.
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int u = 0; u < kU; ++u) {
     const int x = u * kBlock + (int)threadIdx.x;
@@ -1876,23 +1880,21 @@ __global__ void __launch_bounds__(kBlock) k_tx_send(Items it, TEnt te, int n_ste
       c = make_double2(c.x - px[u], c.y - py[u]);
     }
   }
-  __syncthreads();
-  const int D = it.D;
-  const int nbj1 = D == 2 ? it.nb[4 * j + 1] : 1;
+  lds_barrier();
   double acc = 0.0;
   if (NT > 0) {
     for (int t = threadIdx.x; t < 2 * D * nrow; t += blockDim.x) {
       const int f = t / nrow, nn = t - f * nrow;
       const int kf = f >> 1;
-      const int nbk = it.nb[4 * j + kf];
-      const int nbf = D == 2 ? it.nb[4 * j + (1 - kf)] : 1;
+      const int nbk = kf == 0 ? nbj0 : nbj1;
+      const int nbf = D == 2 ? (kf == 0 ? nbj1 : nbj0) : 1;
       const int sk = (D == 2 && kf == 0) ? nbj1 : 1;
       const int stt = (D == 2 && kf == 1) ? nbj1 : 1;
       int goff = 0;
       for (int f2 = 0; f2 < f; ++f2) {
         const int k2 = f2 >> 1;
-        const int m = D == 2 ? it.nb[4 * j + (1 - k2)] : 1;
-        goff += it.nb[4 * j + k2] + m * m;
+        const int m = D == 2 ? (k2 == 0 ? nbj1 : nbj0) : 1;
+        goff += (k2 == 0 ? nbj0 : nbj1) + m * m;
       }
       const double* b = gpiece + goff;
       const double* W = b + nbk;
@@ -1931,8 +1933,8 @@ __global__ void __launch_bounds__(kBlock) k_tx_send(Items it, TEnt te, int n_ste
   int goff = 0;
   for (int f = 0; NT == 0 && f < 2 * D; ++f) {
     const int kf = f >> 1;
-    const int nbk = it.nb[4 * j + kf];
-    const int nbf = D == 2 ? it.nb[4 * j + (1 - kf)] : 1;
+    const int nbk = kf == 0 ? nbj0 : nbj1;
+    const int nbf = D == 2 ? (kf == 0 ? nbj1 : nbj0) : 1;
     const int sk = (D == 2 && kf == 0) ? nbj1 : 1;
     const int stt = (D == 2 && kf == 1) ? nbj1 : 1;
     const double* b = gpiece + goff;
@@ -1948,7 +1950,7 @@ __global__ void __launch_bounds__(kBlock) k_tx_send(Items it, TEnt te, int n_ste
       }
       Ub[nn * nbt + mt] = w;
     }
-    __syncthreads();
+    lds_barrier();
     for (int x = threadIdx.x; x < nrow * nbf; x += blockDim.x) {
       const int nn = x / nbf, lt = x - nn * nbf;
       const double2* wr = Ub + nn * nbt;
@@ -1961,15 +1963,15 @@ __global__ void __launch_bounds__(kBlock) k_tx_send(Items it, TEnt te, int n_ste
       const double wn = (n == 0 || n == n_steps) ? 0.5 * jobs.dt : jobs.dt;
       acc += wn * (wr[lt].x * sx + wr[lt].y * sy);
     }
-    __syncthreads();
+    lds_barrier();
   }
   // block sum in a fixed order
   __shared__ double red[kBlock];
   red[threadIdx.x] = acc;
-  __syncthreads();
+  lds_barrier();
   for (int w = kBlock / 2; w > 0; w >>= 1) {
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
+    lds_barrier();
   }
   if (threadIdx.x == 0) part[(int64_t)j * jobs.part_stride + jobs.part_base[job] + blockIdx.x] = red[0];
 }
