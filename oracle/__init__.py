@@ -20,4 +20,4 @@ itself) is given per module; all parts are pinned by tests under `tests/`
 (closed forms, textbook special cases, invariants, brute force) except
 where a module header says "parity unpinned".
 """
-from . import gauss1d, geometry, quadrature, lsd, slater, assemble, swr, tise, reconstruct, mlp, learned  # noqa: F401
+from . import gauss1d, geometry, quadrature, lsd, lo2, slater, assemble, swr, tise, reconstruct, mlp, learned  # noqa: F401

@@ -41,7 +41,7 @@ import math
 
 import numpy as np
 
-from . import gauss1d, quadrature, slater
+from . import gauss1d, lo2, quadrature, slater
 
 
 def kron_all(mats):
@@ -59,10 +59,15 @@ class LocalSystem:
         D = dec.D
         self.sub = s
         self.D = D
-        if slater.is_slater(s):
-            # Section 2, eq. (LSD): M = T M_E T^T over the extended tensor basis
-            ext = LocalSystem(dec, slater.extended(s))
-            T = slater.transform(s)
+        if slater.is_slater(s) or lo2.is_lo2(s):
+            # Section 2, eq. (LSD): M = T M_E T^T over the extended tensor
+            # basis; Section 3 in d = 2: over the box's own Gaussians
+            if lo2.is_lo2(s):
+                ext = LocalSystem(dec, lo2.gaussians(s))
+                T = lo2.transform(s)
+            else:
+                ext = LocalSystem(dec, slater.extended(s))
+                T = slater.transform(s)
             for name in ("A", "Kin", "B", "W", "Q", "V"):
                 setattr(self, name, T @ getattr(ext, name) @ T.T)
             if hasattr(ext, "Q2"):
@@ -227,6 +232,8 @@ def projection_rhs(dec, s):
     D = dec.D
     alpha0 = float(cfg["init"]["alpha"])
     cen = [float(c) for c in cfg["init"]["center"]]
+    if lo2.is_lo2(s):
+        return lo2.transform(s) @ projection_rhs(dec, lo2.gaussians(s))
     if slater.is_slater(s):
         ext = slater.extended(s)
         proj = [[gauss1d.gaussian_projection(ext.alpha[k], ext.delta[k], s.lo[k], s.hi[k],

@@ -133,6 +133,17 @@ class Decomposition:
                 s.lsd = True
                 s.lo_coef = [orb[s.idx[0]][1], orb[s.idx[1]][1]]
                 s.K = len(slater.pairs(s))
+        if cfg.get("basis", "gaussian") == "lo":
+            # Section 3 in d = 2, one electron: each box's local orbitals in
+            # its tensor Gaussians (oracle/lo2.py)
+            from . import lo2
+            self.orbital_energies = {}
+            for s in self.subs:
+                lam, C = lo2.orbitals2(cfg, s)
+                s.lo2 = True
+                s.lo_coef = C
+                s.K = C.shape[1]
+                self.orbital_energies[s.lin] = lam
         for s in self.subs:
             s.faces = self._faces(s)
 

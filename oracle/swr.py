@@ -33,7 +33,7 @@ with a known time profile (same file).
 """
 import numpy as np
 
-from . import assemble, gauss1d, slater
+from . import assemble, gauss1d, lo2, slater
 from .geometry import Decomposition
 
 
@@ -64,6 +64,8 @@ def basis_values(s, pts):
     """v_l(y) for all points (rows) and local basis functions (columns)."""
     if slater.is_slater(s):
         return basis_values(slater.extended(s), pts) @ slater.transform(s).T
+    if lo2.is_lo2(s):
+        return basis_values(lo2.gaussians(s), pts) @ lo2.transform(s).T
     out = np.ones((pts.shape[0], 1))
     for k in range(s.D):
         vk = gauss1d.values(s.alpha[k], s.delta[k], pts[:, k])
@@ -75,6 +77,8 @@ def basis_derivative(s, pts, kd):
     """d v_l / d x_kd at the points."""
     if slater.is_slater(s):
         return basis_derivative(slater.extended(s), pts, kd) @ slater.transform(s).T
+    if lo2.is_lo2(s):
+        return basis_derivative(lo2.gaussians(s), pts, kd) @ lo2.transform(s).T
     out = np.ones((pts.shape[0], 1))
     for k in range(s.D):
         if k == kd:

@@ -12,5 +12,6 @@ from .configs import (  # noqa: F401
     random_small_configs,
     slater_configs,
     lsd_configs,
+    lo_configs,
     tiny_configs,
 )

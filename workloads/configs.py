@@ -349,6 +349,34 @@ def lsd_configs():
     return [copy.deepcopy(t) for t in (t1, t2, t3, t4, t5, t6)]
 
 
+def lo_configs():
+    """Small workloads in the local orbital basis of one electron in two
+    dimensions (Section 3 with d = 2): 2 x 2 boxes of [-6, 6]^2 (overlap
+    1.0), 5 x 5 Gaussians per box (25), 8 orbitals per box, one nucleus of
+    charge 1 at (0.3, -0.2) (the SWR Hamiltonian keeps its soft-Coulomb
+    attraction, eps_en 0.5), a barrier of half-width 3.6 about each box's
+    centre (the boxes' half-width is 3.25), transition width 0.6, height 30,
+    the order-4 mollifier of radius 0.3; real time (complex Robin
+    constant, sine field) and imaginary time (real Robin constant).
+    tiny-lo-all keeps all 25 orbitals: the Gaussian basis's space."""
+    lo = dict(orbitals=8, barrier=3.6, barrier_width=0.6, v_inf=30.0, moll_eps=0.3,
+              moll_order=4)
+    t1 = dict(
+        name="tiny-lo", mode="tdse", n_elec=1, dim=2, basis="lo",
+        L=[2, 2], box_lo=[-6.0, -6.0], box_hi=[6.0, 6.0], overlap=[1.0, 1.0],
+        nbasis=[5, 5], width=None, width_ratio=0.8,
+        nuclei=[[0.3, -0.2]], charges=[1.0], eps_en=0.5, eps_ee=0.5,
+        dt=0.02, n_steps=10, mu=[0.0, -4.0],
+        field=dict(E0=0.2, omega=0.9, phase=0.1, axis=0),
+        init=dict(alpha=0.5, center=[0.4, -0.3]),
+        iters=4, tol=1e-8, face_nodes=[4, 6], quad_nodes=16, lo=lo,
+    )
+    t2 = dict(t1, name="tiny-lo-tise", mode="tise", mu=[6.0, 0.0], dt=0.05,
+              field=dict(E0=0.0, omega=0.0, phase=0.0, axis=0))
+    t3 = dict(t1, name="tiny-lo-all", lo=dict(lo, orbitals=25))
+    return [copy.deepcopy(t) for t in (t1, t2, t3)]
+
+
 def random_small_configs(n, seed=4021):
     """Seeded small real-time configurations for broad parity checks: one
     electron in one or two dimensions or two electrons in one, 1 to 3
