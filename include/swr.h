@@ -143,7 +143,22 @@ typedef struct swr_desc {
    * lsd_augment = g > 0 adds the interval's g Gaussians nearest each end of
    * its box (the first g, then the last g from the end inwards; g = 1 adds
    * the two centred on the box's ends) to the orbitals as further
-   * one-electron functions, so the pairs run over M + 2g functions. */
+   * one-electron functions, so the pairs run over M + 2g functions.
+   * SWR_BASIS_LO, local orbitals of one electron in two dimensions
+   * (Section 3 with d = 2): the basis of each subdomain (a box with centre
+   * x_c and n_0 x n_1 <= 64 tensor Gaussians, at most 8 per dimension) is
+   * its lsd_orbitals (M) lowest eigenfunctions of
+   *   -1/2 div(a grad) + V_n + V_inf sum_k s(|x_k - x_ck| - x_b),
+   *   a = prod_k (1 - s(|x_k - x_ck| - x_b)),
+   * in the box's Gaussians over the plane (s, x_b, V_inf as above), with
+   * V_n = sum_A -Z_A G(|x - R_A|) for every nucleus, G the bare Coulomb
+   * kernel 1/|x| convolved with B(y) = (M' + 1) / (pi eps^2)
+   * (1 - |y|^2 / eps^2)^M' on |y| <= eps (eps = lsd_moll_eps, M' =
+   * lsd_moll_order in 2..8), S-normalised and signed so that
+   * sum_u (u + 1) C[u][l] > 0; every matrix is C^T (Gaussian matrix) C.
+   * One geometry, the sine field, the narrow path (dense transmission);
+   * lsd_augment must be 0.  The SWR Hamiltonian keeps its soft-Coulomb
+   * terms (eps_en). */
   int32_t basis_kind;
   /* Local orbitals (SWR_BASIS_LSD only; 2 <= M <= Gaussians per interval,
    * M <= 8; 0 <= lsd_augment and M + 2 lsd_augment at most 8 and at most
@@ -155,7 +170,7 @@ typedef struct swr_desc {
 } swr_desc;
 
 enum { SWR_FIELD_SINE = 0, SWR_FIELD_CIRCULAR = 1 };
-enum { SWR_BASIS_GAUSSIAN = 0, SWR_BASIS_SLATER = 1, SWR_BASIS_LSD = 2 };
+enum { SWR_BASIS_GAUSSIAN = 0, SWR_BASIS_SLATER = 1, SWR_BASIS_LSD = 2, SWR_BASIS_LO = 3 };
 
 typedef struct swr_handle_s* swr_handle;
 

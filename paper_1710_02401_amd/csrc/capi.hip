@@ -230,6 +230,13 @@ struct swr_handle_s {
   // local orbitals (SWR_BASIS_LSD): coefficients per interval, the items'
   // one-dimensional orbital integrals, the orbital problem's rules
   Buf bLoC, bLoTab, bLoQx, bLoQw, bLoQoff, bLoMx, bLoMw;
+  // local orbitals in two dimensions: the Gaussian matrices (offsets
+  // lo_off2g, sizes lo_kg), the angle rule, node Gaussians, 1-D integrals
+  // and the nuclear term's first contraction
+  Buf bKG, bOff2G, bAG, bKinG, bVG, bQG, bBG, bWG, bLoAng, bLoGt, bLoPP;
+  std::vector<int32_t> lo_kg;
+  std::vector<int64_t> lo_off2g;
+  std::vector<double> lo_ang;
   Buf bNItem, bNFace, bNCount, bNCover, bNX, bNW, bNOff, bLag, bLMax;
   Buf bPI, bPJ, bPOff, bTOff, bPNode, bPNOff;
   Buf bPos, bCharge, bS1Off, bS1, bScrOff, bScr, bCenter;
@@ -362,6 +369,11 @@ struct swr_handle_s {
       it.lo_C = ptr<double>(bLoC);
       it.lo_tab = ptr<double>(bLoTab);
     }
+    if (g.desc.basis_kind == SWR_BASIS_LO) {
+      it.lo2 = 1;
+      it.n_orb = g.desc.lsd_orbitals;
+      it.lo_C = ptr<double>(bLoC);
+    }
     if (g.desc.field_shape == SWR_FIELD_CIRCULAR) {
       it.qmask0 = g.desc.field_mask[0];
       it.qmask1 = g.desc.field_mask[1];
@@ -389,6 +401,16 @@ struct swr_handle_s {
     it.qw = ptr<double>(bQw);
     return it;
   }
+  // local orbitals: the same items over their tensor Gaussians (the
+  // assembly of the matrices the orbitals transform)
+  swr::Items items_gaussian() const {
+    swr::Items it = items();
+    it.lo2 = 0;
+    it.K = ptr<int32_t>(bKG);
+    it.off2 = ptr<int64_t>(bOff2G);
+    return it;
+  }
+
   swr::Nodes nodes() const {
     swr::Nodes nd{};
     nd.n = (int64_t)g.nodes.size();
@@ -561,6 +583,42 @@ void plan_layout(swr_handle h) {
     h->bLoQoff = L.add(g.lo_qoff.size() * 8);
     h->bLoMx = L.add(g.lo_mx.size() * 8);
     h->bLoMw = L.add(g.lo_mw.size() * 8);
+  }
+  if (g.desc.basis_kind == SWR_BASIS_LO) {
+    const int M = g.desc.lsd_orbitals;
+    h->lo_kg.assign(NI, 0);
+    h->lo_off2g.assign(NI + 1, 0);
+    for (size_t s = 0; s < NI; ++s) {
+      h->lo_kg[s] = g.nb[s * 4] * g.nb[s * 4 + 1];
+      h->lo_off2g[s + 1] = h->lo_off2g[s] + (int64_t)h->lo_kg[s] * h->lo_kg[s];
+    }
+    const size_t g2 = (size_t)h->lo_off2g[NI] * 8;
+    h->bKG = L.add(NI * 4);
+    h->bOff2G = L.add((NI + 1) * 8);
+    h->bAG = L.add(g2);
+    h->bKinG = L.add(g2);
+    h->bVG = L.add(g2);
+    h->bQG = L.add(g2);
+    h->bBG = L.add(g2);
+    h->bWG = L.add(g2);
+    h->bLoC = L.add(NI * (size_t)swr::kSmallK * M * 8);
+    h->bLoQx = L.add(g.lo_qx.size() * 8);
+    h->bLoQw = L.add(g.lo_qw.size() * 8);
+    h->bLoQoff = L.add(g.lo_qoff.size() * 8);
+    h->bLoAng = L.add(2 * g.lo_mx.size() * 16);
+    h->bLoGt = L.add(g.lo_qx.size() * 8 * 8);
+    h->bLoTab = L.add(NI * 2 * 4 * 64 * 8);
+    h->bLoPP = L.add(g.lo_qx.size() * 64 * 8);
+    // the angle rule on [0, pi/2]: (sin, cos) of the nodes, then (weight, 0)
+    const double qa = 0.25 * 3.14159265358979323846;
+    const size_t nm = g.lo_mx.size();
+    h->lo_ang.assign(4 * nm, 0.0);
+    for (size_t j = 0; j < nm; ++j) {
+      const double a = qa * (g.lo_mx[j] + 1.0);
+      h->lo_ang[2 * j] = std::sin(a);
+      h->lo_ang[2 * j + 1] = std::cos(a);
+      h->lo_ang[2 * (nm + j)] = qa * g.lo_mw[j];
+    }
   }
   const size_t m2 = h->sum_K2 * 8;
   h->bA = L.add(m2);
@@ -1389,7 +1447,7 @@ int32_t swr_create(const swr_desc* desc, swr_handle* out) {
   // Local Slater determinants are not a tensor basis: their Gram matrices
   // are checked once assembled (swr_assemble), the orbitals being computed
   // there.
-  if (g.desc.basis_kind != SWR_BASIS_LSD) {
+  if (g.desc.basis_kind != SWR_BASIS_LSD && g.desc.basis_kind != SWR_BASIS_LO) {
     const double cond = gram_cond;
     if (!(cond <= kCondLimit)) {
       char buf[200];
@@ -1677,6 +1735,14 @@ int32_t swr_assemble(swr_handle h, void* stream) {
     HIPCHECK(h, upload(h, h->bLoMx, g.lo_mx, st));
     HIPCHECK(h, upload(h, h->bLoMw, g.lo_mw, st));
   }
+  if (g.desc.basis_kind == SWR_BASIS_LO) {
+    HIPCHECK(h, upload(h, h->bLoQx, g.lo_qx, st));
+    HIPCHECK(h, upload(h, h->bLoQw, g.lo_qw, st));
+    HIPCHECK(h, upload(h, h->bLoQoff, g.lo_qoff, st));
+    HIPCHECK(h, upload(h, h->bLoAng, h->lo_ang, st));
+    HIPCHECK(h, upload(h, h->bKG, h->lo_kg, st));
+    HIPCHECK(h, upload(h, h->bOff2G, h->lo_off2g, st));
+  }
   HIPCHECK(h, upload(h, h->bNItem, nitem, st));
   HIPCHECK(h, upload(h, h->bNFace, nface, st));
   HIPCHECK(h, upload(h, h->bNCount, ncount, st));
@@ -1752,6 +1818,7 @@ int32_t swr_assemble(swr_handle h, void* stream) {
   swr::Potential pot{g.desc.n_nuc, h->ptr<double>(h->bPos), h->ptr<double>(h->bCharge),
                      g.desc.eps_en, g.desc.eps_ee};
   const bool lsd = g.desc.basis_kind == SWR_BASIS_LSD;
+  const bool lo = g.desc.basis_kind == SWR_BASIS_LO;
   const bool slater = g.desc.basis_kind == SWR_BASIS_SLATER || lsd;
   if (lsd) {
     // Section 3: the local orbitals of every interval, then the items'
@@ -1782,6 +1849,43 @@ int32_t swr_assemble(swr_handle h, void* stream) {
     HIPCHECK(h, swr::launch_slater_potential(it, pot, h->ptr<int64_t>(h->bScrOff),
                                              h->ptr<double>(h->bScr), n_max, q_max,
                                              h->ptr<double>(h->bV), g.K_max, st));
+  } else if (lo) {
+    // Section 3 in d = 2: the box's Gaussian matrices, its orbitals, then
+    // every matrix as C^T (Gaussian matrix) C
+    const swr::Items itg = h->items_gaussian();
+    int kg_max = 1;
+    for (const int k : h->lo_kg) kg_max = std::max(kg_max, k);
+    HIPCHECK(h, swr::launch_assemble(itg, h->ptr<double>(h->bAG), h->ptr<double>(h->bKinG),
+                                     h->ptr<double>(h->bQG), nullptr, h->ptr<double>(h->bBG),
+                                     h->ptr<double>(h->bWG), h->ptr<double>(h->bS1),
+                                     h->ptr<int64_t>(h->bS1Off), kg_max, st));
+    HIPCHECK(h, swr::launch_potential(itg, pot, h->ptr<double>(h->bS1),
+                                      h->ptr<int64_t>(h->bS1Off), h->ptr<double>(h->bVG),
+                                      h->ptr<double>(h->bScr), h->ptr<int64_t>(h->bScrOff), st));
+    const int order = g.desc.lsd_moll_order;
+    const double e = g.desc.lsd_moll_eps;
+    // 2 sigma 2^(2M+1) (M!)^2 / ((2M+1)! eps^(2M+2)), sigma = (M+1) / pi, and
+    // 2^(2M+1) (M!)^2 / (2M+1)! = 2 prod_{j <= M} 2j / (2j + 1)
+    double pref = 2.0 * (order + 1) / 3.14159265358979323846 * 2.0;
+    for (int j = 1; j <= order; ++j) pref *= (2.0 * j) / (2.0 * j + 1.0);
+    pref /= std::pow(e, 2 * order + 2);
+    int64_t nq1 = 1;
+    for (int s = 0; s < g.n_items; ++s)
+      nq1 = std::max(nq1, g.lo_qoff[2 * s + 2] - g.lo_qoff[2 * s + 1]);
+    const swr::LoParams lp{g.desc.lsd_barrier, g.desc.lsd_barrier_width, g.desc.lsd_v_inf, e,
+                           pref, order, g.desc.lsd_orbitals};
+    HIPCHECK(h, swr::launch_lo2_orbitals(it, pot, lp, h->ptr<double>(h->bLoQx),
+                                         h->ptr<double>(h->bLoQw), h->ptr<int64_t>(h->bLoQoff),
+                                         h->ptr<double2>(h->bLoAng), (int)g.lo_mx.size(), nq1,
+                                         h->ptr<double>(h->bLoGt), h->ptr<double>(h->bLoTab),
+                                         h->ptr<double>(h->bLoPP), h->ptr<double>(h->bLoC),
+                                         h->ptr<int>(h->bFlags), st));
+    const int64_t* og = h->ptr<int64_t>(h->bOff2G);
+    const std::pair<Buf, Buf> mats[] = {{h->bAG, h->bA},   {h->bKinG, h->bKin}, {h->bVG, h->bV},
+                                        {h->bQG, h->bQ},   {h->bBG, h->bB},     {h->bWG, h->bW}};
+    for (const auto& m : mats)
+      HIPCHECK(h, swr::launch_lo2_transform(it, og, h->ptr<double>(m.first),
+                                            h->ptr<double>(m.second), st));
   } else {
     HIPCHECK(h, swr::launch_assemble(it, h->ptr<double>(h->bA), h->ptr<double>(h->bKin),
                                      h->ptr<double>(h->bQ), it.Q2 ? h->ptr<double>(h->bQ2) : nullptr,
@@ -1789,7 +1893,7 @@ int32_t swr_assemble(swr_handle h, void* stream) {
                                      h->ptr<double>(h->bS1),
                                      h->ptr<int64_t>(h->bS1Off), g.K_max, st));
   }
-  if (slater) {
+  if (slater || lo) {
     // V assembled above
   } else if (h->wide)
     HIPCHECK(h, swr::launch_potential_wide(it, pot, h->ptr<double>(h->bV), g.K_max, st));
@@ -1822,9 +1926,9 @@ int32_t swr_assemble(swr_handle h, void* stream) {
   HIPCHECK(h, swr::launch_face_gram(it, nd, h->ptr<double>(h->bG), g.K_max, st));
   // the uploads above read host vectors local to this call
   HIPCHECK(h, hipStreamSynchronize(st));
-  if (lsd) {
-    // the determinants' Gram matrices A against the same limit as the
-    // tensor bases' at swr_create
+  if (lsd || lo) {
+    // the determinants' (orbitals') Gram matrices A against the same limit
+    // as the tensor bases' at swr_create
     std::vector<double> A(h->sum_K2);
     HIPCHECK(h, hipMemcpy(A.data(), h->ptr<double>(h->bA), h->sum_K2 * 8, hipMemcpyDeviceToHost));
     double worst = 1.0;
@@ -1835,9 +1939,10 @@ int32_t swr_assemble(swr_handle h, void* stream) {
     if (!(worst <= kCondLimit)) {
       char buf[240];
       std::snprintf(buf, sizeof buf,
-                    "a subdomain's determinant Gram matrix has condition %.3g, above the %.0e "
+                    "a subdomain's %s Gram matrix has condition %.3g, above the %.0e "
                     "the stored-inverse recurrence keeps to 1e-10 (fewer orbitals or added "
-                    "Gaussians, or wider overlaps)", worst, kCondLimit);
+                    "Gaussians, or wider overlaps)", lo ? "orbital" : "determinant", worst,
+                    kCondLimit);
       return fail(h, worst <= kSingularLimit ? SWR_E_COND : SWR_E_SINGULAR, buf);
     }
   }

@@ -111,8 +111,25 @@ std::string build_geometry(const swr_desc& d, Geometry* g, int* code) {
   if (!(d.width > 0.0) && !(d.width_ratio > 0.0)) return "width or width_ratio must be > 0";
   if (d.basis_extend < 0) return "basis_extend must be >= 0";
   if (d.basis_kind != SWR_BASIS_GAUSSIAN && d.basis_kind != SWR_BASIS_SLATER &&
-      d.basis_kind != SWR_BASIS_LSD)
-    return "basis_kind must be SWR_BASIS_GAUSSIAN, SWR_BASIS_SLATER or SWR_BASIS_LSD";
+      d.basis_kind != SWR_BASIS_LSD && d.basis_kind != SWR_BASIS_LO)
+    return "basis_kind must be SWR_BASIS_GAUSSIAN, SWR_BASIS_SLATER, SWR_BASIS_LSD or SWR_BASIS_LO";
+  if (d.basis_kind == SWR_BASIS_LO) {
+    if (d.n_elec != 1 || d.dim != 2)
+      return "local orbitals (SWR_BASIS_LO) are for one electron in two dimensions";
+    if (!d.nbasis || d.nbasis[0] < 1 || d.nbasis[1] < 1 || d.nbasis[0] > 8 || d.nbasis[1] > 8)
+      return "local orbitals take 1..8 Gaussians per dimension";
+    if (!(d.lsd_orbitals >= 1 && d.lsd_orbitals <= d.nbasis[0] * d.nbasis[1]))
+      return "lsd_orbitals must be in 1..(Gaussians per box)";
+    if (!(d.lsd_barrier > 0.0) || !(d.lsd_barrier_width > 0.0) || !(d.lsd_v_inf >= 0.0) ||
+        !(d.lsd_moll_eps > 0.0) || d.lsd_moll_order < 2 || d.lsd_moll_order > 8)
+      return "local orbitals need lsd_barrier, lsd_barrier_width, lsd_moll_eps > 0, "
+             "lsd_v_inf >= 0 and lsd_moll_order in 2..8";
+    if (d.lsd_augment != 0) return "lsd_augment applies to local Slater determinants only";
+    if (d.n_geom != 1) return "local orbitals take one geometry";
+    if (d.field_shape != SWR_FIELD_SINE) return "local orbitals take the sine field";
+    if (d.factor_mode == SWR_FACTOR_BLOCK || d.factor_mode == SWR_FACTOR_WIDE)
+      return "local orbitals run on the narrow path";
+  }
   if (d.basis_kind == SWR_BASIS_LSD) {
     if (!(d.lsd_orbitals >= 2 && d.lsd_orbitals <= 8 && d.nbasis && d.lsd_orbitals <= d.nbasis[0]))
       return "lsd_orbitals must be in 2..8 and at most the Gaussians per interval";
@@ -236,6 +253,7 @@ std::string build_geometry(const swr_desc& d, Geometry* g, int* code) {
       g->qx.insert(g->qx.end(), x.begin(), x.end());
       g->qw.insert(g->qw.end(), w.begin(), w.end());
     }
+    if (d.basis_kind == SWR_BASIS_LO) K = d.lsd_orbitals;  // Section 3, d = 2
     if (d.basis_kind == SWR_BASIS_SLATER || d.basis_kind == SWR_BASIS_LSD) {
       // Section 2 eq. (LSD): antisymmetrised pairs of Gaussians (or, Section
       // 3, of local orbitals); l < p on the diagonal
@@ -376,6 +394,39 @@ std::string build_geometry(const swr_desc& d, Geometry* g, int* code) {
       g->lo_qw.insert(g->lo_qw.end(), w.begin(), w.end());
       g->lo_qoff.push_back((int64_t)g->lo_qx.size());
     }
+    gauss_legendre(64, &g->lo_mx, &g->lo_mw);
+  }
+  if (d.basis_kind == SWR_BASIS_LO) {
+    // one electron in two dimensions: the rule per (item s, dimension k) at
+    // lo_qoff[2 s + k] (the same recipe as the oracle's): composite
+    // 16-point Gauss-Legendre on [x_c - R, x_c + R], R = x_b + eps_b / 2 +
+    // 7 / sqrt(delta), breaks at the barrier's transition edges and at every
+    // nucleus +- eps inside the range, panels no wider than 0.4 / sqrt(delta)
+    for (int s = 0; s < NI; ++s)
+      for (int k = 0; k < 2; ++k) {
+        const size_t q = (size_t)s * kMaxD + k;
+        const double xc = 0.5 * (g->lo[q] + g->hi[q]), dl = g->delta[q];
+        const double xb = d.lsd_barrier, eb = d.lsd_barrier_width, em = d.lsd_moll_eps;
+        const double R = xb + 0.5 * eb + 7.0 / std::sqrt(dl), h = 0.4 / std::sqrt(dl);
+        std::vector<double> br = {xc - R, xc - xb - 0.5 * eb, xc - xb + 0.5 * eb,
+                                  xc + xb - 0.5 * eb, xc + xb + 0.5 * eb, xc + R};
+        for (int a = 0; a < d.n_nuc; ++a)
+          for (const double e : {d.nuc_pos[a * 2 + k] - em, d.nuc_pos[a * 2 + k] + em})
+            if (xc - R < e && e < xc + R) br.push_back(e);
+        std::sort(br.begin(), br.end());
+        br.erase(std::unique(br.begin(), br.end()), br.end());
+        std::vector<double> edges;
+        for (size_t b = 0; b + 1 < br.size(); ++b) {
+          const int np = std::max(1, (int)std::ceil((br[b + 1] - br[b]) / h));
+          for (int j = 0; j < np; ++j) edges.push_back(br[b] + (br[b + 1] - br[b]) * j / np);
+        }
+        edges.push_back(br.back());
+        std::vector<double> x, w;
+        composite(edges, std::vector<int>(edges.size() - 1, 16), &x, &w);
+        g->lo_qx.insert(g->lo_qx.end(), x.begin(), x.end());
+        g->lo_qw.insert(g->lo_qw.end(), w.begin(), w.end());
+        g->lo_qoff.push_back((int64_t)g->lo_qx.size());
+      }
     gauss_legendre(64, &g->lo_mx, &g->lo_mw);
   }
 

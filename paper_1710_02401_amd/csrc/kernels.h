@@ -25,6 +25,10 @@ struct Items {
   int lsd, n_orb;
   const double* lo_C;
   const double* lo_tab;
+  // 1: local orbitals of one electron in two dimensions (Section 3, d = 2):
+  // item s's function l is sum_u C[u][l] g_u over its tensor Gaussians g_u
+  // (u = u0 nb1 + u1), C at lo_C + s nb0 nb1 n_orb, entry u * n_orb + l
+  int lo2;
   // configuration coordinates (bit el * dim + a) the field couples to: the
   // first (or only) component and the second of a circular field (0: none)
   int qmask0, qmask1;

@@ -389,8 +389,42 @@ __global__ void k_pot2_combine(Items it, const double* S1, const int64_t* s1off,
 // ---------------------------------------------------------------------------
 // Basis values at a point: v_l(y) = prod_k phi_{l_k}(y_k) (or the Slater
 // pair of slater.h)
+// Local orbital l of item s (one electron, two dimensions) at y, and its
+// derivative along dimension kf when dv is given.
+__device__ inline double lo2_value(const Items& it, int s, int l, const double* y, int kf,
+                                   double* dv) {
+  const int n0 = it.nb[4 * s], n1 = it.nb[4 * s + 1], M = it.n_orb;
+  const double d0 = it.delta[4 * s], d1 = it.delta[4 * s + 1];
+  const double* a0 = it.alpha + it.aoff[4 * s];
+  const double* a1 = it.alpha + it.aoff[4 * s + 1];
+  const double* C = it.lo_C + (int64_t)s * n0 * n1 * M + l;
+  double g1[8], h1[8];  // at most 8 Gaussians per dimension
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const double t = u < n1 ? y[1] - a1[u] : 0.0;
+    g1[u] = exp(-d1 * t * t);
+    h1[u] = kf == 1 ? -2.0 * d1 * t * g1[u] : g1[u];
+  }
+  double v = 0.0, w = 0.0;
+  for (int u0 = 0; u0 < n0; ++u0) {
+    const double t = y[0] - a0[u0];
+    const double g0 = exp(-d0 * t * t);
+    const double h0 = kf == 0 ? -2.0 * d0 * t * g0 : g0;
+#pragma unroll
+    for (int u1 = 0; u1 < 8; ++u1)
+      if (u1 < n1) {
+        const double c = C[(int64_t)(u0 * n1 + u1) * M];
+        v = fma(c * g0, g1[u1], v);
+        w = fma(c * h0, h1[u1], w);
+      }
+  }
+  if (dv) *dv = w;
+  return v;
+}
+
 __device__ inline double basis_value(const Items& it, int s, int l, const double* y) {
   if (it.slater) return slater_value(it, s, l, y, nullptr);
+  if (it.lo2) return lo2_value(it, s, l, y, 0, nullptr);
   const int32_t* nb = it.nb + 4 * s;
   int li[4];
   split_index(l, nb, it.D, li);
@@ -412,6 +446,7 @@ __device__ inline double basis_value_deriv(const Items& it, int j, int m, const 
     *dv = gr[kf];
     return v;
   }
+  if (it.lo2) return lo2_value(it, j, m, y, kf, dv);
   int mi[4];
   split_index(m, it.nb + 4 * j, it.D, mi);
   double v = 1.0;
@@ -581,7 +616,12 @@ __global__ void k_project(Items it, const double* A, double init_alpha, const do
   __shared__ double b[kSmallK];
   for (int e = threadIdx.x; e < K * K; e += blockDim.x) a[e] = A[it.off2[s] + e];
   const double norm = pow(2.0 * init_alpha / M_PI, 0.25 * D);
-  for (int l = threadIdx.x; l < K; l += blockDim.x) {
+  // local orbitals: the projections onto the box's Gaussians first, then
+  // c~_l = sum_u C[u][l] c~_u
+  __shared__ double bg[kSmallK];
+  const int KG = it.lo2 ? it.nb[4 * s] * it.nb[4 * s + 1] : K;
+  double* bt = it.lo2 ? bg : b;
+  for (int l = threadIdx.x; l < KG; l += blockDim.x) {
     int li[4];
     split_index(l, it.nb + 4 * s, D, li);
     double v = norm;
@@ -590,9 +630,18 @@ __global__ void k_project(Items it, const double* A, double init_alpha, const do
       v *= pair_overlap(al, it.delta[4 * s + k], center[k], init_alpha, it.lo[4 * s + k],
                         it.hi[4 * s + k]);
     }
-    b[l] = v;
+    bt[l] = v;
   }
   __syncthreads();
+  if (it.lo2) {
+    const double* C = it.lo_C + (int64_t)s * KG * K;
+    for (int l = threadIdx.x; l < K; l += blockDim.x) {
+      double v = 0.0;
+      for (int u = 0; u < KG; ++u) v = fma(C[u * K + l], bg[u], v);
+      b[l] = v;
+    }
+    __syncthreads();
+  }
   // forward elimination without pivoting
   for (int p = 0; p < K; ++p) {
     const double piv = a[p * K + p];

@@ -131,4 +131,22 @@ hipError_t launch_lo_orbitals(const Items& it, int n_iv, const Potential& pot, L
 // extended orbitals into it.lo_tab (needs it.lo_C).
 hipError_t launch_lo_tables(const Items& it, double* tab, hipStream_t st);
 
+// Local orbitals of one electron in two dimensions (Section 3, d = 2), per
+// item (box) s: the Gaussians at the orbital rule's nodes (x, w at
+// qoff[2 s + k] .. qoff[2 s + k + 1] for dimension k) into gt, the
+// one-dimensional integrals into tab, the nuclear term's first contraction
+// into pp (64 per dimension-1 node), then the orbital problem (S, H over the
+// box's n0 n1 <= 64 Gaussians) and its lp.n_eig lowest orbitals into C_out
+// (n0 n1 x n_eig per item).  lp.sigma is the mollified Coulomb kernel's
+// prefactor (slater.hip); ang: (sin, cos) of the angle rule's nodes on
+// [0, pi/2], then (weight, 0).
+hipError_t launch_lo2_orbitals(const Items& it, const Potential& pot, LoParams lp,
+                               const double* qx, const double* qw, const int64_t* qoff,
+                               const double2* ang, int n_m, int64_t n_q1_max, double* gt,
+                               double* tab, double* pp, double* C_out, int* flags,
+                               hipStream_t st);
+// X = C^T XG C per item (XG over the box's Gaussians at offsets og).
+hipError_t launch_lo2_transform(const Items& it, const int64_t* og, const double* XG, double* X,
+                                hipStream_t st);
+
 }  // namespace swr

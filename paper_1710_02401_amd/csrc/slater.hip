@@ -304,9 +304,10 @@ __device__ inline double lo_mollified(double x, double Z, double eta, const LoPa
   return acc;
 }
 
-// Generalised symmetric eigenproblem H c = lambda S c (n <= kLoN) by one
+// Generalised symmetric eigenproblem H c = lambda S c (n <= NMAX) by one
 // thread: Cholesky S = L L^T, A = L^{-1} H L^{-T}, cyclic Jacobi on A, the
 // M lowest eigenvectors back-transformed, C[u * ld + l].
+template <int NMAX>
 __device__ void lo_eigen(int n, int M, int ld, double* S, double* H, double* V, double* C,
                          int* flags) {
   for (int j = 0; j < n; ++j) {
@@ -372,14 +373,14 @@ __device__ void lo_eigen(int n, int M, int ld, double* S, double* H, double* V, 
         }
       }
   }
-  bool used[kLoN] = {};
+  bool used[NMAX] = {};
   for (int l = 0; l < M; ++l) {
     int best = -1;
     for (int i = 0; i < n; ++i)
       if (!used[i] && (best < 0 || H[i * n + i] < H[best * n + best])) best = i;
     used[best] = true;
     // c = L^{-T} v (back substitution)
-    double c[kLoN];
+    double c[NMAX];
     for (int i = n - 1; i >= 0; --i) {
       double v = V[i * n + best];
       for (int k = i + 1; k < n; ++k) v -= S[k * n + i] * c[k];
@@ -449,7 +450,7 @@ __global__ void __launch_bounds__(kST) k_lo_orbitals(Items it, Potential pot, Lo
   }
   __syncthreads();
   double* C = C_out + (int64_t)i * n * M;
-  if (threadIdx.x == 0) lo_eigen(n, lp.n_eig, M, Sm, Hm, Vm, C, flags);
+  if (threadIdx.x == 0) lo_eigen<kLoN>(n, lp.n_eig, M, Sm, Hm, Vm, C, flags);
   // Section 3.3: the Gaussians added at the interval's ends, unit columns
   const int g = (M - lp.n_eig) / 2;
   for (int e = threadIdx.x; e < n * 2 * g; e += blockDim.x) {
@@ -513,6 +514,193 @@ __global__ void __launch_bounds__(kST) k_lo_tables(Items it, double* tab) {
   }
 }
 
+
+// ---- local orbitals of one electron in two dimensions (Section 3, d = 2) ----
+
+// (1/|.| * B)(rho), B(y) = sigma / eps^2 (1 - |y|^2 / eps^2)^M on |y| <= eps.
+// About the evaluation point, the two rays of directions theta and
+// theta + pi together cross the support along one chord of length 2 sqrt(D),
+// D = eps^2 - rho^2 sin^2 theta, on which B integrates in closed form,
+// int ((r - r1)(r2 - r))^M dr = (r2 - r1)^(2M+1) (M!)^2 / (2M+1)!; so
+//   G = pref int_0^{pi/2} D^(M+1/2) dtheta                                   (rho <= eps),
+//   G = pref int_0^{pi/2} (eps cos p)^(2M+1) (eps/rho) cos p / sqrt(1 - (eps sin p / rho)^2) dp
+//                                         (rho > eps, sin theta = (eps / rho) sin p),
+// pref = 2 sigma 2^(2M+1) (M!)^2 / ((2M+1)! eps^(2M+2)) (lp.sigma), both by
+// a Gauss-Legendre rule on [0, pi/2]: ang[j] = (sin, cos) of its nodes,
+// ang[n_m + j] = (weight, 0).
+__device__ double lo2_coulomb(double rho, const LoParams& lp, const double2* ang, int n_m) {
+  const double e = lp.eps;
+  double acc = 0.0;
+  if (rho <= e) {
+    for (int j = 0; j < n_m; ++j) {
+      const double sn = ang[j].x * rho;
+      const double D = e * e - sn * sn;
+      double p = sqrt(D);
+      for (int k = 0; k < lp.order; ++k) p *= D;
+      acc = fma(ang[n_m + j].x, p, acc);
+    }
+  } else {
+    const double r = e / rho;
+    for (int j = 0; j < n_m; ++j) {
+      const double c = ang[j].y, sn = ang[j].x * r;
+      const double pe = e * c;
+      double p = pe;
+      for (int k = 0; k < lp.order; ++k) p *= pe * pe;
+      acc = fma(ang[n_m + j].x, p * r * c / sqrt(1.0 - sn * sn), acc);
+    }
+  }
+  return lp.sigma * acc;
+}
+
+// Per (item s, dimension k): the Gaussians at the orbital rule's nodes,
+// gt[q * 8 + u] (q the rule's global node index), and the one-dimensional
+// integrals tab[((s * 2 + k) * 4 + kind) * 64 + u * 8 + w] of kind
+// S = int g g, A = int a g g, Ad = int a g' g', Bs = int s g g over the rule.
+__global__ void __launch_bounds__(kST) k_lo2_tables(Items it, LoParams lp, const double* qx,
+                                                    const double* qw, const int64_t* qoff,
+                                                    double* gt, double* tab) {
+  const int s = blockIdx.x, k = blockIdx.y;
+  const int n = it.nb[4 * s + k];
+  const double* al = it.alpha + it.aoff[4 * s + k];
+  const double dl = it.delta[4 * s + k];
+  const double xc = 0.5 * (it.lo[4 * s + k] + it.hi[4 * s + k]);
+  const int64_t q0 = qoff[2 * s + k], q1 = qoff[2 * s + k + 1];
+  for (int64_t e = threadIdx.x; e < (q1 - q0) * 8; e += blockDim.x) {
+    const int64_t q = q0 + e / 8;
+    const int u = (int)(e % 8);
+    gt[q * 8 + u] = u < n ? exp(-dl * (qx[q] - al[u]) * (qx[q] - al[u])) : 0.0;
+  }
+  const int kind = threadIdx.x >> 6, u = (threadIdx.x >> 3) & 7, w = threadIdx.x & 7;
+  if (u >= n || w >= n) return;
+  double acc = 0.0;
+  for (int64_t q = q0; q < q1; ++q) {
+    const double x = qx[q];
+    const double gu = exp(-dl * (x - al[u]) * (x - al[u]));
+    const double gw = exp(-dl * (x - al[w]) * (x - al[w]));
+    const double st = lo_step(fabs(x - xc) - lp.barrier, lp.width);
+    double f;
+    if (kind == 0) f = gu * gw;
+    else if (kind == 1) f = (1.0 - st) * gu * gw;
+    else if (kind == 2) f = (1.0 - st) * (-2.0 * dl * (x - al[u]) * gu) * (-2.0 * dl * (x - al[w]) * gw);
+    else f = st * gu * gw;
+    acc = fma(qw[q], f, acc);
+  }
+  tab[((s * 2 + k) * 4 + kind) * 64 + u * 8 + w] = acc;
+}
+
+// First contraction of the nuclear term: for the item's dimension-1 nodes
+// q1 of this block (64 of them) and pairs p = (u0, w0),
+//   P[q1][p] = sum_{q0} w0 w1 V_n(x0, x1) g0[q0][u0] g0[q0][w0],
+// V_n = sum_A -Z_A G(|x - R_A|), P at pp[q1 * 64 + p] (q1 global).
+constexpr int kLo2Q = 64;
+__global__ void __launch_bounds__(kST) k_lo2_nuclear(Items it, Potential pot, LoParams lp,
+                                                     const double* qx, const double* qw,
+                                                     const int64_t* qoff, const double2* ang,
+                                                     int n_m, const double* gt, double* pp) {
+  const int s = blockIdx.x;
+  const int64_t b0 = qoff[2 * s], b1 = qoff[2 * s + 1], c0 = qoff[2 * s + 1], c1 = qoff[2 * s + 2];
+  const int64_t q1a = c0 + (int64_t)blockIdx.y * kLo2Q;
+  if (q1a >= c1) return;  // uniform over the block
+  const int n0 = it.nb[4 * s];
+  __shared__ double sv[kLo2Q][kLo2Q + 1];  // [q0 - chunk][q1 - q1a]
+  __shared__ double sg[kLo2Q][8];
+  const int ql = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int64_t q1 = q1a + ql;
+  double acc[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) acc[j] = 0.0;
+  for (int64_t ch = b0; ch < b1; ch += kLo2Q) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < kLo2Q * kLo2Q; e += blockDim.x) {
+      const int a = e / kLo2Q, bq = e % kLo2Q;
+      const int64_t qa = ch + a, qb = q1a + bq;
+      double v = 0.0;
+      if (qa < b1 && qb < c1) {
+        const double x0 = qx[qa], x1 = qx[qb];
+        for (int A = 0; A < pot.n_nuc; ++A) {
+          const double r0 = x0 - pot.pos[2 * A], r1 = x1 - pot.pos[2 * A + 1];
+          v -= pot.charge[A] * lo2_coulomb(sqrt(r0 * r0 + r1 * r1), lp, ang, n_m);
+        }
+        v *= qw[qa] * qw[qb];
+      }
+      sv[a][bq] = v;
+    }
+    for (int e = threadIdx.x; e < kLo2Q * 8; e += blockDim.x) {
+      const int64_t qa = ch + e / 8;
+      sg[e / 8][e % 8] = qa < b1 ? gt[qa * 8 + e % 8] : 0.0;
+    }
+    __syncthreads();
+    const int lim = b1 - ch < kLo2Q ? (int)(b1 - ch) : kLo2Q;
+    for (int a = 0; a < lim; ++a) {
+      const double v = sv[a][ql];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int p = grp * 16 + j;  // (u0, w0) = (p / 8, p % 8)
+        acc[j] = fma(v * sg[a][p >> 3], sg[a][p & 7], acc[j]);
+      }
+    }
+  }
+  if (q1 < c1)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int p = grp * 16 + j;
+      if ((p >> 3) < n0 && (p & 7) < n0) pp[q1 * 64 + p] = acc[j];
+    }
+}
+
+// The orbital problem of item s: N[(u0,w0),(u1,w1)] = sum_{q1} P[q1][(u0,w0)]
+// g1[q1][u1] g1[q1][w1], then S = S0 x S1 and
+// H = 1/2 (Ad0 x A1 + A0 x Ad1) + V_inf (Bs0 x S1 + S0 x Bs1) + N over
+// u = u0 n1 + u1, and the n_eig lowest orbitals into C_out + s n0 n1 n_eig.
+__global__ void __launch_bounds__(kST) k_lo2_orbitals(Items it, LoParams lp, const int64_t* qoff,
+                                                      const double* gt, const double* pp,
+                                                      const double* tab, double* C_out,
+                                                      int* flags) {
+  const int s = blockIdx.x;
+  const int n0 = it.nb[4 * s], n1 = it.nb[4 * s + 1], KG = n0 * n1;
+  __shared__ double Sm[kSmallK * kSmallK], Hm[kSmallK * kSmallK], Vm[kSmallK * kSmallK];
+  const double* t0 = tab + (size_t)(s * 2) * 4 * 64;
+  const double* t1 = tab + (size_t)(s * 2 + 1) * 4 * 64;
+  const int64_t c0 = qoff[2 * s + 1], c1 = qoff[2 * s + 2];
+  for (int e = threadIdx.x; e < KG * KG; e += blockDim.x) {
+    const int ua = e / KG, wa = e % KG;
+    const int u0 = ua / n1, u1 = ua % n1, w0 = wa / n1, w1 = wa % n1;
+    const int p0 = u0 * 8 + w0, p1 = u1 * 8 + w1;
+    double nuc = 0.0;
+    for (int64_t q = c0; q < c1; ++q) nuc = fma(pp[q * 64 + p0], gt[q * 8 + u1] * gt[q * 8 + w1], nuc);
+    const double S0 = t0[p0], A0 = t0[64 + p0], Ad0 = t0[128 + p0], B0 = t0[192 + p0];
+    const double S1 = t1[p1], A1 = t1[64 + p1], Ad1 = t1[128 + p1], B1 = t1[192 + p1];
+    Sm[e] = S0 * S1;
+    Hm[e] = 0.5 * (Ad0 * A1 + A0 * Ad1) + lp.v_inf * (B0 * S1 + S0 * B1) + nuc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    lo_eigen<kSmallK>(KG, lp.n_eig, lp.n_eig, Sm, Hm, Vm, C_out + (int64_t)s * KG * lp.n_eig, flags);
+}
+
+// Every matrix of the basis: X[l][m] = sum_{u,w} C[u][l] XG[u][w] C[w][m],
+// XG over the item's Gaussians (offsets og), X over its orbitals (it.off2).
+__global__ void __launch_bounds__(kST) k_lo2_transform(Items it, const int64_t* og,
+                                                       const double* XG, double* X) {
+  const int s = blockIdx.x;
+  const int KG = it.nb[4 * s] * it.nb[4 * s + 1], M = it.n_orb;
+  const double* C = it.lo_C + (int64_t)s * KG * M;
+  __shared__ double Y[kSmallK * kSmallK];  // [u][m] = sum_w XG[u][w] C[w][m]
+  for (int e = threadIdx.x; e < KG * M; e += blockDim.x) {
+    const int u = e / M, m = e % M;
+    double v = 0.0;
+    for (int w = 0; w < KG; ++w) v = fma(XG[og[s] + (int64_t)u * KG + w], C[w * M + m], v);
+    Y[e] = v;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < M * M; e += blockDim.x) {
+    const int l = e / M, m = e % M;
+    double v = 0.0;
+    for (int u = 0; u < KG; ++u) v = fma(C[u * M + l], Y[u * M + m], v);
+    X[it.off2[s] + e] = v;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_slater_assemble(const Items& it, double* A, double* Kin, double* Q, double* B,
@@ -557,6 +745,27 @@ hipError_t launch_lo_orbitals(const Items& it, int n_iv, const Potential& pot, L
 
 hipError_t launch_lo_tables(const Items& it, double* tab, hipStream_t st) {
   hipLaunchKernelGGL(k_lo_tables, dim3(it.n_items, 2), dim3(kST), 0, st, it, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_lo2_orbitals(const Items& it, const Potential& pot, LoParams lp,
+                               const double* qx, const double* qw, const int64_t* qoff,
+                               const double2* ang, int n_m, int64_t n_q1_max, double* gt,
+                               double* tab, double* pp, double* C_out, int* flags,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_lo2_tables, dim3(it.n_items, 2), dim3(kST), 0, st, it, lp, qx, qw, qoff,
+                     gt, tab);
+  const int chunks = (int)((n_q1_max + kLo2Q - 1) / kLo2Q);
+  hipLaunchKernelGGL(k_lo2_nuclear, dim3(it.n_items, chunks), dim3(kST), 0, st, it, pot, lp, qx,
+                     qw, qoff, ang, n_m, gt, pp);
+  hipLaunchKernelGGL(k_lo2_orbitals, dim3(it.n_items), dim3(kST), 0, st, it, lp, qoff, gt, pp,
+                     tab, C_out, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_lo2_transform(const Items& it, const int64_t* og, const double* XG, double* X,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(k_lo2_transform, dim3(it.n_items), dim3(kST), 0, st, it, og, XG, X);
   return hipGetLastError();
 }
 

@@ -19,7 +19,7 @@ SWR_TDSE, SWR_TISE = 0, 1
 SWR_WARM_PLAIN, SWR_WARM_ZERO, SWR_WARM_GIVEN = 0, 1, 2
 SWR_FACTOR_AUTO, SWR_FACTOR_DIRECT, SWR_FACTOR_WIDE, SWR_FACTOR_BLOCK = 0, 1, 2, 3
 SWR_FIELD_SINE, SWR_FIELD_CIRCULAR = 0, 1
-SWR_BASIS_GAUSSIAN, SWR_BASIS_SLATER, SWR_BASIS_LSD = 0, 1, 2
+SWR_BASIS_GAUSSIAN, SWR_BASIS_SLATER, SWR_BASIS_LSD, SWR_BASIS_LO = 0, 1, 2, 3
 MATRICES = {"A": 0, "Kin": 1, "V": 2, "Q": 3, "B": 4, "W": 5, "G": 6, "Q2": 7}
 
 _c_i32p = ctypes.POINTER(ctypes.c_int32)
@@ -243,9 +243,10 @@ def desc_from_config(cfg):
                      "wide": SWR_FACTOR_WIDE, "block": SWR_FACTOR_BLOCK}[cfg.get("factor", "auto")]
     d.unnormalized = 1 if cfg.get("unnormalized", False) else 0
     d.basis_kind = {"gaussian": SWR_BASIS_GAUSSIAN, "slater": SWR_BASIS_SLATER,
-                    "lsd": SWR_BASIS_LSD}[cfg.get("basis", "gaussian")]
-    if "lsd" in cfg and d.basis_kind == SWR_BASIS_LSD:
-        p = cfg["lsd"]
+                    "lsd": SWR_BASIS_LSD, "lo": SWR_BASIS_LO}[cfg.get("basis", "gaussian")]
+    pkey = {SWR_BASIS_LSD: "lsd", SWR_BASIS_LO: "lo"}.get(d.basis_kind)
+    if pkey in cfg:
+        p = cfg[pkey]
         d.lsd_orbitals = int(p["orbitals"])
         d.lsd_barrier = float(p["barrier"])
         d.lsd_barrier_width = float(p["barrier_width"])

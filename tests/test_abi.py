@@ -171,10 +171,10 @@ def _oracle_maps(dec):
 
 @pytest.mark.parametrize("name", ["tiny-1d", "tiny-2d", "c1-1e-1d", "c2-2e-1d", "tiny-slater",
                                   "c2-2e-1d-slater", "tiny-lsd", "paper-lsd-test-2a",
-                                  "tiny-lsd-aug", "paper-lsd-test-2b"])
+                                  "tiny-lsd-aug", "paper-lsd-test-2b", "tiny-lo"])
 def test_index_maps_and_boxes_bit_exact(S, name):
     cfgs = {c["name"]: c for c in workloads.tiny_configs() + workloads.slater_configs()
-            + workloads.lsd_configs()}
+            + workloads.lsd_configs() + workloads.lo_configs()}
     cfg = cfgs.get(name) or workloads.get_config(name)
     lib = S.load_library()
     rc, h = _create(S, cfg)
@@ -261,6 +261,32 @@ def test_batched_geometries_share_one_decomposition(S):
     dec = Decomposition(dict(cfg, nuclei=cfg["geometries"][0]))
     assert np.array_equal(maps[:per_geom], _oracle_maps(dec))
     lib.swr_destroy(h)
+
+
+def test_local_orbital_basis_in_two_dimensions_is_validated(S):
+    """Local orbitals of one electron in two dimensions (Section 3, d = 2)
+    take one electron in two dimensions, 1..(Gaussians per box) orbitals, at
+    most 8 Gaussians per dimension, positive barrier and mollifier widths, a
+    mollifier order of at least 2, no added Gaussians and one geometry."""
+    lib = S.load_library()
+    base = workloads.lo_configs()[0]
+    rc, h = _create(S, base)
+    assert rc == 0
+    info = S.swr_info()
+    assert lib.swr_query(h, ctypes.byref(info)) == 0 and info.K_max == 8 and info.tx_tile == 0
+    lib.swr_destroy(h)
+    bad_lo = [(dict(orbitals=0), "lsd_orbitals"), (dict(orbitals=26), "lsd_orbitals"),
+              (dict(moll_order=1), "lsd_moll_order"), (dict(moll_eps=0.0), "lsd_moll_eps"),
+              (dict(augment=1), "lsd_augment")]
+    for bad, why in bad_lo:
+        rc, h = _create(S, dict(base, lo=dict(base["lo"], **bad)))
+        assert rc == S.SWR_E_ARG, bad
+        assert why in lib.swr_last_error(None).decode(), bad
+    for bad, why in [(dict(nbasis=[9, 5]), "8 Gaussians"),
+                     (dict(n_elec=2, dim=1, nuclei=[[0.3]]), "one electron in two dimensions")]:
+        rc, h = _create(S, dict(base, **bad))
+        assert rc == S.SWR_E_ARG, bad
+        assert why in lib.swr_last_error(None).decode(), bad
 
 
 def test_schedule_is_set_only_after_assembly(S):
