@@ -119,3 +119,51 @@ def test_lo_reconstruction_is_the_oracles():
     ref = o_rec.reconstruct(prob, [h[7] for h in h_o], pts)
     got = _np(s.reconstruct(torch.from_numpy(pts), step=7))
     assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
+def test_full_size_workload_sampled_boxes():
+    """The 4 x 4 workload (8 x 8 Gaussians and 16 orbitals per box, two
+    nuclei): matrices and projected initial coefficients of four boxes
+    (corners and interior), the oracle building only those boxes' orbitals;
+    then the 20-iteration window against the oracle's stored result
+    (tests/golden/lo_1e_2d_window.json, written by make_lo2d_fixture.py):
+    Res(k) to 1e-7 relative, and every box's coefficients at the last step
+    to 1e-10 in the A-norm."""
+    import json
+    import os
+    from oracle import assemble as o_asm
+    from oracle import geometry as o_geo
+    from oracle import lo2 as o_lo2
+    cfg = workloads.get_config("lo-1e-2d")
+    s = _solver(cfg)
+    cg = dict(cfg, basis="gaussian")
+    cg.pop("lo")
+    dec = o_geo.Decomposition(cg)
+    mats = {w: s.matrix(w) for w in ("A", "Kin", "V", "Q", "B", "W")}
+    c0 = [_np(v) for v in s.split_vector(s.initial())]
+    for i in (0, 5, 10, 15):
+        sub = dec.subs[i]
+        sub.lo_coef = o_lo2.orbitals2(cfg, sub)[1]
+        sub.lo2 = True
+        sub.K = sub.lo_coef.shape[1]
+        sy = o_asm.LocalSystem(dec, sub)
+        for which, m in mats.items():
+            ref = getattr(sy, which)
+            assert np.max(np.abs(_np(m[i]) - ref)) <= 1e-11 * np.max(np.abs(ref)), (which, i)
+        ref_c0 = o_asm.project_initial(dec, sub, sy.A)
+        d = c0[i] - ref_c0
+        assert np.sqrt(abs(np.conj(d) @ sy.A @ d) / abs(np.conj(ref_c0) @ sy.A @ ref_c0)) <= 1e-10, i
+    with open(os.path.join(os.path.dirname(__file__), "golden", "lo_1e_2d_window.json")) as f:
+        fx = json.load(f)
+    st = s.run(k_max=fx["iters"], tol=-1.0)
+    for a, b in zip(st["res"], fx["res"]):
+        assert a == pytest.approx(b, rel=1e-7, abs=1e-12)
+    h = [_np(x) for x in s.split_history(s.history())]
+    num = den = 0.0
+    for i, (c, A) in enumerate(zip(fx["last"], fx["A"])):
+        ref = np.array([complex(*z) for z in c])
+        d = h[i][cfg["n_steps"]] - ref
+        A = np.array(A)
+        num += abs(np.conj(d) @ A @ d)
+        den += abs(np.conj(ref) @ A @ ref)
+    assert np.sqrt(num / den) <= 1e-10

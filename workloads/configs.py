@@ -203,6 +203,25 @@ _T2B_LSD = dict(
     lsd=dict(orbitals=4, augment=1, barrier=1.0, barrier_width=0.2, v_inf=30.0, moll_eps=0.1,
              moll_order=4),
 )
+# Local orbitals of one electron in two dimensions (Section 3 with d = 2):
+# 4 x 4 boxes of [-8, 8]^2 (overlap 0.5), 8 x 8 Gaussians per box at 0.7 x
+# spacing, the 16 lowest orbitals of each box (barrier half-width 2.6 about
+# its centre, transition 0.4, height 30, order-4 mollifier of radius 0.2)
+# for a one-electron molecule with two unit charges at (-/+0.7, 0); real
+# time with a complex Robin constant and a sine field, 200 steps, 20
+# iterations.
+_LO_2D = dict(
+    name="lo-1e-2d", mode="tdse", n_elec=1, dim=2, basis="lo",
+    L=[4, 4], box_lo=[-8.0, -8.0], box_hi=[8.0, 8.0], overlap=[0.5, 0.5],
+    nbasis=[8, 8], width=None, width_ratio=0.7,
+    nuclei=[[-0.7, 0.0], [0.7, 0.0]], charges=[1.0, 1.0], eps_en=0.5, eps_ee=0.5,
+    dt=0.01, n_steps=200, mu=[0.0, -4.0],
+    field=dict(E0=0.1, omega=0.5, phase=0.0, axis=0),
+    init=dict(alpha=0.5, center=[0.3, -0.2]),
+    iters=20, tol=1e-8, face_nodes=[16, 32], quad_nodes=16,
+    lo=dict(orbitals=16, barrier=2.6, barrier_width=0.4, v_inf=30.0, moll_eps=0.2,
+            moll_order=4),
+)
 _T2B = dict(_T2A, name="paper-test-2b", box_lo=[-6.5, -6.5], box_hi=[6.5, 6.5],
             overlap=[0.26, 0.26], width=0.5,                  # delta = 2
             nuclei=[[-0.5], [0.5]], dt=0.01, n_steps=400,
@@ -257,7 +276,7 @@ _C2_SLATER_TISE = dict(_C2_TISE, name="c2-2e-1d-slater-tise", basis="slater",
                        init=dict(alpha=1.0, center=[-1.0, 1.0]))
 
 CONFIGS = {c["name"]: c for c in (_C1, _C2, _C2_TISE, _C3, _C3_MINI, _C3_WIDE, _C4, _C5, _T2A_LSD,
-                                   _T2B_LSD,
+                                   _T2B_LSD, _LO_2D,
                                    _C5_K16, _C5_MINI, _C5_MINI_1E, _T1B, _T2A, _T2B, _T3,
                                    _C2_SLATER, _C2_SLATER_TISE)}
 
