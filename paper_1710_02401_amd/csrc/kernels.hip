@@ -1576,10 +1576,12 @@ __global__ void __launch_bounds__(kBlock) k_transmit(Items it, Pairs pr, int n_s
   // sums over the pairs, then the columns, in order
   __shared__ double2 Ts[kTM * kTRow];  // [m - m0][l], rows padded against bank conflicts
   __shared__ double2 Cs[kTN * kSmallK];  // [nn][m]
-  const int l = threadIdx.x & 63;
-  const int nn0 = threadIdx.x >> 6;
-  double2 acc[kTN / 4];
-  for (int q = 0; q < kTN / 4; ++q) acc[q] = make_double2(0.0, 0.0);
+  // thread: receiver functions l0 and l0 + 32, steps nn0 + 8 q (two outputs
+  // per operator entry and coefficient read from LDS)
+  const int l0 = threadIdx.x & 31, l1 = l0 + 32;
+  const int nn0 = threadIdx.x >> 5;
+  double2 acc0[kTN / 8], acc1[kTN / 8];
+  for (int q = 0; q < kTN / 8; ++q) acc0[q] = acc1[q] = make_double2(0.0, 0.0);
   // Stages (pair p, slice from column m0), each one's loads issued into
   // registers while the previous one computes.
   constexpr int kUT = kTM * kSmallK / kBlock, kUC = kTN * kSmallK / kBlock;
@@ -1637,21 +1639,25 @@ __global__ void __launch_bounds__(kBlock) k_transmit(Items it, Pairs pr, int n_s
       ++p;
     }
     if (p < pr.poff[i + 1]) fetch(p, m0);
-    if (l < Ki) {
+    if (l0 < Ki) {
       for (int mm = 0; mm < cnt; ++mm) {
-        const double2 t = Ts[mm * kTRow + l];
-        for (int q = 0; q < kTN / 4; ++q)
-          acc[q] = cfma(t, Cs[(nn0 + 4 * q) * Kj + cm0 + mm], acc[q]);
+        const double2 t0 = Ts[mm * kTRow + l0], t1 = Ts[mm * kTRow + l1];
+        for (int q = 0; q < kTN / 8; ++q) {
+          const double2 c = Cs[(nn0 + 8 * q) * Kj + cm0 + mm];
+          acc0[q] = cfma(t0, c, acc0[q]);
+          acc1[q] = cfma(t1, c, acc1[q]);
+        }
       }
     }
   }
-  if (l < Ki) {
+  if (l0 < Ki) {
     const int64_t fb = (int64_t)(n_steps + 1) * it.off1[i];
-    for (int q = 0; q < kTN / 4; ++q) {
-      const int n = n0 + nn0 + 4 * q;
+    for (int q = 0; q < kTN / 8; ++q) {
+      const int n = n0 + nn0 + 8 * q;
       if (n > n_hi) continue;
       const double sc = scale ? scale[n] : 1.0;
-      F[fb + (int64_t)n * Ki + l] = cscale(acc[q], sc);
+      F[fb + (int64_t)n * Ki + l0] = cscale(acc0[q], sc);
+      if (l1 < Ki) F[fb + (int64_t)n * Ki + l1] = cscale(acc1[q], sc);
     }
   }
 }
