@@ -552,6 +552,171 @@ __device__ double lo2_coulomb(double rho, const LoParams& lp, const double2* ang
   return lp.sigma * acc;
 }
 
+// The generalised problem of lo_eigen solved by the whole block (n <= 64):
+// Cholesky one column at a time, L^{-1} H L^{-T} by triangular solves, one
+// column per thread, then cyclic Jacobi in the round-robin ordering (each
+// round n/2 disjoint rotations, computed from the round's matrix and applied
+// together: disjoint rotations commute), the M lowest eigenvectors
+// back-transformed (one per thread) and signed as lo_eigen's.  Every barrier
+// is reached by every thread (loop bounds are block-uniform).
+__device__ void lo_eigen_block(int n, int M, int ld, double* S, double* H, double* V, double* C,
+                               int* flags) {
+  __shared__ double rc[32], rs[32], red[kST];
+  __shared__ int rp[32], rq[32], order[kSmallK];
+  __shared__ int bad;
+  const int t = threadIdx.x;
+  if (t == 0) bad = 0;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (t == 0) {
+      double d = S[j * n + j];
+      for (int k = 0; k < j; ++k) d -= S[j * n + k] * S[j * n + k];
+      if (!(d > 0.0)) bad = 1;
+      S[j * n + j] = d > 0.0 ? sqrt(d) : 1.0;
+    }
+    __syncthreads();
+    for (int i = j + 1 + t; i < n; i += blockDim.x) {
+      double v = S[i * n + j];
+      for (int k = 0; k < j; ++k) v -= S[i * n + k] * S[j * n + k];
+      S[i * n + j] = v / S[j * n + j];
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    if (t == 0) atomicOr(flags, kFlagPivot);
+    return;  // uniform: bad is read after a barrier
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int c = t; c < n; c += blockDim.x)
+      for (int i = 0; i < n; ++i) {
+        double v = H[i * n + c];
+        for (int k = 0; k < i; ++k) v -= S[i * n + k] * H[k * n + c];
+        H[i * n + c] = v / S[i * n + i];
+      }
+    __syncthreads();
+    for (int e = t; e < n * n; e += blockDim.x) {
+      const int i = e / n, c = e % n;
+      if (c > i) {
+        const double x = H[i * n + c];
+        H[i * n + c] = H[c * n + i];
+        H[c * n + i] = x;
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < n * n; e += blockDim.x) V[e] = (e / n == e % n) ? 1.0 : 0.0;
+  const int m = n + (n & 1);  // players of the round-robin (one idle if n is odd)
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int e = t; e < n * n; e += blockDim.x) {
+      const int i = e / n, c = e % n;
+      const double x = H[e] * H[e];
+      if (i == c) dia += x;
+      else if (c > i) off += x;
+    }
+    red[t] = off;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+      if (t < w) red[t] += red[t + w];
+      __syncthreads();
+    }
+    const double off_all = red[0];
+    __syncthreads();
+    red[t] = dia;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+      if (t < w) red[t] += red[t + w];
+      __syncthreads();
+    }
+    const double dia_all = red[0];
+    __syncthreads();
+    if (off_all <= 1e-34 * dia_all) break;  // uniform
+    for (int r = 0; r < m - 1; ++r) {
+      if (t < m / 2) {
+        int a, b;
+        if (t == 0) {
+          a = r;
+          b = m - 1;
+        } else {
+          a = (r + t) % (m - 1);
+          b = (r - t + m - 1) % (m - 1);
+        }
+        const int p = a < b ? a : b, q = a < b ? b : a;
+        double c = 1.0, sn = 0.0;
+        if (q < n) {
+          const double apq = H[p * n + q];
+          if (apq != 0.0) {
+            const double th = (H[q * n + q] - H[p * n + p]) / (2.0 * apq);
+            const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+            c = 1.0 / sqrt(tt * tt + 1.0);
+            sn = tt * c;
+          }
+        }
+        rp[t] = p;
+        rq[t] = q < n ? q : p;
+        rc[t] = c;
+        rs[t] = sn;
+      }
+      __syncthreads();
+      // columns of H and V
+      for (int e = t; e < (m / 2) * n; e += blockDim.x) {
+        const int g = e / n, k = e % n;
+        const int p = rp[g], q = rq[g];
+        if (p == q) continue;
+        const double c = rc[g], sn = rs[g];
+        const double hp = H[k * n + p], hq = H[k * n + q];
+        H[k * n + p] = c * hp - sn * hq;
+        H[k * n + q] = sn * hp + c * hq;
+        const double vp = V[k * n + p], vq = V[k * n + q];
+        V[k * n + p] = c * vp - sn * vq;
+        V[k * n + q] = sn * vp + c * vq;
+      }
+      __syncthreads();
+      // rows of H
+      for (int e = t; e < (m / 2) * n; e += blockDim.x) {
+        const int g = e / n, k = e % n;
+        const int p = rp[g], q = rq[g];
+        if (p == q) continue;
+        const double c = rc[g], sn = rs[g];
+        const double hp = H[p * n + k], hq = H[q * n + k];
+        H[p * n + k] = c * hp - sn * hq;
+        H[q * n + k] = sn * hp + c * hq;
+      }
+      __syncthreads();
+    }
+  }
+  if (t == 0) {
+    // the M lowest eigenvalues, ascending (ties to the lower index)
+    for (int l = 0; l < M; ++l) {
+      int best = -1;
+      for (int i = 0; i < n; ++i) {
+        bool taken = false;
+        for (int k = 0; k < l; ++k) taken |= order[k] == i;
+        if (!taken && (best < 0 || H[i * n + i] < H[best * n + best])) best = i;
+      }
+      order[l] = best;
+    }
+  }
+  __syncthreads();
+  for (int l = t; l < M; l += blockDim.x) {
+    const int b = order[l];
+    // c = L^{-T} v in place in column b of V (back substitution)
+    for (int i = n - 1; i >= 0; --i) {
+      double v = V[i * n + b];
+      for (int k = i + 1; k < n; ++k) v -= S[k * n + i] * V[k * n + b];
+      V[i * n + b] = v / S[i * n + i];
+    }
+    double sg = 0.0;
+    for (int u = 0; u < n; ++u) sg += (u + 1) * V[u * n + b];
+    const double f = sg < 0.0 ? -1.0 : 1.0;
+    for (int u = 0; u < n; ++u) {
+      const double x = f * V[u * n + b];
+      C[u * ld + l] = x;
+      if (!isfinite(x)) atomicOr(flags, kFlagNaN);
+    }
+  }
+}
+
 // Per (item s, dimension k): the Gaussians at the orbital rule's nodes,
 // gt[q * 8 + u] (q the rule's global node index), and the one-dimensional
 // integrals tab[((s * 2 + k) * 4 + kind) * 64 + u * 8 + w] of kind
@@ -674,8 +839,7 @@ __global__ void __launch_bounds__(kST) k_lo2_orbitals(Items it, LoParams lp, con
     Hm[e] = 0.5 * (Ad0 * A1 + A0 * Ad1) + lp.v_inf * (B0 * S1 + S0 * B1) + nuc;
   }
   __syncthreads();
-  if (threadIdx.x == 0)
-    lo_eigen<kSmallK>(KG, lp.n_eig, lp.n_eig, Sm, Hm, Vm, C_out + (int64_t)s * KG * lp.n_eig, flags);
+  lo_eigen_block(KG, lp.n_eig, lp.n_eig, Sm, Hm, Vm, C_out + (int64_t)s * KG * lp.n_eig, flags);
 }
 
 // Every matrix of the basis: X[l][m] = sum_{u,w} C[u][l] XG[u][w] C[w][m],
