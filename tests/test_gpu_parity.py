@@ -18,7 +18,8 @@ from oracle import tise as o_tise
 
 pytestmark = pytest.mark.gpu
 
-TINY = {c["name"]: c for c in workloads.tiny_configs()}
+TINY = {c["name"]: c for c in workloads.tiny_configs() + workloads.slater_configs()
+        + workloads.lsd_configs() + workloads.lo_configs()}
 
 
 def _cfg(name):
@@ -438,7 +439,7 @@ def test_series_falls_back_to_direct_inversion_for_strong_fields():
     assert s.factor_terms() == -1 and st["iters"] == 2
 
 
-@pytest.mark.parametrize("name", ["tiny-2d", "c2-2e-1d"])
+@pytest.mark.parametrize("name", ["tiny-2d", "c2-2e-1d", "tiny-slater", "tiny-lsd-aug", "tiny-lo"])
 def test_graph_replay_equals_eager_run(name):
     """A fixed-iteration window captured as a HIP graph and replayed, with
     eager runs of another length between the replays, gives the eager run's
@@ -461,7 +462,7 @@ def test_graph_replay_equals_eager_run(name):
         s.run(k_max=2, tol=-1.0)  # eager work between the replays
 
 
-@pytest.mark.parametrize("name", ["tiny-2d", "c2-2e-1d"])
+@pytest.mark.parametrize("name", ["tiny-2d", "c2-2e-1d", "tiny-lsd-aug", "tiny-lo"])
 def test_autotuned_schedule_changes_no_result(name):
     """The autotuner measures every depth and transmission tile and keeps the
     fastest; the schedule only reorders the same arithmetic, so a run under
