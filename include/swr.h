@@ -47,7 +47,7 @@ enum {
   SWR_E_NOCONV = -7,   /* iteration cap reached above the residual target      */
   SWR_E_COND = -8      /* a local Gram matrix is too ill-conditioned for the
                           accuracy of the path (see swr_create and, for
-                          local Slater determinants, swr_assemble)           */
+                          local orbital bases, swr_assemble)                 */
 };
 
 enum { SWR_TDSE = 0, SWR_TISE = 1 };
@@ -239,9 +239,9 @@ int32_t swr_bind_workspace(swr_handle h, void* dev, uint64_t bytes);
  * (Gauss-Legendre quadrature), dipole matrix Q = sum_m <x_m v, v>, boundary
  * mass B, partition-of-unity mass W, the Robin transfer operators and the
  * face Gram matrices used by the residual.  Requires a bound workspace.
- * Synchronises the stream.  In the local Slater determinant basis (not a
- * tensor basis, its orbitals computed here) the condition limits of
- * swr_create apply to the assembled determinants' Gram matrices instead:
+ * Synchronises the stream.  In the local Slater determinant and local
+ * orbital bases (not tensor bases, their orbitals computed here) the
+ * condition limits of swr_create apply to the assembled Gram matrices instead:
  * SWR_E_COND above 1e6, SWR_E_SINGULAR above 1e14 or when one is not
  * positive definite; the handle then stays unassembled. */
 int32_t swr_assemble(swr_handle h, void* stream);
