@@ -2601,7 +2601,7 @@ int32_t swr_run(swr_handle h, const swr_run_opts* o, swr_run_stats* stats, void*
   swr_run_stats s{};
   const int P = o->depth <= 0 ? h->depth_run : std::min(o->depth, h->depth);
   const bool tise = h->g.desc.mode == SWR_TISE;
-  const bool graph = o->graph != 0 && o->tol < 0.0 && !h->timing && !tise;
+  const bool graph = o->graph != 0 && o->tol < 0.0 && !h->timing;
   h->growth = Growth{};
   if (o->warm == SWR_WARM_GIVEN) h->growth.limit = o->growth_guard == 0 ? 2 : std::max(0, o->growth_guard);
   auto iterate = [&]() -> int32_t {

@@ -439,7 +439,8 @@ def test_series_falls_back_to_direct_inversion_for_strong_fields():
     assert s.factor_terms() == -1 and st["iters"] == 2
 
 
-@pytest.mark.parametrize("name", ["tiny-2d", "c2-2e-1d", "tiny-slater", "tiny-lsd-aug", "tiny-lo"])
+@pytest.mark.parametrize("name", ["tiny-2d", "c2-2e-1d", "tiny-slater", "tiny-lsd-aug", "tiny-lo",
+                                  "tiny-2d-tise", "tiny-lsd-aug-tise", "c2-2e-1d-tise"])
 def test_graph_replay_equals_eager_run(name):
     """A fixed-iteration window captured as a HIP graph and replayed, with
     eager runs of another length between the replays, gives the eager run's
@@ -458,6 +459,8 @@ def test_graph_replay_equals_eager_run(name):
         assert np.array_equal(_np(s.history()), h_e), rep
         assert np.array_equal(_np(s.forcing()), f_e), rep
         assert st_g["res"] == st_e["res"], rep
+        if cfg["mode"] == "tise":
+            assert st_g["energy"] == st_e["energy"], rep
         s.set_initial(c0)
         s.run(k_max=2, tol=-1.0)  # eager work between the replays
 
