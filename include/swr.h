@@ -349,8 +349,9 @@ typedef struct swr_run_opts {
   int32_t graph;             /* 1: with tol < 0 (exactly k_max iterations),
                                 depth > 1 and no timing, the window's launches
                                 are captured once into a HIP graph (per k_max
-                                and depth) and replayed; the residuals are
-                                read after the window                        */
+                                and depth) and replayed, in real and in
+                                imaginary time; the residuals are read after
+                                the window                                   */
   int32_t growth_guard;      /* GIVEN warm start: consecutive increases of
                                 Res(k) that trigger the PLAIN fallback
                                 (0: 2; negative: never)                      */
