@@ -20,16 +20,28 @@ constexpr int kT = 64;   // output tile (rows and columns)
 constexpr int kK = 16;   // reduction chunk
 
 // C[m][n] = sum_k A(m,k) B(k,n) (+ bias[n]) (+ C[m][n] if accumulate), with
-// A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn], C row-major.
+// A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn], C row-major, on the
+// matrix cores: a 64 x 64 tile per block of four waves, 32 x 32 per wave as
+// 2 x 2 products of v_mfma_f32_16x16x4f32 (A fragment: lane l holds
+// A[l % 16][l / 16], B fragment B[l / 16][l % 16], the 16 x 16 result
+// D[4 (l / 16) + v][l % 16] in its v-th register); the operands staged in
+// LDS k-chunk by k-chunk (any strides).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 __global__ void __launch_bounds__(256) k_sgemm(int M, int N, int K, const float* A, int64_t sam,
                                               int64_t sak, const float* B, int64_t sbk,
                                               int64_t sbn, float* C, int64_t ldc,
                                               const float* bias, int accumulate) {
-  __shared__ float As[kK][kT + 1];
-  __shared__ float Bs[kK][kT + 1];
+  __shared__ float As[kK][kT + 4];
+  __shared__ float Bs[kK][kT + 4];
   const int m0 = blockIdx.y * kT, n0 = blockIdx.x * kT;
-  const int tm = threadIdx.x >> 4, tn = threadIdx.x & 15;
-  float acc[4][4] = {};
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  const int fr = lane & 15, fk = lane >> 4;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   for (int k0 = 0; k0 < K; k0 += kK) {
     for (int e = threadIdx.x; e < kK * kT; e += blockDim.x) {
       const int kk = e / kT, mm = e % kT;
@@ -40,33 +52,34 @@ __global__ void __launch_bounds__(256) k_sgemm(int M, int N, int K, const float*
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < kK; ++kk) {
-      float a[4], b[4];
+    for (int k4 = 0; k4 < kK; k4 += 4) {
+      float a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][tm * 4 + i];
+      for (int i = 0; i < 2; ++i) a[i] = As[k4 + fk][wm + 16 * i + fr];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tn * 4 + j];
+      for (int j = 0; j < 2; ++j) b[j] = Bs[k4 + fk][wn + 16 * j + fr];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int m = m0 + tm * 4 + i;
-    if (m >= M) continue;
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int n = n0 + tn * 4 + j;
-      if (n >= N) continue;
-      float v = acc[i][j];
-      if (bias) v += bias[n];
-      if (accumulate) v += C[m * ldc + n];
-      C[m * ldc + n] = v;
-    }
-  }
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = m0 + wm + 16 * i + 4 * fk + v;
+        const int n = n0 + wn + 16 * j + fr;
+        if (m >= M || n >= N) continue;
+        float x = acc[i][j][v];
+        if (bias) x += bias[n];
+        if (accumulate) x += C[m * ldc + n];
+        C[m * ldc + n] = x;
+      }
 }
 
 __device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
