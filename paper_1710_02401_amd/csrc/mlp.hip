@@ -26,25 +26,30 @@ constexpr int kK = 16;   // reduction chunk
 // A[l % 16][l / 16], B fragment B[l / 16][l % 16], the 16 x 16 result
 // D[4 (l / 16) + v][l % 16] in its v-th register); the operands staged in
 // LDS k-chunk by k-chunk (any strides).
+// TILE = 64: 32 x 32 per wave (2 x 2 products); TILE = 32: 16 x 16 per wave,
+// for products too small to give the chip enough 64 x 64 tiles.  Each
+// output's k order is the same for both.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+template <int TILE>
 __global__ void __launch_bounds__(256) k_sgemm(int M, int N, int K, const float* A, int64_t sam,
                                               int64_t sak, const float* B, int64_t sbk,
                                               int64_t sbn, float* C, int64_t ldc,
                                               const float* bias, int accumulate) {
-  __shared__ float As[kK][kT + 4];
-  __shared__ float Bs[kK][kT + 4];
-  const int m0 = blockIdx.y * kT, n0 = blockIdx.x * kT;
+  constexpr int R = TILE / 32;  // 16 x 16 products per wave and dimension
+  __shared__ float As[kK][TILE + 4];
+  __shared__ float Bs[kK][TILE + 4];
+  const int m0 = blockIdx.y * TILE, n0 = blockIdx.x * TILE;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  const int wm = (w >> 1) * (TILE / 2), wn = (w & 1) * (TILE / 2);
   const int fr = lane & 15, fk = lane >> 4;
-  f32x4 acc[2][2];
+  f32x4 acc[R][R];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < R; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int j = 0; j < R; ++j) acc[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   for (int k0 = 0; k0 < K; k0 += kK) {
-    for (int e = threadIdx.x; e < kK * kT; e += blockDim.x) {
-      const int kk = e / kT, mm = e % kT;
+    for (int e = threadIdx.x; e < kK * TILE; e += blockDim.x) {
+      const int kk = e / TILE, mm = e % TILE;
       const int m = m0 + mm, k = k0 + kk;
       As[kk][mm] = (m < M && k < K) ? A[m * sam + k * sak] : 0.0f;
       const int n = n0 + mm;
@@ -53,23 +58,23 @@ __global__ void __launch_bounds__(256) k_sgemm(int M, int N, int K, const float*
     __syncthreads();
 #pragma unroll
     for (int k4 = 0; k4 < kK; k4 += 4) {
-      float a[2], b[2];
+      float a[R], b[R];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = As[k4 + fk][wm + 16 * i + fr];
+      for (int i = 0; i < R; ++i) a[i] = As[k4 + fk][wm + 16 * i + fr];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = Bs[k4 + fk][wn + 16 * j + fr];
+      for (int j = 0; j < R; ++j) b[j] = Bs[k4 + fk][wn + 16 * j + fr];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < R; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < R; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < R; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < R; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int m = m0 + wm + 16 * i + 4 * fk + v;
@@ -211,9 +216,17 @@ uint64_t plan_ws(const Net& net, int batch, char* base, Ws* ws) {
 void gemm(hipStream_t st, int M, int N, int K, const float* A, int64_t sam, int64_t sak,
           const float* B, int64_t sbk, int64_t sbn, float* C, int64_t ldc, const float* bias,
           int accumulate) {
-  dim3 grid((N + kT - 1) / kT, (M + kT - 1) / kT);
-  hipLaunchKernelGGL(k_sgemm, grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk, sbn, C, ldc,
-                     bias, accumulate);
+  // 64 x 64 tiles where they give at least 256 blocks, else 32 x 32
+  const int64_t big = (int64_t)((N + kT - 1) / kT) * ((M + kT - 1) / kT);
+  if (big >= 256) {
+    dim3 grid((N + kT - 1) / kT, (M + kT - 1) / kT);
+    hipLaunchKernelGGL(k_sgemm<64>, grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk, sbn, C,
+                       ldc, bias, accumulate);
+  } else {
+    dim3 grid((N + 31) / 32, (M + 31) / 32);
+    hipLaunchKernelGGL(k_sgemm<32>, grid, dim3(256), 0, st, M, N, K, A, sam, sak, B, sbk, sbn, C,
+                       ldc, bias, accumulate);
+  }
 }
 
 // forward pass; the output layer's result is ws.h.back() (= ws.z.back())

@@ -518,6 +518,29 @@ def test_every_transmission_tile_gives_the_same_histories(name):
         assert e.value.code == S.SWR_E_ARG, bad
 
 
+def test_wide_path_schedules_give_the_same_histories():
+    """On the wide-basis path swr_set_schedule takes every transmission tile
+    (8, 16, 32) and both recurrence orders: the same histories bit for bit;
+    the narrow path's order 1 is refused there only."""
+    cfg = dict(_cfg("c3-mini"), factor="wide")
+    s = _solver(cfg)
+    assert s.info.wide == 1
+    ref = None
+    for tile in (8, 16, 32):
+        for order in (0, 1):
+            print(f"[gpu] c3-mini: tile {tile}, order {order}", flush=True)
+            s.set_schedule(1, tile, order)
+            assert s.info.tx_tile == tile and s.info.wide_order == order
+            s.set_initial()
+            st = s.run(k_max=3, tol=-1.0)
+            h = _np(s.history())
+            if ref is None:
+                ref = (h, st["res"])
+                continue
+            assert np.array_equal(h, ref[0]), (tile, order)
+            assert np.allclose(st["res"], ref[1], rtol=1e-12, atol=0), (tile, order)
+
+
 def test_imaginary_time_pipelined_stops_where_depth_one_stops():
     """With a residual target, the pipelined imaginary-time window stops at
     the same iterate as one iterate at a time (the iterates started past it
