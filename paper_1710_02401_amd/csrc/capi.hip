@@ -47,7 +47,7 @@ bool distinct_time_nodes(int n_T, int M) {
   return true;
 }
 
-constexpr int kMaxDepth = 8;    // iterates in flight at most (one job each per launch)
+constexpr int kMaxDepth = 16;   // iterates in flight at most (one job each per launch)
 constexpr int kMaxSlots = kMaxDepth + 2;  // + the previous iterate, + one for the residual lag
 static_assert(kMaxDepth <= swr::kMaxJobs, "one job per iterate in flight");
 constexpr int kResEvents = 8;   // residual read-backs in flight

@@ -112,7 +112,7 @@ struct TEnt {
 // Work lists of the chunked sweep, passed by value: job q covers the steps
 // [n_lo, n_hi] (transmit) or the Crank-Nicolson steps n_lo .. n_lo+n_cnt-1
 // (recurrence) of one Schwarz iterate.
-constexpr int kMaxJobs = 8;
+constexpr int kMaxJobs = 16;
 struct TxJobs {
   int n;
   const double2* src[kMaxJobs];  // sending histories

@@ -306,7 +306,7 @@ def test_pipelined_run_equals_one_iterate_at_a_time(name):
     by chunk, so they agree to rounding."""
     cfg = _cfg(name)
     s = _solver(cfg)
-    assert s.info.depth == min(8, -(-256 // len(s.K)), cfg["n_steps"])
+    assert s.info.depth == min(16, -(-256 // len(s.K)), cfg["n_steps"])
     c0 = s.initial().clone()
     out = {}
     for depth in (1, 2, 3, 4, 7, 0):
