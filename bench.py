@@ -52,10 +52,10 @@ MEASURED_TRAFFIC = {
     # 16-step transmission tile (the autotuned default): 23 recurrence
     # launches (the series evaluated in the step), 27 transmissions, one
     # factorisation
-    "k_cn_recur_series": {"kernels_sha256": "39f566548ee6aef5", "bytes_per_launch": 0.22230e9},
+    "k_cn_recur_series": {"kernels_sha256": "efa8b11e90fcd0d2", "bytes_per_launch": 0.22185e9},
     # per transmission tile (only the measured one)
-    "k_tx_send+k_tx_recv": {"kernels_sha256": "39f566548ee6aef5",
-                            "bytes_per_launch_by_tile": {16: 0.45015e9}},
+    "k_tx_send+k_tx_recv": {"kernels_sha256": "efa8b11e90fcd0d2",
+                            "bytes_per_launch_by_tile": {16: 0.45149e9}},
     # profiles/c3-1e-1d-batched_traffic.md: one sweep of the batched workload
     "k_cn_recur_wide": {"wide_sha256": "8b17b20586e217b0", "bytes_per_launch": 1350.81e9},
     # profiles/c5-2e-2d_traffic.md: median over the 529 step launches of one

@@ -1556,7 +1556,10 @@ __global__ void __launch_bounds__(kRecThreads)
 // ---------------------------------------------------------------------------
 // Transmission as a batched complex product: for receiving item i and a tile
 // of time steps, F_i[n][l] = scale_n * sum_{pairs (i,j)} sum_m T_ij[l][m] C_j[n][m].
-// Dense form (any D); one job per grid z.
+// Dense form (any D); one job per grid z.  The products run on the FP64
+// matrix cores with A = C (steps x columns m) and B = T^T (columns m x
+// receiver functions): per 16 x 16 output tile and four columns, four real
+// v_mfma_f64_16x16x4f64 (re += Cr Tr - Ci Ti, im += Ci Tr + Cr Ti).
 constexpr int kTN = 32;
 constexpr int kTM = 16;
 constexpr int kTRow = kSmallK + 1;
@@ -1571,17 +1574,18 @@ __global__ void __launch_bounds__(kBlock) k_transmit(Items it, Pairs pr, int n_s
   const double2* hist = jobs.src[job];
   double2* F = jobs.dst[job];
   const int Ki = it.K[i];
-  // T in slices of kTM columns: 48 KB of LDS per block instead of 96 KB, so
-  // that three blocks (three waves per SIMD) share a CU; every output still
-  // sums over the pairs, then the columns, in order
-  __shared__ double2 Ts[kTM * kTRow];  // [m - m0][l], rows padded against bank conflicts
-  __shared__ double2 Cs[kTN * kSmallK];  // [nn][m]
-  // thread: receiver functions l0 and l0 + 32, steps nn0 + 8 q (two outputs
-  // per operator entry and coefficient read from LDS)
-  const int l0 = threadIdx.x & 31, l1 = l0 + 32;
-  const int nn0 = threadIdx.x >> 5;
-  double2 acc0[kTN / 8], acc1[kTN / 8];
-  for (int q = 0; q < kTN / 8; ++q) acc0[q] = acc1[q] = make_double2(0.0, 0.0);
+  // T in slices of kTM columns (three blocks share a CU); rows of both
+  // tiles padded to 65 entries, so that the operand reads (16 consecutive
+  // rows or columns per quarter wave) spread over the banks
+  __shared__ double2 Ts[kTM * kTRow];  // [m - m0][l]
+  __shared__ double2 Cs[kTN * kTRow];  // [nn][m]
+  // wave w: steps 16 (w & 1) .. + 15 of the tile, receiver tiles w >> 1 and
+  // (w >> 1) + 2 (so that items with K <= 32 still keep every wave busy)
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lr = lane >> 4, lc = lane & 15;
+  const int rt = w & 1, ct = w >> 1;
+  const bool on0 = 16 * ct < Ki, on1 = 16 * (ct + 2) < Ki;  // uniform over the wave
+  v4d re0 = {0.0, 0.0, 0.0, 0.0}, im0 = re0, re1 = re0, im1 = re0;
   // Stages (pair p, slice from column m0), each one's loads issued into
   // registers while the previous one computes.
   constexpr int kUT = kTM * kSmallK / kBlock, kUC = kTN * kSmallK / kBlock;
@@ -1629,8 +1633,15 @@ __global__ void __launch_bounds__(kBlock) k_transmit(Items it, Pairs pr, int n_s
 #pragma unroll
       for (int u = 0; u < kUC; ++u) {
         const int e = u * kBlock + (int)threadIdx.x;
-        if (e < kTN * Kj) Cs[e] = make_double2(cx[u], cy[u]);
+        const int nn = e / Kj, mm = e - nn * Kj;
+        if (e < kTN * Kj) Cs[nn * kTRow + mm] = make_double2(cx[u], cy[u]);
       }
+    // zeros in the columns that pad the slice to a multiple of four: T's
+    // rows cnt .. (last slice of a pair), C's columns Kj .. (every row)
+    if ((cnt & 3) && (int)threadIdx.x < 64 * (4 - (cnt & 3)))
+      Ts[(cnt + (threadIdx.x >> 6)) * kTRow + (threadIdx.x & 63)] = make_double2(0.0, 0.0);
+    if (m0 == 0 && (Kj & 3) && (int)threadIdx.x < kTN * (4 - (Kj & 3)))
+      Cs[(threadIdx.x % kTN) * kTRow + Kj + threadIdx.x / kTN] = make_double2(0.0, 0.0);
     __syncthreads();
     const int cm0 = m0;
     m0 += kTM;
@@ -1639,27 +1650,39 @@ __global__ void __launch_bounds__(kBlock) k_transmit(Items it, Pairs pr, int n_s
       ++p;
     }
     if (p < pr.poff[i + 1]) fetch(p, m0);
-    if (l0 < Ki) {
-      for (int mm = 0; mm < cnt; ++mm) {
-        const double2 t0 = Ts[mm * kTRow + l0], t1 = Ts[mm * kTRow + l1];
-        for (int q = 0; q < kTN / 8; ++q) {
-          const double2 c = Cs[(nn0 + 8 * q) * Kj + cm0 + mm];
-          acc0[q] = cfma(t0, c, acc0[q]);
-          acc1[q] = cfma(t1, c, acc1[q]);
+    if (on0) {
+      for (int kk = 0; kk < cnt; kk += 4) {
+        const int mm = kk + lr;
+        const double2 a = Cs[(16 * rt + lc) * kTRow + cm0 + mm];
+        const double2 b0 = Ts[mm * kTRow + 16 * ct + lc];
+        re0 = mfma16(a.x, b0.x, re0);
+        re0 = mfma16(-a.y, b0.y, re0);
+        im0 = mfma16(a.y, b0.x, im0);
+        im0 = mfma16(a.x, b0.y, im0);
+        if (on1) {
+          const double2 b1 = Ts[mm * kTRow + 16 * (ct + 2) + lc];
+          re1 = mfma16(a.x, b1.x, re1);
+          re1 = mfma16(-a.y, b1.y, re1);
+          im1 = mfma16(a.y, b1.x, im1);
+          im1 = mfma16(a.x, b1.y, im1);
         }
       }
     }
   }
-  if (l0 < Ki) {
-    const int64_t fb = (int64_t)(n_steps + 1) * it.off1[i];
-    for (int q = 0; q < kTN / 8; ++q) {
-      const int n = n0 + nn0 + 8 * q;
-      if (n > n_hi) continue;
-      const double sc = scale ? scale[n] : 1.0;
-      F[fb + (int64_t)n * Ki + l0] = cscale(acc0[q], sc);
-      if (l1 < Ki) F[fb + (int64_t)n * Ki + l1] = cscale(acc1[q], sc);
-    }
-  }
+  // register r of a tile: step 16 rt + 4 r + lr, receiver function 16 ct + lc
+  const int64_t fb = (int64_t)(n_steps + 1) * it.off1[i];
+  const int l0 = 16 * ct + lc, l1 = l0 + 32;
+  auto put = [&](int r, double a0, double b0, double a1, double b1) {
+    const int n = n0 + 16 * rt + 4 * r + lr;
+    if (n > n_hi) return;
+    const double sc = scale ? scale[n] : 1.0;
+    if (on0 && l0 < Ki) F[fb + (int64_t)n * Ki + l0] = make_double2(a0 * sc, b0 * sc);
+    if (on1 && l1 < Ki) F[fb + (int64_t)n * Ki + l1] = make_double2(a1 * sc, b1 * sc);
+  };
+  put(0, re0.x, im0.x, re1.x, im1.x);
+  put(1, re0.y, im0.y, re1.y, im1.y);
+  put(2, re0.z, im0.z, re1.z, im1.z);
+  put(3, re0.w, im0.w, re1.w, im1.w);
 }
 
 // Factored form (D <= 2), in two passes.  Per entry e (pair (i,j), face of
