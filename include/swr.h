@@ -331,7 +331,7 @@ int32_t swr_transmit(swr_handle h, double* residual_host, void* stream);
  * with the same arithmetic as at depth 1 (identical results); up to P-1
  * iterates past the stopping one are started and discarded.  depth 0 takes
  * swr_info.depth (sized at creation so that P x n_items fills the GPU,
- * P <= 8); 1 runs one iterate at a time; larger values are capped at
+ * P <= 16); 1 runs one iterate at a time; larger values are capped at
  * swr_info.depth.  TISE pipelines the same way, with one launch per step
  * (its global normalisation couples every item at every step) advancing
  * every iterate in flight; each iterate keeps its own normalisation
